@@ -1,0 +1,201 @@
+"""Hartree potential, total energy and the DC-DFT SCF iteration (test
+infrastructure only).
+
+One SCF iteration (Sec. 2.2; the loop runs "as in conventional DFT" over the
+total density):
+  1. V_H from the global Poisson equation of rho_tot^in, discretised with the
+     same nine-point-per-axis Laplacian: L V_H = -4 pi (rho - mean rho),
+     V_H with zero mean (jellium gauge).
+  2. V_eff^alpha = V_loc + V_H (gathered from the global grid) + V_xc[rho_alpha^in]
+     (Eq. (5): exchange-correlation from the fragment density; V^alpha = 0).
+  3. fragment eigensolver (``cg_eigensolver``), core weights.
+  4. global mu (``fermi_level``).
+  5. rho_alpha^out (Eq. (4)); rho_tot^out = sum_alpha core-projected rho_alpha
+     (Eqs. (2)-(3)).
+  6. Harris-Foulkes / Mermin free energy at rho^in (the ion-ion term, constant
+     for a fixed geometry, is omitted).
+  7. residuals: dV sum |rho_out - rho_in| / N_e and the paper's convergence
+     measure dV sum |rho_k^in - rho_(k-1)^in| / N_e (Sec. 3.3).
+  8. linear mixing rho^in <- rho^in + a (rho^out - rho^in), applied to the
+     total density and to every fragment density.
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import numpy as np
+
+from .grid import FD_COEFFS, HALF_WIDTH, build_fragments, laplacian_periodic
+from .model import (fragment_projectors, grid_spacing, kb_projectors, lda_pz81,
+                    local_potential)
+from .rng import initial_orbitals
+from .solver import (apply_h, cg_eigensolver, cholesky_orthonormalize, core_weights,
+                     fermi_level, fermi_occupation, fragment_density)
+
+
+def fd_symbol(n_grid, h) -> np.ndarray:
+    """Eigenvalues of the periodic FD Laplacian on the Fourier modes, (Nz, Ny, Nx)."""
+    lam = []
+    for d in range(3):
+        k = np.arange(n_grid[d])
+        s = FD_COEFFS[0] + 2.0 * sum(FD_COEFFS[j] * np.cos(2.0 * math.pi * j * k / n_grid[d])
+                                     for j in range(1, HALF_WIDTH + 1))
+        lam.append(s / (h[d] * h[d]))
+    return lam[2][:, None, None] + lam[1][None, :, None] + lam[0][None, None, :]
+
+
+def poisson_fd(rho: np.ndarray, h) -> np.ndarray:
+    """Exact solution of L V = -4 pi (rho - mean rho) with mean V = 0, by
+    diagonalising the circulant FD Laplacian with the FFT."""
+    n_grid = (rho.shape[2], rho.shape[1], rho.shape[0])
+    lam = fd_symbol(n_grid, h)
+    rk = np.fft.fftn(rho)
+    lam_safe = lam.copy()
+    lam_safe[0, 0, 0] = 1.0
+    vk = -4.0 * math.pi * rk / lam_safe
+    vk[0, 0, 0] = 0.0
+    return np.real(np.fft.ifftn(vk))
+
+
+def poisson_fd_cg(rho: np.ndarray, h, tol: float = 1e-13, x0: Optional[np.ndarray] = None,
+                  maxiter: int = 20000) -> np.ndarray:
+    """The same equation by conjugate gradients on -L (SPD on zero-mean fields),
+    stopping at ||r|| <= tol ||b||."""
+    b = 4.0 * math.pi * (rho - rho.mean())
+    x = np.zeros_like(rho) if x0 is None else x0 - x0.mean()
+    r = b + laplacian_periodic(x, h)
+    p = r.copy()
+    rr = float(np.sum(r * r))
+    bn = math.sqrt(float(np.sum(b * b)))
+    for _ in range(maxiter):
+        if math.sqrt(rr) <= tol * bn:
+            break
+        ap = -laplacian_periodic(p, h)
+        alpha = rr / float(np.sum(p * ap))
+        x = x + alpha * p
+        r = r - alpha * ap
+        rr_new = float(np.sum(r * r))
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    return x - x.mean()
+
+
+def entropy_term(occ: np.ndarray, w: np.ndarray) -> float:
+    """S = -sum 2 w [f ln f + (1 - f) ln(1 - f)], 0 ln 0 = 0."""
+    f = np.asarray(occ)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t1 = np.where(f > 0, f * np.log(np.where(f > 0, f, 1.0)), 0.0)
+        t2 = np.where(f < 1, (1 - f) * np.log(np.where(f < 1, 1 - f, 1.0)), 0.0)
+    return float(-np.sum(2.0 * w * (t1 + t2)))
+
+
+def total_energy(e_band: float, rho_in: np.ndarray, v_h: np.ndarray, dv: float,
+                 sigma: float, entropy: float) -> float:
+    """E = E_band - dV sum rho_in (V_H + V_xc[rho_in]) + 1/2 dV sum rho_in V_H
+           + dV sum rho_in eps_xc[rho_in] - sigma S."""
+    exc, vxc = lda_pz81(rho_in)
+    return (e_band - dv * float(np.sum(rho_in * (v_h + vxc))) + 0.5 * dv * float(np.sum(rho_in * v_h))
+            + dv * float(np.sum(rho_in * exc)) - sigma * entropy)
+
+
+def _solve_fragment(args):
+    psi, veff, proj, h, dv, sweeps, shape = args
+    m = psi.shape[0]
+    hop = lambda x: apply_h(x.reshape((x.shape[0],) + shape), veff, proj, h, dv).reshape(x.shape[0], -1)
+    return cg_eigensolver(psi, hop, sweeps, dv)
+
+
+class OracleSCF:
+    """State and iteration of the DC-DFT SCF on the CPU, FP64."""
+
+    def __init__(self, cfg, workers: int = 1):
+        self.cfg = cfg
+        sysm = cfg.system
+        self.n_grid = tuple(int(v) for v in cfg.n_grid)
+        self.h = grid_spacing(sysm.cell, self.n_grid)
+        self.dv = float(np.prod(self.h))
+        self.n_global = int(np.prod(self.n_grid))
+        self.ne = sysm.n_electrons
+        self.frags = build_fragments(self.n_grid, cfg.num_fragment, cfg.num_rgrid_buffer)
+        self.vloc = local_potential(sysm, self.n_grid)
+        self.projectors = kb_projectors(sysm, self.n_grid)
+        self.fproj = [fragment_projectors(self.projectors, f, self.n_global) for f in self.frags]
+        self.m = [int(v) for v in cfg.nstate_frag]
+        self.psi = []
+        for f in self.frags:
+            raw = initial_orbitals(cfg.seed, f.alpha, self.m[f.alpha], f.shape).reshape(self.m[f.alpha], -1)
+            self.psi.append(cholesky_orthonormalize(raw, self.dv)[0])
+        omega = float(np.prod(sysm.cell))
+        self.rho_in = np.full(self.n_grid[::-1], self.ne / omega)
+        self.rho_frag_in = [np.full(f.n, self.ne / omega) for f in self.frags]
+        self.rho_out = None
+        self.rho_frag_out = None
+        self.eps = None
+        self.w = None
+        self.mu = None
+        self.iteration = 0
+        self.workers = workers
+
+    def veff(self, alpha: int, v_h: np.ndarray) -> np.ndarray:
+        f = self.frags[alpha]
+        _, vxc = lda_pz81(self.rho_frag_in[alpha])
+        return (self.vloc.ravel()[f.global_index] + v_h.ravel()[f.global_index] + vxc)
+
+    def solve_fragments(self, v_h: np.ndarray, alphas=None):
+        alphas = range(len(self.frags)) if alphas is None else alphas
+        jobs = []
+        for a in alphas:
+            f = self.frags[a]
+            jobs.append((self.psi[a], self.veff(a, v_h).reshape(f.shape), self.fproj[a], self.h,
+                         self.dv, self.cfg.cg_sweeps, f.shape))
+        if self.workers > 1 and len(jobs) > 1:
+            import multiprocessing as mp
+            with mp.get_context("fork").Pool(self.workers) as pool:
+                res = pool.map(_solve_fragment, jobs)
+        else:
+            res = [_solve_fragment(j) for j in jobs]
+        return dict(zip(alphas, res))
+
+    def step(self) -> dict:
+        cfg = self.cfg
+        dv = self.dv
+        v_h = poisson_fd(self.rho_in, self.h)
+        res = self.solve_fragments(v_h)
+        self.eps, self.w = [], []
+        for a, f in enumerate(self.frags):
+            psi, eps = res[a]
+            self.psi[a] = psi
+            self.eps.append(eps)
+            self.w.append(core_weights(psi, f.core_mask, dv))
+        eps_all = np.concatenate(self.eps)
+        w_all = np.concatenate(self.w)
+        mu = fermi_level(eps_all, w_all, self.ne, cfg.smearing)
+        self.mu = mu
+        rho_out = np.zeros(self.n_global)
+        self.rho_frag_out = []
+        occ_all = []
+        for a, f in enumerate(self.frags):
+            occ = fermi_occupation((self.eps[a] - mu) / cfg.smearing)
+            occ_all.append(occ)
+            rf = fragment_density(self.psi[a], occ)
+            self.rho_frag_out.append(rf)
+            rho_out[f.global_index[f.core_mask]] = rf[f.core_mask]
+        rho_out = rho_out.reshape(self.rho_in.shape)
+        self.rho_out = rho_out
+        occ_all = np.concatenate(occ_all)
+        e_band = float(np.sum(2.0 * occ_all * eps_all * w_all))
+        ent = entropy_term(occ_all, w_all)
+        e_tot = total_energy(e_band, self.rho_in, v_h, dv, cfg.smearing, ent)
+        r_out_in = dv * float(np.sum(np.abs(rho_out - self.rho_in))) / self.ne
+        charge = dv * float(np.sum(rho_out))
+        a_mix = cfg.mixing
+        rho_new = self.rho_in + a_mix * (rho_out - self.rho_in)
+        r_paper = dv * float(np.sum(np.abs(rho_new - self.rho_in))) / self.ne
+        self.rho_in = rho_new
+        self.rho_frag_in = [ri + a_mix * (ro - ri) for ri, ro in zip(self.rho_frag_in, self.rho_frag_out)]
+        self.iteration += 1
+        self.v_h = v_h
+        return dict(iter=self.iteration, mu=mu, e_total=e_tot, e_band=e_band,
+                    residual_paper=r_paper, residual_out_in=r_out_in, charge=charge,
+                    entropy=ent)
