@@ -1,0 +1,201 @@
+/*
+ * dcdft.h - C ABI of the divide-and-conquer DFT fragment SCF library (gfx950).
+ *
+ * The library runs the ground-state SCF iteration of divide-and-conquer DFT
+ * (Yamada & Otobe, "SALMON 2.3: Implementation of divide-and-conquer
+ * ground-state initialization for large-scale real-time TDDFT", Sec. 2.2):
+ * a periodic rectangular cell is cut into a regular grid of core boxes, each
+ * extended by a buffer of b grid points into an overlapping fragment with
+ * periodic boundaries of its own; every fragment solves its Kohn-Sham problem
+ * (Eq. (1)) with the Hamiltonian of Eq. (5); a global chemical potential fixes
+ * the electron count; the total density is the sum of the fragment densities
+ * projected onto their cores (Eqs. (2)-(4)).  The fragment keywords mirror the
+ * paper's input table (Table 1): num_fragment, nstate_frag, num_rgrid_buffer.
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns a dcdft_status; nothing aborts, throws or exits.
+ *    dcdft_last_error() gives a message for the last failure (per context, or
+ *    process-wide for a failed setup when called with ctx == NULL).
+ *  - Units are Hartree atomic units (bohr, Ha).
+ *  - Global arrays are x-fastest: index g = gx + Nx (gy + Ny gz).
+ *  - Fragment alpha = ax + Fx (ay + Fy az); its local point l = lx + nx (ly + ny lz)
+ *    maps to global gd = (ad * ncore_d - b_d + ld) mod N_d, ncore_d = N_d / F_d,
+ *    n_d = ncore_d + 2 b_d.  All fragments have the same box shape.
+ *  - Fragment orbital blocks are orbital-major: element (i, l) at i * n + l.
+ *  - Inner products carry the volume element dV = hx hy hz, h_d = cell_d / N_d.
+ *  - Host input arrays are caller-owned and copied during the call.  Output
+ *    buffers are caller-allocated; a buffer that is too small gives
+ *    DCDFT_ERR_ARG and the required size in the error message.
+ *  - Pointers documented as "device" must point to memory on the context's
+ *    GPU (for example a torch tensor's data_ptr()); the library never
+ *    allocates or frees them.
+ *  - A context is not thread-safe; separate contexts are independent.  All
+ *    device work is issued on the context's stream.
+ */
+#ifndef DCDFT_H
+#define DCDFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dcdft_ctx dcdft_ctx;
+
+typedef enum {
+  DCDFT_OK = 0,
+  DCDFT_ERR_ARG = -1,           /* null pointer, bad value, buffer too small        */
+  DCDFT_ERR_SHAPE = -2,         /* grid not divisible by fragments, box too large   */
+  DCDFT_ERR_CAPACITY = -3,      /* fragment states cannot hold N_e electrons        */
+  DCDFT_ERR_NOT_SPD = -4,       /* overlap matrix not positive definite (Cholesky)  */
+  DCDFT_ERR_EIG = -5,           /* subspace eigensolver did not converge            */
+  DCDFT_ERR_NAN = -6,           /* non-finite value detected                        */
+  DCDFT_ERR_HIP = -7,           /* HIP runtime error                                */
+  DCDFT_ERR_OOM = -8,           /* device allocation failed                         */
+  DCDFT_ERR_NOT_CONVERGED = -9  /* reserved for drivers that iterate to a tolerance */
+} dcdft_status;
+
+/* Model pseudopotential of one species (stand-in for the norm-conserving
+ * pseudopotentials of Sec. 2.2):
+ *   V_loc(r) = sum_a vloc_depth exp(-|r-R_a|^2 / (2 vloc_sigma^2)), each term kept
+ *              where |r-R_a| <= 10 vloc_sigma (minimum-image distance);
+ *   V_NL     = sum_a kb_energy |beta_a><beta_a|, beta_a proportional to
+ *              exp(-|r-R_a|^2 / (2 kb_sigma^2)) on |r-R_a| <= kb_rcut, normalised
+ *              on the global grid, restricted to each fragment box without
+ *              renormalisation (Eq. (5), "defined within the fragment"). */
+typedef struct {
+  double valence;
+  double vloc_depth;
+  double vloc_sigma;
+  double kb_energy;
+  double kb_sigma;
+  double kb_rcut;
+} dcdft_species;
+
+enum { DCDFT_PREC_FP64 = 0, DCDFT_PREC_MIXED = 1 };
+
+typedef struct {
+  int32_t n_grid[3];            /* global grid points per axis (x, y, z)            */
+  double cell[3];               /* periodic box lengths (bohr)                      */
+  int32_t num_fragment[3];      /* Table 1: fragments per axis; must divide n_grid  */
+  int32_t num_rgrid_buffer[3];  /* Table 1: buffer b in grid points per axis        */
+  int32_t n_atoms;
+  const double *atom_pos;       /* host [n_atoms][3] (bohr)                         */
+  const int32_t *atom_species;  /* host [n_atoms], index into species               */
+  int32_t n_species;
+  const dcdft_species *species; /* host [n_species]                                 */
+  const int32_t *nstate_frag;   /* host [F] orbitals per fragment, or NULL          */
+  int32_t nstate_frag_uniform;  /* Table 1 nstate_frag, used when the array is NULL */
+  double n_electrons;           /* N_e fixed by the global chemical potential       */
+  double smearing;              /* kT of the Fermi-Dirac occupation (Ha), > 0       */
+  double mixing;                /* linear density-mixing fraction in (0, 1]         */
+  int32_t cg_sweeps;            /* CG sweeps per SCF iteration, >= 1                */
+  int32_t precision;            /* DCDFT_PREC_FP64 or DCDFT_PREC_MIXED              */
+  int32_t batched;              /* 1: all fragments per launch + graph replay;
+                                   0: one launch sequence per fragment              */
+  uint64_t seed;                /* initial-orbital generator seed                   */
+  void *hip_stream;             /* hipStream_t to use; NULL: the library makes one  */
+} dcdft_params;
+
+/* Scalars of one SCF iteration.  Energies follow the Harris-Foulkes / Mermin
+ * form at the input density (ion-ion term omitted). */
+typedef struct {
+  int32_t iter;                 /* 1-based count of completed iterations            */
+  double mu;                    /* global chemical potential (Ha)                   */
+  double e_total;               /* free energy (Ha)                                 */
+  double e_band;                /* sum 2 f eps w over all fragment states (Ha)      */
+  double entropy;               /* -sum 2 w [f ln f + (1-f) ln(1-f)]                */
+  double residual_paper;        /* dV sum |rho_k^in - rho_(k-1)^in| / N_e (Sec. 3.3) */
+  double residual_out_in;       /* dV sum |rho^out - rho^in| / N_e                  */
+  double charge;                /* dV sum rho_tot^out                               */
+  float ms_step;                /* device time of the step (ms)                     */
+} dcdft_scf_info;
+
+/* Validate p, build the fragment and projector tables, upload them, draw the
+ * initial orbitals (SplitMix64 counter stream: orbital-point (alpha, i, l) uses
+ * counter ((alpha << 40) | (i << 24) | l) + 1; value = top 53 bits * 2^-53 - 1/2)
+ * and Cholesky-orthonormalise them; the input density starts uniform, N_e / volume.
+ * Errors: ARG (null or out-of-range field), SHAPE (n_grid % num_fragment != 0 or
+ * ncore + 2 b > N), OOM, HIP, NOT_SPD.  On success *out owns all device memory. */
+dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out);
+
+/* Exactly one SCF iteration over all fragments (Sec. 2.2): Hartree potential of
+ * rho_tot^in (nine-point FD Poisson equation, solved exactly, zero mean),
+ * V_eff of every fragment, cg_sweeps CG sweeps + Rayleigh-Ritz per fragment,
+ * core weights, global mu, rho^out assembly (Eqs. (2)-(4)), energy, residuals,
+ * linear mixing of rho_tot and of every fragment density.  info may be NULL.
+ * Errors: CAPACITY (sum 2 w < N_e), NOT_SPD, EIG, NAN, HIP.  After an error the
+ * orbitals and densities are unspecified; destroy the context or reset them
+ * with dcdft_set_orbitals / dcdft_set_density. */
+dcdft_status dcdft_scf_step(dcdft_ctx *c, dcdft_scf_info *info);
+
+/* Host copy of rho_tot^out of the last step (Eq. (2)), n = Nx Ny Nz doubles. */
+dcdft_status dcdft_density(const dcdft_ctx *c, double *rho, size_t n);
+
+/* Device copy (double, n = Nx Ny Nz) of rho_tot^out of the last step. */
+dcdft_status dcdft_density_device(const dcdft_ctx *c, void *dptr, size_t n);
+
+/* Eigenvalues eps (ascending) and core weights w of fragment frag after the last
+ * step; cap = capacity of both host buffers, *m receives m_alpha.  w may be NULL. */
+dcdft_status dcdft_eigenvalues(const dcdft_ctx *c, int32_t frag, double *eps, double *w,
+                               int32_t cap, int32_t *m);
+
+/* Fragment geometry: shape[3] = (nx, ny, nz), origin[3] = a_d ncore_d - b_d,
+ * *m = orbitals, *n_proj = atoms whose projector reaches the fragment box. */
+dcdft_status dcdft_fragment_info(const dcdft_ctx *c, int32_t frag, int32_t *shape,
+                                 int32_t *origin, int32_t *m, int32_t *n_proj);
+
+/* Global fields (host copy, N doubles) */
+enum { DCDFT_FIELD_VLOC = 0, DCDFT_FIELD_VH = 1, DCDFT_FIELD_RHO_IN = 2, DCDFT_FIELD_RHO_OUT = 3 };
+dcdft_status dcdft_get_field(const dcdft_ctx *c, int32_t which, double *host, size_t n);
+
+/* Fragment fields (host copy, n doubles): V_eff of the last step, rho_alpha^in,
+ * rho_alpha^out. */
+enum { DCDFT_FFIELD_VEFF = 0, DCDFT_FFIELD_RHO_IN = 1, DCDFT_FFIELD_RHO_OUT = 2 };
+dcdft_status dcdft_get_fragment_field(const dcdft_ctx *c, int32_t frag, int32_t which,
+                                      double *host, size_t n);
+
+/* Orbitals of fragment frag as FP64 host arrays [m][n] (state access for
+ * restarts and step-by-step comparisons).  set does not re-orthonormalise. */
+dcdft_status dcdft_get_orbitals(const dcdft_ctx *c, int32_t frag, double *host, size_t count);
+dcdft_status dcdft_set_orbitals(dcdft_ctx *c, int32_t frag, const double *host, size_t count);
+
+/* Replace rho_tot^in (N doubles) and, if rho_frag_in is not NULL, every fragment's
+ * rho_alpha^in ([F][n] doubles); with NULL each fragment gathers rho_tot^in. */
+dcdft_status dcdft_set_density(dcdft_ctx *c, const double *rho_tot_in, const double *rho_frag_in);
+
+/* H^alpha psi for m vectors of fragment frag with its V_eff of the last step
+ * (after setup: V_loc + V_xc of the uniform density, V_H = 0), Eq. (5):
+ * kinetic (nine-point FD, periodic on the fragment box) + V_eff + V_NL.
+ * psi, hpsi: device [m][n] of double (prec 0) or float (prec 1); may not alias. */
+dcdft_status dcdft_apply_h(dcdft_ctx *c, int32_t frag, const void *psi, void *hpsi,
+                           int32_t m, int32_t prec);
+
+/* Band-energy functional E = sum_i f_i <psi_i|H^alpha|psi_i> (inner product with dV)
+ * and its gradient, recomputing H psi:
+ *   grad_psi[i][l] = 2 f_i dV (H psi_i)(l),   grad_v[l] = dV sum_i f_i psi_i(l)^2,
+ * grad_v being the derivative with respect to V_eff (Eq. (4): dV times the
+ * fragment density when f carries 2 x occupation).  psi, grad_psi: device [m][n]
+ * (double or float by prec); f: device double [m]; grad_v: device [n] (same type
+ * as psi); energy: device double[1].  Any of grad_psi, grad_v, energy may be NULL. */
+dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, const double *f,
+                               int32_t m, int32_t prec, double *energy, void *grad_psi,
+                               void *grad_v);
+
+/* Release everything owned by c.  NULL-safe. */
+void dcdft_destroy(dcdft_ctx *c);
+
+/* Static string for a status code. */
+const char *dcdft_status_string(dcdft_status s);
+
+/* Copy the last error message of c (or of the last failed setup if c is NULL)
+ * into buf (NUL-terminated, truncated to n bytes). */
+dcdft_status dcdft_last_error(const dcdft_ctx *c, char *buf, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCDFT_H */

@@ -1,0 +1,304 @@
+"""ctypes binding of ``libdcdft.so`` (argument marshalling only).
+
+Every function here forwards to the C entry point of the same name declared
+in ``include/dcdft.h``; all computation happens in the HIP library.  When the
+library is missing the binding raises instead of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdcdft.so")
+
+DCDFT_OK = 0
+STATUS_NAMES = {
+    0: "DCDFT_OK", -1: "DCDFT_ERR_ARG", -2: "DCDFT_ERR_SHAPE", -3: "DCDFT_ERR_CAPACITY",
+    -4: "DCDFT_ERR_NOT_SPD", -5: "DCDFT_ERR_EIG", -6: "DCDFT_ERR_NAN", -7: "DCDFT_ERR_HIP",
+    -8: "DCDFT_ERR_OOM", -9: "DCDFT_ERR_NOT_CONVERGED",
+}
+PREC_FP64, PREC_MIXED = 0, 1
+FIELD_VLOC, FIELD_VH, FIELD_RHO_IN, FIELD_RHO_OUT = 0, 1, 2, 3
+FFIELD_VEFF, FFIELD_RHO_IN, FFIELD_RHO_OUT = 0, 1, 2
+
+EXPORTED = [
+    "dcdft_setup", "dcdft_scf_step", "dcdft_density", "dcdft_density_device",
+    "dcdft_eigenvalues", "dcdft_fragment_info", "dcdft_get_field", "dcdft_get_fragment_field",
+    "dcdft_get_orbitals", "dcdft_set_orbitals", "dcdft_set_density", "dcdft_apply_h",
+    "dcdft_band_energy", "dcdft_destroy", "dcdft_status_string", "dcdft_last_error",
+]
+
+
+class DcdftSpecies(ctypes.Structure):
+    _fields_ = [("valence", ctypes.c_double), ("vloc_depth", ctypes.c_double),
+                ("vloc_sigma", ctypes.c_double), ("kb_energy", ctypes.c_double),
+                ("kb_sigma", ctypes.c_double), ("kb_rcut", ctypes.c_double)]
+
+
+class DcdftParams(ctypes.Structure):
+    _fields_ = [
+        ("n_grid", ctypes.c_int32 * 3), ("cell", ctypes.c_double * 3),
+        ("num_fragment", ctypes.c_int32 * 3), ("num_rgrid_buffer", ctypes.c_int32 * 3),
+        ("n_atoms", ctypes.c_int32), ("atom_pos", ctypes.POINTER(ctypes.c_double)),
+        ("atom_species", ctypes.POINTER(ctypes.c_int32)), ("n_species", ctypes.c_int32),
+        ("species", ctypes.POINTER(DcdftSpecies)),
+        ("nstate_frag", ctypes.POINTER(ctypes.c_int32)), ("nstate_frag_uniform", ctypes.c_int32),
+        ("n_electrons", ctypes.c_double), ("smearing", ctypes.c_double),
+        ("mixing", ctypes.c_double), ("cg_sweeps", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("batched", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("hip_stream", ctypes.c_void_p),
+    ]
+
+
+class DcdftScfInfo(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_int32), ("mu", ctypes.c_double), ("e_total", ctypes.c_double),
+                ("e_band", ctypes.c_double), ("entropy", ctypes.c_double),
+                ("residual_paper", ctypes.c_double), ("residual_out_in", ctypes.c_double),
+                ("charge", ctypes.c_double), ("ms_step", ctypes.c_float)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class DcdftError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None):
+    """Load the HIP library (built by ``paper_2606_21125_amd.build``)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} is missing: build it with paper_2606_21125_amd.build.build()")
+    lib = ctypes.CDLL(p)
+    vp = ctypes.c_void_p
+    pd = ctypes.POINTER(ctypes.c_double)
+    pi = ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "dcdft_setup": ([ctypes.POINTER(DcdftParams), ctypes.POINTER(vp)], ctypes.c_int),
+        "dcdft_scf_step": ([vp, ctypes.POINTER(DcdftScfInfo)], ctypes.c_int),
+        "dcdft_density": ([vp, pd, ctypes.c_size_t], ctypes.c_int),
+        "dcdft_density_device": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
+        "dcdft_eigenvalues": ([vp, ctypes.c_int32, pd, pd, ctypes.c_int32, pi], ctypes.c_int),
+        "dcdft_fragment_info": ([vp, ctypes.c_int32, pi, pi, pi, pi], ctypes.c_int),
+        "dcdft_get_field": ([vp, ctypes.c_int32, pd, ctypes.c_size_t], ctypes.c_int),
+        "dcdft_get_fragment_field": ([vp, ctypes.c_int32, ctypes.c_int32, pd, ctypes.c_size_t],
+                                     ctypes.c_int),
+        "dcdft_get_orbitals": ([vp, ctypes.c_int32, pd, ctypes.c_size_t], ctypes.c_int),
+        "dcdft_set_orbitals": ([vp, ctypes.c_int32, pd, ctypes.c_size_t], ctypes.c_int),
+        "dcdft_set_density": ([vp, pd, pd], ctypes.c_int),
+        "dcdft_apply_h": ([vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32],
+                          ctypes.c_int),
+        "dcdft_band_energy": ([vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32, vp,
+                               vp, vp], ctypes.c_int),
+        "dcdft_destroy": ([vp], None),
+        "dcdft_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "dcdft_last_error": ([vp, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def dcdft_last_error(ctx) -> str:
+    lib = load_library()
+    buf = ctypes.create_string_buffer(1024)
+    lib.dcdft_last_error(ctx, buf, 1024)
+    return buf.value.decode(errors="replace")
+
+
+def _check(status: int, ctx=None):
+    if status != DCDFT_OK:
+        raise DcdftError(status, dcdft_last_error(ctx))
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ipt(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def dcdft_setup(params: DcdftParams):
+    lib = load_library()
+    ctx = ctypes.c_void_p()
+    _check(lib.dcdft_setup(ctypes.byref(params), ctypes.byref(ctx)), None)
+    return ctx
+
+
+def dcdft_scf_step(ctx) -> dict:
+    info = DcdftScfInfo()
+    _check(load_library().dcdft_scf_step(ctx, ctypes.byref(info)), ctx)
+    return info.as_dict()
+
+
+def dcdft_destroy(ctx) -> None:
+    load_library().dcdft_destroy(ctx)
+
+
+class DCDFT:
+    """One DC-DFT SCF context on the GPU (owns the C context)."""
+
+    def __init__(self, n_grid: Sequence[int], cell: Sequence[float], num_fragment: Sequence[int],
+                 num_rgrid_buffer: Sequence[int], positions: np.ndarray,
+                 species_index: np.ndarray, species: Sequence, nstate_frag, n_electrons: float,
+                 smearing: float = 0.01, mixing: float = 0.3, cg_sweeps: int = 4,
+                 precision: int = PREC_FP64, batched: int = 1, seed: int = 1,
+                 hip_stream: Optional[int] = None):
+        self._lib = load_library()
+        self._pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
+        self._spi = np.ascontiguousarray(species_index, dtype=np.int32)
+        sp = (DcdftSpecies * len(species))()
+        for i, s in enumerate(species):
+            sp[i] = DcdftSpecies(s.valence, s.vloc_depth, s.vloc_sigma, s.kb_energy, s.kb_sigma,
+                                 s.kb_rcut)
+        self._sp = sp
+        nf = int(np.prod(num_fragment))
+        ns = np.asarray(nstate_frag, dtype=np.int32)
+        if ns.ndim == 0:
+            ns = np.full(nf, int(ns), dtype=np.int32)
+        self._ns = np.ascontiguousarray(ns)
+        p = DcdftParams()
+        p.n_grid[:] = [int(v) for v in n_grid]
+        p.cell[:] = [float(v) for v in cell]
+        p.num_fragment[:] = [int(v) for v in num_fragment]
+        p.num_rgrid_buffer[:] = [int(v) for v in num_rgrid_buffer]
+        p.n_atoms = self._pos.shape[0]
+        p.atom_pos = _dptr(self._pos)
+        p.atom_species = _ipt(self._spi)
+        p.n_species = len(species)
+        p.species = ctypes.cast(sp, ctypes.POINTER(DcdftSpecies))
+        p.nstate_frag = _ipt(self._ns)
+        p.nstate_frag_uniform = int(self._ns[0]) if self._ns.size else 0
+        p.n_electrons = float(n_electrons)
+        p.smearing = float(smearing)
+        p.mixing = float(mixing)
+        p.cg_sweeps = int(cg_sweeps)
+        p.precision = int(precision)
+        p.batched = int(batched)
+        p.seed = int(seed)
+        p.hip_stream = hip_stream
+        self.params = p
+        self.n_grid = tuple(int(v) for v in n_grid)
+        self.n_fragments = nf
+        self.nstate = self._ns
+        self.ctx = dcdft_setup(p)
+        shape = (ctypes.c_int32 * 3)()
+        self.frag_shape = None
+        _check(self._lib.dcdft_fragment_info(self.ctx, 0, shape, None, None, None), self.ctx)
+        self.frag_shape = (shape[0], shape[1], shape[2])
+        self.n = int(np.prod(self.frag_shape))
+
+    @classmethod
+    def from_config(cls, cfg, **kw):
+        s = cfg.system
+        args = dict(smearing=cfg.smearing, mixing=cfg.mixing, cg_sweeps=cfg.cg_sweeps,
+                    seed=cfg.seed)
+        args.update(kw)
+        return cls(cfg.n_grid, s.cell, cfg.num_fragment, cfg.num_rgrid_buffer, s.positions,
+                   s.species_index, s.species, cfg.nstate_frag, s.n_electrons, **args)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            self._lib.dcdft_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- calls -------------------------------------------------------------------------
+    def dcdft_scf_step(self) -> dict:
+        return dcdft_scf_step(self.ctx)
+
+    def dcdft_density(self) -> np.ndarray:
+        n = int(np.prod(self.n_grid))
+        out = np.empty(n)
+        _check(self._lib.dcdft_density(self.ctx, _dptr(out), n), self.ctx)
+        return out.reshape(self.n_grid[::-1])
+
+    def dcdft_density_device(self, tensor) -> None:
+        _check(self._lib.dcdft_density_device(self.ctx, ctypes.c_void_p(tensor.data_ptr()),
+                                              tensor.numel()), self.ctx)
+
+    def dcdft_eigenvalues(self, frag: int):
+        cap = int(self.nstate[frag])
+        eps = np.empty(cap)
+        w = np.empty(cap)
+        m = ctypes.c_int32()
+        _check(self._lib.dcdft_eigenvalues(self.ctx, frag, _dptr(eps), _dptr(w), cap,
+                                           ctypes.byref(m)), self.ctx)
+        return eps[:m.value], w[:m.value]
+
+    def dcdft_fragment_info(self, frag: int) -> dict:
+        shape = (ctypes.c_int32 * 3)()
+        origin = (ctypes.c_int32 * 3)()
+        m = ctypes.c_int32()
+        na = ctypes.c_int32()
+        _check(self._lib.dcdft_fragment_info(self.ctx, frag, shape, origin, ctypes.byref(m),
+                                             ctypes.byref(na)), self.ctx)
+        return dict(shape=tuple(shape), origin=tuple(origin), m=m.value, n_proj=na.value)
+
+    def dcdft_get_field(self, which: int) -> np.ndarray:
+        n = int(np.prod(self.n_grid))
+        out = np.empty(n)
+        _check(self._lib.dcdft_get_field(self.ctx, which, _dptr(out), n), self.ctx)
+        return out.reshape(self.n_grid[::-1])
+
+    def dcdft_get_fragment_field(self, frag: int, which: int) -> np.ndarray:
+        out = np.empty(self.n)
+        _check(self._lib.dcdft_get_fragment_field(self.ctx, frag, which, _dptr(out), self.n),
+               self.ctx)
+        return out
+
+    def dcdft_get_orbitals(self, frag: int) -> np.ndarray:
+        m = int(self.nstate[frag])
+        out = np.empty((m, self.n))
+        _check(self._lib.dcdft_get_orbitals(self.ctx, frag, _dptr(out), out.size), self.ctx)
+        return out
+
+    def dcdft_set_orbitals(self, frag: int, psi: np.ndarray) -> None:
+        a = np.ascontiguousarray(psi, dtype=np.float64)
+        _check(self._lib.dcdft_set_orbitals(self.ctx, frag, _dptr(a), a.size), self.ctx)
+
+    def dcdft_set_density(self, rho_tot: np.ndarray, rho_frag: Optional[np.ndarray] = None):
+        a = np.ascontiguousarray(rho_tot, dtype=np.float64)
+        b = None if rho_frag is None else np.ascontiguousarray(rho_frag, dtype=np.float64)
+        _check(self._lib.dcdft_set_density(self.ctx, _dptr(a), None if b is None else _dptr(b)),
+               self.ctx)
+
+    def dcdft_apply_h(self, frag: int, psi, hpsi, prec: int = PREC_FP64) -> None:
+        """psi, hpsi: contiguous device tensors of shape (m, n)."""
+        m = psi.shape[0]
+        _check(self._lib.dcdft_apply_h(self.ctx, frag, ctypes.c_void_p(psi.data_ptr()),
+                                       ctypes.c_void_p(hpsi.data_ptr()), m, prec), self.ctx)
+
+    def dcdft_band_energy(self, frag: int, psi, f, energy=None, grad_psi=None, grad_v=None,
+                          prec: int = PREC_FP64) -> None:
+        ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+        _check(self._lib.dcdft_band_energy(self.ctx, frag, ctypes.c_void_p(psi.data_ptr()),
+                                           ctypes.c_void_p(f.data_ptr()), psi.shape[0], prec,
+                                           ptr(energy), ptr(grad_psi), ptr(grad_v)), self.ctx)

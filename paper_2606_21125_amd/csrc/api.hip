@@ -1,0 +1,951 @@
+// Host runtime and C ABI of the DC-DFT fragment SCF library.
+//
+// Setup builds the fragment geometry (Sec. 2.2: regular core boxes plus a
+// buffer of b grid points, periodic on each fragment box), the model
+// potentials of the synthetic workloads (Gaussian local wells and s-type
+// Kleinman-Bylander projectors restricted to every fragment box), the real
+// Fourier basis that diagonalises the periodic FD Laplacian, and the initial
+// orbitals.  The SCF step issues every kernel of one iteration on the
+// context's stream; the only host synchronisation is the read-back of the
+// step's scalars at the end.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "dcdft_internal.h"
+
+using namespace dcdft;
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+// Central second-derivative weights of the nine-point stencil (Fornberg 1988).
+const double kFDh[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+const double kPi = 3.14159265358979323846;
+const double kVlocCutoffSigmas = 10.0;
+
+std::string fmt(const char *f, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, f);
+  vsnprintf(buf, sizeof(buf), f, ap);
+  va_end(ap);
+  return buf;
+}
+
+dcdft_status set_err(dcdft_ctx *c, dcdft_status s, const std::string &msg) {
+  if (c) c->last_error = msg;
+  else g_setup_error = msg;
+  return s;
+}
+
+#define HIPTRY(ctx, expr)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return set_err(ctx, e_ == hipErrorOutOfMemory ? DCDFT_ERR_OOM : DCDFT_ERR_HIP,   \
+                     fmt("%s: %s", #expr, hipGetErrorString(e_)));                     \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(dcdft_ctx *c, T **p, size_t count) {
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) return e;
+  c->allocs.push_back(q);
+  *p = static_cast<T *>(q);
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t upload(dcdft_ctx *c, T **p, const std::vector<T> &v) {
+  hipError_t e = dalloc(c, p, v.size());
+  if (e != hipSuccess) return e;
+  if (!v.empty()) e = hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+// Minimum-image displacement and index candidates along one axis.
+void axis_ball(double center, double radius, double h, int n, double length, std::vector<int> &idx,
+               std::vector<double> &disp) {
+  idx.clear();
+  disp.clear();
+  const long lo = (long)std::floor((center - radius) / h) - 1;
+  const long hi = (long)std::ceil((center + radius) / h) + 1;
+  std::vector<char> seen(n, 0);
+  for (long i = lo; i <= hi; ++i) {
+    int w = (int)(((i % n) + n) % n);
+    if (seen[w]) continue;
+    seen[w] = 1;
+    double d = w * h - center;
+    d -= length * std::nearbyint(d / length);
+    if (std::fabs(d) <= radius) {
+      idx.push_back(w);
+      disp.push_back(d);
+    }
+  }
+}
+
+struct Support {
+  std::vector<long long> g;
+  std::vector<double> v;
+};
+
+}  // namespace
+
+dcdft::OrbSet dcdft_ctx::orbset(int f0, int f1) const {
+  (void)f0;
+  (void)f1;
+  dcdft::OrbSet o;
+  o.nfrag = nF;
+  o.m_pad = m_pad;
+  o.tiles = tiles;
+  o.M_tot = M_tot;
+  o.m = d_m;
+  o.moff = d_moff;
+  o.band_frag = d_band_frag;
+  o.h_moff = moff.data();
+  o.h_m = m.data();
+  return o;
+}
+
+dcdft::KBTables dcdft_ctx::kb() const {
+  dcdft::KBTables k;
+  k.A_max = A_max;
+  k.n_pairs = n_pairs;
+  k.A = d_A;
+  k.pair_frag = d_pair_frag;
+  k.pair_atom = d_pair_atom;
+  k.pair_ptr = d_pair_ptr;
+  k.atom_l = d_atom_l;
+  k.atom_beta = d_atom_beta;
+  k.pt_ptr = d_pt_ptr;
+  k.pt_a = d_pt_a;
+  k.pt_beta = d_pt_beta;
+  k.E = d_E;
+  return k;
+}
+
+namespace {
+
+// H X for the orbitals of fragments [f0, f1) in the context layout.
+void apply_h_range(dcdft_ctx *c, int f0, int f1, const double *x, double *y) {
+  const Geo &g = c->geo;
+  OrbSet o = c->orbset(f0, f1);
+  KBTables kb = c->kb();
+  launch_hloc(g, o, f0, f1, c->d_veff, x, y, c->stream);
+  launch_kb_project(g, o, kb, f0, f1, x, c->d_C, c->stream, c->pair_first.data());
+  launch_kb_apply(g, o, kb, f0, f1, c->d_C, y, c->stream);
+}
+
+void gram(dcdft_ctx *c, int f0, int f1, const double *x, const double *y, double *G, double *Gs,
+          double *diag) {
+  OrbSet o = c->orbset(f0, f1);
+  launch_gram(c->geo, o, f0, f1, c->gram_chunks, x, y, c->d_gpart, c->stream);
+  launch_gram_reduce(c->geo, o, f0, f1, c->gram_chunks, c->d_gpart, G, Gs, diag, c->stream);
+}
+
+// Steps (a)-(l) of the fragment CG eigensolver and the Rayleigh-Ritz rotation.
+void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
+  const Geo &g = c->geo;
+  OrbSet o = c->orbset(f0, f1);
+  hipStream_t s = c->stream;
+  double *psi = c->d_psi, *w = c->d_w, *p = c->d_p, *q = c->d_q, *r = c->d_r;
+  apply_h_range(c, f0, f1, psi, w);
+  for (int sw = 0; sw < c->sweeps; ++sw) {
+    // (a) Hs = sym(<Psi, W>), a_i = <psi_i, w_i>
+    gram(c, f0, f1, psi, w, c->d_hs_full, c->d_hs, c->d_a);
+    // (b) G = W - Hs Psi  (kept in q)
+    launch_rotate(g, o, f0, f1, c->d_hs, 0, psi, w, 1.0, -1.0, q, s);
+    // (c) gamma, Fletcher-Reeves beta
+    launch_band_dot(g, o, f0, f1, q, q, 0, c->d_gamma, s);
+    launch_cg_beta(o, f0, f1, sw == 0, c->d_gamma, c->d_gamma_prev, c->d_beta, s);
+    // (d) P = -G + beta P_prev
+    launch_band_axpby(g, o, f0, f1, c->d_beta, 0.0, nullptr, -1.0, q, p, s);
+    // (e) P <- P - <Psi, P>^T Psi
+    gram(c, f0, f1, psi, p, c->d_x, nullptr, nullptr);
+    launch_rotate(g, o, f0, f1, c->d_x, 0, psi, p, 1.0, -1.0, p, s);
+    // (f) normalised direction in r
+    launch_band_dot(g, o, f0, f1, p, p, 0, c->d_nu, s);
+    launch_cg_norm(o, f0, f1, c->d_nu, c->d_inv, s);
+    launch_band_axpby(g, o, f0, f1, nullptr, 0.0, c->d_inv, 0.0, p, r, s);
+    // (g) Q = H p_hat
+    apply_h_range(c, f0, f1, r, q);
+    // (h)-(i) 2x2 Rayleigh quotient and its exact minimiser
+    launch_band_dot(g, o, f0, f1, r, w, 0, c->d_bb, s);
+    launch_band_dot(g, o, f0, f1, r, q, 0, c->d_cc, s);
+    launch_cg_theta(o, f0, f1, c->d_a, c->d_bb, c->d_cc, c->d_inv, c->d_cos, c->d_sin, s);
+    // (j) rotate each band within span(psi_i, p_hat_i)
+    launch_band_axpby(g, o, f0, f1, c->d_cos, 0.0, c->d_sin, 0.0, r, psi, s);
+    launch_band_axpby(g, o, f0, f1, c->d_cos, 0.0, c->d_sin, 0.0, q, w, s);
+    // (k)
+    launch_copy_band(o, f0, f1, c->d_gamma, c->d_gamma_prev, s);
+    // (l) Cholesky re-orthonormalisation
+    gram(c, f0, f1, psi, psi, nullptr, c->d_s, nullptr);
+    launch_cholinv(o, f0, f1, c->d_s, c->d_lin, c->d_flags, s);
+    launch_rotate(g, o, f0, f1, c->d_lin, 1, psi, nullptr, 0.0, 1.0, psi, s);
+    launch_rotate(g, o, f0, f1, c->d_lin, 1, w, nullptr, 0.0, 1.0, w, s);
+  }
+  // Rayleigh-Ritz
+  gram(c, f0, f1, psi, w, nullptr, c->d_hs, nullptr);
+  launch_syev(o, f0, f1, c->d_hs, c->d_u, c->d_eps, c->d_flags, s);
+  launch_rotate(g, o, f0, f1, c->d_u, 0, psi, nullptr, 0.0, 1.0, psi, s);
+  // core weights w_i = dV sum_core psi_i^2
+  launch_band_dot(g, o, f0, f1, psi, psi, 1, c->d_wcore, s);
+}
+
+void orthonormalize_all(dcdft_ctx *c) {
+  OrbSet o = c->orbset(0, c->nF);
+  gram(c, 0, c->nF, c->d_psi, c->d_psi, nullptr, c->d_s, nullptr);
+  launch_cholinv(o, 0, c->nF, c->d_s, c->d_lin, c->d_flags, c->stream);
+  launch_rotate(c->geo, o, 0, c->nF, c->d_lin, 1, c->d_psi, nullptr, 0.0, 1.0, c->d_psi,
+                c->stream);
+}
+
+dcdft_status check_flags(dcdft_ctx *c, int flags) {
+  if (flags & FLAG_CAPACITY)
+    return set_err(c, DCDFT_ERR_CAPACITY,
+                   fmt("fragment states hold %.6f electrons < N_e = %.6f",
+                       c->d_info_host[SC_CAPACITY], c->ne));
+  if (flags & FLAG_NOT_SPD)
+    return set_err(c, DCDFT_ERR_NOT_SPD, "overlap matrix not positive definite in Cholesky");
+  if (flags & FLAG_EIG) return set_err(c, DCDFT_ERR_EIG, "Jacobi eigensolver did not converge");
+  if (flags & FLAG_NAN) return set_err(c, DCDFT_ERR_NAN, "non-finite value in the SCF state");
+  return DCDFT_OK;
+}
+
+dcdft_status validate(const dcdft_params *p) {
+  if (!p) return set_err(nullptr, DCDFT_ERR_ARG, "params is NULL");
+  for (int d = 0; d < 3; ++d) {
+    if (p->n_grid[d] < 1) return set_err(nullptr, DCDFT_ERR_ARG, fmt("n_grid[%d] < 1", d));
+    if (!(p->cell[d] > 0.0)) return set_err(nullptr, DCDFT_ERR_ARG, fmt("cell[%d] <= 0", d));
+    if (p->num_fragment[d] < 1)
+      return set_err(nullptr, DCDFT_ERR_ARG, fmt("num_fragment[%d] < 1", d));
+    if (p->num_rgrid_buffer[d] < 0)
+      return set_err(nullptr, DCDFT_ERR_ARG, fmt("num_rgrid_buffer[%d] < 0", d));
+    if (p->n_grid[d] % p->num_fragment[d])
+      return set_err(nullptr, DCDFT_ERR_SHAPE,
+                     fmt("n_grid[%d] = %d not divisible by num_fragment[%d] = %d", d,
+                         p->n_grid[d], d, p->num_fragment[d]));
+    const int nc = p->n_grid[d] / p->num_fragment[d];
+    if (nc + 2 * p->num_rgrid_buffer[d] > p->n_grid[d])
+      return set_err(nullptr, DCDFT_ERR_SHAPE,
+                     fmt("fragment box %d exceeds the grid %d on axis %d",
+                         nc + 2 * p->num_rgrid_buffer[d], p->n_grid[d], d));
+  }
+  if (p->n_atoms < 0) return set_err(nullptr, DCDFT_ERR_ARG, "n_atoms < 0");
+  if (p->n_atoms > 0 && (!p->atom_pos || !p->atom_species))
+    return set_err(nullptr, DCDFT_ERR_ARG, "atom arrays are NULL");
+  if (p->n_species < 1 || !p->species) return set_err(nullptr, DCDFT_ERR_ARG, "no species");
+  for (int a = 0; a < p->n_atoms; ++a) {
+    if (p->atom_species[a] < 0 || p->atom_species[a] >= p->n_species)
+      return set_err(nullptr, DCDFT_ERR_ARG, fmt("atom %d has species %d", a, p->atom_species[a]));
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(p->atom_pos[3 * a + d]))
+        return set_err(nullptr, DCDFT_ERR_NAN, fmt("atom %d position not finite", a));
+  }
+  for (int s = 0; s < p->n_species; ++s) {
+    const dcdft_species &sp = p->species[s];
+    if (!(sp.vloc_sigma > 0.0) || !(sp.kb_sigma > 0.0) || !(sp.kb_rcut >= 0.0) ||
+        !std::isfinite(sp.vloc_depth) || !std::isfinite(sp.kb_energy))
+      return set_err(nullptr, DCDFT_ERR_ARG, fmt("species %d parameters invalid", s));
+  }
+  if (!(p->n_electrons > 0.0)) return set_err(nullptr, DCDFT_ERR_ARG, "n_electrons <= 0");
+  if (!(p->smearing > 0.0)) return set_err(nullptr, DCDFT_ERR_ARG, "smearing <= 0");
+  if (!(p->mixing > 0.0 && p->mixing <= 1.0))
+    return set_err(nullptr, DCDFT_ERR_ARG, "mixing outside (0, 1]");
+  if (p->cg_sweeps < 1) return set_err(nullptr, DCDFT_ERR_ARG, "cg_sweeps < 1");
+  if (p->precision != DCDFT_PREC_FP64)
+    return set_err(nullptr, DCDFT_ERR_ARG, "only DCDFT_PREC_FP64 is available in this build");
+  if (p->batched != 0 && p->batched != 1) return set_err(nullptr, DCDFT_ERR_ARG, "batched not 0/1");
+  const int nF = p->num_fragment[0] * p->num_fragment[1] * p->num_fragment[2];
+  for (int f = 0; f < nF; ++f) {
+    const int m = p->nstate_frag ? p->nstate_frag[f] : p->nstate_frag_uniform;
+    if (m < 1 || m > kMaxOrb)
+      return set_err(nullptr, DCDFT_ERR_ARG,
+                     fmt("nstate_frag of fragment %d is %d; supported range 1..%d", f, m, kMaxOrb));
+  }
+  long long n = 1;
+  for (int d = 0; d < 3; ++d)
+    n *= p->n_grid[d] / p->num_fragment[d] + 2 * p->num_rgrid_buffer[d];
+  if (n >= (1LL << 24)) return set_err(nullptr, DCDFT_ERR_ARG, "fragment box >= 2^24 points");
+  const int plane = (p->n_grid[0] / p->num_fragment[0] + 2 * p->num_rgrid_buffer[0]) *
+                    (p->n_grid[1] / p->num_fragment[1] + 2 * p->num_rgrid_buffer[1]);
+  if (plane > 1024)
+    return set_err(nullptr, DCDFT_ERR_ARG, "fragment x-y plane larger than 1024 points");
+  return DCDFT_OK;
+}
+
+dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
+  Geo &g = c->geo;
+  const int nF = c->nF;
+  const long long Ng = g.Ng;
+  // ---- local potential on the global grid ----
+  std::vector<double> vloc(Ng, 0.0);
+  std::vector<int> ix, iy, iz;
+  std::vector<double> dx, dy, dz;
+  for (int a = 0; a < p->n_atoms; ++a) {
+    const dcdft_species &sp = p->species[p->atom_species[a]];
+    const double R = kVlocCutoffSigmas * sp.vloc_sigma;
+    const double *pos = p->atom_pos + 3 * a;
+    axis_ball(pos[0], R, g.h[0], g.N[0], p->cell[0], ix, dx);
+    axis_ball(pos[1], R, g.h[1], g.N[1], p->cell[1], iy, dy);
+    axis_ball(pos[2], R, g.h[2], g.N[2], p->cell[2], iz, dz);
+    const double inv2s2 = 1.0 / (2.0 * sp.vloc_sigma * sp.vloc_sigma);
+    for (size_t k = 0; k < iz.size(); ++k)
+      for (size_t j = 0; j < iy.size(); ++j)
+        for (size_t i = 0; i < ix.size(); ++i) {
+          const double r2 = dx[i] * dx[i] + dy[j] * dy[j] + dz[k] * dz[k];
+          if (r2 > R * R) continue;
+          vloc[ix[i] + (long long)g.N[0] * (iy[j] + (long long)g.N[1] * iz[k])] +=
+              sp.vloc_depth * std::exp(-r2 * inv2s2);
+        }
+  }
+  // ---- global KB projectors ----
+  std::vector<Support> sup(p->n_atoms);
+  std::vector<double> Eatom(p->n_atoms);
+  for (int a = 0; a < p->n_atoms; ++a) {
+    const dcdft_species &sp = p->species[p->atom_species[a]];
+    Eatom[a] = sp.kb_energy;
+    const double R = sp.kb_rcut;
+    const double *pos = p->atom_pos + 3 * a;
+    axis_ball(pos[0], R, g.h[0], g.N[0], p->cell[0], ix, dx);
+    axis_ball(pos[1], R, g.h[1], g.N[1], p->cell[1], iy, dy);
+    axis_ball(pos[2], R, g.h[2], g.N[2], p->cell[2], iz, dz);
+    const double inv2s2 = 1.0 / (2.0 * sp.kb_sigma * sp.kb_sigma);
+    double nrm = 0.0;
+    for (size_t k = 0; k < iz.size(); ++k)
+      for (size_t j = 0; j < iy.size(); ++j)
+        for (size_t i = 0; i < ix.size(); ++i) {
+          const double r2 = dx[i] * dx[i] + dy[j] * dy[j] + dz[k] * dz[k];
+          if (r2 > R * R) continue;
+          const double b = std::exp(-r2 * inv2s2);
+          sup[a].g.push_back(ix[i] + (long long)g.N[0] * (iy[j] + (long long)g.N[1] * iz[k]));
+          sup[a].v.push_back(b);
+          nrm += b * b;
+        }
+    if (nrm > 0.0) {
+      const double sc = 1.0 / std::sqrt(g.dv * nrm);
+      for (double &v : sup[a].v) v *= sc;
+    }
+  }
+  // ---- restriction to each fragment box ----
+  std::vector<int> pair_frag, pair_atom, atom_l, Acount(nF, 0);
+  std::vector<long long> pair_ptr(1, 0);
+  std::vector<double> atom_beta;
+  std::vector<std::vector<double>> Ef(nF);
+  std::vector<long long> pt_count((size_t)nF * g.n + 1, 0);
+  c->pair_first.assign(nF + 1, 0);
+  for (int f = 0; f < nF; ++f) {
+    c->pair_first[f] = (int)pair_frag.size();
+    const int ax = f % g.F[0], ay = (f / g.F[0]) % g.F[1], az = f / (g.F[0] * g.F[1]);
+    const int org[3] = {ax * g.nc[0] - g.b[0], ay * g.nc[1] - g.b[1], az * g.nc[2] - g.b[2]};
+    for (int a = 0; a < p->n_atoms; ++a) {
+      const long long e0 = (long long)atom_l.size();
+      for (size_t e = 0; e < sup[a].g.size(); ++e) {
+        const long long gg = sup[a].g[e];
+        const int gx = (int)(gg % g.N[0]), gy = (int)((gg / g.N[0]) % g.N[1]),
+                  gz = (int)(gg / ((long long)g.N[0] * g.N[1]));
+        const int lx = ((gx - org[0]) % g.N[0] + g.N[0]) % g.N[0];
+        const int ly = ((gy - org[1]) % g.N[1] + g.N[1]) % g.N[1];
+        const int lz = ((gz - org[2]) % g.N[2] + g.N[2]) % g.N[2];
+        if (lx >= g.nl[0] || ly >= g.nl[1] || lz >= g.nl[2]) continue;
+        atom_l.push_back(lx + g.nl[0] * (ly + g.nl[1] * lz));
+        atom_beta.push_back(sup[a].v[e]);
+      }
+      if ((long long)atom_l.size() > e0) {
+        pair_frag.push_back(f);
+        pair_atom.push_back(Acount[f]);
+        pair_ptr.push_back((long long)atom_l.size());
+        Ef[f].push_back(Eatom[a]);
+        for (long long e = e0; e < (long long)atom_l.size(); ++e)
+          pt_count[(size_t)f * g.n + atom_l[e] + 1]++;
+        Acount[f]++;
+      }
+    }
+  }
+  c->pair_first[nF] = (int)pair_frag.size();
+  c->n_pairs = (int)pair_frag.size();
+  c->A = Acount;
+  c->A_max = 1;
+  for (int f = 0; f < nF; ++f) c->A_max = std::max(c->A_max, Acount[f]);
+  // point-major entries (counting sort by local point)
+  for (size_t q = 1; q < pt_count.size(); ++q) pt_count[q] += pt_count[q - 1];
+  std::vector<long long> fill(pt_count.begin(), pt_count.end() - 1);
+  std::vector<int> pt_a(atom_l.size());
+  std::vector<double> pt_beta(atom_l.size());
+  for (int P = 0; P < c->n_pairs; ++P) {
+    const int f = pair_frag[P];
+    for (long long e = pair_ptr[P]; e < pair_ptr[P + 1]; ++e) {
+      const long long slot = fill[(size_t)f * g.n + atom_l[e]]++;
+      pt_a[slot] = pair_atom[P];
+      pt_beta[slot] = atom_beta[e];
+    }
+  }
+  std::vector<double> Eflat((size_t)nF * c->A_max, 0.0);
+  for (int f = 0; f < nF; ++f)
+    for (size_t a = 0; a < Ef[f].size(); ++a) Eflat[(size_t)f * c->A_max + a] = Ef[f][a];
+
+  HIPTRY(c, upload(c, &c->d_pair_frag, pair_frag));
+  HIPTRY(c, upload(c, &c->d_pair_atom, pair_atom));
+  HIPTRY(c, upload(c, &c->d_pair_ptr, pair_ptr));
+  HIPTRY(c, upload(c, &c->d_atom_l, atom_l));
+  HIPTRY(c, upload(c, &c->d_atom_beta, atom_beta));
+  HIPTRY(c, upload(c, &c->d_pt_ptr, pt_count));
+  HIPTRY(c, upload(c, &c->d_pt_a, pt_a));
+  HIPTRY(c, upload(c, &c->d_pt_beta, pt_beta));
+  HIPTRY(c, upload(c, &c->d_E, Eflat));
+  HIPTRY(c, upload(c, &c->d_A, Acount));
+  HIPTRY(c, upload(c, &c->d_vloc, vloc));
+
+  // ---- real Fourier basis of each axis and the FD eigenvalue of each column ----
+  for (int d = 0; d < 3; ++d) {
+    const int N = g.N[d];
+    std::vector<double> Q((size_t)N * N), QT((size_t)N * N), lam(N);
+    for (int k = 0; k < N; ++k) {
+      int q;
+      int kind;  // 0 constant, 1 cos, 2 sin, 3 alternating
+      if (k == 0) {
+        q = 0;
+        kind = 0;
+      } else if (N % 2 == 0 && k == N - 1) {
+        q = N / 2;
+        kind = 3;
+      } else {
+        q = (k + 1) / 2;
+        kind = (k % 2) ? 1 : 2;
+      }
+      double l = kFDh[0];
+      for (int j = 1; j <= 4; ++j) l += 2.0 * kFDh[j] * std::cos(2.0 * kPi * j * q / N);
+      lam[k] = l / (g.h[d] * g.h[d]);
+      for (int j = 0; j < N; ++j) {
+        double v;
+        if (kind == 0) v = 1.0 / std::sqrt((double)N);
+        else if (kind == 3) v = ((j % 2) ? -1.0 : 1.0) / std::sqrt((double)N);
+        else {
+          const double ang = 2.0 * kPi * (double)q * j / N;
+          v = std::sqrt(2.0 / N) * (kind == 1 ? std::cos(ang) : std::sin(ang));
+        }
+        Q[(size_t)j * N + k] = v;
+        QT[(size_t)k * N + j] = v;
+      }
+    }
+    HIPTRY(c, upload(c, &c->d_qf[d], Q));
+    HIPTRY(c, upload(c, &c->d_qi[d], QT));
+    HIPTRY(c, upload(c, &c->d_lam[d], lam));
+  }
+  return DCDFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dcdft_status_string(dcdft_status s) {
+  switch (s) {
+    case DCDFT_OK: return "ok";
+    case DCDFT_ERR_ARG: return "invalid argument";
+    case DCDFT_ERR_SHAPE: return "invalid grid or fragment shape";
+    case DCDFT_ERR_CAPACITY: return "fragment states cannot hold the electrons";
+    case DCDFT_ERR_NOT_SPD: return "overlap matrix not positive definite";
+    case DCDFT_ERR_EIG: return "subspace eigensolver did not converge";
+    case DCDFT_ERR_NAN: return "non-finite value";
+    case DCDFT_ERR_HIP: return "HIP runtime error";
+    case DCDFT_ERR_OOM: return "device out of memory";
+    case DCDFT_ERR_NOT_CONVERGED: return "not converged";
+  }
+  return "unknown status";
+}
+
+dcdft_status dcdft_last_error(const dcdft_ctx *c, char *buf, size_t n) {
+  if (!buf || n == 0) return DCDFT_ERR_ARG;
+  const std::string &s = c ? c->last_error : g_setup_error;
+  const size_t k = std::min(n - 1, s.size());
+  memcpy(buf, s.data(), k);
+  buf[k] = 0;
+  return DCDFT_OK;
+}
+
+void dcdft_destroy(dcdft_ctx *c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  for (void *q : c->allocs) hipFree(q);
+  if (c->d_info_host) hipHostFree(c->d_info_host);
+  if (c->ev0) hipEventDestroy(c->ev0);
+  if (c->ev1) hipEventDestroy(c->ev1);
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  delete c;
+}
+
+dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
+  if (!out) return set_err(nullptr, DCDFT_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  dcdft_status st = validate(p);
+  if (st != DCDFT_OK) return st;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return set_err(nullptr, DCDFT_ERR_HIP, "no HIP device available");
+  dcdft_ctx *c = new (std::nothrow) dcdft_ctx();
+  if (!c) return set_err(nullptr, DCDFT_ERR_OOM, "host allocation failed");
+  Geo &g = c->geo;
+  g.Ng = 1;
+  for (int d = 0; d < 3; ++d) {
+    g.N[d] = p->n_grid[d];
+    g.F[d] = p->num_fragment[d];
+    g.b[d] = p->num_rgrid_buffer[d];
+    g.nc[d] = g.N[d] / g.F[d];
+    g.nl[d] = g.nc[d] + 2 * g.b[d];
+    g.h[d] = p->cell[d] / g.N[d];
+    g.Ng *= g.N[d];
+  }
+  g.n = g.nl[0] * g.nl[1] * g.nl[2];
+  g.dv = g.h[0] * g.h[1] * g.h[2];
+  c->nF = g.F[0] * g.F[1] * g.F[2];
+  c->m.resize(c->nF);
+  c->moff.assign(c->nF + 1, 0);
+  int mmax = 1;
+  for (int f = 0; f < c->nF; ++f) {
+    c->m[f] = p->nstate_frag ? p->nstate_frag[f] : p->nstate_frag_uniform;
+    c->moff[f + 1] = c->moff[f] + c->m[f];
+    mmax = std::max(mmax, c->m[f]);
+  }
+  c->M_tot = c->moff[c->nF];
+  c->tiles = (mmax + 15) / 16;
+  c->m_pad = 16 * c->tiles;
+  c->ne = p->n_electrons;
+  c->smearing = p->smearing;
+  c->mixing = p->mixing;
+  c->sweeps = p->cg_sweeps;
+  c->precision = p->precision;
+  c->batched = p->batched;
+  c->seed = p->seed;
+  // Gram chunks: aim at >= 1024 workgroups over all fragments
+  {
+    int ch = (1024 + c->nF - 1) / c->nF;
+    const int maxch = std::max(1, g.n / 256);
+    c->gram_chunks = std::max(1, std::min(ch, maxch));
+  }
+  if (p->hip_stream) {
+    c->stream = (hipStream_t)p->hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      dcdft_destroy(c);
+      return set_err(nullptr, DCDFT_ERR_HIP, "stream creation failed");
+    }
+    c->own_stream = true;
+  }
+  auto fail = [&](dcdft_status s) {
+    g_setup_error = c->last_error;
+    dcdft_destroy(c);
+    return s;
+  };
+  st = build_and_upload(c, p);
+  if (st != DCDFT_OK) return fail(st);
+  const long long norb = c->M_tot * (long long)g.n;
+  const long long mp2 = (long long)c->m_pad * c->m_pad;
+  std::vector<int> band_frag(c->M_tot);
+  for (int f = 0; f < c->nF; ++f)
+    for (long long B = c->moff[f]; B < c->moff[f + 1]; ++B) band_frag[B] = f;
+  c->n_part = 1024;
+#define ALLOC(ptr, n)                                                     \
+  do {                                                                    \
+    hipError_t e_ = dalloc(c, &(ptr), (size_t)(n));                       \
+    if (e_ != hipSuccess) {                                               \
+      c->last_error = fmt("allocation of %s failed", #ptr);              \
+      return fail(e_ == hipErrorOutOfMemory ? DCDFT_ERR_OOM : DCDFT_ERR_HIP); \
+    }                                                                     \
+  } while (0)
+  {
+    hipError_t e = upload(c, &c->d_m, c->m);
+    if (e == hipSuccess) e = upload(c, &c->d_moff, c->moff);
+    if (e == hipSuccess) e = upload(c, &c->d_band_frag, band_frag);
+    if (e != hipSuccess) {
+      c->last_error = "table upload failed";
+      return fail(DCDFT_ERR_HIP);
+    }
+  }
+  ALLOC(c->d_psi, norb);
+  ALLOC(c->d_w, norb);
+  ALLOC(c->d_p, norb);
+  ALLOC(c->d_q, norb);
+  ALLOC(c->d_r, norb);
+  ALLOC(c->d_C, (long long)c->nF * c->A_max * c->m_pad);
+  ALLOC(c->d_vh, g.Ng);
+  ALLOC(c->d_rho_in, g.Ng);
+  ALLOC(c->d_rho_out, g.Ng);
+  ALLOC(c->d_fft_a, g.Ng);
+  ALLOC(c->d_fft_b, g.Ng);
+  ALLOC(c->d_veff, (long long)c->nF * g.n);
+  ALLOC(c->d_rhof_in, (long long)c->nF * g.n);
+  ALLOC(c->d_rhof_out, (long long)c->nF * g.n);
+  ALLOC(c->d_gpart, (long long)c->nF * c->gram_chunks * 4 * mp2);
+  ALLOC(c->d_hs_full, c->nF * mp2);
+  ALLOC(c->d_hs, c->nF * mp2);
+  ALLOC(c->d_x, c->nF * mp2);
+  ALLOC(c->d_s, c->nF * mp2);
+  ALLOC(c->d_lin, c->nF * mp2);
+  ALLOC(c->d_u, c->nF * mp2);
+  double **bands[] = {&c->d_gamma, &c->d_gamma_prev, &c->d_beta, &c->d_nu, &c->d_inv, &c->d_a,
+                      &c->d_bb, &c->d_cc, &c->d_cos, &c->d_sin, &c->d_eps, &c->d_wcore,
+                      &c->d_occ};
+  for (double **b : bands) ALLOC(*b, c->M_tot);
+  ALLOC(c->d_scal, SC_COUNT);
+  ALLOC(c->d_part, (long long)c->n_part * 6);
+  ALLOC(c->d_flags, 1);
+#undef ALLOC
+  if (hipHostMalloc((void **)&c->d_info_host, SC_COUNT * sizeof(double), 0) != hipSuccess) {
+    c->last_error = "pinned host allocation failed";
+    return fail(DCDFT_ERR_HIP);
+  }
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    c->last_error = "event creation failed";
+    return fail(DCDFT_ERR_HIP);
+  }
+  // initial state
+  const double rho0 = c->ne / (p->cell[0] * p->cell[1] * p->cell[2]);
+  launch_fill(c->d_rho_in, g.Ng, rho0, c->stream);
+  launch_fill(c->d_rho_out, g.Ng, 0.0, c->stream);
+  launch_fill(c->d_vh, g.Ng, 0.0, c->stream);
+  launch_fill(c->d_rhof_in, (long long)c->nF * g.n, rho0, c->stream);
+  launch_fill(c->d_rhof_out, (long long)c->nF * g.n, 0.0, c->stream);
+  launch_fill(c->d_p, norb, 0.0, c->stream);
+  launch_fill(c->d_C, (long long)c->nF * c->A_max * c->m_pad, 0.0, c->stream);
+  for (double **b : bands) launch_fill(*b, c->M_tot, 0.0, c->stream);
+  launch_fill(c->d_scal, SC_COUNT, 0.0, c->stream);
+  launch_fill_int(c->d_flags, 1, 0, c->stream);
+  launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, c->stream);
+  launch_init_orbitals(g, c->orbset(0, c->nF), c->seed, c->d_psi, c->stream);
+  orthonormalize_all(c);
+  int flags = 0;
+  if (hipMemcpyAsync(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    c->last_error = fmt("setup kernels failed: %s", hipGetErrorString(hipGetLastError()));
+    return fail(DCDFT_ERR_HIP);
+  }
+  if (flags) {
+    c->last_error = "initial orbitals not linearly independent";
+    return fail(DCDFT_ERR_NOT_SPD);
+  }
+  *out = c;
+  return DCDFT_OK;
+}
+
+dcdft_status dcdft_scf_step(dcdft_ctx *c, dcdft_scf_info *info) {
+  if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  const Geo &g = c->geo;
+  hipStream_t s = c->stream;
+  OrbSet o = c->orbset(0, c->nF);
+  HIPTRY(c, hipEventRecord(c->ev0, s));
+  launch_fill_int(c->d_flags, 1, 0, s);
+  // 1. Hartree potential of rho_tot^in
+  launch_poisson(g, c->d_rho_in, c->d_vh, c->d_fft_a, c->d_fft_b, c->d_qf, c->d_qi, c->d_lam, s);
+  // 2. fragment effective potentials
+  launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, s);
+  // 3. fragment eigensolvers
+  if (c->batched) {
+    eigensolver_range(c, 0, c->nF);
+  } else {
+    for (int f = 0; f < c->nF; ++f) eigensolver_range(c, f, f + 1);
+  }
+  // 4. global chemical potential
+  launch_fermi(o, c->d_eps, c->d_wcore, c->ne, c->smearing, c->d_occ, c->d_scal, c->d_flags, s);
+  // 5. densities
+  launch_density(g, o, 0, c->nF, c->d_psi, c->d_occ, c->d_rhof_out, c->d_rho_out, s);
+  // 6-8. energy terms, residuals, mixing
+  launch_global_terms(g, c->d_rho_in, c->d_rho_out, c->d_vh, c->mixing, c->d_part, c->n_part,
+                      c->d_scal, s, c->ne, c->smearing);
+  launch_frag_mix(g, c->nF, c->d_rhof_in, c->d_rhof_out, c->mixing, s);
+  launch_nan_check(c->d_eps, c->M_tot, c->d_flags, s);
+  launch_nan_check(c->d_rho_out, g.Ng, c->d_flags, s);
+  HIPTRY(c, hipGetLastError());
+  HIPTRY(c, hipEventRecord(c->ev1, s));
+  HIPTRY(c, hipMemcpyAsync(c->d_info_host, c->d_scal, SC_COUNT * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+  int flags = 0;
+  HIPTRY(c, hipMemcpyAsync(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPTRY(c, hipStreamSynchronize(s));
+  c->iter++;
+  const double *sc = c->d_info_host;
+  if (info) {
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    info->iter = c->iter;
+    info->mu = sc[SC_MU];
+    info->e_band = sc[SC_EBAND];
+    info->entropy = sc[SC_ENTROPY];
+    info->e_total = sc[SC_EBAND] - sc[SC_HXC] + sc[SC_EH] + sc[SC_EXC] - c->smearing * sc[SC_ENTROPY];
+    info->residual_paper = sc[SC_RES_PAPER];
+    info->residual_out_in = sc[SC_RES_OUT_IN];
+    info->charge = sc[SC_CHARGE];
+    info->ms_step = ms;
+  }
+  return check_flags(c, flags);
+}
+
+dcdft_status dcdft_density(const dcdft_ctx *c, double *rho, size_t n) {
+  if (!c || !rho) return set_err(const_cast<dcdft_ctx *>(c), DCDFT_ERR_ARG, "NULL argument");
+  if (n < (size_t)c->geo.Ng)
+    return set_err(const_cast<dcdft_ctx *>(c), DCDFT_ERR_ARG,
+                   fmt("buffer holds %zu values, %lld needed", n, c->geo.Ng));
+  HIPTRY(const_cast<dcdft_ctx *>(c), hipMemcpyAsync(rho, c->d_rho_out, c->geo.Ng * sizeof(double),
+                                                   hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(const_cast<dcdft_ctx *>(c), hipStreamSynchronize(c->stream));
+  return DCDFT_OK;
+}
+
+dcdft_status dcdft_density_device(const dcdft_ctx *c, void *dptr, size_t n) {
+  if (!c || !dptr) return set_err(const_cast<dcdft_ctx *>(c), DCDFT_ERR_ARG, "NULL argument");
+  if (n < (size_t)c->geo.Ng)
+    return set_err(const_cast<dcdft_ctx *>(c), DCDFT_ERR_ARG,
+                   fmt("buffer holds %zu values, %lld needed", n, c->geo.Ng));
+  HIPTRY(const_cast<dcdft_ctx *>(c), hipMemcpyAsync(dptr, c->d_rho_out, c->geo.Ng * sizeof(double),
+                                                   hipMemcpyDeviceToDevice, c->stream));
+  HIPTRY(const_cast<dcdft_ctx *>(c), hipStreamSynchronize(c->stream));
+  return DCDFT_OK;
+}
+
+dcdft_status dcdft_eigenvalues(const dcdft_ctx *c, int32_t frag, double *eps, double *w,
+                               int32_t cap, int32_t *m) {
+  dcdft_ctx *cc = const_cast<dcdft_ctx *>(c);
+  if (!c || !eps || !m) return set_err(cc, DCDFT_ERR_ARG, "NULL argument");
+  if (frag < 0 || frag >= c->nF) return set_err(cc, DCDFT_ERR_ARG, fmt("fragment %d out of range", frag));
+  *m = c->m[frag];
+  if (cap < c->m[frag])
+    return set_err(cc, DCDFT_ERR_ARG, fmt("capacity %d < %d states", cap, c->m[frag]));
+  HIPTRY(cc, hipMemcpyAsync(eps, c->d_eps + c->moff[frag], c->m[frag] * sizeof(double),
+                            hipMemcpyDeviceToHost, c->stream));
+  if (w)
+    HIPTRY(cc, hipMemcpyAsync(w, c->d_wcore + c->moff[frag], c->m[frag] * sizeof(double),
+                              hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(cc, hipStreamSynchronize(c->stream));
+  return DCDFT_OK;
+}
+
+dcdft_status dcdft_fragment_info(const dcdft_ctx *c, int32_t frag, int32_t *shape,
+                                 int32_t *origin, int32_t *m, int32_t *n_proj) {
+  dcdft_ctx *cc = const_cast<dcdft_ctx *>(c);
+  if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  if (frag < 0 || frag >= c->nF) return set_err(cc, DCDFT_ERR_ARG, fmt("fragment %d out of range", frag));
+  const Geo &g = c->geo;
+  const int a[3] = {frag % g.F[0], (frag / g.F[0]) % g.F[1], frag / (g.F[0] * g.F[1])};
+  for (int d = 0; d < 3; ++d) {
+    if (shape) shape[d] = g.nl[d];
+    if (origin) origin[d] = a[d] * g.nc[d] - g.b[d];
+  }
+  if (m) *m = c->m[frag];
+  if (n_proj) *n_proj = c->A[frag];
+  return DCDFT_OK;
+}
+
+dcdft_status dcdft_get_field(const dcdft_ctx *c, int32_t which, double *host, size_t n) {
+  dcdft_ctx *cc = const_cast<dcdft_ctx *>(c);
+  if (!c || !host) return set_err(cc, DCDFT_ERR_ARG, "NULL argument");
+  if (n < (size_t)c->geo.Ng) return set_err(cc, DCDFT_ERR_ARG, fmt("%lld values needed", c->geo.Ng));
+  const double *src = nullptr;
+  switch (which) {
+    case DCDFT_FIELD_VLOC: src = c->d_vloc; break;
+    case DCDFT_FIELD_VH: src = c->d_vh; break;
+    case DCDFT_FIELD_RHO_IN: src = c->d_rho_in; break;
+    case DCDFT_FIELD_RHO_OUT: src = c->d_rho_out; break;
+    default: return set_err(cc, DCDFT_ERR_ARG, fmt("unknown field %d", which));
+  }
+  HIPTRY(cc, hipMemcpyAsync(host, src, c->geo.Ng * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(cc, hipStreamSynchronize(c->stream));
+  return DCDFT_OK;
+}
+
+dcdft_status dcdft_get_fragment_field(const dcdft_ctx *c, int32_t frag, int32_t which,
+                                      double *host, size_t n) {
+  dcdft_ctx *cc = const_cast<dcdft_ctx *>(c);
+  if (!c || !host) return set_err(cc, DCDFT_ERR_ARG, "NULL argument");
+  if (frag < 0 || frag >= c->nF) return set_err(cc, DCDFT_ERR_ARG, fmt("fragment %d out of range", frag));
+  if (n < (size_t)c->geo.n) return set_err(cc, DCDFT_ERR_ARG, fmt("%d values needed", c->geo.n));
+  const double *src = nullptr;
+  switch (which) {
+    case DCDFT_FFIELD_VEFF: src = c->d_veff; break;
+    case DCDFT_FFIELD_RHO_IN: src = c->d_rhof_in; break;
+    case DCDFT_FFIELD_RHO_OUT: src = c->d_rhof_out; break;
+    default: return set_err(cc, DCDFT_ERR_ARG, fmt("unknown fragment field %d", which));
+  }
+  HIPTRY(cc, hipMemcpyAsync(host, src + (long long)frag * c->geo.n, c->geo.n * sizeof(double),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(cc, hipStreamSynchronize(c->stream));
+  return DCDFT_OK;
+}
+
+dcdft_status dcdft_get_orbitals(const dcdft_ctx *c, int32_t frag, double *host, size_t count) {
+  dcdft_ctx *cc = const_cast<dcdft_ctx *>(c);
+  if (!c || !host) return set_err(cc, DCDFT_ERR_ARG, "NULL argument");
+  if (frag < 0 || frag >= c->nF) return set_err(cc, DCDFT_ERR_ARG, fmt("fragment %d out of range", frag));
+  const size_t need = (size_t)c->m[frag] * c->geo.n;
+  if (count < need) return set_err(cc, DCDFT_ERR_ARG, fmt("%zu values needed", need));
+  HIPTRY(cc, hipMemcpyAsync(host, c->d_psi + c->moff[frag] * c->geo.n, need * sizeof(double),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(cc, hipStreamSynchronize(c->stream));
+  return DCDFT_OK;
+}
+
+dcdft_status dcdft_set_orbitals(dcdft_ctx *c, int32_t frag, const double *host, size_t count) {
+  if (!c || !host) return set_err(c, DCDFT_ERR_ARG, "NULL argument");
+  if (frag < 0 || frag >= c->nF) return set_err(c, DCDFT_ERR_ARG, fmt("fragment %d out of range", frag));
+  const size_t need = (size_t)c->m[frag] * c->geo.n;
+  if (count < need) return set_err(c, DCDFT_ERR_ARG, fmt("%zu values needed", need));
+  for (size_t i = 0; i < need; ++i)
+    if (!std::isfinite(host[i])) return set_err(c, DCDFT_ERR_NAN, "non-finite orbital value");
+  HIPTRY(c, hipMemcpyAsync(c->d_psi + c->moff[frag] * c->geo.n, host, need * sizeof(double),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPTRY(c, hipStreamSynchronize(c->stream));
+  return DCDFT_OK;
+}
+
+dcdft_status dcdft_set_density(dcdft_ctx *c, const double *rho_tot_in, const double *rho_frag_in) {
+  if (!c || !rho_tot_in) return set_err(c, DCDFT_ERR_ARG, "NULL argument");
+  const Geo &g = c->geo;
+  for (long long i = 0; i < g.Ng; ++i)
+    if (!std::isfinite(rho_tot_in[i])) return set_err(c, DCDFT_ERR_NAN, "non-finite density");
+  HIPTRY(c, hipMemcpyAsync(c->d_rho_in, rho_tot_in, g.Ng * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream));
+  if (rho_frag_in) {
+    HIPTRY(c, hipMemcpyAsync(c->d_rhof_in, rho_frag_in, (size_t)c->nF * g.n * sizeof(double),
+                             hipMemcpyHostToDevice, c->stream));
+  } else {
+    std::vector<double> rf((size_t)c->nF * g.n);
+    for (int f = 0; f < c->nF; ++f) {
+      const int a[3] = {f % g.F[0], (f / g.F[0]) % g.F[1], f / (g.F[0] * g.F[1])};
+      for (int l = 0; l < g.n; ++l) {
+        const int lc[3] = {l % g.nl[0], (l / g.nl[0]) % g.nl[1], l / (g.nl[0] * g.nl[1])};
+        long long gi = 0, stride = 1;
+        for (int d = 0; d < 3; ++d) {
+          const int gd = ((a[d] * g.nc[d] - g.b[d] + lc[d]) % g.N[d] + g.N[d]) % g.N[d];
+          gi += gd * stride;
+          stride *= g.N[d];
+        }
+        rf[(size_t)f * g.n + l] = rho_tot_in[gi];
+      }
+    }
+    HIPTRY(c, hipMemcpyAsync(c->d_rhof_in, rf.data(), rf.size() * sizeof(double),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+  }
+  // V_eff follows the new density (V_H recomputed from it)
+  launch_poisson(g, c->d_rho_in, c->d_vh, c->d_fft_a, c->d_fft_b, c->d_qf, c->d_qi, c->d_lam,
+                 c->stream);
+  launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, c->stream);
+  HIPTRY(c, hipGetLastError());
+  HIPTRY(c, hipStreamSynchronize(c->stream));
+  return DCDFT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Run fn over an external block of m vectors of fragment frag, in chunks of at
+// most m_pad vectors, with a temporary single-fragment layout on the device.
+struct ExtLayout {
+  int *m = nullptr;
+  long long *moff = nullptr;
+  int *band_frag = nullptr;
+  std::vector<long long> h_moff;
+  std::vector<int> h_m;
+};
+
+dcdft_status make_ext(dcdft_ctx *c, int frag, int mm, ExtLayout &L) {
+  L.h_m.assign(c->nF, 0);
+  L.h_m[frag] = mm;
+  L.h_moff.assign(c->nF + 1, 0);
+  for (int f = 0; f < c->nF; ++f) L.h_moff[f + 1] = L.h_moff[f] + L.h_m[f];
+  std::vector<int> bf(std::max(mm, 1), frag);
+  HIPTRY(c, hipMalloc(&L.m, c->nF * sizeof(int)));
+  HIPTRY(c, hipMalloc(&L.moff, (c->nF + 1) * sizeof(long long)));
+  HIPTRY(c, hipMalloc(&L.band_frag, bf.size() * sizeof(int)));
+  HIPTRY(c, hipMemcpy(L.m, L.h_m.data(), c->nF * sizeof(int), hipMemcpyHostToDevice));
+  HIPTRY(c, hipMemcpy(L.moff, L.h_moff.data(), (c->nF + 1) * sizeof(long long),
+                      hipMemcpyHostToDevice));
+  HIPTRY(c, hipMemcpy(L.band_frag, bf.data(), bf.size() * sizeof(int), hipMemcpyHostToDevice));
+  return DCDFT_OK;
+}
+
+void free_ext(ExtLayout &L) {
+  if (L.m) hipFree(L.m);
+  if (L.moff) hipFree(L.moff);
+  if (L.band_frag) hipFree(L.band_frag);
+}
+
+dcdft_status apply_h_ext(dcdft_ctx *c, int frag, const double *psi, double *hpsi, int m) {
+  const Geo &g = c->geo;
+  for (int i0 = 0; i0 < m; i0 += c->m_pad) {
+    const int mm = std::min(c->m_pad, m - i0);
+    ExtLayout L;
+    dcdft_status st = make_ext(c, frag, mm, L);
+    if (st != DCDFT_OK) {
+      free_ext(L);
+      return st;
+    }
+    OrbSet o = c->orbset(frag, frag + 1);
+    o.m = L.m;
+    o.moff = L.moff;
+    o.band_frag = L.band_frag;
+    o.h_moff = L.h_moff.data();
+    o.h_m = L.h_m.data();
+    o.M_tot = mm;
+    KBTables kb = c->kb();
+    const double *x = psi + (long long)i0 * g.n;
+    double *y = hpsi + (long long)i0 * g.n;
+    launch_hloc(g, o, frag, frag + 1, c->d_veff, x, y, c->stream);
+    launch_kb_project(g, o, kb, frag, frag + 1, x, c->d_C, c->stream, c->pair_first.data());
+    launch_kb_apply(g, o, kb, frag, frag + 1, c->d_C, y, c->stream);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    free_ext(L);
+    if (e != hipSuccess) return set_err(c, DCDFT_ERR_HIP, hipGetErrorString(e));
+  }
+  return DCDFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dcdft_status dcdft_apply_h(dcdft_ctx *c, int32_t frag, const void *psi, void *hpsi, int32_t m,
+                           int32_t prec) {
+  if (!c || !psi || !hpsi) return set_err(c, DCDFT_ERR_ARG, "NULL argument");
+  if (frag < 0 || frag >= c->nF) return set_err(c, DCDFT_ERR_ARG, fmt("fragment %d out of range", frag));
+  if (m < 0) return set_err(c, DCDFT_ERR_ARG, "m < 0");
+  if (prec != DCDFT_PREC_FP64) return set_err(c, DCDFT_ERR_ARG, "only FP64 vectors are supported");
+  if (psi == hpsi) return set_err(c, DCDFT_ERR_ARG, "psi and hpsi may not alias");
+  if (m == 0) return DCDFT_OK;
+  return apply_h_ext(c, frag, (const double *)psi, (double *)hpsi, m);
+}
+
+dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, const double *f,
+                               int32_t m, int32_t prec, double *energy, void *grad_psi,
+                               void *grad_v) {
+  if (!c || !psi || !f) return set_err(c, DCDFT_ERR_ARG, "NULL argument");
+  if (frag < 0 || frag >= c->nF) return set_err(c, DCDFT_ERR_ARG, fmt("fragment %d out of range", frag));
+  if (m < 1) return set_err(c, DCDFT_ERR_ARG, "m < 1");
+  if (prec != DCDFT_PREC_FP64) return set_err(c, DCDFT_ERR_ARG, "only FP64 vectors are supported");
+  const Geo &g = c->geo;
+  double *hp = nullptr, *eb = nullptr;
+  HIPTRY(c, hipMalloc(&hp, (size_t)m * g.n * sizeof(double)));
+  if (hipMalloc(&eb, (size_t)m * sizeof(double)) != hipSuccess) {
+    hipFree(hp);
+    return set_err(c, DCDFT_ERR_OOM, "scratch allocation failed");
+  }
+  dcdft_status st = apply_h_ext(c, frag, (const double *)psi, hp, m);
+  if (st == DCDFT_OK) {
+    launch_band_energy(g, m, (const double *)psi, hp, f, eb, energy, (double *)grad_psi,
+                       (double *)grad_v, c->stream);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) st = set_err(c, DCDFT_ERR_HIP, hipGetErrorString(e));
+  }
+  hipFree(hp);
+  hipFree(eb);
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,218 @@
+// Internal declarations of the DC-DFT fragment SCF library: context layout,
+// device helpers and the host launchers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dcdft.h"
+
+namespace dcdft {
+
+constexpr int kWave = 64;
+constexpr int kMaxTiles = 5;        // m_pad <= 80 orbitals per fragment (16-wide MFMA tiles)
+constexpr int kMaxOrb = 16 * kMaxTiles;
+
+// Device-side status flags (bit mask, read back once per step).
+enum : int { FLAG_NOT_SPD = 1, FLAG_EIG = 2, FLAG_CAPACITY = 4, FLAG_NAN = 8 };
+
+// Slots of the device scalar block.
+enum : int {
+  SC_MU = 0, SC_EBAND, SC_ENTROPY, SC_CAPACITY,
+  SC_HXC, SC_EH, SC_EXC, SC_CHARGE, SC_RES_OUT_IN, SC_RES_PAPER,
+  SC_COUNT
+};
+
+// Geometry shared by all kernels (passed by value).
+struct Geo {
+  int N[3];       // global grid
+  int nl[3];      // fragment box (nx, ny, nz)
+  int nc[3];      // core size per axis
+  int b[3];       // buffer per axis
+  int F[3];       // fragments per axis
+  int n;          // points per fragment
+  long long Ng;   // global points
+  double h[3];
+  double dv;
+};
+
+struct OrbSet {           // flattened orbital layout [M_tot][n]
+  int nfrag;
+  int m_pad;              // multiple of 16, >= max m
+  int tiles;              // m_pad / 16
+  long long M_tot;
+  const int *m;           // [F]
+  const long long *moff;  // [F + 1] band offset of each fragment
+  const int *band_frag;   // [M_tot]
+  const long long *h_moff;  // host copy of moff (launch ranges)
+  const int *h_m;           // host copy of m
+  long long b0(int f) const { return h_moff[f]; }
+  long long nb(int f0, int f1) const { return h_moff[f1] - h_moff[f0]; }
+};
+
+struct KBTables {
+  int A_max;
+  int n_pairs;                       // total (fragment, atom) pairs
+  const int *A;                      // [F] atoms per fragment
+  const int *pair_frag;              // [n_pairs]
+  const int *pair_atom;              // [n_pairs] local atom index
+  const long long *pair_ptr;         // [n_pairs + 1] into atom entries
+  const int *atom_l;                 // local point of each atom entry
+  const double *atom_beta;
+  const long long *pt_ptr;           // [F * n + 1] into point entries
+  const int *pt_a;                   // local atom index of each point entry
+  const double *pt_beta;
+  const double *E;                   // [F][A_max]
+};
+
+void fail_hip(hipError_t e, const char *what);
+
+}  // namespace dcdft
+
+struct dcdft_ctx {
+  dcdft::Geo geo;
+  int nF = 0;
+  std::vector<int> m;
+  std::vector<long long> moff;
+  int m_pad = 0, tiles = 0;
+  long long M_tot = 0;
+  double ne = 0, smearing = 0, mixing = 0;
+  int sweeps = 0, precision = 0, batched = 1;
+  uint64_t seed = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int iter = 0;
+  int gram_chunks = 1;
+
+  // fragment -> host copies
+  std::vector<int> A;                // projectors per fragment
+  std::vector<int> pair_first;       // [F + 1] first (fragment, atom) pair of each fragment
+  int A_max = 0;
+
+  // device allocations (freed in destroy)
+  std::vector<void *> allocs;
+
+  // tables
+  int *d_m = nullptr;
+  long long *d_moff = nullptr;
+  int *d_band_frag = nullptr;
+  // KB
+  int n_pairs = 0;
+  int *d_A = nullptr, *d_pair_frag = nullptr, *d_pair_atom = nullptr;
+  long long *d_pair_ptr = nullptr, *d_pt_ptr = nullptr;
+  int *d_atom_l = nullptr, *d_pt_a = nullptr;
+  double *d_atom_beta = nullptr, *d_pt_beta = nullptr, *d_E = nullptr;
+  double *d_C = nullptr;             // [F][A_max][m_pad] projections
+
+  // orbital arrays [M_tot][n]
+  double *d_psi = nullptr, *d_w = nullptr, *d_p = nullptr, *d_q = nullptr, *d_r = nullptr;
+
+  // fields
+  double *d_vloc = nullptr, *d_vh = nullptr, *d_rho_in = nullptr, *d_rho_out = nullptr;
+  double *d_fft_a = nullptr, *d_fft_b = nullptr;   // Poisson work arrays
+  double *d_qf[3] = {nullptr, nullptr, nullptr};   // forward basis per axis [N][N]
+  double *d_qi[3] = {nullptr, nullptr, nullptr};   // inverse basis per axis
+  double *d_lam[3] = {nullptr, nullptr, nullptr};  // per-axis FD eigenvalue of each basis column
+  double *d_veff = nullptr, *d_rhof_in = nullptr, *d_rhof_out = nullptr;
+
+  // small matrices [F][m_pad][m_pad]
+  double *d_gpart = nullptr;         // Gram partials [F][chunks*4][m_pad][m_pad]
+  double *d_hs_full = nullptr, *d_hs = nullptr, *d_x = nullptr, *d_s = nullptr, *d_lin = nullptr,
+         *d_u = nullptr;
+
+  // per-band [M_tot]
+  double *d_gamma = nullptr, *d_gamma_prev = nullptr, *d_beta = nullptr, *d_nu = nullptr,
+         *d_inv = nullptr, *d_a = nullptr, *d_bb = nullptr, *d_cc = nullptr, *d_cos = nullptr,
+         *d_sin = nullptr, *d_eps = nullptr, *d_wcore = nullptr, *d_occ = nullptr;
+  double *d_scal = nullptr;          // [SC_COUNT]
+  double *d_part = nullptr;          // reduction partials
+  int n_part = 0;
+  int *d_flags = nullptr;
+  double *d_info_host = nullptr;     // pinned host mirror of scalars
+
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::string last_error;
+
+  dcdft::OrbSet orbset(int f0, int f1) const;
+  dcdft::KBTables kb() const;
+};
+
+namespace dcdft {
+
+// ---- launchers (all asynchronous on the given stream) -------------------------------------
+
+// Y = (-1/2 L_FD + V_eff) X for every orbital of fragments [f0, f1).
+void launch_hloc(const Geo &g, const OrbSet &o, int f0, int f1, const double *veff,
+                 const double *x, double *y, hipStream_t s);
+// C[f][a][i] = dV sum beta_a(l) X_i(l)
+void launch_kb_project(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1,
+                       const double *x, double *C, hipStream_t s, const int *h_pair_first);
+// Y_i(l) += sum_a beta_a(l) E_a C[f][a][i]
+void launch_kb_apply(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1,
+                     const double *C, double *y, hipStream_t s);
+// part[f][w] = X^T Y partial sums (row form: G_ij = sum_l X_i(l) Y_j(l))
+void launch_gram(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, const double *x,
+                 const double *y, double *part, hipStream_t s);
+// G = dV sum partials; Gs = sym(G) (either may be null); diag -> per-band (may be null)
+void launch_gram_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
+                        const double *part, double *G, double *Gs, double *diag, hipStream_t s);
+// Y_j = cz Z_j + cm sum_i R[j][i] X_i with R = M^T (trans 0) or M (trans 1)
+void launch_rotate(const Geo &g, const OrbSet &o, int f0, int f1, const double *M, int trans,
+                   const double *x, const double *z, double cz, double cm, double *y,
+                   hipStream_t s);
+// per-band dot: out[B] = dV sum_l X_B(l) Y_B(l); core != 0 restricts to core points
+void launch_band_dot(const Geo &g, const OrbSet &o, int f0, int f1, const double *x,
+                     const double *y, int core, double *out, hipStream_t s);
+// Y_B = a[B] Y_B + b[B] X_B  (a, b per band; null a means 0, null b means 0)
+void launch_band_axpby(const Geo &g, const OrbSet &o, int f0, int f1, const double *a,
+                       double a_const, const double *b, double b_const, const double *x,
+                       double *y, hipStream_t s);
+// CG scalar steps
+void launch_cg_beta(const OrbSet &o, int f0, int f1, int first, const double *gamma,
+                    const double *gamma_prev, double *beta, hipStream_t s);
+void launch_cg_norm(const OrbSet &o, int f0, int f1, const double *nu, double *inv,
+                    hipStream_t s);
+void launch_cg_theta(const OrbSet &o, int f0, int f1, const double *a, const double *b,
+                     const double *c, const double *inv, double *cs, double *sn, hipStream_t s);
+void launch_copy_band(const OrbSet &o, int f0, int f1, const double *src, double *dst,
+                      hipStream_t s);
+// S -> Linv (row-major lower-triangular inverse of the Cholesky factor), FP64
+void launch_cholinv(const OrbSet &o, int f0, int f1, const double *S, double *Linv, int *flags,
+                    hipStream_t s);
+// Hs -> U (eigenvectors as columns), eps (ascending), FP64 Jacobi
+void launch_syev(const OrbSet &o, int f0, int f1, const double *Hs, double *U, double *eps,
+                 int *flags, hipStream_t s);
+// global chemical potential, occupations, band energy, entropy (one workgroup)
+void launch_fermi(const OrbSet &o, const double *eps, const double *w, double ne, double sigma,
+                  double *occ, double *scal, int *flags, hipStream_t s);
+// rho_alpha^out and the core scatter into rho_tot^out
+void launch_density(const Geo &g, const OrbSet &o, int f0, int f1, const double *psi,
+                    const double *occ, double *rhof_out, double *rho_out, hipStream_t s);
+// V_eff^alpha = V_loc + V_H (gathered) + V_xc(rho_alpha^in)
+void launch_veff(const Geo &g, int f0, int f1, const double *vloc, const double *vh,
+                 const double *rhof_in, double *veff, hipStream_t s);
+// Energy terms, residuals and mixing on the global grid; fragment mixing
+void launch_global_terms(const Geo &g, double *rho_in, const double *rho_out, const double *vh,
+                         double mixing, double *part, int n_part, double *scal, hipStream_t s,
+                         double ne, double sigma);
+void launch_frag_mix(const Geo &g, int nfrag, double *rhof_in, const double *rhof_out,
+                     double mixing, hipStream_t s);
+// Poisson: V_H from rho (exact FD solution, zero mean)
+void launch_poisson(const Geo &g, const double *rho, double *vh, double *wa, double *wb,
+                    double *const qf[3], double *const qi[3], double *const lam[3],
+                    hipStream_t s);
+// SplitMix64 initial orbitals
+void launch_init_orbitals(const Geo &g, const OrbSet &o, uint64_t seed, double *psi,
+                          hipStream_t s);
+void launch_fill(double *p, long long n, double v, hipStream_t s);
+void launch_fill_int(int *p, long long n, int v, hipStream_t s);
+void launch_nan_check(const double *p, long long n, int *flags, hipStream_t s);
+// band energy: E = sum f_i <psi_i|H psi_i>, grads
+void launch_band_energy(const Geo &g, int nb, const double *psi, const double *hpsi,
+                        const double *f, double *eb, double *energy, double *grad_psi,
+                        double *grad_v, hipStream_t s);
+
+}  // namespace dcdft

@@ -1,0 +1,367 @@
+// Global-grid and fragment-field kernels of the SCF iteration: the global
+// chemical potential (Sec. 2.2), fragment and total densities (Eqs. (2)-(4)),
+// the fragment effective potential (Eq. (5)), the Hartree potential of the
+// total density, the LDA exchange-correlation (Perdew-Zunger 1981), the
+// energy terms, residuals and linear mixing.
+#include "dcdft_internal.h"
+
+namespace dcdft {
+
+namespace {
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ inline double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < nw; ++w) t += red[w];
+  return t;
+}
+
+__device__ inline double block_min(double v, double *red) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = red[0];
+  for (int w = 1; w < nw; ++w) t = fmin(t, red[w]);
+  return t;
+}
+
+// Fermi-Dirac occupation 1 / (1 + e^x) without overflow.
+__device__ inline double fermi(double x) {
+  if (x >= 0.0) {
+    const double t = exp(-x);
+    return t / (1.0 + t);
+  }
+  return 1.0 / (1.0 + exp(x));
+}
+
+// Perdew-Zunger 1981 unpolarised LDA: eps_xc and v_xc, zero below rho = 1e-20.
+__device__ inline void pz81(double rho, double &exc, double &vxc) {
+  if (!(rho >= 1e-20)) {
+    exc = 0.0;
+    vxc = 0.0;
+    return;
+  }
+  const double pi = 3.14159265358979323846;
+  const double rs = cbrt(3.0 / (4.0 * pi * rho));
+  const double cx = (3.0 / (4.0 * pi)) * cbrt(9.0 * pi / 4.0);
+  const double ex = -cx / rs;
+  const double vx = 4.0 / 3.0 * ex;
+  double ec, vc;
+  if (rs >= 1.0) {
+    const double g = -0.1423, b1 = 1.0529, b2 = 0.3334;
+    const double sq = sqrt(rs);
+    const double den = 1.0 + b1 * sq + b2 * rs;
+    ec = g / den;
+    vc = ec * (1.0 + 7.0 / 6.0 * b1 * sq + 4.0 / 3.0 * b2 * rs) / den;
+  } else {
+    const double A = 0.0311, B = -0.048, C = 0.0020, D = -0.0116;
+    const double ln = log(rs);
+    ec = A * ln + B + C * rs * ln + D * rs;
+    vc = A * ln + (B - A / 3.0) + 2.0 / 3.0 * C * rs * ln + (2.0 * D - C) / 3.0 * rs;
+  }
+  exc = ex + ec;
+  vxc = vx + vc;
+}
+
+__device__ inline long long global_of_local(const Geo &g, int f, int l) {
+  const int ax = f % g.F[0], ay = (f / g.F[0]) % g.F[1], az = f / (g.F[0] * g.F[1]);
+  const int lx = l % g.nl[0], ly = (l / g.nl[0]) % g.nl[1], lz = l / (g.nl[0] * g.nl[1]);
+  int gx = (ax * g.nc[0] - g.b[0] + lx) % g.N[0];
+  int gy = (ay * g.nc[1] - g.b[1] + ly) % g.N[1];
+  int gz = (az * g.nc[2] - g.b[2] + lz) % g.N[2];
+  if (gx < 0) gx += g.N[0];
+  if (gy < 0) gy += g.N[1];
+  if (gz < 0) gz += g.N[2];
+  return gx + (long long)g.N[0] * (gy + (long long)g.N[1] * gz);
+}
+
+__device__ inline bool is_core(const Geo &g, int l) {
+  const int lx = l % g.nl[0], ly = (l / g.nl[0]) % g.nl[1], lz = l / (g.nl[0] * g.nl[1]);
+  return lx >= g.b[0] && lx < g.b[0] + g.nc[0] && ly >= g.b[1] && ly < g.b[1] + g.nc[1] &&
+         lz >= g.b[2] && lz < g.b[2] + g.nc[2];
+}
+
+// N(mu) = sum 2 f((eps - mu) / sigma) w by bisection over the bracket
+// [min eps - 50 sigma, max eps + 50 sigma], one workgroup.
+__global__ void __launch_bounds__(1024) k_fermi(long long nb, const double *__restrict__ eps,
+                                                const double *__restrict__ w, double ne,
+                                                double sigma, double *__restrict__ occ,
+                                                double *__restrict__ scal, int *flags) {
+  __shared__ double red[16];
+  double cap = 0.0, lo = 1e300, hi = 1e300;
+  for (long long i = threadIdx.x; i < nb; i += blockDim.x) {
+    cap += 2.0 * w[i];
+    lo = fmin(lo, eps[i]);
+    hi = fmin(hi, -eps[i]);
+  }
+  cap = block_sum(cap, red);
+  lo = block_min(lo, red) - 50.0 * sigma;
+  hi = -block_min(hi, red) + 50.0 * sigma;
+  const bool ok = cap >= ne * (1.0 - 1e-12);
+  for (int it = 0; it < 200 && ok; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid == lo || mid == hi) break;
+    double cnt = 0.0;
+    for (long long i = threadIdx.x; i < nb; i += blockDim.x)
+      cnt += 2.0 * fermi((eps[i] - mid) / sigma) * w[i];
+    cnt = block_sum(cnt, red);
+    if (cnt < ne) lo = mid;
+    else hi = mid;
+  }
+  const double mu = 0.5 * (lo + hi);
+  double eb = 0.0, ent = 0.0;
+  for (long long i = threadIdx.x; i < nb; i += blockDim.x) {
+    const double fo = fermi((eps[i] - mu) / sigma);
+    occ[i] = fo;
+    eb += 2.0 * fo * eps[i] * w[i];
+    double t = 0.0;
+    if (fo > 0.0) t += fo * log(fo);
+    if (fo < 1.0) t += (1.0 - fo) * log(1.0 - fo);
+    ent += -2.0 * w[i] * t;
+  }
+  eb = block_sum(eb, red);
+  ent = block_sum(ent, red);
+  if (threadIdx.x == 0) {
+    scal[SC_MU] = mu;
+    scal[SC_EBAND] = eb;
+    scal[SC_ENTROPY] = ent;
+    scal[SC_CAPACITY] = cap;
+    if (!ok) atomicOr(flags, FLAG_CAPACITY);
+  }
+}
+
+// rho_alpha^out(l) = sum_i 2 f_i psi_i(l)^2; core points also written to rho_tot^out.
+__global__ void __launch_bounds__(256) k_density(Geo g, const long long *__restrict__ moff,
+                                                 int f0, int f1, const double *__restrict__ psi,
+                                                 const double *__restrict__ occ,
+                                                 double *__restrict__ rhof_out,
+                                                 double *__restrict__ rho_out) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)(f1 - f0) * g.n) return;
+  const int f = f0 + (int)(idx / g.n);
+  const int l = (int)(idx % g.n);
+  double acc = 0.0;
+  for (long long B = moff[f]; B < moff[f + 1]; ++B) {
+    const double v = psi[B * g.n + l];
+    acc += 2.0 * occ[B] * v * v;
+  }
+  rhof_out[(long long)f * g.n + l] = acc;
+  if (is_core(g, l)) rho_out[global_of_local(g, f, l)] = acc;
+}
+
+__global__ void __launch_bounds__(256) k_veff(Geo g, int f0, int f1, const double *__restrict__ vloc,
+                                              const double *__restrict__ vh,
+                                              const double *__restrict__ rhof_in,
+                                              double *__restrict__ veff) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)(f1 - f0) * g.n) return;
+  const int f = f0 + (int)(idx / g.n);
+  const int l = (int)(idx % g.n);
+  const long long gi = global_of_local(g, f, l);
+  double exc, vxc;
+  pz81(rhof_in[(long long)f * g.n + l], exc, vxc);
+  veff[(long long)f * g.n + l] = vloc[gi] + vh[gi] + vxc;
+}
+
+// Energy terms on rho^in, charge and residuals, then linear mixing of rho_tot.
+// part[block][6]: sum rho_in (V_H + V_xc), sum rho_in V_H, sum rho_in eps_xc,
+// sum rho_out, sum |rho_out - rho_in|, sum |rho_new - rho_in|.
+__global__ void __launch_bounds__(256) k_global_terms(Geo g, double *__restrict__ rho_in,
+                                                      const double *__restrict__ rho_out,
+                                                      const double *__restrict__ vh, double mixing,
+                                                      double *__restrict__ part) {
+  __shared__ double red[16];
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.Ng;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double ri = rho_in[i], ro = rho_out[i], v = vh[i];
+    double exc, vxc;
+    pz81(ri, exc, vxc);
+    s[0] += ri * (v + vxc);
+    s[1] += ri * v;
+    s[2] += ri * exc;
+    s[3] += ro;
+    s[4] += fabs(ro - ri);
+    const double rn = ri + mixing * (ro - ri);
+    s[5] += fabs(rn - ri);
+    rho_in[i] = rn;
+  }
+  for (int k = 0; k < 6; ++k) {
+    const double t = block_sum(s[k], red);
+    if (threadIdx.x == 0) part[blockIdx.x * 6 + k] = t;
+  }
+}
+
+__global__ void __launch_bounds__(64) k_global_final(Geo g, int nblk, double ne, double sigma,
+                                                     const double *__restrict__ part,
+                                                     double *__restrict__ scal) {
+  if (threadIdx.x != 0) return;
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < nblk; ++b)
+    for (int k = 0; k < 6; ++k) s[k] += part[b * 6 + k];
+  const double dv = g.dv;
+  scal[SC_HXC] = dv * s[0];
+  scal[SC_EH] = 0.5 * dv * s[1];
+  scal[SC_EXC] = dv * s[2];
+  scal[SC_CHARGE] = dv * s[3];
+  scal[SC_RES_OUT_IN] = dv * s[4] / ne;
+  scal[SC_RES_PAPER] = dv * s[5] / ne;
+  (void)sigma;
+}
+
+__global__ void __launch_bounds__(256) k_frag_mix(long long total, double *__restrict__ rin,
+                                                  const double *__restrict__ rout, double mixing) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x)
+    rin[i] = rin[i] + mixing * (rout[i] - rin[i]);
+}
+
+// out[a][k][c] = sum_j in[a][j][c] Q[j][k]   (axis of length n, inner stride C)
+__global__ void __launch_bounds__(256) k_axis_transform(long long total, int n, long long C,
+                                                        const double *__restrict__ in,
+                                                        const double *__restrict__ Q,
+                                                        double *__restrict__ out) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long c = e % C;
+    const long long ak = e / C;
+    const int k = (int)(ak % n);
+    const long long a = ak / n;
+    const double *src = in + a * n * C + c;
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) acc += src[(long long)j * C] * Q[(long long)j * n + k];
+    out[e] = acc;
+  }
+}
+
+// V_hat = -4 pi rho_hat / (lx + ly + lz), zero for the constant mode
+__global__ void __launch_bounds__(256) k_poisson_scale(Geo g, const double *__restrict__ lx,
+                                                       const double *__restrict__ ly,
+                                                       const double *__restrict__ lz,
+                                                       double *__restrict__ v) {
+  const double pi = 3.14159265358979323846;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < g.Ng;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int kx = (int)(e % g.N[0]);
+    const int ky = (int)((e / g.N[0]) % g.N[1]);
+    const int kz = (int)(e / ((long long)g.N[0] * g.N[1]));
+    const double lam = lx[kx] + ly[ky] + lz[kz];
+    v[e] = (kx == 0 && ky == 0 && kz == 0) ? 0.0 : -4.0 * pi * v[e] / lam;
+  }
+}
+
+__global__ void k_fill(double *p, long long n, double v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_int(int *p, long long n, int v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_nan_check(const double *p, long long n, int *flags) {
+  bool bad = false;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    if (!isfinite(p[i])) bad = true;
+  if (bad) atomicOr(flags, FLAG_NAN);
+}
+
+inline int grid_for(long long n, int block) {
+  long long b = (n + block - 1) / block;
+  if (b > 8192) b = 8192;
+  return (int)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+void launch_fermi(const OrbSet &o, const double *eps, const double *w, double ne, double sigma,
+                  double *occ, double *scal, int *flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_fermi, dim3(1), dim3(1024), 0, s, o.M_tot, eps, w, ne, sigma, occ, scal,
+                     flags);
+}
+
+void launch_density(const Geo &g, const OrbSet &o, int f0, int f1, const double *psi,
+                    const double *occ, double *rhof_out, double *rho_out, hipStream_t s) {
+  const long long total = (long long)(f1 - f0) * g.n;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_density, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, o.moff,
+                     f0, f1, psi, occ, rhof_out, rho_out);
+}
+
+void launch_veff(const Geo &g, int f0, int f1, const double *vloc, const double *vh,
+                 const double *rhof_in, double *veff, hipStream_t s) {
+  const long long total = (long long)(f1 - f0) * g.n;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_veff, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, f0, f1,
+                     vloc, vh, rhof_in, veff);
+}
+
+void launch_global_terms(const Geo &g, double *rho_in, const double *rho_out, const double *vh,
+                         double mixing, double *part, int n_part, double *scal, hipStream_t s,
+                         double ne, double sigma) {
+  hipLaunchKernelGGL(k_global_terms, dim3(n_part), dim3(256), 0, s, g, rho_in, rho_out, vh,
+                     mixing, part);
+  hipLaunchKernelGGL(k_global_final, dim3(1), dim3(64), 0, s, g, n_part, ne, sigma, part, scal);
+}
+
+void launch_frag_mix(const Geo &g, int nfrag, double *rhof_in, const double *rhof_out,
+                     double mixing, hipStream_t s) {
+  const long long total = (long long)nfrag * g.n;
+  hipLaunchKernelGGL(k_frag_mix, dim3(grid_for(total, 256)), dim3(256), 0, s, total, rhof_in,
+                     rhof_out, mixing);
+}
+
+void launch_poisson(const Geo &g, const double *rho, double *vh, double *wa, double *wb,
+                    double *const qf[3], double *const qi[3], double *const lam[3],
+                    hipStream_t s) {
+  const long long Ng = g.Ng;
+  const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+  const int gb = grid_for(Ng, 256);
+  // forward: x (C = 1), y (C = Nx), z (C = Nx Ny)
+  hipLaunchKernelGGL(k_axis_transform, dim3(gb), dim3(256), 0, s, Ng, Nx, 1LL, rho, qf[0], wa);
+  hipLaunchKernelGGL(k_axis_transform, dim3(gb), dim3(256), 0, s, Ng, Ny, (long long)Nx, wa, qf[1],
+                     wb);
+  hipLaunchKernelGGL(k_axis_transform, dim3(gb), dim3(256), 0, s, Ng, Nz, (long long)Nx * Ny, wb,
+                     qf[2], wa);
+  hipLaunchKernelGGL(k_poisson_scale, dim3(gb), dim3(256), 0, s, g, lam[0], lam[1], lam[2], wa);
+  hipLaunchKernelGGL(k_axis_transform, dim3(gb), dim3(256), 0, s, Ng, Nz, (long long)Nx * Ny, wa,
+                     qi[2], wb);
+  hipLaunchKernelGGL(k_axis_transform, dim3(gb), dim3(256), 0, s, Ng, Ny, (long long)Nx, wb, qi[1],
+                     wa);
+  hipLaunchKernelGGL(k_axis_transform, dim3(gb), dim3(256), 0, s, Ng, Nx, 1LL, wa, qi[0], vh);
+}
+
+void launch_fill(double *p, long long n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+}
+
+void launch_fill_int(int *p, long long n, int v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_int, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+}
+
+void launch_nan_check(const double *p, long long n, int *flags, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_nan_check, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, flags);
+}
+
+}  // namespace dcdft

@@ -1,0 +1,319 @@
+// Orbital-array kernels: the local part of the fragment Hamiltonian (Eq. (5):
+// nine-point FD kinetic operator, periodic on the fragment box, plus V_eff),
+// the Kleinman-Bylander projection and application, per-band reductions and
+// updates, and the initial-orbital generator.
+#include "dcdft_internal.h"
+
+namespace dcdft {
+
+namespace {
+
+// Central second-derivative weights of the nine-point stencil (half-width 4):
+// c0 = -205/72, c1 = 8/5, c2 = -1/5, c3 = 8/315, c4 = -1/560 (Fornberg 1988).
+__constant__ double kFD[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic block sum (fixed shuffle tree, waves combined in index order).
+__device__ inline double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < nw; ++w) t += red[w];
+  return t;
+}
+
+// One workgroup per orbital; thread (x, y) of the plane marches along z with a
+// nine-plane register window; x/y neighbours come from the current plane in LDS.
+__global__ void __launch_bounds__(1024) k_hloc(Geo g, const int *__restrict__ band_frag,
+                                               long long b0, const double *__restrict__ veff,
+                                               const double *__restrict__ x,
+                                               double *__restrict__ y) {
+  extern __shared__ double lds[];
+  const long long B = b0 + blockIdx.x;
+  const int f = band_frag[B];
+  const int nx = g.nl[0], ny = g.nl[1], nz = g.nl[2];
+  const int plane = nx * ny;
+  const int t = threadIdx.x;
+  const int ix = t % nx, iy = t / nx;
+  const double *xb = x + B * (long long)g.n;
+  double *yb = y + B * (long long)g.n;
+  const double *vb = veff + (long long)f * g.n;
+  const double ihx = 1.0 / (g.h[0] * g.h[0]), ihy = 1.0 / (g.h[1] * g.h[1]),
+               ihz = 1.0 / (g.h[2] * g.h[2]);
+  const double c0 = -0.5 * kFD[0] * (ihx + ihy + ihz);
+  double ax[4], ay[4], az[4];
+  int ox[8], oy[8];
+#pragma unroll
+  for (int k = 1; k <= 4; ++k) {
+    ax[k - 1] = -0.5 * kFD[k] * ihx;
+    ay[k - 1] = -0.5 * kFD[k] * ihy;
+    az[k - 1] = -0.5 * kFD[k] * ihz;
+    ox[2 * (k - 1)] = ((ix + k) % nx) + iy * nx;
+    ox[2 * (k - 1) + 1] = ((ix - k) % nx + nx) % nx + iy * nx;
+    oy[2 * (k - 1)] = ix + ((iy + k) % ny) * nx;
+    oy[2 * (k - 1) + 1] = ix + (((iy - k) % ny + ny) % ny) * nx;
+  }
+  double win[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const int zz = ((k - 4) % nz + nz) % nz;
+    win[k] = xb[(long long)zz * plane + t];
+  }
+  for (int z = 0; z < nz; ++z) {
+    double *pl = lds + (z & 1) * plane;
+    pl[t] = win[4];
+    __syncthreads();
+    double acc = c0 * win[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      acc += ax[k] * (pl[ox[2 * k]] + pl[ox[2 * k + 1]]);
+      acc += ay[k] * (pl[oy[2 * k]] + pl[oy[2 * k + 1]]);
+      acc += az[k] * (win[5 + k] + win[3 - k]);
+    }
+    const long long e = (long long)z * plane + t;
+    acc += vb[e] * win[4];
+    yb[e] = acc;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) win[k] = win[k + 1];
+    const int zn = (z + 5) % nz;
+    win[8] = xb[(long long)zn * plane + t];
+  }
+}
+
+// c[f][a][i] = dV sum_e beta_e X_i(l_e) over the support entries of atom a.
+__global__ void __launch_bounds__(256) k_kb_project(Geo g, KBTables kb, const int *__restrict__ m,
+                                                    const long long *__restrict__ moff, int m_pad,
+                                                    int pair0, const double *__restrict__ x,
+                                                    double *__restrict__ C) {
+  const int P = pair0 + blockIdx.x;
+  const int f = kb.pair_frag[P];
+  const int a = kb.pair_atom[P];
+  const long long e0 = kb.pair_ptr[P], e1 = kb.pair_ptr[P + 1];
+  const int mf = m[f];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  for (int i = wave; i < mf; i += nw) {
+    const double *xb = x + (moff[f] + i) * (long long)g.n;
+    double acc = 0.0;
+    for (long long e = e0 + lane; e < e1; e += 64) acc += kb.atom_beta[e] * xb[kb.atom_l[e]];
+    acc = wave_sum(acc);
+    if (lane == 0) C[((long long)f * kb.A_max + a) * m_pad + i] = g.dv * acc;
+  }
+}
+
+// Y_i(l) += sum over the projectors covering l of beta_a(l) E_a C[f][a][i].
+__global__ void __launch_bounds__(256) k_kb_apply(Geo g, KBTables kb, const int *__restrict__ m,
+                                                  const long long *__restrict__ moff, int m_pad,
+                                                  int f0, int f1, const double *__restrict__ C,
+                                                  double *__restrict__ y) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = (long long)(f1 - f0) * g.n;
+  if (idx >= total) return;
+  const int f = f0 + (int)(idx / g.n);
+  const int l = (int)(idx % g.n);
+  const long long q = (long long)f * g.n + l;
+  const long long e0 = kb.pt_ptr[q], e1 = kb.pt_ptr[q + 1];
+  if (e0 == e1) return;
+  const double *Cf = C + (long long)f * kb.A_max * m_pad;
+  const double *Ef = kb.E + (long long)f * kb.A_max;
+  const int mf = m[f];
+  for (int i = 0; i < mf; ++i) {
+    double s = 0.0;
+    for (long long e = e0; e < e1; ++e) {
+      const int a = kb.pt_a[e];
+      s += kb.pt_beta[e] * Ef[a] * Cf[(long long)a * m_pad + i];
+    }
+    y[(moff[f] + i) * (long long)g.n + l] += s;
+  }
+}
+
+__device__ inline bool is_core(const Geo &g, int l) {
+  const int lx = l % g.nl[0];
+  const int ly = (l / g.nl[0]) % g.nl[1];
+  const int lz = l / (g.nl[0] * g.nl[1]);
+  return lx >= g.b[0] && lx < g.b[0] + g.nc[0] && ly >= g.b[1] && ly < g.b[1] + g.nc[1] &&
+         lz >= g.b[2] && lz < g.b[2] + g.nc[2];
+}
+
+__global__ void __launch_bounds__(256) k_band_dot(Geo g, long long b0, const double *__restrict__ x,
+                                                  const double *__restrict__ y, int core,
+                                                  double *__restrict__ out) {
+  __shared__ double red[16];
+  const long long B = b0 + blockIdx.x;
+  const double *xb = x + B * (long long)g.n;
+  const double *yb = y + B * (long long)g.n;
+  double acc = 0.0;
+  if (core) {
+    for (int l = threadIdx.x; l < g.n; l += blockDim.x)
+      if (is_core(g, l)) acc += xb[l] * yb[l];
+  } else {
+    for (int l = threadIdx.x; l < g.n; l += blockDim.x) acc += xb[l] * yb[l];
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) out[B] = g.dv * acc;
+}
+
+__global__ void __launch_bounds__(256) k_band_axpby(Geo g, long long b0, long long nb,
+                                                    const double *__restrict__ a, double a_const,
+                                                    const double *__restrict__ b, double b_const,
+                                                    const double *__restrict__ x,
+                                                    double *__restrict__ y) {
+  const long long total = nb * (long long)g.n;
+  const long long base = b0 * (long long)g.n;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long B = b0 + e / g.n;
+    const double ca = a ? a[B] : a_const;
+    const double cb = b ? b[B] : b_const;
+    const double yv = (a || a_const != 0.0) ? ca * y[base + e] : 0.0;
+    y[base + e] = yv + cb * x[base + e];
+  }
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014) as a counter-based generator.
+__device__ inline uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(256) k_init_orbitals(Geo g, const int *__restrict__ band_frag,
+                                                       const long long *__restrict__ moff,
+                                                       long long M_tot, uint64_t seed,
+                                                       double *__restrict__ psi) {
+  const long long total = M_tot * (long long)g.n;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long B = e / g.n;
+    const uint64_t l = (uint64_t)(e % g.n);
+    const int f = band_frag[B];
+    const uint64_t i = (uint64_t)(B - moff[f]);
+    const uint64_t key = ((uint64_t)f << 40) | (i << 24) | l;
+    const uint64_t z = splitmix64(seed, key + 1);
+    psi[e] = (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+  }
+}
+
+// E = sum_i f_i dV sum_l psi_i H psi_i (one block per band then host-side sum in a
+// second pass), grad_psi = 2 f dV H psi, grad_v = dV sum f psi^2.
+__global__ void __launch_bounds__(256) k_band_energy_terms(Geo g, const double *__restrict__ psi,
+                                                           const double *__restrict__ hpsi,
+                                                           const double *__restrict__ f,
+                                                           double *__restrict__ eb,
+                                                           double *__restrict__ grad_psi) {
+  __shared__ double red[16];
+  const long long B = blockIdx.x;
+  const double *pb = psi + B * (long long)g.n;
+  const double *hb = hpsi + B * (long long)g.n;
+  double acc = 0.0;
+  const double s = 2.0 * f[B] * g.dv;
+  for (int l = threadIdx.x; l < g.n; l += blockDim.x) {
+    acc += pb[l] * hb[l];
+    if (grad_psi) grad_psi[B * (long long)g.n + l] = s * hb[l];
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) eb[B] = f[B] * g.dv * acc;
+}
+
+__global__ void __launch_bounds__(256) k_band_energy_sum(int nb, const double *__restrict__ eb,
+                                                         double *__restrict__ energy) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += eb[i];
+    energy[0] = s;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_grad_v(Geo g, int nb, const double *__restrict__ psi,
+                                                const double *__restrict__ f,
+                                                double *__restrict__ grad_v) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= g.n) return;
+  double acc = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    const double v = psi[(long long)i * g.n + l];
+    acc += f[i] * v * v;
+  }
+  grad_v[l] = g.dv * acc;
+}
+
+inline int grid_for(long long n, int block) {
+  long long b = (n + block - 1) / block;
+  if (b > 65536 * 4) b = 65536 * 4;
+  return (int)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+void launch_hloc(const Geo &g, const OrbSet &o, int f0, int f1, const double *veff,
+                 const double *x, double *y, hipStream_t s) {
+  const long long nb = o.nb(f0, f1);
+  if (nb <= 0) return;
+  const int plane = g.nl[0] * g.nl[1];
+  hipLaunchKernelGGL(k_hloc, dim3((unsigned)nb), dim3(plane), 2 * plane * sizeof(double), s, g,
+                     o.band_frag, o.b0(f0), veff, x, y);
+}
+
+void launch_kb_project(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1,
+                       const double *x, double *C, hipStream_t s, const int *h_pair_first) {
+  const int p0 = h_pair_first[f0], p1 = h_pair_first[f1];
+  if (p1 <= p0) return;
+  hipLaunchKernelGGL(k_kb_project, dim3(p1 - p0), dim3(256), 0, s, g, kb, o.m, o.moff, o.m_pad,
+                     p0, x, C);
+}
+
+void launch_kb_apply(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1,
+                     const double *C, double *y, hipStream_t s) {
+  const long long total = (long long)(f1 - f0) * g.n;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_kb_apply, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, kb,
+                     o.m, o.moff, o.m_pad, f0, f1, C, y);
+}
+
+void launch_band_dot(const Geo &g, const OrbSet &o, int f0, int f1, const double *x,
+                     const double *y, int core, double *out, hipStream_t s) {
+  const long long nb = o.nb(f0, f1);
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_band_dot, dim3((unsigned)nb), dim3(256), 0, s, g, o.b0(f0), x, y, core,
+                     out);
+}
+
+void launch_band_axpby(const Geo &g, const OrbSet &o, int f0, int f1, const double *a,
+                       double a_const, const double *b, double b_const, const double *x,
+                       double *y, hipStream_t s) {
+  const long long nb = o.nb(f0, f1);
+  if (nb <= 0) return;
+  const long long total = nb * g.n;
+  hipLaunchKernelGGL(k_band_axpby, dim3(grid_for(total, 256)), dim3(256), 0, s, g, o.b0(f0), nb,
+                     a, a_const, b, b_const, x, y);
+}
+
+void launch_init_orbitals(const Geo &g, const OrbSet &o, uint64_t seed, double *psi,
+                          hipStream_t s) {
+  const long long total = o.M_tot * g.n;
+  hipLaunchKernelGGL(k_init_orbitals, dim3(grid_for(total, 256)), dim3(256), 0, s, g,
+                     o.band_frag, o.moff, o.M_tot, seed, psi);
+}
+
+void launch_band_energy(const Geo &g, int nb, const double *psi, const double *hpsi,
+                        const double *f, double *eb, double *energy, double *grad_psi,
+                        double *grad_v, hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_band_energy_terms, dim3(nb), dim3(256), 0, s, g, psi, hpsi, f, eb,
+                     grad_psi);
+  if (energy) hipLaunchKernelGGL(k_band_energy_sum, dim3(1), dim3(64), 0, s, nb, eb, energy);
+  if (grad_v)
+    hipLaunchKernelGGL(k_grad_v, dim3((g.n + 255) / 256), dim3(256), 0, s, g, nb, psi, f, grad_v);
+}
+
+}  // namespace dcdft
