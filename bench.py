@@ -1,0 +1,151 @@
+#!/usr/bin/env python3
+"""Throughput of the DC-DFT fragment SCF step on one MI355X.
+
+One step = one SCF iteration over all fragments (Hartree potential, fragment
+potentials, CG sweeps + Rayleigh-Ritz on every fragment, core weights, global
+chemical potential, density assembly, energy, residuals, mixing).  The
+workload is the 512-atom a-Si-like cell (4x4x4 diamond cells, 64^3 grid,
+4x4x4 fragments of 24^3 points, 64 orbitals each) with synthetic, seeded
+atom positions.  Prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fragment H·ψ GB/s + SCF iters/sec (all fragments), mixed+batched vs FP64"
+HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
+
+
+def workload_config(k: int):
+    import workloads
+    return workloads.config(k)
+
+
+def cpu_baseline(cfg, max_workers: int = 16) -> dict:
+    """The FP64 oracle on host cores, on a bounded sample of one SCF iteration:
+    the global Hartree solve plus one fragment eigensolve per worker process
+    (BLAS single-threaded per worker), scaled to all fragments."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+
+    workers = max(1, min(max_workers, os.cpu_count() or 1, cfg.n_fragments))
+    o = oracle.OracleSCF(cfg, workers=workers)
+    t0 = time.perf_counter()
+    v_h = oracle.poisson_fd(o.rho_in, o.h)
+    for a in range(cfg.n_fragments):
+        o.veff(a, v_h)
+    t_global = time.perf_counter() - t0
+    sample = list(range(min(cfg.n_fragments, 2 * workers)))
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        o.solve_fragments(v_h, alphas=sample)
+        t_sample = time.perf_counter() - t0
+    t_iter = t_global + t_sample * cfg.n_fragments / len(sample)
+    return {"value": 1.0 / t_iter, "unit": "SCF iter/s", "cores": workers, "kind": "oracle",
+            "sample": (f"one SCF iteration of the same workload: Hartree solve and all fragment "
+                       f"potentials, plus {len(sample)} of {cfg.n_fragments} fragment "
+                       f"eigensolves on {workers} processes (1 BLAS thread each), scaled to all "
+                       f"fragments; measured {t_global + t_sample:.1f} s wall")}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, help="workload number (default 2)")
+    ap.add_argument("--batched", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        return 1
+    from paper_2606_21125_amd import (DCDFT, KERNEL_GRAM, KERNEL_HLOC, KERNEL_ROTATE)
+
+    cfg = workload_config(args.config)
+    print(f"[bench] setup {cfg.name}: {cfg.system.n_atoms} atoms, grid {cfg.n_grid}, "
+          f"{cfg.n_fragments} fragments of {cfg.fragment_shape}", file=sys.stderr, flush=True)
+    d = DCDFT.from_config(cfg, batched=args.batched)
+    for _ in range(args.warmup):
+        d.dcdft_scf_step()
+    torch.cuda.synchronize()
+    d.dcdft_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = None
+    for _ in range(args.steps):
+        info = d.dcdft_scf_step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = {name: d.dcdft_kernel_time(k) for name, k in
+          (("hloc", KERNEL_HLOC), ("gram", KERNEL_GRAM), ("rotate", KERNEL_ROTATE))}
+    d.close()
+    elapsed = t1 - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    value = args.steps / elapsed
+
+    h = kt["hloc"]
+    h_gbs = h["bytes"] / (h["ms"] * 1e-3) / 1e9 if h["ms"] > 0 else 0.0
+    g = kt["gram"]
+    g_tf = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
+    r = kt["rotate"]
+    r_gbs = r["bytes"] / (r["ms"] * 1e-3) / 1e9 if r["ms"] > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(h_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(h_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_hloc (fragment H_loc psi, FP64)",
+                "avg_launch_ms": round(h["ms"] / max(1, h["launches"]), 4),
+                "bytes_per_launch": h["bytes"] / max(1, h["launches"])}
+    extra = {
+        "hpsi_gbs": round(h_gbs, 1),
+        "gram": {"bound": "mfma", "achieved": round(g_tf, 2), "peak": FP64_MFMA_PEAK_TFLOPS,
+                 "unit": "TFLOP/s", "frac": round(g_tf / FP64_MFMA_PEAK_TFLOPS, 4),
+                 "avg_launch_ms": round(g["ms"] / max(1, g["launches"]), 4)},
+        "rotate": {"bound": "hbm", "achieved": round(r_gbs, 1), "peak": HBM_PEAK_GBS,
+                   "unit": "GB/s", "frac": round(r_gbs / HBM_PEAK_GBS, 4),
+                   "avg_launch_ms": round(r["ms"] / max(1, r["launches"]), 4)},
+        "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in kt.items()},
+        "last_step": {k: info[k] for k in ("mu", "e_total", "residual_out_in", "charge")},
+    }
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(cfg)
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "SCF iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"{cfg.name}: {cfg.system.n_atoms}-atom a-Si-like cell, grid "
+                                f"{'x'.join(map(str, cfg.n_grid))}, "
+                                f"{'x'.join(map(str, cfg.num_fragment))} fragments of "
+                                f"{'x'.join(map(str, cfg.fragment_shape))} points, "
+                                f"{int(cfg.nstate_frag[0])} orbitals each, "
+                                f"{cfg.cg_sweeps} CG sweeps per SCF iteration"),
+                   "n_fragments": cfg.n_fragments, "batched": bool(args.batched),
+                   "precision": "fp64"},
+        "roofline": roofline, "cpu_baseline": cpu, **extra,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -184,6 +184,23 @@ dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, cons
                                int32_t m, int32_t prec, double *energy, void *grad_psi,
                                void *grad_v);
 
+/* Device-time accounting of kernel families (for roofline reports).  While
+ * enabled, every launch of the families below is bracketed by HIP events on the
+ * context's stream; dcdft_kernel_time returns, since timing was (re-)enabled,
+ * the number of launches, their summed device milliseconds, and their summed
+ * algorithmic HBM bytes and flops (minimum traffic: every operand read once,
+ * every result written once; any of the outputs may be NULL).  Enabling resets
+ * the counters.  Timing adds two event records per launch and nothing else.
+ *   HLOC:   (-1/2 L_FD + V_eff) X; bytes 2 s n per orbital + 8 n per fragment
+ *           (s = 8 for FP64), flops 55 n per orbital.
+ *   GRAM:   X^T Y per fragment; bytes s n (m_x + m_y), flops 2 n m^2.
+ *   ROTATE: Y = c Z + M^T X per fragment; bytes s n m (2 or 3), flops 2 n m^2. */
+enum { DCDFT_KERNEL_HLOC = 0, DCDFT_KERNEL_GRAM = 1, DCDFT_KERNEL_ROTATE = 2,
+       DCDFT_KERNEL_COUNT = 3 };
+dcdft_status dcdft_kernel_timing(dcdft_ctx *c, int32_t enable);
+dcdft_status dcdft_kernel_time(dcdft_ctx *c, int32_t kernel, int64_t *launches, double *ms,
+                               double *bytes, double *flops);
+
 /* Release everything owned by c.  NULL-safe. */
 void dcdft_destroy(dcdft_ctx *c);
 

@@ -29,8 +29,10 @@ EXPORTED = [
     "dcdft_setup", "dcdft_scf_step", "dcdft_density", "dcdft_density_device",
     "dcdft_eigenvalues", "dcdft_fragment_info", "dcdft_get_field", "dcdft_get_fragment_field",
     "dcdft_get_orbitals", "dcdft_set_orbitals", "dcdft_set_density", "dcdft_apply_h",
-    "dcdft_band_energy", "dcdft_destroy", "dcdft_status_string", "dcdft_last_error",
+    "dcdft_band_energy", "dcdft_kernel_timing", "dcdft_kernel_time", "dcdft_destroy",
+    "dcdft_status_string", "dcdft_last_error",
 ]
+KERNEL_HLOC, KERNEL_GRAM, KERNEL_ROTATE = 0, 1, 2
 
 
 class DcdftSpecies(ctypes.Structure):
@@ -102,6 +104,9 @@ def load_library(path: Optional[str] = None):
                           ctypes.c_int),
         "dcdft_band_energy": ([vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32, vp,
                                vp, vp], ctypes.c_int),
+        "dcdft_kernel_timing": ([vp, ctypes.c_int32], ctypes.c_int),
+        "dcdft_kernel_time": ([vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), pd, pd, pd],
+                              ctypes.c_int),
         "dcdft_destroy": ([vp], None),
         "dcdft_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "dcdft_last_error": ([vp, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
@@ -295,6 +300,18 @@ class DCDFT:
         m = psi.shape[0]
         _check(self._lib.dcdft_apply_h(self.ctx, frag, ctypes.c_void_p(psi.data_ptr()),
                                        ctypes.c_void_p(hpsi.data_ptr()), m, prec), self.ctx)
+
+    def dcdft_kernel_timing(self, enable: bool) -> None:
+        _check(self._lib.dcdft_kernel_timing(self.ctx, int(bool(enable))), self.ctx)
+
+    def dcdft_kernel_time(self, kernel: int) -> dict:
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        fl = ctypes.c_double()
+        _check(self._lib.dcdft_kernel_time(self.ctx, kernel, ctypes.byref(n), ctypes.byref(ms),
+                                           ctypes.byref(by), ctypes.byref(fl)), self.ctx)
+        return dict(launches=n.value, ms=ms.value, bytes=by.value, flops=fl.value)
 
     def dcdft_band_energy(self, frag: int, psi, f, energy=None, grad_psi=None, grad_v=None,
                           prec: int = PREC_FP64) -> None:

@@ -132,12 +132,88 @@ dcdft::KBTables dcdft_ctx::kb() const {
 
 namespace {
 
+hipEvent_t pool_event(dcdft_ctx *c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Bracket one launch of a timed kernel family with events.
+struct Timed {
+  dcdft_ctx *c;
+  dcdft_ctx::PendingTimer t;
+  bool on;
+  Timed(dcdft_ctx *cc, int kind, double bytes, double flops) : c(cc), on(cc->timing) {
+    if (!on) return;
+    t.a = pool_event(c);
+    t.b = pool_event(c);
+    t.kind = kind;
+    t.bytes = bytes;
+    t.flops = flops;
+    if (!t.a || !t.b) {
+      on = false;
+      return;
+    }
+    hipEventRecord(t.a, c->stream);
+  }
+  ~Timed() {
+    if (!on) return;
+    hipEventRecord(t.b, c->stream);
+    c->pending.push_back(t);
+  }
+};
+
+void drain_timers(dcdft_ctx *c) {
+  for (auto &t : c->pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      c->k_launches[t.kind] += 1;
+      c->k_ms[t.kind] += ms;
+      c->k_bytes[t.kind] += t.bytes;
+      c->k_flops[t.kind] += t.flops;
+    }
+    c->event_pool.push_back(t.a);
+    c->event_pool.push_back(t.b);
+  }
+  c->pending.clear();
+}
+
+double orbitals_in(const dcdft_ctx *c, int f0, int f1) {
+  return (double)(c->moff[f1] - c->moff[f0]);
+}
+
+double sum_m2(const dcdft_ctx *c, int f0, int f1) {
+  double s = 0.0;
+  for (int f = f0; f < f1; ++f) s += (double)c->m[f] * c->m[f];
+  return s;
+}
+
+void hloc(dcdft_ctx *c, int f0, int f1, const double *x, double *y) {
+  const double n = c->geo.n;
+  Timed t(c, DCDFT_KERNEL_HLOC, 16.0 * n * orbitals_in(c, f0, f1) + 8.0 * n * (f1 - f0),
+          55.0 * n * orbitals_in(c, f0, f1));
+  launch_hloc(c->geo, c->orbset(f0, f1), f0, f1, c->d_veff, x, y, c->stream);
+}
+
+void rotate(dcdft_ctx *c, int f0, int f1, const double *M, int trans, const double *x,
+            const double *z, double cz, double cm, double *y) {
+  const double n = c->geo.n;
+  Timed t(c, DCDFT_KERNEL_ROTATE, 8.0 * n * orbitals_in(c, f0, f1) * (z ? 3.0 : 2.0),
+          2.0 * n * sum_m2(c, f0, f1));
+  launch_rotate(c->geo, c->orbset(f0, f1), f0, f1, M, trans, x, z, cz, cm, y, c->stream);
+}
+
 // H X for the orbitals of fragments [f0, f1) in the context layout.
 void apply_h_range(dcdft_ctx *c, int f0, int f1, const double *x, double *y) {
   const Geo &g = c->geo;
   OrbSet o = c->orbset(f0, f1);
   KBTables kb = c->kb();
-  launch_hloc(g, o, f0, f1, c->d_veff, x, y, c->stream);
+  hloc(c, f0, f1, x, y);
   launch_kb_project(g, o, kb, f0, f1, x, c->d_C, c->stream, c->pair_first.data());
   launch_kb_apply(g, o, kb, f0, f1, c->d_C, y, c->stream);
 }
@@ -145,8 +221,14 @@ void apply_h_range(dcdft_ctx *c, int f0, int f1, const double *x, double *y) {
 void gram(dcdft_ctx *c, int f0, int f1, const double *x, const double *y, double *G, double *Gs,
           double *diag) {
   OrbSet o = c->orbset(f0, f1);
-  launch_gram(c->geo, o, f0, f1, c->gram_chunks, x, y, c->d_gpart, c->stream);
-  launch_gram_reduce(c->geo, o, f0, f1, c->gram_chunks, c->d_gpart, G, Gs, diag, c->stream);
+  {
+    const double n = c->geo.n;
+    Timed t(c, DCDFT_KERNEL_GRAM, 8.0 * n * orbitals_in(c, f0, f1) * (x == y ? 1.0 : 2.0),
+            2.0 * n * sum_m2(c, f0, f1));
+    launch_gram(c->geo, o, f0, f1, c->gram_chunks, x, y, c->d_gpart, c->stream);
+  }
+  launch_gram_reduce(c->geo, o, f0, f1, c->gram_chunks, x == y, c->d_gpart, G ? G : c->d_gtmp, Gs,
+                     diag, c->stream);
 }
 
 // Steps (a)-(l) of the fragment CG eigensolver and the Rayleigh-Ritz rotation.
@@ -160,7 +242,7 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
     // (a) Hs = sym(<Psi, W>), a_i = <psi_i, w_i>
     gram(c, f0, f1, psi, w, c->d_hs_full, c->d_hs, c->d_a);
     // (b) G = W - Hs Psi  (kept in q)
-    launch_rotate(g, o, f0, f1, c->d_hs, 0, psi, w, 1.0, -1.0, q, s);
+    rotate(c, f0, f1, c->d_hs, 0, psi, w, 1.0, -1.0, q);
     // (c) gamma, Fletcher-Reeves beta
     launch_band_dot(g, o, f0, f1, q, q, 0, c->d_gamma, s);
     launch_cg_beta(o, f0, f1, sw == 0, c->d_gamma, c->d_gamma_prev, c->d_beta, s);
@@ -168,7 +250,7 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
     launch_band_axpby(g, o, f0, f1, c->d_beta, 0.0, nullptr, -1.0, q, p, s);
     // (e) P <- P - <Psi, P>^T Psi
     gram(c, f0, f1, psi, p, c->d_x, nullptr, nullptr);
-    launch_rotate(g, o, f0, f1, c->d_x, 0, psi, p, 1.0, -1.0, p, s);
+    rotate(c, f0, f1, c->d_x, 0, psi, p, 1.0, -1.0, p);
     // (f) normalised direction in r
     launch_band_dot(g, o, f0, f1, p, p, 0, c->d_nu, s);
     launch_cg_norm(o, f0, f1, c->d_nu, c->d_inv, s);
@@ -185,25 +267,24 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
     // (k)
     launch_copy_band(o, f0, f1, c->d_gamma, c->d_gamma_prev, s);
     // (l) Cholesky re-orthonormalisation
-    gram(c, f0, f1, psi, psi, nullptr, c->d_s, nullptr);
+    gram(c, f0, f1, psi, psi, c->d_s, nullptr, nullptr);
     launch_cholinv(o, f0, f1, c->d_s, c->d_lin, c->d_flags, s);
-    launch_rotate(g, o, f0, f1, c->d_lin, 1, psi, nullptr, 0.0, 1.0, psi, s);
-    launch_rotate(g, o, f0, f1, c->d_lin, 1, w, nullptr, 0.0, 1.0, w, s);
+    rotate(c, f0, f1, c->d_lin, 1, psi, nullptr, 0.0, 1.0, psi);
+    rotate(c, f0, f1, c->d_lin, 1, w, nullptr, 0.0, 1.0, w);
   }
   // Rayleigh-Ritz
-  gram(c, f0, f1, psi, w, nullptr, c->d_hs, nullptr);
+  gram(c, f0, f1, psi, w, c->d_hs, nullptr, nullptr);
   launch_syev(o, f0, f1, c->d_hs, c->d_u, c->d_eps, c->d_flags, s);
-  launch_rotate(g, o, f0, f1, c->d_u, 0, psi, nullptr, 0.0, 1.0, psi, s);
+  rotate(c, f0, f1, c->d_u, 0, psi, nullptr, 0.0, 1.0, psi);
   // core weights w_i = dV sum_core psi_i^2
   launch_band_dot(g, o, f0, f1, psi, psi, 1, c->d_wcore, s);
 }
 
 void orthonormalize_all(dcdft_ctx *c) {
   OrbSet o = c->orbset(0, c->nF);
-  gram(c, 0, c->nF, c->d_psi, c->d_psi, nullptr, c->d_s, nullptr);
+  gram(c, 0, c->nF, c->d_psi, c->d_psi, c->d_s, nullptr, nullptr);
   launch_cholinv(o, 0, c->nF, c->d_s, c->d_lin, c->d_flags, c->stream);
-  launch_rotate(c->geo, o, 0, c->nF, c->d_lin, 1, c->d_psi, nullptr, 0.0, 1.0, c->d_psi,
-                c->stream);
+  rotate(c, 0, c->nF, c->d_lin, 1, c->d_psi, nullptr, 0.0, 1.0, c->d_psi);
 }
 
 dcdft_status check_flags(dcdft_ctx *c, int flags) {
@@ -477,6 +558,11 @@ void dcdft_destroy(dcdft_ctx *c) {
   if (c->d_info_host) hipHostFree(c->d_info_host);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
+  for (auto &t : c->pending) {
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -523,9 +609,9 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   c->precision = p->precision;
   c->batched = p->batched;
   c->seed = p->seed;
-  // Gram chunks: aim at >= 1024 workgroups over all fragments
+  // Gram chunks: aim at >= 512 four-wave workgroups over all fragments
   {
-    int ch = (1024 + c->nF - 1) / c->nF;
+    int ch = (512 + c->nF - 1) / c->nF;
     const int maxch = std::max(1, g.n / 256);
     c->gram_chunks = std::max(1, std::min(ch, maxch));
   }
@@ -582,7 +668,8 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   ALLOC(c->d_veff, (long long)c->nF * g.n);
   ALLOC(c->d_rhof_in, (long long)c->nF * g.n);
   ALLOC(c->d_rhof_out, (long long)c->nF * g.n);
-  ALLOC(c->d_gpart, (long long)c->nF * c->gram_chunks * 4 * mp2);
+  ALLOC(c->d_gpart, (long long)c->nF * c->gram_chunks * mp2);
+  ALLOC(c->d_gtmp, c->nF * mp2);
   ALLOC(c->d_hs_full, c->nF * mp2);
   ALLOC(c->d_hs, c->nF * mp2);
   ALLOC(c->d_x, c->nF * mp2);
@@ -669,6 +756,7 @@ dcdft_status dcdft_scf_step(dcdft_ctx *c, dcdft_scf_info *info) {
   int flags = 0;
   HIPTRY(c, hipMemcpyAsync(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPTRY(c, hipStreamSynchronize(s));
+  drain_timers(c);
   c->iter++;
   const double *sc = c->d_info_host;
   if (info) {
@@ -946,6 +1034,36 @@ dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, cons
   hipFree(hp);
   hipFree(eb);
   return st;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+dcdft_status dcdft_kernel_timing(dcdft_ctx *c, int32_t enable) {
+  if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  HIPTRY(c, hipStreamSynchronize(c->stream));
+  drain_timers(c);
+  c->timing = enable != 0;
+  for (int k = 0; k < DCDFT_KERNEL_COUNT; ++k) {
+    c->k_launches[k] = 0;
+    c->k_ms[k] = c->k_bytes[k] = c->k_flops[k] = 0.0;
+  }
+  return DCDFT_OK;
+}
+
+dcdft_status dcdft_kernel_time(dcdft_ctx *c, int32_t kernel, int64_t *launches, double *ms,
+                               double *bytes, double *flops) {
+  if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  if (kernel < 0 || kernel >= DCDFT_KERNEL_COUNT)
+    return set_err(c, DCDFT_ERR_ARG, fmt("unknown kernel family %d", kernel));
+  HIPTRY(c, hipStreamSynchronize(c->stream));
+  drain_timers(c);
+  if (launches) *launches = c->k_launches[kernel];
+  if (ms) *ms = c->k_ms[kernel];
+  if (bytes) *bytes = c->k_bytes[kernel];
+  if (flops) *flops = c->k_flops[kernel];
+  return DCDFT_OK;
 }
 
 }  // extern "C"

@@ -119,7 +119,8 @@ struct dcdft_ctx {
   double *d_veff = nullptr, *d_rhof_in = nullptr, *d_rhof_out = nullptr;
 
   // small matrices [F][m_pad][m_pad]
-  double *d_gpart = nullptr;         // Gram partials [F][chunks*4][m_pad][m_pad]
+  double *d_gpart = nullptr;         // Gram partials [F][chunks][m_pad][m_pad]
+  double *d_gtmp = nullptr;          // Gram result when only the symmetric part is kept
   double *d_hs_full = nullptr, *d_hs = nullptr, *d_x = nullptr, *d_s = nullptr, *d_lin = nullptr,
          *d_u = nullptr;
 
@@ -135,6 +136,18 @@ struct dcdft_ctx {
 
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string last_error;
+
+  // kernel-family timing (dcdft_kernel_timing)
+  struct PendingTimer {
+    hipEvent_t a, b;
+    int kind;
+    double bytes, flops;
+  };
+  bool timing = false;
+  std::vector<PendingTimer> pending;
+  std::vector<hipEvent_t> event_pool;
+  long long k_launches[3] = {0, 0, 0};
+  double k_ms[3] = {0, 0, 0}, k_bytes[3] = {0, 0, 0}, k_flops[3] = {0, 0, 0};
 
   dcdft::OrbSet orbset(int f0, int f1) const;
   dcdft::KBTables kb() const;
@@ -156,8 +169,9 @@ void launch_kb_apply(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, 
 // part[f][w] = X^T Y partial sums (row form: G_ij = sum_l X_i(l) Y_j(l))
 void launch_gram(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, const double *x,
                  const double *y, double *part, hipStream_t s);
-// G = dV sum partials; Gs = sym(G) (either may be null); diag -> per-band (may be null)
-void launch_gram_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
+// G = dV sum of chunk partials (sym: X == Y, lower tiles mirrored); Gs = sym(G) if
+// not null; diag -> per-band (may be null)
+void launch_gram_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int sym,
                         const double *part, double *G, double *Gs, double *diag, hipStream_t s);
 // Y_j = cz Z_j + cm sum_i R[j][i] X_i with R = M^T (trans 0) or M (trans 1)
 void launch_rotate(const Geo &g, const OrbSet &o, int f0, int f1, const double *M, int trans,

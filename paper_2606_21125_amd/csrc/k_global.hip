@@ -206,13 +206,15 @@ __global__ void __launch_bounds__(256) k_global_terms(Geo g, double *__restrict_
   }
 }
 
-__global__ void __launch_bounds__(64) k_global_final(Geo g, int nblk, double ne, double sigma,
-                                                     const double *__restrict__ part,
-                                                     double *__restrict__ scal) {
-  if (threadIdx.x != 0) return;
+__global__ void __launch_bounds__(256) k_global_final(Geo g, int nblk, double ne, double sigma,
+                                                      const double *__restrict__ part,
+                                                      double *__restrict__ scal) {
+  __shared__ double red[16];
   double s[6] = {0, 0, 0, 0, 0, 0};
-  for (int b = 0; b < nblk; ++b)
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
     for (int k = 0; k < 6; ++k) s[k] += part[b * 6 + k];
+  for (int k = 0; k < 6; ++k) s[k] = block_sum(s[k], red);
+  if (threadIdx.x != 0) return;
   const double dv = g.dv;
   scal[SC_HXC] = dv * s[0];
   scal[SC_EH] = 0.5 * dv * s[1];
@@ -319,7 +321,7 @@ void launch_global_terms(const Geo &g, double *rho_in, const double *rho_out, co
                          double ne, double sigma) {
   hipLaunchKernelGGL(k_global_terms, dim3(n_part), dim3(256), 0, s, g, rho_in, rho_out, vh,
                      mixing, part);
-  hipLaunchKernelGGL(k_global_final, dim3(1), dim3(64), 0, s, g, n_part, ne, sigma, part, scal);
+  hipLaunchKernelGGL(k_global_final, dim3(1), dim3(256), 0, s, g, n_part, ne, sigma, part, scal);
 }
 
 void launch_frag_mix(const Geo &g, int nfrag, double *rhof_in, const double *rhof_out,

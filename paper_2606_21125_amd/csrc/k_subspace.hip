@@ -19,19 +19,27 @@ __device__ inline dbl4 mfma16x16x4(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Partial Gram products over point chunks.  Workgroup = (fragment, chunk); its 4
-// waves split the chunk into 4 point ranges and each accumulates the full
-// m_pad x m_pad product of its range.  The K index of the MFMA walks points in
-// the order p0 + 4 (l / 16) + t, which covers every point of the range once.
-template <int TM>
-__global__ void __launch_bounds__(256) k_gram(Geo g, OrbSet o, int f0, int chunks, int kchunk,
-                                              const double *__restrict__ x,
-                                              const double *__restrict__ y,
-                                              double *__restrict__ part) {
+// LDS row stride for an m_pad-wide operand block: the smallest S >= m_pad with
+// S = 16 (mod 32), so the four 16-lane groups of an MFMA operand read land on
+// different bank halves.
+__host__ __device__ constexpr int lds_stride(int mp) { return mp + ((16 - mp % 32) + 32) % 32; }
+
+// Gram partials, version 2.  Workgroup = (fragment, chunk of kchunk points); each
+// of the 4 waves accumulates every output tile over a quarter of the chunk (the
+// upper-triangle tiles only when X == Y), then the 4 wave results are summed in
+// LDS and one partial per workgroup is written.  With VEC each lane fetches its 4
+// consecutive points as two 16-byte loads (rows are 32-byte aligned when n % 4 == 0).
+template <int TM, bool SYM, bool VEC>
+__global__ void __launch_bounds__(256) k_gram2(Geo g, OrbSet o, int f0, int chunks, int kchunk,
+                                               const double *__restrict__ x,
+                                               const double *__restrict__ y,
+                                               double *__restrict__ part) {
+  __shared__ double red[kMaxOrb * kMaxOrb];
   const int f = f0 + blockIdx.x / chunks;
   const int c = blockIdx.x % chunks;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mf = o.m[f];
+  const int mp = o.m_pad;
   const long long base = o.moff[f] * (long long)g.n;
   const int sub = kchunk / 4;
   const int p_begin = c * kchunk + wave * sub;
@@ -44,18 +52,33 @@ __global__ void __launch_bounds__(256) k_gram(Geo g, OrbSet o, int f0, int chunk
     for (int j = 0; j < TM; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
   for (int p0 = p_begin; p0 < p_end; p0 += 16) {
     double xa[TM][4], yb[TM][4];
+    const int pl = p0 + 4 * kk;
 #pragma unroll
     for (int ti = 0; ti < TM; ++ti) {
       const int row = ti * 16 + r;
       const bool rok = row < mf;
       const double *xr = x + base + (long long)row * g.n;
       const double *yr = y + base + (long long)row * g.n;
+      if (VEC && rok && pl + 3 < p_end) {
+        const double2 a0 = *reinterpret_cast<const double2 *>(xr + pl);
+        const double2 a1 = *reinterpret_cast<const double2 *>(xr + pl + 2);
+        xa[ti][0] = a0.x; xa[ti][1] = a0.y; xa[ti][2] = a1.x; xa[ti][3] = a1.y;
+        if (!SYM) {
+          const double2 b0 = *reinterpret_cast<const double2 *>(yr + pl);
+          const double2 b1 = *reinterpret_cast<const double2 *>(yr + pl + 2);
+          yb[ti][0] = b0.x; yb[ti][1] = b0.y; yb[ti][2] = b1.x; yb[ti][3] = b1.y;
+        }
+      } else {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int p = p0 + 4 * kk + t;
-        const bool ok = rok && p < p_end;
-        xa[ti][t] = ok ? xr[p] : 0.0;
-        yb[ti][t] = ok ? yr[p] : 0.0;
+        for (int t = 0; t < 4; ++t) {
+          const bool ok = rok && pl + t < p_end;
+          xa[ti][t] = ok ? xr[pl + t] : 0.0;
+          if (!SYM) yb[ti][t] = ok ? yr[pl + t] : 0.0;
+        }
+      }
+      if (SYM) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) yb[ti][t] = xa[ti][t];
       }
     }
 #pragma unroll
@@ -63,138 +86,189 @@ __global__ void __launch_bounds__(256) k_gram(Geo g, OrbSet o, int f0, int chunk
 #pragma unroll
       for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < TM; ++tj) acc[ti][tj] = mfma16x16x4(xa[ti][t], yb[tj][t], acc[ti][tj]);
+        for (int tj = 0; tj < TM; ++tj)
+          if (!SYM || ti <= tj) acc[ti][tj] = mfma16x16x4(xa[ti][t], yb[tj][t], acc[ti][tj]);
   }
-  const int mp = o.m_pad;
-  double *out = part + (((long long)(f - f0) * chunks + c) * 4 + wave) * mp * mp;
+  // sum the four wave partials in LDS (fixed order: wave 0, 1, 2, 3)
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
 #pragma unroll
-  for (int ti = 0; ti < TM; ++ti)
+      for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
-    for (int tj = 0; tj < TM; ++tj)
+        for (int tj = 0; tj < TM; ++tj) {
+          if (SYM && ti > tj) continue;
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int row = ti * 16 + (lane >> 4) + 4 * rr;
-        const int col = tj * 16 + (lane & 15);
-        out[row * mp + col] = acc[ti][tj][rr];
-      }
-}
-
-__global__ void __launch_bounds__(256) k_gram_reduce(Geo g, OrbSet o, int f0, int nparts,
-                                                     const double *__restrict__ part,
-                                                     double *__restrict__ G,
-                                                     double *__restrict__ Gs,
-                                                     double *__restrict__ diag) {
-  const int f = f0 + blockIdx.x;
-  const int mp = o.m_pad, mf = o.m[f];
-  const double *pf = part + (long long)(f - f0) * nparts * mp * mp;
+          for (int rr = 0; rr < 4; ++rr) {
+            const int row = ti * 16 + (lane >> 4) + 4 * rr;
+            const int col = tj * 16 + (lane & 15);
+            const double v = acc[ti][tj][rr];
+            red[row * mp + col] = (w == 0) ? v : red[row * mp + col] + v;
+          }
+        }
+    }
+    __syncthreads();
+  }
+  double *out = part + ((long long)(f - f0) * chunks + c) * mp * mp;
   for (int e = threadIdx.x; e < mp * mp; e += blockDim.x) {
     const int i = e / mp, j = e % mp;
-    double sij = 0.0, sji = 0.0;
-    if (i < mf && j < mf) {
-      for (int q = 0; q < nparts; ++q) {
-        sij += pf[(long long)q * mp * mp + i * mp + j];
-        sji += pf[(long long)q * mp * mp + j * mp + i];
-      }
-    }
-    const double gij = g.dv * sij;
-    if (G) G[(long long)f * mp * mp + e] = gij;
-    if (Gs) Gs[(long long)f * mp * mp + e] = 0.5 * (gij + g.dv * sji);
-    if (diag && i == j && i < mf) diag[o.moff[f] + i] = gij;
+    double v = 0.0;
+    if (!SYM || (i / 16) <= (j / 16)) v = red[e];
+    out[e] = v;
   }
 }
 
-// Y_j = cz Z_j + cm sum_i R[j][i] X_i over all orbitals j of the fragment, with
-// R = M^T (trans 0) or R = M (trans 1).  Each wave owns 16 points and every
-// output orbital, so Y may alias X or Z.
-template <int TM>
-__global__ void __launch_bounds__(256) k_rotate(Geo g, OrbSet o, int f0, int tpf,
-                                                const double *__restrict__ M, int trans,
-                                                const double *x, const double *z, double cz,
-                                                double cm, double *y) {
-  const int f = f0 + blockIdx.x / tpf;
-  const int tile = blockIdx.x % tpf;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int p0 = (tile * 4 + wave) * 16;
-  if (p0 >= g.n) return;
-  const int mf = o.m[f], mp = o.m_pad;
-  const long long base = o.moff[f] * (long long)g.n;
-  const double *Mf = M + (long long)f * mp * mp;
-  const int pc = p0 + (lane & 15);
-  const bool pin = pc < g.n;
-  const int kk = lane >> 4;
-  dbl4 acc[TM];
-#pragma unroll
-  for (int j = 0; j < TM; ++j) acc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int i0 = 0; i0 < mf; i0 += 4) {
-    const int i = i0 + kk;
-    const bool iok = i < mf;
-    const double bx = (iok && pin) ? x[base + (long long)i * g.n + pc] : 0.0;
-#pragma unroll
-    for (int jt = 0; jt < TM; ++jt) {
-      const int j = jt * 16 + (lane & 15);
-      double a = 0.0;
-      if (iok && j < mf) a = trans ? Mf[j * mp + i] : Mf[i * mp + j];
-      acc[jt] = mfma16x16x4(a, bx, acc[jt]);
+// G = dV sum over chunk partials, element-parallel; for symmetric products the
+// tiles below the diagonal are taken from their mirror.
+__global__ void __launch_bounds__(256) k_gram_reduce2(Geo g, OrbSet o, int f0, int nf, int chunks,
+                                                      int sym, const double *__restrict__ part,
+                                                      double *__restrict__ G,
+                                                      double *__restrict__ diag) {
+  const int mp = o.m_pad;
+  const long long total = (long long)nf * mp * mp;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int fl = (int)(idx / (mp * mp));
+  const int e = (int)(idx % (mp * mp));
+  const int f = f0 + fl;
+  int i = e / mp, j = e % mp;
+  const int mf = o.m[f];
+  double s = 0.0;
+  if (i < mf && j < mf) {
+    int si = i, sj = j;
+    if (sym && (i / 16) > (j / 16)) {
+      si = j;
+      sj = i;
     }
+    const double *pf = part + (long long)fl * chunks * mp * mp + si * mp + sj;
+    for (int q = 0; q < chunks; ++q) s += pf[(long long)q * mp * mp];
   }
+  const double v = g.dv * s;
+  G[(long long)f * mp * mp + e] = v;
+  if (diag && i == j && i < mf) diag[o.moff[f] + i] = v;
+}
+
+__global__ void __launch_bounds__(256) k_symmetrize(OrbSet o, int f0, int nf,
+                                                    const double *__restrict__ G,
+                                                    double *__restrict__ Gs) {
+  const int mp = o.m_pad;
+  const long long total = (long long)nf * mp * mp;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int f = f0 + (int)(idx / (mp * mp));
+  const int e = (int)(idx % (mp * mp));
+  const int i = e / mp, j = e % mp;
+  const double *Gf = G + (long long)f * mp * mp;
+  Gs[(long long)f * mp * mp + e] = 0.5 * (Gf[i * mp + j] + Gf[j * mp + i]);
+}
+
+// Rotation, version 2: R^T (as Rt[i][j] = R[j][i]) staged once per workgroup in
+// LDS; each wave handles NT tiles of 16 points and all output orbitals; the
+// X column of a tile (m_pad/4 doubles per lane) is fetched in one burst before
+// its MFMA chain.  Y may alias X or Z (each wave reads its points fully first).
+template <int TM, int NT>
+__global__ void __launch_bounds__(256) k_rotate2(Geo g, OrbSet o, int f0, int wpf,
+                                                 const double *__restrict__ M, int trans,
+                                                 const double *x, const double *z, double cz,
+                                                 double cm, double *y) {
+  constexpr int MP = 16 * TM;
+  constexpr int S = lds_stride(MP);
+  __shared__ double Rt[MP * S];
+  const int f = f0 + blockIdx.x / wpf;
+  const int wg = blockIdx.x % wpf;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int mf = o.m[f], mp = o.m_pad;
+  const double *Mf = M + (long long)f * mp * mp;
+  for (int e = threadIdx.x; e < MP * MP; e += blockDim.x) {
+    const int i = e / MP, j = e % MP;
+    double v = 0.0;
+    if (i < mf && j < mf) v = trans ? Mf[j * mp + i] : Mf[i * mp + j];
+    Rt[i * S + j] = v;
+  }
+  __syncthreads();
+  const long long base = o.moff[f] * (long long)g.n;
+  const int jl = lane & 15, kk = lane >> 4;
+  for (int u = 0; u < NT; ++u) {
+    const int p0 = ((wg * 4 + wave) * NT + u) * 16;
+    if (p0 >= g.n) break;
+    const int pc = p0 + jl;
+    const bool pin = pc < g.n;
+    double bx[TM * 4];
 #pragma unroll
-  for (int jt = 0; jt < TM; ++jt)
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const int j = jt * 16 + (lane >> 4) + 4 * rr;
-      const int p = p0 + (lane & 15);
-      if (j < mf && p < g.n) {
-        const long long e = base + (long long)j * g.n + p;
-        double v = cm * acc[jt][rr];
-        if (z) v += cz * z[e];
-        y[e] = v;
-      }
+    for (int s = 0; s < TM * 4; ++s) {
+      const int i = 4 * s + kk;
+      bx[s] = (i < mf && pin) ? x[base + (long long)i * g.n + pc] : 0.0;
     }
+    dbl4 acc[TM];
+#pragma unroll
+    for (int j = 0; j < TM; ++j) acc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < TM * 4; ++s) {
+      const double *rrow = Rt + (4 * s + kk) * S + jl;
+#pragma unroll
+      for (int jt = 0; jt < TM; ++jt) acc[jt] = mfma16x16x4(rrow[jt * 16], bx[s], acc[jt]);
+    }
+#pragma unroll
+    for (int jt = 0; jt < TM; ++jt)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int j = jt * 16 + kk + 4 * rr;
+        if (j < mf && pin) {
+          const long long e = base + (long long)j * g.n + pc;
+          double v = cm * acc[jt][rr];
+          if (z) v += cz * z[e];
+          y[e] = v;
+        }
+      }
+  }
 }
 
 // Cholesky S = L L^T in LDS and the rows of L^-1 (row-major, lower triangular).
 __global__ void __launch_bounds__(256) k_cholinv(OrbSet o, int f0, const double *__restrict__ S,
                                                  double *__restrict__ Linv, int *flags) {
-  __shared__ double A[kMaxOrb * kMaxOrb];
+  __shared__ double A[kMaxOrb * (kMaxOrb + 1)];
+  __shared__ double X[kMaxOrb * (kMaxOrb + 1)];
   __shared__ int bad;
   const int f = f0 + blockIdx.x;
   const int mf = o.m[f], mp = o.m_pad;
+  const int ld = mf + 1;   // odd row stride: column walks hit distinct banks
   const double *Sf = S + (long long)f * mp * mp;
   double *Lf = Linv + (long long)f * mp * mp;
   if (threadIdx.x == 0) bad = 0;
-  for (int e = threadIdx.x; e < mf * mf; e += blockDim.x) A[e] = Sf[(e / mf) * mp + e % mf];
+  for (int e = threadIdx.x; e < mf * mf; e += blockDim.x)
+    A[(e / mf) * ld + e % mf] = 0.5 * (Sf[(e / mf) * mp + e % mf] + Sf[(e % mf) * mp + e / mf]);
   for (int k = 0; k < mf; ++k) {
     __syncthreads();
     if (threadIdx.x == 0) {
-      double d = A[k * mf + k];
+      double d = A[k * ld + k];
       if (!(d > 0.0)) {
         bad = 1;
         d = 1.0;
       }
-      A[k * mf + k] = sqrt(d);
+      A[k * ld + k] = sqrt(d);
     }
     __syncthreads();
-    const double dk = A[k * mf + k];
-    for (int i = k + 1 + threadIdx.x; i < mf; i += blockDim.x) A[i * mf + k] /= dk;
+    const double dk = A[k * ld + k];
+    for (int i = k + 1 + threadIdx.x; i < mf; i += blockDim.x) A[i * ld + k] /= dk;
     __syncthreads();
     const int w = mf - k - 1;
     for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
       const int i = k + 1 + e / w, j = k + 1 + e % w;
-      if (j <= i) A[i * mf + j] -= A[i * mf + k] * A[j * mf + k];
+      if (j <= i) A[i * ld + j] -= A[i * ld + k] * A[j * ld + k];
     }
   }
   __syncthreads();
-  // column c of L^-1 by forward substitution; stored as Lf[r][c]
-  for (int c = threadIdx.x; c < mp; c += blockDim.x) {
-    for (int r = 0; r < mp; ++r) {
-      double v = 0.0;
-      if (c < mf && r < mf && r >= c) {
-        double s = (r == c) ? 1.0 : 0.0;
-        for (int q = c; q < r; ++q) s -= A[r * mf + q] * Lf[q * mp + c];
-        v = s / A[r * mf + r];
-      }
-      Lf[r * mp + c] = v;
+  // column c of L^-1 by forward substitution in LDS, then stored as Lf[r][c]
+  for (int c = threadIdx.x; c < mf; c += blockDim.x) {
+    for (int r = c; r < mf; ++r) {
+      double s = (r == c) ? 1.0 : 0.0;
+      for (int q = c; q < r; ++q) s -= A[r * ld + q] * X[q * ld + c];
+      X[r * ld + c] = s / A[r * ld + r];
     }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < mp * mp; e += blockDim.x) {
+    const int r = e / mp, c = e % mp;
+    Lf[e] = (r < mf && c < mf && r >= c) ? X[r * ld + c] : 0.0;
   }
   if (threadIdx.x == 0 && bad) atomicOr(flags, FLAG_NOT_SPD);
 }
@@ -219,19 +293,20 @@ __device__ inline void rr_pair(int mm, int r, int k, int &p, int &q) {
 __global__ void __launch_bounds__(256) k_syev(OrbSet o, int f0, const double *__restrict__ H,
                                               double *__restrict__ U, double *__restrict__ eps,
                                               int *flags) {
-  __shared__ double A[kMaxOrb * kMaxOrb];
-  __shared__ double V[kMaxOrb * kMaxOrb];
+  __shared__ double A[kMaxOrb * (kMaxOrb + 1)];
+  __shared__ double V[kMaxOrb * (kMaxOrb + 1)];
   __shared__ double cs[kMaxOrb / 2 + 1], sn[kMaxOrb / 2 + 1];
   __shared__ int pp[kMaxOrb / 2 + 1], qq[kMaxOrb / 2 + 1];
   __shared__ double red[16];
   __shared__ int rank_of[kMaxOrb];
   const int f = f0 + blockIdx.x;
   const int mf = o.m[f], mp = o.m_pad;
+  const int ld = mf + 1;   // odd row stride: column walks hit distinct banks
   const double *Hf = H + (long long)f * mp * mp;
   for (int e = threadIdx.x; e < mf * mf; e += blockDim.x) {
     const int i = e / mf, j = e % mf;
-    A[e] = Hf[i * mp + j];
-    V[e] = (i == j) ? 1.0 : 0.0;
+    A[i * ld + j] = 0.5 * (Hf[i * mp + j] + Hf[j * mp + i]);
+    V[i * ld + j] = (i == j) ? 1.0 : 0.0;
   }
   const int mm = (mf % 2) ? mf + 1 : mf;   // an odd size gets one idle index
   const int npair = mm / 2;
@@ -242,7 +317,7 @@ __global__ void __launch_bounds__(256) k_syev(OrbSet o, int f0, const double *__
     double off = 0.0, dia = 0.0;
     for (int e = threadIdx.x; e < mf * mf; e += blockDim.x) {
       const int i = e / mf, j = e % mf;
-      const double v = fabs(A[e]);
+      const double v = fabs(A[i * ld + j]);
       if (i == j) dia = fmax(dia, v);
       else off = fmax(off, v);
     }
@@ -272,9 +347,9 @@ __global__ void __launch_bounds__(256) k_syev(OrbSet o, int f0, const double *__
         rr_pair(mm, r, k, p, q);
         double c = 1.0, s = 0.0;
         if (q < mf) {
-          const double apq = A[p * mf + q];
+          const double apq = A[p * ld + q];
           if (apq != 0.0) {
-            const double tau = (A[q * mf + q] - A[p * mf + p]) / (2.0 * apq);
+            const double tau = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
             const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
@@ -292,9 +367,9 @@ __global__ void __launch_bounds__(256) k_syev(OrbSet o, int f0, const double *__
         const int p = pp[k], q = qq[k];
         if (q >= mf) continue;
         const double c = cs[k], s = sn[k];
-        const double ap = A[p * mf + j], aq = A[q * mf + j];
-        A[p * mf + j] = c * ap - s * aq;
-        A[q * mf + j] = s * ap + c * aq;
+        const double ap = A[p * ld + j], aq = A[q * ld + j];
+        A[p * ld + j] = c * ap - s * aq;
+        A[q * ld + j] = s * ap + c * aq;
       }
       __syncthreads();
       // columns: A <- A J, V <- V J
@@ -303,22 +378,22 @@ __global__ void __launch_bounds__(256) k_syev(OrbSet o, int f0, const double *__
         const int p = pp[k], q = qq[k];
         if (q >= mf) continue;
         const double c = cs[k], s = sn[k];
-        const double ap = A[i * mf + p], aq = A[i * mf + q];
-        A[i * mf + p] = c * ap - s * aq;
-        A[i * mf + q] = s * ap + c * aq;
-        const double vp = V[i * mf + p], vq = V[i * mf + q];
-        V[i * mf + p] = c * vp - s * vq;
-        V[i * mf + q] = s * vp + c * vq;
+        const double ap = A[i * ld + p], aq = A[i * ld + q];
+        A[i * ld + p] = c * ap - s * aq;
+        A[i * ld + q] = s * ap + c * aq;
+        const double vp = V[i * ld + p], vq = V[i * ld + q];
+        V[i * ld + p] = c * vp - s * vq;
+        V[i * ld + q] = s * vp + c * vq;
       }
     }
   }
   __syncthreads();
   // ascending order (ties by index), then canonical column signs
   for (int i = threadIdx.x; i < mf; i += blockDim.x) {
-    const double ai = A[i * mf + i];
+    const double ai = A[i * ld + i];
     int rk = 0;
     for (int j = 0; j < mf; ++j) {
-      const double aj = A[j * mf + j];
+      const double aj = A[j * ld + j];
       if (aj < ai || (aj == ai && j < i)) ++rk;
     }
     rank_of[i] = rk;
@@ -330,15 +405,15 @@ __global__ void __launch_bounds__(256) k_syev(OrbSet o, int f0, const double *__
     int best = 0;
     double bv = -1.0;
     for (int r = 0; r < mf; ++r) {
-      const double v = fabs(V[r * mf + i]);
+      const double v = fabs(V[r * ld + i]);
       if (v > bv) {
         bv = v;
         best = r;
       }
     }
-    const double sg = V[best * mf + i] < 0.0 ? -1.0 : 1.0;
-    for (int r = 0; r < mp; ++r) Uf[r * mp + col] = (r < mf) ? sg * V[r * mf + i] : 0.0;
-    eps[o.moff[f] + col] = A[i * mf + i];
+    const double sg = V[best * ld + i] < 0.0 ? -1.0 : 1.0;
+    for (int r = 0; r < mp; ++r) Uf[r * mp + col] = (r < mf) ? sg * V[r * ld + i] : 0.0;
+    eps[o.moff[f] + col] = A[i * ld + i];
   }
   for (int e = threadIdx.x; e < mp * mp; e += blockDim.x) {
     const int c = e % mp;
@@ -389,16 +464,32 @@ __global__ void k_copy(long long b0, long long nb, const double *__restrict__ sr
 template <int TM>
 void gram_t(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int kchunk,
             const double *x, const double *y, double *part, hipStream_t s) {
-  hipLaunchKernelGGL(k_gram<TM>, dim3((f1 - f0) * chunks), dim3(256), 0, s, g, o, f0, chunks,
-                     kchunk, x, y, part);
+  const bool sym = (x == y);
+  const bool vec = (g.n % 4) == 0;
+  const dim3 grid((f1 - f0) * chunks), block(256);
+  if (sym && vec)
+    hipLaunchKernelGGL((k_gram2<TM, true, true>), grid, block, 0, s, g, o, f0, chunks, kchunk, x,
+                       y, part);
+  else if (sym)
+    hipLaunchKernelGGL((k_gram2<TM, true, false>), grid, block, 0, s, g, o, f0, chunks, kchunk, x,
+                       y, part);
+  else if (vec)
+    hipLaunchKernelGGL((k_gram2<TM, false, true>), grid, block, 0, s, g, o, f0, chunks, kchunk, x,
+                       y, part);
+  else
+    hipLaunchKernelGGL((k_gram2<TM, false, false>), grid, block, 0, s, g, o, f0, chunks, kchunk,
+                       x, y, part);
 }
 
+constexpr int kRotTiles = 4;   // 16-point tiles per wave in k_rotate2
+
 template <int TM>
-void rotate_t(const Geo &g, const OrbSet &o, int f0, int f1, int tpf, const double *M,
-              int trans, const double *x, const double *z, double cz, double cm, double *y,
-              hipStream_t s) {
-  hipLaunchKernelGGL(k_rotate<TM>, dim3((f1 - f0) * tpf), dim3(256), 0, s, g, o, f0, tpf, M,
-                     trans, x, z, cz, cm, y);
+void rotate_t(const Geo &g, const OrbSet &o, int f0, int f1, const double *M, int trans,
+              const double *x, const double *z, double cz, double cm, double *y, hipStream_t s) {
+  const int per_wg = 4 * kRotTiles * 16;
+  const int wpf = (g.n + per_wg - 1) / per_wg;
+  hipLaunchKernelGGL((k_rotate2<TM, kRotTiles>), dim3((f1 - f0) * wpf), dim3(256), 0, s, g, o, f0,
+                     wpf, M, trans, x, z, cz, cm, y);
 }
 
 }  // namespace
@@ -421,24 +512,26 @@ void launch_gram(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, cons
   }
 }
 
-void launch_gram_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
+void launch_gram_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int sym,
                         const double *part, double *G, double *Gs, double *diag, hipStream_t s) {
   if (f1 <= f0) return;
-  hipLaunchKernelGGL(k_gram_reduce, dim3(f1 - f0), dim3(256), 0, s, g, o, f0, chunks * 4, part,
-                     G, Gs, diag);
+  const long long total = (long long)(f1 - f0) * o.m_pad * o.m_pad;
+  const unsigned nb = (unsigned)((total + 255) / 256);
+  hipLaunchKernelGGL(k_gram_reduce2, dim3(nb), dim3(256), 0, s, g, o, f0, f1 - f0, chunks, sym,
+                     part, G, diag);
+  if (Gs) hipLaunchKernelGGL(k_symmetrize, dim3(nb), dim3(256), 0, s, o, f0, f1 - f0, G, Gs);
 }
 
 void launch_rotate(const Geo &g, const OrbSet &o, int f0, int f1, const double *M, int trans,
                    const double *x, const double *z, double cz, double cm, double *y,
                    hipStream_t s) {
   if (f1 <= f0) return;
-  const int tpf = (g.n + 63) / 64;
   switch (o.tiles) {
-    case 1: rotate_t<1>(g, o, f0, f1, tpf, M, trans, x, z, cz, cm, y, s); break;
-    case 2: rotate_t<2>(g, o, f0, f1, tpf, M, trans, x, z, cz, cm, y, s); break;
-    case 3: rotate_t<3>(g, o, f0, f1, tpf, M, trans, x, z, cz, cm, y, s); break;
-    case 4: rotate_t<4>(g, o, f0, f1, tpf, M, trans, x, z, cz, cm, y, s); break;
-    default: rotate_t<5>(g, o, f0, f1, tpf, M, trans, x, z, cz, cm, y, s); break;
+    case 1: rotate_t<1>(g, o, f0, f1, M, trans, x, z, cz, cm, y, s); break;
+    case 2: rotate_t<2>(g, o, f0, f1, M, trans, x, z, cz, cm, y, s); break;
+    case 3: rotate_t<3>(g, o, f0, f1, M, trans, x, z, cz, cm, y, s); break;
+    case 4: rotate_t<4>(g, o, f0, f1, M, trans, x, z, cz, cm, y, s); break;
+    default: rotate_t<5>(g, o, f0, f1, M, trans, x, z, cz, cm, y, s); break;
   }
 }
 
