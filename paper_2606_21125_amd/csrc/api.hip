@@ -127,6 +127,13 @@ dcdft::KBTables dcdft_ctx::kb() const {
   k.pt_a = d_pt_a;
   k.pt_beta = d_pt_beta;
   k.E = d_E;
+  k.NR = NR;
+  k.KS = KS;
+  k.reg_atom = d_reg_atom;
+  k.reg_beta = d_reg_beta;
+  k.ar_ptr = d_ar_ptr;
+  k.ar_reg = d_ar_reg;
+  k.ar_slot = d_ar_slot;
   return k;
 }
 
@@ -193,11 +200,11 @@ double sum_m2(const dcdft_ctx *c, int f0, int f1) {
   return s;
 }
 
-void hloc(dcdft_ctx *c, int f0, int f1, const double *x, double *y) {
+void hloc(dcdft_ctx *c, int f0, int f1, const double *x, double *y, double *dot = nullptr) {
   const double n = c->geo.n;
   Timed t(c, DCDFT_KERNEL_HLOC, 16.0 * n * orbitals_in(c, f0, f1) + 8.0 * n * (f1 - f0),
           55.0 * n * orbitals_in(c, f0, f1));
-  launch_hloc(c->geo, c->orbset(f0, f1), f0, f1, c->d_veff, x, y, c->stream);
+  launch_hloc(c->geo, c->orbset(f0, f1), f0, f1, c->d_veff, x, y, c->stream, dot);
 }
 
 void rotate(dcdft_ctx *c, int f0, int f1, const double *M, int trans, const double *x,
@@ -214,7 +221,7 @@ void apply_h_range(dcdft_ctx *c, int f0, int f1, const double *x, double *y) {
   OrbSet o = c->orbset(f0, f1);
   KBTables kb = c->kb();
   hloc(c, f0, f1, x, y);
-  launch_kb_project(g, o, kb, f0, f1, x, c->d_C, c->stream, c->pair_first.data());
+  launch_kb_project(g, o, kb, f0, f1, x, c->d_C, c->d_cpart, c->stream);
   launch_kb_apply(g, o, kb, f0, f1, c->d_C, y, c->stream);
 }
 
@@ -231,53 +238,73 @@ void gram(dcdft_ctx *c, int f0, int f1, const double *x, const double *y, double
                      diag, c->stream);
 }
 
-// Steps (a)-(l) of the fragment CG eigensolver and the Rayleigh-Ritz rotation.
+// Steps (a)-(l) of the fragment CG eigensolver and the Rayleigh-Ritz rotation,
+// fused so that each kernel makes one pass over the orbital blocks it touches:
+//   G = W - Hs Psi with |g_i|^2; P = beta P_prev - G with <Psi, P>;
+//   P <- P - <Psi,P>^T Psi with |p_i|^2 and <p_i, w_i>; Q = H P with <p_i, q_i>;
+//   Psi <- c Psi + s P / |p|, W <- c W + s Q / |p| with <Psi, Psi>;
+//   Psi, W <- L^-1 (Psi, W).
+// The search direction is kept unnormalised (H is linear, so Q = H P and the
+// normalisation enters only through the scalars of the 2x2 problem).
 void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
   const Geo &g = c->geo;
   OrbSet o = c->orbset(f0, f1);
+  KBTables kb = c->kb();
   hipStream_t s = c->stream;
-  double *psi = c->d_psi, *w = c->d_w, *p = c->d_p, *q = c->d_q, *r = c->d_r;
+  double *psi = c->d_psi, *w = c->d_w, *p = c->d_p, *q = c->d_q;
+  const double n = g.n;
+  const double nb = orbitals_in(c, f0, f1);
+  const double m2 = sum_m2(c, f0, f1);
+  const int ch = c->gram_chunks;
   apply_h_range(c, f0, f1, psi, w);
   for (int sw = 0; sw < c->sweeps; ++sw) {
     // (a) Hs = sym(<Psi, W>), a_i = <psi_i, w_i>
     gram(c, f0, f1, psi, w, c->d_hs_full, c->d_hs, c->d_a);
-    // (b) G = W - Hs Psi  (kept in q)
-    rotate(c, f0, f1, c->d_hs, 0, psi, w, 1.0, -1.0, q);
-    // (c) gamma, Fletcher-Reeves beta
-    launch_band_dot(g, o, f0, f1, q, q, 0, c->d_gamma, s);
+    // (b)-(c) G = W - Hs Psi (kept in q), gamma_i = <g_i, g_i>, Fletcher-Reeves beta
+    {
+      Timed t(c, DCDFT_KERNEL_ROTATE, 24.0 * n * nb, 2.0 * n * m2);
+      launch_rot_residual(g, o, f0, f1, c->d_hs, psi, w, q, c->d_dpart, c->d_gamma, s);
+    }
     launch_cg_beta(o, f0, f1, sw == 0, c->d_gamma, c->d_gamma_prev, c->d_beta, s);
-    // (d) P = -G + beta P_prev
-    launch_band_axpby(g, o, f0, f1, c->d_beta, 0.0, nullptr, -1.0, q, p, s);
-    // (e) P <- P - <Psi, P>^T Psi
-    gram(c, f0, f1, psi, p, c->d_x, nullptr, nullptr);
-    rotate(c, f0, f1, c->d_x, 0, psi, p, 1.0, -1.0, p);
-    // (f) normalised direction in r
-    launch_band_dot(g, o, f0, f1, p, p, 0, c->d_nu, s);
+    // (d)-(e) P = -G + beta P_prev, X = <Psi, P>
+    {
+      Timed t(c, DCDFT_KERNEL_GRAM, 32.0 * n * nb, 2.0 * n * m2);
+      launch_gram_direction(g, o, f0, f1, ch, psi, q, p, c->d_beta, c->d_gpart, s);
+    }
+    launch_gram_reduce(g, o, f0, f1, ch, 0, c->d_gpart, c->d_x, nullptr, nullptr, s);
+    // (e)-(f) P <- P - X^T Psi, nu_i = <p_i, p_i>, <p_i, w_i>
+    {
+      Timed t(c, DCDFT_KERNEL_ROTATE, 32.0 * n * nb, 2.0 * n * m2);
+      launch_rot_project_out(g, o, f0, f1, c->d_x, psi, p, w, c->d_dpart, c->d_nu, c->d_bb, s);
+    }
     launch_cg_norm(o, f0, f1, c->d_nu, c->d_inv, s);
-    launch_band_axpby(g, o, f0, f1, nullptr, 0.0, c->d_inv, 0.0, p, r, s);
-    // (g) Q = H p_hat
-    apply_h_range(c, f0, f1, r, q);
-    // (h)-(i) 2x2 Rayleigh quotient and its exact minimiser
-    launch_band_dot(g, o, f0, f1, r, w, 0, c->d_bb, s);
-    launch_band_dot(g, o, f0, f1, r, q, 0, c->d_cc, s);
+    // (g) Q = H P and <p_i, q_i>
+    hloc(c, f0, f1, p, q, c->d_cc);
+    launch_kb_project(g, o, kb, f0, f1, p, c->d_C, c->d_cpart, s);
+    launch_kb_apply(g, o, kb, f0, f1, c->d_C, q, s);
+    launch_kb_quad(o, f0, f1, kb, c->d_C, c->d_cc, s);
+    // (h)-(i) exact minimiser of the 2x2 Rayleigh quotient
     launch_cg_theta(o, f0, f1, c->d_a, c->d_bb, c->d_cc, c->d_inv, c->d_cos, c->d_sin, s);
-    // (j) rotate each band within span(psi_i, p_hat_i)
-    launch_band_axpby(g, o, f0, f1, c->d_cos, 0.0, c->d_sin, 0.0, r, psi, s);
-    launch_band_axpby(g, o, f0, f1, c->d_cos, 0.0, c->d_sin, 0.0, q, w, s);
-    // (k)
-    launch_copy_band(o, f0, f1, c->d_gamma, c->d_gamma_prev, s);
-    // (l) Cholesky re-orthonormalisation
-    gram(c, f0, f1, psi, psi, c->d_s, nullptr, nullptr);
+    // (j) band rotations and (l) S = sym(<Psi, Psi>)
+    {
+      Timed t(c, DCDFT_KERNEL_GRAM, 48.0 * n * nb, 1.0 * n * m2);
+      launch_gram_update(g, o, f0, f1, ch, psi, p, w, q, c->d_cos, c->d_sin, c->d_gpart, s);
+    }
+    launch_gram_reduce(g, o, f0, f1, ch, 1, c->d_gpart, c->d_s, nullptr, nullptr, s);
+    // (l) S = L L^T, Psi <- L^-1 Psi, W <- L^-1 W
     launch_cholinv(o, f0, f1, c->d_s, c->d_lin, c->d_flags, s);
-    rotate(c, f0, f1, c->d_lin, 1, psi, nullptr, 0.0, 1.0, psi);
-    rotate(c, f0, f1, c->d_lin, 1, w, nullptr, 0.0, 1.0, w);
+    {
+      Timed t(c, DCDFT_KERNEL_ROTATE, 32.0 * n * nb, 2.0 * n * m2);
+      launch_rot_cholesky(g, o, f0, f1, c->d_lin, psi, w, s);
+    }
   }
-  // Rayleigh-Ritz
+  // Rayleigh-Ritz, then core weights w_i = dV sum_core psi_i^2
   gram(c, f0, f1, psi, w, c->d_hs, nullptr, nullptr);
   launch_syev(o, f0, f1, c->d_hs, c->d_u, c->d_eps, c->d_flags, s);
-  rotate(c, f0, f1, c->d_u, 0, psi, nullptr, 0.0, 1.0, psi);
-  // core weights w_i = dV sum_core psi_i^2
-  launch_band_dot(g, o, f0, f1, psi, psi, 1, c->d_wcore, s);
+  {
+    Timed t(c, DCDFT_KERNEL_ROTATE, 16.0 * n * nb, 2.0 * n * m2);
+    launch_rot_ritz(g, o, f0, f1, c->d_u, psi, c->d_dpart, c->d_wcore, s);
+  }
 }
 
 void orthonormalize_all(dcdft_ctx *c) {
@@ -467,6 +494,69 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
       pt_beta[slot] = atom_beta[e];
     }
   }
+  // region-dense tables
+  c->NR = (g.n + kRegion - 1) / kRegion;
+  {
+    std::vector<std::vector<int>> reg_atoms((size_t)nF * c->NR);
+    for (int P = 0; P < c->n_pairs; ++P) {
+      const int f = pair_frag[P];
+      int last = -1;
+      std::vector<char> seen(c->NR, 0);
+      for (long long e = pair_ptr[P]; e < pair_ptr[P + 1]; ++e) {
+        const int r = atom_l[e] / kRegion;
+        if (!seen[r]) {
+          seen[r] = 1;
+          reg_atoms[(size_t)f * c->NR + r].push_back(pair_atom[P]);
+        }
+        (void)last;
+      }
+    }
+    int ks = 16;
+    for (auto &v : reg_atoms) ks = std::max(ks, (int)v.size());
+    ks = ((ks + 15) / 16) * 16;
+    if (ks > 16 * kMaxSlotTiles)
+      return set_err(c, DCDFT_ERR_ARG,
+                     fmt("%d projectors meet one %d-point region; at most %d are supported", ks,
+                         kRegion, 16 * kMaxSlotTiles));
+    c->KS = ks;
+    std::vector<int> reg_atom((size_t)nF * c->NR * ks, -1);
+    std::vector<double> reg_beta((size_t)nF * c->NR * ks * kRegion, 0.0);
+    // slot of (fragment, region, atom)
+    std::vector<std::vector<std::pair<int, int>>> ar((size_t)nF * c->A_max);
+    for (int f = 0; f < nF; ++f)
+      for (int r = 0; r < c->NR; ++r) {
+        auto &v = reg_atoms[(size_t)f * c->NR + r];
+        std::sort(v.begin(), v.end());
+        for (size_t k = 0; k < v.size(); ++k) {
+          reg_atom[((size_t)f * c->NR + r) * ks + k] = v[k];
+          ar[(size_t)f * c->A_max + v[k]].push_back({r, (int)k});
+        }
+      }
+    for (int P = 0; P < c->n_pairs; ++P) {
+      const int f = pair_frag[P], a = pair_atom[P];
+      for (long long e = pair_ptr[P]; e < pair_ptr[P + 1]; ++e) {
+        const int l = atom_l[e], r = l / kRegion;
+        int slot = -1;
+        for (auto &rs : ar[(size_t)f * c->A_max + a])
+          if (rs.first == r) slot = rs.second;
+        reg_beta[(((size_t)f * c->NR + r) * ks + slot) * kRegion + (l % kRegion)] = atom_beta[e];
+      }
+    }
+    std::vector<long long> ar_ptr((size_t)nF * c->A_max + 1, 0);
+    std::vector<int> ar_reg, ar_slot;
+    for (size_t q = 0; q < ar.size(); ++q) {
+      for (auto &rs : ar[q]) {
+        ar_reg.push_back(rs.first);
+        ar_slot.push_back(rs.second);
+      }
+      ar_ptr[q + 1] = (long long)ar_reg.size();
+    }
+    HIPTRY(c, upload(c, &c->d_reg_atom, reg_atom));
+    HIPTRY(c, upload(c, &c->d_reg_beta, reg_beta));
+    HIPTRY(c, upload(c, &c->d_ar_ptr, ar_ptr));
+    HIPTRY(c, upload(c, &c->d_ar_reg, ar_reg));
+    HIPTRY(c, upload(c, &c->d_ar_slot, ar_slot));
+  }
   std::vector<double> Eflat((size_t)nF * c->A_max, 0.0);
   for (int f = 0; f < nF; ++f)
     for (size_t a = 0; a < Ef[f].size(); ++a) Eflat[(size_t)f * c->A_max + a] = Ef[f][a];
@@ -611,8 +701,8 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   c->seed = p->seed;
   // Gram chunks: aim at >= 512 four-wave workgroups over all fragments
   {
-    int ch = (512 + c->nF - 1) / c->nF;
-    const int maxch = std::max(1, g.n / 256);
+    int ch = (1024 + c->nF - 1) / c->nF;
+    const int maxch = std::max(1, g.n / 128);
     c->gram_chunks = std::max(1, std::min(ch, maxch));
   }
   if (p->hip_stream) {
@@ -660,6 +750,7 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   ALLOC(c->d_q, norb);
   ALLOC(c->d_r, norb);
   ALLOC(c->d_C, (long long)c->nF * c->A_max * c->m_pad);
+  ALLOC(c->d_cpart, (long long)c->nF * c->NR * c->KS * c->m_pad);
   ALLOC(c->d_vh, g.Ng);
   ALLOC(c->d_rho_in, g.Ng);
   ALLOC(c->d_rho_out, g.Ng);
@@ -670,6 +761,7 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   ALLOC(c->d_rhof_out, (long long)c->nF * g.n);
   ALLOC(c->d_gpart, (long long)c->nF * c->gram_chunks * mp2);
   ALLOC(c->d_gtmp, c->nF * mp2);
+  ALLOC(c->d_dpart, (long long)c->nF * rot_wpf(g) * 2 * c->m_pad);
   ALLOC(c->d_hs_full, c->nF * mp2);
   ALLOC(c->d_hs, c->nF * mp2);
   ALLOC(c->d_x, c->nF * mp2);
@@ -986,7 +1078,7 @@ dcdft_status apply_h_ext(dcdft_ctx *c, int frag, const double *psi, double *hpsi
     const double *x = psi + (long long)i0 * g.n;
     double *y = hpsi + (long long)i0 * g.n;
     launch_hloc(g, o, frag, frag + 1, c->d_veff, x, y, c->stream);
-    launch_kb_project(g, o, kb, frag, frag + 1, x, c->d_C, c->stream, c->pair_first.data());
+    launch_kb_project(g, o, kb, frag, frag + 1, x, c->d_C, c->d_cpart, c->stream);
     launch_kb_apply(g, o, kb, frag, frag + 1, c->d_C, y, c->stream);
     hipError_t e = hipStreamSynchronize(c->stream);
     free_ext(L);

@@ -53,8 +53,21 @@ struct OrbSet {           // flattened orbital layout [M_tot][n]
   long long nb(int f0, int f1) const { return h_moff[f1] - h_moff[f0]; }
 };
 
+// Region-dense projector tables: each fragment's points are cut into regions of
+// kRegion consecutive points; a region lists the KS_max (padded) fragment atoms
+// whose support meets it and stores their beta values densely [slot][point].
+constexpr int kRegion = 256;
+constexpr int kMaxSlotTiles = 6;    // KS_max <= 96 slots per region
+
 struct KBTables {
   int A_max;
+  int NR;                            // regions per fragment
+  int KS;                            // slots per region (multiple of 16)
+  const int *reg_atom;               // [F][NR][KS] local atom index or -1
+  const double *reg_beta;            // [F][NR][KS][kRegion]
+  const long long *ar_ptr;           // [F * A_max + 1] into (region, slot) lists
+  const int *ar_reg;                 // region of each entry
+  const int *ar_slot;                // slot of each entry
   int n_pairs;                       // total (fragment, atom) pairs
   const int *A;                      // [F] atoms per fragment
   const int *pair_frag;              // [n_pairs]
@@ -106,6 +119,11 @@ struct dcdft_ctx {
   int *d_atom_l = nullptr, *d_pt_a = nullptr;
   double *d_atom_beta = nullptr, *d_pt_beta = nullptr, *d_E = nullptr;
   double *d_C = nullptr;             // [F][A_max][m_pad] projections
+  int NR = 0, KS = 0;
+  int *d_reg_atom = nullptr, *d_ar_reg = nullptr, *d_ar_slot = nullptr;
+  double *d_reg_beta = nullptr;
+  long long *d_ar_ptr = nullptr;
+  double *d_cpart = nullptr;         // region projection partials [F][NR][KS][m_pad]
 
   // orbital arrays [M_tot][n]
   double *d_psi = nullptr, *d_w = nullptr, *d_p = nullptr, *d_q = nullptr, *d_r = nullptr;
@@ -121,6 +139,7 @@ struct dcdft_ctx {
   // small matrices [F][m_pad][m_pad]
   double *d_gpart = nullptr;         // Gram partials [F][chunks][m_pad][m_pad]
   double *d_gtmp = nullptr;          // Gram result when only the symmetric part is kept
+  double *d_dpart = nullptr;         // per-workgroup band partials [F][wpf][2][m_pad]
   double *d_hs_full = nullptr, *d_hs = nullptr, *d_x = nullptr, *d_s = nullptr, *d_lin = nullptr,
          *d_u = nullptr;
 
@@ -157,12 +176,13 @@ namespace dcdft {
 
 // ---- launchers (all asynchronous on the given stream) -------------------------------------
 
-// Y = (-1/2 L_FD + V_eff) X for every orbital of fragments [f0, f1).
+// Y = (-1/2 L_FD + V_eff) X for every orbital of fragments [f0, f1); dot (if not
+// null) receives dV <x_B, y_B> per band.
 void launch_hloc(const Geo &g, const OrbSet &o, int f0, int f1, const double *veff,
-                 const double *x, double *y, hipStream_t s);
+                 const double *x, double *y, hipStream_t s, double *dot = nullptr);
 // C[f][a][i] = dV sum beta_a(l) X_i(l)
 void launch_kb_project(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1,
-                       const double *x, double *C, hipStream_t s, const int *h_pair_first);
+                       const double *x, double *C, double *part, hipStream_t s);
 // Y_i(l) += sum_a beta_a(l) E_a C[f][a][i]
 void launch_kb_apply(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1,
                      const double *C, double *y, hipStream_t s);
@@ -185,14 +205,43 @@ void launch_band_axpby(const Geo &g, const OrbSet &o, int f0, int f1, const doub
                        double a_const, const double *b, double b_const, const double *x,
                        double *y, hipStream_t s);
 // CG scalar steps
+// beta = gamma / gamma_prev (0 on the first sweep), then gamma_prev = gamma
 void launch_cg_beta(const OrbSet &o, int f0, int f1, int first, const double *gamma,
-                    const double *gamma_prev, double *beta, hipStream_t s);
+                    double *gamma_prev, double *beta, hipStream_t s);
 void launch_cg_norm(const OrbSet &o, int f0, int f1, const double *nu, double *inv,
                     hipStream_t s);
 void launch_cg_theta(const OrbSet &o, int f0, int f1, const double *a, const double *b,
                      const double *c, const double *inv, double *cs, double *sn, hipStream_t s);
 void launch_copy_band(const OrbSet &o, int f0, int f1, const double *src, double *dst,
                       hipStream_t s);
+// Fused sweep kernels (per-band reductions go through dpart, one partial per
+// rotation workgroup, then a band reduction).
+int rot_wpf(const Geo &g);
+// G = W - Hs Psi into gout, gamma = dV |G|^2
+void launch_rot_residual(const Geo &g, const OrbSet &o, int f0, int f1, const double *Hs,
+                         const double *psi, const double *w, double *gout, double *dpart,
+                         double *gamma, hipStream_t s);
+// P <- P - X^T Psi, nu = dV |P|^2, pw = dV <P, W>
+void launch_rot_project_out(const Geo &g, const OrbSet &o, int f0, int f1, const double *X,
+                            const double *psi, double *p, const double *w, double *dpart,
+                            double *nu, double *pw, hipStream_t s);
+// Psi <- Linv Psi, W <- Linv W (Linv lower triangular, row-major)
+void launch_rot_cholesky(const Geo &g, const OrbSet &o, int f0, int f1, const double *Linv,
+                         double *psi, double *w, hipStream_t s);
+// Psi <- U^T Psi (Ritz vectors), wcore = dV sum_core psi^2
+void launch_rot_ritz(const Geo &g, const OrbSet &o, int f0, int f1, const double *U, double *psi,
+                     double *dpart, double *wcore, hipStream_t s);
+// P = beta P - G (in place over P), Gram partials of Psi^T P
+void launch_gram_direction(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
+                           const double *psi, const double *gres, double *p, const double *beta,
+                           double *part, hipStream_t s);
+// Psi <- cs Psi + sn P, W <- cs W + sn Q (in place), symmetric Gram partials of Psi
+void launch_gram_update(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, double *psi,
+                        const double *p, double *w, const double *q, const double *cs,
+                        const double *sn, double *part, hipStream_t s);
+// cp[B] += sum_a E_a C[f][a][i]^2
+void launch_kb_quad(const OrbSet &o, int f0, int f1, const KBTables &kb, const double *C,
+                    double *cp, hipStream_t s);
 // S -> Linv (row-major lower-triangular inverse of the Cholesky factor), FP64
 void launch_cholinv(const OrbSet &o, int f0, int f1, const double *S, double *Linv, int *flags,
                     hipStream_t s);

@@ -36,8 +36,10 @@ __device__ inline double block_sum(double v, double *red) {
 __global__ void __launch_bounds__(1024) k_hloc(Geo g, const int *__restrict__ band_frag,
                                                long long b0, const double *__restrict__ veff,
                                                const double *__restrict__ x,
-                                               double *__restrict__ y) {
+                                               double *__restrict__ y, double *__restrict__ dot) {
   extern __shared__ double lds[];
+  __shared__ double red[16];
+  double dacc = 0.0;
   const long long B = b0 + blockIdx.x;
   const int f = band_frag[B];
   const int nx = g.nl[0], ny = g.nl[1], nz = g.nl[2];
@@ -82,57 +84,153 @@ __global__ void __launch_bounds__(1024) k_hloc(Geo g, const int *__restrict__ ba
     const long long e = (long long)z * plane + t;
     acc += vb[e] * win[4];
     yb[e] = acc;
+    dacc += win[4] * acc;
 #pragma unroll
     for (int k = 0; k < 8; ++k) win[k] = win[k + 1];
     const int zn = (z + 5) % nz;
     win[8] = xb[(long long)zn * plane + t];
   }
-}
-
-// c[f][a][i] = dV sum_e beta_e X_i(l_e) over the support entries of atom a.
-__global__ void __launch_bounds__(256) k_kb_project(Geo g, KBTables kb, const int *__restrict__ m,
-                                                    const long long *__restrict__ moff, int m_pad,
-                                                    int pair0, const double *__restrict__ x,
-                                                    double *__restrict__ C) {
-  const int P = pair0 + blockIdx.x;
-  const int f = kb.pair_frag[P];
-  const int a = kb.pair_atom[P];
-  const long long e0 = kb.pair_ptr[P], e1 = kb.pair_ptr[P + 1];
-  const int mf = m[f];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
-  for (int i = wave; i < mf; i += nw) {
-    const double *xb = x + (moff[f] + i) * (long long)g.n;
-    double acc = 0.0;
-    for (long long e = e0 + lane; e < e1; e += 64) acc += kb.atom_beta[e] * xb[kb.atom_l[e]];
-    acc = wave_sum(acc);
-    if (lane == 0) C[((long long)f * kb.A_max + a) * m_pad + i] = g.dv * acc;
+  if (dot) {
+    dacc = block_sum(dacc, red);
+    if (t == 0) dot[B] = g.dv * dacc;
   }
 }
 
-// Y_i(l) += sum over the projectors covering l of beta_a(l) E_a C[f][a][i].
-__global__ void __launch_bounds__(256) k_kb_apply(Geo g, KBTables kb, const int *__restrict__ m,
-                                                  const long long *__restrict__ moff, int m_pad,
-                                                  int f0, int f1, const double *__restrict__ C,
-                                                  double *__restrict__ y) {
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long total = (long long)(f1 - f0) * g.n;
-  if (idx >= total) return;
-  const int f = f0 + (int)(idx / g.n);
-  const int l = (int)(idx % g.n);
-  const long long q = (long long)f * g.n + l;
-  const long long e0 = kb.pt_ptr[q], e1 = kb.pt_ptr[q + 1];
-  if (e0 == e1) return;
-  const double *Cf = C + (long long)f * kb.A_max * m_pad;
-  const double *Ef = kb.E + (long long)f * kb.A_max;
-  const int mf = m[f];
-  for (int i = 0; i < mf; ++i) {
-    double s = 0.0;
-    for (long long e = e0; e < e1; ++e) {
-      const int a = kb.pt_a[e];
-      s += kb.pt_beta[e] * Ef[a] * Cf[(long long)a * m_pad + i];
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64 (gfx950 lane layout: A[l%16][l/16], B[l/16][l%16],
+// D[l/16 + 4r][l%16]).
+__device__ inline dbl4 mfma16x16x4(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Region partials of the projections: part[(f, region)][slot][i] =
+// sum_{l in region} beta_slot(l) X_i(l), as MFMA products of the dense region
+// block (slots x points) with the region's orbital columns.  Wave w takes the
+// orbital tiles w, w + 4; the K index walks points as u*16 + 4 (lane/16) + t so
+// that every lane reads 32 contiguous bytes of both operands.
+template <int TM, int KT>
+__global__ void __launch_bounds__(256) k_kb_project2(Geo g, OrbSet o, KBTables kb, int f0,
+                                                     const double *__restrict__ x,
+                                                     double *__restrict__ part) {
+  const int f = f0 + blockIdx.x / kb.NR;
+  const int reg = blockIdx.x % kb.NR;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int mf = o.m[f];
+  const int pbase = reg * kRegion;
+  const long long base = o.moff[f] * (long long)g.n;
+  const double *blk = kb.reg_beta + ((long long)f * kb.NR + reg) * kb.KS * kRegion;
+  const int r = lane & 15, kk = lane >> 4;
+  constexpr int JW = (TM + 3) / 4;   // orbital tiles per wave
+  dbl4 acc[KT][JW];
+#pragma unroll
+  for (int a = 0; a < KT; ++a)
+#pragma unroll
+    for (int b = 0; b < JW; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int u = 0; u < kRegion / 16; ++u) {
+    const int pu = pbase + u * 16 + 4 * kk;
+    double bx[JW][4];
+#pragma unroll
+    for (int q = 0; q < JW; ++q) {
+      const int jt = wave + 4 * q;
+      const int orb = jt * 16 + r;
+      const bool ok = jt < TM && orb < mf;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        bx[q][t] = (ok && pu + t < g.n) ? x[base + (long long)orb * g.n + pu + t] : 0.0;
     }
-    y[(moff[f] + i) * (long long)g.n + l] += s;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+      for (int st = 0; st < KT; ++st) {
+        const double av = blk[(st * 16 + r) * kRegion + u * 16 + 4 * kk + t];
+#pragma unroll
+        for (int q = 0; q < JW; ++q) acc[st][q] = mfma16x16x4(av, bx[q][t], acc[st][q]);
+      }
+    }
+  }
+  double *out = part + ((long long)f * kb.NR + reg) * kb.KS * o.m_pad;
+#pragma unroll
+  for (int q = 0; q < JW; ++q) {
+    const int jt = wave + 4 * q;
+    if (jt >= TM) continue;
+#pragma unroll
+    for (int st = 0; st < KT; ++st)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int slot = st * 16 + kk + 4 * rr;
+        const int orb = jt * 16 + r;
+        out[slot * o.m_pad + orb] = acc[st][q][rr];
+      }
+  }
+}
+
+// C[f][a][i] = dV sum over the (region, slot) entries of atom a.
+__global__ void __launch_bounds__(256) k_kb_reduce(Geo g, OrbSet o, KBTables kb, int f0, int nf,
+                                                   const double *__restrict__ part,
+                                                   double *__restrict__ C) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = (long long)nf * kb.A_max * o.m_pad;
+  if (idx >= total) return;
+  const int i = (int)(idx % o.m_pad);
+  const long long fa = (long long)f0 * kb.A_max + idx / o.m_pad;
+  const int f = (int)(fa / kb.A_max);
+  double s = 0.0;
+  for (long long e = kb.ar_ptr[fa]; e < kb.ar_ptr[fa + 1]; ++e) {
+    const long long q = ((long long)f * kb.NR + kb.ar_reg[e]) * kb.KS + kb.ar_slot[e];
+    s += part[q * o.m_pad + i];
+  }
+  C[fa * o.m_pad + i] = g.dv * s;
+}
+
+// Y_i(l) += sum_slot beta_slot(l) E_slot C[f][slot atom][i] per region, as MFMA
+// products of (E C)^T (orbitals x slots, staged in LDS) with the dense region
+// block (slots x points); wave w takes the 16-point tiles w, w + 4, ...
+template <int TM, int KT>
+__global__ void __launch_bounds__(256) k_kb_apply2(Geo g, OrbSet o, KBTables kb, int f0,
+                                                   const double *__restrict__ C,
+                                                   double *__restrict__ y) {
+  constexpr int MP = 16 * TM;
+  constexpr int LD = MP + ((16 - MP % 32) + 32) % 32;
+  constexpr int KSM = 16 * KT;
+  __shared__ double ec[KSM * LD];
+  const int f = f0 + blockIdx.x / kb.NR;
+  const int reg = blockIdx.x % kb.NR;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int mf = o.m[f];
+  const int *ra = kb.reg_atom + ((long long)f * kb.NR + reg) * kb.KS;
+  const double *Cf = C + (long long)f * kb.A_max * o.m_pad;
+  const double *Ef = kb.E + (long long)f * kb.A_max;
+  for (int e = threadIdx.x; e < KSM * MP; e += blockDim.x) {
+    const int slot = e / MP, i = e % MP;
+    const int a = (slot < kb.KS) ? ra[slot] : -1;
+    ec[slot * LD + i] = (a >= 0 && i < mf) ? Ef[a] * Cf[(long long)a * o.m_pad + i] : 0.0;
+  }
+  __syncthreads();
+  const double *blk = kb.reg_beta + ((long long)f * kb.NR + reg) * kb.KS * kRegion;
+  const long long base = o.moff[f] * (long long)g.n;
+  const int c = lane & 15, kk = lane >> 4;
+  for (int u = wave; u < kRegion / 16; u += 4) {
+    const int p = reg * kRegion + u * 16 + c;
+    dbl4 acc[TM];
+#pragma unroll
+    for (int j = 0; j < TM; ++j) acc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int st = 0; st < KT * 4; ++st) {
+      const double bv = blk[(4 * st + kk) * kRegion + u * 16 + c];
+#pragma unroll
+      for (int jt = 0; jt < TM; ++jt)
+        acc[jt] = mfma16x16x4(ec[(4 * st + kk) * LD + jt * 16 + c], bv, acc[jt]);
+    }
+    if (p < g.n) {
+#pragma unroll
+      for (int jt = 0; jt < TM; ++jt)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int orb = jt * 16 + kk + 4 * rr;
+          if (orb < mf) y[base + (long long)orb * g.n + p] += acc[jt][rr];
+        }
+    }
   }
 }
 
@@ -256,28 +354,61 @@ inline int grid_for(long long n, int block) {
 }  // namespace
 
 void launch_hloc(const Geo &g, const OrbSet &o, int f0, int f1, const double *veff,
-                 const double *x, double *y, hipStream_t s) {
+                 const double *x, double *y, hipStream_t s, double *dot) {
   const long long nb = o.nb(f0, f1);
   if (nb <= 0) return;
   const int plane = g.nl[0] * g.nl[1];
   hipLaunchKernelGGL(k_hloc, dim3((unsigned)nb), dim3(plane), 2 * plane * sizeof(double), s, g,
-                     o.band_frag, o.b0(f0), veff, x, y);
+                     o.band_frag, o.b0(f0), veff, x, y, dot);
+}
+
+template <int TM, int KT>
+void kb_t(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1, const double *x,
+          double *C, double *part, double *y, hipStream_t s) {
+  const dim3 grid((f1 - f0) * kb.NR), block(256);
+  if (x) {
+    hipLaunchKernelGGL((k_kb_project2<TM, KT>), grid, block, 0, s, g, o, kb, f0, x, part);
+    const long long total = (long long)(f1 - f0) * kb.A_max * o.m_pad;
+    hipLaunchKernelGGL(k_kb_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, o,
+                       kb, f0, f1 - f0, part, C);
+  } else {
+    hipLaunchKernelGGL((k_kb_apply2<TM, KT>), grid, block, 0, s, g, o, kb, f0, C, y);
+  }
+}
+
+template <int TM>
+void kb_tm(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1, const double *x,
+           double *C, double *part, double *y, hipStream_t s) {
+  switch (kb.KS / 16) {
+    case 1: kb_t<TM, 1>(g, o, kb, f0, f1, x, C, part, y, s); break;
+    case 2: kb_t<TM, 2>(g, o, kb, f0, f1, x, C, part, y, s); break;
+    case 3: kb_t<TM, 3>(g, o, kb, f0, f1, x, C, part, y, s); break;
+    case 4: kb_t<TM, 4>(g, o, kb, f0, f1, x, C, part, y, s); break;
+    case 5: kb_t<TM, 5>(g, o, kb, f0, f1, x, C, part, y, s); break;
+    default: kb_t<TM, 6>(g, o, kb, f0, f1, x, C, part, y, s); break;
+  }
+}
+
+void kb_dispatch(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1,
+                 const double *x, double *C, double *part, double *y, hipStream_t s) {
+  if (f1 <= f0) return;
+  switch (o.tiles) {
+    case 1: kb_tm<1>(g, o, kb, f0, f1, x, C, part, y, s); break;
+    case 2: kb_tm<2>(g, o, kb, f0, f1, x, C, part, y, s); break;
+    case 3: kb_tm<3>(g, o, kb, f0, f1, x, C, part, y, s); break;
+    case 4: kb_tm<4>(g, o, kb, f0, f1, x, C, part, y, s); break;
+    default: kb_tm<5>(g, o, kb, f0, f1, x, C, part, y, s); break;
+  }
 }
 
 void launch_kb_project(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1,
-                       const double *x, double *C, hipStream_t s, const int *h_pair_first) {
-  const int p0 = h_pair_first[f0], p1 = h_pair_first[f1];
-  if (p1 <= p0) return;
-  hipLaunchKernelGGL(k_kb_project, dim3(p1 - p0), dim3(256), 0, s, g, kb, o.m, o.moff, o.m_pad,
-                     p0, x, C);
+                       const double *x, double *C, double *part, hipStream_t s) {
+  kb_dispatch(g, o, kb, f0, f1, x, C, part, nullptr, s);
 }
 
 void launch_kb_apply(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1,
                      const double *C, double *y, hipStream_t s) {
-  const long long total = (long long)(f1 - f0) * g.n;
-  if (total <= 0) return;
-  hipLaunchKernelGGL(k_kb_apply, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, kb,
-                     o.m, o.moff, o.m_pad, f0, f1, C, y);
+  kb_dispatch(g, o, kb, f0, f1, nullptr, const_cast<double *>(C), nullptr, y, s);
 }
 
 void launch_band_dot(const Geo &g, const OrbSet &o, int f0, int f1, const double *x,

@@ -24,99 +24,6 @@ __device__ inline dbl4 mfma16x16x4(double a, double b, dbl4 c) {
 // different bank halves.
 __host__ __device__ constexpr int lds_stride(int mp) { return mp + ((16 - mp % 32) + 32) % 32; }
 
-// Gram partials, version 2.  Workgroup = (fragment, chunk of kchunk points); each
-// of the 4 waves accumulates every output tile over a quarter of the chunk (the
-// upper-triangle tiles only when X == Y), then the 4 wave results are summed in
-// LDS and one partial per workgroup is written.  With VEC each lane fetches its 4
-// consecutive points as two 16-byte loads (rows are 32-byte aligned when n % 4 == 0).
-template <int TM, bool SYM, bool VEC>
-__global__ void __launch_bounds__(256) k_gram2(Geo g, OrbSet o, int f0, int chunks, int kchunk,
-                                               const double *__restrict__ x,
-                                               const double *__restrict__ y,
-                                               double *__restrict__ part) {
-  __shared__ double red[kMaxOrb * kMaxOrb];
-  const int f = f0 + blockIdx.x / chunks;
-  const int c = blockIdx.x % chunks;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int mf = o.m[f];
-  const int mp = o.m_pad;
-  const long long base = o.moff[f] * (long long)g.n;
-  const int sub = kchunk / 4;
-  const int p_begin = c * kchunk + wave * sub;
-  const int p_end = min(p_begin + sub, g.n);
-  const int r = lane & 15, kk = lane >> 4;
-  dbl4 acc[TM][TM];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TM; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int p0 = p_begin; p0 < p_end; p0 += 16) {
-    double xa[TM][4], yb[TM][4];
-    const int pl = p0 + 4 * kk;
-#pragma unroll
-    for (int ti = 0; ti < TM; ++ti) {
-      const int row = ti * 16 + r;
-      const bool rok = row < mf;
-      const double *xr = x + base + (long long)row * g.n;
-      const double *yr = y + base + (long long)row * g.n;
-      if (VEC && rok && pl + 3 < p_end) {
-        const double2 a0 = *reinterpret_cast<const double2 *>(xr + pl);
-        const double2 a1 = *reinterpret_cast<const double2 *>(xr + pl + 2);
-        xa[ti][0] = a0.x; xa[ti][1] = a0.y; xa[ti][2] = a1.x; xa[ti][3] = a1.y;
-        if (!SYM) {
-          const double2 b0 = *reinterpret_cast<const double2 *>(yr + pl);
-          const double2 b1 = *reinterpret_cast<const double2 *>(yr + pl + 2);
-          yb[ti][0] = b0.x; yb[ti][1] = b0.y; yb[ti][2] = b1.x; yb[ti][3] = b1.y;
-        }
-      } else {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const bool ok = rok && pl + t < p_end;
-          xa[ti][t] = ok ? xr[pl + t] : 0.0;
-          if (!SYM) yb[ti][t] = ok ? yr[pl + t] : 0.0;
-        }
-      }
-      if (SYM) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) yb[ti][t] = xa[ti][t];
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int ti = 0; ti < TM; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < TM; ++tj)
-          if (!SYM || ti <= tj) acc[ti][tj] = mfma16x16x4(xa[ti][t], yb[tj][t], acc[ti][tj]);
-  }
-  // sum the four wave partials in LDS (fixed order: wave 0, 1, 2, 3)
-  for (int w = 0; w < 4; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int ti = 0; ti < TM; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < TM; ++tj) {
-          if (SYM && ti > tj) continue;
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) {
-            const int row = ti * 16 + (lane >> 4) + 4 * rr;
-            const int col = tj * 16 + (lane & 15);
-            const double v = acc[ti][tj][rr];
-            red[row * mp + col] = (w == 0) ? v : red[row * mp + col] + v;
-          }
-        }
-    }
-    __syncthreads();
-  }
-  double *out = part + ((long long)(f - f0) * chunks + c) * mp * mp;
-  for (int e = threadIdx.x; e < mp * mp; e += blockDim.x) {
-    const int i = e / mp, j = e % mp;
-    double v = 0.0;
-    if (!SYM || (i / 16) <= (j / 16)) v = red[e];
-    out[e] = v;
-  }
-}
-
 // G = dV sum over chunk partials, element-parallel; for symmetric products the
 // tiles below the diagonal are taken from their mirror.
 __global__ void __launch_bounds__(256) k_gram_reduce2(Geo g, OrbSet o, int f0, int nf, int chunks,
@@ -166,7 +73,7 @@ __global__ void __launch_bounds__(256) k_symmetrize(OrbSet o, int f0, int nf,
 // X column of a tile (m_pad/4 doubles per lane) is fetched in one burst before
 // its MFMA chain.  Y may alias X or Z (each wave reads its points fully first).
 template <int TM, int NT>
-__global__ void __launch_bounds__(256) k_rotate2(Geo g, OrbSet o, int f0, int wpf,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_rotate2(Geo g, OrbSet o, int f0, int wpf,
                                                  const double *__restrict__ M, int trans,
                                                  const double *x, const double *z, double cz,
                                                  double cm, double *y) {
@@ -206,6 +113,7 @@ __global__ void __launch_bounds__(256) k_rotate2(Geo g, OrbSet o, int f0, int wp
       const double *rrow = Rt + (4 * s + kk) * S + jl;
 #pragma unroll
       for (int jt = 0; jt < TM; ++jt) acc[jt] = mfma16x16x4(rrow[jt * 16], bx[s], acc[jt]);
+      if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int jt = 0; jt < TM; ++jt)
@@ -219,6 +127,297 @@ __global__ void __launch_bounds__(256) k_rotate2(Geo g, OrbSet o, int f0, int wp
           y[e] = v;
         }
       }
+  }
+}
+
+// Fused rotation: y = cz z + cm R^T x (and, with RF_TWO, y2 = cm R^T x2 with the
+// same R), with optional per-band reductions of the stored values v over the
+// workgroup's points: RF_DOT_SELF sums v^2, RF_DOT_W sums v * wdot, RF_CORE
+// restricts both to core points.  RF_TRI skips the zero blocks of a
+// lower-triangular R.  Reductions are written as one partial per workgroup:
+// dpart[(f * wpf + wg) * 2 * m_pad + k * m_pad + j], k = 0 (self), 1 (wdot).
+enum { RF_DOT_SELF = 1, RF_DOT_W = 2, RF_CORE = 4, RF_TWO = 8, RF_TRI = 16 };
+
+template <int TM, int NT, int FL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_rot_fused(Geo g, OrbSet o, int f0, int wpf,
+                                                   const double *__restrict__ M, int trans,
+                                                   const double *x, const double *z, double cz,
+                                                   double cm, double *y, const double *x2,
+                                                   double *y2, const double *wdot,
+                                                   double *__restrict__ dpart) {
+  constexpr int MP = 16 * TM;
+  constexpr int S = lds_stride(MP);
+  __shared__ double Rt[MP * S];
+  __shared__ double red[4][2][MP];
+  const int f = f0 + blockIdx.x / wpf;
+  const int wg = blockIdx.x % wpf;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int mf = o.m[f], mp = o.m_pad;
+  const double *Mf = M + (long long)f * mp * mp;
+  for (int e = threadIdx.x; e < MP * MP; e += blockDim.x) {
+    const int i = e / MP, j = e % MP;
+    double v = 0.0;
+    if (i < mf && j < mf) v = trans ? Mf[j * mp + i] : Mf[i * mp + j];
+    Rt[i * S + j] = v;
+  }
+  __syncthreads();
+  const long long base = o.moff[f] * (long long)g.n;
+  const int jl = lane & 15, kk = lane >> 4;
+  double ds[TM][4], dw[TM][4];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) ds[a][b] = dw[a][b] = 0.0;
+  for (int u = 0; u < NT; ++u) {
+    const int p0 = ((wg * 4 + wave) * NT + u) * 16;
+    if (p0 >= g.n) break;
+    const int pc = p0 + jl;
+    const bool pin = pc < g.n;
+    bool core = true;
+    if (FL & RF_CORE) {
+      const int lx = pc % g.nl[0], ly = (pc / g.nl[0]) % g.nl[1], lz = pc / (g.nl[0] * g.nl[1]);
+      core = lx >= g.b[0] && lx < g.b[0] + g.nc[0] && ly >= g.b[1] && ly < g.b[1] + g.nc[1] &&
+             lz >= g.b[2] && lz < g.b[2] + g.nc[2];
+    }
+#pragma unroll
+    for (int arr = 0; arr < ((FL & RF_TWO) ? 2 : 1); ++arr) {
+      const double *xs = arr ? x2 : x;
+      double *ys = arr ? y2 : y;
+      double bx[TM * 4];
+#pragma unroll
+      for (int s = 0; s < TM * 4; ++s) {
+        const int i = 4 * s + kk;
+        bx[s] = (i < mf && pin) ? xs[base + (long long)i * g.n + pc] : 0.0;
+      }
+      dbl4 acc[TM];
+#pragma unroll
+      for (int j = 0; j < TM; ++j) acc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < TM * 4; ++s) {
+        const double *rrow = Rt + (4 * s + kk) * S + jl;
+#pragma unroll
+        for (int jt = 0; jt < TM; ++jt) {
+          if ((FL & RF_TRI) && s > 4 * jt + 3) continue;
+          acc[jt] = mfma16x16x4(rrow[jt * 16], bx[s], acc[jt]);
+        }
+        // keep the operand reads of later steps from being hoisted (register pressure)
+        if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int jt = 0; jt < TM; ++jt)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int j = jt * 16 + kk + 4 * rr;
+          if (j < mf && pin) {
+            const long long e = base + (long long)j * g.n + pc;
+            double v = cm * acc[jt][rr];
+            if (!arr && z) v += cz * z[e];
+            ys[e] = v;
+            if (!arr && core) {
+              if (FL & RF_DOT_SELF) ds[jt][rr] += v * v;
+              if (FL & RF_DOT_W) dw[jt][rr] += v * wdot[e];
+            }
+          }
+        }
+    }
+  }
+  if (FL & (RF_DOT_SELF | RF_DOT_W)) {
+    // sum over the 16 lanes that share a row, then over the 4 waves in LDS
+#pragma unroll
+    for (int jt = 0; jt < TM; ++jt)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+          ds[jt][rr] += __shfl_xor(ds[jt][rr], off, 64);
+          dw[jt][rr] += __shfl_xor(dw[jt][rr], off, 64);
+        }
+    if (jl == 0) {
+#pragma unroll
+      for (int jt = 0; jt < TM; ++jt)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          red[wave][0][jt * 16 + kk + 4 * rr] = ds[jt][rr];
+          red[wave][1][jt * 16 + kk + 4 * rr] = dw[jt][rr];
+        }
+    }
+    __syncthreads();
+    double *out = dpart + ((long long)f * wpf + wg) * 2 * mp;
+    for (int e = threadIdx.x; e < 2 * MP; e += blockDim.x) {
+      const int k = e / MP, j = e % MP;
+      out[k * mp + j] = red[0][k][j] + red[1][k][j] + red[2][k][j] + red[3][k][j];
+    }
+  }
+}
+
+// out_k[B] = dV sum over the workgroup partials of band B (k = 0, 1; null skips).
+__global__ void __launch_bounds__(256) k_band_reduce(Geo g, OrbSet o, long long b0, long long nb,
+                                                     int wpf, const double *__restrict__ dpart,
+                                                     double *__restrict__ out0,
+                                                     double *__restrict__ out1) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nb) return;
+  const long long B = b0 + t;
+  const int f = o.band_frag[B];
+  const int i = (int)(B - o.moff[f]);
+  const int mp = o.m_pad;
+  double s0 = 0.0, s1 = 0.0;
+  for (int wg = 0; wg < wpf; ++wg) {
+    const double *pp = dpart + ((long long)f * wpf + wg) * 2 * mp;
+    s0 += pp[i];
+    s1 += pp[mp + i];
+  }
+  if (out0) out0[B] = g.dv * s0;
+  if (out1) out1[B] = g.dv * s1;
+}
+
+// Gram products, version 3.  Workgroup = (fragment, chunk of points).  Per step of
+// KT = 32 points the workgroup loads the operand rows cooperatively (16-byte
+// loads, one 32-byte run per thread and item) into LDS at a row stride of
+// KT + 2 doubles (the 16x4 MFMA operand reads are then bank-conflict free), and
+// each wave accumulates its share of the output tiles.  The second operand can
+// be built during the load:
+//   GM_PLAIN:  Y given (SYM when X == Y: upper tiles only, one operand).
+//   GM_DIR:    Y = P = beta P_prev - G, written over P_prev.
+//   GM_UPDATE: X = Psi' = c Psi + s P and W' = c W + s Q, both written in place;
+//              symmetric product of Psi'.
+enum { GM_PLAIN = 0, GM_DIR = 1, GM_UPDATE = 2 };
+constexpr int kGramKT = 32;
+constexpr int kGramLd = kGramKT + 2;
+
+template <int TM, int MODE, bool SYM, bool VEC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, double *x, double *a1, const double *a2,
+        double *a3, const double *a4, const double *__restrict__ c1,
+        const double *__restrict__ c2, double *__restrict__ part) {
+  constexpr int MP = 16 * TM;
+  constexpr int NTILE = SYM ? TM * (TM + 1) / 2 : TM * TM;
+  constexpr int PER_WAVE = (NTILE + 3) / 4;
+  __shared__ double Xs[MP * kGramLd];
+  __shared__ double Ys[SYM ? 1 : MP * kGramLd];
+  const int f = f0 + blockIdx.x / chunks;
+  const int c = blockIdx.x % chunks;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int mf = o.m[f];
+  const int mp = o.m_pad;
+  const long long base = o.moff[f] * (long long)g.n;
+  const int p_begin = c * kchunk;
+  const int p_end = min(p_begin + kchunk, g.n);
+  // tiles owned by this wave
+  int tI[PER_WAVE], tJ[PER_WAVE];
+  {
+    int k = 0, q = 0;
+#pragma unroll
+    for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < TM; ++tj) {
+        if (SYM && ti > tj) continue;
+        if (q % 4 == wave && k < PER_WAVE) {
+          tI[k] = ti;
+          tJ[k] = tj;
+          ++k;
+        }
+        ++q;
+      }
+#pragma unroll
+    for (; k < PER_WAVE; ++k) {
+      tI[k] = -1;
+      tJ[k] = -1;
+    }
+  }
+  dbl4 acc[PER_WAVE];
+#pragma unroll
+  for (int k = 0; k < PER_WAVE; ++k) acc[k] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const double *Yl = SYM ? Xs : Ys;
+  for (int p0 = p_begin; p0 < p_end; p0 += kGramKT) {
+    __syncthreads();
+    for (int it = threadIdx.x; it < MP * (kGramKT / 4); it += blockDim.x) {
+      const int row = it / (kGramKT / 4);
+      const int pq = (it % (kGramKT / 4)) * 4;
+      const int p = p0 + pq;
+      double xv[4] = {0, 0, 0, 0}, yv[4] = {0, 0, 0, 0};
+      if (row < mf) {
+        const long long ro = base + (long long)row * g.n;
+        const bool full = VEC && (p + 3 < p_end);
+        double v1[4], v2[4], v3[4], v4[4];
+#define DCDFT_LOAD4(dst, src)                                                         \
+  if (full) {                                                                         \
+    const double2 t0 = *reinterpret_cast<const double2 *>((src) + ro + p);           \
+    const double2 t1 = *reinterpret_cast<const double2 *>((src) + ro + p + 2);       \
+    dst[0] = t0.x; dst[1] = t0.y; dst[2] = t1.x; dst[3] = t1.y;                       \
+  } else {                                                                            \
+    for (int t = 0; t < 4; ++t) dst[t] = (p + t < p_end) ? (src)[ro + p + t] : 0.0;   \
+  }
+#define DCDFT_STORE4(dstp, val)                                                       \
+  if (full) {                                                                         \
+    *reinterpret_cast<double2 *>((dstp) + ro + p) = double2{val[0], val[1]};          \
+    *reinterpret_cast<double2 *>((dstp) + ro + p + 2) = double2{val[2], val[3]};      \
+  } else {                                                                            \
+    for (int t = 0; t < 4; ++t)                                                       \
+      if (p + t < p_end) (dstp)[ro + p + t] = val[t];                                 \
+  }
+        if (MODE == GM_PLAIN) {
+          DCDFT_LOAD4(xv, x);
+          if (!SYM) { DCDFT_LOAD4(yv, a1); }
+        } else if (MODE == GM_DIR) {
+          DCDFT_LOAD4(xv, x);
+          DCDFT_LOAD4(v2, a2);
+          const double b = c1[o.moff[f] + row];
+          if (b != 0.0) {
+            DCDFT_LOAD4(v1, a1);
+            for (int t = 0; t < 4; ++t) yv[t] = b * v1[t] - v2[t];
+          } else {
+            for (int t = 0; t < 4; ++t) yv[t] = -v2[t];
+          }
+          DCDFT_STORE4(a1, yv);
+        } else {
+          DCDFT_LOAD4(v1, x);
+          DCDFT_LOAD4(v2, a1);
+          DCDFT_LOAD4(v3, a3);
+          DCDFT_LOAD4(v4, a4);
+          const double cs = c1[o.moff[f] + row], sn = c2[o.moff[f] + row];
+          for (int t = 0; t < 4; ++t) {
+            xv[t] = cs * v1[t] + sn * v2[t];
+            v3[t] = cs * v3[t] + sn * v4[t];
+          }
+          DCDFT_STORE4(x, xv);
+          DCDFT_STORE4(a3, v3);
+        }
+#undef DCDFT_LOAD4
+#undef DCDFT_STORE4
+        for (int t = 0; t < 4; ++t)
+          if (p + t >= p_end) xv[t] = yv[t] = 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        Xs[row * kGramLd + pq + t] = xv[t];
+        if (!SYM) Ys[row * kGramLd + pq + t] = yv[t];
+      }
+    }
+    __syncthreads();
+    const int r = lane & 15, kk = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < kGramKT / 4; ++t) {
+#pragma unroll
+      for (int k = 0; k < PER_WAVE; ++k) {
+        if (tI[k] < 0) continue;
+        const double av = Xs[(tI[k] * 16 + r) * kGramLd + 4 * t + kk];
+        const double bv = Yl[(tJ[k] * 16 + r) * kGramLd + 4 * t + kk];
+        acc[k] = mfma16x16x4(av, bv, acc[k]);
+      }
+      if ((t & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  double *out = part + ((long long)(f - f0) * chunks + c) * mp * mp;
+#pragma unroll
+  for (int k = 0; k < PER_WAVE; ++k) {
+    if (tI[k] < 0) continue;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int row = tI[k] * 16 + (lane >> 4) + 4 * rr;
+      const int col = tJ[k] * 16 + (lane & 15);
+      out[row * mp + col] = acc[k][rr];
+    }
   }
 }
 
@@ -423,12 +622,13 @@ __global__ void __launch_bounds__(256) k_syev(OrbSet o, int f0, const double *__
 }
 
 __global__ void k_cg_beta(long long b0, long long nb, int first, const double *__restrict__ gamma,
-                          const double *__restrict__ gamma_prev, double *__restrict__ beta) {
+                          double *__restrict__ gamma_prev, double *__restrict__ beta) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
   const long long B = b0 + i;
   const double gp = gamma_prev[B];
   beta[B] = (first || !(gp > 0.0)) ? 0.0 : gamma[B] / gp;
+  gamma_prev[B] = gamma[B];
 }
 
 __global__ void k_cg_norm(long long b0, long long nb, const double *__restrict__ nu,
@@ -440,18 +640,38 @@ __global__ void k_cg_norm(long long b0, long long nb, const double *__restrict__
   inv[B] = (v > 1e-300) ? 1.0 / sqrt(v) : 0.0;
 }
 
-// theta = atan2(-2b, c - a) / 2 with b, c taken for the normalised direction
+// theta = atan2(-2b, c - a) / 2 for the normalised direction p_hat = inv p:
+// b = inv <p, w>, c = inv^2 <p, H p>; returns cos(theta) and inv sin(theta).
 __global__ void k_cg_theta(long long b0, long long nb, const double *__restrict__ a,
-                           const double *__restrict__ b, const double *__restrict__ c,
+                           const double *__restrict__ bp, const double *__restrict__ cp,
                            const double *__restrict__ inv, double *__restrict__ cs,
                            double *__restrict__ sn) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
   const long long B = b0 + i;
+  const double iv = inv[B];
   double th = 0.0;
-  if (inv[B] != 0.0) th = 0.5 * atan2(-2.0 * b[B], c[B] - a[B]);
+  if (iv != 0.0) th = 0.5 * atan2(-2.0 * iv * bp[B], iv * iv * cp[B] - a[B]);
   cs[B] = cos(th);
-  sn[B] = sin(th);
+  sn[B] = iv * sin(th);
+}
+
+// c'[B] += sum_a E_a C[f][a][i]^2 (the projector part of <p, H p>)
+__global__ void k_kb_quad(long long b0, long long nb, const int *__restrict__ band_frag,
+                          const long long *__restrict__ moff, const int *__restrict__ A,
+                          int A_max, int m_pad, const double *__restrict__ E,
+                          const double *__restrict__ C, double *__restrict__ cp) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nb) return;
+  const long long B = b0 + t;
+  const int f = band_frag[B];
+  const int i = (int)(B - moff[f]);
+  double s = 0.0;
+  for (int a = 0; a < A[f]; ++a) {
+    const double v = C[((long long)f * A_max + a) * m_pad + i];
+    s += E[(long long)f * A_max + a] * v * v;
+  }
+  cp[B] += s;
 }
 
 __global__ void k_copy(long long b0, long long nb, const double *__restrict__ src,
@@ -461,24 +681,32 @@ __global__ void k_copy(long long b0, long long nb, const double *__restrict__ sr
   dst[b0 + i] = src[b0 + i];
 }
 
-template <int TM>
-void gram_t(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int kchunk,
-            const double *x, const double *y, double *part, hipStream_t s) {
-  const bool sym = (x == y);
-  const bool vec = (g.n % 4) == 0;
+template <int TM, int MODE, bool SYM>
+void gram3_t(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int kchunk, double *x,
+             double *a1, const double *a2, double *a3, const double *a4, const double *c1,
+             const double *c2, double *part, hipStream_t s) {
   const dim3 grid((f1 - f0) * chunks), block(256);
-  if (sym && vec)
-    hipLaunchKernelGGL((k_gram2<TM, true, true>), grid, block, 0, s, g, o, f0, chunks, kchunk, x,
-                       y, part);
-  else if (sym)
-    hipLaunchKernelGGL((k_gram2<TM, true, false>), grid, block, 0, s, g, o, f0, chunks, kchunk, x,
-                       y, part);
-  else if (vec)
-    hipLaunchKernelGGL((k_gram2<TM, false, true>), grid, block, 0, s, g, o, f0, chunks, kchunk, x,
-                       y, part);
+  if ((g.n % 4) == 0)
+    hipLaunchKernelGGL((k_gram3<TM, MODE, SYM, true>), grid, block, 0, s, g, o, f0, chunks, kchunk,
+                       x, a1, a2, a3, a4, c1, c2, part);
   else
-    hipLaunchKernelGGL((k_gram2<TM, false, false>), grid, block, 0, s, g, o, f0, chunks, kchunk,
-                       x, y, part);
+    hipLaunchKernelGGL((k_gram3<TM, MODE, SYM, false>), grid, block, 0, s, g, o, f0, chunks,
+                       kchunk, x, a1, a2, a3, a4, c1, c2, part);
+}
+
+template <int MODE, bool SYM>
+void gram3_tm(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, double *x, double *a1,
+              const double *a2, double *a3, const double *a4, const double *c1, const double *c2,
+              double *part, hipStream_t s) {
+  int kc = (g.n + chunks - 1) / chunks;
+  kc = ((kc + kGramKT - 1) / kGramKT) * kGramKT;
+  switch (o.tiles) {
+    case 1: gram3_t<1, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
+    case 2: gram3_t<2, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
+    case 3: gram3_t<3, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
+    case 4: gram3_t<4, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
+    default: gram3_t<5, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
+  }
 }
 
 constexpr int kRotTiles = 4;   // 16-point tiles per wave in k_rotate2
@@ -494,22 +722,16 @@ void rotate_t(const Geo &g, const OrbSet &o, int f0, int f1, const double *M, in
 
 }  // namespace
 
-int gram_kchunk(const Geo &g, int chunks) {
-  int k = (g.n + chunks - 1) / chunks;
-  return ((k + 63) / 64) * 64;
-}
-
 void launch_gram(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, const double *x,
                  const double *y, double *part, hipStream_t s) {
   if (f1 <= f0) return;
-  const int kc = gram_kchunk(g, chunks);
-  switch (o.tiles) {
-    case 1: gram_t<1>(g, o, f0, f1, chunks, kc, x, y, part, s); break;
-    case 2: gram_t<2>(g, o, f0, f1, chunks, kc, x, y, part, s); break;
-    case 3: gram_t<3>(g, o, f0, f1, chunks, kc, x, y, part, s); break;
-    case 4: gram_t<4>(g, o, f0, f1, chunks, kc, x, y, part, s); break;
-    default: gram_t<5>(g, o, f0, f1, chunks, kc, x, y, part, s); break;
-  }
+  double *xx = const_cast<double *>(x), *yy = const_cast<double *>(y);
+  if (x == y)
+    gram3_tm<GM_PLAIN, true>(g, o, f0, f1, chunks, xx, xx, nullptr, nullptr, nullptr, nullptr,
+                             nullptr, part, s);
+  else
+    gram3_tm<GM_PLAIN, false>(g, o, f0, f1, chunks, xx, yy, nullptr, nullptr, nullptr, nullptr,
+                              nullptr, part, s);
 }
 
 void launch_gram_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int sym,
@@ -548,7 +770,7 @@ void launch_syev(const OrbSet &o, int f0, int f1, const double *Hs, double *U, d
 }
 
 void launch_cg_beta(const OrbSet &o, int f0, int f1, int first, const double *gamma,
-                    const double *gamma_prev, double *beta, hipStream_t s) {
+                    double *gamma_prev, double *beta, hipStream_t s) {
   const long long nb = o.nb(f0, f1);
   if (nb <= 0) return;
   hipLaunchKernelGGL(k_cg_beta, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, o.b0(f0), nb,
@@ -577,6 +799,103 @@ void launch_copy_band(const OrbSet &o, int f0, int f1, const double *src, double
   if (nb <= 0) return;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, o.b0(f0), nb,
                      src, dst);
+}
+
+
+namespace {
+template <int TM, int FL>
+void rot_fused_t(const Geo &g, const OrbSet &o, int f0, int f1, int wpf, const double *M,
+                 int trans, const double *x, const double *z, double cz, double cm, double *y,
+                 const double *x2, double *y2, const double *wdot, double *dpart, hipStream_t s) {
+  hipLaunchKernelGGL((k_rot_fused<TM, kRotTiles, FL>), dim3((f1 - f0) * wpf), dim3(256), 0, s, g,
+                     o, f0, wpf, M, trans, x, z, cz, cm, y, x2, y2, wdot, dpart);
+}
+
+template <int FL>
+void rot_fused_tm(const Geo &g, const OrbSet &o, int f0, int f1, int wpf, const double *M,
+                  int trans, const double *x, const double *z, double cz, double cm, double *y,
+                  const double *x2, double *y2, const double *wdot, double *dpart, hipStream_t s) {
+  switch (o.tiles) {
+    case 1: rot_fused_t<1, FL>(g, o, f0, f1, wpf, M, trans, x, z, cz, cm, y, x2, y2, wdot, dpart, s); break;
+    case 2: rot_fused_t<2, FL>(g, o, f0, f1, wpf, M, trans, x, z, cz, cm, y, x2, y2, wdot, dpart, s); break;
+    case 3: rot_fused_t<3, FL>(g, o, f0, f1, wpf, M, trans, x, z, cz, cm, y, x2, y2, wdot, dpart, s); break;
+    case 4: rot_fused_t<4, FL>(g, o, f0, f1, wpf, M, trans, x, z, cz, cm, y, x2, y2, wdot, dpart, s); break;
+    default: rot_fused_t<5, FL>(g, o, f0, f1, wpf, M, trans, x, z, cz, cm, y, x2, y2, wdot, dpart, s); break;
+  }
+}
+
+}  // namespace
+
+int rot_wpf(const Geo &g) {
+  const int per_wg = 4 * kRotTiles * 16;
+  return (g.n + per_wg - 1) / per_wg;
+}
+
+void launch_rot_residual(const Geo &g, const OrbSet &o, int f0, int f1, const double *Hs,
+                         const double *psi, const double *w, double *gout, double *dpart,
+                         double *gamma, hipStream_t s) {
+  if (f1 <= f0) return;
+  const int wpf = rot_wpf(g);
+  rot_fused_tm<RF_DOT_SELF>(g, o, f0, f1, wpf, Hs, 0, psi, w, 1.0, -1.0, gout, nullptr, nullptr,
+                            nullptr, dpart, s);
+  const long long nb = o.nb(f0, f1);
+  hipLaunchKernelGGL(k_band_reduce, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, g, o,
+                     o.b0(f0), nb, wpf, dpart, gamma, nullptr);
+}
+
+void launch_rot_project_out(const Geo &g, const OrbSet &o, int f0, int f1, const double *X,
+                            const double *psi, double *p, const double *w, double *dpart,
+                            double *nu, double *pw, hipStream_t s) {
+  if (f1 <= f0) return;
+  const int wpf = rot_wpf(g);
+  rot_fused_tm<RF_DOT_SELF | RF_DOT_W>(g, o, f0, f1, wpf, X, 0, psi, p, 1.0, -1.0, p, nullptr,
+                                       nullptr, w, dpart, s);
+  const long long nb = o.nb(f0, f1);
+  hipLaunchKernelGGL(k_band_reduce, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, g, o,
+                     o.b0(f0), nb, wpf, dpart, nu, pw);
+}
+
+void launch_rot_cholesky(const Geo &g, const OrbSet &o, int f0, int f1, const double *Linv,
+                         double *psi, double *w, hipStream_t s) {
+  if (f1 <= f0) return;
+  const int wpf = rot_wpf(g);
+  rot_fused_tm<RF_TWO | RF_TRI>(g, o, f0, f1, wpf, Linv, 1, psi, nullptr, 0.0, 1.0, psi, w, w,
+                                nullptr, nullptr, s);
+}
+
+void launch_rot_ritz(const Geo &g, const OrbSet &o, int f0, int f1, const double *U, double *psi,
+                     double *dpart, double *wcore, hipStream_t s) {
+  if (f1 <= f0) return;
+  const int wpf = rot_wpf(g);
+  rot_fused_tm<RF_DOT_SELF | RF_CORE>(g, o, f0, f1, wpf, U, 0, psi, nullptr, 0.0, 1.0, psi,
+                                      nullptr, nullptr, nullptr, dpart, s);
+  const long long nb = o.nb(f0, f1);
+  hipLaunchKernelGGL(k_band_reduce, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, g, o,
+                     o.b0(f0), nb, wpf, dpart, wcore, nullptr);
+}
+
+void launch_gram_direction(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
+                           const double *psi, const double *gres, double *p, const double *beta,
+                           double *part, hipStream_t s) {
+  if (f1 <= f0) return;
+  gram3_tm<GM_DIR, false>(g, o, f0, f1, chunks, const_cast<double *>(psi), p, gres, nullptr,
+                          nullptr, beta, nullptr, part, s);
+}
+
+void launch_gram_update(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, double *psi,
+                        const double *p, double *w, const double *q, const double *cs,
+                        const double *sn, double *part, hipStream_t s) {
+  if (f1 <= f0) return;
+  gram3_tm<GM_UPDATE, true>(g, o, f0, f1, chunks, psi, const_cast<double *>(p), nullptr, w, q, cs,
+                            sn, part, s);
+}
+
+void launch_kb_quad(const OrbSet &o, int f0, int f1, const KBTables &kb, const double *C,
+                    double *cp, hipStream_t s) {
+  const long long nb = o.nb(f0, f1);
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_kb_quad, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, o.b0(f0), nb,
+                     o.band_frag, o.moff, kb.A, kb.A_max, o.m_pad, kb.E, C, cp);
 }
 
 }  // namespace dcdft
