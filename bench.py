@@ -69,6 +69,9 @@ def main() -> int:
     ap.add_argument("--config", type=int, default=2, help="workload number (default 2)")
     ap.add_argument("--batched", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=float, default=0.0,
+                    help="run one plain device-to-device copy of this many MB first (a "
+                         "reference kernel for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -80,6 +83,16 @@ def main() -> int:
         return 1
     from paper_2606_21125_amd import (DCDFT, KERNEL_GRAM, KERNEL_HLOC, KERNEL_ROTATE)
 
+    if args.copy_probe_mb > 0:
+        n = int(args.copy_probe_mb * 1e6) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy probe: {n * 8} bytes read, {n * 8} bytes written",
+              file=sys.stderr, flush=True)
+        del src, dst
     cfg = workload_config(args.config)
     print(f"[bench] setup {cfg.name}: {cfg.system.n_atoms} atoms, grid {cfg.n_grid}, "
           f"{cfg.n_fragments} fragments of {cfg.fragment_shape}", file=sys.stderr, flush=True)

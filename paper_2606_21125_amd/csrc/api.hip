@@ -680,6 +680,13 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   }
   g.n = g.nl[0] * g.nl[1] * g.nl[2];
   g.dv = g.h[0] * g.h[1] * g.h[2];
+  {
+    const double ih[3] = {1.0 / (g.h[0] * g.h[0]), 1.0 / (g.h[1] * g.h[1]),
+                          1.0 / (g.h[2] * g.h[2])};
+    g.kc[0] = -0.5 * kFDh[0] * (ih[0] + ih[1] + ih[2]);
+    for (int d = 0; d < 3; ++d)
+      for (int k = 1; k <= 4; ++k) g.kc[1 + 4 * d + (k - 1)] = -0.5 * kFDh[k] * ih[d];
+  }
   c->nF = g.F[0] * g.F[1] * g.F[2];
   c->m.resize(c->nF);
   c->moff.assign(c->nF + 1, 0);

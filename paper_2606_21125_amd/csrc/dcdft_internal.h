@@ -37,6 +37,9 @@ struct Geo {
   long long Ng;   // global points
   double h[3];
   double dv;
+  // kinetic stencil coefficients -1/2 c_k / h_d^2: [0] centre (all axes), then
+  // x k=1..4, y k=1..4, z k=1..4 (set once at setup, uniform in every kernel)
+  double kc[13];
 };
 
 struct OrbSet {           // flattened orbital layout [M_tot][n]

@@ -8,10 +8,6 @@ namespace dcdft {
 
 namespace {
 
-// Central second-derivative weights of the nine-point stencil (half-width 4):
-// c0 = -205/72, c1 = 8/5, c2 = -1/5, c3 = 8/315, c4 = -1/560 (Fornberg 1988).
-__constant__ double kFD[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
-
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -49,16 +45,11 @@ __global__ void __launch_bounds__(1024) k_hloc(Geo g, const int *__restrict__ ba
   const double *xb = x + B * (long long)g.n;
   double *yb = y + B * (long long)g.n;
   const double *vb = veff + (long long)f * g.n;
-  const double ihx = 1.0 / (g.h[0] * g.h[0]), ihy = 1.0 / (g.h[1] * g.h[1]),
-               ihz = 1.0 / (g.h[2] * g.h[2]);
-  const double c0 = -0.5 * kFD[0] * (ihx + ihy + ihz);
-  double ax[4], ay[4], az[4];
+  const double c0 = g.kc[0];
+  const double *ax = g.kc + 1, *ay = g.kc + 5, *az = g.kc + 9;
   int ox[8], oy[8];
 #pragma unroll
   for (int k = 1; k <= 4; ++k) {
-    ax[k - 1] = -0.5 * kFD[k] * ihx;
-    ay[k - 1] = -0.5 * kFD[k] * ihy;
-    az[k - 1] = -0.5 * kFD[k] * ihz;
     ox[2 * (k - 1)] = ((ix + k) % nx) + iy * nx;
     ox[2 * (k - 1) + 1] = ((ix - k) % nx + nx) % nx + iy * nx;
     oy[2 * (k - 1)] = ix + ((iy + k) % ny) * nx;
@@ -70,6 +61,8 @@ __global__ void __launch_bounds__(1024) k_hloc(Geo g, const int *__restrict__ ba
     const int zz = ((k - 4) % nz + nz) % nz;
     win[k] = xb[(long long)zz * plane + t];
   }
+  // V_eff two planes ahead of use, so its load latency overlaps the stencil
+  double v0 = vb[t], v1 = (nz > 1) ? vb[plane + t] : 0.0;
   for (int z = 0; z < nz; ++z) {
     double *pl = lds + (z & 1) * plane;
     pl[t] = win[4];
@@ -82,9 +75,11 @@ __global__ void __launch_bounds__(1024) k_hloc(Geo g, const int *__restrict__ ba
       acc += az[k] * (win[5 + k] + win[3 - k]);
     }
     const long long e = (long long)z * plane + t;
-    acc += vb[e] * win[4];
+    acc += v0 * win[4];
     yb[e] = acc;
     dacc += win[4] * acc;
+    v0 = v1;
+    if (z + 2 < nz) v1 = vb[e + 2 * plane];
 #pragma unroll
     for (int k = 0; k < 8; ++k) win[k] = win[k + 1];
     const int zn = (z + 5) % nz;
@@ -187,7 +182,7 @@ __global__ void __launch_bounds__(256) k_kb_reduce(Geo g, OrbSet o, KBTables kb,
 // products of (E C)^T (orbitals x slots, staged in LDS) with the dense region
 // block (slots x points); wave w takes the 16-point tiles w, w + 4, ...
 template <int TM, int KT>
-__global__ void __launch_bounds__(256) k_kb_apply2(Geo g, OrbSet o, KBTables kb, int f0,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_kb_apply2(Geo g, OrbSet o, KBTables kb, int f0,
                                                    const double *__restrict__ C,
                                                    double *__restrict__ y) {
   constexpr int MP = 16 * TM;
@@ -221,6 +216,7 @@ __global__ void __launch_bounds__(256) k_kb_apply2(Geo g, OrbSet o, KBTables kb,
 #pragma unroll
       for (int jt = 0; jt < TM; ++jt)
         acc[jt] = mfma16x16x4(ec[(4 * st + kk) * LD + jt * 16 + c], bv, acc[jt]);
+      if ((st & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
     if (p < g.n) {
 #pragma unroll

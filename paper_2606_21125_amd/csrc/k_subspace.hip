@@ -489,14 +489,14 @@ __device__ inline void rr_pair(int mm, int r, int k, int &p, int &q) {
 }
 
 // Parallel cyclic Jacobi: each round rotates mm/2 disjoint (p, q) planes at once.
-__global__ void __launch_bounds__(256) k_syev(OrbSet o, int f0, const double *__restrict__ H,
+__global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *__restrict__ H,
                                               double *__restrict__ U, double *__restrict__ eps,
                                               int *flags) {
   __shared__ double A[kMaxOrb * (kMaxOrb + 1)];
   __shared__ double V[kMaxOrb * (kMaxOrb + 1)];
   __shared__ double cs[kMaxOrb / 2 + 1], sn[kMaxOrb / 2 + 1];
   __shared__ int pp[kMaxOrb / 2 + 1], qq[kMaxOrb / 2 + 1];
-  __shared__ double red[16];
+  __shared__ double red[32];
   __shared__ int rank_of[kMaxOrb];
   const int f = f0 + blockIdx.x;
   const int mf = o.m[f], mp = o.m_pad;
@@ -510,6 +510,7 @@ __global__ void __launch_bounds__(256) k_syev(OrbSet o, int f0, const double *__
   const int mm = (mf % 2) ? mf + 1 : mf;   // an odd size gets one idle index
   const int npair = mm / 2;
   bool converged = (mf <= 1);
+  double prev_off = 1e300;
   for (int sweep = 0; sweep < 60 && !converged; ++sweep) {
     __syncthreads();
     // convergence: max |off-diagonal| against the largest diagonal magnitude
@@ -527,18 +528,21 @@ __global__ void __launch_bounds__(256) k_syev(OrbSet o, int f0, const double *__
     __syncthreads();
     if ((threadIdx.x & 63) == 0) {
       red[threadIdx.x >> 6] = off;
-      red[8 + (threadIdx.x >> 6)] = dia;
+      red[16 + (threadIdx.x >> 6)] = dia;
     }
     __syncthreads();
     double offm = 0.0, diam = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
       offm = fmax(offm, red[w]);
-      diam = fmax(diam, red[8 + w]);
+      diam = fmax(diam, red[16 + w]);
     }
-    if (offm <= 1e-14 * diam || offm == 0.0) {
+    // converged at 1e-13 of the largest diagonal entry, or at the rounding floor
+    // (no further halving once below 1e-11 of it)
+    if (offm <= 1e-13 * diam || offm == 0.0 || (offm < 1e-11 * diam && offm > 0.5 * prev_off)) {
       converged = true;
       break;
     }
+    prev_off = offm;
     for (int r = 0; r < mm - 1; ++r) {
       __syncthreads();
       for (int k = threadIdx.x; k < npair; k += blockDim.x) {
@@ -766,7 +770,7 @@ void launch_cholinv(const OrbSet &o, int f0, int f1, const double *S, double *Li
 void launch_syev(const OrbSet &o, int f0, int f1, const double *Hs, double *U, double *eps,
                  int *flags, hipStream_t s) {
   if (f1 <= f0) return;
-  hipLaunchKernelGGL(k_syev, dim3(f1 - f0), dim3(256), 0, s, o, f0, Hs, U, eps, flags);
+  hipLaunchKernelGGL(k_syev, dim3(f1 - f0), dim3(1024), 0, s, o, f0, Hs, U, eps, flags);
 }
 
 void launch_cg_beta(const OrbSet &o, int f0, int f1, int first, const double *gamma,
