@@ -69,6 +69,8 @@ def main() -> int:
     ap.add_argument("--config", type=int, default=2, help="workload number (default 2)")
     ap.add_argument("--batched", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the plain per-fragment FP64 comparison run")
     ap.add_argument("--copy-probe-mb", type=float, default=0.0,
                     help="run one plain device-to-device copy of this many MB first (a "
                          "reference kernel for scaling HBM counters)")
@@ -100,16 +102,22 @@ def main() -> int:
     for _ in range(args.warmup):
         d.dcdft_scf_step()
     torch.cuda.synchronize()
-    d.dcdft_kernel_timing(True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     info = None
     for _ in range(args.steps):
         info = d.dcdft_scf_step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # per-kernel device times: the same steps run eagerly with every launch of the
+    # stencil, Gram and rotation families bracketed by HIP events on the
+    # library's stream (event records cannot be captured into the step graph)
+    d.dcdft_kernel_timing(True)
+    n_timed = max(2, min(args.steps, 4))
+    for _ in range(n_timed):
+        d.dcdft_scf_step()
     kt = {name: d.dcdft_kernel_time(k) for name, k in
           (("hloc", KERNEL_HLOC), ("gram", KERNEL_GRAM), ("rotate", KERNEL_ROTATE))}
+    d.dcdft_kernel_timing(False)
     d.close()
     elapsed = t1 - t0
     ms_per_step = 1000.0 * elapsed / args.steps
@@ -125,7 +133,9 @@ def main() -> int:
                 "frac": round(h_gbs / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": "k_hloc (fragment H_loc psi, FP64)",
                 "avg_launch_ms": round(h["ms"] / max(1, h["launches"]), 4),
-                "bytes_per_launch": h["bytes"] / max(1, h["launches"])}
+                "bytes_per_launch": h["bytes"] / max(1, h["launches"]),
+                "measured": f"HIP events around every launch over {n_timed} eager steps "
+                            f"following the timed region"}
     extra = {
         "hpsi_gbs": round(h_gbs, 1),
         "gram": {"bound": "mfma", "achieved": round(g_tf, 2), "peak": FP64_MFMA_PEAK_TFLOPS,
@@ -134,9 +144,25 @@ def main() -> int:
         "rotate": {"bound": "hbm", "achieved": round(r_gbs, 1), "peak": HBM_PEAK_GBS,
                    "unit": "GB/s", "frac": round(r_gbs / HBM_PEAK_GBS, 4),
                    "avg_launch_ms": round(r["ms"] / max(1, r["launches"]), 4)},
-        "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in kt.items()},
+        "kernel_ms_per_step": {k: round(v["ms"] / n_timed, 3) for k, v in kt.items()},
         "last_step": {k: info[k] for k in ("mu", "e_total", "residual_out_in", "charge")},
     }
+    # plain FP64 path: one launch sequence per fragment, no graph
+    plain = None
+    if args.batched and not args.no_compare:
+        print("[bench] plain per-fragment FP64 path", file=sys.stderr, flush=True)
+        d2 = DCDFT.from_config(cfg, batched=0)
+        d2.dcdft_scf_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            d2.dcdft_scf_step()
+        torch.cuda.synchronize()
+        t_plain = (time.perf_counter() - t0) / 2
+        d2.close()
+        plain = {"value": round(1.0 / t_plain, 3), "unit": "SCF iter/s",
+                 "ms_per_step": round(1000.0 * t_plain, 3),
+                 "speedup_of_value": round(value * t_plain, 3)}
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
@@ -154,7 +180,7 @@ def main() -> int:
                                 f"{cfg.cg_sweeps} CG sweeps per SCF iteration"),
                    "n_fragments": cfg.n_fragments, "batched": bool(args.batched),
                    "precision": "fp64"},
-        "roofline": roofline, "cpu_baseline": cpu, **extra,
+        "roofline": roofline, "cpu_baseline": cpu, "plain_fp64_per_fragment": plain, **extra,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -185,8 +185,8 @@ dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, cons
                                void *grad_v);
 
 /* Device-time accounting of kernel families (for roofline reports).  While
- * enabled, every launch of the families below is bracketed by HIP events on the
- * context's stream; dcdft_kernel_time returns, since timing was (re-)enabled,
+ * enabled, steps run eagerly (not from the step graph) and every launch of the
+ * families below is bracketed by HIP events on the context's stream; dcdft_kernel_time returns, since timing was (re-)enabled,
  * the number of launches, their summed device milliseconds, and their summed
  * algorithmic HBM bytes and flops (minimum traffic: every operand read once,
  * every result written once; any of the outputs may be NULL).  Enabling resets

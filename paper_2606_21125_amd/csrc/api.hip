@@ -614,6 +614,63 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
 
 }  // namespace
 
+namespace {
+
+// Every kernel of one SCF iteration, in order, on the context's stream.
+void enqueue_step(dcdft_ctx *c) {
+  const Geo &g = c->geo;
+  hipStream_t s = c->stream;
+  OrbSet o = c->orbset(0, c->nF);
+  launch_fill_int(c->d_flags, 1, 0, s);
+  // 1. Hartree potential of rho_tot^in
+  launch_poisson(g, c->d_rho_in, c->d_vh, c->d_fft_a, c->d_fft_b, c->d_qf, c->d_qi, c->d_lam, s);
+  // 2. fragment effective potentials
+  launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, s);
+  // 3. fragment eigensolvers
+  if (c->batched) {
+    eigensolver_range(c, 0, c->nF);
+  } else {
+    for (int f = 0; f < c->nF; ++f) eigensolver_range(c, f, f + 1);
+  }
+  // 4. global chemical potential
+  launch_fermi(o, c->d_eps, c->d_wcore, c->ne, c->smearing, c->d_occ, c->d_scal, c->d_flags, s);
+  // 5. densities
+  launch_density(g, o, 0, c->nF, c->d_psi, c->d_occ, c->d_rhof_out, c->d_rho_out, s);
+  // 6-8. energy terms, residuals, mixing
+  launch_global_terms(g, c->d_rho_in, c->d_rho_out, c->d_vh, c->mixing, c->d_part, c->n_part,
+                      c->d_scal, s, c->ne, c->smearing);
+  launch_frag_mix(g, c->nF, c->d_rhof_in, c->d_rhof_out, c->mixing, s);
+  launch_nan_check(c->d_eps, c->M_tot, c->d_flags, s);
+  launch_nan_check(c->d_rho_out, g.Ng, c->d_flags, s);
+}
+
+void drop_graph(dcdft_ctx *c) {
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+  for (auto &t : c->graph_timers) {
+    c->event_pool.push_back(t.a);
+    c->event_pool.push_back(t.b);
+  }
+  c->graph_timers.clear();
+}
+
+// Accumulate the event pairs recorded inside the graph (they persist across replays).
+void read_graph_timers(dcdft_ctx *c) {
+  for (auto &t : c->graph_timers) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      c->k_launches[t.kind] += 1;
+      c->k_ms[t.kind] += ms;
+      c->k_bytes[t.kind] += t.bytes;
+      c->k_flops[t.kind] += t.flops;
+    }
+  }
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *dcdft_status_string(dcdft_status s) {
@@ -653,6 +710,7 @@ void dcdft_destroy(dcdft_ctx *c) {
     hipEventDestroy(t.b);
   }
   for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
+  drop_graph(c);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -823,31 +881,32 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
 
 dcdft_status dcdft_scf_step(dcdft_ctx *c, dcdft_scf_info *info) {
   if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
-  const Geo &g = c->geo;
   hipStream_t s = c->stream;
-  OrbSet o = c->orbset(0, c->nF);
-  HIPTRY(c, hipEventRecord(c->ev0, s));
-  launch_fill_int(c->d_flags, 1, 0, s);
-  // 1. Hartree potential of rho_tot^in
-  launch_poisson(g, c->d_rho_in, c->d_vh, c->d_fft_a, c->d_fft_b, c->d_qf, c->d_qi, c->d_lam, s);
-  // 2. fragment effective potentials
-  launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, s);
-  // 3. fragment eigensolvers
-  if (c->batched) {
-    eigensolver_range(c, 0, c->nF);
-  } else {
-    for (int f = 0; f < c->nF; ++f) eigensolver_range(c, f, f + 1);
+  // Timed steps run eagerly: event records are not captured into the graph.
+  const bool graph = c->batched && c->use_graph && !c->timing;
+  if (graph && !c->graph_exec) {
+    drain_timers(c);
+    HIPTRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    enqueue_step(c);
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &gr);
+    c->graph_timers.swap(c->pending);
+    c->pending.clear();
+    c->graph_timed = c->timing;
+    if (e != hipSuccess) return set_err(c, DCDFT_ERR_HIP, fmt("graph capture: %s", hipGetErrorString(e)));
+    c->graph = gr;
+    e = hipGraphInstantiate(&c->graph_exec, gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      drop_graph(c);
+      return set_err(c, DCDFT_ERR_HIP, fmt("graph instantiation: %s", hipGetErrorString(e)));
+    }
   }
-  // 4. global chemical potential
-  launch_fermi(o, c->d_eps, c->d_wcore, c->ne, c->smearing, c->d_occ, c->d_scal, c->d_flags, s);
-  // 5. densities
-  launch_density(g, o, 0, c->nF, c->d_psi, c->d_occ, c->d_rhof_out, c->d_rho_out, s);
-  // 6-8. energy terms, residuals, mixing
-  launch_global_terms(g, c->d_rho_in, c->d_rho_out, c->d_vh, c->mixing, c->d_part, c->n_part,
-                      c->d_scal, s, c->ne, c->smearing);
-  launch_frag_mix(g, c->nF, c->d_rhof_in, c->d_rhof_out, c->mixing, s);
-  launch_nan_check(c->d_eps, c->M_tot, c->d_flags, s);
-  launch_nan_check(c->d_rho_out, g.Ng, c->d_flags, s);
+  HIPTRY(c, hipEventRecord(c->ev0, s));
+  if (graph) {
+    HIPTRY(c, hipGraphLaunch(c->graph_exec, s));
+  } else {
+    enqueue_step(c);
+  }
   HIPTRY(c, hipGetLastError());
   HIPTRY(c, hipEventRecord(c->ev1, s));
   HIPTRY(c, hipMemcpyAsync(c->d_info_host, c->d_scal, SC_COUNT * sizeof(double),
@@ -855,7 +914,8 @@ dcdft_status dcdft_scf_step(dcdft_ctx *c, dcdft_scf_info *info) {
   int flags = 0;
   HIPTRY(c, hipMemcpyAsync(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPTRY(c, hipStreamSynchronize(s));
-  drain_timers(c);
+  if (graph) read_graph_timers(c);
+  else drain_timers(c);
   c->iter++;
   const double *sc = c->d_info_host;
   if (info) {

@@ -159,6 +159,7 @@ struct dcdft_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string last_error;
 
+
   // kernel-family timing (dcdft_kernel_timing)
   struct PendingTimer {
     hipEvent_t a, b;
@@ -170,6 +171,13 @@ struct dcdft_ctx {
   std::vector<hipEvent_t> event_pool;
   long long k_launches[3] = {0, 0, 0};
   double k_ms[3] = {0, 0, 0}, k_bytes[3] = {0, 0, 0}, k_flops[3] = {0, 0, 0};
+
+  // graph of one batched SCF step (captured on first use, replayed after)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  bool use_graph = true;
+  bool graph_timed = false;
+  std::vector<PendingTimer> graph_timers;
 
   dcdft::OrbSet orbset(int f0, int f1) const;
   dcdft::KBTables kb() const;
