@@ -131,6 +131,7 @@ dcdft::KBTables dcdft_ctx::kb() const {
   k.KS = KS;
   k.reg_atom = d_reg_atom;
   k.reg_beta = d_reg_beta;
+  k.reg_beta32 = d_reg_beta32;
   k.ar_ptr = d_ar_ptr;
   k.ar_reg = d_ar_reg;
   k.ar_slot = d_ar_slot;
@@ -200,39 +201,34 @@ double sum_m2(const dcdft_ctx *c, int f0, int f1) {
   return s;
 }
 
-void hloc(dcdft_ctx *c, int f0, int f1, const double *x, double *y, double *dot = nullptr) {
-  const double n = c->geo.n;
-  Timed t(c, DCDFT_KERNEL_HLOC, 16.0 * n * orbitals_in(c, f0, f1) + 8.0 * n * (f1 - f0),
+template <typename T>
+void hloc(dcdft_ctx *c, int f0, int f1, const T *x, T *y, double *dot = nullptr) {
+  const double n = c->geo.n, sz = sizeof(T);
+  Timed t(c, DCDFT_KERNEL_HLOC, 2.0 * sz * n * orbitals_in(c, f0, f1) + 8.0 * n * (f1 - f0),
           55.0 * n * orbitals_in(c, f0, f1));
-  launch_hloc(c->geo, c->orbset(f0, f1), f0, f1, c->d_veff, x, y, c->stream, dot);
-}
-
-void rotate(dcdft_ctx *c, int f0, int f1, const double *M, int trans, const double *x,
-            const double *z, double cz, double cm, double *y) {
-  const double n = c->geo.n;
-  Timed t(c, DCDFT_KERNEL_ROTATE, 8.0 * n * orbitals_in(c, f0, f1) * (z ? 3.0 : 2.0),
-          2.0 * n * sum_m2(c, f0, f1));
-  launch_rotate(c->geo, c->orbset(f0, f1), f0, f1, M, trans, x, z, cz, cm, y, c->stream);
+  launch_hloc<T>(c->geo, c->orbset(f0, f1), f0, f1, c->d_veff, x, y, c->stream, dot);
 }
 
 // H X for the orbitals of fragments [f0, f1) in the context layout.
-void apply_h_range(dcdft_ctx *c, int f0, int f1, const double *x, double *y) {
+template <typename T>
+void apply_h_range(dcdft_ctx *c, int f0, int f1, const T *x, T *y) {
   const Geo &g = c->geo;
   OrbSet o = c->orbset(f0, f1);
   KBTables kb = c->kb();
-  hloc(c, f0, f1, x, y);
-  launch_kb_project(g, o, kb, f0, f1, x, c->d_C, c->d_cpart, c->stream);
-  launch_kb_apply(g, o, kb, f0, f1, c->d_C, y, c->stream);
+  hloc<T>(c, f0, f1, x, y);
+  launch_kb_project<T>(g, o, kb, f0, f1, x, c->d_C, c->d_cpart, c->stream);
+  launch_kb_apply<T>(g, o, kb, f0, f1, c->d_C, y, c->stream);
 }
 
-void gram(dcdft_ctx *c, int f0, int f1, const double *x, const double *y, double *G, double *Gs,
+template <typename T>
+void gram(dcdft_ctx *c, int f0, int f1, const T *x, const T *y, double *G, double *Gs,
           double *diag) {
   OrbSet o = c->orbset(f0, f1);
   {
-    const double n = c->geo.n;
-    Timed t(c, DCDFT_KERNEL_GRAM, 8.0 * n * orbitals_in(c, f0, f1) * (x == y ? 1.0 : 2.0),
+    const double n = c->geo.n, sz = sizeof(T);
+    Timed t(c, DCDFT_KERNEL_GRAM, sz * n * orbitals_in(c, f0, f1) * (x == y ? 1.0 : 2.0),
             2.0 * n * sum_m2(c, f0, f1));
-    launch_gram(c->geo, o, f0, f1, c->gram_chunks, x, y, c->d_gpart, c->stream);
+    launch_gram<T>(c->geo, o, f0, f1, c->gram_chunks, x, y, c->d_gpart, c->stream);
   }
   launch_gram_reduce(c->geo, o, f0, f1, c->gram_chunks, x == y, c->d_gpart, G ? G : c->d_gtmp, Gs,
                      diag, c->stream);
@@ -245,73 +241,79 @@ void gram(dcdft_ctx *c, int f0, int f1, const double *x, const double *y, double
 //   Psi <- c Psi + s P / |p|, W <- c W + s Q / |p| with <Psi, Psi>;
 //   Psi, W <- L^-1 (Psi, W).
 // The search direction is kept unnormalised (H is linear, so Q = H P and the
-// normalisation enters only through the scalars of the 2x2 problem).
+// normalisation enters only through the scalars of the 2x2 problem).  T is the
+// storage and matrix-core precision of the orbital arrays; every reduction,
+// the 2x2 problems, Cholesky and the Rayleigh-Ritz eigensolve are FP64.
+template <typename T>
 void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
   const Geo &g = c->geo;
   OrbSet o = c->orbset(f0, f1);
   KBTables kb = c->kb();
   hipStream_t s = c->stream;
-  double *psi = c->d_psi, *w = c->d_w, *p = c->d_p, *q = c->d_q;
-  const double n = g.n;
+  T *psi = (T *)c->d_psi, *w = (T *)c->d_w, *p = (T *)c->d_p, *q = (T *)c->d_q;
+  const double n = g.n, sz = sizeof(T);
   const double nb = orbitals_in(c, f0, f1);
   const double m2 = sum_m2(c, f0, f1);
   const int ch = c->gram_chunks;
-  apply_h_range(c, f0, f1, psi, w);
+  apply_h_range<T>(c, f0, f1, psi, w);
   for (int sw = 0; sw < c->sweeps; ++sw) {
     // (a) Hs = sym(<Psi, W>), a_i = <psi_i, w_i>
-    gram(c, f0, f1, psi, w, c->d_hs_full, c->d_hs, c->d_a);
+    gram<T>(c, f0, f1, psi, w, c->d_hs_full, c->d_hs, c->d_a);
     // (b)-(c) G = W - Hs Psi (kept in q), gamma_i = <g_i, g_i>, Fletcher-Reeves beta
     {
-      Timed t(c, DCDFT_KERNEL_ROTATE, 24.0 * n * nb, 2.0 * n * m2);
-      launch_rot_residual(g, o, f0, f1, c->d_hs, psi, w, q, c->d_dpart, c->d_gamma, s);
+      Timed t(c, DCDFT_KERNEL_ROTATE, 3.0 * sz * n * nb, 2.0 * n * m2);
+      launch_rot_residual<T>(g, o, f0, f1, c->d_hs, psi, w, q, c->d_dpart, c->d_gamma, s);
     }
     launch_cg_beta(o, f0, f1, sw == 0, c->d_gamma, c->d_gamma_prev, c->d_beta, s);
     // (d)-(e) P = -G + beta P_prev, X = <Psi, P>
     {
-      Timed t(c, DCDFT_KERNEL_GRAM, 32.0 * n * nb, 2.0 * n * m2);
-      launch_gram_direction(g, o, f0, f1, ch, psi, q, p, c->d_beta, c->d_gpart, s);
+      Timed t(c, DCDFT_KERNEL_GRAM, 4.0 * sz * n * nb, 2.0 * n * m2);
+      launch_gram_direction<T>(g, o, f0, f1, ch, psi, q, p, c->d_beta, c->d_gpart, s);
     }
     launch_gram_reduce(g, o, f0, f1, ch, 0, c->d_gpart, c->d_x, nullptr, nullptr, s);
     // (e)-(f) P <- P - X^T Psi, nu_i = <p_i, p_i>, <p_i, w_i>
     {
-      Timed t(c, DCDFT_KERNEL_ROTATE, 32.0 * n * nb, 2.0 * n * m2);
-      launch_rot_project_out(g, o, f0, f1, c->d_x, psi, p, w, c->d_dpart, c->d_nu, c->d_bb, s);
+      Timed t(c, DCDFT_KERNEL_ROTATE, 4.0 * sz * n * nb, 2.0 * n * m2);
+      launch_rot_project_out<T>(g, o, f0, f1, c->d_x, psi, p, w, c->d_dpart, c->d_nu, c->d_bb,
+                                s);
     }
     launch_cg_norm(o, f0, f1, c->d_nu, c->d_inv, s);
     // (g) Q = H P and <p_i, q_i>
-    hloc(c, f0, f1, p, q, c->d_cc);
-    launch_kb_project(g, o, kb, f0, f1, p, c->d_C, c->d_cpart, s);
-    launch_kb_apply(g, o, kb, f0, f1, c->d_C, q, s);
+    hloc<T>(c, f0, f1, p, q, c->d_cc);
+    launch_kb_project<T>(g, o, kb, f0, f1, p, c->d_C, c->d_cpart, s);
+    launch_kb_apply<T>(g, o, kb, f0, f1, c->d_C, q, s);
     launch_kb_quad(o, f0, f1, kb, c->d_C, c->d_cc, s);
     // (h)-(i) exact minimiser of the 2x2 Rayleigh quotient
     launch_cg_theta(o, f0, f1, c->d_a, c->d_bb, c->d_cc, c->d_inv, c->d_cos, c->d_sin, s);
     // (j) band rotations and (l) S = sym(<Psi, Psi>)
     {
-      Timed t(c, DCDFT_KERNEL_GRAM, 48.0 * n * nb, 1.0 * n * m2);
-      launch_gram_update(g, o, f0, f1, ch, psi, p, w, q, c->d_cos, c->d_sin, c->d_gpart, s);
+      Timed t(c, DCDFT_KERNEL_GRAM, 6.0 * sz * n * nb, 1.0 * n * m2);
+      launch_gram_update<T>(g, o, f0, f1, ch, psi, p, w, q, c->d_cos, c->d_sin, c->d_gpart, s);
     }
     launch_gram_reduce(g, o, f0, f1, ch, 1, c->d_gpart, c->d_s, nullptr, nullptr, s);
     // (l) S = L L^T, Psi <- L^-1 Psi, W <- L^-1 W
     launch_cholinv(o, f0, f1, c->d_s, c->d_lin, c->d_flags, s);
     {
-      Timed t(c, DCDFT_KERNEL_ROTATE, 32.0 * n * nb, 2.0 * n * m2);
-      launch_rot_cholesky(g, o, f0, f1, c->d_lin, psi, w, s);
+      Timed t(c, DCDFT_KERNEL_ROTATE, 4.0 * sz * n * nb, 2.0 * n * m2);
+      launch_rot_cholesky<T>(g, o, f0, f1, c->d_lin, psi, w, s);
     }
   }
   // Rayleigh-Ritz, then core weights w_i = dV sum_core psi_i^2
-  gram(c, f0, f1, psi, w, c->d_hs, nullptr, nullptr);
+  gram<T>(c, f0, f1, psi, w, c->d_hs, nullptr, nullptr);
   launch_syev(o, f0, f1, c->d_hs, c->d_u, c->d_eps, c->d_flags, s);
   {
-    Timed t(c, DCDFT_KERNEL_ROTATE, 16.0 * n * nb, 2.0 * n * m2);
-    launch_rot_ritz(g, o, f0, f1, c->d_u, psi, c->d_dpart, c->d_wcore, s);
+    Timed t(c, DCDFT_KERNEL_ROTATE, 2.0 * sz * n * nb, 2.0 * n * m2);
+    launch_rot_ritz<T>(g, o, f0, f1, c->d_u, psi, c->d_dpart, c->d_wcore, s);
   }
 }
 
+template <typename T>
 void orthonormalize_all(dcdft_ctx *c) {
   OrbSet o = c->orbset(0, c->nF);
-  gram(c, 0, c->nF, c->d_psi, c->d_psi, c->d_s, nullptr, nullptr);
+  T *psi = (T *)c->d_psi;
+  gram<T>(c, 0, c->nF, psi, psi, c->d_s, nullptr, nullptr);
   launch_cholinv(o, 0, c->nF, c->d_s, c->d_lin, c->d_flags, c->stream);
-  rotate(c, 0, c->nF, c->d_lin, 1, c->d_psi, nullptr, 0.0, 1.0, c->d_psi);
+  launch_rot_cholesky<T>(c->geo, o, 0, c->nF, c->d_lin, psi, (T *)nullptr, c->stream);
 }
 
 dcdft_status check_flags(dcdft_ctx *c, int flags) {
@@ -367,8 +369,8 @@ dcdft_status validate(const dcdft_params *p) {
   if (!(p->mixing > 0.0 && p->mixing <= 1.0))
     return set_err(nullptr, DCDFT_ERR_ARG, "mixing outside (0, 1]");
   if (p->cg_sweeps < 1) return set_err(nullptr, DCDFT_ERR_ARG, "cg_sweeps < 1");
-  if (p->precision != DCDFT_PREC_FP64)
-    return set_err(nullptr, DCDFT_ERR_ARG, "only DCDFT_PREC_FP64 is available in this build");
+  if (p->precision != DCDFT_PREC_FP64 && p->precision != DCDFT_PREC_MIXED)
+    return set_err(nullptr, DCDFT_ERR_ARG, "precision must be DCDFT_PREC_FP64 or DCDFT_PREC_MIXED");
   if (p->batched != 0 && p->batched != 1) return set_err(nullptr, DCDFT_ERR_ARG, "batched not 0/1");
   const int nF = p->num_fragment[0] * p->num_fragment[1] * p->num_fragment[2];
   for (int f = 0; f < nF; ++f) {
@@ -553,6 +555,10 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
     }
     HIPTRY(c, upload(c, &c->d_reg_atom, reg_atom));
     HIPTRY(c, upload(c, &c->d_reg_beta, reg_beta));
+    {
+      std::vector<float> rb32(reg_beta.begin(), reg_beta.end());
+      HIPTRY(c, upload(c, &c->d_reg_beta32, rb32));
+    }
     HIPTRY(c, upload(c, &c->d_ar_ptr, ar_ptr));
     HIPTRY(c, upload(c, &c->d_ar_reg, ar_reg));
     HIPTRY(c, upload(c, &c->d_ar_slot, ar_slot));
@@ -628,14 +634,23 @@ void enqueue_step(dcdft_ctx *c) {
   launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, s);
   // 3. fragment eigensolvers
   if (c->batched) {
-    eigensolver_range(c, 0, c->nF);
+    if (c->precision == DCDFT_PREC_MIXED) eigensolver_range<float>(c, 0, c->nF);
+    else eigensolver_range<double>(c, 0, c->nF);
   } else {
-    for (int f = 0; f < c->nF; ++f) eigensolver_range(c, f, f + 1);
+    for (int f = 0; f < c->nF; ++f) {
+      if (c->precision == DCDFT_PREC_MIXED) eigensolver_range<float>(c, f, f + 1);
+      else eigensolver_range<double>(c, f, f + 1);
+    }
   }
   // 4. global chemical potential
   launch_fermi(o, c->d_eps, c->d_wcore, c->ne, c->smearing, c->d_occ, c->d_scal, c->d_flags, s);
   // 5. densities
-  launch_density(g, o, 0, c->nF, c->d_psi, c->d_occ, c->d_rhof_out, c->d_rho_out, s);
+  if (c->precision == DCDFT_PREC_MIXED)
+    launch_density<float>(g, o, 0, c->nF, (const float *)c->d_psi, c->d_occ, c->d_rhof_out,
+                          c->d_rho_out, s);
+  else
+    launch_density<double>(g, o, 0, c->nF, (const double *)c->d_psi, c->d_occ, c->d_rhof_out,
+                           c->d_rho_out, s);
   // 6-8. energy terms, residuals, mixing
   launch_global_terms(g, c->d_rho_in, c->d_rho_out, c->d_vh, c->mixing, c->d_part, c->n_part,
                       c->d_scal, s, c->ne, c->smearing);
@@ -809,11 +824,20 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
       return fail(DCDFT_ERR_HIP);
     }
   }
-  ALLOC(c->d_psi, norb);
-  ALLOC(c->d_w, norb);
-  ALLOC(c->d_p, norb);
-  ALLOC(c->d_q, norb);
-  ALLOC(c->d_r, norb);
+  const bool mixed = c->precision == DCDFT_PREC_MIXED;
+  c->elem = mixed ? sizeof(float) : sizeof(double);
+  {
+    void **orb[] = {&c->d_psi, &c->d_w, &c->d_p, &c->d_q};
+    for (void **a : orb) {
+      char *q = nullptr;
+      hipError_t e_ = dalloc(c, &q, (size_t)norb * c->elem);
+      if (e_ != hipSuccess) {
+        c->last_error = "orbital array allocation failed";
+        return fail(e_ == hipErrorOutOfMemory ? DCDFT_ERR_OOM : DCDFT_ERR_HIP);
+      }
+      *a = q;
+    }
+  }
   ALLOC(c->d_C, (long long)c->nF * c->A_max * c->m_pad);
   ALLOC(c->d_cpart, (long long)c->nF * c->NR * c->KS * c->m_pad);
   ALLOC(c->d_vh, g.Ng);
@@ -856,14 +880,19 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   launch_fill(c->d_vh, g.Ng, 0.0, c->stream);
   launch_fill(c->d_rhof_in, (long long)c->nF * g.n, rho0, c->stream);
   launch_fill(c->d_rhof_out, (long long)c->nF * g.n, 0.0, c->stream);
-  launch_fill(c->d_p, norb, 0.0, c->stream);
+  HIPTRY(c, hipMemsetAsync(c->d_p, 0, (size_t)norb * c->elem, c->stream));
   launch_fill(c->d_C, (long long)c->nF * c->A_max * c->m_pad, 0.0, c->stream);
   for (double **b : bands) launch_fill(*b, c->M_tot, 0.0, c->stream);
   launch_fill(c->d_scal, SC_COUNT, 0.0, c->stream);
   launch_fill_int(c->d_flags, 1, 0, c->stream);
   launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, c->stream);
-  launch_init_orbitals(g, c->orbset(0, c->nF), c->seed, c->d_psi, c->stream);
-  orthonormalize_all(c);
+  if (mixed) {
+    launch_init_orbitals<float>(g, c->orbset(0, c->nF), c->seed, (float *)c->d_psi, c->stream);
+    orthonormalize_all<float>(c);
+  } else {
+    launch_init_orbitals<double>(g, c->orbset(0, c->nF), c->seed, (double *)c->d_psi, c->stream);
+    orthonormalize_all<double>(c);
+  }
   int flags = 0;
   if (hipMemcpyAsync(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->stream) !=
           hipSuccess ||
@@ -1031,9 +1060,17 @@ dcdft_status dcdft_get_orbitals(const dcdft_ctx *c, int32_t frag, double *host, 
   if (frag < 0 || frag >= c->nF) return set_err(cc, DCDFT_ERR_ARG, fmt("fragment %d out of range", frag));
   const size_t need = (size_t)c->m[frag] * c->geo.n;
   if (count < need) return set_err(cc, DCDFT_ERR_ARG, fmt("%zu values needed", need));
-  HIPTRY(cc, hipMemcpyAsync(host, c->d_psi + c->moff[frag] * c->geo.n, need * sizeof(double),
-                            hipMemcpyDeviceToHost, c->stream));
-  HIPTRY(cc, hipStreamSynchronize(c->stream));
+  const char *src = (const char *)c->d_psi + (size_t)c->moff[frag] * c->geo.n * c->elem;
+  if (c->elem == sizeof(double)) {
+    HIPTRY(cc, hipMemcpyAsync(host, src, need * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPTRY(cc, hipStreamSynchronize(c->stream));
+  } else {
+    std::vector<float> tmp(need);
+    HIPTRY(cc, hipMemcpyAsync(tmp.data(), src, need * sizeof(float), hipMemcpyDeviceToHost,
+                              c->stream));
+    HIPTRY(cc, hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < need; ++i) host[i] = tmp[i];
+  }
   return DCDFT_OK;
 }
 
@@ -1044,9 +1081,16 @@ dcdft_status dcdft_set_orbitals(dcdft_ctx *c, int32_t frag, const double *host, 
   if (count < need) return set_err(c, DCDFT_ERR_ARG, fmt("%zu values needed", need));
   for (size_t i = 0; i < need; ++i)
     if (!std::isfinite(host[i])) return set_err(c, DCDFT_ERR_NAN, "non-finite orbital value");
-  HIPTRY(c, hipMemcpyAsync(c->d_psi + c->moff[frag] * c->geo.n, host, need * sizeof(double),
-                           hipMemcpyHostToDevice, c->stream));
-  HIPTRY(c, hipStreamSynchronize(c->stream));
+  char *dst = (char *)c->d_psi + (size_t)c->moff[frag] * c->geo.n * c->elem;
+  if (c->elem == sizeof(double)) {
+    HIPTRY(c, hipMemcpyAsync(dst, host, need * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+  } else {
+    std::vector<float> tmp(host, host + need);
+    HIPTRY(c, hipMemcpyAsync(dst, tmp.data(), need * sizeof(float), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+  }
   return DCDFT_OK;
 }
 
@@ -1124,7 +1168,8 @@ void free_ext(ExtLayout &L) {
   if (L.band_frag) hipFree(L.band_frag);
 }
 
-dcdft_status apply_h_ext(dcdft_ctx *c, int frag, const double *psi, double *hpsi, int m) {
+template <typename T>
+dcdft_status apply_h_ext(dcdft_ctx *c, int frag, const T *psi, T *hpsi, int m) {
   const Geo &g = c->geo;
   for (int i0 = 0; i0 < m; i0 += c->m_pad) {
     const int mm = std::min(c->m_pad, m - i0);
@@ -1142,16 +1187,38 @@ dcdft_status apply_h_ext(dcdft_ctx *c, int frag, const double *psi, double *hpsi
     o.h_m = L.h_m.data();
     o.M_tot = mm;
     KBTables kb = c->kb();
-    const double *x = psi + (long long)i0 * g.n;
-    double *y = hpsi + (long long)i0 * g.n;
-    launch_hloc(g, o, frag, frag + 1, c->d_veff, x, y, c->stream);
-    launch_kb_project(g, o, kb, frag, frag + 1, x, c->d_C, c->d_cpart, c->stream);
-    launch_kb_apply(g, o, kb, frag, frag + 1, c->d_C, y, c->stream);
+    const T *x = psi + (long long)i0 * g.n;
+    T *y = hpsi + (long long)i0 * g.n;
+    launch_hloc<T>(g, o, frag, frag + 1, c->d_veff, x, y, c->stream);
+    launch_kb_project<T>(g, o, kb, frag, frag + 1, x, c->d_C, c->d_cpart, c->stream);
+    launch_kb_apply<T>(g, o, kb, frag, frag + 1, c->d_C, y, c->stream);
     hipError_t e = hipStreamSynchronize(c->stream);
     free_ext(L);
     if (e != hipSuccess) return set_err(c, DCDFT_ERR_HIP, hipGetErrorString(e));
   }
   return DCDFT_OK;
+}
+
+template <typename T>
+dcdft_status band_energy_t(dcdft_ctx *c, int frag, const T *psi, const double *f, int m,
+                           double *energy, T *grad_psi, T *grad_v) {
+  const Geo &g = c->geo;
+  T *hp = nullptr;
+  double *eb = nullptr;
+  HIPTRY(c, hipMalloc(&hp, (size_t)m * g.n * sizeof(T)));
+  if (hipMalloc(&eb, (size_t)m * sizeof(double)) != hipSuccess) {
+    hipFree(hp);
+    return set_err(c, DCDFT_ERR_OOM, "scratch allocation failed");
+  }
+  dcdft_status st = apply_h_ext<T>(c, frag, psi, hp, m);
+  if (st == DCDFT_OK) {
+    launch_band_energy<T>(g, m, psi, hp, f, eb, energy, grad_psi, grad_v, c->stream);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) st = set_err(c, DCDFT_ERR_HIP, hipGetErrorString(e));
+  }
+  hipFree(hp);
+  hipFree(eb);
+  return st;
 }
 
 }  // namespace
@@ -1163,10 +1230,13 @@ dcdft_status dcdft_apply_h(dcdft_ctx *c, int32_t frag, const void *psi, void *hp
   if (!c || !psi || !hpsi) return set_err(c, DCDFT_ERR_ARG, "NULL argument");
   if (frag < 0 || frag >= c->nF) return set_err(c, DCDFT_ERR_ARG, fmt("fragment %d out of range", frag));
   if (m < 0) return set_err(c, DCDFT_ERR_ARG, "m < 0");
-  if (prec != DCDFT_PREC_FP64) return set_err(c, DCDFT_ERR_ARG, "only FP64 vectors are supported");
+  if (prec != DCDFT_PREC_FP64 && prec != DCDFT_PREC_MIXED)
+    return set_err(c, DCDFT_ERR_ARG, "prec must be 0 (double) or 1 (float)");
   if (psi == hpsi) return set_err(c, DCDFT_ERR_ARG, "psi and hpsi may not alias");
   if (m == 0) return DCDFT_OK;
-  return apply_h_ext(c, frag, (const double *)psi, (double *)hpsi, m);
+  if (prec == DCDFT_PREC_MIXED)
+    return apply_h_ext<float>(c, frag, (const float *)psi, (float *)hpsi, m);
+  return apply_h_ext<double>(c, frag, (const double *)psi, (double *)hpsi, m);
 }
 
 dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, const double *f,
@@ -1175,24 +1245,13 @@ dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, cons
   if (!c || !psi || !f) return set_err(c, DCDFT_ERR_ARG, "NULL argument");
   if (frag < 0 || frag >= c->nF) return set_err(c, DCDFT_ERR_ARG, fmt("fragment %d out of range", frag));
   if (m < 1) return set_err(c, DCDFT_ERR_ARG, "m < 1");
-  if (prec != DCDFT_PREC_FP64) return set_err(c, DCDFT_ERR_ARG, "only FP64 vectors are supported");
-  const Geo &g = c->geo;
-  double *hp = nullptr, *eb = nullptr;
-  HIPTRY(c, hipMalloc(&hp, (size_t)m * g.n * sizeof(double)));
-  if (hipMalloc(&eb, (size_t)m * sizeof(double)) != hipSuccess) {
-    hipFree(hp);
-    return set_err(c, DCDFT_ERR_OOM, "scratch allocation failed");
-  }
-  dcdft_status st = apply_h_ext(c, frag, (const double *)psi, hp, m);
-  if (st == DCDFT_OK) {
-    launch_band_energy(g, m, (const double *)psi, hp, f, eb, energy, (double *)grad_psi,
-                       (double *)grad_v, c->stream);
-    hipError_t e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) st = set_err(c, DCDFT_ERR_HIP, hipGetErrorString(e));
-  }
-  hipFree(hp);
-  hipFree(eb);
-  return st;
+  if (prec != DCDFT_PREC_FP64 && prec != DCDFT_PREC_MIXED)
+    return set_err(c, DCDFT_ERR_ARG, "prec must be 0 (double) or 1 (float)");
+  if (prec == DCDFT_PREC_MIXED)
+    return band_energy_t<float>(c, frag, (const float *)psi, f, m, energy, (float *)grad_psi,
+                                (float *)grad_v);
+  return band_energy_t<double>(c, frag, (const double *)psi, f, m, energy, (double *)grad_psi,
+                               (double *)grad_v);
 }
 
 }  // extern "C"

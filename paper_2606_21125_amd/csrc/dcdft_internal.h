@@ -68,6 +68,7 @@ struct KBTables {
   int KS;                            // slots per region (multiple of 16)
   const int *reg_atom;               // [F][NR][KS] local atom index or -1
   const double *reg_beta;            // [F][NR][KS][kRegion]
+  const float *reg_beta32;           // the same values in FP32 (mixed path)
   const long long *ar_ptr;           // [F * A_max + 1] into (region, slot) lists
   const int *ar_reg;                 // region of each entry
   const int *ar_slot;                // slot of each entry
@@ -125,11 +126,13 @@ struct dcdft_ctx {
   int NR = 0, KS = 0;
   int *d_reg_atom = nullptr, *d_ar_reg = nullptr, *d_ar_slot = nullptr;
   double *d_reg_beta = nullptr;
+  float *d_reg_beta32 = nullptr;
   long long *d_ar_ptr = nullptr;
   double *d_cpart = nullptr;         // region projection partials [F][NR][KS][m_pad]
 
-  // orbital arrays [M_tot][n]
-  double *d_psi = nullptr, *d_w = nullptr, *d_p = nullptr, *d_q = nullptr, *d_r = nullptr;
+  // orbital arrays [M_tot][n], element type double (FP64) or float (mixed)
+  void *d_psi = nullptr, *d_w = nullptr, *d_p = nullptr, *d_q = nullptr;
+  size_t elem = sizeof(double);
 
   // fields
   double *d_vloc = nullptr, *d_vh = nullptr, *d_rho_in = nullptr, *d_rho_out = nullptr;
@@ -186,37 +189,71 @@ struct dcdft_ctx {
 namespace dcdft {
 
 // ---- launchers (all asynchronous on the given stream) -------------------------------------
+// Orbital arrays are [M_tot][n] of T = double (FP64 path) or float (mixed path);
+// small matrices, per-band scalars and fields are FP64.
 
 // Y = (-1/2 L_FD + V_eff) X for every orbital of fragments [f0, f1); dot (if not
 // null) receives dV <x_B, y_B> per band.
-void launch_hloc(const Geo &g, const OrbSet &o, int f0, int f1, const double *veff,
-                 const double *x, double *y, hipStream_t s, double *dot = nullptr);
-// C[f][a][i] = dV sum beta_a(l) X_i(l)
+template <typename T>
+void launch_hloc(const Geo &g, const OrbSet &o, int f0, int f1, const double *veff, const T *x,
+                 T *y, hipStream_t s, double *dot = nullptr);
+// C[f][a][i] = dV sum beta_a(l) X_i(l) (region partials in part)
+template <typename T>
 void launch_kb_project(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1,
-                       const double *x, double *C, double *part, hipStream_t s);
+                       const T *x, double *C, double *part, hipStream_t s);
 // Y_i(l) += sum_a beta_a(l) E_a C[f][a][i]
+template <typename T>
 void launch_kb_apply(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1,
-                     const double *C, double *y, hipStream_t s);
-// part[f][w] = X^T Y partial sums (row form: G_ij = sum_l X_i(l) Y_j(l))
-void launch_gram(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, const double *x,
-                 const double *y, double *part, hipStream_t s);
+                     const double *C, T *y, hipStream_t s);
+template <typename T>
+void launch_init_orbitals(const Geo &g, const OrbSet &o, uint64_t seed, T *psi, hipStream_t s);
+// band energy: eb[B] = f_B <psi_B|H psi_B>, energy = sum eb, grads
+template <typename T>
+void launch_band_energy(const Geo &g, int nb, const T *psi, const T *hpsi, const double *f,
+                        double *eb, double *energy, T *grad_psi, T *grad_v, hipStream_t s);
+
+// Gram partials of X^T Y (row form G_ij = sum_l X_i(l) Y_j(l)); X == Y is symmetric
+template <typename T>
+void launch_gram(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, const T *x,
+                 const T *y, double *part, hipStream_t s);
+// P = beta P - G (in place over P), Gram partials of Psi^T P
+template <typename T>
+void launch_gram_direction(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
+                           const T *psi, const T *gres, T *p, const double *beta, double *part,
+                           hipStream_t s);
+// Psi <- cs Psi + sn P, W <- cs W + sn Q (in place), symmetric Gram partials of Psi
+template <typename T>
+void launch_gram_update(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, T *psi,
+                        const T *p, T *w, const T *q, const double *cs, const double *sn,
+                        double *part, hipStream_t s);
 // G = dV sum of chunk partials (sym: X == Y, lower tiles mirrored); Gs = sym(G) if
 // not null; diag -> per-band (may be null)
 void launch_gram_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int sym,
                         const double *part, double *G, double *Gs, double *diag, hipStream_t s);
-// Y_j = cz Z_j + cm sum_i R[j][i] X_i with R = M^T (trans 0) or M (trans 1)
-void launch_rotate(const Geo &g, const OrbSet &o, int f0, int f1, const double *M, int trans,
-                   const double *x, const double *z, double cz, double cm, double *y,
-                   hipStream_t s);
-// per-band dot: out[B] = dV sum_l X_B(l) Y_B(l); core != 0 restricts to core points
-void launch_band_dot(const Geo &g, const OrbSet &o, int f0, int f1, const double *x,
-                     const double *y, int core, double *out, hipStream_t s);
-// Y_B = a[B] Y_B + b[B] X_B  (a, b per band; null a means 0, null b means 0)
-void launch_band_axpby(const Geo &g, const OrbSet &o, int f0, int f1, const double *a,
-                       double a_const, const double *b, double b_const, const double *x,
-                       double *y, hipStream_t s);
-// CG scalar steps
-// beta = gamma / gamma_prev (0 on the first sweep), then gamma_prev = gamma
+// Fused rotations (per-band reductions go through dpart, one partial per
+// rotation workgroup, then a band reduction).
+int rot_wpf(const Geo &g);
+// G = W - Hs Psi into gout, gamma = dV |G|^2
+template <typename T>
+void launch_rot_residual(const Geo &g, const OrbSet &o, int f0, int f1, const double *Hs,
+                         const T *psi, const T *w, T *gout, double *dpart, double *gamma,
+                         hipStream_t s);
+// P <- P - X^T Psi, nu = dV |P|^2, pw = dV <P, W>
+template <typename T>
+void launch_rot_project_out(const Geo &g, const OrbSet &o, int f0, int f1, const double *X,
+                            const T *psi, T *p, const T *w, double *dpart, double *nu,
+                            double *pw, hipStream_t s);
+// Psi <- Linv Psi and, if w is not null, W <- Linv W (Linv lower triangular)
+template <typename T>
+void launch_rot_cholesky(const Geo &g, const OrbSet &o, int f0, int f1, const double *Linv,
+                         T *psi, T *w, hipStream_t s);
+// Psi <- U^T Psi (Ritz vectors), wcore = dV sum_core psi^2
+template <typename T>
+void launch_rot_ritz(const Geo &g, const OrbSet &o, int f0, int f1, const double *U, T *psi,
+                     double *dpart, double *wcore, hipStream_t s);
+
+// CG scalar steps: beta = gamma / gamma_prev (0 on the first sweep), then
+// gamma_prev = gamma; inv = 1/sqrt(nu); theta from the 2x2 problem
 void launch_cg_beta(const OrbSet &o, int f0, int f1, int first, const double *gamma,
                     double *gamma_prev, double *beta, hipStream_t s);
 void launch_cg_norm(const OrbSet &o, int f0, int f1, const double *nu, double *inv,
@@ -225,31 +262,6 @@ void launch_cg_theta(const OrbSet &o, int f0, int f1, const double *a, const dou
                      const double *c, const double *inv, double *cs, double *sn, hipStream_t s);
 void launch_copy_band(const OrbSet &o, int f0, int f1, const double *src, double *dst,
                       hipStream_t s);
-// Fused sweep kernels (per-band reductions go through dpart, one partial per
-// rotation workgroup, then a band reduction).
-int rot_wpf(const Geo &g);
-// G = W - Hs Psi into gout, gamma = dV |G|^2
-void launch_rot_residual(const Geo &g, const OrbSet &o, int f0, int f1, const double *Hs,
-                         const double *psi, const double *w, double *gout, double *dpart,
-                         double *gamma, hipStream_t s);
-// P <- P - X^T Psi, nu = dV |P|^2, pw = dV <P, W>
-void launch_rot_project_out(const Geo &g, const OrbSet &o, int f0, int f1, const double *X,
-                            const double *psi, double *p, const double *w, double *dpart,
-                            double *nu, double *pw, hipStream_t s);
-// Psi <- Linv Psi, W <- Linv W (Linv lower triangular, row-major)
-void launch_rot_cholesky(const Geo &g, const OrbSet &o, int f0, int f1, const double *Linv,
-                         double *psi, double *w, hipStream_t s);
-// Psi <- U^T Psi (Ritz vectors), wcore = dV sum_core psi^2
-void launch_rot_ritz(const Geo &g, const OrbSet &o, int f0, int f1, const double *U, double *psi,
-                     double *dpart, double *wcore, hipStream_t s);
-// P = beta P - G (in place over P), Gram partials of Psi^T P
-void launch_gram_direction(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
-                           const double *psi, const double *gres, double *p, const double *beta,
-                           double *part, hipStream_t s);
-// Psi <- cs Psi + sn P, W <- cs W + sn Q (in place), symmetric Gram partials of Psi
-void launch_gram_update(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, double *psi,
-                        const double *p, double *w, const double *q, const double *cs,
-                        const double *sn, double *part, hipStream_t s);
 // cp[B] += sum_a E_a C[f][a][i]^2
 void launch_kb_quad(const OrbSet &o, int f0, int f1, const KBTables &kb, const double *C,
                     double *cp, hipStream_t s);
@@ -263,7 +275,8 @@ void launch_syev(const OrbSet &o, int f0, int f1, const double *Hs, double *U, d
 void launch_fermi(const OrbSet &o, const double *eps, const double *w, double ne, double sigma,
                   double *occ, double *scal, int *flags, hipStream_t s);
 // rho_alpha^out and the core scatter into rho_tot^out
-void launch_density(const Geo &g, const OrbSet &o, int f0, int f1, const double *psi,
+template <typename T>
+void launch_density(const Geo &g, const OrbSet &o, int f0, int f1, const T *psi,
                     const double *occ, double *rhof_out, double *rho_out, hipStream_t s);
 // V_eff^alpha = V_loc + V_H (gathered) + V_xc(rho_alpha^in)
 void launch_veff(const Geo &g, int f0, int f1, const double *vloc, const double *vh,
@@ -278,15 +291,10 @@ void launch_frag_mix(const Geo &g, int nfrag, double *rhof_in, const double *rho
 void launch_poisson(const Geo &g, const double *rho, double *vh, double *wa, double *wb,
                     double *const qf[3], double *const qi[3], double *const lam[3],
                     hipStream_t s);
-// SplitMix64 initial orbitals
-void launch_init_orbitals(const Geo &g, const OrbSet &o, uint64_t seed, double *psi,
-                          hipStream_t s);
 void launch_fill(double *p, long long n, double v, hipStream_t s);
 void launch_fill_int(int *p, long long n, int v, hipStream_t s);
 void launch_nan_check(const double *p, long long n, int *flags, hipStream_t s);
-// band energy: E = sum f_i <psi_i|H psi_i>, grads
-void launch_band_energy(const Geo &g, int nb, const double *psi, const double *hpsi,
-                        const double *f, double *eb, double *energy, double *grad_psi,
-                        double *grad_v, hipStream_t s);
+void launch_convert(const double *a, float *b, long long n, hipStream_t s);
+void launch_convert(const float *a, double *b, long long n, hipStream_t s);
 
 }  // namespace dcdft

@@ -3,29 +3,11 @@
 // the fragment effective potential (Eq. (5)), the Hartree potential of the
 // total density, the LDA exchange-correlation (Perdew-Zunger 1981), the
 // energy terms, residuals and linear mixing.
-#include "dcdft_internal.h"
+#include "device_common.h"
 
 namespace dcdft {
 
 namespace {
-
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-__device__ inline double block_sum(double v, double *red) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nw = (blockDim.x + 63) >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double t = 0.0;
-  for (int w = 0; w < nw; ++w) t += red[w];
-  return t;
-}
 
 __device__ inline double block_min(double v, double *red) {
   for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
@@ -89,12 +71,6 @@ __device__ inline long long global_of_local(const Geo &g, int f, int l) {
   return gx + (long long)g.N[0] * (gy + (long long)g.N[1] * gz);
 }
 
-__device__ inline bool is_core(const Geo &g, int l) {
-  const int lx = l % g.nl[0], ly = (l / g.nl[0]) % g.nl[1], lz = l / (g.nl[0] * g.nl[1]);
-  return lx >= g.b[0] && lx < g.b[0] + g.nc[0] && ly >= g.b[1] && ly < g.b[1] + g.nc[1] &&
-         lz >= g.b[2] && lz < g.b[2] + g.nc[2];
-}
-
 // N(mu) = sum 2 f((eps - mu) / sigma) w by bisection over the bracket
 // [min eps - 50 sigma, max eps + 50 sigma], one workgroup.
 __global__ void __launch_bounds__(1024) k_fermi(long long nb, const double *__restrict__ eps,
@@ -145,8 +121,9 @@ __global__ void __launch_bounds__(1024) k_fermi(long long nb, const double *__re
 }
 
 // rho_alpha^out(l) = sum_i 2 f_i psi_i(l)^2; core points also written to rho_tot^out.
+template <typename T>
 __global__ void __launch_bounds__(256) k_density(Geo g, const long long *__restrict__ moff,
-                                                 int f0, int f1, const double *__restrict__ psi,
+                                                 int f0, int f1, const T *__restrict__ psi,
                                                  const double *__restrict__ occ,
                                                  double *__restrict__ rhof_out,
                                                  double *__restrict__ rho_out) {
@@ -156,11 +133,11 @@ __global__ void __launch_bounds__(256) k_density(Geo g, const long long *__restr
   const int l = (int)(idx % g.n);
   double acc = 0.0;
   for (long long B = moff[f]; B < moff[f + 1]; ++B) {
-    const double v = psi[B * g.n + l];
+    const double v = (double)psi[B * g.n + l];
     acc += 2.0 * occ[B] * v * v;
   }
   rhof_out[(long long)f * g.n + l] = acc;
-  if (is_core(g, l)) rho_out[global_of_local(g, f, l)] = acc;
+  if (is_core_point(g, l)) rho_out[global_of_local(g, f, l)] = acc;
 }
 
 __global__ void __launch_bounds__(256) k_veff(Geo g, int f0, int f1, const double *__restrict__ vloc,
@@ -300,12 +277,37 @@ void launch_fermi(const OrbSet &o, const double *eps, const double *w, double ne
                      flags);
 }
 
-void launch_density(const Geo &g, const OrbSet &o, int f0, int f1, const double *psi,
+template <typename T>
+void launch_density(const Geo &g, const OrbSet &o, int f0, int f1, const T *psi,
                     const double *occ, double *rhof_out, double *rho_out, hipStream_t s) {
   const long long total = (long long)(f1 - f0) * g.n;
   if (total <= 0) return;
-  hipLaunchKernelGGL(k_density, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, o.moff,
-                     f0, f1, psi, occ, rhof_out, rho_out);
+  hipLaunchKernelGGL(k_density<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g,
+                     o.moff, f0, f1, psi, occ, rhof_out, rho_out);
+}
+template void launch_density<double>(const Geo &, const OrbSet &, int, int, const double *,
+                                     const double *, double *, double *, hipStream_t);
+template void launch_density<float>(const Geo &, const OrbSet &, int, int, const float *,
+                                    const double *, double *, double *, hipStream_t);
+
+__global__ void k_to_float(const double *__restrict__ a, float *__restrict__ b, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+
+__global__ void k_to_double(const float *__restrict__ a, double *__restrict__ b, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    b[i] = (double)a[i];
+}
+
+void launch_convert(const double *a, float *b, long long n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_to_float, dim3(grid_for(n, 256)), dim3(256), 0, s, a, b, n);
+}
+
+void launch_convert(const float *a, double *b, long long n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_to_double, dim3(grid_for(n, 256)), dim3(256), 0, s, a, b, n);
 }
 
 void launch_veff(const Geo &g, int f0, int f1, const double *vloc, const double *vh,

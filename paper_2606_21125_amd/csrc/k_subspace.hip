@@ -1,28 +1,319 @@
 // Subspace kernels of the fragment eigensolver: Gram matrices and subspace
-// rotations on FP64 MFMA (the dense contractions that dominate ground-state
-// cost, Sec. 2.2), the FP64 Cholesky factor inverse for re-orthonormalisation,
-// the FP64 Jacobi eigensolver of the Rayleigh-Ritz step (Eq. (1) restricted to
-// the subspace), and the per-band CG scalar updates.
-#include "dcdft_internal.h"
+// rotations on MFMA (the dense contractions that dominate ground-state cost,
+// Sec. 2.2), with FP64 or FP32 orbital arrays (template T) and FP64 results;
+// the FP64 Cholesky factor inverse for re-orthonormalisation, the FP64 Jacobi
+// eigensolver of the Rayleigh-Ritz step (Eq. (1) in the subspace), and the
+// per-band CG scalar updates.
+#include "device_common.h"
 
 namespace dcdft {
 
 namespace {
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
+// Fused rotation: y = cz z + cm R^T x (and, with RF_TWO, y2 = cm R^T x2 with the
+// same R), with optional per-band reductions of the stored values v over the
+// workgroup's points: RF_DOT_SELF sums v^2, RF_DOT_W sums v * wdot, RF_CORE
+// restricts both to core points.  RF_TRI skips the zero blocks of a
+// lower-triangular R.  R = M^T (trans 0) or M (trans 1) is staged in LDS once per
+// workgroup; each wave handles NT tiles of 16 points and every output orbital,
+// so y may alias x or z.  Reductions go out as one partial per workgroup:
+// dpart[(f * wpf + wg) * 2 * m_pad + k * m_pad + j], k = 0 (self), 1 (wdot).
+enum { RF_DOT_SELF = 1, RF_DOT_W = 2, RF_CORE = 4, RF_TWO = 8, RF_TRI = 16 };
 
-// v_mfma_f64_16x16x4f64 lane layout on gfx950 (checked on the device):
-//   A (16x4): lane l holds A[l % 16][l / 16]
-//   B (4x16): lane l holds B[l / 16][l % 16]
-//   D (16x16): lane l, register r holds D[l / 16 + 4 r][l % 16]
-__device__ inline dbl4 mfma16x16x4(double a, double b, dbl4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+template <typename T, int TM, int NT, int FL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int trans,
+            const T *x, const T *z, double cz, double cm, T *y, const T *x2, T *y2,
+            const T *wdot, double *__restrict__ dpart) {
+  typedef Mfma<T> MM;
+  constexpr int MP = 16 * TM;
+  constexpr int S = lds_stride(MP);
+  __shared__ T Rt[MP * S];
+  __shared__ double red[4][2][MP];
+  const int f = f0 + blockIdx.x / wpf;
+  const int wg = blockIdx.x % wpf;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int mf = o.m[f], mp = o.m_pad;
+  const double *Mf = M + (long long)f * mp * mp;
+  for (int e = threadIdx.x; e < MP * MP; e += blockDim.x) {
+    const int i = e / MP, j = e % MP;
+    double v = 0.0;
+    if (i < mf && j < mf) v = trans ? Mf[j * mp + i] : Mf[i * mp + j];
+    Rt[i * S + j] = (T)v;
+  }
+  __syncthreads();
+  const long long base = o.moff[f] * (long long)g.n;
+  const int jl = lane & 15, kk = lane >> 4;
+  const T tcm = (T)cm, tcz = (T)cz;
+  double ds[TM][4], dw[TM][4];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) ds[a][b] = dw[a][b] = 0.0;
+  for (int u = 0; u < NT; ++u) {
+    const int p0 = ((wg * 4 + wave) * NT + u) * 16;
+    if (p0 >= g.n) break;
+    const int pc = p0 + jl;
+    const bool pin = pc < g.n;
+    const bool core = (FL & RF_CORE) ? is_core_point(g, pc) : true;
+#pragma unroll
+    for (int arr = 0; arr < ((FL & RF_TWO) ? 2 : 1); ++arr) {
+      const T *xs = arr ? x2 : x;
+      T *ys = arr ? y2 : y;
+      T bx[TM * 4];
+#pragma unroll
+      for (int s = 0; s < TM * 4; ++s) {
+        const int i = 4 * s + kk;
+        bx[s] = (i < mf && pin) ? xs[base + (long long)i * g.n + pc] : (T)0;
+      }
+      typename MM::acc_t acc[TM];
+#pragma unroll
+      for (int j = 0; j < TM; ++j) acc[j] = MM::zero();
+#pragma unroll
+      for (int s = 0; s < TM * 4; ++s) {
+        const T *rrow = Rt + (4 * s + kk) * S + jl;
+#pragma unroll
+        for (int jt = 0; jt < TM; ++jt) {
+          if ((FL & RF_TRI) && s > 4 * jt + 3) continue;
+          acc[jt] = MM::mma(rrow[jt * 16], bx[s], acc[jt]);
+        }
+        // keep the operand reads of later steps from being hoisted (register pressure)
+        if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int jt = 0; jt < TM; ++jt)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int j = jt * 16 + MM::row(kk, rr);
+          if (j < mf && pin) {
+            const long long e = base + (long long)j * g.n + pc;
+            T v = tcm * acc[jt][rr];
+            if (!arr && z) v += tcz * z[e];
+            ys[e] = v;
+            if (!arr && core) {
+              if (FL & RF_DOT_SELF) ds[jt][rr] += (double)v * (double)v;
+              if (FL & RF_DOT_W) dw[jt][rr] += (double)v * (double)wdot[e];
+            }
+          }
+        }
+    }
+  }
+  if (FL & (RF_DOT_SELF | RF_DOT_W)) {
+    // sum over the 16 lanes that share a row, then over the 4 waves in LDS
+#pragma unroll
+    for (int jt = 0; jt < TM; ++jt)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+          if (FL & RF_DOT_SELF) ds[jt][rr] += __shfl_xor(ds[jt][rr], off, 64);
+          if (FL & RF_DOT_W) dw[jt][rr] += __shfl_xor(dw[jt][rr], off, 64);
+        }
+    if (jl == 0) {
+#pragma unroll
+      for (int jt = 0; jt < TM; ++jt)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          red[wave][0][jt * 16 + MM::row(kk, rr)] = ds[jt][rr];
+          red[wave][1][jt * 16 + MM::row(kk, rr)] = dw[jt][rr];
+        }
+    }
+    __syncthreads();
+    double *out = dpart + ((long long)f * wpf + wg) * 2 * mp;
+    for (int e = threadIdx.x; e < 2 * MP; e += blockDim.x) {
+      const int k = e / MP, j = e % MP;
+      out[k * mp + j] = red[0][k][j] + red[1][k][j] + red[2][k][j] + red[3][k][j];
+    }
+  }
 }
 
-// LDS row stride for an m_pad-wide operand block: the smallest S >= m_pad with
-// S = 16 (mod 32), so the four 16-lane groups of an MFMA operand read land on
-// different bank halves.
-__host__ __device__ constexpr int lds_stride(int mp) { return mp + ((16 - mp % 32) + 32) % 32; }
+// out_k[B] = dV sum over the workgroup partials of band B (k = 0, 1; null skips).
+__global__ void __launch_bounds__(256) k_band_reduce(Geo g, OrbSet o, long long b0, long long nb,
+                                                     int wpf, const double *__restrict__ dpart,
+                                                     double *__restrict__ out0,
+                                                     double *__restrict__ out1) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nb) return;
+  const long long B = b0 + t;
+  const int f = o.band_frag[B];
+  const int i = (int)(B - o.moff[f]);
+  const int mp = o.m_pad;
+  double s0 = 0.0, s1 = 0.0;
+  for (int wg = 0; wg < wpf; ++wg) {
+    const double *pp = dpart + ((long long)f * wpf + wg) * 2 * mp;
+    s0 += pp[i];
+    s1 += pp[mp + i];
+  }
+  if (out0) out0[B] = g.dv * s0;
+  if (out1) out1[B] = g.dv * s1;
+}
+
+// Gram products.  Workgroup = (fragment, chunk of points).  Per step of KT = 32
+// points the workgroup loads the operand rows cooperatively into LDS at a row
+// stride of KT + 2 elements, and each wave accumulates its share of the output
+// tiles.  The second operand can be built during the load:
+//   GM_PLAIN:  Y given (SYM when X == Y: upper tiles only, one operand).
+//   GM_DIR:    Y = P = beta P_prev - G, written over P_prev.
+//   GM_UPDATE: X = Psi' = c Psi + s P and W' = c W + s Q, both written in place;
+//              symmetric product of Psi'.
+// Partials are written in FP64 (one per workgroup).
+enum { GM_PLAIN = 0, GM_DIR = 1, GM_UPDATE = 2 };
+constexpr int kGramKT = 32;
+constexpr int kGramLd = kGramKT + 2;
+
+template <typename T>
+struct Vec4Load;
+template <>
+struct Vec4Load<double> {
+  __device__ static inline void load(const double *p, double *d) {
+    const double2 a = *reinterpret_cast<const double2 *>(p);
+    const double2 b = *reinterpret_cast<const double2 *>(p + 2);
+    d[0] = a.x; d[1] = a.y; d[2] = b.x; d[3] = b.y;
+  }
+  __device__ static inline void store(double *p, const double *d) {
+    *reinterpret_cast<double2 *>(p) = double2{d[0], d[1]};
+    *reinterpret_cast<double2 *>(p + 2) = double2{d[2], d[3]};
+  }
+};
+template <>
+struct Vec4Load<float> {
+  __device__ static inline void load(const float *p, float *d) {
+    const float4 a = *reinterpret_cast<const float4 *>(p);
+    d[0] = a.x; d[1] = a.y; d[2] = a.z; d[3] = a.w;
+  }
+  __device__ static inline void store(float *p, const float *d) {
+    *reinterpret_cast<float4 *>(p) = float4{d[0], d[1], d[2], d[3]};
+  }
+};
+
+template <typename T, int TM, int MODE, bool SYM, bool VEC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a2, T *a3,
+        const T *a4, const double *__restrict__ c1, const double *__restrict__ c2,
+        double *__restrict__ part) {
+  typedef Mfma<T> MM;
+  constexpr int MP = 16 * TM;
+  constexpr int NTILE = SYM ? TM * (TM + 1) / 2 : TM * TM;
+  constexpr int PER_WAVE = (NTILE + 3) / 4;
+  __shared__ T Xs[MP * kGramLd];
+  __shared__ T Ys[SYM ? 1 : MP * kGramLd];
+  const int f = f0 + blockIdx.x / chunks;
+  const int c = blockIdx.x % chunks;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int mf = o.m[f];
+  const int mp = o.m_pad;
+  const long long base = o.moff[f] * (long long)g.n;
+  const int p_begin = c * kchunk;
+  const int p_end = min(p_begin + kchunk, g.n);
+  int tI[PER_WAVE], tJ[PER_WAVE];
+  {
+    int k = 0, q = 0;
+#pragma unroll
+    for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < TM; ++tj) {
+        if (SYM && ti > tj) continue;
+        if (q % 4 == wave && k < PER_WAVE) {
+          tI[k] = ti;
+          tJ[k] = tj;
+          ++k;
+        }
+        ++q;
+      }
+#pragma unroll
+    for (; k < PER_WAVE; ++k) {
+      tI[k] = -1;
+      tJ[k] = -1;
+    }
+  }
+  typename MM::acc_t acc[PER_WAVE];
+#pragma unroll
+  for (int k = 0; k < PER_WAVE; ++k) acc[k] = MM::zero();
+  const T *Yl = SYM ? Xs : Ys;
+  for (int p0 = p_begin; p0 < p_end; p0 += kGramKT) {
+    __syncthreads();
+    for (int it = threadIdx.x; it < MP * (kGramKT / 4); it += blockDim.x) {
+      const int row = it / (kGramKT / 4);
+      const int pq = (it % (kGramKT / 4)) * 4;
+      const int p = p0 + pq;
+      T xv[4] = {0, 0, 0, 0}, yv[4] = {0, 0, 0, 0};
+      if (row < mf) {
+        const long long ro = base + (long long)row * g.n;
+        const bool full = VEC && (p + 3 < p_end);
+        T v1[4], v2[4], v3[4], v4[4];
+        auto ld4 = [&](const T *src, T *dst) {
+          if (full) Vec4Load<T>::load(src + ro + p, dst);
+          else
+            for (int t = 0; t < 4; ++t) dst[t] = (p + t < p_end) ? src[ro + p + t] : (T)0;
+        };
+        auto st4 = [&](T *dstp, const T *val) {
+          if (full) Vec4Load<T>::store(dstp + ro + p, val);
+          else
+            for (int t = 0; t < 4; ++t)
+              if (p + t < p_end) dstp[ro + p + t] = val[t];
+        };
+        if (MODE == GM_PLAIN) {
+          ld4(x, xv);
+          if (!SYM) ld4(a1, yv);
+        } else if (MODE == GM_DIR) {
+          ld4(x, xv);
+          ld4(a2, v2);
+          const T b = (T)c1[o.moff[f] + row];
+          if (b != (T)0) {
+            ld4(a1, v1);
+            for (int t = 0; t < 4; ++t) yv[t] = b * v1[t] - v2[t];
+          } else {
+            for (int t = 0; t < 4; ++t) yv[t] = -v2[t];
+          }
+          st4(a1, yv);
+        } else {
+          ld4(x, v1);
+          ld4(a1, v2);
+          ld4(a3, v3);
+          ld4(a4, v4);
+          const T cs = (T)c1[o.moff[f] + row], sn = (T)c2[o.moff[f] + row];
+          for (int t = 0; t < 4; ++t) {
+            xv[t] = cs * v1[t] + sn * v2[t];
+            v3[t] = cs * v3[t] + sn * v4[t];
+          }
+          st4(x, xv);
+          st4(a3, v3);
+        }
+        for (int t = 0; t < 4; ++t)
+          if (p + t >= p_end) xv[t] = yv[t] = (T)0;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        Xs[row * kGramLd + pq + t] = xv[t];
+        if (!SYM) Ys[row * kGramLd + pq + t] = yv[t];
+      }
+    }
+    __syncthreads();
+    const int r = lane & 15, kk = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < kGramKT / 4; ++t) {
+#pragma unroll
+      for (int k = 0; k < PER_WAVE; ++k) {
+        if (tI[k] < 0) continue;
+        const T av = Xs[(tI[k] * 16 + r) * kGramLd + 4 * t + kk];
+        const T bv = Yl[(tJ[k] * 16 + r) * kGramLd + 4 * t + kk];
+        acc[k] = MM::mma(av, bv, acc[k]);
+      }
+      if ((t & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  double *out = part + ((long long)(f - f0) * chunks + c) * mp * mp;
+#pragma unroll
+  for (int k = 0; k < PER_WAVE; ++k) {
+    if (tI[k] < 0) continue;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int row = tI[k] * 16 + MM::row(lane >> 4, rr);
+      const int col = tJ[k] * 16 + (lane & 15);
+      out[row * mp + col] = (double)acc[k][rr];
+    }
+  }
+}
 
 // G = dV sum over chunk partials, element-parallel; for symmetric products the
 // tiles below the diagonal are taken from their mirror.
@@ -66,359 +357,6 @@ __global__ void __launch_bounds__(256) k_symmetrize(OrbSet o, int f0, int nf,
   const int i = e / mp, j = e % mp;
   const double *Gf = G + (long long)f * mp * mp;
   Gs[(long long)f * mp * mp + e] = 0.5 * (Gf[i * mp + j] + Gf[j * mp + i]);
-}
-
-// Rotation, version 2: R^T (as Rt[i][j] = R[j][i]) staged once per workgroup in
-// LDS; each wave handles NT tiles of 16 points and all output orbitals; the
-// X column of a tile (m_pad/4 doubles per lane) is fetched in one burst before
-// its MFMA chain.  Y may alias X or Z (each wave reads its points fully first).
-template <int TM, int NT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_rotate2(Geo g, OrbSet o, int f0, int wpf,
-                                                 const double *__restrict__ M, int trans,
-                                                 const double *x, const double *z, double cz,
-                                                 double cm, double *y) {
-  constexpr int MP = 16 * TM;
-  constexpr int S = lds_stride(MP);
-  __shared__ double Rt[MP * S];
-  const int f = f0 + blockIdx.x / wpf;
-  const int wg = blockIdx.x % wpf;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int mf = o.m[f], mp = o.m_pad;
-  const double *Mf = M + (long long)f * mp * mp;
-  for (int e = threadIdx.x; e < MP * MP; e += blockDim.x) {
-    const int i = e / MP, j = e % MP;
-    double v = 0.0;
-    if (i < mf && j < mf) v = trans ? Mf[j * mp + i] : Mf[i * mp + j];
-    Rt[i * S + j] = v;
-  }
-  __syncthreads();
-  const long long base = o.moff[f] * (long long)g.n;
-  const int jl = lane & 15, kk = lane >> 4;
-  for (int u = 0; u < NT; ++u) {
-    const int p0 = ((wg * 4 + wave) * NT + u) * 16;
-    if (p0 >= g.n) break;
-    const int pc = p0 + jl;
-    const bool pin = pc < g.n;
-    double bx[TM * 4];
-#pragma unroll
-    for (int s = 0; s < TM * 4; ++s) {
-      const int i = 4 * s + kk;
-      bx[s] = (i < mf && pin) ? x[base + (long long)i * g.n + pc] : 0.0;
-    }
-    dbl4 acc[TM];
-#pragma unroll
-    for (int j = 0; j < TM; ++j) acc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int s = 0; s < TM * 4; ++s) {
-      const double *rrow = Rt + (4 * s + kk) * S + jl;
-#pragma unroll
-      for (int jt = 0; jt < TM; ++jt) acc[jt] = mfma16x16x4(rrow[jt * 16], bx[s], acc[jt]);
-      if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int jt = 0; jt < TM; ++jt)
-#pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int j = jt * 16 + kk + 4 * rr;
-        if (j < mf && pin) {
-          const long long e = base + (long long)j * g.n + pc;
-          double v = cm * acc[jt][rr];
-          if (z) v += cz * z[e];
-          y[e] = v;
-        }
-      }
-  }
-}
-
-// Fused rotation: y = cz z + cm R^T x (and, with RF_TWO, y2 = cm R^T x2 with the
-// same R), with optional per-band reductions of the stored values v over the
-// workgroup's points: RF_DOT_SELF sums v^2, RF_DOT_W sums v * wdot, RF_CORE
-// restricts both to core points.  RF_TRI skips the zero blocks of a
-// lower-triangular R.  Reductions are written as one partial per workgroup:
-// dpart[(f * wpf + wg) * 2 * m_pad + k * m_pad + j], k = 0 (self), 1 (wdot).
-enum { RF_DOT_SELF = 1, RF_DOT_W = 2, RF_CORE = 4, RF_TWO = 8, RF_TRI = 16 };
-
-template <int TM, int NT, int FL>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_rot_fused(Geo g, OrbSet o, int f0, int wpf,
-                                                   const double *__restrict__ M, int trans,
-                                                   const double *x, const double *z, double cz,
-                                                   double cm, double *y, const double *x2,
-                                                   double *y2, const double *wdot,
-                                                   double *__restrict__ dpart) {
-  constexpr int MP = 16 * TM;
-  constexpr int S = lds_stride(MP);
-  __shared__ double Rt[MP * S];
-  __shared__ double red[4][2][MP];
-  const int f = f0 + blockIdx.x / wpf;
-  const int wg = blockIdx.x % wpf;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int mf = o.m[f], mp = o.m_pad;
-  const double *Mf = M + (long long)f * mp * mp;
-  for (int e = threadIdx.x; e < MP * MP; e += blockDim.x) {
-    const int i = e / MP, j = e % MP;
-    double v = 0.0;
-    if (i < mf && j < mf) v = trans ? Mf[j * mp + i] : Mf[i * mp + j];
-    Rt[i * S + j] = v;
-  }
-  __syncthreads();
-  const long long base = o.moff[f] * (long long)g.n;
-  const int jl = lane & 15, kk = lane >> 4;
-  double ds[TM][4], dw[TM][4];
-#pragma unroll
-  for (int a = 0; a < TM; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) ds[a][b] = dw[a][b] = 0.0;
-  for (int u = 0; u < NT; ++u) {
-    const int p0 = ((wg * 4 + wave) * NT + u) * 16;
-    if (p0 >= g.n) break;
-    const int pc = p0 + jl;
-    const bool pin = pc < g.n;
-    bool core = true;
-    if (FL & RF_CORE) {
-      const int lx = pc % g.nl[0], ly = (pc / g.nl[0]) % g.nl[1], lz = pc / (g.nl[0] * g.nl[1]);
-      core = lx >= g.b[0] && lx < g.b[0] + g.nc[0] && ly >= g.b[1] && ly < g.b[1] + g.nc[1] &&
-             lz >= g.b[2] && lz < g.b[2] + g.nc[2];
-    }
-#pragma unroll
-    for (int arr = 0; arr < ((FL & RF_TWO) ? 2 : 1); ++arr) {
-      const double *xs = arr ? x2 : x;
-      double *ys = arr ? y2 : y;
-      double bx[TM * 4];
-#pragma unroll
-      for (int s = 0; s < TM * 4; ++s) {
-        const int i = 4 * s + kk;
-        bx[s] = (i < mf && pin) ? xs[base + (long long)i * g.n + pc] : 0.0;
-      }
-      dbl4 acc[TM];
-#pragma unroll
-      for (int j = 0; j < TM; ++j) acc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < TM * 4; ++s) {
-        const double *rrow = Rt + (4 * s + kk) * S + jl;
-#pragma unroll
-        for (int jt = 0; jt < TM; ++jt) {
-          if ((FL & RF_TRI) && s > 4 * jt + 3) continue;
-          acc[jt] = mfma16x16x4(rrow[jt * 16], bx[s], acc[jt]);
-        }
-        // keep the operand reads of later steps from being hoisted (register pressure)
-        if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-      }
-#pragma unroll
-      for (int jt = 0; jt < TM; ++jt)
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          const int j = jt * 16 + kk + 4 * rr;
-          if (j < mf && pin) {
-            const long long e = base + (long long)j * g.n + pc;
-            double v = cm * acc[jt][rr];
-            if (!arr && z) v += cz * z[e];
-            ys[e] = v;
-            if (!arr && core) {
-              if (FL & RF_DOT_SELF) ds[jt][rr] += v * v;
-              if (FL & RF_DOT_W) dw[jt][rr] += v * wdot[e];
-            }
-          }
-        }
-    }
-  }
-  if (FL & (RF_DOT_SELF | RF_DOT_W)) {
-    // sum over the 16 lanes that share a row, then over the 4 waves in LDS
-#pragma unroll
-    for (int jt = 0; jt < TM; ++jt)
-#pragma unroll
-      for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-        for (int off = 1; off < 16; off <<= 1) {
-          ds[jt][rr] += __shfl_xor(ds[jt][rr], off, 64);
-          dw[jt][rr] += __shfl_xor(dw[jt][rr], off, 64);
-        }
-    if (jl == 0) {
-#pragma unroll
-      for (int jt = 0; jt < TM; ++jt)
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          red[wave][0][jt * 16 + kk + 4 * rr] = ds[jt][rr];
-          red[wave][1][jt * 16 + kk + 4 * rr] = dw[jt][rr];
-        }
-    }
-    __syncthreads();
-    double *out = dpart + ((long long)f * wpf + wg) * 2 * mp;
-    for (int e = threadIdx.x; e < 2 * MP; e += blockDim.x) {
-      const int k = e / MP, j = e % MP;
-      out[k * mp + j] = red[0][k][j] + red[1][k][j] + red[2][k][j] + red[3][k][j];
-    }
-  }
-}
-
-// out_k[B] = dV sum over the workgroup partials of band B (k = 0, 1; null skips).
-__global__ void __launch_bounds__(256) k_band_reduce(Geo g, OrbSet o, long long b0, long long nb,
-                                                     int wpf, const double *__restrict__ dpart,
-                                                     double *__restrict__ out0,
-                                                     double *__restrict__ out1) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nb) return;
-  const long long B = b0 + t;
-  const int f = o.band_frag[B];
-  const int i = (int)(B - o.moff[f]);
-  const int mp = o.m_pad;
-  double s0 = 0.0, s1 = 0.0;
-  for (int wg = 0; wg < wpf; ++wg) {
-    const double *pp = dpart + ((long long)f * wpf + wg) * 2 * mp;
-    s0 += pp[i];
-    s1 += pp[mp + i];
-  }
-  if (out0) out0[B] = g.dv * s0;
-  if (out1) out1[B] = g.dv * s1;
-}
-
-// Gram products, version 3.  Workgroup = (fragment, chunk of points).  Per step of
-// KT = 32 points the workgroup loads the operand rows cooperatively (16-byte
-// loads, one 32-byte run per thread and item) into LDS at a row stride of
-// KT + 2 doubles (the 16x4 MFMA operand reads are then bank-conflict free), and
-// each wave accumulates its share of the output tiles.  The second operand can
-// be built during the load:
-//   GM_PLAIN:  Y given (SYM when X == Y: upper tiles only, one operand).
-//   GM_DIR:    Y = P = beta P_prev - G, written over P_prev.
-//   GM_UPDATE: X = Psi' = c Psi + s P and W' = c W + s Q, both written in place;
-//              symmetric product of Psi'.
-enum { GM_PLAIN = 0, GM_DIR = 1, GM_UPDATE = 2 };
-constexpr int kGramKT = 32;
-constexpr int kGramLd = kGramKT + 2;
-
-template <int TM, int MODE, bool SYM, bool VEC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
-k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, double *x, double *a1, const double *a2,
-        double *a3, const double *a4, const double *__restrict__ c1,
-        const double *__restrict__ c2, double *__restrict__ part) {
-  constexpr int MP = 16 * TM;
-  constexpr int NTILE = SYM ? TM * (TM + 1) / 2 : TM * TM;
-  constexpr int PER_WAVE = (NTILE + 3) / 4;
-  __shared__ double Xs[MP * kGramLd];
-  __shared__ double Ys[SYM ? 1 : MP * kGramLd];
-  const int f = f0 + blockIdx.x / chunks;
-  const int c = blockIdx.x % chunks;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int mf = o.m[f];
-  const int mp = o.m_pad;
-  const long long base = o.moff[f] * (long long)g.n;
-  const int p_begin = c * kchunk;
-  const int p_end = min(p_begin + kchunk, g.n);
-  // tiles owned by this wave
-  int tI[PER_WAVE], tJ[PER_WAVE];
-  {
-    int k = 0, q = 0;
-#pragma unroll
-    for (int ti = 0; ti < TM; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < TM; ++tj) {
-        if (SYM && ti > tj) continue;
-        if (q % 4 == wave && k < PER_WAVE) {
-          tI[k] = ti;
-          tJ[k] = tj;
-          ++k;
-        }
-        ++q;
-      }
-#pragma unroll
-    for (; k < PER_WAVE; ++k) {
-      tI[k] = -1;
-      tJ[k] = -1;
-    }
-  }
-  dbl4 acc[PER_WAVE];
-#pragma unroll
-  for (int k = 0; k < PER_WAVE; ++k) acc[k] = dbl4{0.0, 0.0, 0.0, 0.0};
-  const double *Yl = SYM ? Xs : Ys;
-  for (int p0 = p_begin; p0 < p_end; p0 += kGramKT) {
-    __syncthreads();
-    for (int it = threadIdx.x; it < MP * (kGramKT / 4); it += blockDim.x) {
-      const int row = it / (kGramKT / 4);
-      const int pq = (it % (kGramKT / 4)) * 4;
-      const int p = p0 + pq;
-      double xv[4] = {0, 0, 0, 0}, yv[4] = {0, 0, 0, 0};
-      if (row < mf) {
-        const long long ro = base + (long long)row * g.n;
-        const bool full = VEC && (p + 3 < p_end);
-        double v1[4], v2[4], v3[4], v4[4];
-#define DCDFT_LOAD4(dst, src)                                                         \
-  if (full) {                                                                         \
-    const double2 t0 = *reinterpret_cast<const double2 *>((src) + ro + p);           \
-    const double2 t1 = *reinterpret_cast<const double2 *>((src) + ro + p + 2);       \
-    dst[0] = t0.x; dst[1] = t0.y; dst[2] = t1.x; dst[3] = t1.y;                       \
-  } else {                                                                            \
-    for (int t = 0; t < 4; ++t) dst[t] = (p + t < p_end) ? (src)[ro + p + t] : 0.0;   \
-  }
-#define DCDFT_STORE4(dstp, val)                                                       \
-  if (full) {                                                                         \
-    *reinterpret_cast<double2 *>((dstp) + ro + p) = double2{val[0], val[1]};          \
-    *reinterpret_cast<double2 *>((dstp) + ro + p + 2) = double2{val[2], val[3]};      \
-  } else {                                                                            \
-    for (int t = 0; t < 4; ++t)                                                       \
-      if (p + t < p_end) (dstp)[ro + p + t] = val[t];                                 \
-  }
-        if (MODE == GM_PLAIN) {
-          DCDFT_LOAD4(xv, x);
-          if (!SYM) { DCDFT_LOAD4(yv, a1); }
-        } else if (MODE == GM_DIR) {
-          DCDFT_LOAD4(xv, x);
-          DCDFT_LOAD4(v2, a2);
-          const double b = c1[o.moff[f] + row];
-          if (b != 0.0) {
-            DCDFT_LOAD4(v1, a1);
-            for (int t = 0; t < 4; ++t) yv[t] = b * v1[t] - v2[t];
-          } else {
-            for (int t = 0; t < 4; ++t) yv[t] = -v2[t];
-          }
-          DCDFT_STORE4(a1, yv);
-        } else {
-          DCDFT_LOAD4(v1, x);
-          DCDFT_LOAD4(v2, a1);
-          DCDFT_LOAD4(v3, a3);
-          DCDFT_LOAD4(v4, a4);
-          const double cs = c1[o.moff[f] + row], sn = c2[o.moff[f] + row];
-          for (int t = 0; t < 4; ++t) {
-            xv[t] = cs * v1[t] + sn * v2[t];
-            v3[t] = cs * v3[t] + sn * v4[t];
-          }
-          DCDFT_STORE4(x, xv);
-          DCDFT_STORE4(a3, v3);
-        }
-#undef DCDFT_LOAD4
-#undef DCDFT_STORE4
-        for (int t = 0; t < 4; ++t)
-          if (p + t >= p_end) xv[t] = yv[t] = 0.0;
-      }
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        Xs[row * kGramLd + pq + t] = xv[t];
-        if (!SYM) Ys[row * kGramLd + pq + t] = yv[t];
-      }
-    }
-    __syncthreads();
-    const int r = lane & 15, kk = lane >> 4;
-#pragma unroll
-    for (int t = 0; t < kGramKT / 4; ++t) {
-#pragma unroll
-      for (int k = 0; k < PER_WAVE; ++k) {
-        if (tI[k] < 0) continue;
-        const double av = Xs[(tI[k] * 16 + r) * kGramLd + 4 * t + kk];
-        const double bv = Yl[(tJ[k] * 16 + r) * kGramLd + 4 * t + kk];
-        acc[k] = mfma16x16x4(av, bv, acc[k]);
-      }
-      if ((t & 1) == 1) __builtin_amdgcn_sched_barrier(0);
-    }
-  }
-  double *out = part + ((long long)(f - f0) * chunks + c) * mp * mp;
-#pragma unroll
-  for (int k = 0; k < PER_WAVE; ++k) {
-    if (tI[k] < 0) continue;
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const int row = tI[k] * 16 + (lane >> 4) + 4 * rr;
-      const int col = tJ[k] * 16 + (lane & 15);
-      out[row * mp + col] = acc[k][rr];
-    }
-  }
 }
 
 // Cholesky S = L L^T in LDS and the rows of L^-1 (row-major, lower triangular).
@@ -685,58 +623,162 @@ __global__ void k_copy(long long b0, long long nb, const double *__restrict__ sr
   dst[b0 + i] = src[b0 + i];
 }
 
-template <int TM, int MODE, bool SYM>
-void gram3_t(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int kchunk, double *x,
-             double *a1, const double *a2, double *a3, const double *a4, const double *c1,
-             const double *c2, double *part, hipStream_t s) {
+
+template <typename T, int TM, int MODE, bool SYM>
+void gram3_t(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int kchunk, T *x, T *a1,
+             const T *a2, T *a3, const T *a4, const double *c1, const double *c2, double *part,
+             hipStream_t s) {
   const dim3 grid((f1 - f0) * chunks), block(256);
   if ((g.n % 4) == 0)
-    hipLaunchKernelGGL((k_gram3<TM, MODE, SYM, true>), grid, block, 0, s, g, o, f0, chunks, kchunk,
-                       x, a1, a2, a3, a4, c1, c2, part);
+    hipLaunchKernelGGL((k_gram3<T, TM, MODE, SYM, true>), grid, block, 0, s, g, o, f0, chunks,
+                       kchunk, x, a1, a2, a3, a4, c1, c2, part);
   else
-    hipLaunchKernelGGL((k_gram3<TM, MODE, SYM, false>), grid, block, 0, s, g, o, f0, chunks,
+    hipLaunchKernelGGL((k_gram3<T, TM, MODE, SYM, false>), grid, block, 0, s, g, o, f0, chunks,
                        kchunk, x, a1, a2, a3, a4, c1, c2, part);
 }
 
-template <int MODE, bool SYM>
-void gram3_tm(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, double *x, double *a1,
-              const double *a2, double *a3, const double *a4, const double *c1, const double *c2,
-              double *part, hipStream_t s) {
+template <typename T, int MODE, bool SYM>
+void gram3_tm(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, T *x, T *a1,
+              const T *a2, T *a3, const T *a4, const double *c1, const double *c2, double *part,
+              hipStream_t s) {
+  if (f1 <= f0) return;
   int kc = (g.n + chunks - 1) / chunks;
   kc = ((kc + kGramKT - 1) / kGramKT) * kGramKT;
   switch (o.tiles) {
-    case 1: gram3_t<1, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
-    case 2: gram3_t<2, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
-    case 3: gram3_t<3, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
-    case 4: gram3_t<4, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
-    default: gram3_t<5, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
+    case 1: gram3_t<T, 1, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
+    case 2: gram3_t<T, 2, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
+    case 3: gram3_t<T, 3, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
+    case 4: gram3_t<T, 4, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
+    default: gram3_t<T, 5, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
   }
 }
 
-constexpr int kRotTiles = 4;   // 16-point tiles per wave in k_rotate2
+constexpr int kRotTiles = 4;   // 16-point tiles per wave in k_rot_fused
 
-template <int TM>
-void rotate_t(const Geo &g, const OrbSet &o, int f0, int f1, const double *M, int trans,
-              const double *x, const double *z, double cz, double cm, double *y, hipStream_t s) {
-  const int per_wg = 4 * kRotTiles * 16;
-  const int wpf = (g.n + per_wg - 1) / per_wg;
-  hipLaunchKernelGGL((k_rotate2<TM, kRotTiles>), dim3((f1 - f0) * wpf), dim3(256), 0, s, g, o, f0,
-                     wpf, M, trans, x, z, cz, cm, y);
+template <typename T, int FL>
+void rot_fused_tm(const Geo &g, const OrbSet &o, int f0, int f1, int wpf, const double *M,
+                  int trans, const T *x, const T *z, double cz, double cm, T *y, const T *x2,
+                  T *y2, const T *wdot, double *dpart, hipStream_t s) {
+  if (f1 <= f0) return;
+  const dim3 grid((f1 - f0) * wpf), block(256);
+#define DCDFT_ROT(TMV)                                                                         \
+  hipLaunchKernelGGL((k_rot_fused<T, TMV, kRotTiles, FL>), grid, block, 0, s, g, o, f0, wpf, M, \
+                     trans, x, z, cz, cm, y, x2, y2, wdot, dpart)
+  switch (o.tiles) {
+    case 1: DCDFT_ROT(1); break;
+    case 2: DCDFT_ROT(2); break;
+    case 3: DCDFT_ROT(3); break;
+    case 4: DCDFT_ROT(4); break;
+    default: DCDFT_ROT(5); break;
+  }
+#undef DCDFT_ROT
+}
+
+void band_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int wpf, const double *dpart,
+                 double *out0, double *out1, hipStream_t s) {
+  const long long nb = o.nb(f0, f1);
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_band_reduce, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, g, o,
+                     o.b0(f0), nb, wpf, dpart, out0, out1);
 }
 
 }  // namespace
 
-void launch_gram(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, const double *x,
-                 const double *y, double *part, hipStream_t s) {
-  if (f1 <= f0) return;
-  double *xx = const_cast<double *>(x), *yy = const_cast<double *>(y);
-  if (x == y)
-    gram3_tm<GM_PLAIN, true>(g, o, f0, f1, chunks, xx, xx, nullptr, nullptr, nullptr, nullptr,
-                             nullptr, part, s);
-  else
-    gram3_tm<GM_PLAIN, false>(g, o, f0, f1, chunks, xx, yy, nullptr, nullptr, nullptr, nullptr,
-                              nullptr, part, s);
+int rot_wpf(const Geo &g) {
+  const int per_wg = 4 * kRotTiles * 16;
+  return (g.n + per_wg - 1) / per_wg;
 }
+
+template <typename T>
+void launch_gram(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, const T *x,
+                 const T *y, double *part, hipStream_t s) {
+  T *xx = const_cast<T *>(x), *yy = const_cast<T *>(y);
+  if (x == y)
+    gram3_tm<T, GM_PLAIN, true>(g, o, f0, f1, chunks, xx, xx, nullptr, nullptr, nullptr, nullptr,
+                                nullptr, part, s);
+  else
+    gram3_tm<T, GM_PLAIN, false>(g, o, f0, f1, chunks, xx, yy, nullptr, nullptr, nullptr, nullptr,
+                                 nullptr, part, s);
+}
+
+template <typename T>
+void launch_gram_direction(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
+                           const T *psi, const T *gres, T *p, const double *beta, double *part,
+                           hipStream_t s) {
+  gram3_tm<T, GM_DIR, false>(g, o, f0, f1, chunks, const_cast<T *>(psi), p, gres, nullptr,
+                             nullptr, beta, nullptr, part, s);
+}
+
+template <typename T>
+void launch_gram_update(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, T *psi,
+                        const T *p, T *w, const T *q, const double *cs, const double *sn,
+                        double *part, hipStream_t s) {
+  gram3_tm<T, GM_UPDATE, true>(g, o, f0, f1, chunks, psi, const_cast<T *>(p), nullptr, w, q, cs,
+                               sn, part, s);
+}
+
+template <typename T>
+void launch_rot_residual(const Geo &g, const OrbSet &o, int f0, int f1, const double *Hs,
+                         const T *psi, const T *w, T *gout, double *dpart, double *gamma,
+                         hipStream_t s) {
+  const int wpf = rot_wpf(g);
+  rot_fused_tm<T, RF_DOT_SELF>(g, o, f0, f1, wpf, Hs, 0, psi, w, 1.0, -1.0, gout, nullptr,
+                               nullptr, nullptr, dpart, s);
+  band_reduce(g, o, f0, f1, wpf, dpart, gamma, nullptr, s);
+}
+
+template <typename T>
+void launch_rot_project_out(const Geo &g, const OrbSet &o, int f0, int f1, const double *X,
+                            const T *psi, T *p, const T *w, double *dpart, double *nu,
+                            double *pw, hipStream_t s) {
+  const int wpf = rot_wpf(g);
+  rot_fused_tm<T, RF_DOT_SELF | RF_DOT_W>(g, o, f0, f1, wpf, X, 0, psi, p, 1.0, -1.0, p, nullptr,
+                                          nullptr, w, dpart, s);
+  band_reduce(g, o, f0, f1, wpf, dpart, nu, pw, s);
+}
+
+template <typename T>
+void launch_rot_cholesky(const Geo &g, const OrbSet &o, int f0, int f1, const double *Linv,
+                         T *psi, T *w, hipStream_t s) {
+  const int wpf = rot_wpf(g);
+  if (w)
+    rot_fused_tm<T, RF_TWO | RF_TRI>(g, o, f0, f1, wpf, Linv, 1, psi, nullptr, 0.0, 1.0, psi, w,
+                                     w, nullptr, nullptr, s);
+  else
+    rot_fused_tm<T, RF_TRI>(g, o, f0, f1, wpf, Linv, 1, psi, nullptr, 0.0, 1.0, psi, nullptr,
+                            nullptr, nullptr, nullptr, s);
+}
+
+template <typename T>
+void launch_rot_ritz(const Geo &g, const OrbSet &o, int f0, int f1, const double *U, T *psi,
+                     double *dpart, double *wcore, hipStream_t s) {
+  const int wpf = rot_wpf(g);
+  rot_fused_tm<T, RF_DOT_SELF | RF_CORE>(g, o, f0, f1, wpf, U, 0, psi, nullptr, 0.0, 1.0, psi,
+                                         nullptr, nullptr, nullptr, dpart, s);
+  band_reduce(g, o, f0, f1, wpf, dpart, wcore, nullptr, s);
+}
+
+#define DCDFT_INSTANTIATE(T)                                                                    \
+  template void launch_gram<T>(const Geo &, const OrbSet &, int, int, int, const T *, const T *, \
+                               double *, hipStream_t);                                        \
+  template void launch_gram_direction<T>(const Geo &, const OrbSet &, int, int, int, const T *,  \
+                                         const T *, T *, const double *, double *, hipStream_t); \
+  template void launch_gram_update<T>(const Geo &, const OrbSet &, int, int, int, T *, const T *, \
+                                      T *, const T *, const double *, const double *, double *,  \
+                                      hipStream_t);                                           \
+  template void launch_rot_residual<T>(const Geo &, const OrbSet &, int, int, const double *,    \
+                                       const T *, const T *, T *, double *, double *,            \
+                                       hipStream_t);                                          \
+  template void launch_rot_project_out<T>(const Geo &, const OrbSet &, int, int, const double *, \
+                                          const T *, T *, const T *, double *, double *,         \
+                                          double *, hipStream_t);                               \
+  template void launch_rot_cholesky<T>(const Geo &, const OrbSet &, int, int, const double *, T *, \
+                                       T *, hipStream_t);                                       \
+  template void launch_rot_ritz<T>(const Geo &, const OrbSet &, int, int, const double *, T *,   \
+                                   double *, double *, hipStream_t);
+DCDFT_INSTANTIATE(double)
+DCDFT_INSTANTIATE(float)
+#undef DCDFT_INSTANTIATE
 
 void launch_gram_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int sym,
                         const double *part, double *G, double *Gs, double *diag, hipStream_t s) {
@@ -746,19 +788,6 @@ void launch_gram_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int chunk
   hipLaunchKernelGGL(k_gram_reduce2, dim3(nb), dim3(256), 0, s, g, o, f0, f1 - f0, chunks, sym,
                      part, G, diag);
   if (Gs) hipLaunchKernelGGL(k_symmetrize, dim3(nb), dim3(256), 0, s, o, f0, f1 - f0, G, Gs);
-}
-
-void launch_rotate(const Geo &g, const OrbSet &o, int f0, int f1, const double *M, int trans,
-                   const double *x, const double *z, double cz, double cm, double *y,
-                   hipStream_t s) {
-  if (f1 <= f0) return;
-  switch (o.tiles) {
-    case 1: rotate_t<1>(g, o, f0, f1, M, trans, x, z, cz, cm, y, s); break;
-    case 2: rotate_t<2>(g, o, f0, f1, M, trans, x, z, cz, cm, y, s); break;
-    case 3: rotate_t<3>(g, o, f0, f1, M, trans, x, z, cz, cm, y, s); break;
-    case 4: rotate_t<4>(g, o, f0, f1, M, trans, x, z, cz, cm, y, s); break;
-    default: rotate_t<5>(g, o, f0, f1, M, trans, x, z, cz, cm, y, s); break;
-  }
 }
 
 void launch_cholinv(const OrbSet &o, int f0, int f1, const double *S, double *Linv, int *flags,
@@ -805,94 +834,6 @@ void launch_copy_band(const OrbSet &o, int f0, int f1, const double *src, double
                      src, dst);
 }
 
-
-namespace {
-template <int TM, int FL>
-void rot_fused_t(const Geo &g, const OrbSet &o, int f0, int f1, int wpf, const double *M,
-                 int trans, const double *x, const double *z, double cz, double cm, double *y,
-                 const double *x2, double *y2, const double *wdot, double *dpart, hipStream_t s) {
-  hipLaunchKernelGGL((k_rot_fused<TM, kRotTiles, FL>), dim3((f1 - f0) * wpf), dim3(256), 0, s, g,
-                     o, f0, wpf, M, trans, x, z, cz, cm, y, x2, y2, wdot, dpart);
-}
-
-template <int FL>
-void rot_fused_tm(const Geo &g, const OrbSet &o, int f0, int f1, int wpf, const double *M,
-                  int trans, const double *x, const double *z, double cz, double cm, double *y,
-                  const double *x2, double *y2, const double *wdot, double *dpart, hipStream_t s) {
-  switch (o.tiles) {
-    case 1: rot_fused_t<1, FL>(g, o, f0, f1, wpf, M, trans, x, z, cz, cm, y, x2, y2, wdot, dpart, s); break;
-    case 2: rot_fused_t<2, FL>(g, o, f0, f1, wpf, M, trans, x, z, cz, cm, y, x2, y2, wdot, dpart, s); break;
-    case 3: rot_fused_t<3, FL>(g, o, f0, f1, wpf, M, trans, x, z, cz, cm, y, x2, y2, wdot, dpart, s); break;
-    case 4: rot_fused_t<4, FL>(g, o, f0, f1, wpf, M, trans, x, z, cz, cm, y, x2, y2, wdot, dpart, s); break;
-    default: rot_fused_t<5, FL>(g, o, f0, f1, wpf, M, trans, x, z, cz, cm, y, x2, y2, wdot, dpart, s); break;
-  }
-}
-
-}  // namespace
-
-int rot_wpf(const Geo &g) {
-  const int per_wg = 4 * kRotTiles * 16;
-  return (g.n + per_wg - 1) / per_wg;
-}
-
-void launch_rot_residual(const Geo &g, const OrbSet &o, int f0, int f1, const double *Hs,
-                         const double *psi, const double *w, double *gout, double *dpart,
-                         double *gamma, hipStream_t s) {
-  if (f1 <= f0) return;
-  const int wpf = rot_wpf(g);
-  rot_fused_tm<RF_DOT_SELF>(g, o, f0, f1, wpf, Hs, 0, psi, w, 1.0, -1.0, gout, nullptr, nullptr,
-                            nullptr, dpart, s);
-  const long long nb = o.nb(f0, f1);
-  hipLaunchKernelGGL(k_band_reduce, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, g, o,
-                     o.b0(f0), nb, wpf, dpart, gamma, nullptr);
-}
-
-void launch_rot_project_out(const Geo &g, const OrbSet &o, int f0, int f1, const double *X,
-                            const double *psi, double *p, const double *w, double *dpart,
-                            double *nu, double *pw, hipStream_t s) {
-  if (f1 <= f0) return;
-  const int wpf = rot_wpf(g);
-  rot_fused_tm<RF_DOT_SELF | RF_DOT_W>(g, o, f0, f1, wpf, X, 0, psi, p, 1.0, -1.0, p, nullptr,
-                                       nullptr, w, dpart, s);
-  const long long nb = o.nb(f0, f1);
-  hipLaunchKernelGGL(k_band_reduce, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, g, o,
-                     o.b0(f0), nb, wpf, dpart, nu, pw);
-}
-
-void launch_rot_cholesky(const Geo &g, const OrbSet &o, int f0, int f1, const double *Linv,
-                         double *psi, double *w, hipStream_t s) {
-  if (f1 <= f0) return;
-  const int wpf = rot_wpf(g);
-  rot_fused_tm<RF_TWO | RF_TRI>(g, o, f0, f1, wpf, Linv, 1, psi, nullptr, 0.0, 1.0, psi, w, w,
-                                nullptr, nullptr, s);
-}
-
-void launch_rot_ritz(const Geo &g, const OrbSet &o, int f0, int f1, const double *U, double *psi,
-                     double *dpart, double *wcore, hipStream_t s) {
-  if (f1 <= f0) return;
-  const int wpf = rot_wpf(g);
-  rot_fused_tm<RF_DOT_SELF | RF_CORE>(g, o, f0, f1, wpf, U, 0, psi, nullptr, 0.0, 1.0, psi,
-                                      nullptr, nullptr, nullptr, dpart, s);
-  const long long nb = o.nb(f0, f1);
-  hipLaunchKernelGGL(k_band_reduce, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, g, o,
-                     o.b0(f0), nb, wpf, dpart, wcore, nullptr);
-}
-
-void launch_gram_direction(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
-                           const double *psi, const double *gres, double *p, const double *beta,
-                           double *part, hipStream_t s) {
-  if (f1 <= f0) return;
-  gram3_tm<GM_DIR, false>(g, o, f0, f1, chunks, const_cast<double *>(psi), p, gres, nullptr,
-                          nullptr, beta, nullptr, part, s);
-}
-
-void launch_gram_update(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, double *psi,
-                        const double *p, double *w, const double *q, const double *cs,
-                        const double *sn, double *part, hipStream_t s) {
-  if (f1 <= f0) return;
-  gram3_tm<GM_UPDATE, true>(g, o, f0, f1, chunks, psi, const_cast<double *>(p), nullptr, w, q, cs,
-                            sn, part, s);
-}
 
 void launch_kb_quad(const OrbSet &o, int f0, int f1, const KBTables &kb, const double *C,
                     double *cp, hipStream_t s) {
