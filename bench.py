@@ -25,6 +25,7 @@ if ROOT not in sys.path:
 METRIC = "fragment H·ψ GB/s + SCF iters/sec (all fragments), mixed+batched vs FP64"
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3
 
 
 def workload_config(k: int):
@@ -68,6 +69,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2, help="workload number (default 2)")
     ap.add_argument("--batched", type=int, default=1)
+    ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed",
+                    help="mixed: FP32 orbital arrays/stencil/matrix cores with FP64 "
+                         "reductions, Cholesky, eigensolve and Fermi level")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain per-fragment FP64 comparison run")
@@ -83,7 +87,9 @@ def main() -> int:
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         return 1
-    from paper_2606_21125_amd import (DCDFT, KERNEL_GRAM, KERNEL_HLOC, KERNEL_ROTATE)
+    from paper_2606_21125_amd import (DCDFT, KERNEL_GRAM, KERNEL_HLOC, KERNEL_ROTATE, PREC_FP64,
+                                      PREC_MIXED)
+    prec = PREC_MIXED if args.precision == "mixed" else PREC_FP64
 
     if args.copy_probe_mb > 0:
         n = int(args.copy_probe_mb * 1e6) // 8
@@ -98,7 +104,7 @@ def main() -> int:
     cfg = workload_config(args.config)
     print(f"[bench] setup {cfg.name}: {cfg.system.n_atoms} atoms, grid {cfg.n_grid}, "
           f"{cfg.n_fragments} fragments of {cfg.fragment_shape}", file=sys.stderr, flush=True)
-    d = DCDFT.from_config(cfg, batched=args.batched)
+    d = DCDFT.from_config(cfg, batched=args.batched, precision=prec)
     for _ in range(args.warmup):
         d.dcdft_scf_step()
     torch.cuda.synchronize()
@@ -123,6 +129,7 @@ def main() -> int:
     ms_per_step = 1000.0 * elapsed / args.steps
     value = args.steps / elapsed
 
+    mfma_peak = FP32_MFMA_PEAK_TFLOPS if prec != PREC_FP64 else FP64_MFMA_PEAK_TFLOPS
     h = kt["hloc"]
     h_gbs = h["bytes"] / (h["ms"] * 1e-3) / 1e9 if h["ms"] > 0 else 0.0
     g = kt["gram"]
@@ -131,15 +138,15 @@ def main() -> int:
     r_gbs = r["bytes"] / (r["ms"] * 1e-3) / 1e9 if r["ms"] > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(h_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(h_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_hloc (fragment H_loc psi, FP64)",
+                "kernel": f"k_hloc (fragment H_loc psi, {'FP32' if prec != PREC_FP64 else 'FP64'})",
                 "avg_launch_ms": round(h["ms"] / max(1, h["launches"]), 4),
                 "bytes_per_launch": h["bytes"] / max(1, h["launches"]),
                 "measured": f"HIP events around every launch over {n_timed} eager steps "
                             f"following the timed region"}
     extra = {
         "hpsi_gbs": round(h_gbs, 1),
-        "gram": {"bound": "mfma", "achieved": round(g_tf, 2), "peak": FP64_MFMA_PEAK_TFLOPS,
-                 "unit": "TFLOP/s", "frac": round(g_tf / FP64_MFMA_PEAK_TFLOPS, 4),
+        "gram": {"bound": "mfma", "achieved": round(g_tf, 2), "peak": mfma_peak,
+                 "unit": "TFLOP/s", "frac": round(g_tf / mfma_peak, 4),
                  "avg_launch_ms": round(g["ms"] / max(1, g["launches"]), 4)},
         "rotate": {"bound": "hbm", "achieved": round(r_gbs, 1), "peak": HBM_PEAK_GBS,
                    "unit": "GB/s", "frac": round(r_gbs / HBM_PEAK_GBS, 4),
@@ -147,22 +154,27 @@ def main() -> int:
         "kernel_ms_per_step": {k: round(v["ms"] / n_timed, 3) for k, v in kt.items()},
         "last_step": {k: info[k] for k in ("mu", "e_total", "residual_out_in", "charge")},
     }
-    # plain FP64 path: one launch sequence per fragment, no graph
-    plain = None
+    # comparison paths on the same workload: batched FP64 (graph) and plain FP64
+    # (one launch sequence per fragment, no graph)
+    comparisons = {}
     if args.batched and not args.no_compare:
-        print("[bench] plain per-fragment FP64 path", file=sys.stderr, flush=True)
-        d2 = DCDFT.from_config(cfg, batched=0)
-        d2.dcdft_scf_step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(2):
+        variants = [("plain_fp64_per_fragment", 0, PREC_FP64, 2)]
+        if prec != PREC_FP64:
+            variants.insert(0, ("batched_fp64", 1, PREC_FP64, max(3, args.steps // 2)))
+        for name, batched, pr, k in variants:
+            print(f"[bench] comparison {name}", file=sys.stderr, flush=True)
+            d2 = DCDFT.from_config(cfg, batched=batched, precision=pr)
             d2.dcdft_scf_step()
-        torch.cuda.synchronize()
-        t_plain = (time.perf_counter() - t0) / 2
-        d2.close()
-        plain = {"value": round(1.0 / t_plain, 3), "unit": "SCF iter/s",
-                 "ms_per_step": round(1000.0 * t_plain, 3),
-                 "speedup_of_value": round(value * t_plain, 3)}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(k):
+                d2.dcdft_scf_step()
+            torch.cuda.synchronize()
+            tk = (time.perf_counter() - t0) / k
+            d2.close()
+            comparisons[name] = {"value": round(1.0 / tk, 3), "unit": "SCF iter/s",
+                                 "ms_per_step": round(1000.0 * tk, 3), "steps": k,
+                                 "speedup_of_value": round(value * tk, 3)}
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
@@ -170,7 +182,8 @@ def main() -> int:
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "SCF iter/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32/f64" if prec != PREC_FP64 else "f64",
         "data": "synthetic",
         "config": {"workload": (f"{cfg.name}: {cfg.system.n_atoms}-atom a-Si-like cell, grid "
                                 f"{'x'.join(map(str, cfg.n_grid))}, "
@@ -179,8 +192,8 @@ def main() -> int:
                                 f"{int(cfg.nstate_frag[0])} orbitals each, "
                                 f"{cfg.cg_sweeps} CG sweeps per SCF iteration"),
                    "n_fragments": cfg.n_fragments, "batched": bool(args.batched),
-                   "precision": "fp64"},
-        "roofline": roofline, "cpu_baseline": cpu, "plain_fp64_per_fragment": plain, **extra,
+                   "precision": args.precision},
+        "roofline": roofline, "cpu_baseline": cpu, "comparisons": comparisons, **extra,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -176,13 +176,16 @@ dcdft_status dcdft_apply_h(dcdft_ctx *c, int32_t frag, const void *psi, void *hp
 /* Band-energy functional E = sum_i f_i <psi_i|H^alpha|psi_i> (inner product with dV)
  * and its gradient, recomputing H psi:
  *   grad_psi[i][l] = 2 f_i dV (H psi_i)(l),   grad_v[l] = dV sum_i f_i psi_i(l)^2,
- * grad_v being the derivative with respect to V_eff (Eq. (4): dV times the
- * fragment density when f carries 2 x occupation).  psi, grad_psi: device [m][n]
- * (double or float by prec); f: device double [m]; grad_v: device [n] (same type
- * as psi); energy: device double[1].  Any of grad_psi, grad_v, energy may be NULL. */
+ * grad_v being the derivative with respect to the local potential V_eff (with f
+ * carrying 2 x occupation it is dV times the fragment density of Eq. (4)).
+ * psi, grad_psi: device [m][n], double (prec 0) or float (prec 1); f: device
+ * double [m]; veff: device double [n] used as V_eff of the fragment, or NULL for
+ * the fragment's V_eff of the last step; grad_v: device double [n]; energy:
+ * device double [1].  Any of energy, grad_psi, grad_v may be NULL.  The call
+ * allocates device scratch for H psi. */
 dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, const double *f,
-                               int32_t m, int32_t prec, double *energy, void *grad_psi,
-                               void *grad_v);
+                               int32_t m, int32_t prec, const double *veff, double *energy,
+                               void *grad_psi, double *grad_v);
 
 /* Device-time accounting of kernel families (for roofline reports).  While
  * enabled, steps run eagerly (not from the step graph) and every launch of the

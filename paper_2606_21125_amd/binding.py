@@ -103,7 +103,7 @@ def load_library(path: Optional[str] = None):
         "dcdft_apply_h": ([vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32],
                           ctypes.c_int),
         "dcdft_band_energy": ([vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32, vp,
-                               vp, vp], ctypes.c_int),
+                               vp, vp, vp], ctypes.c_int),
         "dcdft_kernel_timing": ([vp, ctypes.c_int32], ctypes.c_int),
         "dcdft_kernel_time": ([vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), pd, pd, pd],
                               ctypes.c_int),
@@ -313,9 +313,13 @@ class DCDFT:
                                            ctypes.byref(by), ctypes.byref(fl)), self.ctx)
         return dict(launches=n.value, ms=ms.value, bytes=by.value, flops=fl.value)
 
-    def dcdft_band_energy(self, frag: int, psi, f, energy=None, grad_psi=None, grad_v=None,
-                          prec: int = PREC_FP64) -> None:
+    def dcdft_band_energy(self, frag: int, psi, f, veff=None, energy=None, grad_psi=None,
+                          grad_v=None, prec: int = PREC_FP64) -> None:
+        """psi: device (m, n) double/float; f: device (m,) double; veff: device (n,)
+        double or None; outputs are device tensors (energy (1,), grad_psi like psi,
+        grad_v (n,) double)."""
         ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
         _check(self._lib.dcdft_band_energy(self.ctx, frag, ctypes.c_void_p(psi.data_ptr()),
                                            ctypes.c_void_p(f.data_ptr()), psi.shape[0], prec,
-                                           ptr(energy), ptr(grad_psi), ptr(grad_v)), self.ctx)
+                                           ptr(veff), ptr(energy), ptr(grad_psi), ptr(grad_v)),
+               self.ctx)

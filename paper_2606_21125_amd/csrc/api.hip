@@ -1168,8 +1168,11 @@ void free_ext(ExtLayout &L) {
   if (L.band_frag) hipFree(L.band_frag);
 }
 
+// H psi for an external block of m vectors of fragment frag, in chunks of at most
+// m_pad vectors; veff_ext (device, n doubles) replaces the fragment's V_eff if given.
 template <typename T>
-dcdft_status apply_h_ext(dcdft_ctx *c, int frag, const T *psi, T *hpsi, int m) {
+dcdft_status apply_h_ext(dcdft_ctx *c, int frag, const T *psi, T *hpsi, int m,
+                         const double *veff_ext = nullptr) {
   const Geo &g = c->geo;
   for (int i0 = 0; i0 < m; i0 += c->m_pad) {
     const int mm = std::min(c->m_pad, m - i0);
@@ -1189,7 +1192,10 @@ dcdft_status apply_h_ext(dcdft_ctx *c, int frag, const T *psi, T *hpsi, int m) {
     KBTables kb = c->kb();
     const T *x = psi + (long long)i0 * g.n;
     T *y = hpsi + (long long)i0 * g.n;
-    launch_hloc<T>(g, o, frag, frag + 1, c->d_veff, x, y, c->stream);
+    if (veff_ext)
+      launch_hloc<T>(g, o, frag, frag + 1, veff_ext, x, y, c->stream, nullptr, frag);
+    else
+      launch_hloc<T>(g, o, frag, frag + 1, c->d_veff, x, y, c->stream);
     launch_kb_project<T>(g, o, kb, frag, frag + 1, x, c->d_C, c->d_cpart, c->stream);
     launch_kb_apply<T>(g, o, kb, frag, frag + 1, c->d_C, y, c->stream);
     hipError_t e = hipStreamSynchronize(c->stream);
@@ -1201,7 +1207,7 @@ dcdft_status apply_h_ext(dcdft_ctx *c, int frag, const T *psi, T *hpsi, int m) {
 
 template <typename T>
 dcdft_status band_energy_t(dcdft_ctx *c, int frag, const T *psi, const double *f, int m,
-                           double *energy, T *grad_psi, T *grad_v) {
+                           const double *veff, double *energy, T *grad_psi, double *grad_v) {
   const Geo &g = c->geo;
   T *hp = nullptr;
   double *eb = nullptr;
@@ -1210,7 +1216,7 @@ dcdft_status band_energy_t(dcdft_ctx *c, int frag, const T *psi, const double *f
     hipFree(hp);
     return set_err(c, DCDFT_ERR_OOM, "scratch allocation failed");
   }
-  dcdft_status st = apply_h_ext<T>(c, frag, psi, hp, m);
+  dcdft_status st = apply_h_ext<T>(c, frag, psi, hp, m, veff);
   if (st == DCDFT_OK) {
     launch_band_energy<T>(g, m, psi, hp, f, eb, energy, grad_psi, grad_v, c->stream);
     hipError_t e = hipStreamSynchronize(c->stream);
@@ -1240,18 +1246,18 @@ dcdft_status dcdft_apply_h(dcdft_ctx *c, int32_t frag, const void *psi, void *hp
 }
 
 dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, const double *f,
-                               int32_t m, int32_t prec, double *energy, void *grad_psi,
-                               void *grad_v) {
+                               int32_t m, int32_t prec, const double *veff, double *energy,
+                               void *grad_psi, double *grad_v) {
   if (!c || !psi || !f) return set_err(c, DCDFT_ERR_ARG, "NULL argument");
   if (frag < 0 || frag >= c->nF) return set_err(c, DCDFT_ERR_ARG, fmt("fragment %d out of range", frag));
   if (m < 1) return set_err(c, DCDFT_ERR_ARG, "m < 1");
   if (prec != DCDFT_PREC_FP64 && prec != DCDFT_PREC_MIXED)
     return set_err(c, DCDFT_ERR_ARG, "prec must be 0 (double) or 1 (float)");
   if (prec == DCDFT_PREC_MIXED)
-    return band_energy_t<float>(c, frag, (const float *)psi, f, m, energy, (float *)grad_psi,
-                                (float *)grad_v);
-  return band_energy_t<double>(c, frag, (const double *)psi, f, m, energy, (double *)grad_psi,
-                               (double *)grad_v);
+    return band_energy_t<float>(c, frag, (const float *)psi, f, m, veff, energy,
+                                (float *)grad_psi, grad_v);
+  return band_energy_t<double>(c, frag, (const double *)psi, f, m, veff, energy,
+                               (double *)grad_psi, grad_v);
 }
 
 }  // extern "C"

@@ -196,7 +196,7 @@ namespace dcdft {
 // null) receives dV <x_B, y_B> per band.
 template <typename T>
 void launch_hloc(const Geo &g, const OrbSet &o, int f0, int f1, const double *veff, const T *x,
-                 T *y, hipStream_t s, double *dot = nullptr);
+                 T *y, hipStream_t s, double *dot = nullptr, int vbase = 0);
 // C[f][a][i] = dV sum beta_a(l) X_i(l) (region partials in part)
 template <typename T>
 void launch_kb_project(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1,
@@ -210,7 +210,7 @@ void launch_init_orbitals(const Geo &g, const OrbSet &o, uint64_t seed, T *psi, 
 // band energy: eb[B] = f_B <psi_B|H psi_B>, energy = sum eb, grads
 template <typename T>
 void launch_band_energy(const Geo &g, int nb, const T *psi, const T *hpsi, const double *f,
-                        double *eb, double *energy, T *grad_psi, T *grad_v, hipStream_t s);
+                        double *eb, double *energy, T *grad_psi, double *grad_v, hipStream_t s);
 
 // Gram partials of X^T Y (row form G_ij = sum_l X_i(l) Y_j(l)); X == Y is symmetric
 template <typename T>

@@ -11,10 +11,12 @@ namespace {
 
 // One workgroup per orbital; thread (x, y) of the plane marches along z with a
 // nine-plane register window; x/y neighbours come from the current plane in LDS.
-// dot (if not null) receives dV <x, y> for the orbital.
+// V_eff of fragment f starts at veff + (f - vbase) n.  dot (if not null)
+// receives dV <x, y> for the orbital.
 template <typename T>
 __global__ void __launch_bounds__(1024) k_hloc(Geo g, const int *__restrict__ band_frag,
-                                               long long b0, const double *__restrict__ veff,
+                                               long long b0, int vbase,
+                                               const double *__restrict__ veff,
                                                const T *__restrict__ x, T *__restrict__ y,
                                                double *__restrict__ dot) {
   extern __shared__ char lds_raw[];
@@ -29,7 +31,7 @@ __global__ void __launch_bounds__(1024) k_hloc(Geo g, const int *__restrict__ ba
   const int ix = t % nx, iy = t / nx;
   const T *xb = x + B * (long long)g.n;
   T *yb = y + B * (long long)g.n;
-  const double *vb = veff + (long long)f * g.n;
+  const double *vb = veff + (long long)(f - vbase) * g.n;
   const T c0 = (T)g.kc[0];
   T ax[4], ay[4], az[4];
   int ox[8], oy[8];
@@ -283,7 +285,7 @@ __global__ void __launch_bounds__(64) k_band_energy_sum(int nb, const double *__
 template <typename T>
 __global__ void __launch_bounds__(256) k_grad_v(Geo g, int nb, const T *__restrict__ psi,
                                                 const double *__restrict__ f,
-                                                T *__restrict__ grad_v) {
+                                                double *__restrict__ grad_v) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= g.n) return;
   double acc = 0.0;
@@ -291,7 +293,7 @@ __global__ void __launch_bounds__(256) k_grad_v(Geo g, int nb, const T *__restri
     const double v = (double)psi[(long long)i * g.n + l];
     acc += f[i] * v * v;
   }
-  grad_v[l] = (T)(g.dv * acc);
+  grad_v[l] = g.dv * acc;
 }
 
 inline int grid_for(long long n, int block) {
@@ -344,12 +346,12 @@ void kb_dispatch(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int 
 
 template <typename T>
 void launch_hloc(const Geo &g, const OrbSet &o, int f0, int f1, const double *veff, const T *x,
-                 T *y, hipStream_t s, double *dot) {
+                 T *y, hipStream_t s, double *dot, int vbase) {
   const long long nb = o.nb(f0, f1);
   if (nb <= 0) return;
   const int plane = g.nl[0] * g.nl[1];
   hipLaunchKernelGGL(k_hloc<T>, dim3((unsigned)nb), dim3(plane), 2 * plane * sizeof(T), s, g,
-                     o.band_frag, o.b0(f0), veff, x, y, dot);
+                     o.band_frag, o.b0(f0), vbase, veff, x, y, dot);
 }
 
 template <typename T>
@@ -373,7 +375,7 @@ void launch_init_orbitals(const Geo &g, const OrbSet &o, uint64_t seed, T *psi, 
 
 template <typename T>
 void launch_band_energy(const Geo &g, int nb, const T *psi, const T *hpsi, const double *f,
-                        double *eb, double *energy, T *grad_psi, T *grad_v, hipStream_t s) {
+                        double *eb, double *energy, T *grad_psi, double *grad_v, hipStream_t s) {
   if (nb <= 0) return;
   hipLaunchKernelGGL(k_band_energy_terms<T>, dim3(nb), dim3(256), 0, s, g, psi, hpsi, f, eb,
                      grad_psi);
@@ -385,7 +387,7 @@ void launch_band_energy(const Geo &g, int nb, const T *psi, const T *hpsi, const
 
 #define DCDFT_INSTANTIATE(T)                                                                   \
   template void launch_hloc<T>(const Geo &, const OrbSet &, int, int, const double *,        \
-                               const T *, T *, hipStream_t, double *);                       \
+                               const T *, T *, hipStream_t, double *, int);                  \
   template void launch_kb_project<T>(const Geo &, const OrbSet &, const KBTables &, int, int, \
                                      const T *, double *, double *, hipStream_t);            \
   template void launch_kb_apply<T>(const Geo &, const OrbSet &, const KBTables &, int, int,   \
@@ -393,7 +395,7 @@ void launch_band_energy(const Geo &g, int nb, const T *psi, const T *hpsi, const
   template void launch_init_orbitals<T>(const Geo &, const OrbSet &, uint64_t, T *,           \
                                         hipStream_t);                                        \
   template void launch_band_energy<T>(const Geo &, int, const T *, const T *, const double *, \
-                                      double *, double *, T *, T *, hipStream_t);
+                                      double *, double *, T *, double *, hipStream_t);
 DCDFT_INSTANTIATE(double)
 DCDFT_INSTANTIATE(float)
 #undef DCDFT_INSTANTIATE
