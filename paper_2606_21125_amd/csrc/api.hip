@@ -418,6 +418,21 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
   // ---- global KB projectors ----
   std::vector<Support> sup(p->n_atoms);
   std::vector<double> Eatom(p->n_atoms);
+  // near_axis[a][axis d, fragment index along d]: some support index of atom a
+  // along d falls inside that fragment box's window along d
+  const int fsum = g.F[0] + g.F[1] + g.F[2];
+  std::vector<char> near_axis((size_t)p->n_atoms * fsum, 0);
+  auto mark_near = [&](int a, int d, const std::vector<int> &idx) {
+    const int off = d == 0 ? 0 : (d == 1 ? g.F[0] : g.F[0] + g.F[1]);
+    for (int fd = 0; fd < g.F[d]; ++fd) {
+      const int o = fd * g.nc[d] - g.b[d];
+      for (int i : idx)
+        if (((i - o) % g.N[d] + g.N[d]) % g.N[d] < g.nl[d]) {
+          near_axis[(size_t)a * fsum + off + fd] = 1;
+          break;
+        }
+    }
+  };
   for (int a = 0; a < p->n_atoms; ++a) {
     const dcdft_species &sp = p->species[p->atom_species[a]];
     Eatom[a] = sp.kb_energy;
@@ -426,6 +441,9 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
     axis_ball(pos[0], R, g.h[0], g.N[0], p->cell[0], ix, dx);
     axis_ball(pos[1], R, g.h[1], g.N[1], p->cell[1], iy, dy);
     axis_ball(pos[2], R, g.h[2], g.N[2], p->cell[2], iz, dz);
+    mark_near(a, 0, ix);
+    mark_near(a, 1, iy);
+    mark_near(a, 2, iz);
     const double inv2s2 = 1.0 / (2.0 * sp.kb_sigma * sp.kb_sigma);
     double nrm = 0.0;
     for (size_t k = 0; k < iz.size(); ++k)
@@ -455,6 +473,11 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
     const int ax = f % g.F[0], ay = (f / g.F[0]) % g.F[1], az = f / (g.F[0] * g.F[1]);
     const int org[3] = {ax * g.nc[0] - g.b[0], ay * g.nc[1] - g.b[1], az * g.nc[2] - g.b[2]};
     for (int a = 0; a < p->n_atoms; ++a) {
+      // skip pairs whose support misses the box along some axis (exact: the
+      // support lies inside the product of its three axis index sets)
+      if (!near_axis[(size_t)a * fsum + ax] || !near_axis[(size_t)a * fsum + g.F[0] + ay] ||
+          !near_axis[(size_t)a * fsum + g.F[0] + g.F[1] + az])
+        continue;
       const long long e0 = (long long)atom_l.size();
       for (size_t e = 0; e < sup[a].g.size(); ++e) {
         const long long gg = sup[a].g[e];
