@@ -72,6 +72,10 @@ def main() -> int:
     ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed",
                     help="mixed: FP32 orbital arrays/stencil/matrix cores with FP64 "
                          "reductions, Cholesky, eigensolve and Fermi level")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes instead of timing the candidates")
+    ap.add_argument("--tune-cache", default=None,
+                    help="text file of earlier autotuner choices (read, then appended)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain per-fragment FP64 comparison run")
@@ -105,6 +109,10 @@ def main() -> int:
     print(f"[bench] setup {cfg.name}: {cfg.system.n_atoms} atoms, grid {cfg.n_grid}, "
           f"{cfg.n_fragments} fragments of {cfg.fragment_shape}", file=sys.stderr, flush=True)
     d = DCDFT.from_config(cfg, batched=args.batched, precision=prec)
+    tune = None
+    if not args.no_autotune:
+        tune = d.dcdft_autotune(args.tune_cache)
+        print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         d.dcdft_scf_step()
     torch.cuda.synchronize()
@@ -152,6 +160,7 @@ def main() -> int:
                    "unit": "GB/s", "frac": round(r_gbs / HBM_PEAK_GBS, 4),
                    "avg_launch_ms": round(r["ms"] / max(1, r["launches"]), 4)},
         "kernel_ms_per_step": {k: round(v["ms"] / n_timed, 3) for k, v in kt.items()},
+        "launch_shapes": tune,
         "last_step": {k: info[k] for k in ("mu", "e_total", "residual_out_in", "charge")},
     }
     # comparison paths on the same workload: batched FP64 (graph) and plain FP64
@@ -164,6 +173,8 @@ def main() -> int:
         for name, batched, pr, k in variants:
             print(f"[bench] comparison {name}", file=sys.stderr, flush=True)
             d2 = DCDFT.from_config(cfg, batched=batched, precision=pr)
+            if batched and not args.no_autotune:
+                d2.dcdft_autotune(args.tune_cache)
             d2.dcdft_scf_step()
             torch.cuda.synchronize()
             t0 = time.perf_counter()

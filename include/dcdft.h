@@ -204,6 +204,47 @@ dcdft_status dcdft_kernel_timing(dcdft_ctx *c, int32_t enable);
 dcdft_status dcdft_kernel_time(dcdft_ctx *c, int32_t kernel, int64_t *launches, double *ms,
                                double *bytes, double *flops);
 
+/* Launch-shape autotuner for the batched step.  Times, on this context's own
+ * orbital arrays and with HIP events on its stream, the candidate shapes of
+ *   - the stencil kernel H_loc X (DCDFT_HLOC_*: one plane in flight, or a
+ *     haloed LDS plane with 2-, 3- or 4-plane load chunks, or 2-plane chunks
+ *     with the periodic end planes held in registers),
+ *   - the rotation kernels (2, 4 or 8 sixteen-point tiles per wave),
+ *   - the Gram products (the point range of a fragment cut into G chunks,
+ *     G among half, one, two and four times the default),
+ * and keeps the fastest of each for every later step (the step graph is
+ * re-captured).  Stencil variants give bitwise-identical results; the tile
+ * and chunk counts change only the summation order of FP64 partial sums.
+ * Call between steps: it overwrites work arrays, never the SCF state.
+ * cache_path (may be NULL): a text file of earlier choices, one line per
+ * device/shape key; a matching line is applied without timing, otherwise the
+ * new choice is appended (an unwritable file gives DCDFT_ERR_ARG after the
+ * choice has been applied).  out (may be NULL) receives the choice and the
+ * measured milliseconds per launch (-1: candidate not applicable or not
+ * timed). */
+enum { DCDFT_HLOC_PLANE = 0, DCDFT_HLOC_HALO_PD2 = 1, DCDFT_HLOC_HALO_PD3 = 2,
+       DCDFT_HLOC_HALO_PD4 = 3, DCDFT_HLOC_HALO_PD2_ENDS = 4, DCDFT_HLOC_COUNT = 5 };
+typedef struct {
+  int32_t hloc_variant;  /* DCDFT_HLOC_* */
+  int32_t rot_tiles;     /* 2, 4 or 8 */
+  int32_t gram_chunks;
+  int32_t from_cache;    /* 1 if the choice came from cache_path */
+  double ms_hloc[DCDFT_HLOC_COUNT];
+  double ms_rot[3];      /* tiles 2, 4, 8 */
+  int32_t gram_candidates[4];
+  double ms_gram[4];
+} dcdft_tune_info;
+dcdft_status dcdft_autotune(dcdft_ctx *c, const char *cache_path, dcdft_tune_info *out);
+
+/* Read or set the launch shapes directly.  set: hloc_variant DCDFT_HLOC_* (the
+ * halo variants need a fragment box of at least 4 x 4 x 8 points), rot_tiles
+ * 2, 4 or 8, gram_chunks 1..gram_chunks_max (as get reports it); anything else
+ * is DCDFT_ERR_ARG and changes nothing.  get: any pointer may be NULL. */
+dcdft_status dcdft_get_launch(const dcdft_ctx *c, int32_t *hloc_variant, int32_t *rot_tiles,
+                              int32_t *gram_chunks, int32_t *gram_chunks_max);
+dcdft_status dcdft_set_launch(dcdft_ctx *c, int32_t hloc_variant, int32_t rot_tiles,
+                              int32_t gram_chunks);
+
 /* Release everything owned by c.  NULL-safe. */
 void dcdft_destroy(dcdft_ctx *c);
 

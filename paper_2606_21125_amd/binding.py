@@ -29,10 +29,13 @@ EXPORTED = [
     "dcdft_setup", "dcdft_scf_step", "dcdft_density", "dcdft_density_device",
     "dcdft_eigenvalues", "dcdft_fragment_info", "dcdft_get_field", "dcdft_get_fragment_field",
     "dcdft_get_orbitals", "dcdft_set_orbitals", "dcdft_set_density", "dcdft_apply_h",
-    "dcdft_band_energy", "dcdft_kernel_timing", "dcdft_kernel_time", "dcdft_destroy",
+    "dcdft_band_energy", "dcdft_kernel_timing", "dcdft_kernel_time", "dcdft_autotune",
+    "dcdft_get_launch", "dcdft_set_launch",
+    "dcdft_destroy",
     "dcdft_status_string", "dcdft_last_error",
 ]
 KERNEL_HLOC, KERNEL_GRAM, KERNEL_ROTATE = 0, 1, 2
+HLOC_VARIANTS = ("plane", "halo_pd2", "halo_pd3", "halo_pd4", "halo_pd2_ends")
 
 
 class DcdftSpecies(ctypes.Structure):
@@ -64,6 +67,21 @@ class DcdftScfInfo(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class DcdftTuneInfo(ctypes.Structure):
+    _fields_ = [("hloc_variant", ctypes.c_int32), ("rot_tiles", ctypes.c_int32),
+                ("gram_chunks", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("ms_hloc", ctypes.c_double * 5), ("ms_rot", ctypes.c_double * 3),
+                ("gram_candidates", ctypes.c_int32 * 4), ("ms_gram", ctypes.c_double * 4)]
+
+    def as_dict(self) -> dict:
+        return {"hloc_variant": HLOC_VARIANTS[self.hloc_variant], "rot_tiles": self.rot_tiles,
+                "gram_chunks": self.gram_chunks, "from_cache": bool(self.from_cache),
+                "ms_hloc": dict(zip(HLOC_VARIANTS, (round(v, 4) for v in self.ms_hloc))),
+                "ms_rot": dict(zip((2, 4, 8), (round(v, 4) for v in self.ms_rot))),
+                "ms_gram": {int(c): round(v, 4) for c, v in zip(self.gram_candidates,
+                                                                 self.ms_gram) if v >= 0}}
 
 
 class DcdftError(RuntimeError):
@@ -107,6 +125,9 @@ def load_library(path: Optional[str] = None):
         "dcdft_kernel_timing": ([vp, ctypes.c_int32], ctypes.c_int),
         "dcdft_kernel_time": ([vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), pd, pd, pd],
                               ctypes.c_int),
+        "dcdft_autotune": ([vp, ctypes.c_char_p, ctypes.POINTER(DcdftTuneInfo)], ctypes.c_int),
+        "dcdft_get_launch": ([vp, pi, pi, pi, pi], ctypes.c_int),
+        "dcdft_set_launch": ([vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
         "dcdft_destroy": ([vp], None),
         "dcdft_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "dcdft_last_error": ([vp, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
@@ -312,6 +333,22 @@ class DCDFT:
         _check(self._lib.dcdft_kernel_time(self.ctx, kernel, ctypes.byref(n), ctypes.byref(ms),
                                            ctypes.byref(by), ctypes.byref(fl)), self.ctx)
         return dict(launches=n.value, ms=ms.value, bytes=by.value, flops=fl.value)
+
+    def dcdft_autotune(self, cache_path: Optional[str] = None) -> dict:
+        info = DcdftTuneInfo()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(self._lib.dcdft_autotune(self.ctx, path, ctypes.byref(info)), self.ctx)
+        return info.as_dict()
+
+    def dcdft_get_launch(self) -> dict:
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(self._lib.dcdft_get_launch(self.ctx, *[ctypes.byref(x) for x in v]), self.ctx)
+        return dict(hloc_variant=v[0].value, rot_tiles=v[1].value, gram_chunks=v[2].value,
+                    gram_chunks_max=v[3].value)
+
+    def dcdft_set_launch(self, hloc_variant: int, rot_tiles: int, gram_chunks: int) -> None:
+        _check(self._lib.dcdft_set_launch(self.ctx, hloc_variant, rot_tiles, gram_chunks),
+               self.ctx)
 
     def dcdft_band_energy(self, frag: int, psi, f, veff=None, energy=None, grad_psi=None,
                           grad_v=None, prec: int = PREC_FP64) -> None:

@@ -802,12 +802,16 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   c->precision = p->precision;
   c->batched = p->batched;
   c->seed = p->seed;
-  // Gram chunks: aim at >= 512 four-wave workgroups over all fragments
+  // Gram chunks: aim at >= 1024 four-wave workgroups over all fragments; the
+  // partial buffer is sized for the autotuner's largest candidate (4x)
   {
     int ch = (1024 + c->nF - 1) / c->nF;
     const int maxch = std::max(1, g.n / 128);
     c->gram_chunks = std::max(1, std::min(ch, maxch));
+    c->gram_chunks_max = std::max(1, std::min(4 * c->gram_chunks, maxch));
   }
+  g.hloc_variant = hloc_halo_ok(g) ? HLOC_HALO_PD2 : HLOC_PLANE;
+  g.rot_tiles = 4;
   if (p->hip_stream) {
     c->stream = (hipStream_t)p->hip_stream;
   } else {
@@ -871,9 +875,14 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   ALLOC(c->d_veff, (long long)c->nF * g.n);
   ALLOC(c->d_rhof_in, (long long)c->nF * g.n);
   ALLOC(c->d_rhof_out, (long long)c->nF * g.n);
-  ALLOC(c->d_gpart, (long long)c->nF * c->gram_chunks * mp2);
+  ALLOC(c->d_gpart, (long long)c->nF * c->gram_chunks_max * mp2);
   ALLOC(c->d_gtmp, c->nF * mp2);
-  ALLOC(c->d_dpart, (long long)c->nF * rot_wpf(g) * 2 * c->m_pad);
+  {
+    // rotation partials for the smallest tile count the autotuner may pick
+    Geo g2 = g;
+    g2.rot_tiles = 2;
+    ALLOC(c->d_dpart, (long long)c->nF * rot_wpf(g2) * 2 * c->m_pad);
+  }
   ALLOC(c->d_hs_full, c->nF * mp2);
   ALLOC(c->d_hs, c->nF * mp2);
   ALLOC(c->d_x, c->nF * mp2);
@@ -1310,6 +1319,202 @@ dcdft_status dcdft_kernel_time(dcdft_ctx *c, int32_t kernel, int64_t *launches, 
   if (ms) *ms = c->k_ms[kernel];
   if (bytes) *bytes = c->k_bytes[kernel];
   if (flops) *flops = c->k_flops[kernel];
+  return DCDFT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Mean device milliseconds of one call of fn over reps calls (after one
+// untimed call), from events on the context's stream.
+template <typename F>
+double time_launches(dcdft_ctx *c, F fn, int reps) {
+  fn();
+  hipEventRecord(c->ev0, c->stream);
+  for (int r = 0; r < reps; ++r) fn();
+  hipEventRecord(c->ev1, c->stream);
+  if (hipEventSynchronize(c->ev1) != hipSuccess) return -1.0;
+  float ms = 0.0f;
+  if (hipEventElapsedTime(&ms, c->ev0, c->ev1) != hipSuccess) return -1.0;
+  return ms / reps;
+}
+
+std::string tune_key(const dcdft_ctx *c) {
+  hipDeviceProp_t prop;
+  int dev = 0;
+  std::string arch = "unknown";
+  int cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    cus = prop.multiProcessorCount;
+  }
+  for (char &ch : arch)
+    if (ch == ' ') ch = '_';
+  const Geo &g = c->geo;
+  return fmt("arch=%s;cu=%d;prec=%d;box=%dx%dx%d;F=%d;M=%lld;mpad=%d", arch.c_str(), cus,
+             c->precision, g.nl[0], g.nl[1], g.nl[2], c->nF, (long long)c->M_tot, c->m_pad);
+}
+
+bool tune_valid(const dcdft_ctx *c, int hv, int rt, int gc) {
+  if (hv < 0 || hv >= HLOC_NVARIANT) return false;
+  if (hv != HLOC_PLANE && !hloc_halo_ok(c->geo)) return false;
+  if (rt != 2 && rt != 4 && rt != 8) return false;
+  return gc >= 1 && gc <= c->gram_chunks_max;
+}
+
+template <typename T>
+void autotune_t(dcdft_ctx *c, dcdft_tune_info &info) {
+  Geo &g = c->geo;
+  const OrbSet o = c->orbset(0, c->nF);
+  T *psi = (T *)c->d_psi, *w = (T *)c->d_w, *q = (T *)c->d_q;
+  const int reps = 3;
+  // stencil variants
+  double best = 1e300;
+  int hv_best = g.hloc_variant;
+  for (int v = 0; v < HLOC_NVARIANT; ++v) {
+    info.ms_hloc[v] = -1.0;
+    if (v != HLOC_PLANE && !hloc_halo_ok(g)) continue;
+    g.hloc_variant = v;
+    const double ms = time_launches(
+        c, [&] { launch_hloc<T>(g, o, 0, c->nF, c->d_veff, psi, w, c->stream); }, reps);
+    info.ms_hloc[v] = ms;
+    if (ms >= 0.0 && ms < best) {
+      best = ms;
+      hv_best = v;
+    }
+  }
+  g.hloc_variant = hv_best;
+  // Gram chunk counts (also leaves a finite matrix in d_gtmp for the rotations)
+  const int base = c->gram_chunks;
+  int cand[4] = {std::max(1, base / 2), base, 2 * base, 4 * base};
+  best = 1e300;
+  int gc_best = base;
+  for (int k = 0; k < 4; ++k) {
+    info.gram_candidates[k] = cand[k];
+    info.ms_gram[k] = -1.0;
+    bool dup = false;
+    for (int j = 0; j < k; ++j) dup |= cand[j] == cand[k];
+    if (dup || cand[k] > c->gram_chunks_max) continue;
+    const int ch = cand[k];
+    const double ms = time_launches(
+        c,
+        [&] {
+          launch_gram<T>(g, o, 0, c->nF, ch, psi, w, c->d_gpart, c->stream);
+          launch_gram_reduce(g, o, 0, c->nF, ch, 0, c->d_gpart, c->d_gtmp, nullptr, nullptr,
+                             c->stream);
+        },
+        reps);
+    info.ms_gram[k] = ms;
+    if (ms >= 0.0 && ms < best) {
+      best = ms;
+      gc_best = ch;
+    }
+  }
+  c->gram_chunks = gc_best;
+  // rotation tiles
+  const int tiles[3] = {2, 4, 8};
+  best = 1e300;
+  int rt_best = g.rot_tiles;
+  for (int k = 0; k < 3; ++k) {
+    g.rot_tiles = tiles[k];
+    const double ms = time_launches(
+        c,
+        [&] {
+          launch_rot_residual<T>(g, o, 0, c->nF, c->d_gtmp, psi, w, q, c->d_dpart, c->d_nu,
+                                 c->stream);
+        },
+        reps);
+    info.ms_rot[k] = ms;
+    if (ms >= 0.0 && ms < best) {
+      best = ms;
+      rt_best = tiles[k];
+    }
+  }
+  g.rot_tiles = rt_best;
+}
+
+}  // namespace
+
+extern "C" {
+
+dcdft_status dcdft_autotune(dcdft_ctx *c, const char *cache_path, dcdft_tune_info *out) {
+  if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  dcdft_tune_info info;
+  std::memset(&info, 0, sizeof(info));
+  for (double &v : info.ms_hloc) v = -1.0;
+  for (double &v : info.ms_rot) v = -1.0;
+  for (double &v : info.ms_gram) v = -1.0;
+  HIPTRY(c, hipStreamSynchronize(c->stream));
+  const std::string key = tune_key(c);
+  bool cached = false;
+  if (cache_path) {
+    if (FILE *fp = std::fopen(cache_path, "r")) {
+      char line[1024];
+      while (std::fgets(line, sizeof line, fp)) {
+        char k[800];
+        int hv, rt, gc;
+        if (std::sscanf(line, "%799s %d %d %d", k, &hv, &rt, &gc) == 4 && key == k &&
+            tune_valid(c, hv, rt, gc)) {
+          c->geo.hloc_variant = hv;
+          c->geo.rot_tiles = rt;
+          c->gram_chunks = gc;
+          cached = true;
+        }
+      }
+      std::fclose(fp);
+    }
+  }
+  if (!cached) {
+    const bool was_timing = c->timing;
+    c->timing = false;
+    if (c->elem == sizeof(double))
+      autotune_t<double>(c, info);
+    else
+      autotune_t<float>(c, info);
+    c->timing = was_timing;
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+  }
+  drop_graph(c);
+  info.hloc_variant = c->geo.hloc_variant;
+  info.rot_tiles = c->geo.rot_tiles;
+  info.gram_chunks = c->gram_chunks;
+  info.from_cache = cached ? 1 : 0;
+  if (out) *out = info;
+  if (cache_path && !cached) {
+    FILE *fp = std::fopen(cache_path, "a");
+    if (!fp) return set_err(c, DCDFT_ERR_ARG, fmt("cannot write tuning cache %s", cache_path));
+    std::fprintf(fp, "%s %d %d %d\n", key.c_str(), info.hloc_variant, info.rot_tiles,
+                 info.gram_chunks);
+    std::fclose(fp);
+  }
+  return DCDFT_OK;
+}
+
+
+dcdft_status dcdft_get_launch(const dcdft_ctx *c, int32_t *hloc_variant, int32_t *rot_tiles,
+                              int32_t *gram_chunks, int32_t *gram_chunks_max) {
+  if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  if (hloc_variant) *hloc_variant = c->geo.hloc_variant;
+  if (rot_tiles) *rot_tiles = c->geo.rot_tiles;
+  if (gram_chunks) *gram_chunks = c->gram_chunks;
+  if (gram_chunks_max) *gram_chunks_max = c->gram_chunks_max;
+  return DCDFT_OK;
+}
+
+dcdft_status dcdft_set_launch(dcdft_ctx *c, int32_t hloc_variant, int32_t rot_tiles,
+                              int32_t gram_chunks) {
+  if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  if (!tune_valid(c, hloc_variant, rot_tiles, gram_chunks))
+    return set_err(c, DCDFT_ERR_ARG,
+                   fmt("invalid launch shape (hloc %d, rot tiles %d, gram chunks %d; chunks "
+                       "1..%d, halo variants need a 4x4x8 box)",
+                       hloc_variant, rot_tiles, gram_chunks, c->gram_chunks_max));
+  HIPTRY(c, hipStreamSynchronize(c->stream));
+  c->geo.hloc_variant = hloc_variant;
+  c->geo.rot_tiles = rot_tiles;
+  c->gram_chunks = gram_chunks;
+  drop_graph(c);
   return DCDFT_OK;
 }
 

@@ -40,7 +40,21 @@ struct Geo {
   // kinetic stencil coefficients -1/2 c_k / h_d^2: [0] centre (all axes), then
   // x k=1..4, y k=1..4, z k=1..4 (set once at setup, uniform in every kernel)
   double kc[13];
+  // launch choices (set at setup, possibly replaced by the autotuner)
+  int hloc_variant;  // HLOC_*
+  int rot_tiles;     // 16-point tiles per wave of the rotation kernels: 2, 4 or 8
 };
+
+// stencil kernel variants; all compute the same sums in the same order
+enum {
+  HLOC_PLANE = DCDFT_HLOC_PLANE,                  // one plane in flight
+  HLOC_HALO_PD2 = DCDFT_HLOC_HALO_PD2,            // haloed LDS plane, 2-plane load chunks
+  HLOC_HALO_PD3 = DCDFT_HLOC_HALO_PD3,            // ... 3-plane chunks
+  HLOC_HALO_PD4 = DCDFT_HLOC_HALO_PD4,            // ... 4-plane chunks
+  HLOC_HALO_PD2_ENDS = DCDFT_HLOC_HALO_PD2_ENDS,  // 2-plane chunks, end planes in registers
+  HLOC_NVARIANT = DCDFT_HLOC_COUNT
+};
+bool hloc_halo_ok(const Geo &g);
 
 struct OrbSet {           // flattened orbital layout [M_tot][n]
   int nfrag;
@@ -103,6 +117,7 @@ struct dcdft_ctx {
   bool own_stream = false;
   int iter = 0;
   int gram_chunks = 1;
+  int gram_chunks_max = 1;
 
   // fragment -> host copies
   std::vector<int> A;                // projectors per fragment

@@ -81,6 +81,125 @@ __global__ void __launch_bounds__(1024) k_hloc(Geo g, const int *__restrict__ ba
   }
 }
 
+// Same operator for boxes with nx, ny >= 4, built for memory-level
+// parallelism: the plane sits in LDS with a four-point periodic halo on both
+// axes (row stride SX = nx + 32, so consecutive rows continue the bank sequence
+// of an unpadded plane), which turns every neighbour read into a fixed offset
+// from one address; the planes entering the window are loaded a chunk of PD
+// iterations ahead, so PD..2PD plane loads of a workgroup are in flight; and
+// the four planes at each end of the periodic z range stay in registers, so
+// every plane of the orbital is read from memory once.  NX > 0 fixes nx at
+// compile time (immediate LDS offsets); NX = 0 takes it from the geometry.
+template <typename T, int NX, int PD, bool HT>
+__global__ void __launch_bounds__(1024) k_hloc_halo(Geo g, const int *__restrict__ band_frag,
+                                                    long long b0, int vbase,
+                                                    const double *__restrict__ veff,
+                                                    const T *__restrict__ x, T *__restrict__ y,
+                                                    double *__restrict__ dot) {
+  extern __shared__ char lds_raw[];
+  T *lds = reinterpret_cast<T *>(lds_raw);
+  __shared__ double red[16];
+  const long long B = b0 + blockIdx.x;
+  const int f = band_frag[B];
+  const int nx = NX > 0 ? NX : g.nl[0];
+  const int ny = g.nl[1], nz = g.nl[2];
+  const int SX = nx + 32;
+  const int plane = nx * ny;
+  const int lplane = (ny + 8) * SX;
+  const int t = threadIdx.x;
+  const int ix = t % nx, iy = t / nx;
+  const int tp = (iy + 4) * SX + ix + 4;
+  // periodic copies this thread also writes: into the high halo (ix < 4) and
+  // into the low halo (ix >= nx - 4), both when nx < 8; likewise along y
+  const bool xh = ix < 4, xl = ix >= nx - 4, yh = iy < 4, yl = iy >= ny - 4;
+  const T *xb = x + B * (long long)g.n;
+  T *yb = y + B * (long long)g.n;
+  const double *vb = veff + (long long)(f - vbase) * g.n;
+  const T c0 = (T)g.kc[0];
+  T ax[4], ay[4], az[4];
+#pragma unroll
+  for (int k = 1; k <= 4; ++k) {
+    ax[k - 1] = (T)g.kc[k];
+    ay[k - 1] = (T)g.kc[4 + k];
+    az[k - 1] = (T)g.kc[8 + k];
+  }
+  // head = planes 0..3, tail = planes nz-4..nz-1 (nz >= 8), window = z-4..z+4
+  T head[HT ? 4 : 1], tail[HT ? 4 : 1], win[9];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    win[k] = xb[(long long)(nz - 4 + k) * plane + t];
+    win[4 + k] = xb[(long long)k * plane + t];
+    if (HT) {
+      head[k] = win[4 + k];
+      tail[k] = win[k];
+    }
+  }
+  win[8] = xb[4LL * plane + t];
+  // planes 5 .. nz-5 come through the prefetch chunks
+  T nxt[PD];
+#pragma unroll
+  for (int j = 0; j < PD; ++j) {
+    const int pz = 5 + j;
+    nxt[j] = pz <= nz - 5 ? xb[(long long)pz * plane + t] : (T)0;
+  }
+  double v0 = vb[t];
+  double dacc = 0.0;
+  for (int z0 = 0; z0 < nz; z0 += PD) {
+    T fut[PD];
+#pragma unroll
+    for (int j = 0; j < PD; ++j) {
+      const int pz = z0 + 5 + PD + j;
+      fut[j] = pz <= nz - 5 ? xb[(long long)pz * plane + t] : (T)0;
+    }
+#pragma unroll
+    for (int j = 0; j < PD; ++j) {
+      const int z = z0 + j;
+      if (z >= nz) break;
+      const double v1 = z + 1 < nz ? vb[(long long)(z + 1) * plane + t] : 0.0;
+      T *pl = lds + (z & 1) * lplane;
+      const T c = win[4];
+      pl[tp] = c;
+      if (xh) pl[tp + nx] = c;
+      if (xl) pl[tp - nx] = c;
+      if (yh) pl[tp + ny * SX] = c;
+      if (yl) pl[tp - ny * SX] = c;
+      __syncthreads();
+      T acc = c0 * c;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        acc += ax[k] * (pl[tp + k + 1] + pl[tp - k - 1]);
+        acc += ay[k] * (pl[tp + (k + 1) * SX] + pl[tp - (k + 1) * SX]);
+        acc += az[k] * (win[5 + k] + win[3 - k]);
+      }
+      acc += (T)v0 * c;
+      yb[(long long)z * plane + t] = acc;
+      dacc += (double)c * (double)acc;
+      v0 = v1;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) win[k] = win[k + 1];
+      // plane z + 5 enters the window
+      const int pz = z + 5;
+      T w8 = nxt[j];
+      if (pz > nz - 5) {
+        if (HT) {
+          const int ht = pz >= nz ? pz - nz : pz - (nz - 4);
+          const T *src = pz >= nz ? head : tail;
+          w8 = ht == 0 ? src[0] : (ht == 1 ? src[1] : (ht == 2 ? src[2] : src[3]));
+        } else {
+          w8 = xb[(long long)(pz >= nz ? pz - nz : pz) * plane + t];
+        }
+      }
+      win[8] = w8;
+    }
+#pragma unroll
+    for (int j = 0; j < PD; ++j) nxt[j] = fut[j];
+  }
+  if (dot) {
+    dacc = block_sum(dacc, red);
+    if (t == 0) dot[B] = g.dv * dacc;
+  }
+}
+
 template <typename T>
 __device__ inline const T *region_beta(const KBTables &kb);
 template <>
@@ -342,7 +461,30 @@ void kb_dispatch(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int 
   }
 }
 
+template <typename T, int PD, bool HT>
+void launch_halo(const Geo &g, long long nb, const OrbSet &o, int f0, const double *veff,
+                 const T *x, T *y, hipStream_t s, double *dot, int vbase) {
+  const int plane = g.nl[0] * g.nl[1];
+  const size_t lds = 2 * (size_t)(g.nl[1] + 8) * (g.nl[0] + 32) * sizeof(T);
+  if (g.nl[0] == 24)
+    hipLaunchKernelGGL((k_hloc_halo<T, 24, PD, HT>), dim3((unsigned)nb), dim3(plane), lds, s, g,
+                       o.band_frag, o.b0(f0), vbase, veff, x, y, dot);
+  else if (g.nl[0] == 32)
+    hipLaunchKernelGGL((k_hloc_halo<T, 32, PD, HT>), dim3((unsigned)nb), dim3(plane), lds, s, g,
+                       o.band_frag, o.b0(f0), vbase, veff, x, y, dot);
+  else
+    hipLaunchKernelGGL((k_hloc_halo<T, 0, PD, HT>), dim3((unsigned)nb), dim3(plane), lds, s, g,
+                       o.band_frag, o.b0(f0), vbase, veff, x, y, dot);
+}
+
 }  // namespace
+
+bool hloc_halo_ok(const Geo &g) {
+  // halo copies need nx, ny >= 4; the held end planes need nz >= 8; the padded
+  // double plane must fit the 64 KB LDS a workgroup may address
+  return g.nl[0] >= 4 && g.nl[1] >= 4 && g.nl[2] >= 8 &&
+         2 * (size_t)(g.nl[1] + 8) * (g.nl[0] + 32) * sizeof(double) <= 65536;
+}
 
 template <typename T>
 void launch_hloc(const Geo &g, const OrbSet &o, int f0, int f1, const double *veff, const T *x,
@@ -350,6 +492,17 @@ void launch_hloc(const Geo &g, const OrbSet &o, int f0, int f1, const double *ve
   const long long nb = o.nb(f0, f1);
   if (nb <= 0) return;
   const int plane = g.nl[0] * g.nl[1];
+  if (hloc_halo_ok(g)) {
+    switch (g.hloc_variant) {
+      case HLOC_HALO_PD2: launch_halo<T, 2, false>(g, nb, o, f0, veff, x, y, s, dot, vbase); return;
+      case HLOC_HALO_PD3: launch_halo<T, 3, false>(g, nb, o, f0, veff, x, y, s, dot, vbase); return;
+      case HLOC_HALO_PD4: launch_halo<T, 4, false>(g, nb, o, f0, veff, x, y, s, dot, vbase); return;
+      case HLOC_HALO_PD2_ENDS:
+        launch_halo<T, 2, true>(g, nb, o, f0, veff, x, y, s, dot, vbase);
+        return;
+      default: break;
+    }
+  }
   hipLaunchKernelGGL(k_hloc<T>, dim3((unsigned)nb), dim3(plane), 2 * plane * sizeof(T), s, g,
                      o.band_frag, o.b0(f0), vbase, veff, x, y, dot);
 }

@@ -653,17 +653,21 @@ void gram3_tm(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, T *x, T
   }
 }
 
-constexpr int kRotTiles = 4;   // 16-point tiles per wave in k_rot_fused
-
 template <typename T, int FL>
 void rot_fused_tm(const Geo &g, const OrbSet &o, int f0, int f1, int wpf, const double *M,
                   int trans, const T *x, const T *z, double cz, double cm, T *y, const T *x2,
                   T *y2, const T *wdot, double *dpart, hipStream_t s) {
   if (f1 <= f0) return;
   const dim3 grid((f1 - f0) * wpf), block(256);
-#define DCDFT_ROT(TMV)                                                                         \
-  hipLaunchKernelGGL((k_rot_fused<T, TMV, kRotTiles, FL>), grid, block, 0, s, g, o, f0, wpf, M, \
-                     trans, x, z, cz, cm, y, x2, y2, wdot, dpart)
+#define DCDFT_ROT_NT(TMV, NT)                                                                  \
+  hipLaunchKernelGGL((k_rot_fused<T, TMV, NT, FL>), grid, block, 0, s, g, o, f0, wpf, M, trans, \
+                     x, z, cz, cm, y, x2, y2, wdot, dpart)
+#define DCDFT_ROT(TMV)                                   \
+  do {                                                   \
+    if (g.rot_tiles == 2) DCDFT_ROT_NT(TMV, 2);          \
+    else if (g.rot_tiles == 8) DCDFT_ROT_NT(TMV, 8);     \
+    else DCDFT_ROT_NT(TMV, 4);                           \
+  } while (0)
   switch (o.tiles) {
     case 1: DCDFT_ROT(1); break;
     case 2: DCDFT_ROT(2); break;
@@ -672,6 +676,7 @@ void rot_fused_tm(const Geo &g, const OrbSet &o, int f0, int f1, int wpf, const 
     default: DCDFT_ROT(5); break;
   }
 #undef DCDFT_ROT
+#undef DCDFT_ROT_NT
 }
 
 void band_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int wpf, const double *dpart,
@@ -685,7 +690,8 @@ void band_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int wpf, const d
 }  // namespace
 
 int rot_wpf(const Geo &g) {
-  const int per_wg = 4 * kRotTiles * 16;
+  const int nt = (g.rot_tiles == 2 || g.rot_tiles == 8) ? g.rot_tiles : 4;
+  const int per_wg = 4 * nt * 16;
   return (g.n + per_wg - 1) / per_wg;
 }
 

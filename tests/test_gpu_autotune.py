@@ -1,0 +1,127 @@
+"""Launch-shape variants and the autotuner, through the C ABI.
+
+Every stencil variant computes the same sums in the same order, so H psi must
+agree bitwise across variants (and with the oracle to 1e-12 relative).  The
+rotation tile count and the Gram chunk count change only the order of FP64
+partial sums: SCF results stay within the FP64 parity tolerances of the
+default shapes.  The autotuner must leave a valid choice, re-use it from its
+cache file, and keep the step results within those tolerances."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import solver as osol
+from tests.gpu_common import l1_over_ne, require_gpu
+from tests.helpers import tiny_config
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _ragged_tiny():
+    cfg = tiny_config(n_grid=(12, 12, 10), cell=(7.2, 7.2, 6.0), n_atoms=5, nstate=9,
+                      num_fragment=(2, 2, 1), buffer=(2, 3, 0), smearing=0.05, valence=2.0)
+    cfg.nstate_frag = np.array([9, 12, 7, 17], dtype=np.int32)
+    return cfg
+
+
+@pytest.mark.parametrize("which", ["config1", "ragged"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_stencil_variants_bitwise(which, prec):
+    require_gpu()
+    import torch
+    from paper_2606_21125_amd import DCDFT, HLOC_VARIANTS
+    cfg = workloads.config(1) if which == "config1" else _ragged_tiny()
+    o = oracle.OracleSCF(cfg)
+    v_h = np.zeros_like(o.rho_in)
+    dt = torch.float64 if prec == 0 else torch.float32
+    with DCDFT.from_config(cfg, precision=prec) as d:
+        launch = d.dcdft_get_launch()
+        rng = np.random.default_rng(11)
+        for frag in (0, cfg.n_fragments - 1):
+            shape = o.frags[frag].shape
+            m = 21
+            x = rng.normal(size=(m,) + shape)
+            xt = torch.tensor(x.reshape(m, -1), device="cuda", dtype=dt)
+            outs = []
+            for v in range(len(HLOC_VARIANTS)):
+                d.dcdft_set_launch(v, launch["rot_tiles"], launch["gram_chunks"])
+                yt = torch.empty_like(xt)
+                d.dcdft_apply_h(frag, xt, yt, prec=prec)
+                outs.append(yt.cpu())
+            for v in range(1, len(outs)):
+                assert torch.equal(outs[0], outs[v]), (which, frag, HLOC_VARIANTS[v])
+            if prec == 0:
+                veff = o.veff(frag, v_h).reshape(shape)
+                ref = osol.apply_h(x, veff, o.fproj[frag], o.h, o.dv).reshape(m, -1)
+                got = outs[1].numpy()
+                assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_set_launch_rejects_invalid_shapes():
+    require_gpu()
+    from paper_2606_21125_amd import DCDFT, DcdftError
+    cfg = workloads.config(1)
+    with DCDFT.from_config(cfg) as d:
+        launch = d.dcdft_get_launch()
+        for bad in [(9, 4, 1), (1, 3, 1), (1, 4, 0), (1, 4, launch["gram_chunks_max"] + 1)]:
+            with pytest.raises(DcdftError):
+                d.dcdft_set_launch(*bad)
+        assert d.dcdft_get_launch() == launch
+
+
+def _l1(a, b, cfg):
+    dv = float(np.prod(np.asarray(cfg.system.cell) / np.asarray(cfg.n_grid)))
+    return l1_over_ne(a, b, dv, cfg.system.n_electrons)
+
+
+def _run(d, steps):
+    info = [d.dcdft_scf_step() for _ in range(steps)]
+    return info, d.dcdft_density(), [d.dcdft_eigenvalues(a)[0] for a in range(d.n_fragments)]
+
+
+@pytest.mark.parametrize("rot_tiles,chunk_scale", [(2, 1), (8, 2), (4, 0.5)])
+def test_rotation_tiles_and_gram_chunks_keep_results(rot_tiles, chunk_scale):
+    require_gpu()
+    from paper_2606_21125_amd import DCDFT
+    cfg = workloads.config(1)
+    with DCDFT.from_config(cfg) as d0:
+        i0, rho0, eps0 = _run(d0, 3)
+    with DCDFT.from_config(cfg) as d1:
+        launch = d1.dcdft_get_launch()
+        ch = max(1, min(launch["gram_chunks_max"], int(launch["gram_chunks"] * chunk_scale)))
+        d1.dcdft_set_launch(launch["hloc_variant"], rot_tiles, ch)
+        i1, rho1, eps1 = _run(d1, 3)
+    for a, b in zip(i0, i1):
+        assert abs(a["mu"] - b["mu"]) <= 1e-10
+    assert _l1(rho0, rho1, cfg) <= 1e-9
+    for a, b in zip(eps0, eps1):
+        assert np.abs(a - b).max() <= 1e-10
+
+
+def test_autotune_choice_cache_and_results(tmp_path):
+    require_gpu()
+    from paper_2606_21125_amd import DCDFT, HLOC_VARIANTS
+    cfg = workloads.config(2)
+    cache = str(tmp_path / "tune.txt")
+    with DCDFT.from_config(cfg, precision=1) as d:
+        t = d.dcdft_autotune(cache)
+        print("autotune:", t, flush=True)
+        assert not t["from_cache"]
+        assert t["hloc_variant"] in HLOC_VARIANTS and t["rot_tiles"] in (2, 4, 8)
+        times = [v for v in t["ms_hloc"].values() if v >= 0]
+        assert len(times) == len(HLOC_VARIANTS) and t["ms_hloc"][t["hloc_variant"]] == min(times)
+        t2 = d.dcdft_autotune(cache)
+        assert t2["from_cache"]
+        for k in ("hloc_variant", "rot_tiles", "gram_chunks"):
+            assert t2[k] == t[k]
+    cfg1 = workloads.config(1)
+    with DCDFT.from_config(cfg1) as d0:
+        i0, rho0, eps0 = _run(d0, 2)
+    with DCDFT.from_config(cfg1) as d1:
+        d1.dcdft_autotune(None)
+        i1, rho1, eps1 = _run(d1, 2)
+    assert abs(i0[-1]["mu"] - i1[-1]["mu"]) <= 1e-10
+    assert _l1(rho0, rho1, cfg1) <= 1e-9
+    for a, b in zip(eps0, eps1):
+        assert np.abs(a - b).max() <= 1e-10
