@@ -208,7 +208,13 @@ dcdft_status dcdft_kernel_time(dcdft_ctx *c, int32_t kernel, int64_t *launches, 
  * orbital arrays and with HIP events on its stream, the candidate shapes of
  *   - the stencil kernel H_loc X (DCDFT_HLOC_*: one plane in flight, or a
  *     haloed LDS plane with 2-, 3- or 4-plane load chunks, or 2-plane chunks
- *     with the periodic end planes held in registers),
+ *     with the periodic end planes held in registers, or 16-byte runs of x
+ *     points per thread with one-plane chunks and a few orbitals per
+ *     workgroup (fewest that keep 85% of lanes busy, or the most that fill
+ *     whole waves), also with z cut into 2 or 3 segments per orbital (more
+ *     workgroups in flight, four extra planes read at each cut); the vector
+ *     forms need n_x a multiple of 16 / element size (segments: n_z / segments
+ *     >= 4) and fall back to the 2-plane haloed kernel otherwise),
  *   - the rotation kernels (2, 4 or 8 sixteen-point tiles per wave),
  *   - the Gram products (the point range of a fragment cut into G chunks,
  *     G among half, one, two and four times the default),
@@ -223,7 +229,9 @@ dcdft_status dcdft_kernel_time(dcdft_ctx *c, int32_t kernel, int64_t *launches, 
  * measured milliseconds per launch (-1: candidate not applicable or not
  * timed). */
 enum { DCDFT_HLOC_PLANE = 0, DCDFT_HLOC_HALO_PD2 = 1, DCDFT_HLOC_HALO_PD3 = 2,
-       DCDFT_HLOC_HALO_PD4 = 3, DCDFT_HLOC_HALO_PD2_ENDS = 4, DCDFT_HLOC_COUNT = 5 };
+       DCDFT_HLOC_HALO_PD4 = 3, DCDFT_HLOC_HALO_PD2_ENDS = 4, DCDFT_HLOC_VEC = 5,
+       DCDFT_HLOC_VEC_WIDE = 6, DCDFT_HLOC_VEC_Z2 = 7, DCDFT_HLOC_VEC_Z3 = 8,
+       DCDFT_HLOC_COUNT = 9 };
 typedef struct {
   int32_t hloc_variant;  /* DCDFT_HLOC_* */
   int32_t rot_tiles;     /* 2, 4 or 8 */

@@ -35,7 +35,8 @@ EXPORTED = [
     "dcdft_status_string", "dcdft_last_error",
 ]
 KERNEL_HLOC, KERNEL_GRAM, KERNEL_ROTATE = 0, 1, 2
-HLOC_VARIANTS = ("plane", "halo_pd2", "halo_pd3", "halo_pd4", "halo_pd2_ends")
+HLOC_VARIANTS = ("plane", "halo_pd2", "halo_pd3", "halo_pd4", "halo_pd2_ends", "vec",
+                 "vec_wide", "vec_z2", "vec_z3")
 
 
 class DcdftSpecies(ctypes.Structure):
@@ -72,7 +73,7 @@ class DcdftScfInfo(ctypes.Structure):
 class DcdftTuneInfo(ctypes.Structure):
     _fields_ = [("hloc_variant", ctypes.c_int32), ("rot_tiles", ctypes.c_int32),
                 ("gram_chunks", ctypes.c_int32), ("from_cache", ctypes.c_int32),
-                ("ms_hloc", ctypes.c_double * 5), ("ms_rot", ctypes.c_double * 3),
+                ("ms_hloc", ctypes.c_double * 9), ("ms_rot", ctypes.c_double * 3),
                 ("gram_candidates", ctypes.c_int32 * 4), ("ms_gram", ctypes.c_double * 4)]
 
     def as_dict(self) -> dict:

@@ -201,12 +201,25 @@ double sum_m2(const dcdft_ctx *c, int f0, int f1) {
   return s;
 }
 
+// V_eff in the storage type of the orbital arrays
+template <typename T>
+const T *veff_t(const dcdft_ctx *c);
+template <>
+const double *veff_t<double>(const dcdft_ctx *c) {
+  return c->d_veff;
+}
+template <>
+const float *veff_t<float>(const dcdft_ctx *c) {
+  return c->d_veff32;
+}
+
 template <typename T>
 void hloc(dcdft_ctx *c, int f0, int f1, const T *x, T *y, double *dot = nullptr) {
   const double n = c->geo.n, sz = sizeof(T);
   Timed t(c, DCDFT_KERNEL_HLOC, 2.0 * sz * n * orbitals_in(c, f0, f1) + 8.0 * n * (f1 - f0),
           55.0 * n * orbitals_in(c, f0, f1));
-  launch_hloc<T>(c->geo, c->orbset(f0, f1), f0, f1, c->d_veff, x, y, c->stream, dot);
+  launch_hloc<T>(c->geo, c->orbset(f0, f1), f0, f1, c->d_veff, veff_t<T>(c), x, y, c->stream,
+                 dot, 0, c->d_hdot);
 }
 
 // H X for the orbitals of fragments [f0, f1) in the context layout.
@@ -654,7 +667,7 @@ void enqueue_step(dcdft_ctx *c) {
   // 1. Hartree potential of rho_tot^in
   launch_poisson(g, c->d_rho_in, c->d_vh, c->d_fft_a, c->d_fft_b, c->d_qf, c->d_qi, c->d_lam, s);
   // 2. fragment effective potentials
-  launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, s);
+  launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, c->d_veff32, s);
   // 3. fragment eigensolvers
   if (c->batched) {
     if (c->precision == DCDFT_PREC_MIXED) eigensolver_range<float>(c, 0, c->nF);
@@ -873,6 +886,8 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   ALLOC(c->d_fft_a, g.Ng);
   ALLOC(c->d_fft_b, g.Ng);
   ALLOC(c->d_veff, (long long)c->nF * g.n);
+  ALLOC(c->d_veff32, (long long)c->nF * g.n);
+  ALLOC(c->d_hdot, (long long)kHlocZsMax * c->M_tot);
   ALLOC(c->d_rhof_in, (long long)c->nF * g.n);
   ALLOC(c->d_rhof_out, (long long)c->nF * g.n);
   ALLOC(c->d_gpart, (long long)c->nF * c->gram_chunks_max * mp2);
@@ -917,7 +932,7 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   for (double **b : bands) launch_fill(*b, c->M_tot, 0.0, c->stream);
   launch_fill(c->d_scal, SC_COUNT, 0.0, c->stream);
   launch_fill_int(c->d_flags, 1, 0, c->stream);
-  launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, c->stream);
+  launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, c->d_veff32, c->stream);
   if (mixed) {
     launch_init_orbitals<float>(g, c->orbset(0, c->nF), c->seed, (float *)c->d_psi, c->stream);
     orthonormalize_all<float>(c);
@@ -1158,7 +1173,7 @@ dcdft_status dcdft_set_density(dcdft_ctx *c, const double *rho_tot_in, const dou
   // V_eff follows the new density (V_H recomputed from it)
   launch_poisson(g, c->d_rho_in, c->d_vh, c->d_fft_a, c->d_fft_b, c->d_qf, c->d_qi, c->d_lam,
                  c->stream);
-  launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, c->stream);
+  launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, c->d_veff32, c->stream);
   HIPTRY(c, hipGetLastError());
   HIPTRY(c, hipStreamSynchronize(c->stream));
   return DCDFT_OK;
@@ -1224,10 +1239,12 @@ dcdft_status apply_h_ext(dcdft_ctx *c, int frag, const T *psi, T *hpsi, int m,
     KBTables kb = c->kb();
     const T *x = psi + (long long)i0 * g.n;
     T *y = hpsi + (long long)i0 * g.n;
-    if (veff_ext)
-      launch_hloc<T>(g, o, frag, frag + 1, veff_ext, x, y, c->stream, nullptr, frag);
-    else
-      launch_hloc<T>(g, o, frag, frag + 1, c->d_veff, x, y, c->stream);
+    if (veff_ext) {
+      const T *vt = sizeof(T) == sizeof(double) ? reinterpret_cast<const T *>(veff_ext) : nullptr;
+      launch_hloc<T>(g, o, frag, frag + 1, veff_ext, vt, x, y, c->stream, nullptr, frag);
+    } else {
+      launch_hloc<T>(g, o, frag, frag + 1, c->d_veff, veff_t<T>(c), x, y, c->stream);
+    }
     launch_kb_project<T>(g, o, kb, frag, frag + 1, x, c->d_C, c->d_cpart, c->stream);
     launch_kb_apply<T>(g, o, kb, frag, frag + 1, c->d_C, y, c->stream);
     hipError_t e = hipStreamSynchronize(c->stream);
@@ -1377,7 +1394,8 @@ void autotune_t(dcdft_ctx *c, dcdft_tune_info &info) {
     if (v != HLOC_PLANE && !hloc_halo_ok(g)) continue;
     g.hloc_variant = v;
     const double ms = time_launches(
-        c, [&] { launch_hloc<T>(g, o, 0, c->nF, c->d_veff, psi, w, c->stream); }, reps);
+        c, [&] { launch_hloc<T>(g, o, 0, c->nF, c->d_veff, veff_t<T>(c), psi, w, c->stream); },
+        reps);
     info.ms_hloc[v] = ms;
     if (ms >= 0.0 && ms < best) {
       best = ms;

@@ -52,6 +52,10 @@ enum {
   HLOC_HALO_PD3 = DCDFT_HLOC_HALO_PD3,            // ... 3-plane chunks
   HLOC_HALO_PD4 = DCDFT_HLOC_HALO_PD4,            // ... 4-plane chunks
   HLOC_HALO_PD2_ENDS = DCDFT_HLOC_HALO_PD2_ENDS,  // 2-plane chunks, end planes in registers
+  HLOC_VEC = DCDFT_HLOC_VEC,                      // 16-byte x runs per thread, few orbitals/WG
+  HLOC_VEC_WIDE = DCDFT_HLOC_VEC_WIDE,            // ... whole-wave orbital groups
+  HLOC_VEC_Z2 = DCDFT_HLOC_VEC_Z2,                // HLOC_VEC with z cut into 2 segments
+  HLOC_VEC_Z3 = DCDFT_HLOC_VEC_Z3,                // ... 3 segments
   HLOC_NVARIANT = DCDFT_HLOC_COUNT
 };
 bool hloc_halo_ok(const Geo &g);
@@ -156,6 +160,8 @@ struct dcdft_ctx {
   double *d_qi[3] = {nullptr, nullptr, nullptr};   // inverse basis per axis
   double *d_lam[3] = {nullptr, nullptr, nullptr};  // per-axis FD eigenvalue of each basis column
   double *d_veff = nullptr, *d_rhof_in = nullptr, *d_rhof_out = nullptr;
+  float *d_veff32 = nullptr;  // FP32 rounding of d_veff (read by the FP32 stencil)
+  double *d_hdot = nullptr;   // stencil dot partials [kHlocZsMax][M_tot]
 
   // small matrices [F][m_pad][m_pad]
   double *d_gpart = nullptr;         // Gram partials [F][chunks][m_pad][m_pad]
@@ -208,10 +214,16 @@ namespace dcdft {
 // small matrices, per-band scalars and fields are FP64.
 
 // Y = (-1/2 L_FD + V_eff) X for every orbital of fragments [f0, f1); dot (if not
-// null) receives dV <x_B, y_B> per band.
+// null) receives dV <x_B, y_B> per band.  veffT is V_eff in the storage type
+// (the FP32 rounding for float; may be null, which rules out the variants that
+// read it).
+// dot_part: kHlocZsMax x (bands of the launch) doubles of scratch for the
+// z-segmented variants (null: those variants fall back when dot is wanted).
+constexpr int kHlocZsMax = 3;
 template <typename T>
-void launch_hloc(const Geo &g, const OrbSet &o, int f0, int f1, const double *veff, const T *x,
-                 T *y, hipStream_t s, double *dot = nullptr, int vbase = 0);
+void launch_hloc(const Geo &g, const OrbSet &o, int f0, int f1, const double *veff,
+                 const T *veffT, const T *x, T *y, hipStream_t s, double *dot = nullptr,
+                 int vbase = 0, double *dot_part = nullptr);
 // C[f][a][i] = dV sum beta_a(l) X_i(l) (region partials in part)
 template <typename T>
 void launch_kb_project(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1,
@@ -294,8 +306,9 @@ template <typename T>
 void launch_density(const Geo &g, const OrbSet &o, int f0, int f1, const T *psi,
                     const double *occ, double *rhof_out, double *rho_out, hipStream_t s);
 // V_eff^alpha = V_loc + V_H (gathered) + V_xc(rho_alpha^in)
+// (and, if veff32 is not null, its FP32 rounding)
 void launch_veff(const Geo &g, int f0, int f1, const double *vloc, const double *vh,
-                 const double *rhof_in, double *veff, hipStream_t s);
+                 const double *rhof_in, double *veff, float *veff32, hipStream_t s);
 // Energy terms, residuals and mixing on the global grid; fragment mixing
 void launch_global_terms(const Geo &g, double *rho_in, const double *rho_out, const double *vh,
                          double mixing, double *part, int n_part, double *scal, hipStream_t s,

@@ -143,7 +143,8 @@ __global__ void __launch_bounds__(256) k_density(Geo g, const long long *__restr
 __global__ void __launch_bounds__(256) k_veff(Geo g, int f0, int f1, const double *__restrict__ vloc,
                                               const double *__restrict__ vh,
                                               const double *__restrict__ rhof_in,
-                                              double *__restrict__ veff) {
+                                              double *__restrict__ veff,
+                                              float *__restrict__ veff32) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long long)(f1 - f0) * g.n) return;
   const int f = f0 + (int)(idx / g.n);
@@ -151,7 +152,9 @@ __global__ void __launch_bounds__(256) k_veff(Geo g, int f0, int f1, const doubl
   const long long gi = global_of_local(g, f, l);
   double exc, vxc;
   pz81(rhof_in[(long long)f * g.n + l], exc, vxc);
-  veff[(long long)f * g.n + l] = vloc[gi] + vh[gi] + vxc;
+  const double v = vloc[gi] + vh[gi] + vxc;
+  veff[(long long)f * g.n + l] = v;
+  if (veff32) veff32[(long long)f * g.n + l] = (float)v;
 }
 
 // Energy terms on rho^in, charge and residuals, then linear mixing of rho_tot.
@@ -311,11 +314,11 @@ void launch_convert(const float *a, double *b, long long n, hipStream_t s) {
 }
 
 void launch_veff(const Geo &g, int f0, int f1, const double *vloc, const double *vh,
-                 const double *rhof_in, double *veff, hipStream_t s) {
+                 const double *rhof_in, double *veff, float *veff32, hipStream_t s) {
   const long long total = (long long)(f1 - f0) * g.n;
   if (total <= 0) return;
   hipLaunchKernelGGL(k_veff, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, f0, f1,
-                     vloc, vh, rhof_in, veff);
+                     vloc, vh, rhof_in, veff, veff32);
 }
 
 void launch_global_terms(const Geo &g, double *rho_in, const double *rho_out, const double *vh,

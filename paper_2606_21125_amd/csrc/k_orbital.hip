@@ -3,6 +3,8 @@
 // the Kleinman-Bylander projection and application, the initial-orbital
 // generator and the band-energy functional with its gradient.  Orbital arrays
 // are FP64 or FP32 (template T); reductions accumulate in FP64.
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace dcdft {
@@ -135,27 +137,38 @@ __global__ void __launch_bounds__(1024) k_hloc_halo(Geo g, const int *__restrict
     }
   }
   win[8] = xb[4LL * plane + t];
-  // planes 5 .. nz-5 come through the prefetch chunks
+  // Planes 5, 6, ... come through the prefetch chunks.  Every load below is
+  // unconditional, with its plane index wrapped or clamped into the box: a
+  // load on one side of a branch makes the compiler drain all outstanding
+  // loads where the paths merge, which would undo the prefetch.
+  auto chunk_plane = [&](int pz) {
+    if (HT) return pz < nz - 4 ? pz : nz - 5;  // end planes come from registers
+    pz = pz < nz ? pz : pz - nz;               // pz <= nz + 2 PD + 3 < 3 nz
+    return pz < nz ? pz : pz - nz;
+  };
+  // V_eff goes through the same chunks (a load needed one iteration after it
+  // was issued would make every older load wait too).
+  auto v_plane = [&](int pz) { return pz < nz ? pz : nz - 1; };
   T nxt[PD];
+  double vn[PD];
 #pragma unroll
-  for (int j = 0; j < PD; ++j) {
-    const int pz = 5 + j;
-    nxt[j] = pz <= nz - 5 ? xb[(long long)pz * plane + t] : (T)0;
-  }
-  double v0 = vb[t];
+  for (int j = 0; j < PD; ++j) nxt[j] = xb[(long long)chunk_plane(5 + j) * plane + t];
+#pragma unroll
+  for (int j = 0; j < PD; ++j) vn[j] = vb[(long long)v_plane(j) * plane + t];
   double dacc = 0.0;
   for (int z0 = 0; z0 < nz; z0 += PD) {
     T fut[PD];
+    double vfut[PD];
 #pragma unroll
-    for (int j = 0; j < PD; ++j) {
-      const int pz = z0 + 5 + PD + j;
-      fut[j] = pz <= nz - 5 ? xb[(long long)pz * plane + t] : (T)0;
-    }
+    for (int j = 0; j < PD; ++j)
+      fut[j] = xb[(long long)chunk_plane(z0 + 5 + PD + j) * plane + t];
+#pragma unroll
+    for (int j = 0; j < PD; ++j) vfut[j] = vb[(long long)v_plane(z0 + PD + j) * plane + t];
 #pragma unroll
     for (int j = 0; j < PD; ++j) {
       const int z = z0 + j;
       if (z >= nz) break;
-      const double v1 = z + 1 < nz ? vb[(long long)(z + 1) * plane + t] : 0.0;
+      const double v0 = vn[j];
       T *pl = lds + (z & 1) * lplane;
       const T c = win[4];
       pl[tp] = c;
@@ -174,30 +187,187 @@ __global__ void __launch_bounds__(1024) k_hloc_halo(Geo g, const int *__restrict
       acc += (T)v0 * c;
       yb[(long long)z * plane + t] = acc;
       dacc += (double)c * (double)acc;
-      v0 = v1;
 #pragma unroll
       for (int k = 0; k < 8; ++k) win[k] = win[k + 1];
       // plane z + 5 enters the window
       const int pz = z + 5;
       T w8 = nxt[j];
-      if (pz > nz - 5) {
-        if (HT) {
-          const int ht = pz >= nz ? pz - nz : pz - (nz - 4);
-          const T *src = pz >= nz ? head : tail;
-          w8 = ht == 0 ? src[0] : (ht == 1 ? src[1] : (ht == 2 ? src[2] : src[3]));
-        } else {
-          w8 = xb[(long long)(pz >= nz ? pz - nz : pz) * plane + t];
-        }
+      if (HT && pz > nz - 5) {
+        const int ht = pz >= nz ? pz - nz : pz - (nz - 4);
+        const T *src = pz >= nz ? head : tail;
+        w8 = ht == 0 ? src[0] : (ht == 1 ? src[1] : (ht == 2 ? src[2] : src[3]));
       }
       win[8] = w8;
     }
 #pragma unroll
-    for (int j = 0; j < PD; ++j) nxt[j] = fut[j];
+    for (int j = 0; j < PD; ++j) {
+      nxt[j] = fut[j];
+      vn[j] = vfut[j];
+    }
   }
   if (dot) {
     dacc = block_sum(dacc, red);
     if (t == 0) dot[B] = g.dv * dacc;
   }
+}
+
+// Vector form of the haloed-plane kernel: each thread owns a run of
+// RX = 16 / sizeof(T) consecutive x points (one 16-byte load, store and LDS
+// access per plane for the run; the x neighbours come from the two runs beside
+// it), opw orbitals share a workgroup (tpo = nx / RX * ny threads each), and
+// V_eff is read in the storage type (its FP32 rounding on the mixed path, which
+// is what the FP32 product uses anyway).  Same sums in the same order as the
+// other variants.  Needs nx % RX == 0, nx, ny >= 4, nz >= 8 and 16-byte
+// aligned arrays.  Bands past the batch are computed as duplicates of the last
+// band (identical values to identical addresses) so every load stays
+// unconditional; only the per-band dot is masked.
+template <typename T, int PD>
+__global__ void __launch_bounds__(1024) k_hloc_vec(Geo g, const int *__restrict__ band_frag,
+                                                   long long b0, long long nbands, int opw,
+                                                   int zs, int vbase, const T *__restrict__ veff,
+                                                   const T *__restrict__ x, T *__restrict__ y,
+                                                   double *__restrict__ dot,
+                                                   double *__restrict__ dot_part) {
+  constexpr int RX = 16 / sizeof(T);
+  typedef T vec __attribute__((ext_vector_type(RX)));
+  extern __shared__ __attribute__((aligned(16))) char lds_vec[];
+  const int nx = g.nl[0], ny = g.nl[1], nz = g.nl[2];
+  const int bx = nx / RX, tpo = bx * ny;
+  const int SX = nx + 8, lplane = (ny + 8) * SX;
+  const int ol = threadIdx.x / tpo, tt = threadIdx.x % tpo;
+  // z segments of one orbital group are consecutive workgroups
+  const int seg = blockIdx.x % zs;
+  const int zlen = (nz + zs - 1) / zs;
+  const int zb = seg * zlen, ze = zb + zlen < nz ? zb + zlen : nz;
+  long long B = b0 + (long long)(blockIdx.x / zs) * opw + ol;
+  const bool valid = B < b0 + nbands;
+  if (!valid) B = b0 + nbands - 1;
+  const int f = band_frag[B];
+  const int ix = (tt % bx) * RX, iy = tt / bx;
+  T *lds = reinterpret_cast<T *>(lds_vec) + (size_t)ol * 2 * lplane;
+  const int tp = (iy + 4) * SX + ix + 4;
+  const int pvec = bx * ny;  // vectors per plane
+  const vec *xb = reinterpret_cast<const vec *>(x + B * (long long)g.n) + tt;
+  vec *yb = reinterpret_cast<vec *>(y + B * (long long)g.n) + tt;
+  const vec *vb = reinterpret_cast<const vec *>(veff + (long long)(f - vbase) * g.n) + tt;
+  const bool xh = ix < 4, xl = ix >= nx - 4, yh = iy < 4, yl = iy >= ny - 4;
+  const T c0 = (T)g.kc[0];
+  T ax[4], ay[4], az[4];
+#pragma unroll
+  for (int k = 1; k <= 4; ++k) {
+    ax[k - 1] = (T)g.kc[k];
+    ay[k - 1] = (T)g.kc[4 + k];
+    az[k - 1] = (T)g.kc[8 + k];
+  }
+  auto wrap = [&](int pz) {  // pz < 3 nz
+    pz = pz < nz ? pz : pz - nz;
+    return pz < nz ? pz : pz - nz;
+  };
+  auto clampz = [&](int pz) { return pz < nz ? pz : nz - 1; };
+  vec win[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) win[k] = xb[(long long)wrap(zb + nz - 4 + k) * pvec];
+  vec nxt[PD], vn[PD];
+#pragma unroll
+  for (int j = 0; j < PD; ++j) nxt[j] = xb[(long long)wrap(zb + 5 + j) * pvec];
+#pragma unroll
+  for (int j = 0; j < PD; ++j) vn[j] = vb[(long long)clampz(zb + j) * pvec];
+  double dacc = 0.0;
+  for (int z0 = zb; z0 < ze; z0 += PD) {
+    vec fut[PD], vfut[PD];
+#pragma unroll
+    for (int j = 0; j < PD; ++j) fut[j] = xb[(long long)wrap(z0 + 5 + PD + j) * pvec];
+#pragma unroll
+    for (int j = 0; j < PD; ++j) vfut[j] = vb[(long long)clampz(z0 + PD + j) * pvec];
+#pragma unroll
+    for (int j = 0; j < PD; ++j) {
+      const int z = z0 + j;
+      if (z >= ze) break;
+      T *pl = lds + (z & 1) * lplane;
+      const vec c = win[4];
+      *reinterpret_cast<vec *>(pl + tp) = c;
+      if (xh) *reinterpret_cast<vec *>(pl + tp + nx) = c;
+      if (xl) *reinterpret_cast<vec *>(pl + tp - nx) = c;
+      if (yh) *reinterpret_cast<vec *>(pl + tp + ny * SX) = c;
+      if (yl) *reinterpret_cast<vec *>(pl + tp - ny * SX) = c;
+      __syncthreads();
+      // e[q] = value at x - 4 + q, q = 0 .. RX + 7
+      T e[RX + 8];
+#pragma unroll
+      for (int q = 0; q < 4 / RX; ++q) {
+        const vec a = *reinterpret_cast<const vec *>(pl + tp - 4 + q * RX);
+        const vec b = *reinterpret_cast<const vec *>(pl + tp + RX + q * RX);
+#pragma unroll
+        for (int i = 0; i < RX; ++i) {
+          e[q * RX + i] = a[i];
+          e[4 + RX + q * RX + i] = b[i];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < RX; ++i) e[4 + i] = c[i];
+      T acc[RX];
+#pragma unroll
+      for (int i = 0; i < RX; ++i) acc[i] = c0 * c[i];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const vec yp = *reinterpret_cast<const vec *>(pl + tp + (k + 1) * SX);
+        const vec ym = *reinterpret_cast<const vec *>(pl + tp - (k + 1) * SX);
+#pragma unroll
+        for (int i = 0; i < RX; ++i) {
+          acc[i] += ax[k] * (e[4 + i + k + 1] + e[4 + i - k - 1]);
+          acc[i] += ay[k] * (yp[i] + ym[i]);
+          acc[i] += az[k] * (win[5 + k][i] + win[3 - k][i]);
+        }
+      }
+      vec out;
+#pragma unroll
+      for (int i = 0; i < RX; ++i) {
+        acc[i] += vn[j][i] * c[i];
+        out[i] = acc[i];
+        dacc += (double)c[i] * (double)acc[i];
+      }
+      yb[(long long)z * pvec] = out;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) win[k] = win[k + 1];
+      win[8] = nxt[j];
+    }
+#pragma unroll
+    for (int j = 0; j < PD; ++j) {
+      nxt[j] = fut[j];
+      vn[j] = vfut[j];
+    }
+  }
+  if (dot) {
+    // per-orbital tree over the orbital's threads (fixed order), in the
+    // (no longer needed) plane area
+    double *red = reinterpret_cast<double *>(lds_vec) + (size_t)ol * tpo;
+    __syncthreads();
+    red[tt] = dacc;
+    __syncthreads();
+    int p2 = 1;
+    while (p2 < tpo) p2 <<= 1;
+    for (int sft = p2 >> 1; sft > 0; sft >>= 1) {
+      if (tt < sft && tt + sft < tpo) red[tt] += red[tt + sft];
+      __syncthreads();
+    }
+    if (tt == 0 && valid) {
+      if (zs == 1)
+        dot[B] = g.dv * red[0];
+      else
+        dot_part[(long long)seg * nbands + (B - b0)] = red[0];
+    }
+  }
+}
+
+// dot[b0 + i] = dV sum over segments (in order) of the segment partials
+__global__ void __launch_bounds__(256) k_dot_segments(Geo g, long long b0, long long nbands,
+                                                      int zs, const double *__restrict__ part,
+                                                      double *__restrict__ dot) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nbands) return;
+  double sum = 0.0;
+  for (int q = 0; q < zs; ++q) sum += part[(long long)q * nbands + i];
+  dot[b0 + i] = g.dv * sum;
 }
 
 template <typename T>
@@ -477,6 +647,43 @@ void launch_halo(const Geo &g, long long nb, const OrbSet &o, int f0, const doub
                        o.band_frag, o.b0(f0), vbase, veff, x, y, dot);
 }
 
+// Orbitals per workgroup of the vector kernel (0: not applicable): wide = the
+// largest count whose thread total is a whole number of waves, otherwise the
+// smallest count that keeps at least 85% of the lanes busy.
+template <typename T>
+int vec_opw(const Geo &g, bool wide) {
+  constexpr int RX = 16 / sizeof(T);
+  if (g.nl[0] % RX || !hloc_halo_ok(g)) return 0;
+  const int tpo = g.nl[0] / RX * g.nl[1];
+  if (tpo > 1024) return 0;
+  const size_t lds1 = 2 * (size_t)(g.nl[1] + 8) * (g.nl[0] + 8) * sizeof(T);
+  const int top = std::min(4, 1024 / tpo);
+  if (wide) {
+    for (int opw = top; opw >= 1; --opw)
+      if (opw * lds1 <= 65536 && (opw * tpo) % 64 == 0) return opw;
+  }
+  for (int opw = 1; opw <= top; ++opw) {
+    if (opw * lds1 > 65536) break;
+    const int threads = opw * tpo, lanes = (threads + 63) / 64 * 64;
+    if (threads >= 0.85 * lanes) return opw;
+  }
+  return lds1 <= 65536 ? 1 : 0;
+}
+
+template <typename T, int PD>
+void launch_vec(const Geo &g, long long nb, int opw, int zs, const OrbSet &o, int f0,
+                const T *veffT, const T *x, T *y, hipStream_t s, double *dot, double *dot_part,
+                int vbase) {
+  const int tpo = g.nl[0] / (16 / (int)sizeof(T)) * g.nl[1];
+  const size_t lds = (size_t)opw * 2 * (g.nl[1] + 8) * (g.nl[0] + 8) * sizeof(T);
+  const unsigned grid = (unsigned)((nb + opw - 1) / opw * zs);
+  hipLaunchKernelGGL((k_hloc_vec<T, PD>), dim3(grid), dim3(opw * tpo), lds, s, g, o.band_frag,
+                     o.b0(f0), nb, opw, zs, vbase, veffT, x, y, dot, dot_part);
+  if (dot && zs > 1)
+    hipLaunchKernelGGL(k_dot_segments, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, g,
+                       o.b0(f0), nb, zs, dot_part, dot);
+}
+
 }  // namespace
 
 bool hloc_halo_ok(const Geo &g) {
@@ -487,13 +694,29 @@ bool hloc_halo_ok(const Geo &g) {
 }
 
 template <typename T>
-void launch_hloc(const Geo &g, const OrbSet &o, int f0, int f1, const double *veff, const T *x,
-                 T *y, hipStream_t s, double *dot, int vbase) {
+void launch_hloc(const Geo &g, const OrbSet &o, int f0, int f1, const double *veff,
+                 const T *veffT, const T *x, T *y, hipStream_t s, double *dot, int vbase,
+                 double *dot_part) {
   const long long nb = o.nb(f0, f1);
   if (nb <= 0) return;
   const int plane = g.nl[0] * g.nl[1];
+  int hv = g.hloc_variant;
+  if (hv == HLOC_VEC || hv == HLOC_VEC_WIDE || hv == HLOC_VEC_Z2 || hv == HLOC_VEC_Z3) {
+    const int opw = vec_opw<T>(g, hv == HLOC_VEC_WIDE);
+    const int zs = hv == HLOC_VEC_Z2 ? 2 : (hv == HLOC_VEC_Z3 ? 3 : 1);
+    const bool aligned = ((uintptr_t)x % 16 == 0) && ((uintptr_t)y % 16 == 0) && veffT &&
+                         ((uintptr_t)veffT % 16 == 0);
+    // z segments need nz / zs >= 4 and, with a dot, a partial buffer of
+    // kHlocZsMax x nb doubles
+    const bool zs_ok = zs == 1 || (g.nl[2] / zs >= 4 && (!dot || dot_part));
+    if (opw > 0 && aligned && zs_ok) {
+      launch_vec<T, 1>(g, nb, opw, zs, o, f0, veffT, x, y, s, dot, dot_part, vbase);
+      return;
+    }
+    hv = HLOC_HALO_PD2;  // same results
+  }
   if (hloc_halo_ok(g)) {
-    switch (g.hloc_variant) {
+    switch (hv) {
       case HLOC_HALO_PD2: launch_halo<T, 2, false>(g, nb, o, f0, veff, x, y, s, dot, vbase); return;
       case HLOC_HALO_PD3: launch_halo<T, 3, false>(g, nb, o, f0, veff, x, y, s, dot, vbase); return;
       case HLOC_HALO_PD4: launch_halo<T, 4, false>(g, nb, o, f0, veff, x, y, s, dot, vbase); return;
@@ -540,7 +763,8 @@ void launch_band_energy(const Geo &g, int nb, const T *psi, const T *hpsi, const
 
 #define DCDFT_INSTANTIATE(T)                                                                   \
   template void launch_hloc<T>(const Geo &, const OrbSet &, int, int, const double *,        \
-                               const T *, T *, hipStream_t, double *, int);                  \
+                               const T *, const T *, T *, hipStream_t, double *, int,        \
+                               double *);                                                    \
   template void launch_kb_project<T>(const Geo &, const OrbSet &, const KBTables &, int, int, \
                                      const T *, double *, double *, hipStream_t);            \
   template void launch_kb_apply<T>(const Geo &, const OrbSet &, const KBTables &, int, int,   \

@@ -80,17 +80,23 @@ def _run(d, steps):
     return info, d.dcdft_density(), [d.dcdft_eigenvalues(a)[0] for a in range(d.n_fragments)]
 
 
-@pytest.mark.parametrize("rot_tiles,chunk_scale", [(2, 1), (8, 2), (4, 0.5)])
-def test_rotation_tiles_and_gram_chunks_keep_results(rot_tiles, chunk_scale):
+@pytest.mark.parametrize("hloc,rot_tiles,chunk_scale", [(None, 2, 1), (None, 8, 2),
+                                                        (None, 4, 0.5), ("vec", 4, 1),
+                                                        ("vec_z2", 4, 1), ("vec_z3", 2, 1),
+                                                        ("plane", 4, 1)])
+def test_launch_shapes_keep_results(hloc, rot_tiles, chunk_scale):
+    """Every launch shape, through full SCF steps (the stencil's fused per-band
+    dot included), stays within the FP64 parity tolerances of the default."""
     require_gpu()
-    from paper_2606_21125_amd import DCDFT
+    from paper_2606_21125_amd import DCDFT, HLOC_VARIANTS
     cfg = workloads.config(1)
     with DCDFT.from_config(cfg) as d0:
         i0, rho0, eps0 = _run(d0, 3)
     with DCDFT.from_config(cfg) as d1:
         launch = d1.dcdft_get_launch()
         ch = max(1, min(launch["gram_chunks_max"], int(launch["gram_chunks"] * chunk_scale)))
-        d1.dcdft_set_launch(launch["hloc_variant"], rot_tiles, ch)
+        hv = launch["hloc_variant"] if hloc is None else HLOC_VARIANTS.index(hloc)
+        d1.dcdft_set_launch(hv, rot_tiles, ch)
         i1, rho1, eps1 = _run(d1, 3)
     for a, b in zip(i0, i1):
         assert abs(a["mu"] - b["mu"]) <= 1e-10
