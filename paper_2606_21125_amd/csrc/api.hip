@@ -867,10 +867,15 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   const bool mixed = c->precision == DCDFT_PREC_MIXED;
   c->elem = mixed ? sizeof(float) : sizeof(double);
   {
+    // m_pad zeroed rows of n points after the last band: kernels may read rows
+    // up to the padded count of any fragment without a per-lane clamp
+    const long long pad = (long long)c->m_pad * g.n;
     void **orb[] = {&c->d_psi, &c->d_w, &c->d_p, &c->d_q};
     for (void **a : orb) {
       char *q = nullptr;
-      hipError_t e_ = dalloc(c, &q, (size_t)norb * c->elem);
+      hipError_t e_ = dalloc(c, &q, (size_t)(norb + pad) * c->elem);
+      if (e_ == hipSuccess)
+        e_ = hipMemset(q + (size_t)norb * c->elem, 0, (size_t)pad * c->elem);
       if (e_ != hipSuccess) {
         c->last_error = "orbital array allocation failed";
         return fail(e_ == hipErrorOutOfMemory ? DCDFT_ERR_OOM : DCDFT_ERR_HIP);

@@ -45,6 +45,9 @@ struct Mfma<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   __device__ static inline int row(int kk, int r) { return kk + 4 * r; }
+  // row(kk, r) = row_u(r) + row_l(kk): wave-uniform and lane parts
+  __device__ static inline int row_u(int r) { return 4 * r; }
+  __device__ static inline int row_l(int kk) { return kk; }
 };
 
 template <>
@@ -55,6 +58,8 @@ struct Mfma<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   __device__ static inline int row(int kk, int r) { return 4 * kk + r; }
+  __device__ static inline int row_u(int r) { return r; }
+  __device__ static inline int row_l(int kk) { return 4 * kk; }
 };
 
 // LDS row stride for an MP-wide operand block: the smallest S >= MP with

@@ -14,20 +14,51 @@ namespace {
 // same R), with optional per-band reductions of the stored values v over the
 // workgroup's points: RF_DOT_SELF sums v^2, RF_DOT_W sums v * wdot, RF_CORE
 // restricts both to core points.  RF_TRI skips the zero blocks of a
-// lower-triangular R.  R = M^T (trans 0) or M (trans 1) is staged in LDS once per
-// workgroup; each wave handles NT tiles of 16 points and every output orbital,
-// so y may alias x or z.  Reductions go out as one partial per workgroup:
-// dpart[(f * wpf + wg) * 2 * m_pad + k * m_pad + j], k = 0 (self), 1 (wdot).
-enum { RF_DOT_SELF = 1, RF_DOT_W = 2, RF_CORE = 4, RF_TWO = 8, RF_TRI = 16 };
+// lower-triangular R; RF_Z says z is given.  R = M^T (trans 0) or M (trans 1)
+// is staged in LDS once per workgroup; each wave handles NT tiles of 16 points
+// and every output orbital, so y may alias x or z.  Per tile a wave issues the
+// loads of the next tile's operand rows before its own matrix-core products
+// (and the z / wdot rows of its own outputs), so one tile of loads is always in
+// flight.  Loads are unconditional (indices clamped into the arrays, values
+// masked after): a load under a branch makes the compiler drain every
+// outstanding load where the paths merge.  The per-band sums of a tile are
+// reduced over the 16 point lanes with row-local DPP moves and added into a
+// per-wave LDS row by one lane, then the waves are added in order: one FP64
+// partial per workgroup, dpart[(f * wpf + wg) * 2 * m_pad + k * m_pad + j],
+// k = 0 (self), 1 (wdot).
+enum { RF_DOT_SELF = 1, RF_DOT_W = 2, RF_CORE = 4, RF_TWO = 8, RF_TRI = 16, RF_Z = 32 };
+
+template <int CTRL>
+__device__ inline double dpp_double(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 16 lanes of a DPP row (rotate by 8, by 4, then quad swaps);
+// every lane of the row gets a sum of all 16 values in a fixed order.
+__device__ inline double row16_sum(double v) {
+  v += dpp_double<0x128>(v);  // row_ror:8
+  v += dpp_double<0x124>(v);  // row_ror:4
+  v += dpp_double<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_double<0xB1>(v);   // quad_perm [1,0,3,2]
+  return v;
+}
 
 template <typename T, int TM, int NT, int FL>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && TM < 5 ? 4 : 2, 8)))
 k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int trans,
             const T *x, const T *z, double cz, double cm, T *y, const T *x2, T *y2,
             const T *wdot, double *__restrict__ dpart) {
   typedef Mfma<T> MM;
   constexpr int MP = 16 * TM;
   constexpr int S = lds_stride(MP);
+  constexpr bool DOTS = (FL & (RF_DOT_SELF | RF_DOT_W)) != 0;
+  constexpr int NARR = (FL & RF_TWO) ? 2 : 1;
+  constexpr int NITEM = NT * NARR;
+  static_assert(!(FL & RF_TWO) || !(FL & (RF_Z | RF_DOT_SELF | RF_DOT_W)),
+                "the second array is rotated without z or reductions");
   __shared__ T Rt[MP * S];
   __shared__ double red[4][2][MP];
   const int f = f0 + blockIdx.x / wpf;
@@ -41,83 +72,98 @@ k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int 
     if (i < mf && j < mf) v = trans ? Mf[j * mp + i] : Mf[i * mp + j];
     Rt[i * S + j] = (T)v;
   }
+  if (DOTS)
+    for (int e = lane; e < 2 * MP; e += 64) red[wave][e / MP][e % MP] = 0.0;
   __syncthreads();
   const long long base = o.moff[f] * (long long)g.n;
   const int jl = lane & 15, kk = lane >> 4;
   const T tcm = (T)cm, tcz = (T)cz;
-  double ds[TM][4], dw[TM][4];
+  const int pw0 = (wg * 4 + wave) * NT * 16;  // first point of the wave
+  // Addresses split into a wave-uniform row part and one lane offset (rows up
+  // to the padded count exist: the arrays carry m_pad spare rows).
+  // operand rows i = 4 s + kk of item it at the lane's point
+  auto load_rows = [&](int it, T *bx) {
+    const int u = it / NARR, arr = it % NARR;
+    const int pc = pw0 + u * 16 + jl;
+    const bool pin = pc < g.n;
+    const int lo = kk * g.n + (pin ? pc : g.n - 1);
+    const T *xs = (arr ? x2 : x) + base;
 #pragma unroll
-  for (int a = 0; a < TM; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) ds[a][b] = dw[a][b] = 0.0;
-  for (int u = 0; u < NT; ++u) {
-    const int p0 = ((wg * 4 + wave) * NT + u) * 16;
+    for (int s = 0; s < TM * 4; ++s) {
+      const T v = (xs + (long long)(4 * s) * g.n)[lo];
+      bx[s] = (4 * s + kk < mf && pin) ? v : (T)0;
+    }
+  };
+  T bx[TM * 4];
+  load_rows(0, bx);
+  for (int it = 0; it < NITEM; ++it) {
+    const int u = it / NARR, arr = it % NARR;
+    const int p0 = pw0 + u * 16;
     if (p0 >= g.n) break;
     const int pc = p0 + jl;
     const bool pin = pc < g.n;
     const bool core = (FL & RF_CORE) ? is_core_point(g, pc) : true;
-#pragma unroll
-    for (int arr = 0; arr < ((FL & RF_TWO) ? 2 : 1); ++arr) {
-      const T *xs = arr ? x2 : x;
-      T *ys = arr ? y2 : y;
-      T bx[TM * 4];
-#pragma unroll
-      for (int s = 0; s < TM * 4; ++s) {
-        const int i = 4 * s + kk;
-        bx[s] = (i < mf && pin) ? xs[base + (long long)i * g.n + pc] : (T)0;
-      }
-      typename MM::acc_t acc[TM];
-#pragma unroll
-      for (int j = 0; j < TM; ++j) acc[j] = MM::zero();
-#pragma unroll
-      for (int s = 0; s < TM * 4; ++s) {
-        const T *rrow = Rt + (4 * s + kk) * S + jl;
-#pragma unroll
-        for (int jt = 0; jt < TM; ++jt) {
-          if ((FL & RF_TRI) && s > 4 * jt + 3) continue;
-          acc[jt] = MM::mma(rrow[jt * 16], bx[s], acc[jt]);
-        }
-        // keep the operand reads of later steps from being hoisted (register pressure)
-        if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-      }
+    // output rows j = jt*16 + row_u(rr) + row_l(kk) of this lane
+    const int lo_out = MM::row_l(kk) * g.n + (pin ? pc : g.n - 1);
+    T zv[TM][4], wv[TM][4];
+    if (FL & RF_Z) {
 #pragma unroll
       for (int jt = 0; jt < TM; ++jt)
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          const int j = jt * 16 + MM::row(kk, rr);
-          if (j < mf && pin) {
-            const long long e = base + (long long)j * g.n + pc;
-            T v = tcm * acc[jt][rr];
-            if (!arr && z) v += tcz * z[e];
-            ys[e] = v;
-            if (!arr && core) {
-              if (FL & RF_DOT_SELF) ds[jt][rr] += (double)v * (double)v;
-              if (FL & RF_DOT_W) dw[jt][rr] += (double)v * (double)wdot[e];
-            }
-          }
-        }
+        for (int rr = 0; rr < 4; ++rr)
+          zv[jt][rr] = (z + base + (long long)(jt * 16 + MM::row_u(rr)) * g.n)[lo_out];
     }
-  }
-  if (FL & (RF_DOT_SELF | RF_DOT_W)) {
-    // sum over the 16 lanes that share a row, then over the 4 waves in LDS
+    if (FL & RF_DOT_W) {
+#pragma unroll
+      for (int jt = 0; jt < TM; ++jt)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+          wv[jt][rr] = (wdot + base + (long long)(jt * 16 + MM::row_u(rr)) * g.n)[lo_out];
+    }
+    T bn[TM * 4];
+    if (it + 1 < NITEM) load_rows(it + 1, bn);
+    typename MM::acc_t acc[TM];
+#pragma unroll
+    for (int jt = 0; jt < TM; ++jt) acc[jt] = MM::zero();
+#pragma unroll
+    for (int s = 0; s < TM * 4; ++s) {
+      const T *rrow = Rt + (4 * s + kk) * S + jl;
+#pragma unroll
+      for (int jt = 0; jt < TM; ++jt) {
+        if ((FL & RF_TRI) && s > 4 * jt + 3) continue;
+        acc[jt] = MM::mma(rrow[jt * 16], bx[s], acc[jt]);
+      }
+      // keep later operand reads from being hoisted (register pressure)
+      if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+    T *ys = arr ? y2 : y;
 #pragma unroll
     for (int jt = 0; jt < TM; ++jt)
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-        for (int off = 1; off < 16; off <<= 1) {
-          if (FL & RF_DOT_SELF) ds[jt][rr] += __shfl_xor(ds[jt][rr], off, 64);
-          if (FL & RF_DOT_W) dw[jt][rr] += __shfl_xor(dw[jt][rr], off, 64);
+      for (int rr = 0; rr < 4; ++rr) {
+        const int j = jt * 16 + MM::row(kk, rr);
+        const bool ok = j < mf && pin;
+        T v = tcm * acc[jt][rr];
+        if (FL & RF_Z) v += tcz * zv[jt][rr];
+        if (ok) (ys + base + (long long)(jt * 16 + MM::row_u(rr)) * g.n)[lo_out] = v;
+        if (DOTS) {
+          const bool use = ok && core;
+          if (FL & RF_DOT_SELF) {
+            const double d = row16_sum(use ? (double)v * (double)v : 0.0);
+            if (jl == 0) red[wave][0][j] += d;
+          }
+          if (FL & RF_DOT_W) {
+            const double d = row16_sum(use ? (double)v * (double)wv[jt][rr] : 0.0);
+            if (jl == 0) red[wave][1][j] += d;
+          }
         }
-    if (jl == 0) {
+      }
+    if (it + 1 < NITEM) {
 #pragma unroll
-      for (int jt = 0; jt < TM; ++jt)
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          red[wave][0][jt * 16 + MM::row(kk, rr)] = ds[jt][rr];
-          red[wave][1][jt * 16 + MM::row(kk, rr)] = dw[jt][rr];
-        }
+      for (int s = 0; s < TM * 4; ++s) bx[s] = bn[s];
     }
+  }
+  if (DOTS) {
     __syncthreads();
     double *out = dpart + ((long long)f * wpf + wg) * 2 * mp;
     for (int e = threadIdx.x; e < 2 * MP; e += blockDim.x) {
@@ -187,7 +233,8 @@ struct Vec4Load<float> {
 };
 
 template <typename T, int TM, int MODE, bool SYM, bool VEC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 || TM < 5 ? 4 : 2, 8)))
 k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a2, T *a3,
         const T *a4, const double *__restrict__ c1, const double *__restrict__ c2,
         double *__restrict__ part) {
@@ -195,100 +242,137 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a
   constexpr int MP = 16 * TM;
   constexpr int NTILE = SYM ? TM * (TM + 1) / 2 : TM * TM;
   constexpr int PER_WAVE = (NTILE + 3) / 4;
+  // operand items of one step: MP rows x KT/4 runs of 4 points, over 256 threads
+  constexpr int NI = (MP * (kGramKT / 4) + 255) / 256;
+  // arrays read per item: PLAIN x (and y), DIR x, G, P_prev, UPDATE Psi, P, W, Q
+  constexpr int NA = MODE == GM_PLAIN ? (SYM ? 1 : 2) : (MODE == GM_DIR ? 3 : 4);
   __shared__ T Xs[MP * kGramLd];
   __shared__ T Ys[SYM ? 1 : MP * kGramLd];
   const int f = f0 + blockIdx.x / chunks;
   const int c = blockIdx.x % chunks;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int mf = o.m[f];
   const int mp = o.m_pad;
   const long long base = o.moff[f] * (long long)g.n;
   const int p_begin = c * kchunk;
   const int p_end = min(p_begin + kchunk, g.n);
+  // tiles of this wave: the (wave + 4 k)-th output tile in row order (upper
+  // triangle only when SYM); fixed indexing keeps the table in registers
   int tI[PER_WAVE], tJ[PER_WAVE];
-  {
-    int k = 0, q = 0;
+#pragma unroll
+  for (int k = 0; k < PER_WAVE; ++k) {
+    const int q = wave + 4 * k;
+    tI[k] = -1;
+    tJ[k] = -1;
+    int idx = 0;
 #pragma unroll
     for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
       for (int tj = 0; tj < TM; ++tj) {
         if (SYM && ti > tj) continue;
-        if (q % 4 == wave && k < PER_WAVE) {
+        if (idx == q) {
           tI[k] = ti;
           tJ[k] = tj;
-          ++k;
         }
-        ++q;
+        ++idx;
       }
-#pragma unroll
-    for (; k < PER_WAVE; ++k) {
-      tI[k] = -1;
-      tJ[k] = -1;
-    }
   }
   typename MM::acc_t acc[PER_WAVE];
 #pragma unroll
   for (int k = 0; k < PER_WAVE; ++k) acc[k] = MM::zero();
   const T *Yl = SYM ? Xs : Ys;
+  auto src = [&](int a) -> const T * {
+    return a == 0 ? x : (a == 1 ? (MODE == GM_DIR ? a2 : a1) : (a == 2 ? (MODE == GM_DIR ? a1 : a3) : a4));
+  };
+  // Raw operand values of one step, loaded a step ahead of their use.  Rows up
+  // to MP exist in the arrays (m_pad spare rows at the end), points outside
+  // the chunk are read at a clamped index; both are masked at commit.
+  // (prefetch only while the raw values fit in 48 registers per lane)
+  constexpr bool PF = NI * NA * 4 * sizeof(T) <= 192;
+  T raw[NI][NA][4];
+  auto load_item = [&](int k, int p0) {
+    {
+      const int it = threadIdx.x + 256 * k;
+      const int row = it / (kGramKT / 4) < MP ? it / (kGramKT / 4) : MP - 1;
+      const int p = p0 + (it % (kGramKT / 4)) * 4;
+      const int lo = row * g.n;  // lane offset (fits: m_pad n < 2^31)
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        const T *rp = src(a) + base;  // wave-uniform
+        if (VEC) {
+          Vec4Load<T>::load(rp + (lo + (p < p_end ? p : p_begin)), raw[k][a]);
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) raw[k][a][t] = rp[lo + (p + t < p_end ? p + t : p_begin)];
+        }
+      }
+    }
+  };
+  auto load_step = [&](int p0) {
+#pragma unroll
+    for (int k = 0; k < NI; ++k) load_item(k, p0);
+  };
+  if (PF) load_step(p_begin);
   for (int p0 = p_begin; p0 < p_end; p0 += kGramKT) {
-    __syncthreads();
-    for (int it = threadIdx.x; it < MP * (kGramKT / 4); it += blockDim.x) {
+    __syncthreads();  // the previous step's products are done with the LDS rows
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+      if (!PF) load_item(k, p0);
+      const int it = threadIdx.x + 256 * k;
       const int row = it / (kGramKT / 4);
       const int pq = (it % (kGramKT / 4)) * 4;
       const int p = p0 + pq;
-      T xv[4] = {0, 0, 0, 0}, yv[4] = {0, 0, 0, 0};
-      if (row < mf) {
-        const long long ro = base + (long long)row * g.n;
-        const bool full = VEC && (p + 3 < p_end);
-        T v1[4], v2[4], v3[4], v4[4];
-        auto ld4 = [&](const T *src, T *dst) {
-          if (full) Vec4Load<T>::load(src + ro + p, dst);
-          else
-            for (int t = 0; t < 4; ++t) dst[t] = (p + t < p_end) ? src[ro + p + t] : (T)0;
-        };
-        auto st4 = [&](T *dstp, const T *val) {
-          if (full) Vec4Load<T>::store(dstp + ro + p, val);
-          else
-            for (int t = 0; t < 4; ++t)
-              if (p + t < p_end) dstp[ro + p + t] = val[t];
-        };
-        if (MODE == GM_PLAIN) {
-          ld4(x, xv);
-          if (!SYM) ld4(a1, yv);
-        } else if (MODE == GM_DIR) {
-          ld4(x, xv);
-          ld4(a2, v2);
-          const T b = (T)c1[o.moff[f] + row];
-          if (b != (T)0) {
-            ld4(a1, v1);
-            for (int t = 0; t < 4; ++t) yv[t] = b * v1[t] - v2[t];
-          } else {
-            for (int t = 0; t < 4; ++t) yv[t] = -v2[t];
-          }
-          st4(a1, yv);
-        } else {
-          ld4(x, v1);
-          ld4(a1, v2);
-          ld4(a3, v3);
-          ld4(a4, v4);
-          const T cs = (T)c1[o.moff[f] + row], sn = (T)c2[o.moff[f] + row];
-          for (int t = 0; t < 4; ++t) {
-            xv[t] = cs * v1[t] + sn * v2[t];
-            v3[t] = cs * v3[t] + sn * v4[t];
-          }
-          st4(x, xv);
-          st4(a3, v3);
+      if (row >= MP) continue;
+      const bool rin = row < mf;
+      T xv[4], yv[4];
+      if (MODE == GM_PLAIN) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          xv[t] = raw[k][0][t];
+          yv[t] = SYM ? (T)0 : raw[k][NA - 1][t];
         }
-        for (int t = 0; t < 4; ++t)
-          if (p + t >= p_end) xv[t] = yv[t] = (T)0;
+      } else if (MODE == GM_DIR) {
+        // P = beta P_prev - G (beta = 0: P = -G without reading P_prev's value)
+        const T b = (T)c1[o.moff[f] + (rin ? row : 0)];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          xv[t] = raw[k][0][t];
+          yv[t] = b != (T)0 ? b * raw[k][2][t] - raw[k][1][t] : -raw[k][1][t];
+        }
+      } else {
+        const T cs = (T)c1[o.moff[f] + (rin ? row : 0)];
+        const T sn = (T)c2[o.moff[f] + (rin ? row : 0)];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          xv[t] = cs * raw[k][0][t] + sn * raw[k][1][t];
+          yv[t] = cs * raw[k][2][t] + sn * raw[k][3][t];
+        }
+      }
+      if (MODE != GM_PLAIN && rin) {
+        const long long ro = base + (long long)row * g.n;
+        T *d0 = MODE == GM_DIR ? a1 : x;
+        const T *v0 = MODE == GM_DIR ? yv : xv;
+        if (VEC && p + 3 < p_end) {
+          Vec4Load<T>::store(d0 + ro + p, v0);
+          if (MODE == GM_UPDATE) Vec4Load<T>::store(a3 + ro + p, yv);
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (p + t < p_end) {
+              d0[ro + p + t] = v0[t];
+              if (MODE == GM_UPDATE) a3[ro + p + t] = yv[t];
+            }
+        }
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        Xs[row * kGramLd + pq + t] = xv[t];
-        if (!SYM) Ys[row * kGramLd + pq + t] = yv[t];
+        const bool ok = rin && p + t < p_end;
+        Xs[row * kGramLd + pq + t] = ok ? xv[t] : (T)0;
+        if (!SYM) Ys[row * kGramLd + pq + t] = ok ? yv[t] : (T)0;
       }
     }
     __syncthreads();
+    if (PF && p0 + kGramKT < p_end) load_step(p0 + kGramKT);
     const int r = lane & 15, kk = lane >> 4;
 #pragma unroll
     for (int t = 0; t < kGramKT / 4; ++t) {
@@ -728,7 +812,7 @@ void launch_rot_residual(const Geo &g, const OrbSet &o, int f0, int f1, const do
                          const T *psi, const T *w, T *gout, double *dpart, double *gamma,
                          hipStream_t s) {
   const int wpf = rot_wpf(g);
-  rot_fused_tm<T, RF_DOT_SELF>(g, o, f0, f1, wpf, Hs, 0, psi, w, 1.0, -1.0, gout, nullptr,
+  rot_fused_tm<T, RF_DOT_SELF | RF_Z>(g, o, f0, f1, wpf, Hs, 0, psi, w, 1.0, -1.0, gout, nullptr,
                                nullptr, nullptr, dpart, s);
   band_reduce(g, o, f0, f1, wpf, dpart, gamma, nullptr, s);
 }
@@ -738,7 +822,8 @@ void launch_rot_project_out(const Geo &g, const OrbSet &o, int f0, int f1, const
                             const T *psi, T *p, const T *w, double *dpart, double *nu,
                             double *pw, hipStream_t s) {
   const int wpf = rot_wpf(g);
-  rot_fused_tm<T, RF_DOT_SELF | RF_DOT_W>(g, o, f0, f1, wpf, X, 0, psi, p, 1.0, -1.0, p, nullptr,
+  rot_fused_tm<T, RF_DOT_SELF | RF_DOT_W | RF_Z>(g, o, f0, f1, wpf, X, 0, psi, p, 1.0, -1.0, p,
+                                                 nullptr,
                                           nullptr, w, dpart, s);
   band_reduce(g, o, f0, f1, wpf, dpart, nu, pw, s);
 }
