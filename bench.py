@@ -33,33 +33,70 @@ def workload_config(k: int):
     return workloads.config(k)
 
 
-def cpu_baseline(cfg, max_workers: int = 16) -> dict:
-    """The FP64 oracle on host cores, on a bounded sample of one SCF iteration:
-    the global Hartree solve plus one fragment eigensolve per worker process
-    (BLAS single-threaded per worker), scaled to all fragments."""
-    import numpy as np
+def cpu_baseline(cfg, max_workers: int = 16, min_seconds: float = 10.0) -> dict:
+    """The FP64 oracle as it stands on host cores: whole SCF iterations of the
+    same workload (fragment eigensolves spread over worker processes, one BLAS
+    thread each), repeated until at least min_seconds of wall time."""
     from threadpoolctl import threadpool_limits
 
     import oracle
 
     workers = max(1, min(max_workers, os.cpu_count() or 1, cfg.n_fragments))
     o = oracle.OracleSCF(cfg, workers=workers)
-    t0 = time.perf_counter()
-    v_h = oracle.poisson_fd(o.rho_in, o.h)
-    for a in range(cfg.n_fragments):
-        o.veff(a, v_h)
-    t_global = time.perf_counter() - t0
-    sample = list(range(min(cfg.n_fragments, 2 * workers)))
+    steps = 0
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        o.solve_fragments(v_h, alphas=sample)
-        t_sample = time.perf_counter() - t0
-    t_iter = t_global + t_sample * cfg.n_fragments / len(sample)
-    return {"value": 1.0 / t_iter, "unit": "SCF iter/s", "cores": workers, "kind": "oracle",
-            "sample": (f"one SCF iteration of the same workload: Hartree solve and all fragment "
-                       f"potentials, plus {len(sample)} of {cfg.n_fragments} fragment "
-                       f"eigensolves on {workers} processes (1 BLAS thread each), scaled to all "
-                       f"fragments; measured {t_global + t_sample:.1f} s wall")}
+        while True:
+            o.step()
+            steps += 1
+            elapsed = time.perf_counter() - t0
+            if elapsed >= min_seconds:
+                break
+    return {"value": steps / elapsed, "unit": "SCF iter/s", "cores": workers, "kind": "oracle",
+            "sample": (f"{steps} whole SCF iterations of the same workload (all "
+                       f"{cfg.n_fragments} fragment eigensolves on {workers} processes, 1 BLAS "
+                       f"thread each), {elapsed:.1f} s wall")}
+
+
+HLOC_KERNEL = {"plane": "k_hloc<{t}>", "halo_pd2": "k_hloc_halo<{t}, {nx}, 2, false>",
+               "halo_pd3": "k_hloc_halo<{t}, {nx}, 3, false>",
+               "halo_pd4": "k_hloc_halo<{t}, {nx}, 4, false>",
+               "halo_pd2_ends": "k_hloc_halo<{t}, {nx}, 2, true>"}
+
+
+def hloc_kernel_name(variant: str, prec_mixed: bool, box) -> str:
+    """Kernel the library launches for a stencil variant on this machine shape."""
+    t = "float" if prec_mixed else "double"
+    nx, ny, nz = box
+    halo = nx >= 4 and ny >= 4 and nz >= 8
+    if variant.startswith("vec"):
+        rx = 4 if prec_mixed else 2
+        if halo and nx % rx == 0:
+            return f"k_hloc_vec<{t}, 1>"
+        variant = "halo_pd2"
+    if variant != "plane" and not halo:
+        variant = "plane"
+    return HLOC_KERNEL[variant].format(t=t, nx=nx if nx in (24, 32) else 0)
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summaries, if they were
+    taken on the current stencil source for this kernel and workload."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2606_21125_amd", "csrc", "k_orbital.hip")
+    with open(src, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_counters.md"))):
+        with open(path) as fh:
+            for line in fh:
+                if not line.startswith("traffic:"):
+                    continue
+                parts = [p.strip() for p in line[len("traffic:"):].split("|")]
+                if len(parts) == 4 and parts[0] == kernel and parts[1] == workload and \
+                        parts[3] == sha:
+                    return float(parts[2]), os.path.relpath(path, ROOT)
+    return None, None
 
 
 def main() -> int:
@@ -91,16 +128,17 @@ def main() -> int:
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         return 1
-    from paper_2606_21125_amd import (DCDFT, KERNEL_GRAM, KERNEL_HLOC, KERNEL_ROTATE, PREC_FP64,
-                                      PREC_MIXED)
+    from paper_2606_21125_amd import (DCDFT, HLOC_VARIANTS, KERNEL_GRAM, KERNEL_HLOC,
+                                      KERNEL_ROTATE, PREC_FP64, PREC_MIXED)
     prec = PREC_MIXED if args.precision == "mixed" else PREC_FP64
 
     if args.copy_probe_mb > 0:
+        # one elementwise kernel that reads and writes n * 8 bytes (y = 1.0 * x)
         n = int(args.copy_probe_mb * 1e6) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         print(f"[bench] copy probe: {n * 8} bytes read, {n * 8} bytes written",
               file=sys.stderr, flush=True)
@@ -109,6 +147,7 @@ def main() -> int:
     print(f"[bench] setup {cfg.name}: {cfg.system.n_atoms} atoms, grid {cfg.n_grid}, "
           f"{cfg.n_fragments} fragments of {cfg.fragment_shape}", file=sys.stderr, flush=True)
     d = DCDFT.from_config(cfg, batched=args.batched, precision=prec)
+    launch0 = d.dcdft_get_launch()
     tune = None
     if not args.no_autotune:
         tune = d.dcdft_autotune(args.tune_cache)
@@ -144,9 +183,14 @@ def main() -> int:
     g_tf = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
     r = kt["rotate"]
     r_gbs = r["bytes"] / (r["ms"] * 1e-3) / 1e9 if r["ms"] > 0 else 0.0
+    variant = tune["hloc_variant"] if tune else HLOC_VARIANTS[launch0["hloc_variant"]]
+    kname = hloc_kernel_name(variant, prec != PREC_FP64, cfg.fragment_shape)
+    traffic, traffic_src = recorded_traffic(kname, cfg.name)
     roofline = {"bound": "hbm", "achieved": round(h_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(h_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"k_hloc (fragment H_loc psi, {'FP32' if prec != PREC_FP64 else 'FP64'})",
+                "frac": round(h_gbs / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic),
+                "traffic_source": traffic_src,
+                "kernel": kname,
                 "avg_launch_ms": round(h["ms"] / max(1, h["launches"]), 4),
                 "bytes_per_launch": h["bytes"] / max(1, h["launches"]),
                 "measured": f"HIP events around every launch over {n_timed} eager steps "
