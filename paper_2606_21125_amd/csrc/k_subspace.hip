@@ -13,10 +13,12 @@ namespace {
 // Fused rotation: y = cz z + cm R^T x (and, with RF_TWO, y2 = cm R^T x2 with the
 // same R), with optional per-band reductions of the stored values v over the
 // workgroup's points: RF_DOT_SELF sums v^2, RF_DOT_W sums v * wdot, RF_CORE
-// restricts both to core points.  RF_TRI skips the zero blocks of a
-// lower-triangular R; RF_Z says z is given.  R = M^T (trans 0) or M (trans 1)
-// is staged in LDS once per workgroup; each wave handles NT tiles of 16 points
-// and every output orbital, so y may alias x or z.  Per tile a wave issues the
+// restricts both to core points; RF_Z says z is given.  R = M^T (trans 0) or M
+// (trans 1) is staged in LDS once per workgroup, transposed so that the R values
+// one lane feeds to the matrix cores for an output tile are contiguous (the
+// lane group kk takes the input orbitals kk*4TM .. kk*4TM + 4TM - 1); each wave
+// handles NT tiles of 16 points and every output orbital, so y may alias x or
+// z.  Per tile a wave issues the
 // loads of the next tile's operand rows before its own matrix-core products
 // (and the z / wdot rows of its own outputs), so one tile of loads is always in
 // flight.  Loads are unconditional (indices clamped into the arrays, values
@@ -26,7 +28,21 @@ namespace {
 // per-wave LDS row by one lane, then the waves are added in order: one FP64
 // partial per workgroup, dpart[(f * wpf + wg) * 2 * m_pad + k * m_pad + j],
 // k = 0 (self), 1 (wdot).
-enum { RF_DOT_SELF = 1, RF_DOT_W = 2, RF_CORE = 4, RF_TWO = 8, RF_TRI = 16, RF_Z = 32 };
+enum { RF_DOT_SELF = 1, RF_DOT_W = 2, RF_CORE = 4, RF_TWO = 8, RF_Z = 32 };
+
+// n consecutive values from 16-byte aligned LDS
+template <typename T, int N>
+__device__ inline void lds_read_vec(const T *p, T *d) {
+  static_assert((N * sizeof(T)) % 16 == 0, "whole 16-byte vectors");
+  typedef T v16 __attribute__((ext_vector_type(16 / sizeof(T))));
+  constexpr int V = 16 / sizeof(T);
+#pragma unroll
+  for (int q = 0; q < N / V; ++q) {
+    const v16 v = reinterpret_cast<const v16 *>(p)[q];
+#pragma unroll
+    for (int i = 0; i < V; ++i) d[q * V + i] = v[i];
+  }
+}
 
 template <int CTRL>
 __device__ inline double dpp_double(double v) {
@@ -53,24 +69,26 @@ k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int 
             const T *wdot, double *__restrict__ dpart) {
   typedef Mfma<T> MM;
   constexpr int MP = 16 * TM;
-  constexpr int S = lds_stride(MP);
+  constexpr int NS = 4 * TM;                     // MFMA steps over the input orbitals
+  constexpr int S2 = MP + 16 / (int)sizeof(T);   // row stride of R^T in LDS (16-byte rows)
   constexpr bool DOTS = (FL & (RF_DOT_SELF | RF_DOT_W)) != 0;
   constexpr int NARR = (FL & RF_TWO) ? 2 : 1;
   constexpr int NITEM = NT * NARR;
   static_assert(!(FL & RF_TWO) || !(FL & (RF_Z | RF_DOT_SELF | RF_DOT_W)),
                 "the second array is rotated without z or reductions");
-  __shared__ T Rt[MP * S];
+  __shared__ __attribute__((aligned(16))) T RtT[MP * S2];
   __shared__ double red[4][2][MP];
   const int f = f0 + blockIdx.x / wpf;
   const int wg = blockIdx.x % wpf;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mf = o.m[f], mp = o.m_pad;
   const double *Mf = M + (long long)f * mp * mp;
+  // R^T with output orbital j as the row: RtT[j][i] = R[i][j]
   for (int e = threadIdx.x; e < MP * MP; e += blockDim.x) {
     const int i = e / MP, j = e % MP;
     double v = 0.0;
     if (i < mf && j < mf) v = trans ? Mf[j * mp + i] : Mf[i * mp + j];
-    Rt[i * S + j] = (T)v;
+    RtT[j * S2 + i] = (T)v;
   }
   if (DOTS)
     for (int e = lane; e < 2 * MP; e += 64) red[wave][e / MP][e % MP] = 0.0;
@@ -81,20 +99,22 @@ k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int 
   const int pw0 = (wg * 4 + wave) * NT * 16;  // first point of the wave
   // Addresses split into a wave-uniform row part and one lane offset (rows up
   // to the padded count exist: the arrays carry m_pad spare rows).
-  // operand rows i = 4 s + kk of item it at the lane's point
+  // Input orbital of MFMA step s in lane group kk: i = kk * NS + s, so a lane's
+  // R values for one output tile are contiguous in LDS (16-byte reads).
+  // operand rows i of item it at the lane's point:
   auto load_rows = [&](int it, T *bx) {
     const int u = it / NARR, arr = it % NARR;
     const int pc = pw0 + u * 16 + jl;
     const bool pin = pc < g.n;
-    const int lo = kk * g.n + (pin ? pc : g.n - 1);
+    const int lo = kk * NS * g.n + (pin ? pc : g.n - 1);
     const T *xs = (arr ? x2 : x) + base;
 #pragma unroll
-    for (int s = 0; s < TM * 4; ++s) {
-      const T v = (xs + (long long)(4 * s) * g.n)[lo];
-      bx[s] = (4 * s + kk < mf && pin) ? v : (T)0;
+    for (int s = 0; s < NS; ++s) {
+      const T v = (xs + (long long)s * g.n)[lo];
+      bx[s] = (kk * NS + s < mf && pin) ? v : (T)0;
     }
   };
-  T bx[TM * 4];
+  T bx[NS];
   load_rows(0, bx);
   for (int it = 0; it < NITEM; ++it) {
     const int u = it / NARR, arr = it % NARR;
@@ -120,21 +140,19 @@ k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int 
         for (int rr = 0; rr < 4; ++rr)
           wv[jt][rr] = (wdot + base + (long long)(jt * 16 + MM::row_u(rr)) * g.n)[lo_out];
     }
-    T bn[TM * 4];
-    if (it + 1 < NITEM) load_rows(it + 1, bn);
+    T bn[NS];
+    load_rows(it + 1 < NITEM ? it + 1 : it, bn);  // unconditional (see above)
     typename MM::acc_t acc[TM];
 #pragma unroll
     for (int jt = 0; jt < TM; ++jt) acc[jt] = MM::zero();
 #pragma unroll
-    for (int s = 0; s < TM * 4; ++s) {
-      const T *rrow = Rt + (4 * s + kk) * S + jl;
+    for (int jt = 0; jt < TM; ++jt) {
+      T a[NS];
+      lds_read_vec<T, NS>(RtT + (jt * 16 + jl) * S2 + kk * NS, a);
 #pragma unroll
-      for (int jt = 0; jt < TM; ++jt) {
-        if ((FL & RF_TRI) && s > 4 * jt + 3) continue;
-        acc[jt] = MM::mma(rrow[jt * 16], bx[s], acc[jt]);
-      }
+      for (int s = 0; s < NS; ++s) acc[jt] = MM::mma(a[s], bx[s], acc[jt]);
       // keep later operand reads from being hoisted (register pressure)
-      if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_sched_barrier(0);
     }
     T *ys = arr ? y2 : y;
 #pragma unroll
@@ -158,10 +176,8 @@ k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int 
           }
         }
       }
-    if (it + 1 < NITEM) {
 #pragma unroll
-      for (int s = 0; s < TM * 4; ++s) bx[s] = bn[s];
-    }
+    for (int s = 0; s < NS; ++s) bx[s] = bn[s];
   }
   if (DOTS) {
     __syncthreads();
@@ -205,7 +221,10 @@ __global__ void __launch_bounds__(256) k_band_reduce(Geo g, OrbSet o, long long 
 // Partials are written in FP64 (one per workgroup).
 enum { GM_PLAIN = 0, GM_DIR = 1, GM_UPDATE = 2 };
 constexpr int kGramKT = 32;
-constexpr int kGramLd = kGramKT + 2;
+// LDS row stride: rows stay 16-byte aligned for vector reads, with a 16-byte skew
+template <typename T>
+constexpr int gram_ld() { return kGramKT + 16 / (int)sizeof(T); }
+
 
 template <typename T>
 struct Vec4Load;
@@ -246,8 +265,9 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a
   constexpr int NI = (MP * (kGramKT / 4) + 255) / 256;
   // arrays read per item: PLAIN x (and y), DIR x, G, P_prev, UPDATE Psi, P, W, Q
   constexpr int NA = MODE == GM_PLAIN ? (SYM ? 1 : 2) : (MODE == GM_DIR ? 3 : 4);
-  __shared__ T Xs[MP * kGramLd];
-  __shared__ T Ys[SYM ? 1 : MP * kGramLd];
+  constexpr int LD = gram_ld<T>();
+  __shared__ __attribute__((aligned(16))) T Xs[MP * LD];
+  __shared__ __attribute__((aligned(16))) T Ys[SYM ? 4 : MP * LD];
   const int f = f0 + blockIdx.x / chunks;
   const int c = blockIdx.x % chunks;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -367,23 +387,27 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const bool ok = rin && p + t < p_end;
-        Xs[row * kGramLd + pq + t] = ok ? xv[t] : (T)0;
-        if (!SYM) Ys[row * kGramLd + pq + t] = ok ? yv[t] : (T)0;
+        Xs[row * LD + pq + t] = ok ? xv[t] : (T)0;
+        if (!SYM) Ys[row * LD + pq + t] = ok ? yv[t] : (T)0;
       }
     }
     __syncthreads();
-    if (PF && p0 + kGramKT < p_end) load_step(p0 + kGramKT);
+    // unconditional: past the chunk the point index is clamped inside load_step
+    if (PF) load_step(p0 + kGramKT);
+    // lane (r, kk) takes the step's points kk*KQ .. kk*KQ + KQ - 1 (any
+    // assignment of points to the K slots gives the same sum up to rounding):
+    // contiguous in LDS, so a tile's operands come in 16-byte reads
     const int r = lane & 15, kk = lane >> 4;
+    constexpr int KQ = kGramKT / 4;
 #pragma unroll
-    for (int t = 0; t < kGramKT / 4; ++t) {
+    for (int k = 0; k < PER_WAVE; ++k) {
+      if (tI[k] < 0) continue;
+      T av[KQ], bv[KQ];
+      lds_read_vec<T, KQ>(Xs + (tI[k] * 16 + r) * LD + kk * KQ, av);
+      lds_read_vec<T, KQ>(Yl + (tJ[k] * 16 + r) * LD + kk * KQ, bv);
 #pragma unroll
-      for (int k = 0; k < PER_WAVE; ++k) {
-        if (tI[k] < 0) continue;
-        const T av = Xs[(tI[k] * 16 + r) * kGramLd + 4 * t + kk];
-        const T bv = Yl[(tJ[k] * 16 + r) * kGramLd + 4 * t + kk];
-        acc[k] = MM::mma(av, bv, acc[k]);
-      }
-      if ((t & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+      for (int t = 0; t < KQ; ++t) acc[k] = MM::mma(av[t], bv[t], acc[k]);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   double *out = part + ((long long)(f - f0) * chunks + c) * mp * mp;
@@ -833,10 +857,10 @@ void launch_rot_cholesky(const Geo &g, const OrbSet &o, int f0, int f1, const do
                          T *psi, T *w, hipStream_t s) {
   const int wpf = rot_wpf(g);
   if (w)
-    rot_fused_tm<T, RF_TWO | RF_TRI>(g, o, f0, f1, wpf, Linv, 1, psi, nullptr, 0.0, 1.0, psi, w,
+    rot_fused_tm<T, RF_TWO>(g, o, f0, f1, wpf, Linv, 1, psi, nullptr, 0.0, 1.0, psi, w,
                                      w, nullptr, nullptr, s);
   else
-    rot_fused_tm<T, RF_TRI>(g, o, f0, f1, wpf, Linv, 1, psi, nullptr, 0.0, 1.0, psi, nullptr,
+    rot_fused_tm<T, 0>(g, o, f0, f1, wpf, Linv, 1, psi, nullptr, 0.0, 1.0, psi, nullptr,
                             nullptr, nullptr, nullptr, s);
 }
 
