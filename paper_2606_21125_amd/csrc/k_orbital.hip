@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(1024) k_hloc_vec(Geo g, const int *__restrict_
   extern __shared__ __attribute__((aligned(16))) char lds_vec[];
   const int nx = g.nl[0], ny = g.nl[1], nz = g.nl[2];
   const int bx = nx / RX, tpo = bx * ny;
-  const int SX = nx + 8, lplane = (ny + 8) * SX;
+  const int SX = nx + 32, lplane = (ny + 8) * SX;  // rows continue the bank sequence
   const int ol = threadIdx.x / tpo, tt = threadIdx.x % tpo;
   // z segments of one orbital group are consecutive workgroups
   const int seg = blockIdx.x % zs;
@@ -656,7 +656,7 @@ int vec_opw(const Geo &g, bool wide) {
   if (g.nl[0] % RX || !hloc_halo_ok(g)) return 0;
   const int tpo = g.nl[0] / RX * g.nl[1];
   if (tpo > 1024) return 0;
-  const size_t lds1 = 2 * (size_t)(g.nl[1] + 8) * (g.nl[0] + 8) * sizeof(T);
+  const size_t lds1 = 2 * (size_t)(g.nl[1] + 8) * (g.nl[0] + 32) * sizeof(T);
   const int top = std::min(4, 1024 / tpo);
   if (wide) {
     for (int opw = top; opw >= 1; --opw)
@@ -675,7 +675,7 @@ void launch_vec(const Geo &g, long long nb, int opw, int zs, const OrbSet &o, in
                 const T *veffT, const T *x, T *y, hipStream_t s, double *dot, double *dot_part,
                 int vbase) {
   const int tpo = g.nl[0] / (16 / (int)sizeof(T)) * g.nl[1];
-  const size_t lds = (size_t)opw * 2 * (g.nl[1] + 8) * (g.nl[0] + 8) * sizeof(T);
+  const size_t lds = (size_t)opw * 2 * (g.nl[1] + 8) * (g.nl[0] + 32) * sizeof(T);
   const unsigned grid = (unsigned)((nb + opw - 1) / opw * zs);
   hipLaunchKernelGGL((k_hloc_vec<T, PD>), dim3(grid), dim3(opw * tpo), lds, s, g, o.band_frag,
                      o.b0(f0), nb, opw, zs, vbase, veffT, x, y, dot, dot_part);

@@ -96,7 +96,11 @@ k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int 
   const long long base = o.moff[f] * (long long)g.n;
   const int jl = lane & 15, kk = lane >> 4;
   const T tcm = (T)cm, tcz = (T)cz;
-  const int pw0 = (wg * 4 + wave) * NT * 16;  // first point of the wave
+  // Tile u of wave w covers points (wg*NT*4 + u*4 + w)*16 .. +15: at each tile
+  // step the four waves cover 64 consecutive points, so the two 16-point halves
+  // of a 128-byte FP32 line are requested together (by neighbouring waves)
+  // rather than one tile step apart.
+  auto tile_p0 = [&](int u) { return ((wg * NT + u) * 4 + wave) * 16; };
   // Addresses split into a wave-uniform row part and one lane offset (rows up
   // to the padded count exist: the arrays carry m_pad spare rows).
   // Input orbital of MFMA step s in lane group kk: i = kk * NS + s, so a lane's
@@ -104,7 +108,7 @@ k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int 
   // operand rows i of item it at the lane's point:
   auto load_rows = [&](int it, T *bx) {
     const int u = it / NARR, arr = it % NARR;
-    const int pc = pw0 + u * 16 + jl;
+    const int pc = tile_p0(u) + jl;
     const bool pin = pc < g.n;
     const int lo = kk * NS * g.n + (pin ? pc : g.n - 1);
     const T *xs = (arr ? x2 : x) + base;
@@ -118,7 +122,7 @@ k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int 
   load_rows(0, bx);
   for (int it = 0; it < NITEM; ++it) {
     const int u = it / NARR, arr = it % NARR;
-    const int p0 = pw0 + u * 16;
+    const int p0 = tile_p0(u);
     if (p0 >= g.n) break;
     const int pc = p0 + jl;
     const bool pin = pc < g.n;
@@ -211,8 +215,8 @@ __global__ void __launch_bounds__(256) k_band_reduce(Geo g, OrbSet o, long long 
 }
 
 // Gram products.  Workgroup = (fragment, chunk of points).  Per step of KT = 32
-// points the workgroup loads the operand rows cooperatively into LDS at a row
-// stride of KT + 2 elements, and each wave accumulates its share of the output
+// points the workgroup loads the operand rows cooperatively into LDS (rows
+// padded by 16 bytes), and each wave accumulates its share of the output
 // tiles.  The second operand can be built during the load:
 //   GM_PLAIN:  Y given (SYM when X == Y: upper tiles only, one operand).
 //   GM_DIR:    Y = P = beta P_prev - G, written over P_prev.
