@@ -128,8 +128,9 @@ def main() -> int:
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         return 1
-    from paper_2606_21125_amd import (DCDFT, HLOC_VARIANTS, KERNEL_GRAM, KERNEL_HLOC,
-                                      KERNEL_ROTATE, PREC_FP64, PREC_MIXED)
+    from paper_2606_21125_amd import (DCDFT, HLOC_VARIANTS, KERNEL_GRAM, KERNEL_GRAM_FUSED,
+                                      KERNEL_HLOC, KERNEL_KB, KERNEL_ROTATE, PREC_FP64,
+                                      PREC_MIXED)
     prec = PREC_MIXED if args.precision == "mixed" else PREC_FP64
 
     if args.copy_probe_mb > 0:
@@ -169,7 +170,8 @@ def main() -> int:
     for _ in range(n_timed):
         d.dcdft_scf_step()
     kt = {name: d.dcdft_kernel_time(k) for name, k in
-          (("hloc", KERNEL_HLOC), ("gram", KERNEL_GRAM), ("rotate", KERNEL_ROTATE))}
+          (("hloc", KERNEL_HLOC), ("gram", KERNEL_GRAM), ("rotate", KERNEL_ROTATE),
+           ("gram_fused", KERNEL_GRAM_FUSED), ("kb", KERNEL_KB))}
     d.dcdft_kernel_timing(False)
     d.close()
     elapsed = t1 - t0
@@ -183,6 +185,10 @@ def main() -> int:
     g_tf = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
     r = kt["rotate"]
     r_gbs = r["bytes"] / (r["ms"] * 1e-3) / 1e9 if r["ms"] > 0 else 0.0
+    gf = kt["gram_fused"]
+    gf_gbs = gf["bytes"] / (gf["ms"] * 1e-3) / 1e9 if gf["ms"] > 0 else 0.0
+    kb = kt["kb"]
+    kb_gbs = kb["bytes"] / (kb["ms"] * 1e-3) / 1e9 if kb["ms"] > 0 else 0.0
     variant = tune["hloc_variant"] if tune else HLOC_VARIANTS[launch0["hloc_variant"]]
     kname = hloc_kernel_name(variant, prec != PREC_FP64, cfg.fragment_shape)
     traffic, traffic_src = recorded_traffic(kname, cfg.name)
@@ -203,6 +209,12 @@ def main() -> int:
         "rotate": {"bound": "hbm", "achieved": round(r_gbs, 1), "peak": HBM_PEAK_GBS,
                    "unit": "GB/s", "frac": round(r_gbs / HBM_PEAK_GBS, 4),
                    "avg_launch_ms": round(r["ms"] / max(1, r["launches"]), 4)},
+        "gram_fused": {"bound": "hbm", "achieved": round(gf_gbs, 1), "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(gf_gbs / HBM_PEAK_GBS, 4),
+                       "avg_launch_ms": round(gf["ms"] / max(1, gf["launches"]), 4)},
+        "projectors": {"bound": "hbm", "achieved": round(kb_gbs, 1), "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(kb_gbs / HBM_PEAK_GBS, 4),
+                       "avg_launch_ms": round(kb["ms"] / max(1, kb["launches"]), 4)},
         "kernel_ms_per_step": {k: round(v["ms"] / n_timed, 3) for k, v in kt.items()},
         "launch_shapes": tune,
         "last_step": {k: info[k] for k in ("mu", "e_total", "residual_out_in", "charge")},

@@ -196,10 +196,15 @@ dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, cons
  * the counters.  Timing adds two event records per launch and nothing else.
  *   HLOC:   (-1/2 L_FD + V_eff) X; bytes 2 s n per orbital + 8 n per fragment
  *           (s = 8 for FP64), flops 55 n per orbital.
- *   GRAM:   X^T Y per fragment; bytes s n (m_x + m_y), flops 2 n m^2.
- *   ROTATE: Y = c Z + M^T X per fragment; bytes s n m (2 or 3), flops 2 n m^2. */
+ *   GRAM:   plain X^T Y per fragment; bytes s n (m_x + m_y), flops 2 n m^2.
+ *   ROTATE: Y = c Z + M^T X per fragment; bytes s n m (2 to 4), flops 2 n m^2.
+ *   GRAM_FUSED: Gram products fused with building their operand (P = beta P -
+ *           G, written; or the 2x2 band rotations of Psi and W, written);
+ *           bytes s n m (4 or 6), flops 2 n m^2 (n m^2 when symmetric).
+ *   KB:     projections c = dV beta^T X (bytes s n m) and their application
+ *           Y += beta E c (bytes 2 s n m); flops not counted. */
 enum { DCDFT_KERNEL_HLOC = 0, DCDFT_KERNEL_GRAM = 1, DCDFT_KERNEL_ROTATE = 2,
-       DCDFT_KERNEL_COUNT = 3 };
+       DCDFT_KERNEL_GRAM_FUSED = 3, DCDFT_KERNEL_KB = 4, DCDFT_KERNEL_COUNT = 5 };
 dcdft_status dcdft_kernel_timing(dcdft_ctx *c, int32_t enable);
 dcdft_status dcdft_kernel_time(dcdft_ctx *c, int32_t kernel, int64_t *launches, double *ms,
                                double *bytes, double *flops);

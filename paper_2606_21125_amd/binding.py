@@ -34,7 +34,7 @@ EXPORTED = [
     "dcdft_destroy",
     "dcdft_status_string", "dcdft_last_error",
 ]
-KERNEL_HLOC, KERNEL_GRAM, KERNEL_ROTATE = 0, 1, 2
+KERNEL_HLOC, KERNEL_GRAM, KERNEL_ROTATE, KERNEL_GRAM_FUSED, KERNEL_KB = 0, 1, 2, 3, 4
 HLOC_VARIANTS = ("plane", "halo_pd2", "halo_pd3", "halo_pd4", "halo_pd2_ends", "vec",
                  "vec_wide", "vec_z2", "vec_z3")
 

@@ -110,6 +110,7 @@ dcdft::OrbSet dcdft_ctx::orbset(int f0, int f1) const {
   o.band_frag = d_band_frag;
   o.h_moff = moff.data();
   o.h_m = m.data();
+  o.row_pad = 1;
   return o;
 }
 
@@ -222,15 +223,25 @@ void hloc(dcdft_ctx *c, int f0, int f1, const T *x, T *y, double *dot = nullptr)
                  dot, 0, c->d_hdot);
 }
 
+template <typename T>
+void kb_project(dcdft_ctx *c, int f0, int f1, const T *x) {
+  Timed t(c, DCDFT_KERNEL_KB, (double)sizeof(T) * c->geo.n * orbitals_in(c, f0, f1), 0.0);
+  launch_kb_project<T>(c->geo, c->orbset(f0, f1), c->kb(), f0, f1, x, c->d_C, c->d_cpart,
+                       c->stream);
+}
+
+template <typename T>
+void kb_apply(dcdft_ctx *c, int f0, int f1, T *y) {
+  Timed t(c, DCDFT_KERNEL_KB, 2.0 * sizeof(T) * c->geo.n * orbitals_in(c, f0, f1), 0.0);
+  launch_kb_apply<T>(c->geo, c->orbset(f0, f1), c->kb(), f0, f1, c->d_C, y, c->stream);
+}
+
 // H X for the orbitals of fragments [f0, f1) in the context layout.
 template <typename T>
 void apply_h_range(dcdft_ctx *c, int f0, int f1, const T *x, T *y) {
-  const Geo &g = c->geo;
-  OrbSet o = c->orbset(f0, f1);
-  KBTables kb = c->kb();
   hloc<T>(c, f0, f1, x, y);
-  launch_kb_project<T>(g, o, kb, f0, f1, x, c->d_C, c->d_cpart, c->stream);
-  launch_kb_apply<T>(g, o, kb, f0, f1, c->d_C, y, c->stream);
+  kb_project<T>(c, f0, f1, x);
+  kb_apply<T>(c, f0, f1, y);
 }
 
 template <typename T>
@@ -280,7 +291,7 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
     launch_cg_beta(o, f0, f1, sw == 0, c->d_gamma, c->d_gamma_prev, c->d_beta, s);
     // (d)-(e) P = -G + beta P_prev, X = <Psi, P>
     {
-      Timed t(c, DCDFT_KERNEL_GRAM, 4.0 * sz * n * nb, 2.0 * n * m2);
+      Timed t(c, DCDFT_KERNEL_GRAM_FUSED, 4.0 * sz * n * nb, 2.0 * n * m2);
       launch_gram_direction<T>(g, o, f0, f1, ch, psi, q, p, c->d_beta, c->d_gpart, s);
     }
     launch_gram_reduce(g, o, f0, f1, ch, 0, c->d_gpart, c->d_x, nullptr, nullptr, s);
@@ -293,14 +304,14 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
     launch_cg_norm(o, f0, f1, c->d_nu, c->d_inv, s);
     // (g) Q = H P and <p_i, q_i>
     hloc<T>(c, f0, f1, p, q, c->d_cc);
-    launch_kb_project<T>(g, o, kb, f0, f1, p, c->d_C, c->d_cpart, s);
-    launch_kb_apply<T>(g, o, kb, f0, f1, c->d_C, q, s);
+    kb_project<T>(c, f0, f1, p);
+    kb_apply<T>(c, f0, f1, q);
     launch_kb_quad(o, f0, f1, kb, c->d_C, c->d_cc, s);
     // (h)-(i) exact minimiser of the 2x2 Rayleigh quotient
     launch_cg_theta(o, f0, f1, c->d_a, c->d_bb, c->d_cc, c->d_inv, c->d_cos, c->d_sin, s);
     // (j) band rotations and (l) S = sym(<Psi, Psi>)
     {
-      Timed t(c, DCDFT_KERNEL_GRAM, 6.0 * sz * n * nb, 1.0 * n * m2);
+      Timed t(c, DCDFT_KERNEL_GRAM_FUSED, 6.0 * sz * n * nb, 1.0 * n * m2);
       launch_gram_update<T>(g, o, f0, f1, ch, psi, p, w, q, c->d_cos, c->d_sin, c->d_gpart, s);
     }
     launch_gram_reduce(g, o, f0, f1, ch, 1, c->d_gpart, c->d_s, nullptr, nullptr, s);
@@ -1241,6 +1252,7 @@ dcdft_status apply_h_ext(dcdft_ctx *c, int frag, const T *psi, T *hpsi, int m,
     o.h_moff = L.h_moff.data();
     o.h_m = L.h_m.data();
     o.M_tot = mm;
+    o.row_pad = 0;
     KBTables kb = c->kb();
     const T *x = psi + (long long)i0 * g.n;
     T *y = hpsi + (long long)i0 * g.n;

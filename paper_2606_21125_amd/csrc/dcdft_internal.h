@@ -70,6 +70,10 @@ struct OrbSet {           // flattened orbital layout [M_tot][n]
   const int *band_frag;   // [M_tot]
   const long long *h_moff;  // host copy of moff (launch ranges)
   const int *h_m;           // host copy of m
+  // 1: the arrays hold m_pad spare rows after the last band, so a kernel may
+  // read any padded row of a fragment (context arrays); 0: rows past a
+  // fragment's m must not be read (caller-provided arrays)
+  int row_pad;
   long long b0(int f) const { return h_moff[f]; }
   long long nb(int f0, int f1) const { return h_moff[f1] - h_moff[f0]; }
 };
@@ -193,8 +197,9 @@ struct dcdft_ctx {
   bool timing = false;
   std::vector<PendingTimer> pending;
   std::vector<hipEvent_t> event_pool;
-  long long k_launches[3] = {0, 0, 0};
-  double k_ms[3] = {0, 0, 0}, k_bytes[3] = {0, 0, 0}, k_flops[3] = {0, 0, 0};
+  long long k_launches[DCDFT_KERNEL_COUNT] = {};
+  double k_ms[DCDFT_KERNEL_COUNT] = {}, k_bytes[DCDFT_KERNEL_COUNT] = {},
+         k_flops[DCDFT_KERNEL_COUNT] = {};
 
   // graph of one batched SCF step (captured on first use, replayed after)
   hipGraph_t graph = nullptr;

@@ -370,6 +370,21 @@ __global__ void __launch_bounds__(256) k_dot_segments(Geo g, long long b0, long 
   dot[b0 + i] = g.dv * sum;
 }
 
+// Four consecutive values from global memory at a 16-byte aligned address.
+template <typename T>
+__device__ inline void load4_aligned(const T *p, T *d);
+template <>
+__device__ inline void load4_aligned<float>(const float *p, float *d) {
+  const float4 v = *reinterpret_cast<const float4 *>(p);
+  d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+}
+template <>
+__device__ inline void load4_aligned<double>(const double *p, double *d) {
+  const double2 a = reinterpret_cast<const double2 *>(p)[0];
+  const double2 b = reinterpret_cast<const double2 *>(p)[1];
+  d[0] = a.x; d[1] = a.y; d[2] = b.x; d[3] = b.y;
+}
+
 template <typename T>
 __device__ inline const T *region_beta(const KBTables &kb);
 template <>
@@ -385,16 +400,21 @@ __device__ inline const float *region_beta<float>(const KBTables &kb) {
 // sum_{l in region} beta_slot(l) X_i(l), as MFMA products of the dense region
 // block (slots x points) with the region's orbital columns.  Wave w takes the
 // orbital tiles w, w + 4; the K index walks points as u*16 + 4 (lane/16) + t so
-// that every lane reads contiguous runs of both operands.
-template <typename T, int TM, int KT>
+// that every lane reads runs of 4 contiguous values of both operands (16-byte
+// loads when VEC: n % 4 == 0).  The operands of the next 16-point step are
+// loaded before the products of the current one; every load is unconditional
+// (rows and points clamped into the arrays, values masked).
+template <typename T, int TM, int KT, bool VEC>
 __global__ void __launch_bounds__(256) k_kb_project2(Geo g, OrbSet o, KBTables kb, int f0,
                                                      const T *__restrict__ x,
                                                      double *__restrict__ part) {
   typedef Mfma<T> MM;
+  constexpr int MP = 16 * TM;
   const int f = f0 + blockIdx.x / kb.NR;
   const int reg = blockIdx.x % kb.NR;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mf = o.m[f];
+  const int rmax = o.row_pad ? MP - 1 : mf - 1;
   const int pbase = reg * kRegion;
   const long long base = o.moff[f] * (long long)g.n;
   const T *blk = region_beta<T>(kb) + ((long long)f * kb.NR + reg) * kb.KS * kRegion;
@@ -405,27 +425,54 @@ __global__ void __launch_bounds__(256) k_kb_project2(Geo g, OrbSet o, KBTables k
   for (int a = 0; a < KT; ++a)
 #pragma unroll
     for (int b = 0; b < JW; ++b) acc[a][b] = MM::zero();
-  for (int u = 0; u < kRegion / 16; ++u) {
+  auto load_step = [&](int u, T (*bx)[4], T (*av)[4]) {
     const int pu = pbase + u * 16 + 4 * kk;
-    T bx[JW][4];
 #pragma unroll
     for (int q = 0; q < JW; ++q) {
       const int jt = wave + 4 * q;
       const int orb = jt * 16 + r;
       const bool ok = jt < TM && orb < mf;
+      const T *row = x + base + (long long)(orb < rmax ? orb : rmax) * g.n;
+      if (VEC) {
+        // n % 4 == 0 and pu % 4 == 0: the run lies wholly inside or outside
+        const int pc = pu < g.n ? pu : g.n - 4;
+        T v[4];
+        load4_aligned(row + pc, v);
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        bx[q][t] = (ok && pu + t < g.n) ? x[base + (long long)orb * g.n + pu + t] : (T)0;
+        for (int t = 0; t < 4; ++t) bx[q][t] = (ok && pu < g.n) ? v[t] : (T)0;
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int pt = pu + t;
+          const T v = row[pt < g.n ? pt : g.n - 1];
+          bx[q][t] = (ok && pt < g.n) ? v : (T)0;
+        }
+      }
     }
+#pragma unroll
+    for (int st = 0; st < KT; ++st) load4_aligned(blk + (st * 16 + r) * kRegion + pu - pbase, av[st]);
+  };
+  T bx[JW][4], av[KT][4];
+  load_step(0, bx, av);
+  for (int u = 0; u < kRegion / 16; ++u) {
+    T bn[JW][4], an[KT][4];
+    load_step(u + 1 < kRegion / 16 ? u + 1 : u, bn, an);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
 #pragma unroll
       for (int st = 0; st < KT; ++st) {
-        const T av = blk[(st * 16 + r) * kRegion + u * 16 + 4 * kk + t];
 #pragma unroll
-        for (int q = 0; q < JW; ++q) acc[st][q] = MM::mma(av, bx[q][t], acc[st][q]);
+        for (int q = 0; q < JW; ++q) acc[st][q] = MM::mma(av[st][t], bx[q][t], acc[st][q]);
       }
     }
+#pragma unroll
+    for (int q = 0; q < JW; ++q)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) bx[q][t] = bn[q][t];
+#pragma unroll
+    for (int st = 0; st < KT; ++st)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) av[st][t] = an[st][t];
   }
   double *out = part + ((long long)f * kb.NR + reg) * kb.KS * o.m_pad;
 #pragma unroll
@@ -463,20 +510,26 @@ __global__ void __launch_bounds__(256) k_kb_reduce(Geo g, OrbSet o, KBTables kb,
 
 // Y_i(l) += sum_slot beta_slot(l) E_slot C[f][slot atom][i] per region, as MFMA
 // products of (E C)^T (orbitals x slots, staged in LDS) with the dense region
-// block (slots x points); wave w takes the 16-point tiles w, w + 4, ...
-template <typename T, int TM, int KT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+// block (slots x points); wave w takes the 16-point tiles w, w + 4, ... so the
+// four waves cover 64 consecutive points at a time.  The beta values and the
+// old Y values of the next tile are loaded before the products of the current
+// one (unconditional loads, rows and points clamped, stores masked).
+template <typename T, int TM, int KT, bool RP>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2, 8)))
 k_kb_apply2(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
             T *__restrict__ y) {
   typedef Mfma<T> MM;
   constexpr int MP = 16 * TM;
   constexpr int LD = lds_stride(MP);
   constexpr int KSM = 16 * KT;
+  constexpr int NU = kRegion / 16 / 4;  // tiles per wave
   __shared__ T ec[KSM * LD];
   const int f = f0 + blockIdx.x / kb.NR;
   const int reg = blockIdx.x % kb.NR;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mf = o.m[f];
+  const int rmax = o.row_pad ? MP - 1 : mf - 1;
   const int *ra = kb.reg_atom + ((long long)f * kb.NR + reg) * kb.KS;
   const double *Cf = C + (long long)f * kb.A_max * o.m_pad;
   const double *Ef = kb.E + (long long)f * kb.A_max;
@@ -489,28 +542,56 @@ k_kb_apply2(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
   const T *blk = region_beta<T>(kb) + ((long long)f * kb.NR + reg) * kb.KS * kRegion;
   const long long base = o.moff[f] * (long long)g.n;
   const int c = lane & 15, kk = lane >> 4;
-  for (int u = wave; u < kRegion / 16; u += 4) {
+  // Y row orb = jt*16 + row_u(rr) + row_l(kk): with padded arrays (RP) the
+  // address is a wave-uniform row part plus one lane offset; otherwise rows are
+  // clamped per lane to the fragment's last band
+  auto yaddr = [&](int jt, int rr, int pc) -> T * {
+    if (RP)
+      return y + base + (long long)(jt * 16 + MM::row_u(rr)) * g.n + (MM::row_l(kk) * g.n + pc);
+    const int orb = jt * 16 + MM::row(kk, rr);
+    return y + base + (long long)(orb < rmax ? orb : rmax) * g.n + pc;
+  };
+  auto load_tile = [&](int k, T *bv, T (*yv)[4]) {
+    const int u = wave + 4 * k;
     const int p = reg * kRegion + u * 16 + c;
+    const int pc = p < g.n ? p : g.n - 1;
+#pragma unroll
+    for (int st = 0; st < KT * 4; ++st)
+      bv[st] = (blk + 4 * st * kRegion + u * 16)[kk * kRegion + c];
+#pragma unroll
+    for (int jt = 0; jt < TM; ++jt)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) yv[jt][rr] = *yaddr(jt, rr, pc);
+  };
+  T bv[KT * 4], yv[TM][4];
+  load_tile(0, bv, yv);
+  for (int k = 0; k < NU; ++k) {
+    T bn[KT * 4], yn[TM][4];
+    load_tile(k + 1 < NU ? k + 1 : k, bn, yn);
+    const int p = reg * kRegion + (wave + 4 * k) * 16 + c;
     typename MM::acc_t acc[TM];
 #pragma unroll
     for (int j = 0; j < TM; ++j) acc[j] = MM::zero();
 #pragma unroll
     for (int st = 0; st < KT * 4; ++st) {
-      const T bv = blk[(4 * st + kk) * kRegion + u * 16 + c];
 #pragma unroll
       for (int jt = 0; jt < TM; ++jt)
-        acc[jt] = MM::mma(ec[(4 * st + kk) * LD + jt * 16 + c], bv, acc[jt]);
+        acc[jt] = MM::mma(ec[(4 * st + kk) * LD + jt * 16 + c], bv[st], acc[jt]);
       if ((st & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
-    if (p < g.n) {
 #pragma unroll
-      for (int jt = 0; jt < TM; ++jt)
+    for (int jt = 0; jt < TM; ++jt)
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          const int orb = jt * 16 + MM::row(kk, rr);
-          if (orb < mf) y[base + (long long)orb * g.n + p] += acc[jt][rr];
-        }
-    }
+      for (int rr = 0; rr < 4; ++rr) {
+        const int orb = jt * 16 + MM::row(kk, rr);
+        if (orb < mf && p < g.n) *yaddr(jt, rr, p) = yv[jt][rr] + acc[jt][rr];
+      }
+#pragma unroll
+    for (int st = 0; st < KT * 4; ++st) bv[st] = bn[st];
+#pragma unroll
+    for (int jt = 0; jt < TM; ++jt)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) yv[jt][rr] = yn[jt][rr];
   }
 }
 
@@ -596,12 +677,20 @@ void kb_t(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1, con
           double *C, double *part, T *y, hipStream_t s) {
   const dim3 grid((f1 - f0) * kb.NR), block(256);
   if (x) {
-    hipLaunchKernelGGL((k_kb_project2<T, TM, KT>), grid, block, 0, s, g, o, kb, f0, x, part);
+    // 16-byte runs need n % 4 == 0 and an aligned array
+    if (g.n % 4 == 0 && (uintptr_t)x % 16 == 0)
+      hipLaunchKernelGGL((k_kb_project2<T, TM, KT, true>), grid, block, 0, s, g, o, kb, f0, x,
+                         part);
+    else
+      hipLaunchKernelGGL((k_kb_project2<T, TM, KT, false>), grid, block, 0, s, g, o, kb, f0, x,
+                         part);
     const long long total = (long long)(f1 - f0) * kb.A_max * o.m_pad;
     hipLaunchKernelGGL(k_kb_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, o,
                        kb, f0, f1 - f0, part, C);
+  } else if (o.row_pad) {
+    hipLaunchKernelGGL((k_kb_apply2<T, TM, KT, true>), grid, block, 0, s, g, o, kb, f0, C, y);
   } else {
-    hipLaunchKernelGGL((k_kb_apply2<T, TM, KT>), grid, block, 0, s, g, o, kb, f0, C, y);
+    hipLaunchKernelGGL((k_kb_apply2<T, TM, KT, false>), grid, block, 0, s, g, o, kb, f0, C, y);
   }
 }
 
