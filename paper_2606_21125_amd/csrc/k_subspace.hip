@@ -594,6 +594,7 @@ __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *_
     }
     prev_off = offm;
     for (int r = 0; r < mm - 1; ++r) {
+      // the round's rotations (needs the previous round's A: barrier below)
       __syncthreads();
       for (int k = threadIdx.x; k < npair; k += blockDim.x) {
         int p, q;
@@ -614,26 +615,32 @@ __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *_
         sn[k] = s;
       }
       __syncthreads();
-      // rows: A <- J^T A
-      for (int e = threadIdx.x; e < npair * mf; e += blockDim.x) {
-        const int k = e / mf, j = e % mf;
-        const int p = pp[k], q = qq[k];
-        if (q >= mf) continue;
-        const double c = cs[k], s = sn[k];
-        const double ap = A[p * ld + j], aq = A[q * ld + j];
-        A[p * ld + j] = c * ap - s * aq;
-        A[q * ld + j] = s * ap + c * aq;
+      // A <- J^T A J as 2x2 blocks (rows of pair k1, columns of pair k2: the
+      // blocks are disjoint, so one pass with no intermediate barrier), and
+      // V <- V J.  The idle index of an odd size (q = mf) is neither read nor
+      // written.
+      for (int e = threadIdx.x; e < npair * npair; e += blockDim.x) {
+        const int k1 = e / npair, k2 = e % npair;
+        const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
+        const bool h1 = q1 < mf, h2 = q2 < mf;
+        const double c1 = cs[k1], s1 = sn[k1], c2 = cs[k2], s2 = sn[k2];
+        const double app = A[p1 * ld + p2];
+        const double apq = h2 ? A[p1 * ld + q2] : 0.0;
+        const double aqp = h1 ? A[q1 * ld + p2] : 0.0;
+        const double aqq = (h1 && h2) ? A[q1 * ld + q2] : 0.0;
+        // rows (pair k1), then columns (pair k2)
+        const double rpp = c1 * app - s1 * aqp, rpq = c1 * apq - s1 * aqq;
+        const double rqp = s1 * app + c1 * aqp, rqq = s1 * apq + c1 * aqq;
+        A[p1 * ld + p2] = c2 * rpp - s2 * rpq;
+        if (h2) A[p1 * ld + q2] = s2 * rpp + c2 * rpq;
+        if (h1) A[q1 * ld + p2] = c2 * rqp - s2 * rqq;
+        if (h1 && h2) A[q1 * ld + q2] = s2 * rqp + c2 * rqq;
       }
-      __syncthreads();
-      // columns: A <- A J, V <- V J
       for (int e = threadIdx.x; e < npair * mf; e += blockDim.x) {
         const int k = e / mf, i = e % mf;
         const int p = pp[k], q = qq[k];
         if (q >= mf) continue;
         const double c = cs[k], s = sn[k];
-        const double ap = A[i * ld + p], aq = A[i * ld + q];
-        A[i * ld + p] = c * ap - s * aq;
-        A[i * ld + q] = s * ap + c * aq;
         const double vp = V[i * ld + p], vq = V[i * ld + q];
         V[i * ld + p] = c * vp - s * vq;
         V[i * ld + q] = s * vp + c * vq;
