@@ -301,9 +301,19 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a
         ++idx;
       }
   }
+  // FP32 products: each step's 32-point sums leave the matrix cores in FP32 and
+  // are added into FP64 accumulators (the chunk sum of up to thousands of
+  // points would otherwise accumulate in FP32); FP64 products accumulate in the
+  // matrix cores directly.
+  constexpr bool ACC64 = sizeof(T) == 4;
   typename MM::acc_t acc[PER_WAVE];
+  double acc64[ACC64 ? PER_WAVE : 1][4];
 #pragma unroll
   for (int k = 0; k < PER_WAVE; ++k) acc[k] = MM::zero();
+#pragma unroll
+  for (int k = 0; k < (ACC64 ? PER_WAVE : 1); ++k)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc64[k][rr] = 0.0;
   const T *Yl = SYM ? Xs : Ys;
   auto src = [&](int a) -> const T * {
     return a == 0 ? x : (a == 1 ? (MODE == GM_DIR ? a2 : a1) : (a == 2 ? (MODE == GM_DIR ? a1 : a3) : a4));
@@ -409,8 +419,13 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a
       T av[KQ], bv[KQ];
       lds_read_vec<T, KQ>(Xs + (tI[k] * 16 + r) * LD + kk * KQ, av);
       lds_read_vec<T, KQ>(Yl + (tJ[k] * 16 + r) * LD + kk * KQ, bv);
+      if (ACC64) acc[k] = MM::zero();
 #pragma unroll
       for (int t = 0; t < KQ; ++t) acc[k] = MM::mma(av[t], bv[t], acc[k]);
+      if (ACC64) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) acc64[k][rr] += (double)acc[k][rr];
+      }
       __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -422,7 +437,7 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a
     for (int rr = 0; rr < 4; ++rr) {
       const int row = tI[k] * 16 + MM::row(lane >> 4, rr);
       const int col = tJ[k] * 16 + (lane & 15);
-      out[row * mp + col] = (double)acc[k][rr];
+      out[row * mp + col] = ACC64 ? acc64[k][rr] : (double)acc[k][rr];
     }
   }
 }
