@@ -88,17 +88,39 @@ __global__ void __launch_bounds__(1024) k_fermi(long long nb, const double *__re
   lo = block_min(lo, red) - 50.0 * sigma;
   hi = -block_min(hi, red) + 50.0 * sigma;
   const bool ok = cap >= ne * (1.0 - 1e-12);
+  // N(mu) is increasing: keep a bracket lo < mu* <= hi and take Newton steps
+  // (N' = sum 2 w f (1 - f) / sigma) from the previous step's mu when they
+  // stay inside it, bisection otherwise; stop when N(mu) = N_e to 1e-14
+  // relative, the Newton step is below 1e-15 |mu|, or the bracket cannot be
+  // halved any more.
+  double mu = scal[SC_MU];
+  if (!(mu > lo && mu < hi)) mu = 0.5 * (lo + hi);
   for (int it = 0; it < 200 && ok; ++it) {
+    double cnt = 0.0, der = 0.0;
+    for (long long i = threadIdx.x; i < nb; i += blockDim.x) {
+      const double fo = fermi((eps[i] - mu) / sigma);
+      cnt += 2.0 * fo * w[i];
+      der += 2.0 * fo * (1.0 - fo) * w[i];
+    }
+    cnt = block_sum(cnt, red);
+    der = block_sum(der, red) / sigma;
+    if (fabs(cnt - ne) <= 1e-14 * ne) break;
+    if (cnt < ne) lo = mu;
+    else hi = mu;
     const double mid = 0.5 * (lo + hi);
     if (mid == lo || mid == hi) break;
-    double cnt = 0.0;
-    for (long long i = threadIdx.x; i < nb; i += blockDim.x)
-      cnt += 2.0 * fermi((eps[i] - mid) / sigma) * w[i];
-    cnt = block_sum(cnt, red);
-    if (cnt < ne) lo = mid;
-    else hi = mid;
+    const double step = (der > 0.0) ? (ne - cnt) / der : 0.0;
+    const double nt = mu + step;
+    if (der > 0.0 && nt > lo && nt < hi) {
+      if (fabs(step) <= 1e-15 * fmax(1.0, fabs(mu))) {
+        mu = nt;
+        break;
+      }
+      mu = nt;
+    } else {
+      mu = mid;
+    }
   }
-  const double mu = 0.5 * (lo + hi);
   double eb = 0.0, ent = 0.0;
   for (long long i = threadIdx.x; i < nb; i += blockDim.x) {
     const double fo = fermi((eps[i] - mu) / sigma);

@@ -497,9 +497,11 @@ __global__ void __launch_bounds__(256) k_cholinv(OrbSet o, int f0, const double 
   const int ld = mf + 1;   // odd row stride: column walks hit distinct banks
   const double *Sf = S + (long long)f * mp * mp;
   double *Lf = Linv + (long long)f * mp * mp;
+  // 16 x 16 thread grid (no runtime division in the index arithmetic)
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   if (threadIdx.x == 0) bad = 0;
-  for (int e = threadIdx.x; e < mf * mf; e += blockDim.x)
-    A[(e / mf) * ld + e % mf] = 0.5 * (Sf[(e / mf) * mp + e % mf] + Sf[(e % mf) * mp + e / mf]);
+  for (int i = ty; i < mf; i += 16)
+    for (int j = tx; j < mf; j += 16) A[i * ld + j] = 0.5 * (Sf[i * mp + j] + Sf[j * mp + i]);
   for (int k = 0; k < mf; ++k) {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -511,13 +513,12 @@ __global__ void __launch_bounds__(256) k_cholinv(OrbSet o, int f0, const double 
       A[k * ld + k] = sqrt(d);
     }
     __syncthreads();
-    const double dk = A[k * ld + k];
-    for (int i = k + 1 + threadIdx.x; i < mf; i += blockDim.x) A[i * ld + k] /= dk;
+    const double rdk = 1.0 / A[k * ld + k];
+    for (int i = k + 1 + threadIdx.x; i < mf; i += blockDim.x) A[i * ld + k] *= rdk;
     __syncthreads();
-    const int w = mf - k - 1;
-    for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
-      const int i = k + 1 + e / w, j = k + 1 + e % w;
-      if (j <= i) A[i * ld + j] -= A[i * ld + k] * A[j * ld + k];
+    for (int i = k + 1 + ty; i < mf; i += 16) {
+      const double lik = A[i * ld + k];
+      for (int j = k + 1 + tx; j <= i; j += 16) A[i * ld + j] -= lik * A[j * ld + k];
     }
   }
   __syncthreads();
@@ -530,10 +531,9 @@ __global__ void __launch_bounds__(256) k_cholinv(OrbSet o, int f0, const double 
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < mp * mp; e += blockDim.x) {
-    const int r = e / mp, c = e % mp;
-    Lf[e] = (r < mf && c < mf && r >= c) ? X[r * ld + c] : 0.0;
-  }
+  for (int r = ty; r < mp; r += 16)
+    for (int c = tx; c < mp; c += 16)
+      Lf[r * mp + c] = (r < mf && c < mf && r >= c) ? X[r * ld + c] : 0.0;
   if (threadIdx.x == 0 && bad) atomicOr(flags, FLAG_NOT_SPD);
 }
 
@@ -567,11 +567,13 @@ __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *_
   const int mf = o.m[f], mp = o.m_pad;
   const int ld = mf + 1;   // odd row stride: column walks hit distinct banks
   const double *Hf = H + (long long)f * mp * mp;
-  for (int e = threadIdx.x; e < mf * mf; e += blockDim.x) {
-    const int i = e / mf, j = e % mf;
-    A[i * ld + j] = 0.5 * (Hf[i * mp + j] + Hf[j * mp + i]);
-    V[i * ld + j] = (i == j) ? 1.0 : 0.0;
-  }
+  // 32 x 32 thread grid (no runtime division in the index arithmetic)
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int i = ty; i < mf; i += 32)
+    for (int j = tx; j < mf; j += 32) {
+      A[i * ld + j] = 0.5 * (Hf[i * mp + j] + Hf[j * mp + i]);
+      V[i * ld + j] = (i == j) ? 1.0 : 0.0;
+    }
   const int mm = (mf % 2) ? mf + 1 : mf;   // an odd size gets one idle index
   const int npair = mm / 2;
   bool converged = (mf <= 1);
@@ -580,12 +582,12 @@ __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *_
     __syncthreads();
     // convergence: max |off-diagonal| against the largest diagonal magnitude
     double off = 0.0, dia = 0.0;
-    for (int e = threadIdx.x; e < mf * mf; e += blockDim.x) {
-      const int i = e / mf, j = e % mf;
-      const double v = fabs(A[i * ld + j]);
-      if (i == j) dia = fmax(dia, v);
-      else off = fmax(off, v);
-    }
+    for (int i = ty; i < mf; i += 32)
+      for (int j = tx; j < mf; j += 32) {
+        const double v = fabs(A[i * ld + j]);
+        if (i == j) dia = fmax(dia, v);
+        else off = fmax(off, v);
+      }
     for (int s = 32; s > 0; s >>= 1) {
       off = fmax(off, __shfl_xor(off, s, 64));
       dia = fmax(dia, __shfl_xor(dia, s, 64));
@@ -634,8 +636,8 @@ __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *_
       // blocks are disjoint, so one pass with no intermediate barrier), and
       // V <- V J.  The idle index of an odd size (q = mf) is neither read nor
       // written.
-      for (int e = threadIdx.x; e < npair * npair; e += blockDim.x) {
-        const int k1 = e / npair, k2 = e % npair;
+      for (int k1 = ty; k1 < npair; k1 += 32)
+      for (int k2 = tx; k2 < npair; k2 += 32) {
         const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
         const bool h1 = q1 < mf, h2 = q2 < mf;
         const double c1 = cs[k1], s1 = sn[k1], c2 = cs[k2], s2 = sn[k2];
@@ -651,8 +653,8 @@ __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *_
         if (h1) A[q1 * ld + p2] = c2 * rqp - s2 * rqq;
         if (h1 && h2) A[q1 * ld + q2] = s2 * rqp + c2 * rqq;
       }
-      for (int e = threadIdx.x; e < npair * mf; e += blockDim.x) {
-        const int k = e / mf, i = e % mf;
+      for (int k = ty; k < npair; k += 32)
+      for (int i = tx; i < mf; i += 32) {
         const int p = pp[k], q = qq[k];
         if (q >= mf) continue;
         const double c = cs[k], s = sn[k];
