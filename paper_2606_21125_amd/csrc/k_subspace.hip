@@ -501,7 +501,10 @@ __global__ void __launch_bounds__(256) k_cholinv(OrbSet o, int f0, const double 
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   if (threadIdx.x == 0) bad = 0;
   for (int i = ty; i < mf; i += 16)
-    for (int j = tx; j < mf; j += 16) A[i * ld + j] = 0.5 * (Sf[i * mp + j] + Sf[j * mp + i]);
+    for (int j = tx; j < mf; j += 16) {
+      A[i * ld + j] = 0.5 * (Sf[i * mp + j] + Sf[j * mp + i]);
+      X[i * ld + j] = (i == j) ? 1.0 : 0.0;
+    }
   for (int k = 0; k < mf; ++k) {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -515,19 +518,16 @@ __global__ void __launch_bounds__(256) k_cholinv(OrbSet o, int f0, const double 
     __syncthreads();
     const double rdk = 1.0 / A[k * ld + k];
     for (int i = k + 1 + threadIdx.x; i < mf; i += blockDim.x) A[i * ld + k] *= rdk;
+    // L^-1 by the same elimination applied to the identity: row k of X is
+    // divided by L_kk here, and L_ik times it is subtracted from the rows
+    // below in the next phase (X rows r hold the finished rows of L^-1 for
+    // r <= k)
+    for (int c = threadIdx.x; c <= k; c += blockDim.x) X[k * ld + c] *= rdk;
     __syncthreads();
     for (int i = k + 1 + ty; i < mf; i += 16) {
       const double lik = A[i * ld + k];
       for (int j = k + 1 + tx; j <= i; j += 16) A[i * ld + j] -= lik * A[j * ld + k];
-    }
-  }
-  __syncthreads();
-  // column c of L^-1 by forward substitution in LDS, then stored as Lf[r][c]
-  for (int c = threadIdx.x; c < mf; c += blockDim.x) {
-    for (int r = c; r < mf; ++r) {
-      double s = (r == c) ? 1.0 : 0.0;
-      for (int q = c; q < r; ++q) s -= A[r * ld + q] * X[q * ld + c];
-      X[r * ld + c] = s / A[r * ld + r];
+      for (int c = tx; c <= k; c += 16) X[i * ld + c] -= lik * X[k * ld + c];
     }
   }
   __syncthreads();
