@@ -507,16 +507,14 @@ __global__ void __launch_bounds__(256) k_cholinv(OrbSet o, int f0, const double 
     }
   for (int k = 0; k < mf; ++k) {
     __syncthreads();
-    if (threadIdx.x == 0) {
-      double d = A[k * ld + k];
-      if (!(d > 0.0)) {
-        bad = 1;
-        d = 1.0;
-      }
-      A[k * ld + k] = sqrt(d);
+    // every thread takes the pivot itself (A_kk is not written, so no barrier
+    // separates reading it from scaling with it)
+    double d = A[k * ld + k];
+    if (!(d > 0.0)) {
+      if (threadIdx.x == 0) bad = 1;
+      d = 1.0;
     }
-    __syncthreads();
-    const double rdk = 1.0 / A[k * ld + k];
+    const double rdk = 1.0 / sqrt(d);
     for (int i = k + 1 + threadIdx.x; i < mf; i += blockDim.x) A[i * ld + k] *= rdk;
     // L^-1 by the same elimination applied to the identity: row k of X is
     // divided by L_kk here, and L_ik times it is subtracted from the rows
