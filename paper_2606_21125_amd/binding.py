@@ -127,8 +127,9 @@ def load_library(path: Optional[str] = None):
         "dcdft_kernel_time": ([vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), pd, pd, pd],
                               ctypes.c_int),
         "dcdft_autotune": ([vp, ctypes.c_char_p, ctypes.POINTER(DcdftTuneInfo)], ctypes.c_int),
-        "dcdft_get_launch": ([vp, pi, pi, pi, pi], ctypes.c_int),
-        "dcdft_set_launch": ([vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+        "dcdft_get_launch": ([vp, pi, pi, pi, pi, pi], ctypes.c_int),
+        "dcdft_set_launch": ([vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+                             ctypes.c_int),
         "dcdft_destroy": ([vp], None),
         "dcdft_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "dcdft_last_error": ([vp, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
@@ -342,14 +343,17 @@ class DCDFT:
         return info.as_dict()
 
     def dcdft_get_launch(self) -> dict:
-        v = [ctypes.c_int32() for _ in range(4)]
+        v = [ctypes.c_int32() for _ in range(5)]
         _check(self._lib.dcdft_get_launch(self.ctx, *[ctypes.byref(x) for x in v]), self.ctx)
         return dict(hloc_variant=v[0].value, rot_tiles=v[1].value, gram_chunks=v[2].value,
-                    gram_chunks_max=v[3].value)
+                    gram_chunks_max=v[3].value, streams=v[4].value)
 
-    def dcdft_set_launch(self, hloc_variant: int, rot_tiles: int, gram_chunks: int) -> None:
-        _check(self._lib.dcdft_set_launch(self.ctx, hloc_variant, rot_tiles, gram_chunks),
-               self.ctx)
+    def dcdft_set_launch(self, hloc_variant: int, rot_tiles: int, gram_chunks: int,
+                         streams: Optional[int] = None) -> None:
+        if streams is None:
+            streams = self.dcdft_get_launch()["streams"]
+        _check(self._lib.dcdft_set_launch(self.ctx, hloc_variant, rot_tiles, gram_chunks,
+                                          streams), self.ctx)
 
     def dcdft_band_energy(self, frag: int, psi, f, veff=None, energy=None, grad_psi=None,
                           grad_v=None, prec: int = PREC_FP64) -> None:

@@ -214,26 +214,36 @@ const float *veff_t<float>(const dcdft_ctx *c) {
   return c->d_veff32;
 }
 
+// stream the eigensolver helpers issue to
+hipStream_t xstream(const dcdft_ctx *c) { return c->xs ? c->xs : c->stream; }
+
+// Gram partials of fragments [f0, ...) at their absolute place
+// [F][chunks][m_pad][m_pad], so concurrent fragment groups do not share rows
+double *gpart_at(const dcdft_ctx *c, int f0) {
+  return c->d_gpart + (long long)f0 * c->gram_chunks * c->m_pad * c->m_pad;
+}
+
 template <typename T>
 void hloc(dcdft_ctx *c, int f0, int f1, const T *x, T *y, double *dot = nullptr) {
   const double n = c->geo.n, sz = sizeof(T);
   Timed t(c, DCDFT_KERNEL_HLOC, 2.0 * sz * n * orbitals_in(c, f0, f1) + 8.0 * n * (f1 - f0),
           55.0 * n * orbitals_in(c, f0, f1));
-  launch_hloc<T>(c->geo, c->orbset(f0, f1), f0, f1, c->d_veff, veff_t<T>(c), x, y, c->stream,
-                 dot, 0, c->d_hdot);
+  // dot partials at [kHlocZsMax x bands) from the group's first band
+  launch_hloc<T>(c->geo, c->orbset(f0, f1), f0, f1, c->d_veff, veff_t<T>(c), x, y, xstream(c),
+                 dot, 0, c->d_hdot + (long long)kHlocZsMax * c->moff[f0]);
 }
 
 template <typename T>
 void kb_project(dcdft_ctx *c, int f0, int f1, const T *x) {
   Timed t(c, DCDFT_KERNEL_KB, (double)sizeof(T) * c->geo.n * orbitals_in(c, f0, f1), 0.0);
   launch_kb_project<T>(c->geo, c->orbset(f0, f1), c->kb(), f0, f1, x, c->d_C, c->d_cpart,
-                       c->stream);
+                       xstream(c));
 }
 
 template <typename T>
 void kb_apply(dcdft_ctx *c, int f0, int f1, T *y) {
   Timed t(c, DCDFT_KERNEL_KB, 2.0 * sizeof(T) * c->geo.n * orbitals_in(c, f0, f1), 0.0);
-  launch_kb_apply<T>(c->geo, c->orbset(f0, f1), c->kb(), f0, f1, c->d_C, y, c->stream);
+  launch_kb_apply<T>(c->geo, c->orbset(f0, f1), c->kb(), f0, f1, c->d_C, y, xstream(c));
 }
 
 // H X for the orbitals of fragments [f0, f1) in the context layout.
@@ -252,10 +262,10 @@ void gram(dcdft_ctx *c, int f0, int f1, const T *x, const T *y, double *G, doubl
     const double n = c->geo.n, sz = sizeof(T);
     Timed t(c, DCDFT_KERNEL_GRAM, sz * n * orbitals_in(c, f0, f1) * (x == y ? 1.0 : 2.0),
             2.0 * n * sum_m2(c, f0, f1));
-    launch_gram<T>(c->geo, o, f0, f1, c->gram_chunks, x, y, c->d_gpart, c->stream);
+    launch_gram<T>(c->geo, o, f0, f1, c->gram_chunks, x, y, gpart_at(c, f0), xstream(c));
   }
-  launch_gram_reduce(c->geo, o, f0, f1, c->gram_chunks, x == y, c->d_gpart, G ? G : c->d_gtmp, Gs,
-                     diag, c->stream);
+  launch_gram_reduce(c->geo, o, f0, f1, c->gram_chunks, x == y, gpart_at(c, f0),
+                     G ? G : c->d_gtmp, Gs, diag, xstream(c));
 }
 
 // Steps (a)-(l) of the fragment CG eigensolver and the Rayleigh-Ritz rotation,
@@ -273,7 +283,7 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
   const Geo &g = c->geo;
   OrbSet o = c->orbset(f0, f1);
   KBTables kb = c->kb();
-  hipStream_t s = c->stream;
+  hipStream_t s = xstream(c);
   T *psi = (T *)c->d_psi, *w = (T *)c->d_w, *p = (T *)c->d_p, *q = (T *)c->d_q;
   const double n = g.n, sz = sizeof(T);
   const double nb = orbitals_in(c, f0, f1);
@@ -292,9 +302,9 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
     // (d)-(e) P = -G + beta P_prev, X = <Psi, P>
     {
       Timed t(c, DCDFT_KERNEL_GRAM_FUSED, 4.0 * sz * n * nb, 2.0 * n * m2);
-      launch_gram_direction<T>(g, o, f0, f1, ch, psi, q, p, c->d_beta, c->d_gpart, s);
+      launch_gram_direction<T>(g, o, f0, f1, ch, psi, q, p, c->d_beta, gpart_at(c, f0), s);
     }
-    launch_gram_reduce(g, o, f0, f1, ch, 0, c->d_gpart, c->d_x, nullptr, nullptr, s);
+    launch_gram_reduce(g, o, f0, f1, ch, 0, gpart_at(c, f0), c->d_x, nullptr, nullptr, s);
     // (e)-(f) P <- P - X^T Psi, nu_i = <p_i, p_i>, <p_i, w_i>
     {
       Timed t(c, DCDFT_KERNEL_ROTATE, 4.0 * sz * n * nb, 2.0 * n * m2);
@@ -312,9 +322,9 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
     // (j) band rotations and (l) S = sym(<Psi, Psi>)
     {
       Timed t(c, DCDFT_KERNEL_GRAM_FUSED, 6.0 * sz * n * nb, 1.0 * n * m2);
-      launch_gram_update<T>(g, o, f0, f1, ch, psi, p, w, q, c->d_cos, c->d_sin, c->d_gpart, s);
+      launch_gram_update<T>(g, o, f0, f1, ch, psi, p, w, q, c->d_cos, c->d_sin, gpart_at(c, f0), s);
     }
-    launch_gram_reduce(g, o, f0, f1, ch, 1, c->d_gpart, c->d_s, nullptr, nullptr, s);
+    launch_gram_reduce(g, o, f0, f1, ch, 1, gpart_at(c, f0), c->d_s, nullptr, nullptr, s);
     // (l) S = L L^T, Psi <- L^-1 Psi, W <- L^-1 W
     launch_cholinv(o, f0, f1, c->d_s, c->d_lin, c->d_flags, s);
     {
@@ -681,8 +691,26 @@ void enqueue_step(dcdft_ctx *c) {
   launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, c->d_veff32, s);
   // 3. fragment eigensolvers
   if (c->batched) {
-    if (c->precision == DCDFT_PREC_MIXED) eigensolver_range<float>(c, 0, c->nF);
-    else eigensolver_range<double>(c, 0, c->nF);
+    auto run = [&](int a, int b) {
+      if (c->precision == DCDFT_PREC_MIXED) eigensolver_range<float>(c, a, b);
+      else eigensolver_range<double>(c, a, b);
+    };
+    if (c->streams > 1 && c->nF >= 2 && c->stream2 && !c->timing) {
+      // two fragment groups of about half the orbitals each, concurrently
+      int h = 1;
+      while (h < c->nF - 1 && 2 * c->moff[h] < c->M_tot) ++h;
+      hipEventRecord(c->ev_fork, s);
+      hipStreamWaitEvent(c->stream2, c->ev_fork, 0);
+      c->xs = s;
+      run(0, h);
+      c->xs = c->stream2;
+      run(h, c->nF);
+      hipEventRecord(c->ev_join, c->stream2);
+      hipStreamWaitEvent(s, c->ev_join, 0);
+      c->xs = nullptr;
+    } else {
+      run(0, c->nF);
+    }
   } else {
     for (int f = 0; f < c->nF; ++f) {
       if (c->precision == DCDFT_PREC_MIXED) eigensolver_range<float>(c, f, f + 1);
@@ -773,6 +801,9 @@ void dcdft_destroy(dcdft_ctx *c) {
   }
   for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
   drop_graph(c);
+  if (c->stream2) hipStreamDestroy(c->stream2);
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_join) hipEventDestroy(c->ev_join);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -930,6 +961,12 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
 #undef ALLOC
   if (hipHostMalloc((void **)&c->d_info_host, SC_COUNT * sizeof(double), 0) != hipSuccess) {
     c->last_error = "pinned host allocation failed";
+    return fail(DCDFT_ERR_HIP);
+  }
+  if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    c->last_error = "second stream or fork/join event creation failed";
     return fail(DCDFT_ERR_HIP);
   }
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
@@ -1528,27 +1565,29 @@ dcdft_status dcdft_autotune(dcdft_ctx *c, const char *cache_path, dcdft_tune_inf
 
 
 dcdft_status dcdft_get_launch(const dcdft_ctx *c, int32_t *hloc_variant, int32_t *rot_tiles,
-                              int32_t *gram_chunks, int32_t *gram_chunks_max) {
+                              int32_t *gram_chunks, int32_t *gram_chunks_max, int32_t *streams) {
   if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
   if (hloc_variant) *hloc_variant = c->geo.hloc_variant;
   if (rot_tiles) *rot_tiles = c->geo.rot_tiles;
   if (gram_chunks) *gram_chunks = c->gram_chunks;
   if (gram_chunks_max) *gram_chunks_max = c->gram_chunks_max;
+  if (streams) *streams = c->streams;
   return DCDFT_OK;
 }
 
 dcdft_status dcdft_set_launch(dcdft_ctx *c, int32_t hloc_variant, int32_t rot_tiles,
-                              int32_t gram_chunks) {
+                              int32_t gram_chunks, int32_t streams) {
   if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
-  if (!tune_valid(c, hloc_variant, rot_tiles, gram_chunks))
+  if (!tune_valid(c, hloc_variant, rot_tiles, gram_chunks) || (streams != 1 && streams != 2))
     return set_err(c, DCDFT_ERR_ARG,
-                   fmt("invalid launch shape (hloc %d, rot tiles %d, gram chunks %d; chunks "
-                       "1..%d, halo variants need a 4x4x8 box)",
-                       hloc_variant, rot_tiles, gram_chunks, c->gram_chunks_max));
+                   fmt("invalid launch shape (hloc %d, rot tiles %d, gram chunks %d, streams "
+                       "%d; chunks 1..%d, streams 1 or 2, halo variants need a 4x4x8 box)",
+                       hloc_variant, rot_tiles, gram_chunks, streams, c->gram_chunks_max));
   HIPTRY(c, hipStreamSynchronize(c->stream));
   c->geo.hloc_variant = hloc_variant;
   c->geo.rot_tiles = rot_tiles;
   c->gram_chunks = gram_chunks;
+  c->streams = streams;
   drop_graph(c);
   return DCDFT_OK;
 }

@@ -123,6 +123,15 @@ struct dcdft_ctx {
   uint64_t seed = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // Concurrent fragment groups of the batched step: the eigensolver runs over
+  // `streams` groups of fragments (split at equal orbital counts), group g on
+  // stream g (group 0 on the context's stream), forked and joined by events
+  // inside the captured step.  xs is the stream the eigensolver helpers issue
+  // to (null: the context's stream).
+  int streams = 2;
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t xs = nullptr;
   int iter = 0;
   int gram_chunks = 1;
   int gram_chunks_max = 1;
