@@ -695,18 +695,27 @@ void enqueue_step(dcdft_ctx *c) {
       if (c->precision == DCDFT_PREC_MIXED) eigensolver_range<float>(c, a, b);
       else eigensolver_range<double>(c, a, b);
     };
-    if (c->streams > 1 && c->nF >= 2 && c->stream2 && !c->timing) {
-      // two fragment groups of about half the orbitals each, concurrently
-      int h = 1;
-      while (h < c->nF - 1 && 2 * c->moff[h] < c->M_tot) ++h;
+    const int G = std::min(c->streams, c->nF);
+    if (G > 1 && !c->timing) {
+      // G fragment groups of about M_tot / G orbitals each, concurrently
+      int bound[dcdft_ctx::kMaxStreams + 1];
+      bound[0] = 0;
+      for (int q = 1; q < G; ++q) {
+        int h = bound[q - 1] + 1;
+        while (h < c->nF - (G - q) && (long long)G * c->moff[h] < (long long)q * c->M_tot) ++h;
+        bound[q] = h;
+      }
+      bound[G] = c->nF;
       hipEventRecord(c->ev_fork, s);
-      hipStreamWaitEvent(c->stream2, c->ev_fork, 0);
-      c->xs = s;
-      run(0, h);
-      c->xs = c->stream2;
-      run(h, c->nF);
-      hipEventRecord(c->ev_join, c->stream2);
-      hipStreamWaitEvent(s, c->ev_join, 0);
+      for (int q = 1; q < G; ++q) hipStreamWaitEvent(c->xstreams[q], c->ev_fork, 0);
+      for (int q = 0; q < G; ++q) {
+        c->xs = q ? c->xstreams[q] : s;
+        run(bound[q], bound[q + 1]);
+      }
+      for (int q = 1; q < G; ++q) {
+        hipEventRecord(c->ev_join[q], c->xstreams[q]);
+        hipStreamWaitEvent(s, c->ev_join[q], 0);
+      }
       c->xs = nullptr;
     } else {
       run(0, c->nF);
@@ -801,9 +810,11 @@ void dcdft_destroy(dcdft_ctx *c) {
   }
   for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
   drop_graph(c);
-  if (c->stream2) hipStreamDestroy(c->stream2);
+  for (int q = 1; q < dcdft_ctx::kMaxStreams; ++q) {
+    if (c->xstreams[q]) hipStreamDestroy(c->xstreams[q]);
+    if (c->ev_join[q]) hipEventDestroy(c->ev_join[q]);
+  }
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
-  if (c->ev_join) hipEventDestroy(c->ev_join);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -963,11 +974,15 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
     c->last_error = "pinned host allocation failed";
     return fail(DCDFT_ERR_HIP);
   }
-  if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
-    c->last_error = "second stream or fork/join event creation failed";
-    return fail(DCDFT_ERR_HIP);
+  {
+    bool ok = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;
+    for (int q = 1; q < dcdft_ctx::kMaxStreams && ok; ++q)
+      ok = hipStreamCreateWithFlags(&c->xstreams[q], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&c->ev_join[q], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      c->last_error = "group stream or fork/join event creation failed";
+      return fail(DCDFT_ERR_HIP);
+    }
   }
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
     c->last_error = "event creation failed";
@@ -1578,10 +1593,11 @@ dcdft_status dcdft_get_launch(const dcdft_ctx *c, int32_t *hloc_variant, int32_t
 dcdft_status dcdft_set_launch(dcdft_ctx *c, int32_t hloc_variant, int32_t rot_tiles,
                               int32_t gram_chunks, int32_t streams) {
   if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
-  if (!tune_valid(c, hloc_variant, rot_tiles, gram_chunks) || (streams != 1 && streams != 2))
+  if (!tune_valid(c, hloc_variant, rot_tiles, gram_chunks) || streams < 1 ||
+      streams > dcdft_ctx::kMaxStreams)
     return set_err(c, DCDFT_ERR_ARG,
                    fmt("invalid launch shape (hloc %d, rot tiles %d, gram chunks %d, streams "
-                       "%d; chunks 1..%d, streams 1 or 2, halo variants need a 4x4x8 box)",
+                       "%d; chunks 1..%d, streams 1..4, halo variants need a 4x4x8 box)",
                        hloc_variant, rot_tiles, gram_chunks, streams, c->gram_chunks_max));
   HIPTRY(c, hipStreamSynchronize(c->stream));
   c->geo.hloc_variant = hloc_variant;

@@ -128,9 +128,10 @@ struct dcdft_ctx {
   // stream g (group 0 on the context's stream), forked and joined by events
   // inside the captured step.  xs is the stream the eigensolver helpers issue
   // to (null: the context's stream).
+  static constexpr int kMaxStreams = 4;
   int streams = 2;
-  hipStream_t stream2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t xstreams[kMaxStreams] = {};  // [0] unused (the context's stream)
+  hipEvent_t ev_fork = nullptr, ev_join[kMaxStreams] = {};
   hipStream_t xs = nullptr;
   int iter = 0;
   int gram_chunks = 1;

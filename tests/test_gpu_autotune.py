@@ -65,7 +65,7 @@ def test_set_launch_rejects_invalid_shapes():
     with DCDFT.from_config(cfg) as d:
         launch = d.dcdft_get_launch()
         for bad in [(9, 4, 1, 2), (1, 3, 1, 2), (1, 4, 0, 2),
-                    (1, 4, launch["gram_chunks_max"] + 1, 2), (1, 4, 1, 3), (1, 4, 1, 0)]:
+                    (1, 4, launch["gram_chunks_max"] + 1, 2), (1, 4, 1, 5), (1, 4, 1, 0)]:
             with pytest.raises(DcdftError):
                 d.dcdft_set_launch(*bad)
         assert d.dcdft_get_launch() == launch
@@ -137,20 +137,22 @@ def test_autotune_choice_cache_and_results(tmp_path):
 @pytest.mark.parametrize("which", ["config1", "ragged"])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_concurrent_fragment_groups_bitwise(which, prec):
-    """The batched step with its eigensolver split over two streams computes the
-    same per-fragment sums as with one stream: bitwise-equal results."""
+    """The batched step with its eigensolver split over two or four streams
+    computes the same per-fragment sums as with one stream: bitwise-equal
+    results."""
     require_gpu()
     from paper_2606_21125_amd import DCDFT
     cfg = workloads.config(1) if which == "config1" else _ragged_tiny()
     out = []
-    for streams in (1, 2):
+    for streams in (1, 2, 4):
         with DCDFT.from_config(cfg, precision=prec) as d:
             l0 = d.dcdft_get_launch()
             d.dcdft_set_launch(l0["hloc_variant"], l0["rot_tiles"], l0["gram_chunks"], streams)
             assert d.dcdft_get_launch()["streams"] == streams
             out.append(_run(d, 3))
-    (i1, r1, e1), (i2, r2, e2) = out
-    assert [a["mu"] for a in i1] == [a["mu"] for a in i2]
-    assert np.array_equal(r1, r2)
-    for a, b in zip(e1, e2):
-        assert np.array_equal(a, b)
+    i1, r1, e1 = out[0]
+    for i2, r2, e2 in out[1:]:
+        assert [a["mu"] for a in i1] == [a["mu"] for a in i2]
+        assert np.array_equal(r1, r2)
+        for a, b in zip(e1, e2):
+            assert np.array_equal(a, b)
