@@ -70,9 +70,10 @@ def hloc_kernel_name(variant: str, prec_mixed: bool, box) -> str:
     nx, ny, nz = box
     halo = nx >= 4 and ny >= 4 and nz >= 8
     if variant.startswith("vec"):
-        rx = 4 if prec_mixed else 2
+        vb = 8 if variant.startswith("vec8") else 16
+        rx = vb // (4 if prec_mixed else 8)
         if halo and nx % rx == 0:
-            return f"k_hloc_vec<{t}, 1>"
+            return f"k_hloc_vec<{t}, 1, {vb}>"
         variant = "halo_pd2"
     if variant != "plane" and not halo:
         variant = "plane"

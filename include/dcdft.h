@@ -217,9 +217,10 @@ dcdft_status dcdft_kernel_time(dcdft_ctx *c, int32_t kernel, int64_t *launches, 
  *     points per thread with one-plane chunks and a few orbitals per
  *     workgroup (fewest that keep 85% of lanes busy, or the most that fill
  *     whole waves), also with z cut into 2 or 3 segments per orbital (more
- *     workgroups in flight, four extra planes read at each cut); the vector
- *     forms need n_x a multiple of 16 / element size (segments: n_z / segments
- *     >= 4) and fall back to the 2-plane haloed kernel otherwise),
+ *     workgroups in flight, four extra planes read at each cut), or 8-byte
+ *     runs (fewer registers per thread, more waves); the vector forms need n_x
+ *     a multiple of the run length (segments: n_z / segments >= 4) and fall
+ *     back to the 2-plane haloed kernel otherwise),
  *   - the rotation kernels (2, 4 or 8 sixteen-point tiles per wave),
  *   - the Gram products (the point range of a fragment cut into G chunks,
  *     G among half, one, two and four times the default),
@@ -236,7 +237,7 @@ dcdft_status dcdft_kernel_time(dcdft_ctx *c, int32_t kernel, int64_t *launches, 
 enum { DCDFT_HLOC_PLANE = 0, DCDFT_HLOC_HALO_PD2 = 1, DCDFT_HLOC_HALO_PD3 = 2,
        DCDFT_HLOC_HALO_PD4 = 3, DCDFT_HLOC_HALO_PD2_ENDS = 4, DCDFT_HLOC_VEC = 5,
        DCDFT_HLOC_VEC_WIDE = 6, DCDFT_HLOC_VEC_Z2 = 7, DCDFT_HLOC_VEC_Z3 = 8,
-       DCDFT_HLOC_COUNT = 9 };
+       DCDFT_HLOC_VEC8 = 9, DCDFT_HLOC_VEC8_WIDE = 10, DCDFT_HLOC_COUNT = 11 };
 typedef struct {
   int32_t hloc_variant;  /* DCDFT_HLOC_* */
   int32_t rot_tiles;     /* 2, 4 or 8 */

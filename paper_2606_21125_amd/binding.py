@@ -36,7 +36,7 @@ EXPORTED = [
 ]
 KERNEL_HLOC, KERNEL_GRAM, KERNEL_ROTATE, KERNEL_GRAM_FUSED, KERNEL_KB = 0, 1, 2, 3, 4
 HLOC_VARIANTS = ("plane", "halo_pd2", "halo_pd3", "halo_pd4", "halo_pd2_ends", "vec",
-                 "vec_wide", "vec_z2", "vec_z3")
+                 "vec_wide", "vec_z2", "vec_z3", "vec8", "vec8_wide")
 
 
 class DcdftSpecies(ctypes.Structure):
@@ -73,7 +73,7 @@ class DcdftScfInfo(ctypes.Structure):
 class DcdftTuneInfo(ctypes.Structure):
     _fields_ = [("hloc_variant", ctypes.c_int32), ("rot_tiles", ctypes.c_int32),
                 ("gram_chunks", ctypes.c_int32), ("from_cache", ctypes.c_int32),
-                ("ms_hloc", ctypes.c_double * 9), ("ms_rot", ctypes.c_double * 3),
+                ("ms_hloc", ctypes.c_double * 11), ("ms_rot", ctypes.c_double * 3),
                 ("gram_candidates", ctypes.c_int32 * 4), ("ms_gram", ctypes.c_double * 4)]
 
     def as_dict(self) -> dict:

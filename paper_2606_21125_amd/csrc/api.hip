@@ -289,15 +289,22 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
   const double nb = orbitals_in(c, f0, f1);
   const double m2 = sum_m2(c, f0, f1);
   const int ch = c->gram_chunks;
+  // FP32 arrays: the re-orthonormalisation of one sweep also forms the next
+  // sweep's Hs and residual (fused rotation, fewer passes).  FP64 arrays keep
+  // the separate passes (the fused rotation's three matrix-core products per
+  // tile do not fit the FP64 register budget well).
+  constexpr bool fuse = sizeof(T) == 4;
   apply_h_range<T>(c, f0, f1, psi, w);
   for (int sw = 0; sw < c->sweeps; ++sw) {
-    // (a) Hs = sym(<Psi, W>), a_i = <psi_i, w_i>
-    gram<T>(c, f0, f1, psi, w, c->d_hs_full, c->d_hs, c->d_a);
-    // (b)-(c) G = W - Hs Psi (kept in q), gamma_i = <g_i, g_i>, Fletcher-Reeves beta
-    {
+    const bool last = sw + 1 == c->sweeps;
+    if (sw == 0 || !fuse) {
+      // (a) Hs = sym(<Psi, W>), a_i = <psi_i, w_i>; (b) G = W - Hs Psi (in q),
+      // gamma_i = <g_i, g_i>
+      gram<T>(c, f0, f1, psi, w, c->d_hs_full, c->d_hs, c->d_a);
       Timed t(c, DCDFT_KERNEL_ROTATE, 3.0 * sz * n * nb, 2.0 * n * m2);
       launch_rot_residual<T>(g, o, f0, f1, c->d_hs, psi, w, q, c->d_dpart, c->d_gamma, s);
     }
+    // (c) Fletcher-Reeves beta
     launch_cg_beta(o, f0, f1, sw == 0, c->d_gamma, c->d_gamma_prev, c->d_beta, s);
     // (d)-(e) P = -G + beta P_prev, X = <Psi, P>
     {
@@ -325,15 +332,33 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
       launch_gram_update<T>(g, o, f0, f1, ch, psi, p, w, q, c->d_cos, c->d_sin, gpart_at(c, f0), s);
     }
     launch_gram_reduce(g, o, f0, f1, ch, 1, gpart_at(c, f0), c->d_s, nullptr, nullptr, s);
-    // (l) S = L L^T, Psi <- L^-1 Psi, W <- L^-1 W
-    launch_cholinv(o, f0, f1, c->d_s, c->d_lin, c->d_flags, s);
-    {
+    if (!fuse) {
+      // (l) S = L L^T, Psi <- L^-1 Psi, W <- L^-1 W
+      launch_cholinv(o, f0, f1, c->d_s, c->d_lin, c->d_flags, s);
       Timed t(c, DCDFT_KERNEL_ROTATE, 4.0 * sz * n * nb, 2.0 * n * m2);
       launch_rot_cholesky<T>(g, o, f0, f1, c->d_lin, psi, w, s);
+      continue;
+    }
+    // M = <Psi', W'> of the rotated (not yet re-orthonormalised) arrays
+    gram<T>(c, f0, f1, psi, w, c->d_hs_full, nullptr, nullptr);
+    // (l) S = L L^T; with Psi = L^-1 Psi', W = L^-1 W' the next sweep's
+    // Hs = sym(<Psi, W>) = sym(L^-1 M L^-T) and a_i = Hs_ii, B = Hs L^-1
+    launch_cholinv(o, f0, f1, c->d_s, c->d_lin, c->d_flags, s, c->d_hs_full, c->d_hs, c->d_a,
+                   c->d_bmat);
+    if (!last) {
+      // Psi <- L^-1 Psi', W <- L^-1 W' and the next sweep's (b): G = W - B Psi'
+      Timed t(c, DCDFT_KERNEL_ROTATE, 5.0 * sz * n * nb, 6.0 * n * m2);
+      launch_rot_cholres<T>(g, o, f0, f1, c->d_lin, c->d_bmat, psi, w, q, c->d_dpart,
+                            c->d_gamma, s);
+    } else {
+      // after the last sweep only Psi is used (W is rebuilt by the next step)
+      Timed t(c, DCDFT_KERNEL_ROTATE, 2.0 * sz * n * nb, 2.0 * n * m2);
+      launch_rot_cholesky<T>(g, o, f0, f1, c->d_lin, psi, (T *)nullptr, s);
     }
   }
-  // Rayleigh-Ritz, then core weights w_i = dV sum_core psi_i^2
-  gram<T>(c, f0, f1, psi, w, c->d_hs, nullptr, nullptr);
+  // Rayleigh-Ritz on Hs = sym(<Psi, W>) (from the last sweep's re-orthonormalisation
+  // when fused), then core weights w_i = dV sum_core psi_i^2
+  if (!fuse) gram<T>(c, f0, f1, psi, w, c->d_hs, nullptr, nullptr);
   launch_syev(o, f0, f1, c->d_hs, c->d_u, c->d_eps, c->d_flags, s);
   {
     Timed t(c, DCDFT_KERNEL_ROTATE, 2.0 * sz * n * nb, 2.0 * n * m2);
@@ -958,6 +983,7 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   }
   ALLOC(c->d_hs_full, c->nF * mp2);
   ALLOC(c->d_hs, c->nF * mp2);
+  ALLOC(c->d_bmat, c->nF * mp2);
   ALLOC(c->d_x, c->nF * mp2);
   ALLOC(c->d_s, c->nF * mp2);
   ALLOC(c->d_lin, c->nF * mp2);

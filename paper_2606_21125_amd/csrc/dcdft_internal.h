@@ -56,6 +56,8 @@ enum {
   HLOC_VEC_WIDE = DCDFT_HLOC_VEC_WIDE,            // ... whole-wave orbital groups
   HLOC_VEC_Z2 = DCDFT_HLOC_VEC_Z2,                // HLOC_VEC with z cut into 2 segments
   HLOC_VEC_Z3 = DCDFT_HLOC_VEC_Z3,                // ... 3 segments
+  HLOC_VEC8 = DCDFT_HLOC_VEC8,                    // 8-byte x runs, few orbitals/WG
+  HLOC_VEC8_WIDE = DCDFT_HLOC_VEC8_WIDE,          // ... whole-wave orbital groups
   HLOC_NVARIANT = DCDFT_HLOC_COUNT
 };
 bool hloc_halo_ok(const Geo &g);
@@ -182,7 +184,7 @@ struct dcdft_ctx {
   double *d_gtmp = nullptr;          // Gram result when only the symmetric part is kept
   double *d_dpart = nullptr;         // per-workgroup band partials [F][wpf][2][m_pad]
   double *d_hs_full = nullptr, *d_hs = nullptr, *d_x = nullptr, *d_s = nullptr, *d_lin = nullptr,
-         *d_u = nullptr;
+         *d_u = nullptr, *d_bmat = nullptr;
 
   // per-band [M_tot]
   double *d_gamma = nullptr, *d_gamma_prev = nullptr, *d_beta = nullptr, *d_nu = nullptr,
@@ -307,9 +309,17 @@ void launch_copy_band(const OrbSet &o, int f0, int f1, const double *src, double
 // cp[B] += sum_a E_a C[f][a][i]^2
 void launch_kb_quad(const OrbSet &o, int f0, int f1, const KBTables &kb, const double *C,
                     double *cp, hipStream_t s);
-// S -> Linv (row-major lower-triangular inverse of the Cholesky factor), FP64
+// Psi <- Linv Psi', W <- Linv W' (in place) and G = W - Bm Psi' into gout, with
+// gamma = dV |g|^2 (Bm = Hs Linv from launch_cholinv)
+template <typename T>
+void launch_rot_cholres(const Geo &g, const OrbSet &o, int f0, int f1, const double *Linv,
+                        const double *Bm, T *psi, T *w, T *gout, double *dpart, double *gamma,
+                        hipStream_t s);
+// S -> Linv (row-major lower-triangular inverse of the Cholesky factor), FP64;
+// with M = <Psi', W'> also Hs = sym(Linv M Linv^T), its diagonal and Bm = Hs Linv
 void launch_cholinv(const OrbSet &o, int f0, int f1, const double *S, double *Linv, int *flags,
-                    hipStream_t s);
+                    hipStream_t s, const double *M = nullptr, double *Hs = nullptr,
+                    double *adiag = nullptr, double *Bm = nullptr);
 // Hs -> U (eigenvectors as columns), eps (ascending), FP64 Jacobi
 void launch_syev(const OrbSet &o, int f0, int f1, const double *Hs, double *U, double *eps,
                  int *flags, hipStream_t s);

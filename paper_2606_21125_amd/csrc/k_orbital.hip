@@ -212,7 +212,7 @@ __global__ void __launch_bounds__(1024) k_hloc_halo(Geo g, const int *__restrict
 }
 
 // Vector form of the haloed-plane kernel: each thread owns a run of
-// RX = 16 / sizeof(T) consecutive x points (one 16-byte load, store and LDS
+// RX = VB / sizeof(T) consecutive x points (one VB-byte load, store and LDS
 // access per plane for the run; the x neighbours come from the two runs beside
 // it), opw orbitals share a workgroup (tpo = nx / RX * ny threads each), and
 // V_eff is read in the storage type (its FP32 rounding on the mixed path, which
@@ -221,14 +221,14 @@ __global__ void __launch_bounds__(1024) k_hloc_halo(Geo g, const int *__restrict
 // aligned arrays.  Bands past the batch are computed as duplicates of the last
 // band (identical values to identical addresses) so every load stays
 // unconditional; only the per-band dot is masked.
-template <typename T, int PD>
+template <typename T, int PD, int VB>
 __global__ void __launch_bounds__(1024) k_hloc_vec(Geo g, const int *__restrict__ band_frag,
                                                    long long b0, long long nbands, int opw,
                                                    int zs, int vbase, const T *__restrict__ veff,
                                                    const T *__restrict__ x, T *__restrict__ y,
                                                    double *__restrict__ dot,
                                                    double *__restrict__ dot_part) {
-  constexpr int RX = 16 / sizeof(T);
+  constexpr int RX = VB / sizeof(T);
   typedef T vec __attribute__((ext_vector_type(RX)));
   extern __shared__ __attribute__((aligned(16))) char lds_vec[];
   const int nx = g.nl[0], ny = g.nl[1], nz = g.nl[2];
@@ -739,9 +739,9 @@ void launch_halo(const Geo &g, long long nb, const OrbSet &o, int f0, const doub
 // Orbitals per workgroup of the vector kernel (0: not applicable): wide = the
 // largest count whose thread total is a whole number of waves, otherwise the
 // smallest count that keeps at least 85% of the lanes busy.
-template <typename T>
+template <typename T, int VB>
 int vec_opw(const Geo &g, bool wide) {
-  constexpr int RX = 16 / sizeof(T);
+  constexpr int RX = VB / sizeof(T) > 0 ? VB / sizeof(T) : 1;
   if (g.nl[0] % RX || !hloc_halo_ok(g)) return 0;
   const int tpo = g.nl[0] / RX * g.nl[1];
   if (tpo > 1024) return 0;
@@ -759,14 +759,14 @@ int vec_opw(const Geo &g, bool wide) {
   return lds1 <= 65536 ? 1 : 0;
 }
 
-template <typename T, int PD>
+template <typename T, int PD, int VB>
 void launch_vec(const Geo &g, long long nb, int opw, int zs, const OrbSet &o, int f0,
                 const T *veffT, const T *x, T *y, hipStream_t s, double *dot, double *dot_part,
                 int vbase) {
-  const int tpo = g.nl[0] / (16 / (int)sizeof(T)) * g.nl[1];
+  const int tpo = g.nl[0] / (VB / (int)sizeof(T)) * g.nl[1];
   const size_t lds = (size_t)opw * 2 * (g.nl[1] + 8) * (g.nl[0] + 32) * sizeof(T);
   const unsigned grid = (unsigned)((nb + opw - 1) / opw * zs);
-  hipLaunchKernelGGL((k_hloc_vec<T, PD>), dim3(grid), dim3(opw * tpo), lds, s, g, o.band_frag,
+  hipLaunchKernelGGL((k_hloc_vec<T, PD, VB>), dim3(grid), dim3(opw * tpo), lds, s, g, o.band_frag,
                      o.b0(f0), nb, opw, zs, vbase, veffT, x, y, dot, dot_part);
   if (dot && zs > 1)
     hipLaunchKernelGGL(k_dot_segments, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, g,
@@ -790,16 +790,23 @@ void launch_hloc(const Geo &g, const OrbSet &o, int f0, int f1, const double *ve
   if (nb <= 0) return;
   const int plane = g.nl[0] * g.nl[1];
   int hv = g.hloc_variant;
-  if (hv == HLOC_VEC || hv == HLOC_VEC_WIDE || hv == HLOC_VEC_Z2 || hv == HLOC_VEC_Z3) {
-    const int opw = vec_opw<T>(g, hv == HLOC_VEC_WIDE);
+  if (hv == HLOC_VEC || hv == HLOC_VEC_WIDE || hv == HLOC_VEC_Z2 || hv == HLOC_VEC_Z3 ||
+      hv == HLOC_VEC8 || hv == HLOC_VEC8_WIDE) {
+    const bool v8 = hv == HLOC_VEC8 || hv == HLOC_VEC8_WIDE;
+    const bool wide = hv == HLOC_VEC_WIDE || hv == HLOC_VEC8_WIDE;
+    const int opw = v8 ? vec_opw<T, 8>(g, wide) : vec_opw<T, 16>(g, wide);
     const int zs = hv == HLOC_VEC_Z2 ? 2 : (hv == HLOC_VEC_Z3 ? 3 : 1);
-    const bool aligned = ((uintptr_t)x % 16 == 0) && ((uintptr_t)y % 16 == 0) && veffT &&
-                         ((uintptr_t)veffT % 16 == 0);
+    const int vb = v8 ? 8 : 16;
+    const bool aligned = ((uintptr_t)x % vb == 0) && ((uintptr_t)y % vb == 0) && veffT &&
+                         ((uintptr_t)veffT % vb == 0);
     // z segments need nz / zs >= 4 and, with a dot, a partial buffer of
     // kHlocZsMax x nb doubles
     const bool zs_ok = zs == 1 || (g.nl[2] / zs >= 4 && (!dot || dot_part));
     if (opw > 0 && aligned && zs_ok) {
-      launch_vec<T, 1>(g, nb, opw, zs, o, f0, veffT, x, y, s, dot, dot_part, vbase);
+      if (v8)
+        launch_vec<T, 1, 8>(g, nb, opw, zs, o, f0, veffT, x, y, s, dot, dot_part, vbase);
+      else
+        launch_vec<T, 1, 16>(g, nb, opw, zs, o, f0, veffT, x, y, s, dot, dot_part, vbase);
       return;
     }
     hv = HLOC_HALO_PD2;  // same results

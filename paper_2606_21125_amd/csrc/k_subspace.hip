@@ -193,25 +193,141 @@ k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int 
   }
 }
 
-// out_k[B] = dV sum over the workgroup partials of band B (k = 0, 1; null skips).
+// Cholesky re-orthonormalisation fused with the next sweep's residual: from
+// Psi' and W' (in place), Psi = L^-1 Psi', W = L^-1 W' and G = W - B Psi' with
+// B = Hs L^-1 (so G = W - Hs Psi), with the per-band sums |g|^2 as one FP64
+// partial per workgroup in dpart[(f * wpf + wg) * 2 * m_pad + j].  Same tiling,
+// LDS layout and load pipeline as k_rot_fused, with both matrices staged.
+template <typename T, int TM, int NT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+k_rot_cholres(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ Linv,
+              const double *__restrict__ Bm, T *psi, T *w, T *gout,
+              double *__restrict__ dpart) {
+  typedef Mfma<T> MM;
+  constexpr int MP = 16 * TM;
+  constexpr int NS = 4 * TM;
+  constexpr int S2 = MP + 16 / (int)sizeof(T);
+  constexpr bool PF = sizeof(T) == 4;   // FP32: load the next tile during this one
+  __shared__ __attribute__((aligned(16))) T R1[MP * S2];
+  __shared__ __attribute__((aligned(16))) T R2[MP * S2];
+  __shared__ double red[4][MP];
+  const int f = f0 + blockIdx.x / wpf;
+  const int wg = blockIdx.x % wpf;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int mf = o.m[f], mp = o.m_pad;
+  const double *Lf = Linv + (long long)f * mp * mp, *Bf = Bm + (long long)f * mp * mp;
+  for (int e = threadIdx.x; e < MP * MP; e += blockDim.x) {
+    const int j = e / MP, i = e % MP;
+    const bool in = i < mf && j < mf;
+    R1[j * S2 + i] = in ? (T)Lf[j * mp + i] : (T)0;
+    R2[j * S2 + i] = in ? (T)Bf[j * mp + i] : (T)0;
+  }
+  for (int e = lane; e < MP; e += 64) red[wave][e] = 0.0;
+  __syncthreads();
+  const long long base = o.moff[f] * (long long)g.n;
+  const int jl = lane & 15, kk = lane >> 4;
+  auto tile_p0 = [&](int u) { return ((wg * NT + u) * 4 + wave) * 16; };
+  auto load_rows = [&](int u, const T *xs, T *bx) {
+    const int pc = tile_p0(u) + jl;
+    const bool pin = pc < g.n;
+    const int lo = kk * NS * g.n + (pin ? pc : g.n - 1);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const T v = (xs + base + (long long)s * g.n)[lo];
+      bx[s] = (kk * NS + s < mf && pin) ? v : (T)0;
+    }
+  };
+  T bx[NS], bw[NS];
+  load_rows(0, psi, bx);
+  load_rows(0, w, bw);
+  for (int u = 0; u < NT; ++u) {
+    const int p0 = tile_p0(u);
+    if (p0 >= g.n) break;
+    const int pc = p0 + jl;
+    const bool pin = pc < g.n;
+    const int lo_out = MM::row_l(kk) * g.n + (pin ? pc : g.n - 1);
+    T bxn[PF ? NS : 1], bwn[PF ? NS : 1];
+    if (PF) {
+      load_rows(u + 1 < NT ? u + 1 : u, psi, bxn);
+      load_rows(u + 1 < NT ? u + 1 : u, w, bwn);
+    }
+    typename MM::acc_t ap[TM], aw[TM], ab[TM];
+#pragma unroll
+    for (int jt = 0; jt < TM; ++jt) {
+      ap[jt] = MM::zero();
+      aw[jt] = MM::zero();
+      ab[jt] = MM::zero();
+      T a[NS];
+      lds_read_vec<T, NS>(R1 + (jt * 16 + jl) * S2 + kk * NS, a);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        ap[jt] = MM::mma(a[s], bx[s], ap[jt]);
+        aw[jt] = MM::mma(a[s], bw[s], aw[jt]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      lds_read_vec<T, NS>(R2 + (jt * 16 + jl) * S2 + kk * NS, a);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) ab[jt] = MM::mma(a[s], bx[s], ab[jt]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int jt = 0; jt < TM; ++jt)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int j = jt * 16 + MM::row(kk, rr);
+        const bool ok = j < mf && pin;
+        const long long ro = base + (long long)(jt * 16 + MM::row_u(rr)) * g.n;
+        const T vg = aw[jt][rr] - ab[jt][rr];
+        if (ok) {
+          (psi + ro)[lo_out] = ap[jt][rr];
+          (w + ro)[lo_out] = aw[jt][rr];
+          (gout + ro)[lo_out] = vg;
+        }
+        const double d = row16_sum(ok ? (double)vg * (double)vg : 0.0);
+        if (jl == 0) red[wave][j] += d;
+      }
+    if (PF) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        bx[s] = bxn[s];
+        bw[s] = bwn[s];
+      }
+    } else if (u + 1 < NT) {
+      load_rows(u + 1, psi, bx);
+      load_rows(u + 1, w, bw);
+    }
+  }
+  __syncthreads();
+  double *out = dpart + ((long long)f * wpf + wg) * 2 * mp;
+  for (int j = threadIdx.x; j < MP; j += blockDim.x)
+    out[j] = red[0][j] + red[1][j] + red[2][j] + red[3][j];
+}
+
+// out_k[B] = dV sum over the workgroup partials of band B (k = 0, 1; null skips):
+// one wave per band, lanes over the partials, fixed-order wave sum.
 __global__ void __launch_bounds__(256) k_band_reduce(Geo g, OrbSet o, long long b0, long long nb,
                                                      int wpf, const double *__restrict__ dpart,
                                                      double *__restrict__ out0,
                                                      double *__restrict__ out1) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nb) return;
+  const long long t = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t >= nb) return;  // wave-uniform
   const long long B = b0 + t;
   const int f = o.band_frag[B];
   const int i = (int)(B - o.moff[f]);
   const int mp = o.m_pad;
   double s0 = 0.0, s1 = 0.0;
-  for (int wg = 0; wg < wpf; ++wg) {
+  for (int wg = lane; wg < wpf; wg += 64) {
     const double *pp = dpart + ((long long)f * wpf + wg) * 2 * mp;
     s0 += pp[i];
-    s1 += pp[mp + i];
+    if (out1) s1 += pp[mp + i];
   }
-  if (out0) out0[B] = g.dv * s0;
-  if (out1) out1[B] = g.dv * s1;
+  s0 = wave_sum(s0);
+  if (out1) s1 = wave_sum(s1);
+  if (lane == 0) {
+    if (out0) out0[B] = g.dv * s0;
+    if (out1) out1[B] = g.dv * s1;
+  }
 }
 
 // Gram products.  Workgroup = (fragment, chunk of points).  Per step of KT = 32
@@ -487,10 +603,20 @@ __global__ void __launch_bounds__(256) k_symmetrize(OrbSet o, int f0, int nf,
 }
 
 // Cholesky S = L L^T in LDS and the rows of L^-1 (row-major, lower triangular).
+// With M = <Psi', W'> (the raw Gram of the arrays before re-orthonormalisation)
+// the kernel also forms, for Psi = L^-1 Psi' and W = L^-1 W',
+//   Hs = sym(L^-1 M L^-T) = sym(<Psi, W>)  -> Hs (and its diagonal into adiag),
+//   B  = Hs L^-1                          -> Bm,
+// so that G = W - Hs Psi = L^-1 W' - B Psi' needs no second pass.
 __global__ void __launch_bounds__(256) k_cholinv(OrbSet o, int f0, const double *__restrict__ S,
-                                                 double *__restrict__ Linv, int *flags) {
+                                                 double *__restrict__ Linv, int *flags,
+                                                 const double *__restrict__ M,
+                                                 double *__restrict__ Hs,
+                                                 double *__restrict__ adiag,
+                                                 double *__restrict__ Bm) {
   __shared__ double A[kMaxOrb * (kMaxOrb + 1)];
   __shared__ double X[kMaxOrb * (kMaxOrb + 1)];
+  __shared__ double Cb[kMaxOrb * (kMaxOrb + 1)];
   __shared__ int bad;
   const int f = f0 + blockIdx.x;
   const int mf = o.m[f], mp = o.m_pad;
@@ -533,6 +659,42 @@ __global__ void __launch_bounds__(256) k_cholinv(OrbSet o, int f0, const double 
     for (int c = tx; c < mp; c += 16)
       Lf[r * mp + c] = (r < mf && c < mf && r >= c) ? X[r * ld + c] : 0.0;
   if (threadIdx.x == 0 && bad) atomicOr(flags, FLAG_NOT_SPD);
+  if (!M) return;
+  const double *Mf = M + (long long)f * mp * mp;
+  double *Hf = Hs + (long long)f * mp * mp, *Bf = Bm + (long long)f * mp * mp;
+  for (int i = ty; i < mf; i += 16)
+    for (int j = tx; j < mf; j += 16) A[i * ld + j] = Mf[i * mp + j];
+  __syncthreads();
+  // T = X M (X lower triangular)
+  for (int j = ty; j < mf; j += 16)
+    for (int l = tx; l < mf; l += 16) {
+      double acc = 0.0;
+      for (int i = 0; i <= j; ++i) acc += X[j * ld + i] * A[i * ld + l];
+      Cb[j * ld + l] = acc;
+    }
+  __syncthreads();
+  // L^-1 M L^-T = T X^T
+  for (int j = ty; j < mf; j += 16)
+    for (int l = tx; l < mf; l += 16) {
+      double acc = 0.0;
+      for (int i = 0; i <= l; ++i) acc += Cb[j * ld + i] * X[l * ld + i];
+      A[j * ld + l] = acc;
+    }
+  __syncthreads();
+  for (int j = ty; j < mf; j += 16)
+    for (int l = tx; l < mf; l += 16) Cb[j * ld + l] = 0.5 * (A[j * ld + l] + A[l * ld + j]);
+  __syncthreads();
+  for (int j = ty; j < mp; j += 16)
+    for (int l = tx; l < mp; l += 16) {
+      const bool in = j < mf && l < mf;
+      Hf[j * mp + l] = in ? Cb[j * ld + l] : 0.0;
+      if (in && j == l) adiag[o.moff[f] + j] = Cb[j * ld + j];
+      // B = Hs X: B[j][l] = sum_{k >= l} Hs[j][k] X[k][l]
+      double acc = 0.0;
+      if (in)
+        for (int k = l; k < mf; ++k) acc += Cb[j * ld + k] * X[k * ld + l];
+      Bf[j * mp + l] = acc;
+    }
 }
 
 // Round-robin (circle) pairing: in round r of mm - 1, pair k.
@@ -733,21 +895,28 @@ __global__ void k_cg_theta(long long b0, long long nb, const double *__restrict_
 }
 
 // c'[B] += sum_a E_a C[f][a][i]^2 (the projector part of <p, H p>)
-__global__ void k_kb_quad(long long b0, long long nb, const int *__restrict__ band_frag,
-                          const long long *__restrict__ moff, const int *__restrict__ A,
-                          int A_max, int m_pad, const double *__restrict__ E,
-                          const double *__restrict__ C, double *__restrict__ cp) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nb) return;
+// cp[B] += sum_a E_a C[f][a][i]^2 (the projector part of <p, H p>): one wave
+// per band, lanes over the fragment's atoms, fixed-order wave sum.
+__global__ void __launch_bounds__(256) k_kb_quad(long long b0, long long nb,
+                                                 const int *__restrict__ band_frag,
+                                                 const long long *__restrict__ moff,
+                                                 const int *__restrict__ A, int A_max, int m_pad,
+                                                 const double *__restrict__ E,
+                                                 const double *__restrict__ C,
+                                                 double *__restrict__ cp) {
+  const long long t = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t >= nb) return;  // wave-uniform
   const long long B = b0 + t;
   const int f = band_frag[B];
   const int i = (int)(B - moff[f]);
   double s = 0.0;
-  for (int a = 0; a < A[f]; ++a) {
+  for (int a = lane; a < A[f]; a += 64) {
     const double v = C[((long long)f * A_max + a) * m_pad + i];
     s += E[(long long)f * A_max + a] * v * v;
   }
-  cp[B] += s;
+  s = wave_sum(s);
+  if (lane == 0) cp[B] += s;
 }
 
 __global__ void k_copy(long long b0, long long nb, const double *__restrict__ src,
@@ -817,7 +986,7 @@ void band_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int wpf, const d
                  double *out0, double *out1, hipStream_t s) {
   const long long nb = o.nb(f0, f1);
   if (nb <= 0) return;
-  hipLaunchKernelGGL(k_band_reduce, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, g, o,
+  hipLaunchKernelGGL(k_band_reduce, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s, g, o,
                      o.b0(f0), nb, wpf, dpart, out0, out1);
 }
 
@@ -891,6 +1060,36 @@ void launch_rot_cholesky(const Geo &g, const OrbSet &o, int f0, int f1, const do
 }
 
 template <typename T>
+void launch_rot_cholres(const Geo &g, const OrbSet &o, int f0, int f1, const double *Linv,
+                        const double *Bm, T *psi, T *w, T *gout, double *dpart, double *gamma,
+                        hipStream_t s) {
+  if (f1 <= f0) return;
+  const int wpf = rot_wpf(g);
+  const dim3 grid((f1 - f0) * wpf), block(256);
+#define DCDFT_CR(TMV)                                                                         \
+  do {                                                                                        \
+    if (g.rot_tiles == 2)                                                                     \
+      hipLaunchKernelGGL((k_rot_cholres<T, TMV, 2>), grid, block, 0, s, g, o, f0, wpf, Linv, Bm, \
+                         psi, w, gout, dpart);                                                \
+    else if (g.rot_tiles == 8)                                                                \
+      hipLaunchKernelGGL((k_rot_cholres<T, TMV, 8>), grid, block, 0, s, g, o, f0, wpf, Linv, Bm, \
+                         psi, w, gout, dpart);                                                \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_rot_cholres<T, TMV, 4>), grid, block, 0, s, g, o, f0, wpf, Linv, Bm, \
+                         psi, w, gout, dpart);                                                \
+  } while (0)
+  switch (o.tiles) {
+    case 1: DCDFT_CR(1); break;
+    case 2: DCDFT_CR(2); break;
+    case 3: DCDFT_CR(3); break;
+    case 4: DCDFT_CR(4); break;
+    default: DCDFT_CR(5); break;
+  }
+#undef DCDFT_CR
+  band_reduce(g, o, f0, f1, wpf, dpart, gamma, nullptr, s);
+}
+
+template <typename T>
 void launch_rot_ritz(const Geo &g, const OrbSet &o, int f0, int f1, const double *U, T *psi,
                      double *dpart, double *wcore, hipStream_t s) {
   const int wpf = rot_wpf(g);
@@ -916,7 +1115,10 @@ void launch_rot_ritz(const Geo &g, const OrbSet &o, int f0, int f1, const double
   template void launch_rot_cholesky<T>(const Geo &, const OrbSet &, int, int, const double *, T *, \
                                        T *, hipStream_t);                                       \
   template void launch_rot_ritz<T>(const Geo &, const OrbSet &, int, int, const double *, T *,   \
-                                   double *, double *, hipStream_t);
+                                   double *, double *, hipStream_t);                          \
+  template void launch_rot_cholres<T>(const Geo &, const OrbSet &, int, int, const double *,     \
+                                      const double *, T *, T *, T *, double *, double *,         \
+                                      hipStream_t);
 DCDFT_INSTANTIATE(double)
 DCDFT_INSTANTIATE(float)
 #undef DCDFT_INSTANTIATE
@@ -932,9 +1134,10 @@ void launch_gram_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int chunk
 }
 
 void launch_cholinv(const OrbSet &o, int f0, int f1, const double *S, double *Linv, int *flags,
-                    hipStream_t s) {
+                    hipStream_t s, const double *M, double *Hs, double *adiag, double *Bm) {
   if (f1 <= f0) return;
-  hipLaunchKernelGGL(k_cholinv, dim3(f1 - f0), dim3(256), 0, s, o, f0, S, Linv, flags);
+  hipLaunchKernelGGL(k_cholinv, dim3(f1 - f0), dim3(256), 0, s, o, f0, S, Linv, flags, M, Hs,
+                     adiag, Bm);
 }
 
 void launch_syev(const OrbSet &o, int f0, int f1, const double *Hs, double *U, double *eps,
@@ -980,7 +1183,7 @@ void launch_kb_quad(const OrbSet &o, int f0, int f1, const KBTables &kb, const d
                     double *cp, hipStream_t s) {
   const long long nb = o.nb(f0, f1);
   if (nb <= 0) return;
-  hipLaunchKernelGGL(k_kb_quad, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, o.b0(f0), nb,
+  hipLaunchKernelGGL(k_kb_quad, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s, o.b0(f0), nb,
                      o.band_frag, o.moff, kb.A, kb.A_max, o.m_pad, kb.E, C, cp);
 }
 

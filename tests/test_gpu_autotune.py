@@ -60,11 +60,11 @@ def test_stencil_variants_bitwise(which, prec):
 
 def test_set_launch_rejects_invalid_shapes():
     require_gpu()
-    from paper_2606_21125_amd import DCDFT, DcdftError
+    from paper_2606_21125_amd import DCDFT, DcdftError, HLOC_VARIANTS
     cfg = workloads.config(1)
     with DCDFT.from_config(cfg) as d:
         launch = d.dcdft_get_launch()
-        for bad in [(9, 4, 1, 2), (1, 3, 1, 2), (1, 4, 0, 2),
+        for bad in [(len(HLOC_VARIANTS), 4, 1, 2), (-1, 4, 1, 2), (1, 3, 1, 2), (1, 4, 0, 2),
                     (1, 4, launch["gram_chunks_max"] + 1, 2), (1, 4, 1, 5), (1, 4, 1, 0)]:
             with pytest.raises(DcdftError):
                 d.dcdft_set_launch(*bad)
