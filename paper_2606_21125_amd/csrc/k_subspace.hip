@@ -602,7 +602,42 @@ __global__ void __launch_bounds__(256) k_symmetrize(OrbSet o, int f0, int nf,
   Gs[(long long)f * mp * mp + e] = 0.5 * (Gf[i * mp + j] + Gf[j * mp + i]);
 }
 
-// Cholesky S = L L^T in LDS and the rows of L^-1 (row-major, lower triangular).
+// C = P Q (QT: C = P Q^T) for nt x nt tiles of 16 x 16 LDS matrices (row
+// stride ld, entries past the fragment's size zero) on the FP64 matrix cores;
+// wave w takes the 16-row bands w, w + 4, ... of C and hands every entry to
+// out(row, column, value).
+template <bool QT, typename F>
+__device__ inline void lds_gemm_f64(const double *P, const double *Q, int ld, int nt, F out) {
+  typedef Mfma<double> MM;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, kk = lane >> 4;
+  for (int rt = wave; rt < nt; rt += (int)(blockDim.x >> 6)) {
+    MM::acc_t acc[kMaxTiles];
+#pragma unroll
+    for (int ct = 0; ct < kMaxTiles; ++ct) acc[ct] = MM::zero();
+    for (int k = 0; k < 16 * nt; k += 4) {
+      const double a = P[(rt * 16 + r) * ld + k + kk];
+#pragma unroll
+      for (int ct = 0; ct < kMaxTiles; ++ct)
+        if (ct < nt) {
+          const double b = QT ? Q[(ct * 16 + r) * ld + k + kk] : Q[(k + kk) * ld + ct * 16 + r];
+          acc[ct] = MM::mma(a, b, acc[ct]);
+        }
+    }
+#pragma unroll
+    for (int ct = 0; ct < kMaxTiles; ++ct)
+      if (ct < nt)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) out(rt * 16 + MM::row(kk, rr), ct * 16 + r, acc[ct][rr]);
+  }
+}
+
+// Cholesky S = L L^T and the rows of L^-1 (row-major, lower triangular), with
+// the matrix in registers: thread (ty, tx) of a 16 x 16 grid holds the entries
+// (ty + 16 a, tx + 16 b).  At elimination step k the owners of column k of S
+// and of row k of L^-1 publish them to LDS (two buffers, one barrier a step),
+// and every thread scales and applies them to its own entries; L^-1 comes from
+// the same elimination applied to the identity.
 // With M = <Psi', W'> (the raw Gram of the arrays before re-orthonormalisation)
 // the kernel also forms, for Psi = L^-1 Psi' and W = L^-1 W',
 //   Hs = sym(L^-1 M L^-T) = sym(<Psi, W>)  -> Hs (and its diagonal into adiag),
@@ -614,87 +649,124 @@ __global__ void __launch_bounds__(256) k_cholinv(OrbSet o, int f0, const double 
                                                  double *__restrict__ Hs,
                                                  double *__restrict__ adiag,
                                                  double *__restrict__ Bm) {
-  __shared__ double A[kMaxOrb * (kMaxOrb + 1)];
-  __shared__ double X[kMaxOrb * (kMaxOrb + 1)];
-  __shared__ double Cb[kMaxOrb * (kMaxOrb + 1)];
+  constexpr int NT = kMaxTiles;
+  __shared__ double colb[2][kMaxOrb], xrowb[2][kMaxOrb];
+  __shared__ double B0[kMaxOrb * (kMaxOrb + 1)];
+  __shared__ double B1[kMaxOrb * (kMaxOrb + 1)];
+  __shared__ double B2[kMaxOrb * (kMaxOrb + 1)];
   __shared__ int bad;
   const int f = f0 + blockIdx.x;
   const int mf = o.m[f], mp = o.m_pad;
-  const int ld = mf + 1;   // odd row stride: column walks hit distinct banks
   const double *Sf = S + (long long)f * mp * mp;
   double *Lf = Linv + (long long)f * mp * mp;
-  // 16 x 16 thread grid (no runtime division in the index arithmetic)
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   if (threadIdx.x == 0) bad = 0;
-  for (int i = ty; i < mf; i += 16)
-    for (int j = tx; j < mf; j += 16) {
-      A[i * ld + j] = 0.5 * (Sf[i * mp + j] + Sf[j * mp + i]);
-      X[i * ld + j] = (i == j) ? 1.0 : 0.0;
+  double a[NT][NT], x[NT][NT];
+#pragma unroll
+  for (int ai = 0; ai < NT; ++ai)
+#pragma unroll
+    for (int bj = 0; bj < NT; ++bj) {
+      const int i = ty + 16 * ai, j = tx + 16 * bj;
+      const bool in = i < mf && j < mf;
+      a[ai][bj] = in ? 0.5 * (Sf[i * mp + j] + Sf[j * mp + i]) : 0.0;
+      x[ai][bj] = (in && i == j) ? 1.0 : 0.0;
     }
-  for (int k = 0; k < mf; ++k) {
-    __syncthreads();
-    // every thread takes the pivot itself (A_kk is not written, so no barrier
-    // separates reading it from scaling with it)
-    double d = A[k * ld + k];
-    if (!(d > 0.0)) {
-      if (threadIdx.x == 0) bad = 1;
-      d = 1.0;
-    }
-    const double rdk = 1.0 / sqrt(d);
-    for (int i = k + 1 + threadIdx.x; i < mf; i += blockDim.x) A[i * ld + k] *= rdk;
-    // L^-1 by the same elimination applied to the identity: row k of X is
-    // divided by L_kk here, and L_ik times it is subtracted from the rows
-    // below in the next phase (X rows r hold the finished rows of L^-1 for
-    // r <= k)
-    for (int c = threadIdx.x; c <= k; c += blockDim.x) X[k * ld + c] *= rdk;
-    __syncthreads();
-    for (int i = k + 1 + ty; i < mf; i += 16) {
-      const double lik = A[i * ld + k];
-      for (int j = k + 1 + tx; j <= i; j += 16) A[i * ld + j] -= lik * A[j * ld + k];
-      for (int c = tx; c <= k; c += 16) X[i * ld + c] -= lik * X[k * ld + c];
+#pragma unroll
+  for (int kb = 0; kb < NT; ++kb) {
+    if (kb * 16 >= mf) break;
+    for (int kr = 0; kr < 16; ++kr) {
+      const int k = kb * 16 + kr;
+      if (k >= mf) break;
+      const int buf = k & 1;
+      if (tx == kr)
+#pragma unroll
+        for (int ai = 0; ai < NT; ++ai) colb[buf][ty + 16 * ai] = a[ai][kb];
+      if (ty == kr)
+#pragma unroll
+        for (int bj = 0; bj < NT; ++bj) xrowb[buf][tx + 16 * bj] = x[kb][bj];
+      __syncthreads();
+      double d = colb[buf][k];
+      if (!(d > 0.0)) {
+        if (threadIdx.x == 0) bad = 1;
+        d = 1.0;
+      }
+      const double rdk = 1.0 / sqrt(d);
+      double li[NT], lj[NT], xk[NT];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        li[q] = colb[buf][ty + 16 * q] * rdk;
+        lj[q] = colb[buf][tx + 16 * q] * rdk;
+        xk[q] = xrowb[buf][tx + 16 * q] * rdk;
+      }
+      // S_ij -= L_ik L_jk below and right of the pivot; row k of L^-1 is row k
+      // of the running matrix divided by L_kk, and L_ik times it leaves the
+      // rows below
+#pragma unroll
+      for (int ai = 0; ai < NT; ++ai)
+#pragma unroll
+        for (int bj = 0; bj < NT; ++bj) {
+          const int i = ty + 16 * ai, j = tx + 16 * bj;
+          if (i > k && j > k) a[ai][bj] -= li[ai] * lj[bj];
+          if (j <= k) {
+            if (i > k) x[ai][bj] -= li[ai] * xk[bj];
+            else if (i == k) x[ai][bj] = xk[bj];
+          }
+        }
     }
   }
+#pragma unroll
+  for (int ai = 0; ai < NT; ++ai)
+#pragma unroll
+    for (int bj = 0; bj < NT; ++bj) {
+      const int r = ty + 16 * ai, c = tx + 16 * bj;
+      if (r < mp && c < mp) Lf[r * mp + c] = (r < mf && c < mf && r >= c) ? x[ai][bj] : 0.0;
+    }
   __syncthreads();
-  for (int r = ty; r < mp; r += 16)
-    for (int c = tx; c < mp; c += 16)
-      Lf[r * mp + c] = (r < mf && c < mf && r >= c) ? X[r * ld + c] : 0.0;
   if (threadIdx.x == 0 && bad) atomicOr(flags, FLAG_NOT_SPD);
   if (!M) return;
   const double *Mf = M + (long long)f * mp * mp;
   double *Hf = Hs + (long long)f * mp * mp, *Bf = Bm + (long long)f * mp * mp;
-  for (int i = ty; i < mf; i += 16)
-    for (int j = tx; j < mf; j += 16) A[i * ld + j] = Mf[i * mp + j];
-  __syncthreads();
-  // T = X M (X lower triangular)
-  for (int j = ty; j < mf; j += 16)
-    for (int l = tx; l < mf; l += 16) {
-      double acc = 0.0;
-      for (int i = 0; i <= j; ++i) acc += X[j * ld + i] * A[i * ld + l];
-      Cb[j * ld + l] = acc;
+  const int nt = (mf + 15) / 16, mt = 16 * nt;
+  const int ld = mt + 1;
+  // B0 = L^-1, B1 = M (zero past the fragment's size)
+#pragma unroll
+  for (int ai = 0; ai < NT; ++ai)
+#pragma unroll
+    for (int bj = 0; bj < NT; ++bj) {
+      const int i = ty + 16 * ai, j = tx + 16 * bj;
+      if (i < mt && j < mt) {
+        const bool in = i < mf && j < mf;
+        B0[i * ld + j] = in ? x[ai][bj] : 0.0;
+        B1[i * ld + j] = in ? Mf[i * mp + j] : 0.0;
+      }
     }
   __syncthreads();
-  // L^-1 M L^-T = T X^T
-  for (int j = ty; j < mf; j += 16)
-    for (int l = tx; l < mf; l += 16) {
-      double acc = 0.0;
-      for (int i = 0; i <= l; ++i) acc += Cb[j * ld + i] * X[l * ld + i];
-      A[j * ld + l] = acc;
+  // B2 = T = L^-1 M
+  lds_gemm_f64<false>(B0, B1, ld, nt, [&](int r, int c, double v) { B2[r * ld + c] = v; });
+  __syncthreads();
+  // B1 = T L^-T
+  lds_gemm_f64<true>(B2, B0, ld, nt, [&](int r, int c, double v) { B1[r * ld + c] = v; });
+  __syncthreads();
+  // B2 = Hs = sym(B1)
+#pragma unroll
+  for (int ai = 0; ai < NT; ++ai)
+#pragma unroll
+    for (int bj = 0; bj < NT; ++bj) {
+      const int i = ty + 16 * ai, j = tx + 16 * bj;
+      if (i < mp && j < mp) {
+        const bool in = i < mf && j < mf;
+        const double h = in ? 0.5 * (B1[i * ld + j] + B1[j * ld + i]) : 0.0;
+        if (i < mt && j < mt) B2[i * ld + j] = h;
+        Hf[i * mp + j] = h;
+        if (in && i == j) adiag[o.moff[f] + i] = h;
+        if (i >= mt || j >= mt) Bf[i * mp + j] = 0.0;
+      }
     }
   __syncthreads();
-  for (int j = ty; j < mf; j += 16)
-    for (int l = tx; l < mf; l += 16) Cb[j * ld + l] = 0.5 * (A[j * ld + l] + A[l * ld + j]);
-  __syncthreads();
-  for (int j = ty; j < mp; j += 16)
-    for (int l = tx; l < mp; l += 16) {
-      const bool in = j < mf && l < mf;
-      Hf[j * mp + l] = in ? Cb[j * ld + l] : 0.0;
-      if (in && j == l) adiag[o.moff[f] + j] = Cb[j * ld + j];
-      // B = Hs X: B[j][l] = sum_{k >= l} Hs[j][k] X[k][l]
-      double acc = 0.0;
-      if (in)
-        for (int k = l; k < mf; ++k) acc += Cb[j * ld + k] * X[k * ld + l];
-      Bf[j * mp + l] = acc;
-    }
+  // B = Hs L^-1
+  lds_gemm_f64<false>(B2, B0, ld, nt, [&](int r, int c, double v) {
+    if (r < mp && c < mp) Bf[r * mp + c] = (r < mf && c < mf) ? v : 0.0;
+  });
 }
 
 // Round-robin (circle) pairing: in round r of mm - 1, pair k.
