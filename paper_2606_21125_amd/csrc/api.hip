@@ -222,6 +222,9 @@ hipStream_t xstream(const dcdft_ctx *c) { return c->xs ? c->xs : c->stream; }
 double *gpart_at(const dcdft_ctx *c, int f0) {
   return c->d_gpart + (long long)f0 * c->gram_chunks * c->m_pad * c->m_pad;
 }
+double *gpart2_at(const dcdft_ctx *c, int f0) {
+  return c->d_gpart2 + (long long)f0 * c->gram_chunks * c->m_pad * c->m_pad;
+}
 
 template <typename T>
 void hloc(dcdft_ctx *c, int f0, int f1, const T *x, T *y, double *dot = nullptr) {
@@ -326,10 +329,12 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
     launch_kb_quad(o, f0, f1, kb, c->d_C, c->d_cc, s);
     // (h)-(i) exact minimiser of the 2x2 Rayleigh quotient
     launch_cg_theta(o, f0, f1, c->d_a, c->d_bb, c->d_cc, c->d_inv, c->d_cos, c->d_sin, s);
-    // (j) band rotations and (l) S = sym(<Psi, Psi>)
+    // (j) band rotations and (l) S = sym(<Psi, Psi>); fused: also M = <Psi', W'>
+    // of the rotated (not yet re-orthonormalised) arrays
     {
-      Timed t(c, DCDFT_KERNEL_GRAM_FUSED, 6.0 * sz * n * nb, 1.0 * n * m2);
-      launch_gram_update<T>(g, o, f0, f1, ch, psi, p, w, q, c->d_cos, c->d_sin, gpart_at(c, f0), s);
+      Timed t(c, DCDFT_KERNEL_GRAM_FUSED, 6.0 * sz * n * nb, (fuse ? 3.0 : 1.0) * n * m2);
+      launch_gram_update<T>(g, o, f0, f1, ch, psi, p, w, q, c->d_cos, c->d_sin, gpart_at(c, f0), s,
+                            fuse ? gpart2_at(c, f0) : nullptr);
     }
     launch_gram_reduce(g, o, f0, f1, ch, 1, gpart_at(c, f0), c->d_s, nullptr, nullptr, s);
     if (!fuse) {
@@ -339,8 +344,7 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
       launch_rot_cholesky<T>(g, o, f0, f1, c->d_lin, psi, w, s);
       continue;
     }
-    // M = <Psi', W'> of the rotated (not yet re-orthonormalised) arrays
-    gram<T>(c, f0, f1, psi, w, c->d_hs_full, nullptr, nullptr);
+    launch_gram_reduce(g, o, f0, f1, ch, 0, gpart2_at(c, f0), c->d_hs_full, nullptr, nullptr, s);
     // (l) S = L L^T; with Psi = L^-1 Psi', W = L^-1 W' the next sweep's
     // Hs = sym(<Psi, W>) = sym(L^-1 M L^-T) and a_i = Hs_ii, B = Hs L^-1
     launch_cholinv(o, f0, f1, c->d_s, c->d_lin, c->d_flags, s, c->d_hs_full, c->d_hs, c->d_a,
@@ -974,6 +978,7 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   ALLOC(c->d_rhof_in, (long long)c->nF * g.n);
   ALLOC(c->d_rhof_out, (long long)c->nF * g.n);
   ALLOC(c->d_gpart, (long long)c->nF * c->gram_chunks_max * mp2);
+  if (mixed) ALLOC(c->d_gpart2, (long long)c->nF * c->gram_chunks_max * mp2);
   ALLOC(c->d_gtmp, c->nF * mp2);
   {
     // rotation partials for the smallest tile count the autotuner may pick

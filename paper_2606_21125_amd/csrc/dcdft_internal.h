@@ -181,6 +181,7 @@ struct dcdft_ctx {
 
   // small matrices [F][m_pad][m_pad]
   double *d_gpart = nullptr;         // Gram partials [F][chunks][m_pad][m_pad]
+  double *d_gpart2 = nullptr;        // second product of a fused Gram (mixed path), same layout
   double *d_gtmp = nullptr;          // Gram result when only the symmetric part is kept
   double *d_dpart = nullptr;         // per-workgroup band partials [F][wpf][2][m_pad]
   double *d_hs_full = nullptr, *d_hs = nullptr, *d_x = nullptr, *d_s = nullptr, *d_lin = nullptr,
@@ -265,11 +266,12 @@ template <typename T>
 void launch_gram_direction(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
                            const T *psi, const T *gres, T *p, const double *beta, double *part,
                            hipStream_t s);
-// Psi <- cs Psi + sn P, W <- cs W + sn Q (in place), symmetric Gram partials of Psi
+// Psi <- cs Psi + sn P, W <- cs W + sn Q (in place), symmetric Gram partials of Psi;
+// with part_m also the partials of the full product <Psi, W> (same layout)
 template <typename T>
 void launch_gram_update(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, T *psi,
                         const T *p, T *w, const T *q, const double *cs, const double *sn,
-                        double *part, hipStream_t s);
+                        double *part, hipStream_t s, double *part_m = nullptr);
 // G = dV sum of chunk partials (sym: X == Y, lower tiles mirrored); Gs = sym(G) if
 // not null; diag -> per-band (may be null)
 void launch_gram_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int sym,

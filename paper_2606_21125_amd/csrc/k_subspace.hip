@@ -13,10 +13,13 @@ namespace {
 // Fused rotation: y = cz z + cm R^T x (and, with RF_TWO, y2 = cm R^T x2 with the
 // same R), with optional per-band reductions of the stored values v over the
 // workgroup's points: RF_DOT_SELF sums v^2, RF_DOT_W sums v * wdot, RF_CORE
-// restricts both to core points; RF_Z says z is given.  R = M^T (trans 0) or M
-// (trans 1) is staged in LDS once per workgroup, transposed so that the R values
-// one lane feeds to the matrix cores for an output tile are contiguous (the
-// lane group kk takes the input orbitals kk*4TM .. kk*4TM + 4TM - 1); each wave
+// restricts both to core points; RF_Z says z is given; RF_TRI says R^T is lower
+// triangular (y_j needs inputs i <= j only, so the products of input orbitals
+// past an output tile are skipped).  R = M^T (trans 0) or M (trans 1) is staged
+// in LDS once per workgroup, transposed and with the inputs of one matrix-core
+// step side by side (kpos), so that the R values one lane feeds to the matrix
+// cores for an output tile are contiguous; step s takes the input orbitals
+// 4s .. 4s + 3, one per lane group; each wave
 // handles NT tiles of 16 points and every output orbital, so y may alias x or
 // z.  Per tile a wave issues the
 // loads of the next tile's operand rows before its own matrix-core products
@@ -28,7 +31,13 @@ namespace {
 // per-wave LDS row by one lane, then the waves are added in order: one FP64
 // partial per workgroup, dpart[(f * wpf + wg) * 2 * m_pad + k * m_pad + j],
 // k = 0 (self), 1 (wdot).
-enum { RF_DOT_SELF = 1, RF_DOT_W = 2, RF_CORE = 4, RF_TWO = 8, RF_Z = 32 };
+enum { RF_DOT_SELF = 1, RF_DOT_W = 2, RF_CORE = 4, RF_TWO = 8, RF_Z = 32, RF_TRI = 64 };
+
+// LDS column of input orbital i in a staged rotation matrix: matrix-core step s
+// of lane group kk takes input i = 4 s + kk, and a lane's values for one output
+// tile sit contiguously at kk * NS + s.
+template <int NS>
+__device__ inline int kpos(int i) { return (i & 3) * NS + (i >> 2); }
 
 // n consecutive values from 16-byte aligned LDS
 template <typename T, int N>
@@ -83,12 +92,12 @@ k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mf = o.m[f], mp = o.m_pad;
   const double *Mf = M + (long long)f * mp * mp;
-  // R^T with output orbital j as the row: RtT[j][i] = R[i][j]
+  // R^T with output orbital j as the row: RtT[j][kpos(i)] = R[i][j]
   for (int e = threadIdx.x; e < MP * MP; e += blockDim.x) {
     const int i = e / MP, j = e % MP;
     double v = 0.0;
     if (i < mf && j < mf) v = trans ? Mf[j * mp + i] : Mf[i * mp + j];
-    RtT[j * S2 + i] = (T)v;
+    RtT[j * S2 + kpos<NS>(i)] = (T)v;
   }
   if (DOTS)
     for (int e = lane; e < 2 * MP; e += 64) red[wave][e / MP][e % MP] = 0.0;
@@ -103,19 +112,19 @@ k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int 
   auto tile_p0 = [&](int u) { return ((wg * NT + u) * 4 + wave) * 16; };
   // Addresses split into a wave-uniform row part and one lane offset (rows up
   // to the padded count exist: the arrays carry m_pad spare rows).
-  // Input orbital of MFMA step s in lane group kk: i = kk * NS + s, so a lane's
-  // R values for one output tile are contiguous in LDS (16-byte reads).
+  // Input orbital of MFMA step s in lane group kk: i = 4 s + kk (a lane's R
+  // values for one output tile are contiguous in LDS: 16-byte reads).
   // operand rows i of item it at the lane's point:
   auto load_rows = [&](int it, T *bx) {
     const int u = it / NARR, arr = it % NARR;
     const int pc = tile_p0(u) + jl;
     const bool pin = pc < g.n;
-    const int lo = kk * NS * g.n + (pin ? pc : g.n - 1);
+    const int lo = kk * g.n + (pin ? pc : g.n - 1);
     const T *xs = (arr ? x2 : x) + base;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      const T v = (xs + (long long)s * g.n)[lo];
-      bx[s] = (kk * NS + s < mf && pin) ? v : (T)0;
+      const T v = (xs + (long long)(4 * s) * g.n)[lo];
+      bx[s] = (4 * s + kk < mf && pin) ? v : (T)0;
     }
   };
   T bx[NS];
@@ -154,7 +163,8 @@ k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int 
       T a[NS];
       lds_read_vec<T, NS>(RtT + (jt * 16 + jl) * S2 + kk * NS, a);
 #pragma unroll
-      for (int s = 0; s < NS; ++s) acc[jt] = MM::mma(a[s], bx[s], acc[jt]);
+      for (int s = 0; s < NS; ++s)
+        if (!(FL & RF_TRI) || s < 4 * jt + 4) acc[jt] = MM::mma(a[s], bx[s], acc[jt]);
       // keep later operand reads from being hoisted (register pressure)
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -219,8 +229,8 @@ k_rot_cholres(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ Linv,
   for (int e = threadIdx.x; e < MP * MP; e += blockDim.x) {
     const int j = e / MP, i = e % MP;
     const bool in = i < mf && j < mf;
-    R1[j * S2 + i] = in ? (T)Lf[j * mp + i] : (T)0;
-    R2[j * S2 + i] = in ? (T)Bf[j * mp + i] : (T)0;
+    R1[j * S2 + kpos<NS>(i)] = in ? (T)Lf[j * mp + i] : (T)0;
+    R2[j * S2 + kpos<NS>(i)] = in ? (T)Bf[j * mp + i] : (T)0;
   }
   for (int e = lane; e < MP; e += 64) red[wave][e] = 0.0;
   __syncthreads();
@@ -230,11 +240,11 @@ k_rot_cholres(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ Linv,
   auto load_rows = [&](int u, const T *xs, T *bx) {
     const int pc = tile_p0(u) + jl;
     const bool pin = pc < g.n;
-    const int lo = kk * NS * g.n + (pin ? pc : g.n - 1);
+    const int lo = kk * g.n + (pin ? pc : g.n - 1);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      const T v = (xs + base + (long long)s * g.n)[lo];
-      bx[s] = (kk * NS + s < mf && pin) ? v : (T)0;
+      const T v = (xs + base + (long long)(4 * s) * g.n)[lo];
+      bx[s] = (4 * s + kk < mf && pin) ? v : (T)0;
     }
   };
   T bx[NS], bw[NS];
@@ -259,11 +269,13 @@ k_rot_cholres(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ Linv,
       ab[jt] = MM::zero();
       T a[NS];
       lds_read_vec<T, NS>(R1 + (jt * 16 + jl) * S2 + kk * NS, a);
+      // L^-1 is lower triangular: inputs past the output tile contribute nothing
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        ap[jt] = MM::mma(a[s], bx[s], ap[jt]);
-        aw[jt] = MM::mma(a[s], bw[s], aw[jt]);
-      }
+      for (int s = 0; s < NS; ++s)
+        if (s < 4 * jt + 4) {
+          ap[jt] = MM::mma(a[s], bx[s], ap[jt]);
+          aw[jt] = MM::mma(a[s], bw[s], aw[jt]);
+        }
       __builtin_amdgcn_sched_barrier(0);
       lds_read_vec<T, NS>(R2 + (jt * 16 + jl) * S2 + kk * NS, a);
 #pragma unroll
@@ -338,8 +350,9 @@ __global__ void __launch_bounds__(256) k_band_reduce(Geo g, OrbSet o, long long 
 //   GM_DIR:    Y = P = beta P_prev - G, written over P_prev.
 //   GM_UPDATE: X = Psi' = c Psi + s P and W' = c W + s Q, both written in place;
 //              symmetric product of Psi'.
+//   GM_UPDATE_M: as GM_UPDATE, and also the full product <Psi', W'> (into part2).
 // Partials are written in FP64 (one per workgroup).
-enum { GM_PLAIN = 0, GM_DIR = 1, GM_UPDATE = 2 };
+enum { GM_PLAIN = 0, GM_DIR = 1, GM_UPDATE = 2, GM_UPDATE_M = 3 };
 constexpr int kGramKT = 32;
 // LDS row stride: rows stay 16-byte aligned for vector reads, with a 16-byte skew
 template <typename T>
@@ -373,13 +386,15 @@ struct Vec4Load<float> {
 
 template <typename T, int TM, int MODE, bool SYM, bool VEC>
 __global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 || TM < 5 ? 4 : 2, 8)))
+__attribute__((amdgpu_waves_per_eu(MODE == GM_UPDATE_M ? 3 : (sizeof(T) == 4 || TM < 5 ? 4 : 2), 8)))
 k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a2, T *a3,
         const T *a4, const double *__restrict__ c1, const double *__restrict__ c2,
-        double *__restrict__ part) {
+        double *__restrict__ part, double *__restrict__ part2) {
   typedef Mfma<T> MM;
   constexpr int MP = 16 * TM;
-  constexpr int NTILE = SYM ? TM * (TM + 1) / 2 : TM * TM;
+  constexpr bool UPM = MODE == GM_UPDATE_M;   // second (full) product X^T Y into part2
+  constexpr int NTS = SYM ? TM * (TM + 1) / 2 : TM * TM;
+  constexpr int NTILE = NTS + (UPM ? TM * TM : 0);
   constexpr int PER_WAVE = (NTILE + 3) / 4;
   // operand items of one step: MP rows x KT/4 runs of 4 points, over 256 threads
   constexpr int NI = (MP * (kGramKT / 4) + 255) / 256;
@@ -387,7 +402,7 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a
   constexpr int NA = MODE == GM_PLAIN ? (SYM ? 1 : 2) : (MODE == GM_DIR ? 3 : 4);
   constexpr int LD = gram_ld<T>();
   __shared__ __attribute__((aligned(16))) T Xs[MP * LD];
-  __shared__ __attribute__((aligned(16))) T Ys[SYM ? 4 : MP * LD];
+  __shared__ __attribute__((aligned(16))) T Ys[SYM && !UPM ? 4 : MP * LD];
   const int f = f0 + blockIdx.x / chunks;
   const int c = blockIdx.x % chunks;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -397,13 +412,15 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a
   const int p_begin = c * kchunk;
   const int p_end = min(p_begin + kchunk, g.n);
   // tiles of this wave: the (wave + 4 k)-th output tile in row order (upper
-  // triangle only when SYM); fixed indexing keeps the table in registers
-  int tI[PER_WAVE], tJ[PER_WAVE];
+  // triangle only when SYM), then (UPM) the tiles of X^T Y; fixed indexing
+  // keeps the table in registers
+  int tI[PER_WAVE], tJ[PER_WAVE], tW[PER_WAVE];
 #pragma unroll
   for (int k = 0; k < PER_WAVE; ++k) {
     const int q = wave + 4 * k;
     tI[k] = -1;
     tJ[k] = -1;
+    tW[k] = 0;
     int idx = 0;
 #pragma unroll
     for (int ti = 0; ti < TM; ++ti)
@@ -416,6 +433,18 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a
         }
         ++idx;
       }
+    if (UPM)
+#pragma unroll
+      for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < TM; ++tj) {
+          if (idx == q) {
+            tI[k] = ti;
+            tJ[k] = tj;
+            tW[k] = 1;
+          }
+          ++idx;
+        }
   }
   // FP32 products: each step's 32-point sums leave the matrix cores in FP32 and
   // are added into FP64 accumulators (the chunk sum of up to thousands of
@@ -504,13 +533,13 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a
         const T *v0 = MODE == GM_DIR ? yv : xv;
         if (VEC && p + 3 < p_end) {
           Vec4Load<T>::store(d0 + ro + p, v0);
-          if (MODE == GM_UPDATE) Vec4Load<T>::store(a3 + ro + p, yv);
+          if (MODE >= GM_UPDATE) Vec4Load<T>::store(a3 + ro + p, yv);
         } else {
 #pragma unroll
           for (int t = 0; t < 4; ++t)
             if (p + t < p_end) {
               d0[ro + p + t] = v0[t];
-              if (MODE == GM_UPDATE) a3[ro + p + t] = yv[t];
+              if (MODE >= GM_UPDATE) a3[ro + p + t] = yv[t];
             }
         }
       }
@@ -518,7 +547,7 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a
       for (int t = 0; t < 4; ++t) {
         const bool ok = rin && p + t < p_end;
         Xs[row * LD + pq + t] = ok ? xv[t] : (T)0;
-        if (!SYM) Ys[row * LD + pq + t] = ok ? yv[t] : (T)0;
+        if (!SYM || UPM) Ys[row * LD + pq + t] = ok ? yv[t] : (T)0;
       }
     }
     __syncthreads();
@@ -534,7 +563,7 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a
       if (tI[k] < 0) continue;
       T av[KQ], bv[KQ];
       lds_read_vec<T, KQ>(Xs + (tI[k] * 16 + r) * LD + kk * KQ, av);
-      lds_read_vec<T, KQ>(Yl + (tJ[k] * 16 + r) * LD + kk * KQ, bv);
+      lds_read_vec<T, KQ>((UPM && tW[k] ? Ys : Yl) + (tJ[k] * 16 + r) * LD + kk * KQ, bv);
       if (ACC64) acc[k] = MM::zero();
 #pragma unroll
       for (int t = 0; t < KQ; ++t) acc[k] = MM::mma(av[t], bv[t], acc[k]);
@@ -545,10 +574,11 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a
       __builtin_amdgcn_sched_barrier(0);
     }
   }
-  double *out = part + ((long long)(f - f0) * chunks + c) * mp * mp;
+  const long long po = ((long long)(f - f0) * chunks + c) * mp * mp;
 #pragma unroll
   for (int k = 0; k < PER_WAVE; ++k) {
     if (tI[k] < 0) continue;
+    double *out = (UPM && tW[k] ? part2 : part) + po;
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
       const int row = tI[k] * 16 + MM::row(lane >> 4, rr);
@@ -1002,29 +1032,29 @@ __global__ void k_copy(long long b0, long long nb, const double *__restrict__ sr
 template <typename T, int TM, int MODE, bool SYM>
 void gram3_t(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int kchunk, T *x, T *a1,
              const T *a2, T *a3, const T *a4, const double *c1, const double *c2, double *part,
-             hipStream_t s) {
+             double *part2, hipStream_t s) {
   const dim3 grid((f1 - f0) * chunks), block(256);
   if ((g.n % 4) == 0)
     hipLaunchKernelGGL((k_gram3<T, TM, MODE, SYM, true>), grid, block, 0, s, g, o, f0, chunks,
-                       kchunk, x, a1, a2, a3, a4, c1, c2, part);
+                       kchunk, x, a1, a2, a3, a4, c1, c2, part, part2);
   else
     hipLaunchKernelGGL((k_gram3<T, TM, MODE, SYM, false>), grid, block, 0, s, g, o, f0, chunks,
-                       kchunk, x, a1, a2, a3, a4, c1, c2, part);
+                       kchunk, x, a1, a2, a3, a4, c1, c2, part, part2);
 }
 
 template <typename T, int MODE, bool SYM>
 void gram3_tm(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, T *x, T *a1,
               const T *a2, T *a3, const T *a4, const double *c1, const double *c2, double *part,
-              hipStream_t s) {
+              hipStream_t s, double *part2 = nullptr) {
   if (f1 <= f0) return;
   int kc = (g.n + chunks - 1) / chunks;
   kc = ((kc + kGramKT - 1) / kGramKT) * kGramKT;
   switch (o.tiles) {
-    case 1: gram3_t<T, 1, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
-    case 2: gram3_t<T, 2, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
-    case 3: gram3_t<T, 3, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
-    case 4: gram3_t<T, 4, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
-    default: gram3_t<T, 5, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, s); break;
+    case 1: gram3_t<T, 1, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, s); break;
+    case 2: gram3_t<T, 2, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, s); break;
+    case 3: gram3_t<T, 3, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, s); break;
+    case 4: gram3_t<T, 4, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, s); break;
+    default: gram3_t<T, 5, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, s); break;
   }
 }
 
@@ -1093,9 +1123,13 @@ void launch_gram_direction(const Geo &g, const OrbSet &o, int f0, int f1, int ch
 template <typename T>
 void launch_gram_update(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, T *psi,
                         const T *p, T *w, const T *q, const double *cs, const double *sn,
-                        double *part, hipStream_t s) {
-  gram3_tm<T, GM_UPDATE, true>(g, o, f0, f1, chunks, psi, const_cast<T *>(p), nullptr, w, q, cs,
-                               sn, part, s);
+                        double *part, hipStream_t s, double *part_m) {
+  if (part_m)
+    gram3_tm<T, GM_UPDATE_M, true>(g, o, f0, f1, chunks, psi, const_cast<T *>(p), nullptr, w, q,
+                                   cs, sn, part, s, part_m);
+  else
+    gram3_tm<T, GM_UPDATE, true>(g, o, f0, f1, chunks, psi, const_cast<T *>(p), nullptr, w, q,
+                                 cs, sn, part, s);
 }
 
 template <typename T>
@@ -1124,10 +1158,10 @@ void launch_rot_cholesky(const Geo &g, const OrbSet &o, int f0, int f1, const do
                          T *psi, T *w, hipStream_t s) {
   const int wpf = rot_wpf(g);
   if (w)
-    rot_fused_tm<T, RF_TWO>(g, o, f0, f1, wpf, Linv, 1, psi, nullptr, 0.0, 1.0, psi, w,
+    rot_fused_tm<T, RF_TWO | RF_TRI>(g, o, f0, f1, wpf, Linv, 1, psi, nullptr, 0.0, 1.0, psi, w,
                                      w, nullptr, nullptr, s);
   else
-    rot_fused_tm<T, 0>(g, o, f0, f1, wpf, Linv, 1, psi, nullptr, 0.0, 1.0, psi, nullptr,
+    rot_fused_tm<T, RF_TRI>(g, o, f0, f1, wpf, Linv, 1, psi, nullptr, 0.0, 1.0, psi, nullptr,
                             nullptr, nullptr, nullptr, s);
 }
 
@@ -1177,7 +1211,7 @@ void launch_rot_ritz(const Geo &g, const OrbSet &o, int f0, int f1, const double
                                          const T *, T *, const double *, double *, hipStream_t); \
   template void launch_gram_update<T>(const Geo &, const OrbSet &, int, int, int, T *, const T *, \
                                       T *, const T *, const double *, const double *, double *,  \
-                                      hipStream_t);                                           \
+                                      hipStream_t, double *);                                 \
   template void launch_rot_residual<T>(const Geo &, const OrbSet &, int, int, const double *,    \
                                        const T *, const T *, T *, double *, double *,            \
                                        hipStream_t);                                          \
