@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <new>
 
 #include "dcdft_internal.h"
@@ -121,18 +122,13 @@ dcdft::KBTables dcdft_ctx::kb() const {
   k.A = d_A;
   k.pair_frag = d_pair_frag;
   k.pair_atom = d_pair_atom;
-  k.pair_ptr = d_pair_ptr;
-  k.atom_l = d_atom_l;
-  k.atom_beta = d_atom_beta;
-  k.pt_ptr = d_pt_ptr;
-  k.pt_a = d_pt_a;
-  k.pt_beta = d_pt_beta;
+  k.pair_first = d_pair_first;
+  k.pr_sq = d_pr_sq;
+  k.pr_par = d_pr_par;
   k.E = d_E;
   k.NR = NR;
   k.KS = KS;
   k.reg_atom = d_reg_atom;
-  k.reg_beta = d_reg_beta;
-  k.reg_beta32 = d_reg_beta32;
   k.ar_ptr = d_ar_ptr;
   k.ar_reg = d_ar_reg;
   k.ar_slot = d_ar_slot;
@@ -496,40 +492,50 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
         }
     }
   };
+  // per atom and axis: the support's wrapped indices and squared minimum-image
+  // offsets; r2 = (dz^2 + dy^2) + dx^2 from these squares, in this order, is
+  // also what the projector kernels evaluate, so support and values agree
+  std::vector<std::vector<int>> a_idx(3 * (size_t)p->n_atoms);
+  std::vector<std::vector<double>> a_sq(3 * (size_t)p->n_atoms);
+  std::vector<double> a_par(3 * (size_t)p->n_atoms);  // sc, 1 / (2 sigma^2), rcut^2
   for (int a = 0; a < p->n_atoms; ++a) {
     const dcdft_species &sp = p->species[p->atom_species[a]];
     Eatom[a] = sp.kb_energy;
     const double R = sp.kb_rcut;
     const double *pos = p->atom_pos + 3 * a;
-    axis_ball(pos[0], R, g.h[0], g.N[0], p->cell[0], ix, dx);
-    axis_ball(pos[1], R, g.h[1], g.N[1], p->cell[1], iy, dy);
-    axis_ball(pos[2], R, g.h[2], g.N[2], p->cell[2], iz, dz);
-    mark_near(a, 0, ix);
-    mark_near(a, 1, iy);
-    mark_near(a, 2, iz);
+    for (int d = 0; d < 3; ++d) {
+      std::vector<double> disp;
+      axis_ball(pos[d], R, g.h[d], g.N[d], p->cell[d], a_idx[3 * a + d], disp);
+      for (double v : disp) a_sq[3 * a + d].push_back(v * v);
+      mark_near(a, d, a_idx[3 * a + d]);
+    }
+    const std::vector<int> &jx = a_idx[3 * a], &jy = a_idx[3 * a + 1], &jz = a_idx[3 * a + 2];
+    const std::vector<double> &qx = a_sq[3 * a], &qy = a_sq[3 * a + 1], &qz = a_sq[3 * a + 2];
     const double inv2s2 = 1.0 / (2.0 * sp.kb_sigma * sp.kb_sigma);
     double nrm = 0.0;
-    for (size_t k = 0; k < iz.size(); ++k)
-      for (size_t j = 0; j < iy.size(); ++j)
-        for (size_t i = 0; i < ix.size(); ++i) {
-          const double r2 = dx[i] * dx[i] + dy[j] * dy[j] + dz[k] * dz[k];
+    for (size_t k = 0; k < jz.size(); ++k)
+      for (size_t j = 0; j < jy.size(); ++j)
+        for (size_t i = 0; i < jx.size(); ++i) {
+          const double r2 = (qz[k] + qy[j]) + qx[i];
           if (r2 > R * R) continue;
           const double b = std::exp(-r2 * inv2s2);
-          sup[a].g.push_back(ix[i] + (long long)g.N[0] * (iy[j] + (long long)g.N[1] * iz[k]));
-          sup[a].v.push_back(b);
+          sup[a].g.push_back(jx[i] + (long long)g.N[0] * (jy[j] + (long long)g.N[1] * jz[k]));
           nrm += b * b;
         }
-    if (nrm > 0.0) {
-      const double sc = 1.0 / std::sqrt(g.dv * nrm);
-      for (double &v : sup[a].v) v *= sc;
-    }
+    a_par[3 * a] = nrm > 0.0 ? 1.0 / std::sqrt(g.dv * nrm) : 0.0;
+    a_par[3 * a + 1] = inv2s2;
+    a_par[3 * a + 2] = R * R;
   }
   // ---- restriction to each fragment box ----
+  // per (fragment, atom) pair: the squared offsets along each axis at the box's
+  // local coordinates (infinite where the atom's support misses that index) and
+  // the atom's (sc, 1 / (2 sigma^2), rcut^2), from which the kernels evaluate
+  // beta(l) = sc exp(-r2 / (2 sigma^2)) on r2 <= rcut^2
+  const int nls = g.nl[0] + g.nl[1] + g.nl[2];
+  std::vector<double> pr_sq, pr_par;
   std::vector<int> pair_frag, pair_atom, atom_l, Acount(nF, 0);
   std::vector<long long> pair_ptr(1, 0);
-  std::vector<double> atom_beta;
   std::vector<std::vector<double>> Ef(nF);
-  std::vector<long long> pt_count((size_t)nF * g.n + 1, 0);
   c->pair_first.assign(nF + 1, 0);
   for (int f = 0; f < nF; ++f) {
     c->pair_first[f] = (int)pair_frag.size();
@@ -551,16 +557,23 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
         const int lz = ((gz - org[2]) % g.N[2] + g.N[2]) % g.N[2];
         if (lx >= g.nl[0] || ly >= g.nl[1] || lz >= g.nl[2]) continue;
         atom_l.push_back(lx + g.nl[0] * (ly + g.nl[1] * lz));
-        atom_beta.push_back(sup[a].v[e]);
       }
       if ((long long)atom_l.size() > e0) {
         pair_frag.push_back(f);
         pair_atom.push_back(Acount[f]);
         pair_ptr.push_back((long long)atom_l.size());
         Ef[f].push_back(Eatom[a]);
-        for (long long e = e0; e < (long long)atom_l.size(); ++e)
-          pt_count[(size_t)f * g.n + atom_l[e] + 1]++;
         Acount[f]++;
+        const size_t q0 = pr_sq.size();
+        pr_sq.resize(q0 + nls, std::numeric_limits<double>::infinity());
+        for (int d = 0, off = 0; d < 3; off += g.nl[d], ++d) {
+          const std::vector<int> &jd = a_idx[3 * a + d];
+          for (size_t i = 0; i < jd.size(); ++i) {
+            const int l = ((jd[i] - org[d]) % g.N[d] + g.N[d]) % g.N[d];
+            if (l < g.nl[d]) pr_sq[q0 + off + l] = a_sq[3 * a + d][i];
+          }
+        }
+        for (int k = 0; k < 3; ++k) pr_par.push_back(a_par[3 * a + k]);
       }
     }
   }
@@ -569,20 +582,8 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
   c->A = Acount;
   c->A_max = 1;
   for (int f = 0; f < nF; ++f) c->A_max = std::max(c->A_max, Acount[f]);
-  // point-major entries (counting sort by local point)
-  for (size_t q = 1; q < pt_count.size(); ++q) pt_count[q] += pt_count[q - 1];
-  std::vector<long long> fill(pt_count.begin(), pt_count.end() - 1);
-  std::vector<int> pt_a(atom_l.size());
-  std::vector<double> pt_beta(atom_l.size());
-  for (int P = 0; P < c->n_pairs; ++P) {
-    const int f = pair_frag[P];
-    for (long long e = pair_ptr[P]; e < pair_ptr[P + 1]; ++e) {
-      const long long slot = fill[(size_t)f * g.n + atom_l[e]]++;
-      pt_a[slot] = pair_atom[P];
-      pt_beta[slot] = atom_beta[e];
-    }
-  }
-  // region-dense tables
+  // regions: kRegion consecutive local points; each lists the fragment atoms
+  // whose support meets it (sorted, padded to KS slots)
   c->NR = (g.n + kRegion - 1) / kRegion;
   {
     std::vector<std::vector<int>> reg_atoms((size_t)nF * c->NR);
@@ -607,8 +608,16 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
                      fmt("%d projectors meet one %d-point region; at most %d are supported", ks,
                          kRegion, 16 * kMaxSlotTiles));
     c->KS = ks;
+    {
+      const size_t elem = c->precision == DCDFT_PREC_MIXED ? sizeof(float) : sizeof(double);
+      const size_t need = std::max(kb_lds_bytes(g, ks, c->tiles, elem, true),
+                                   kb_lds_bytes(g, ks, c->tiles, elem, false));
+      if (need > 65536)
+        return set_err(c, DCDFT_ERR_ARG,
+                       fmt("%d projectors meet one %d-point region: the projector kernels would "
+                           "need %zu bytes of LDS (at most 65536)", ks, kRegion, need));
+    }
     std::vector<int> reg_atom((size_t)nF * c->NR * ks, -1);
-    std::vector<double> reg_beta((size_t)nF * c->NR * ks * kRegion, 0.0);
     // slot of (fragment, region, atom)
     std::vector<std::vector<std::pair<int, int>>> ar((size_t)nF * c->A_max);
     for (int f = 0; f < nF; ++f)
@@ -620,16 +629,6 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
           ar[(size_t)f * c->A_max + v[k]].push_back({r, (int)k});
         }
       }
-    for (int P = 0; P < c->n_pairs; ++P) {
-      const int f = pair_frag[P], a = pair_atom[P];
-      for (long long e = pair_ptr[P]; e < pair_ptr[P + 1]; ++e) {
-        const int l = atom_l[e], r = l / kRegion;
-        int slot = -1;
-        for (auto &rs : ar[(size_t)f * c->A_max + a])
-          if (rs.first == r) slot = rs.second;
-        reg_beta[(((size_t)f * c->NR + r) * ks + slot) * kRegion + (l % kRegion)] = atom_beta[e];
-      }
-    }
     std::vector<long long> ar_ptr((size_t)nF * c->A_max + 1, 0);
     std::vector<int> ar_reg, ar_slot;
     for (size_t q = 0; q < ar.size(); ++q) {
@@ -640,11 +639,6 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
       ar_ptr[q + 1] = (long long)ar_reg.size();
     }
     HIPTRY(c, upload(c, &c->d_reg_atom, reg_atom));
-    HIPTRY(c, upload(c, &c->d_reg_beta, reg_beta));
-    {
-      std::vector<float> rb32(reg_beta.begin(), reg_beta.end());
-      HIPTRY(c, upload(c, &c->d_reg_beta32, rb32));
-    }
     HIPTRY(c, upload(c, &c->d_ar_ptr, ar_ptr));
     HIPTRY(c, upload(c, &c->d_ar_reg, ar_reg));
     HIPTRY(c, upload(c, &c->d_ar_slot, ar_slot));
@@ -655,12 +649,9 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
 
   HIPTRY(c, upload(c, &c->d_pair_frag, pair_frag));
   HIPTRY(c, upload(c, &c->d_pair_atom, pair_atom));
-  HIPTRY(c, upload(c, &c->d_pair_ptr, pair_ptr));
-  HIPTRY(c, upload(c, &c->d_atom_l, atom_l));
-  HIPTRY(c, upload(c, &c->d_atom_beta, atom_beta));
-  HIPTRY(c, upload(c, &c->d_pt_ptr, pt_count));
-  HIPTRY(c, upload(c, &c->d_pt_a, pt_a));
-  HIPTRY(c, upload(c, &c->d_pt_beta, pt_beta));
+  HIPTRY(c, upload(c, &c->d_pair_first, c->pair_first));
+  HIPTRY(c, upload(c, &c->d_pr_sq, pr_sq));
+  HIPTRY(c, upload(c, &c->d_pr_par, pr_par));
   HIPTRY(c, upload(c, &c->d_E, Eflat));
   HIPTRY(c, upload(c, &c->d_A, Acount));
   HIPTRY(c, upload(c, &c->d_vloc, vloc));

@@ -61,6 +61,9 @@ enum {
   HLOC_NVARIANT = DCDFT_HLOC_COUNT
 };
 bool hloc_halo_ok(const Geo &g);
+// LDS bytes a projector kernel needs (slot tables plus the (E C)^T block of apply
+// or the partial sums of project) for KS slots and tiles 16-orbital tiles
+size_t kb_lds_bytes(const Geo &g, int KS, int tiles, size_t elem, bool apply);
 
 struct OrbSet {           // flattened orbital layout [M_tot][n]
   int nfrag;
@@ -80,19 +83,21 @@ struct OrbSet {           // flattened orbital layout [M_tot][n]
   long long nb(int f0, int f1) const { return h_moff[f1] - h_moff[f0]; }
 };
 
-// Region-dense projector tables: each fragment's points are cut into regions of
-// kRegion consecutive points; a region lists the KS_max (padded) fragment atoms
-// whose support meets it and stores their beta values densely [slot][point].
+// Projector regions: each fragment's points are cut into regions of kRegion
+// consecutive points; a region lists the KS (padded) fragment atoms whose
+// support meets it.  The beta values are not stored: the kernels evaluate
+// beta_a(l) = sc_a exp(-r2 / (2 sigma_a^2)) on r2 <= rcut_a^2, with
+// r2 = (dz^2 + dy^2) + dx^2 taken from per-pair tables of squared offsets.
 constexpr int kRegion = 256;
 constexpr int kMaxSlotTiles = 6;    // KS_max <= 96 slots per region
+// local rows (runs of nl[0] points) a region can touch
+__host__ __device__ constexpr int region_rows(int nx) { return (kRegion - 1) / nx + 2; }
 
 struct KBTables {
   int A_max;
   int NR;                            // regions per fragment
   int KS;                            // slots per region (multiple of 16)
   const int *reg_atom;               // [F][NR][KS] local atom index or -1
-  const double *reg_beta;            // [F][NR][KS][kRegion]
-  const float *reg_beta32;           // the same values in FP32 (mixed path)
   const long long *ar_ptr;           // [F * A_max + 1] into (region, slot) lists
   const int *ar_reg;                 // region of each entry
   const int *ar_slot;                // slot of each entry
@@ -100,12 +105,9 @@ struct KBTables {
   const int *A;                      // [F] atoms per fragment
   const int *pair_frag;              // [n_pairs]
   const int *pair_atom;              // [n_pairs] local atom index
-  const long long *pair_ptr;         // [n_pairs + 1] into atom entries
-  const int *atom_l;                 // local point of each atom entry
-  const double *atom_beta;
-  const long long *pt_ptr;           // [F * n + 1] into point entries
-  const int *pt_a;                   // local atom index of each point entry
-  const double *pt_beta;
+  const int *pair_first;             // [F + 1] pair of local atom a of f: pair_first[f] + a
+  const double *pr_sq;               // [n_pairs][nl0 + nl1 + nl2] squared axis offsets (inf: outside)
+  const double *pr_par;              // [n_pairs][3] sc, 1 / (2 sigma^2), rcut^2
   const double *E;                   // [F][A_max]
 };
 
@@ -153,15 +155,11 @@ struct dcdft_ctx {
   int *d_band_frag = nullptr;
   // KB
   int n_pairs = 0;
-  int *d_A = nullptr, *d_pair_frag = nullptr, *d_pair_atom = nullptr;
-  long long *d_pair_ptr = nullptr, *d_pt_ptr = nullptr;
-  int *d_atom_l = nullptr, *d_pt_a = nullptr;
-  double *d_atom_beta = nullptr, *d_pt_beta = nullptr, *d_E = nullptr;
+  int *d_A = nullptr, *d_pair_frag = nullptr, *d_pair_atom = nullptr, *d_pair_first = nullptr;
+  double *d_pr_sq = nullptr, *d_pr_par = nullptr, *d_E = nullptr;
   double *d_C = nullptr;             // [F][A_max][m_pad] projections
   int NR = 0, KS = 0;
   int *d_reg_atom = nullptr, *d_ar_reg = nullptr, *d_ar_slot = nullptr;
-  double *d_reg_beta = nullptr;
-  float *d_reg_beta32 = nullptr;
   long long *d_ar_ptr = nullptr;
   double *d_cpart = nullptr;         // region projection partials [F][NR][KS][m_pad]
 

@@ -371,6 +371,20 @@ __global__ void __launch_bounds__(256) k_dot_segments(Geo g, long long b0, long 
 }
 
 // Four consecutive values from global memory at a 16-byte aligned address.
+// Four consecutive values from 16-byte aligned LDS.
+template <typename T>
+__device__ inline void lds_read4(const T *p, T *d) {
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  if (sizeof(T) == 4) {
+    const v4 v = *reinterpret_cast<const v4 *>(p);
+    d[0] = v[0]; d[1] = v[1]; d[2] = v[2]; d[3] = v[3];
+  } else {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 a = reinterpret_cast<const v2 *>(p)[0], b = reinterpret_cast<const v2 *>(p)[1];
+    d[0] = a[0]; d[1] = a[1]; d[2] = b[0]; d[3] = b[1];
+  }
+}
+
 template <typename T>
 __device__ inline void load4_aligned(const T *p, T *d);
 template <>
@@ -385,94 +399,177 @@ __device__ inline void load4_aligned<double>(const double *p, double *d) {
   d[0] = a.x; d[1] = a.y; d[2] = b.x; d[3] = b.y;
 }
 
-template <typename T>
-__device__ inline const T *region_beta(const KBTables &kb);
-template <>
-__device__ inline const double *region_beta<double>(const KBTables &kb) {
-  return kb.reg_beta;
-}
-template <>
-__device__ inline const float *region_beta<float>(const KBTables &kb) {
-  return kb.reg_beta32;
+// Slot tables of one projector region in LDS: sx[KS][nx] (squared x offsets of
+// the slot's atom), syz[KS][RR] (dz^2 + dy^2 of the region's rows, row0 + rr),
+// sc, c2, r2c [KS] (normalisation, 1 / (2 sigma^2), rcut^2).  An empty slot
+// gets rcut^2 = -1, so every point lies outside its support.
+__device__ inline void stage_region(const Geo &g, const KBTables &kb, int f, int reg, double *sx,
+                                    double *syz, double *par) {
+  const int nx = g.nl[0], ny = g.nl[1], nls = g.nl[0] + g.nl[1] + g.nl[2];
+  const int RR = region_rows(nx), row0 = reg * kRegion / nx;
+  const int *ra = kb.reg_atom + ((long long)f * kb.NR + reg) * kb.KS;
+  const int pf = kb.pair_first[f];
+  for (int e = threadIdx.x; e < kb.KS * nx; e += blockDim.x) {
+    const int a = ra[e / nx];
+    sx[e] = a >= 0 ? kb.pr_sq[(long long)(pf + a) * nls + e % nx] : 0.0;
+  }
+  for (int e = threadIdx.x; e < kb.KS * RR; e += blockDim.x) {
+    const int a = ra[e / RR];
+    // rows past the box (last region) only meet masked points
+    const int row = row0 + e % RR;
+    const int ly = row % ny, lz = min(row / ny, g.nl[2] - 1);
+    double v = 0.0;
+    if (a >= 0) {
+      const double *q = kb.pr_sq + (long long)(pf + a) * nls;
+      v = q[nx + ny + lz] + q[nx + ly];
+    }
+    syz[e] = v;
+  }
+  for (int e = threadIdx.x; e < kb.KS; e += blockDim.x) {
+    const int a = ra[e];
+    double v0 = 0.0, v1 = 0.0, v2 = -1.0;
+    if (a >= 0) {
+      const double *q = kb.pr_par + (long long)(pf + a) * 3;
+      v0 = q[0];
+      v1 = q[1];
+      v2 = q[2];
+    }
+    par[e] = v0;
+    par[kb.KS + e] = v1;
+    par[2 * kb.KS + e] = v2;
+  }
 }
 
+// beta of slot s at the point (lx, row0 + rr): sc exp(-r2 c2) on r2 <= rcut^2,
+// r2 = (dz^2 + dy^2) + dx^2 in FP64 (the support test is exact); FP32 arrays
+// take the exponential in FP32.
+template <typename T>
+__device__ inline T beta_at(const double *sx, const double *syz, const double *par, int KS, int nx,
+                            int RR, int s, int lx, int rr) {
+  const double r2 = syz[s * RR + rr] + sx[s * nx + lx];
+  const double sc = par[s], c2 = par[KS + s], rc2 = par[2 * KS + s];
+  T v;
+  if (sizeof(T) == 8)
+    v = (T)(sc * exp(-r2 * c2));
+  else
+    v = (T)((float)sc * expf((float)(-r2 * c2)));
+  return r2 > rc2 ? (T)0 : v;
+}
+
+// Points per projector chunk: the region's beta block is evaluated CH points at
+// a time into LDS (double-buffered) and shared by the four waves.
+template <typename T>
+constexpr int kb_chunk() { return sizeof(T) == 4 ? 64 : 32; }
+
 // Region partials of the projections: part[(f, region)][slot][i] =
-// sum_{l in region} beta_slot(l) X_i(l), as MFMA products of the dense region
-// block (slots x points) with the region's orbital columns.  Wave w takes the
-// orbital tiles w, w + 4; the K index walks points as u*16 + 4 (lane/16) + t so
-// that every lane reads runs of 4 contiguous values of both operands (16-byte
-// loads when VEC: n % 4 == 0).  The operands of the next 16-point step are
-// loaded before the products of the current one; every load is unconditional
-// (rows and points clamped into the arrays, values masked).
+// sum_{l in region} beta_slot(l) X_i(l), as MFMA products of the region's beta
+// block (slots x points) with its orbital columns.  The beta block is evaluated
+// chunk by chunk into LDS by all threads (one point and KS / (256 / CH) slots
+// each), the next chunk while the products of the current one run; wave w
+// takes the orbital tiles w, w + 4 over every point.  The K index walks the
+// points of a 16-point step as 4 (lane/16) + t, so every lane reads runs of 4
+// contiguous values of both operands (16-byte loads when VEC: n % 4 == 0); the
+// orbital values of the next chunk are loaded before the products of the
+// current one (unconditional loads, rows and points clamped, values masked).
 template <typename T, int TM, int KT, bool VEC>
-__global__ void __launch_bounds__(256) k_kb_project2(Geo g, OrbSet o, KBTables kb, int f0,
-                                                     const T *__restrict__ x,
-                                                     double *__restrict__ part) {
+__global__ void __launch_bounds__(256) k_kb_project(Geo g, OrbSet o, KBTables kb, int f0,
+                                                    const T *__restrict__ x,
+                                                    double *__restrict__ part) {
   typedef Mfma<T> MM;
   constexpr int MP = 16 * TM;
+  constexpr int KSM = 16 * KT;
+  constexpr int CH = kb_chunk<T>();
+  constexpr int NCH = kRegion / CH;
+  constexpr int NS = CH / 16;                  // 16-point steps per chunk
+  constexpr int BS = CH + 16 / (int)sizeof(T); // beta row stride (16-byte rows, skewed)
+  constexpr int SG = 256 / CH;                 // slot groups of the evaluation
+  constexpr int JW = (TM + 3) / 4;             // orbital tiles per wave
+  extern __shared__ __attribute__((aligned(16))) double kb_lds[];
+  const int nx = g.nl[0], RR = region_rows(nx);
+  double *sx = kb_lds, *syz = sx + kb.KS * nx, *par = syz + kb.KS * RR;
+  T *bl = reinterpret_cast<T *>(par + 3 * kb.KS);   // [2][KSM][BS]
   const int f = f0 + blockIdx.x / kb.NR;
   const int reg = blockIdx.x % kb.NR;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, kk = lane >> 4;
   const int mf = o.m[f];
   const int rmax = o.row_pad ? MP - 1 : mf - 1;
-  const int pbase = reg * kRegion;
+  const int pbase = reg * kRegion, row0 = pbase / nx;
   const long long base = o.moff[f] * (long long)g.n;
-  const T *blk = region_beta<T>(kb) + ((long long)f * kb.NR + reg) * kb.KS * kRegion;
-  const int r = lane & 15, kk = lane >> 4;
-  constexpr int JW = (TM + 3) / 4;   // orbital tiles per wave
-  typename MM::acc_t acc[KT][JW];
-#pragma unroll
-  for (int a = 0; a < KT; ++a)
-#pragma unroll
-    for (int b = 0; b < JW; ++b) acc[a][b] = MM::zero();
-  auto load_step = [&](int u, T (*bx)[4], T (*av)[4]) {
-    const int pu = pbase + u * 16 + 4 * kk;
+  auto load_x = [&](int ch, T (*bx)[NS][4]) {
 #pragma unroll
     for (int q = 0; q < JW; ++q) {
       const int jt = wave + 4 * q;
       const int orb = jt * 16 + r;
       const bool ok = jt < TM && orb < mf;
       const T *row = x + base + (long long)(orb < rmax ? orb : rmax) * g.n;
-      if (VEC) {
-        // n % 4 == 0 and pu % 4 == 0: the run lies wholly inside or outside
-        const int pc = pu < g.n ? pu : g.n - 4;
-        T v[4];
-        load4_aligned(row + pc, v);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) bx[q][t] = (ok && pu < g.n) ? v[t] : (T)0;
-      } else {
+      for (int u = 0; u < NS; ++u) {
+        const int pu = pbase + ch * CH + u * 16 + 4 * kk;
+        if (VEC) {
+          // n % 4 == 0 and pu % 4 == 0: the run lies wholly inside or outside
+          const int pc = pu < g.n ? pu : g.n - 4;
+          T v[4];
+          load4_aligned(row + pc, v);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int pt = pu + t;
-          const T v = row[pt < g.n ? pt : g.n - 1];
-          bx[q][t] = (ok && pt < g.n) ? v : (T)0;
+          for (int t = 0; t < 4; ++t) bx[q][u][t] = (ok && pu < g.n) ? v[t] : (T)0;
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int pt = pu + t;
+            const T v = row[pt < g.n ? pt : g.n - 1];
+            bx[q][u][t] = (ok && pt < g.n) ? v : (T)0;
+          }
         }
       }
     }
-#pragma unroll
-    for (int st = 0; st < KT; ++st) load4_aligned(blk + (st * 16 + r) * kRegion + pu - pbase, av[st]);
   };
-  T bx[JW][4], av[KT][4];
-  load_step(0, bx, av);
-  for (int u = 0; u < kRegion / 16; ++u) {
-    T bn[JW][4], an[KT][4];
-    load_step(u + 1 < kRegion / 16 ? u + 1 : u, bn, an);
+  auto beta_chunk = [&](int ch, T *dst) {
+    const int q = threadIdx.x % CH, sg = threadIdx.x / CH;
+    const int l = pbase + ch * CH + q;
+    const int lc = l < g.n ? l : g.n - 1;
+    const int lx = lc % nx, rr = lc / nx - row0;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int j = 0; j < KSM / SG; ++j) {
+      const int sl = sg + SG * j;
+      const T v = beta_at<T>(sx, syz, par, kb.KS, nx, RR, sl, lx, rr);
+      dst[sl * BS + q] = l < g.n ? v : (T)0;
+    }
+  };
+  T bx[JW][NS][4];
+  load_x(0, bx);
+  stage_region(g, kb, f, reg, sx, syz, par);
+  __syncthreads();
+  beta_chunk(0, bl);
+  __syncthreads();
+  typename MM::acc_t acc[KT][JW];
+#pragma unroll
+  for (int st = 0; st < KT; ++st)
+#pragma unroll
+    for (int q = 0; q < JW; ++q) acc[st][q] = MM::zero();
+  for (int ch = 0; ch < NCH; ++ch) {
+    const T *cur = bl + (ch & 1) * KSM * BS;
+    T bn[JW][NS][4];
+    load_x(ch + 1 < NCH ? ch + 1 : ch, bn);
+#pragma unroll
+    for (int u = 0; u < NS; ++u)
 #pragma unroll
       for (int st = 0; st < KT; ++st) {
+        T av[4];
+        lds_read4(cur + (st * 16 + r) * BS + u * 16 + 4 * kk, av);
 #pragma unroll
-        for (int q = 0; q < JW; ++q) acc[st][q] = MM::mma(av[st][t], bx[q][t], acc[st][q]);
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int q = 0; q < JW; ++q) acc[st][q] = MM::mma(av[t], bx[q][u][t], acc[st][q]);
       }
-    }
+    if (ch + 1 < NCH) beta_chunk(ch + 1, bl + ((ch + 1) & 1) * KSM * BS);
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < JW; ++q)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) bx[q][t] = bn[q][t];
+      for (int u = 0; u < NS; ++u)
 #pragma unroll
-    for (int st = 0; st < KT; ++st)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) av[st][t] = an[st][t];
+        for (int t = 0; t < 4; ++t) bx[q][u][t] = bn[q][u][t];
   }
   double *out = part + ((long long)f * kb.NR + reg) * kb.KS * o.m_pad;
 #pragma unroll
@@ -482,11 +579,8 @@ __global__ void __launch_bounds__(256) k_kb_project2(Geo g, OrbSet o, KBTables k
 #pragma unroll
     for (int st = 0; st < KT; ++st)
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int slot = st * 16 + MM::row(kk, rr);
-        const int orb = jt * 16 + r;
-        out[slot * o.m_pad + orb] = (double)acc[st][q][rr];
-      }
+      for (int rr = 0; rr < 4; ++rr)
+        out[(st * 16 + MM::row(kk, rr)) * o.m_pad + jt * 16 + r] = (double)acc[st][q][rr];
   }
 }
 
@@ -509,27 +603,32 @@ __global__ void __launch_bounds__(256) k_kb_reduce(Geo g, OrbSet o, KBTables kb,
 }
 
 // Y_i(l) += sum_slot beta_slot(l) E_slot C[f][slot atom][i] per region, as MFMA
-// products of (E C)^T (orbitals x slots, staged in LDS) with the dense region
-// block (slots x points); wave w takes the 16-point tiles w, w + 4, ... so the
-// four waves cover 64 consecutive points at a time.  The beta values and the
-// old Y values of the next tile are loaded before the products of the current
-// one (unconditional loads, rows and points clamped, stores masked).
+// products of (E C)^T (orbitals x slots, staged in LDS) with the region's beta
+// block (slots x points, evaluated in registers from the staged slot tables);
+// wave w takes the 16-point tiles w, w + 4, ... so the four waves cover 64
+// consecutive points at a time.  The old Y values of the next tile are loaded
+// before the products of the current one (unconditional loads, rows and points
+// clamped, stores masked).
 template <typename T, int TM, int KT, bool RP>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2, 8)))
-k_kb_apply2(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
-            T *__restrict__ y) {
+k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
+           T *__restrict__ y) {
   typedef Mfma<T> MM;
   constexpr int MP = 16 * TM;
   constexpr int LD = lds_stride(MP);
   constexpr int KSM = 16 * KT;
   constexpr int NU = kRegion / 16 / 4;  // tiles per wave
-  __shared__ T ec[KSM * LD];
+  extern __shared__ __attribute__((aligned(16))) double kb_lds[];
+  const int nx = g.nl[0], RR = region_rows(nx);
+  double *sx = kb_lds, *syz = sx + kb.KS * nx, *par = syz + kb.KS * RR;
+  T *ec = reinterpret_cast<T *>(par + 3 * kb.KS);   // [KSM][LD]
   const int f = f0 + blockIdx.x / kb.NR;
   const int reg = blockIdx.x % kb.NR;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mf = o.m[f];
   const int rmax = o.row_pad ? MP - 1 : mf - 1;
+  const int row0 = reg * kRegion / nx;
   const int *ra = kb.reg_atom + ((long long)f * kb.NR + reg) * kb.KS;
   const double *Cf = C + (long long)f * kb.A_max * o.m_pad;
   const double *Ef = kb.E + (long long)f * kb.A_max;
@@ -538,8 +637,8 @@ k_kb_apply2(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
     const int a = (slot < kb.KS) ? ra[slot] : -1;
     ec[slot * LD + i] = (a >= 0 && i < mf) ? (T)(Ef[a] * Cf[(long long)a * o.m_pad + i]) : (T)0;
   }
+  stage_region(g, kb, f, reg, sx, syz, par);
   __syncthreads();
-  const T *blk = region_beta<T>(kb) + ((long long)f * kb.NR + reg) * kb.KS * kRegion;
   const long long base = o.moff[f] * (long long)g.n;
   const int c = lane & 15, kk = lane >> 4;
   // Y row orb = jt*16 + row_u(rr) + row_l(kk): with padded arrays (RP) the
@@ -551,24 +650,29 @@ k_kb_apply2(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
     const int orb = jt * 16 + MM::row(kk, rr);
     return y + base + (long long)(orb < rmax ? orb : rmax) * g.n + pc;
   };
-  auto load_tile = [&](int k, T *bv, T (*yv)[4]) {
-    const int u = wave + 4 * k;
-    const int p = reg * kRegion + u * 16 + c;
+  auto load_y = [&](int k, T (*yv)[4]) {
+    const int p = reg * kRegion + (wave + 4 * k) * 16 + c;
     const int pc = p < g.n ? p : g.n - 1;
-#pragma unroll
-    for (int st = 0; st < KT * 4; ++st)
-      bv[st] = (blk + 4 * st * kRegion + u * 16)[kk * kRegion + c];
 #pragma unroll
     for (int jt = 0; jt < TM; ++jt)
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) yv[jt][rr] = *yaddr(jt, rr, pc);
   };
-  T bv[KT * 4], yv[TM][4];
-  load_tile(0, bv, yv);
+  T yv[TM][4];
+  load_y(0, yv);
   for (int k = 0; k < NU; ++k) {
-    T bn[KT * 4], yn[TM][4];
-    load_tile(k + 1 < NU ? k + 1 : k, bn, yn);
+    T yn[TM][4];
+    load_y(k + 1 < NU ? k + 1 : k, yn);
     const int p = reg * kRegion + (wave + 4 * k) * 16 + c;
+    const int pc = p < g.n ? p : g.n - 1;
+    const int lx = pc % nx, rr0 = pc / nx - row0;
+    // beta of slots 4 st + kk at the lane's point
+    T bv[KT * 4];
+#pragma unroll
+    for (int st = 0; st < KT * 4; ++st) {
+      const T v = beta_at<T>(sx, syz, par, kb.KS, nx, RR, 4 * st + kk, lx, rr0);
+      bv[st] = p < g.n ? v : (T)0;
+    }
     typename MM::acc_t acc[TM];
 #pragma unroll
     for (int j = 0; j < TM; ++j) acc[j] = MM::zero();
@@ -586,8 +690,6 @@ k_kb_apply2(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
         const int orb = jt * 16 + MM::row(kk, rr);
         if (orb < mf && p < g.n) *yaddr(jt, rr, p) = yv[jt][rr] + acc[jt][rr];
       }
-#pragma unroll
-    for (int st = 0; st < KT * 4; ++st) bv[st] = bn[st];
 #pragma unroll
     for (int jt = 0; jt < TM; ++jt)
 #pragma unroll
@@ -677,20 +779,23 @@ void kb_t(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1, con
           double *C, double *part, T *y, hipStream_t s) {
   const dim3 grid((f1 - f0) * kb.NR), block(256);
   if (x) {
+    const size_t lds = kb_lds_bytes(g, kb.KS, TM, sizeof(T), false);
     // 16-byte runs need n % 4 == 0 and an aligned array
     if (g.n % 4 == 0 && (uintptr_t)x % 16 == 0)
-      hipLaunchKernelGGL((k_kb_project2<T, TM, KT, true>), grid, block, 0, s, g, o, kb, f0, x,
+      hipLaunchKernelGGL((k_kb_project<T, TM, KT, true>), grid, block, lds, s, g, o, kb, f0, x,
                          part);
     else
-      hipLaunchKernelGGL((k_kb_project2<T, TM, KT, false>), grid, block, 0, s, g, o, kb, f0, x,
+      hipLaunchKernelGGL((k_kb_project<T, TM, KT, false>), grid, block, lds, s, g, o, kb, f0, x,
                          part);
     const long long total = (long long)(f1 - f0) * kb.A_max * o.m_pad;
     hipLaunchKernelGGL(k_kb_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, o,
                        kb, f0, f1 - f0, part, C);
-  } else if (o.row_pad) {
-    hipLaunchKernelGGL((k_kb_apply2<T, TM, KT, true>), grid, block, 0, s, g, o, kb, f0, C, y);
   } else {
-    hipLaunchKernelGGL((k_kb_apply2<T, TM, KT, false>), grid, block, 0, s, g, o, kb, f0, C, y);
+    const size_t lds = kb_lds_bytes(g, kb.KS, TM, sizeof(T), true);
+    if (o.row_pad)
+      hipLaunchKernelGGL((k_kb_apply<T, TM, KT, true>), grid, block, lds, s, g, o, kb, f0, C, y);
+    else
+      hipLaunchKernelGGL((k_kb_apply<T, TM, KT, false>), grid, block, lds, s, g, o, kb, f0, C, y);
   }
 }
 
@@ -774,6 +879,16 @@ void launch_vec(const Geo &g, long long nb, int opw, int zs, const OrbSet &o, in
 }
 
 }  // namespace
+
+// LDS bytes of the projector kernels: the slot tables, and the (E C)^T block
+// (apply) or the partial sums (project) of the widest orbital count
+size_t kb_lds_bytes(const Geo &g, int KS, int tiles, size_t elem, bool apply) {
+  const size_t tab = (size_t)KS * (g.nl[0] + region_rows(g.nl[0]) + 3) * sizeof(double);
+  const int MP = 16 * tiles;
+  if (apply) return tab + (size_t)KS * lds_stride(MP) * elem;
+  const int ch = elem == 4 ? 64 : 32;   // project: two beta chunks
+  return tab + 2 * (size_t)KS * (ch + 16 / elem) * elem;
+}
 
 bool hloc_halo_ok(const Geo &g) {
   // halo copies need nx, ny >= 4; the held end planes need nz >= 8; the padded
