@@ -80,9 +80,10 @@ def hloc_kernel_name(variant: str, prec_mixed: bool, box) -> str:
     return HLOC_KERNEL[variant].format(t=t, nx=nx if nx in (24, 32) else 0)
 
 
-def recorded_traffic(kernel: str, workload: str):
+def recorded_traffic(variant: str, kernel: str, workload: str):
     """HBM bytes per launch from the committed counter summaries, if they were
-    taken on the current stencil source for this kernel and workload."""
+    taken on the current stencil source for this launch shape (variant and
+    kernel) and workload."""
     import glob
     import hashlib
     src = os.path.join(ROOT, "paper_2606_21125_amd", "csrc", "k_orbital.hip")
@@ -94,9 +95,9 @@ def recorded_traffic(kernel: str, workload: str):
                 if not line.startswith("traffic:"):
                     continue
                 parts = [p.strip() for p in line[len("traffic:"):].split("|")]
-                if len(parts) == 4 and parts[0] == kernel and parts[1] == workload and \
-                        parts[3] == sha:
-                    return float(parts[2]), os.path.relpath(path, ROOT)
+                if len(parts) == 5 and parts[0] == variant and parts[1] == kernel and \
+                        parts[2] == workload and parts[4] == sha:
+                    return float(parts[3]), os.path.relpath(path, ROOT)
     return None, None
 
 
@@ -192,7 +193,7 @@ def main() -> int:
     kb_gbs = kb["bytes"] / (kb["ms"] * 1e-3) / 1e9 if kb["ms"] > 0 else 0.0
     variant = tune["hloc_variant"] if tune else HLOC_VARIANTS[launch0["hloc_variant"]]
     kname = hloc_kernel_name(variant, prec != PREC_FP64, cfg.fragment_shape)
-    traffic, traffic_src = recorded_traffic(kname, cfg.name)
+    traffic, traffic_src = recorded_traffic(variant, kname, cfg.name)
     roofline = {"bound": "hbm", "achieved": round(h_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(h_gbs / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic),
