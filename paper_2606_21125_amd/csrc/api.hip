@@ -350,19 +350,19 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
       Timed t(c, DCDFT_KERNEL_ROTATE, 5.0 * sz * n * nb, 6.0 * n * m2);
       launch_rot_cholres<T>(g, o, f0, f1, c->d_lin, c->d_bmat, psi, w, q, c->d_dpart,
                             c->d_gamma, s);
-    } else {
-      // after the last sweep only Psi is used (W is rebuilt by the next step)
-      Timed t(c, DCDFT_KERNEL_ROTATE, 2.0 * sz * n * nb, 2.0 * n * m2);
-      launch_rot_cholesky<T>(g, o, f0, f1, c->d_lin, psi, (T *)nullptr, s);
     }
+    // after the last sweep only Psi is used (W is rebuilt by the next step), and
+    // its re-orthonormalisation L^-1 is folded into the Ritz rotation below
   }
   // Rayleigh-Ritz on Hs = sym(<Psi, W>) (from the last sweep's re-orthonormalisation
   // when fused), then core weights w_i = dV sum_core psi_i^2
   if (!fuse) gram<T>(c, f0, f1, psi, w, c->d_hs, nullptr, nullptr);
   launch_syev(o, f0, f1, c->d_hs, c->d_u, c->d_eps, c->d_flags, s);
+  // fused: Psi' is not yet re-orthonormalised; rotate it by C = L^-T U at once
+  if (fuse) launch_ritz_combine(o, f0, f1, c->d_lin, c->d_u, c->d_bmat, s);
   {
     Timed t(c, DCDFT_KERNEL_ROTATE, 2.0 * sz * n * nb, 2.0 * n * m2);
-    launch_rot_ritz<T>(g, o, f0, f1, c->d_u, psi, c->d_dpart, c->d_wcore, s);
+    launch_rot_ritz<T>(g, o, f0, f1, fuse ? c->d_bmat : c->d_u, psi, c->d_dpart, c->d_wcore, s);
   }
 }
 

@@ -321,6 +321,10 @@ void launch_cholinv(const OrbSet &o, int f0, int f1, const double *S, double *Li
                     hipStream_t s, const double *M = nullptr, double *Hs = nullptr,
                     double *adiag = nullptr, double *Bm = nullptr);
 // Hs -> U (eigenvectors as columns), eps (ascending), FP64 Jacobi
+// C = L^-T U per fragment (one rotation by C of the arrays before
+// re-orthonormalisation gives the Ritz vectors)
+void launch_ritz_combine(const OrbSet &o, int f0, int f1, const double *Linv, const double *U,
+                         double *C, hipStream_t s);
 void launch_syev(const OrbSet &o, int f0, int f1, const double *Hs, double *U, double *eps,
                  int *flags, hipStream_t s);
 // global chemical potential, occupations, band energy, entropy (one workgroup)

@@ -799,6 +799,38 @@ __global__ void __launch_bounds__(256) k_cholinv(OrbSet o, int f0, const double 
   });
 }
 
+// C = L^-T U for the closing rotation of the re-orthonormalisation and the
+// Rayleigh-Ritz step together: with Psi = L^-1 Psi' the Ritz vectors are
+// U^T Psi = (L^-T U)^T Psi', so one rotation of Psi' by C replaces two.  One
+// workgroup per fragment, FP64 matrix cores.
+__global__ void __launch_bounds__(256) k_ritz_combine(OrbSet o, int f0,
+                                                      const double *__restrict__ Linv,
+                                                      const double *__restrict__ U,
+                                                      double *__restrict__ C) {
+  __shared__ double P[kMaxOrb * (kMaxOrb + 1)];
+  __shared__ double Q[kMaxOrb * (kMaxOrb + 1)];
+  const int f = f0 + blockIdx.x;
+  const int mf = o.m[f], mp = o.m_pad;
+  const int nt = (mf + 15) / 16, mt = 16 * nt, ld = mt + 1;
+  const double *Lf = Linv + (long long)f * mp * mp, *Uf = U + (long long)f * mp * mp;
+  double *Cf = C + (long long)f * mp * mp;
+  // P = L^-T, Q = U (zero past the fragment's size)
+  for (int e = threadIdx.x; e < mt * mt; e += blockDim.x) {
+    const int i = e / mt, j = e % mt;
+    const bool in = i < mf && j < mf;
+    P[i * ld + j] = in ? Lf[j * mp + i] : 0.0;
+    Q[i * ld + j] = in ? Uf[i * mp + j] : 0.0;
+  }
+  for (int e = threadIdx.x; e < mp * mp; e += blockDim.x) {
+    const int i = e / mp, j = e % mp;
+    if (i >= mt || j >= mt) Cf[e] = 0.0;
+  }
+  __syncthreads();
+  lds_gemm_f64<false>(P, Q, ld, nt, [&](int r, int c, double v) {
+    if (r < mp && c < mp) Cf[r * mp + c] = (r < mf && c < mf) ? v : 0.0;
+  });
+}
+
 // Round-robin (circle) pairing: in round r of mm - 1, pair k.
 __device__ inline void rr_pair(int mm, int r, int k, int &p, int &q) {
   if (k == 0) {
@@ -1244,6 +1276,12 @@ void launch_cholinv(const OrbSet &o, int f0, int f1, const double *S, double *Li
   if (f1 <= f0) return;
   hipLaunchKernelGGL(k_cholinv, dim3(f1 - f0), dim3(256), 0, s, o, f0, S, Linv, flags, M, Hs,
                      adiag, Bm);
+}
+
+void launch_ritz_combine(const OrbSet &o, int f0, int f1, const double *Linv, const double *U,
+                         double *C, hipStream_t s) {
+  if (f1 <= f0) return;
+  hipLaunchKernelGGL(k_ritz_combine, dim3(f1 - f0), dim3(256), 0, s, o, f0, Linv, U, C);
 }
 
 void launch_syev(const OrbSet &o, int f0, int f1, const double *Hs, double *U, double *eps,
