@@ -291,7 +291,8 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
   // FP32 arrays: the re-orthonormalisation of one sweep also forms the next
   // sweep's Hs and residual (fused rotation, fewer passes).  FP64 arrays keep
   // the separate passes (the fused rotation's three matrix-core products per
-  // tile do not fit the FP64 register budget well).
+  // tile do not fit the FP64 register budget well) except in the last sweep,
+  // where both take Hs from <Psi', W'> and fold L^-1 into the Ritz rotation.
   constexpr bool fuse = sizeof(T) == 4;
   apply_h_range<T>(c, f0, f1, psi, w);
   for (int sw = 0; sw < c->sweeps; ++sw) {
@@ -325,15 +326,16 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
     launch_kb_quad(o, f0, f1, kb, c->d_C, c->d_cc, s);
     // (h)-(i) exact minimiser of the 2x2 Rayleigh quotient
     launch_cg_theta(o, f0, f1, c->d_a, c->d_bb, c->d_cc, c->d_inv, c->d_cos, c->d_sin, s);
-    // (j) band rotations and (l) S = sym(<Psi, Psi>); fused: also M = <Psi', W'>
+    // (j) band rotations and (l) S = sym(<Psi, Psi>); with_m: also M = <Psi', W'>
     // of the rotated (not yet re-orthonormalised) arrays
+    const bool with_m = fuse || last;
     {
-      Timed t(c, DCDFT_KERNEL_GRAM_FUSED, 6.0 * sz * n * nb, (fuse ? 3.0 : 1.0) * n * m2);
+      Timed t(c, DCDFT_KERNEL_GRAM_FUSED, 6.0 * sz * n * nb, (with_m ? 3.0 : 1.0) * n * m2);
       launch_gram_update<T>(g, o, f0, f1, ch, psi, p, w, q, c->d_cos, c->d_sin, gpart_at(c, f0), s,
-                            fuse ? gpart2_at(c, f0) : nullptr);
+                            with_m ? gpart2_at(c, f0) : nullptr);
     }
     launch_gram_reduce(g, o, f0, f1, ch, 1, gpart_at(c, f0), c->d_s, nullptr, nullptr, s);
-    if (!fuse) {
+    if (!with_m) {
       // (l) S = L L^T, Psi <- L^-1 Psi, W <- L^-1 W
       launch_cholinv(o, f0, f1, c->d_s, c->d_lin, c->d_flags, s);
       Timed t(c, DCDFT_KERNEL_ROTATE, 4.0 * sz * n * nb, 2.0 * n * m2);
@@ -354,15 +356,14 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
     // after the last sweep only Psi is used (W is rebuilt by the next step), and
     // its re-orthonormalisation L^-1 is folded into the Ritz rotation below
   }
-  // Rayleigh-Ritz on Hs = sym(<Psi, W>) (from the last sweep's re-orthonormalisation
-  // when fused), then core weights w_i = dV sum_core psi_i^2
-  if (!fuse) gram<T>(c, f0, f1, psi, w, c->d_hs, nullptr, nullptr);
+  // Rayleigh-Ritz on Hs = sym(<Psi, W>) from the last sweep's re-orthonormalisation;
+  // Psi' is not yet re-orthonormalised, so it is rotated by C = L^-T U at once;
+  // then core weights w_i = dV sum_core psi_i^2
   launch_syev(o, f0, f1, c->d_hs, c->d_u, c->d_eps, c->d_flags, s);
-  // fused: Psi' is not yet re-orthonormalised; rotate it by C = L^-T U at once
-  if (fuse) launch_ritz_combine(o, f0, f1, c->d_lin, c->d_u, c->d_bmat, s);
+  launch_ritz_combine(o, f0, f1, c->d_lin, c->d_u, c->d_bmat, s);
   {
     Timed t(c, DCDFT_KERNEL_ROTATE, 2.0 * sz * n * nb, 2.0 * n * m2);
-    launch_rot_ritz<T>(g, o, f0, f1, fuse ? c->d_bmat : c->d_u, psi, c->d_dpart, c->d_wcore, s);
+    launch_rot_ritz<T>(g, o, f0, f1, c->d_bmat, psi, c->d_dpart, c->d_wcore, s);
   }
 }
 
@@ -969,7 +970,7 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   ALLOC(c->d_rhof_in, (long long)c->nF * g.n);
   ALLOC(c->d_rhof_out, (long long)c->nF * g.n);
   ALLOC(c->d_gpart, (long long)c->nF * c->gram_chunks_max * mp2);
-  if (mixed) ALLOC(c->d_gpart2, (long long)c->nF * c->gram_chunks_max * mp2);
+  ALLOC(c->d_gpart2, (long long)c->nF * c->gram_chunks_max * mp2);
   ALLOC(c->d_gtmp, c->nF * mp2);
   {
     // rotation partials for the smallest tile count the autotuner may pick

@@ -179,7 +179,7 @@ struct dcdft_ctx {
 
   // small matrices [F][m_pad][m_pad]
   double *d_gpart = nullptr;         // Gram partials [F][chunks][m_pad][m_pad]
-  double *d_gpart2 = nullptr;        // second product of a fused Gram (mixed path), same layout
+  double *d_gpart2 = nullptr;        // second product of a fused Gram, same layout
   double *d_gtmp = nullptr;          // Gram result when only the symmetric part is kept
   double *d_dpart = nullptr;         // per-workgroup band partials [F][wpf][2][m_pad]
   double *d_hs_full = nullptr, *d_hs = nullptr, *d_x = nullptr, *d_s = nullptr, *d_lin = nullptr,
