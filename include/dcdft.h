@@ -117,8 +117,11 @@ typedef struct {
  * initial orbitals (SplitMix64 counter stream: orbital-point (alpha, i, l) uses
  * counter ((alpha << 40) | (i << 24) | l) + 1; value = top 53 bits * 2^-53 - 1/2)
  * and Cholesky-orthonormalise them; the input density starts uniform, N_e / volume.
- * Errors: ARG (null or out-of-range field), SHAPE (n_grid % num_fragment != 0 or
- * ncore + 2 b > N), OOM, HIP, NOT_SPD.  On success *out owns all device memory. */
+ * Errors: ARG (null or out-of-range field; also when more projectors meet one
+ * 256-point region of a fragment box than the projector kernels hold: 96, or
+ * fewer where their slot tables would exceed 64 KB of LDS), SHAPE (n_grid %
+ * num_fragment != 0 or ncore + 2 b > N), OOM, HIP, NOT_SPD.  On success *out owns
+ * all device memory. */
 dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out);
 
 /* Exactly one SCF iteration over all fragments (Sec. 2.2): Hartree potential of
