@@ -302,30 +302,30 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
       // gamma_i = <g_i, g_i>
       gram<T>(c, f0, f1, psi, w, c->d_hs_full, c->d_hs, c->d_a);
       Timed t(c, DCDFT_KERNEL_ROTATE, 3.0 * sz * n * nb, 2.0 * n * m2);
-      launch_rot_residual<T>(g, o, f0, f1, c->d_hs, psi, w, q, c->d_dpart, c->d_gamma, s);
+      // (c) with the Fletcher-Reeves beta
+      launch_rot_residual<T>(g, o, f0, f1, c->d_hs, psi, w, q, c->d_dpart, c->d_gamma, s, sw == 0,
+                             c->d_gamma_prev, c->d_beta);
     }
-    // (c) Fletcher-Reeves beta
-    launch_cg_beta(o, f0, f1, sw == 0, c->d_gamma, c->d_gamma_prev, c->d_beta, s);
     // (d)-(e) P = -G + beta P_prev, X = <Psi, P>
     {
       Timed t(c, DCDFT_KERNEL_GRAM_FUSED, 4.0 * sz * n * nb, 2.0 * n * m2);
       launch_gram_direction<T>(g, o, f0, f1, ch, psi, q, p, c->d_beta, gpart_at(c, f0), s);
     }
     launch_gram_reduce(g, o, f0, f1, ch, 0, gpart_at(c, f0), c->d_x, nullptr, nullptr, s);
-    // (e)-(f) P <- P - X^T Psi, nu_i = <p_i, p_i>, <p_i, w_i>
+    // (e)-(f) P <- P - X^T Psi, nu_i = <p_i, p_i> (and 1/sqrt(nu_i)), <p_i, w_i>
     {
       Timed t(c, DCDFT_KERNEL_ROTATE, 4.0 * sz * n * nb, 2.0 * n * m2);
       launch_rot_project_out<T>(g, o, f0, f1, c->d_x, psi, p, w, c->d_dpart, c->d_nu, c->d_bb,
-                                s);
+                                s, c->d_inv);
     }
-    launch_cg_norm(o, f0, f1, c->d_nu, c->d_inv, s);
     // (g) Q = H P and <p_i, q_i>
     hloc<T>(c, f0, f1, p, q, c->d_cc);
     kb_project<T>(c, f0, f1, p);
     kb_apply<T>(c, f0, f1, q);
-    launch_kb_quad(o, f0, f1, kb, c->d_C, c->d_cc, s);
-    // (h)-(i) exact minimiser of the 2x2 Rayleigh quotient
-    launch_cg_theta(o, f0, f1, c->d_a, c->d_bb, c->d_cc, c->d_inv, c->d_cos, c->d_sin, s);
+    // projector part of <p_i, q_i>, then (h)-(i) the exact minimiser of the 2x2
+    // Rayleigh quotient
+    launch_kb_quad_theta(o, f0, f1, kb, c->d_C, c->d_cc, c->d_a, c->d_bb, c->d_inv, c->d_cos,
+                         c->d_sin, s);
     // (j) band rotations and (l) S = sym(<Psi, Psi>); with_m: also M = <Psi', W'>
     // of the rotated (not yet re-orthonormalised) arrays
     const bool with_m = fuse || last;
@@ -334,24 +334,26 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
       launch_gram_update<T>(g, o, f0, f1, ch, psi, p, w, q, c->d_cos, c->d_sin, gpart_at(c, f0), s,
                             with_m ? gpart2_at(c, f0) : nullptr);
     }
-    launch_gram_reduce(g, o, f0, f1, ch, 1, gpart_at(c, f0), c->d_s, nullptr, nullptr, s);
     if (!with_m) {
+      launch_gram_reduce(g, o, f0, f1, ch, 1, gpart_at(c, f0), c->d_s, nullptr, nullptr, s);
       // (l) S = L L^T, Psi <- L^-1 Psi, W <- L^-1 W
       launch_cholinv(o, f0, f1, c->d_s, c->d_lin, c->d_flags, s);
       Timed t(c, DCDFT_KERNEL_ROTATE, 4.0 * sz * n * nb, 2.0 * n * m2);
       launch_rot_cholesky<T>(g, o, f0, f1, c->d_lin, psi, w, s);
       continue;
     }
-    launch_gram_reduce(g, o, f0, f1, ch, 0, gpart2_at(c, f0), c->d_hs_full, nullptr, nullptr, s);
+    launch_gram_reduce_pair(g, o, f0, f1, ch, gpart_at(c, f0), c->d_s, gpart2_at(c, f0),
+                            c->d_hs_full, s);
     // (l) S = L L^T; with Psi = L^-1 Psi', W = L^-1 W' the next sweep's
     // Hs = sym(<Psi, W>) = sym(L^-1 M L^-T) and a_i = Hs_ii, B = Hs L^-1
     launch_cholinv(o, f0, f1, c->d_s, c->d_lin, c->d_flags, s, c->d_hs_full, c->d_hs, c->d_a,
                    c->d_bmat);
     if (!last) {
-      // Psi <- L^-1 Psi', W <- L^-1 W' and the next sweep's (b): G = W - B Psi'
+      // Psi <- L^-1 Psi', W <- L^-1 W' and the next sweep's (b) and (c):
+      // G = W - B Psi', gamma and the Fletcher-Reeves beta
       Timed t(c, DCDFT_KERNEL_ROTATE, 5.0 * sz * n * nb, 6.0 * n * m2);
       launch_rot_cholres<T>(g, o, f0, f1, c->d_lin, c->d_bmat, psi, w, q, c->d_dpart,
-                            c->d_gamma, s);
+                            c->d_gamma, s, c->d_gamma_prev, c->d_beta);
     }
     // after the last sweep only Psi is used (W is rebuilt by the next step), and
     // its re-orthonormalisation L^-1 is folded into the Ritz rotation below

@@ -274,19 +274,25 @@ void launch_gram_update(const Geo &g, const OrbSet &o, int f0, int f1, int chunk
 // not null; diag -> per-band (may be null)
 void launch_gram_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int sym,
                         const double *part, double *G, double *Gs, double *diag, hipStream_t s);
+// both reductions of a fused update: S (symmetric partials) and M (full)
+void launch_gram_reduce_pair(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
+                             const double *part_s, double *S, const double *part_m, double *M,
+                             hipStream_t s);
 // Fused rotations (per-band reductions go through dpart, one partial per
 // rotation workgroup, then a band reduction).
 int rot_wpf(const Geo &g);
-// G = W - Hs Psi into gout, gamma = dV |G|^2
+// G = W - Hs Psi into gout, gamma = dV |G|^2; with gamma_prev also the
+// Fletcher-Reeves beta = gamma / gamma_prev (0 when first), then gamma_prev = gamma
 template <typename T>
 void launch_rot_residual(const Geo &g, const OrbSet &o, int f0, int f1, const double *Hs,
                          const T *psi, const T *w, T *gout, double *dpart, double *gamma,
-                         hipStream_t s);
-// P <- P - X^T Psi, nu = dV |P|^2, pw = dV <P, W>
+                         hipStream_t s, int first = 0, double *gamma_prev = nullptr,
+                         double *beta = nullptr);
+// P <- P - X^T Psi, nu = dV |P|^2, pw = dV <P, W>; with inv also inv = 1/sqrt(nu)
 template <typename T>
 void launch_rot_project_out(const Geo &g, const OrbSet &o, int f0, int f1, const double *X,
                             const T *psi, T *p, const T *w, double *dpart, double *nu,
-                            double *pw, hipStream_t s);
+                            double *pw, hipStream_t s, double *inv = nullptr);
 // Psi <- Linv Psi and, if w is not null, W <- Linv W (Linv lower triangular)
 template <typename T>
 void launch_rot_cholesky(const Geo &g, const OrbSet &o, int f0, int f1, const double *Linv,
@@ -296,25 +302,19 @@ template <typename T>
 void launch_rot_ritz(const Geo &g, const OrbSet &o, int f0, int f1, const double *U, T *psi,
                      double *dpart, double *wcore, hipStream_t s);
 
-// CG scalar steps: beta = gamma / gamma_prev (0 on the first sweep), then
-// gamma_prev = gamma; inv = 1/sqrt(nu); theta from the 2x2 problem
-void launch_cg_beta(const OrbSet &o, int f0, int f1, int first, const double *gamma,
-                    double *gamma_prev, double *beta, hipStream_t s);
-void launch_cg_norm(const OrbSet &o, int f0, int f1, const double *nu, double *inv,
-                    hipStream_t s);
-void launch_cg_theta(const OrbSet &o, int f0, int f1, const double *a, const double *b,
-                     const double *c, const double *inv, double *cs, double *sn, hipStream_t s);
 void launch_copy_band(const OrbSet &o, int f0, int f1, const double *src, double *dst,
                       hipStream_t s);
-// cp[B] += sum_a E_a C[f][a][i]^2
-void launch_kb_quad(const OrbSet &o, int f0, int f1, const KBTables &kb, const double *C,
-                    double *cp, hipStream_t s);
+// cp[B] += sum_a E_a C[f][a][i]^2, then the 2x2 CG step: theta = atan2(-2 inv bp,
+// inv^2 cp - a) / 2 -> cs = cos(theta), sn = inv sin(theta)
+void launch_kb_quad_theta(const OrbSet &o, int f0, int f1, const KBTables &kb, const double *C,
+                          double *cp, const double *a, const double *bp, const double *inv,
+                          double *cs, double *sn, hipStream_t s);
 // Psi <- Linv Psi', W <- Linv W' (in place) and G = W - Bm Psi' into gout, with
 // gamma = dV |g|^2 (Bm = Hs Linv from launch_cholinv)
 template <typename T>
 void launch_rot_cholres(const Geo &g, const OrbSet &o, int f0, int f1, const double *Linv,
                         const double *Bm, T *psi, T *w, T *gout, double *dpart, double *gamma,
-                        hipStream_t s);
+                        hipStream_t s, double *gamma_prev = nullptr, double *beta = nullptr);
 // S -> Linv (row-major lower-triangular inverse of the Cholesky factor), FP64;
 // with M = <Psi', W'> also Hs = sym(Linv M Linv^T), its diagonal and Bm = Hs Linv
 void launch_cholinv(const OrbSet &o, int f0, int f1, const double *S, double *Linv, int *flags,

@@ -571,7 +571,8 @@ __global__ void __launch_bounds__(256) k_kb_project(Geo g, OrbSet o, KBTables kb
 #pragma unroll
         for (int t = 0; t < 4; ++t) bx[q][u][t] = bn[q][u][t];
   }
-  double *out = part + ((long long)f * kb.NR + reg) * kb.KS * o.m_pad;
+  // partials in the accumulation type (FP32 sums are stored exactly as FP32)
+  T *out = reinterpret_cast<T *>(part) + ((long long)f * kb.NR + reg) * kb.KS * o.m_pad;
 #pragma unroll
   for (int q = 0; q < JW; ++q) {
     const int jt = wave + 4 * q;
@@ -580,13 +581,15 @@ __global__ void __launch_bounds__(256) k_kb_project(Geo g, OrbSet o, KBTables kb
     for (int st = 0; st < KT; ++st)
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr)
-        out[(st * 16 + MM::row(kk, rr)) * o.m_pad + jt * 16 + r] = (double)acc[st][q][rr];
+        out[(st * 16 + MM::row(kk, rr)) * o.m_pad + jt * 16 + r] = acc[st][q][rr];
   }
 }
 
-// C[f][a][i] = dV sum over the (region, slot) entries of atom a.
+// C[f][a][i] = dV sum over the (region, slot) entries of atom a (region partials
+// of type T, summed in FP64).
+template <typename T>
 __global__ void __launch_bounds__(256) k_kb_reduce(Geo g, OrbSet o, KBTables kb, int f0, int nf,
-                                                   const double *__restrict__ part,
+                                                   const T *__restrict__ part,
                                                    double *__restrict__ C) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long total = (long long)nf * kb.A_max * o.m_pad;
@@ -597,7 +600,7 @@ __global__ void __launch_bounds__(256) k_kb_reduce(Geo g, OrbSet o, KBTables kb,
   double s = 0.0;
   for (long long e = kb.ar_ptr[fa]; e < kb.ar_ptr[fa + 1]; ++e) {
     const long long q = ((long long)f * kb.NR + kb.ar_reg[e]) * kb.KS + kb.ar_slot[e];
-    s += part[q * o.m_pad + i];
+    s += (double)part[q * o.m_pad + i];
   }
   C[fa * o.m_pad + i] = g.dv * s;
 }
@@ -788,8 +791,8 @@ void kb_t(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1, con
       hipLaunchKernelGGL((k_kb_project<T, TM, KT, false>), grid, block, lds, s, g, o, kb, f0, x,
                          part);
     const long long total = (long long)(f1 - f0) * kb.A_max * o.m_pad;
-    hipLaunchKernelGGL(k_kb_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, o,
-                       kb, f0, f1 - f0, part, C);
+    hipLaunchKernelGGL(k_kb_reduce<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g,
+                       o, kb, f0, f1 - f0, reinterpret_cast<const T *>(part), C);
   } else {
     const size_t lds = kb_lds_bytes(g, kb.KS, TM, sizeof(T), true);
     if (o.row_pad)

@@ -315,12 +315,37 @@ k_rot_cholres(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ Linv,
     out[j] = red[0][j] + red[1][j] + red[2][j] + red[3][j];
 }
 
+// CG scalar steps of one band (every reduction is FP64):
+// Fletcher-Reeves beta = gamma / gamma_prev (0 on the first sweep or a zero
+// gamma_prev), the inverse norm of the search direction, and the exact
+// minimiser theta = atan2(-2b, c - a) / 2 of the 2x2 Rayleigh quotient for the
+// normalised direction p_hat = inv p (b = inv <p, w>, c = inv^2 <p, H p>),
+// returned as cos(theta) and inv sin(theta).
+__device__ inline double cg_beta_of(double gamma, double gamma_prev, int first) {
+  return (first || !(gamma_prev > 0.0)) ? 0.0 : gamma / gamma_prev;
+}
+__device__ inline double cg_inv_of(double nu) { return (nu > 1e-300) ? 1.0 / sqrt(nu) : 0.0; }
+__device__ inline void cg_theta_of(double a, double b, double c, double inv, double &cs,
+                                   double &sn) {
+  double th = 0.0;
+  if (inv != 0.0) th = 0.5 * atan2(-2.0 * inv * b, inv * inv * c - a);
+  cs = cos(th);
+  sn = inv * sin(th);
+}
+
+// Tail applied to the first band sum: BT_BETA takes it as gamma (x0 = gamma_prev,
+// updated; x1 = beta), BT_INV as nu (x0 = 1 / sqrt(nu)).
+enum { BT_NONE = 0, BT_BETA = 1, BT_INV = 2 };
+
 // out_k[B] = dV sum over the workgroup partials of band B (k = 0, 1; null skips):
-// one wave per band, lanes over the partials, fixed-order wave sum.
+// one wave per band, lanes over the partials, fixed-order wave sum; then the
+// tail (see above).
 __global__ void __launch_bounds__(256) k_band_reduce(Geo g, OrbSet o, long long b0, long long nb,
                                                      int wpf, const double *__restrict__ dpart,
                                                      double *__restrict__ out0,
-                                                     double *__restrict__ out1) {
+                                                     double *__restrict__ out1, int tail,
+                                                     int first, double *__restrict__ x0,
+                                                     double *__restrict__ x1) {
   const long long t = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= nb) return;  // wave-uniform
@@ -337,8 +362,15 @@ __global__ void __launch_bounds__(256) k_band_reduce(Geo g, OrbSet o, long long 
   s0 = wave_sum(s0);
   if (out1) s1 = wave_sum(s1);
   if (lane == 0) {
-    if (out0) out0[B] = g.dv * s0;
+    const double v0 = g.dv * s0;
+    if (out0) out0[B] = v0;
     if (out1) out1[B] = g.dv * s1;
+    if (tail == BT_BETA) {
+      x1[B] = cg_beta_of(v0, x0[B], first);
+      x0[B] = v0;
+    } else if (tail == BT_INV) {
+      x0[B] = cg_inv_of(v0);
+    }
   }
 }
 
@@ -590,14 +622,25 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a
 
 // G = dV sum over chunk partials, element-parallel; for symmetric products the
 // tiles below the diagonal are taken from their mirror.
+// A second product (part2 -> G2, not symmetric) may ride in the same launch:
+// indices past the first product's total handle it.
 __global__ void __launch_bounds__(256) k_gram_reduce2(Geo g, OrbSet o, int f0, int nf, int chunks,
                                                       int sym, const double *__restrict__ part,
                                                       double *__restrict__ G,
-                                                      double *__restrict__ diag) {
+                                                      double *__restrict__ diag,
+                                                      const double *__restrict__ part2,
+                                                      double *__restrict__ G2) {
   const int mp = o.m_pad;
   const long long total = (long long)nf * mp * mp;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
+  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) {
+    if (!part2 || idx >= 2 * total) return;
+    idx -= total;
+    part = part2;
+    G = G2;
+    sym = 0;
+    diag = nullptr;
+  }
   const int fl = (int)(idx / (mp * mp));
   const int e = (int)(idx % (mp * mp));
   const int f = f0 + fl;
@@ -993,51 +1036,21 @@ __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *_
   if (threadIdx.x == 0 && !converged) atomicOr(flags, FLAG_EIG);
 }
 
-__global__ void k_cg_beta(long long b0, long long nb, int first, const double *__restrict__ gamma,
-                          double *__restrict__ gamma_prev, double *__restrict__ beta) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
-  const long long B = b0 + i;
-  const double gp = gamma_prev[B];
-  beta[B] = (first || !(gp > 0.0)) ? 0.0 : gamma[B] / gp;
-  gamma_prev[B] = gamma[B];
-}
-
-__global__ void k_cg_norm(long long b0, long long nb, const double *__restrict__ nu,
-                          double *__restrict__ inv) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
-  const long long B = b0 + i;
-  const double v = nu[B];
-  inv[B] = (v > 1e-300) ? 1.0 / sqrt(v) : 0.0;
-}
-
-// theta = atan2(-2b, c - a) / 2 for the normalised direction p_hat = inv p:
-// b = inv <p, w>, c = inv^2 <p, H p>; returns cos(theta) and inv sin(theta).
-__global__ void k_cg_theta(long long b0, long long nb, const double *__restrict__ a,
-                           const double *__restrict__ bp, const double *__restrict__ cp,
-                           const double *__restrict__ inv, double *__restrict__ cs,
-                           double *__restrict__ sn) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
-  const long long B = b0 + i;
-  const double iv = inv[B];
-  double th = 0.0;
-  if (iv != 0.0) th = 0.5 * atan2(-2.0 * iv * bp[B], iv * iv * cp[B] - a[B]);
-  cs[B] = cos(th);
-  sn[B] = iv * sin(th);
-}
-
-// c'[B] += sum_a E_a C[f][a][i]^2 (the projector part of <p, H p>)
 // cp[B] += sum_a E_a C[f][a][i]^2 (the projector part of <p, H p>): one wave
-// per band, lanes over the fragment's atoms, fixed-order wave sum.
-__global__ void __launch_bounds__(256) k_kb_quad(long long b0, long long nb,
-                                                 const int *__restrict__ band_frag,
-                                                 const long long *__restrict__ moff,
-                                                 const int *__restrict__ A, int A_max, int m_pad,
-                                                 const double *__restrict__ E,
-                                                 const double *__restrict__ C,
-                                                 double *__restrict__ cp) {
+// per band, lanes over the fragment's atoms, fixed-order wave sum; then theta
+// of the 2x2 problem from a, bp, cp and inv (cg_theta_of).
+__global__ void __launch_bounds__(256) k_kb_quad_theta(long long b0, long long nb,
+                                                       const int *__restrict__ band_frag,
+                                                       const long long *__restrict__ moff,
+                                                       const int *__restrict__ A, int A_max,
+                                                       int m_pad, const double *__restrict__ E,
+                                                       const double *__restrict__ C,
+                                                       double *__restrict__ cp,
+                                                       const double *__restrict__ a,
+                                                       const double *__restrict__ bp,
+                                                       const double *__restrict__ inv,
+                                                       double *__restrict__ cs,
+                                                       double *__restrict__ sn) {
   const long long t = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= nb) return;  // wave-uniform
@@ -1050,7 +1063,11 @@ __global__ void __launch_bounds__(256) k_kb_quad(long long b0, long long nb,
     s += E[(long long)f * A_max + a] * v * v;
   }
   s = wave_sum(s);
-  if (lane == 0) cp[B] += s;
+  if (lane == 0) {
+    const double c = cp[B] + s;
+    cp[B] = c;
+    cg_theta_of(a[B], bp[B], c, inv[B], cs[B], sn[B]);
+  }
 }
 
 __global__ void k_copy(long long b0, long long nb, const double *__restrict__ src,
@@ -1117,11 +1134,12 @@ void rot_fused_tm(const Geo &g, const OrbSet &o, int f0, int f1, int wpf, const 
 }
 
 void band_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int wpf, const double *dpart,
-                 double *out0, double *out1, hipStream_t s) {
+                 double *out0, double *out1, hipStream_t s, int tail = BT_NONE, int first = 0,
+                 double *x0 = nullptr, double *x1 = nullptr) {
   const long long nb = o.nb(f0, f1);
   if (nb <= 0) return;
   hipLaunchKernelGGL(k_band_reduce, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s, g, o,
-                     o.b0(f0), nb, wpf, dpart, out0, out1);
+                     o.b0(f0), nb, wpf, dpart, out0, out1, tail, first, x0, x1);
 }
 
 }  // namespace
@@ -1167,22 +1185,23 @@ void launch_gram_update(const Geo &g, const OrbSet &o, int f0, int f1, int chunk
 template <typename T>
 void launch_rot_residual(const Geo &g, const OrbSet &o, int f0, int f1, const double *Hs,
                          const T *psi, const T *w, T *gout, double *dpart, double *gamma,
-                         hipStream_t s) {
+                         hipStream_t s, int first, double *gamma_prev, double *beta) {
   const int wpf = rot_wpf(g);
   rot_fused_tm<T, RF_DOT_SELF | RF_Z>(g, o, f0, f1, wpf, Hs, 0, psi, w, 1.0, -1.0, gout, nullptr,
                                nullptr, nullptr, dpart, s);
-  band_reduce(g, o, f0, f1, wpf, dpart, gamma, nullptr, s);
+  band_reduce(g, o, f0, f1, wpf, dpart, gamma, nullptr, s, gamma_prev ? BT_BETA : BT_NONE, first,
+              gamma_prev, beta);
 }
 
 template <typename T>
 void launch_rot_project_out(const Geo &g, const OrbSet &o, int f0, int f1, const double *X,
                             const T *psi, T *p, const T *w, double *dpart, double *nu,
-                            double *pw, hipStream_t s) {
+                            double *pw, hipStream_t s, double *inv) {
   const int wpf = rot_wpf(g);
   rot_fused_tm<T, RF_DOT_SELF | RF_DOT_W | RF_Z>(g, o, f0, f1, wpf, X, 0, psi, p, 1.0, -1.0, p,
                                                  nullptr,
                                           nullptr, w, dpart, s);
-  band_reduce(g, o, f0, f1, wpf, dpart, nu, pw, s);
+  band_reduce(g, o, f0, f1, wpf, dpart, nu, pw, s, inv ? BT_INV : BT_NONE, 0, inv);
 }
 
 template <typename T>
@@ -1200,7 +1219,7 @@ void launch_rot_cholesky(const Geo &g, const OrbSet &o, int f0, int f1, const do
 template <typename T>
 void launch_rot_cholres(const Geo &g, const OrbSet &o, int f0, int f1, const double *Linv,
                         const double *Bm, T *psi, T *w, T *gout, double *dpart, double *gamma,
-                        hipStream_t s) {
+                        hipStream_t s, double *gamma_prev, double *beta) {
   if (f1 <= f0) return;
   const int wpf = rot_wpf(g);
   const dim3 grid((f1 - f0) * wpf), block(256);
@@ -1224,7 +1243,8 @@ void launch_rot_cholres(const Geo &g, const OrbSet &o, int f0, int f1, const dou
     default: DCDFT_CR(5); break;
   }
 #undef DCDFT_CR
-  band_reduce(g, o, f0, f1, wpf, dpart, gamma, nullptr, s);
+  band_reduce(g, o, f0, f1, wpf, dpart, gamma, nullptr, s, gamma_prev ? BT_BETA : BT_NONE, 0,
+              gamma_prev, beta);
 }
 
 template <typename T>
@@ -1246,17 +1266,17 @@ void launch_rot_ritz(const Geo &g, const OrbSet &o, int f0, int f1, const double
                                       hipStream_t, double *);                                 \
   template void launch_rot_residual<T>(const Geo &, const OrbSet &, int, int, const double *,    \
                                        const T *, const T *, T *, double *, double *,            \
-                                       hipStream_t);                                          \
+                                       hipStream_t, int, double *, double *);                 \
   template void launch_rot_project_out<T>(const Geo &, const OrbSet &, int, int, const double *, \
                                           const T *, T *, const T *, double *, double *,         \
-                                          double *, hipStream_t);                               \
+                                          double *, hipStream_t, double *);                     \
   template void launch_rot_cholesky<T>(const Geo &, const OrbSet &, int, int, const double *, T *, \
                                        T *, hipStream_t);                                       \
   template void launch_rot_ritz<T>(const Geo &, const OrbSet &, int, int, const double *, T *,   \
                                    double *, double *, hipStream_t);                          \
   template void launch_rot_cholres<T>(const Geo &, const OrbSet &, int, int, const double *,     \
                                       const double *, T *, T *, T *, double *, double *,         \
-                                      hipStream_t);
+                                      hipStream_t, double *, double *);
 DCDFT_INSTANTIATE(double)
 DCDFT_INSTANTIATE(float)
 #undef DCDFT_INSTANTIATE
@@ -1267,8 +1287,18 @@ void launch_gram_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int chunk
   const long long total = (long long)(f1 - f0) * o.m_pad * o.m_pad;
   const unsigned nb = (unsigned)((total + 255) / 256);
   hipLaunchKernelGGL(k_gram_reduce2, dim3(nb), dim3(256), 0, s, g, o, f0, f1 - f0, chunks, sym,
-                     part, G, diag);
+                     part, G, diag, (const double *)nullptr, (double *)nullptr);
   if (Gs) hipLaunchKernelGGL(k_symmetrize, dim3(nb), dim3(256), 0, s, o, f0, f1 - f0, G, Gs);
+}
+
+void launch_gram_reduce_pair(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
+                             const double *part_s, double *S, const double *part_m, double *M,
+                             hipStream_t s) {
+  if (f1 <= f0) return;
+  const long long total = (long long)(f1 - f0) * o.m_pad * o.m_pad;
+  const unsigned nb = (unsigned)((2 * total + 255) / 256);
+  hipLaunchKernelGGL(k_gram_reduce2, dim3(nb), dim3(256), 0, s, g, o, f0, f1 - f0, chunks, 1,
+                     part_s, S, (double *)nullptr, part_m, M);
 }
 
 void launch_cholinv(const OrbSet &o, int f0, int f1, const double *S, double *Linv, int *flags,
@@ -1290,30 +1320,6 @@ void launch_syev(const OrbSet &o, int f0, int f1, const double *Hs, double *U, d
   hipLaunchKernelGGL(k_syev, dim3(f1 - f0), dim3(1024), 0, s, o, f0, Hs, U, eps, flags);
 }
 
-void launch_cg_beta(const OrbSet &o, int f0, int f1, int first, const double *gamma,
-                    double *gamma_prev, double *beta, hipStream_t s) {
-  const long long nb = o.nb(f0, f1);
-  if (nb <= 0) return;
-  hipLaunchKernelGGL(k_cg_beta, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, o.b0(f0), nb,
-                     first, gamma, gamma_prev, beta);
-}
-
-void launch_cg_norm(const OrbSet &o, int f0, int f1, const double *nu, double *inv,
-                    hipStream_t s) {
-  const long long nb = o.nb(f0, f1);
-  if (nb <= 0) return;
-  hipLaunchKernelGGL(k_cg_norm, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, o.b0(f0), nb,
-                     nu, inv);
-}
-
-void launch_cg_theta(const OrbSet &o, int f0, int f1, const double *a, const double *b,
-                     const double *c, const double *inv, double *cs, double *sn, hipStream_t s) {
-  const long long nb = o.nb(f0, f1);
-  if (nb <= 0) return;
-  hipLaunchKernelGGL(k_cg_theta, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, o.b0(f0), nb,
-                     a, b, c, inv, cs, sn);
-}
-
 void launch_copy_band(const OrbSet &o, int f0, int f1, const double *src, double *dst,
                       hipStream_t s) {
   const long long nb = o.nb(f0, f1);
@@ -1323,12 +1329,14 @@ void launch_copy_band(const OrbSet &o, int f0, int f1, const double *src, double
 }
 
 
-void launch_kb_quad(const OrbSet &o, int f0, int f1, const KBTables &kb, const double *C,
-                    double *cp, hipStream_t s) {
+void launch_kb_quad_theta(const OrbSet &o, int f0, int f1, const KBTables &kb, const double *C,
+                          double *cp, const double *a, const double *bp, const double *inv,
+                          double *cs, double *sn, hipStream_t s) {
   const long long nb = o.nb(f0, f1);
   if (nb <= 0) return;
-  hipLaunchKernelGGL(k_kb_quad, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s, o.b0(f0), nb,
-                     o.band_frag, o.moff, kb.A, kb.A_max, o.m_pad, kb.E, C, cp);
+  hipLaunchKernelGGL(k_kb_quad_theta, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s, o.b0(f0),
+                     nb, o.band_frag, o.moff, kb.A, kb.A_max, o.m_pad, kb.E, C, cp, a, bp, inv,
+                     cs, sn);
 }
 
 }  // namespace dcdft
