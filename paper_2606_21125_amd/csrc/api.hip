@@ -330,9 +330,11 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
     // of the rotated (not yet re-orthonormalised) arrays
     const bool with_m = fuse || last;
     {
-      Timed t(c, DCDFT_KERNEL_GRAM_FUSED, 6.0 * sz * n * nb, (with_m ? 3.0 : 1.0) * n * m2);
+      Timed t(c, DCDFT_KERNEL_GRAM_FUSED, (last ? 5.0 : 6.0) * sz * n * nb,
+              (with_m ? 3.0 : 1.0) * n * m2);
+      // after the last sweep W is not used (the next step rebuilds it)
       launch_gram_update<T>(g, o, f0, f1, ch, psi, p, w, q, c->d_cos, c->d_sin, gpart_at(c, f0), s,
-                            with_m ? gpart2_at(c, f0) : nullptr);
+                            with_m ? gpart2_at(c, f0) : nullptr, !last);
     }
     if (!with_m) {
       launch_gram_reduce(g, o, f0, f1, ch, 1, gpart_at(c, f0), c->d_s, nullptr, nullptr, s);

@@ -265,11 +265,13 @@ void launch_gram_direction(const Geo &g, const OrbSet &o, int f0, int f1, int ch
                            const T *psi, const T *gres, T *p, const double *beta, double *part,
                            hipStream_t s);
 // Psi <- cs Psi + sn P, W <- cs W + sn Q (in place), symmetric Gram partials of Psi;
-// with part_m also the partials of the full product <Psi, W> (same layout)
+// with part_m also the partials of the full product <Psi, W> (same layout), and
+// then store_w = false leaves W unwritten (only its product is needed)
 template <typename T>
 void launch_gram_update(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, T *psi,
                         const T *p, T *w, const T *q, const double *cs, const double *sn,
-                        double *part, hipStream_t s, double *part_m = nullptr);
+                        double *part, hipStream_t s, double *part_m = nullptr,
+                        bool store_w = true);
 // G = dV sum of chunk partials (sym: X == Y, lower tiles mirrored); Gs = sym(G) if
 // not null; diag -> per-band (may be null)
 void launch_gram_reduce(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int sym,

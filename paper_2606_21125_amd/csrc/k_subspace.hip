@@ -421,7 +421,7 @@ __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(MODE == GM_UPDATE_M ? 3 : (sizeof(T) == 4 || TM < 5 ? 4 : 2), 8)))
 k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a2, T *a3,
         const T *a4, const double *__restrict__ c1, const double *__restrict__ c2,
-        double *__restrict__ part, double *__restrict__ part2) {
+        double *__restrict__ part, double *__restrict__ part2, int store_w) {
   typedef Mfma<T> MM;
   constexpr int MP = 16 * TM;
   constexpr bool UPM = MODE == GM_UPDATE_M;   // second (full) product X^T Y into part2
@@ -565,13 +565,13 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a
         const T *v0 = MODE == GM_DIR ? yv : xv;
         if (VEC && p + 3 < p_end) {
           Vec4Load<T>::store(d0 + ro + p, v0);
-          if (MODE >= GM_UPDATE) Vec4Load<T>::store(a3 + ro + p, yv);
+          if (MODE >= GM_UPDATE && store_w) Vec4Load<T>::store(a3 + ro + p, yv);
         } else {
 #pragma unroll
           for (int t = 0; t < 4; ++t)
             if (p + t < p_end) {
               d0[ro + p + t] = v0[t];
-              if (MODE >= GM_UPDATE) a3[ro + p + t] = yv[t];
+              if (MODE >= GM_UPDATE && store_w) a3[ro + p + t] = yv[t];
             }
         }
       }
@@ -763,7 +763,7 @@ __global__ void __launch_bounds__(256) k_cholinv(OrbSet o, int f0, const double 
         if (threadIdx.x == 0) bad = 1;
         d = 1.0;
       }
-      const double rdk = 1.0 / sqrt(d);
+      const double rdk = rsqrt_f64(d);
       double li[NT], lj[NT], xk[NT];
 #pragma unroll
       for (int q = 0; q < NT; ++q) {
@@ -957,9 +957,14 @@ __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *_
         if (q < mf) {
           const double apq = A[p * ld + q];
           if (apq != 0.0) {
-            const double tau = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
+            // t = sign(tau) / (|tau| + sqrt(1 + tau^2)), c = 1 / sqrt(1 + t^2), s = t c
+            // (|tau| > 1e100: t = 1 / (2 tau), where 1 + tau^2 would overflow)
+            const double tau = (A[q * ld + q] - A[p * ld + p]) * rcp_f64(2.0 * apq);
+            const double x = fma(tau, tau, 1.0);
+            const double t = fabs(tau) > 1e100
+                                 ? 0.5 * rcp_f64(tau)
+                                 : (tau >= 0.0 ? 1.0 : -1.0) * rcp_f64(fabs(tau) + x * rsqrt_f64(x));
+            c = rsqrt_f64(fma(t, t, 1.0));
             s = t * c;
           }
         }
@@ -1081,29 +1086,29 @@ __global__ void k_copy(long long b0, long long nb, const double *__restrict__ sr
 template <typename T, int TM, int MODE, bool SYM>
 void gram3_t(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int kchunk, T *x, T *a1,
              const T *a2, T *a3, const T *a4, const double *c1, const double *c2, double *part,
-             double *part2, hipStream_t s) {
+             double *part2, int store_w, hipStream_t s) {
   const dim3 grid((f1 - f0) * chunks), block(256);
   if ((g.n % 4) == 0)
     hipLaunchKernelGGL((k_gram3<T, TM, MODE, SYM, true>), grid, block, 0, s, g, o, f0, chunks,
-                       kchunk, x, a1, a2, a3, a4, c1, c2, part, part2);
+                       kchunk, x, a1, a2, a3, a4, c1, c2, part, part2, store_w);
   else
     hipLaunchKernelGGL((k_gram3<T, TM, MODE, SYM, false>), grid, block, 0, s, g, o, f0, chunks,
-                       kchunk, x, a1, a2, a3, a4, c1, c2, part, part2);
+                       kchunk, x, a1, a2, a3, a4, c1, c2, part, part2, store_w);
 }
 
 template <typename T, int MODE, bool SYM>
 void gram3_tm(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, T *x, T *a1,
               const T *a2, T *a3, const T *a4, const double *c1, const double *c2, double *part,
-              hipStream_t s, double *part2 = nullptr) {
+              hipStream_t s, double *part2 = nullptr, int store_w = 1) {
   if (f1 <= f0) return;
   int kc = (g.n + chunks - 1) / chunks;
   kc = ((kc + kGramKT - 1) / kGramKT) * kGramKT;
   switch (o.tiles) {
-    case 1: gram3_t<T, 1, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, s); break;
-    case 2: gram3_t<T, 2, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, s); break;
-    case 3: gram3_t<T, 3, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, s); break;
-    case 4: gram3_t<T, 4, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, s); break;
-    default: gram3_t<T, 5, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, s); break;
+    case 1: gram3_t<T, 1, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, store_w, s); break;
+    case 2: gram3_t<T, 2, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, store_w, s); break;
+    case 3: gram3_t<T, 3, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, store_w, s); break;
+    case 4: gram3_t<T, 4, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, store_w, s); break;
+    default: gram3_t<T, 5, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, store_w, s); break;
   }
 }
 
@@ -1173,10 +1178,10 @@ void launch_gram_direction(const Geo &g, const OrbSet &o, int f0, int f1, int ch
 template <typename T>
 void launch_gram_update(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, T *psi,
                         const T *p, T *w, const T *q, const double *cs, const double *sn,
-                        double *part, hipStream_t s, double *part_m) {
+                        double *part, hipStream_t s, double *part_m, bool store_w) {
   if (part_m)
     gram3_tm<T, GM_UPDATE_M, true>(g, o, f0, f1, chunks, psi, const_cast<T *>(p), nullptr, w, q,
-                                   cs, sn, part, s, part_m);
+                                   cs, sn, part, s, part_m, store_w ? 1 : 0);
   else
     gram3_tm<T, GM_UPDATE, true>(g, o, f0, f1, chunks, psi, const_cast<T *>(p), nullptr, w, q,
                                  cs, sn, part, s);
@@ -1263,7 +1268,7 @@ void launch_rot_ritz(const Geo &g, const OrbSet &o, int f0, int f1, const double
                                          const T *, T *, const double *, double *, hipStream_t); \
   template void launch_gram_update<T>(const Geo &, const OrbSet &, int, int, int, T *, const T *, \
                                       T *, const T *, const double *, const double *, double *,  \
-                                      hipStream_t, double *);                                 \
+                                      hipStream_t, double *, bool);                           \
   template void launch_rot_residual<T>(const Geo &, const OrbSet &, int, int, const double *,    \
                                        const T *, const T *, T *, double *, double *,            \
                                        hipStream_t, int, double *, double *);                 \
