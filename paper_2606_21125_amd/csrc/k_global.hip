@@ -252,6 +252,47 @@ __global__ void __launch_bounds__(256) k_axis_transform(long long total, int n, 
   }
 }
 
+// The same contraction on the FP64 matrix cores, for n % 16 == 0 and C % 16 == 0
+// (or C == 1 with A % 16 == 0): one wave per 16 x 16 output tile.  C > 1: tile
+// (a, k0, c0) of Out_a = Q^T In_a with In_a = in[a][.][.] (n x C); C == 1: tile
+// (a0, k0) of Out = In Q with In = in[.][.] (A x n).  Each step takes 4 of the n
+// contracted indices, one per lane group.
+__global__ void __launch_bounds__(256) k_axis_mfma(long long A, int n, long long C,
+                                                   const double *__restrict__ in,
+                                                   const double *__restrict__ Q,
+                                                   double *__restrict__ out) {
+  typedef Mfma<double> MM;
+  const long long tile = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, r = lane & 15, kk = lane >> 4;
+  const long long nkt = n / 16;
+  const long long ntc = C > 1 ? C / 16 : A / 16;   // column tiles (C > 1) or row tiles
+  if (tile >= nkt * ntc * (C > 1 ? A : 1)) return;  // wave-uniform
+  MM::acc_t acc = MM::zero();
+  if (C > 1) {
+    const long long a = tile / (nkt * ntc);
+    const long long rem = tile % (nkt * ntc);
+    const int k0 = (int)(rem / ntc) * 16;
+    const long long c0 = (rem % ntc) * 16;
+    const double *ia = in + a * n * C + c0 + r;
+    for (int j = 0; j < n; j += 4) {
+      // A = Q^T (16 k x 4 j), B = In_a (4 j x 16 c)
+      acc = MM::mma(Q[(long long)(j + kk) * n + k0 + r], ia[(long long)(j + kk) * C], acc);
+    }
+    double *oa = out + a * n * C + c0 + r;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) oa[(long long)(k0 + MM::row(kk, q)) * C] = acc[q];
+  } else {
+    const long long a0 = (tile / nkt) * 16;
+    const int k0 = (int)(tile % nkt) * 16;
+    for (int j = 0; j < n; j += 4) {
+      // A = In (16 a x 4 j), B = Q (4 j x 16 k)
+      acc = MM::mma(in[(a0 + r) * n + j + kk], Q[(long long)(j + kk) * n + k0 + r], acc);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[(a0 + MM::row(kk, q)) * n + k0 + r] = acc[q];
+  }
+}
+
 // V_hat = -4 pi rho_hat / (lx + ly + lz), zero for the constant mode
 __global__ void __launch_bounds__(256) k_poisson_scale(Geo g, const double *__restrict__ lx,
                                                        const double *__restrict__ ly,
@@ -358,6 +399,22 @@ void launch_frag_mix(const Geo &g, int nfrag, double *rhof_in, const double *rho
                      rhof_out, mixing);
 }
 
+// out = in contracted with Q (n x n) along the axis of stride C; matrix cores
+// when the shape allows it.
+static void axis_transform(long long Ng, int n, long long C, const double *in, const double *Q,
+                           double *out, hipStream_t s) {
+  const long long A = Ng / ((long long)n * C);
+  const bool tiles = n % 16 == 0 && (C > 1 ? C % 16 == 0 : A % 16 == 0);
+  if (tiles) {
+    const long long nt = (long long)(n / 16) * (C > 1 ? A * (C / 16) : A / 16);
+    hipLaunchKernelGGL(k_axis_mfma, dim3((unsigned)((nt + 3) / 4)), dim3(256), 0, s, A, n, C, in,
+                       Q, out);
+  } else {
+    hipLaunchKernelGGL(k_axis_transform, dim3(grid_for(Ng, 256)), dim3(256), 0, s, Ng, n, C, in,
+                       Q, out);
+  }
+}
+
 void launch_poisson(const Geo &g, const double *rho, double *vh, double *wa, double *wb,
                     double *const qf[3], double *const qi[3], double *const lam[3],
                     hipStream_t s) {
@@ -365,17 +422,13 @@ void launch_poisson(const Geo &g, const double *rho, double *vh, double *wa, dou
   const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
   const int gb = grid_for(Ng, 256);
   // forward: x (C = 1), y (C = Nx), z (C = Nx Ny)
-  hipLaunchKernelGGL(k_axis_transform, dim3(gb), dim3(256), 0, s, Ng, Nx, 1LL, rho, qf[0], wa);
-  hipLaunchKernelGGL(k_axis_transform, dim3(gb), dim3(256), 0, s, Ng, Ny, (long long)Nx, wa, qf[1],
-                     wb);
-  hipLaunchKernelGGL(k_axis_transform, dim3(gb), dim3(256), 0, s, Ng, Nz, (long long)Nx * Ny, wb,
-                     qf[2], wa);
+  axis_transform(Ng, Nx, 1LL, rho, qf[0], wa, s);
+  axis_transform(Ng, Ny, (long long)Nx, wa, qf[1], wb, s);
+  axis_transform(Ng, Nz, (long long)Nx * Ny, wb, qf[2], wa, s);
   hipLaunchKernelGGL(k_poisson_scale, dim3(gb), dim3(256), 0, s, g, lam[0], lam[1], lam[2], wa);
-  hipLaunchKernelGGL(k_axis_transform, dim3(gb), dim3(256), 0, s, Ng, Nz, (long long)Nx * Ny, wa,
-                     qi[2], wb);
-  hipLaunchKernelGGL(k_axis_transform, dim3(gb), dim3(256), 0, s, Ng, Ny, (long long)Nx, wb, qi[1],
-                     wa);
-  hipLaunchKernelGGL(k_axis_transform, dim3(gb), dim3(256), 0, s, Ng, Nx, 1LL, wa, qi[0], vh);
+  axis_transform(Ng, Nz, (long long)Nx * Ny, wa, qi[2], wb, s);
+  axis_transform(Ng, Ny, (long long)Nx, wb, qi[1], wa, s);
+  axis_transform(Ng, Nx, 1LL, wa, qi[0], vh, s);
 }
 
 void launch_fill(double *p, long long n, double v, hipStream_t s) {
