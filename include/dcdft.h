@@ -228,7 +228,9 @@ dcdft_status dcdft_kernel_time(dcdft_ctx *c, int32_t kernel, int64_t *launches, 
  *   - the Gram products (the point range of a fragment cut into G chunks,
  *     G among half, one, two and four times the default),
  * and keeps the fastest of each for every later step (the step graph is
- * re-captured).  Stencil variants give bitwise-identical results; the tile
+ * re-captured).  Stencil variants are timed with the fused <x, Hx> the sweeps
+ * use; the two fastest are timed again, alternately, before the choice.
+ * Stencil variants give bitwise-identical results; the tile
  * and chunk counts change only the summation order of FP64 partial sums.
  * Call between steps: it overwrites work arrays, never the SCF state.
  * cache_path (may be NULL): a text file of earlier choices, one line per
@@ -255,7 +257,7 @@ dcdft_status dcdft_autotune(dcdft_ctx *c, const char *cache_path, dcdft_tune_inf
 
 /* Read or set the launch shapes directly.  set: hloc_variant DCDFT_HLOC_* (the
  * halo variants need a fragment box of at least 4 x 4 x 8 points), rot_tiles
- * 2, 4 or 8, gram_chunks 1..gram_chunks_max (as get reports it), streams 1 or
+ * 2, 4 or 8, gram_chunks 1..gram_chunks_max (as get reports it), streams
  * 1..4: the batched step's eigensolver runs over `streams` groups of
  * fragments (split at equal orbital counts) on as many streams, forked and
  * joined inside the step (default 2; results do not depend on it); anything

@@ -1482,21 +1482,47 @@ void autotune_t(dcdft_ctx *c, dcdft_tune_info &info) {
   const OrbSet o = c->orbset(0, c->nF);
   T *psi = (T *)c->d_psi, *w = (T *)c->d_w, *q = (T *)c->d_q;
   const int reps = 3;
-  // stencil variants
+  // stencil variants, with the fused <x, Hx> that the sweeps ask for; the two
+  // fastest are then timed again, alternately, and the lower total wins
   double best = 1e300;
   int hv_best = g.hloc_variant;
+  auto time_hloc = [&](int v, int r) {
+    g.hloc_variant = v;
+    return time_launches(
+        c,
+        [&] {
+          launch_hloc<T>(g, o, 0, c->nF, c->d_veff, veff_t<T>(c), psi, w, c->stream, c->d_cc, 0,
+                         c->d_hdot);
+        },
+        r);
+  };
+  int second = -1;
+  double best2 = 1e300;
   for (int v = 0; v < HLOC_NVARIANT; ++v) {
     info.ms_hloc[v] = -1.0;
     if (v != HLOC_PLANE && !hloc_halo_ok(g)) continue;
-    g.hloc_variant = v;
-    const double ms = time_launches(
-        c, [&] { launch_hloc<T>(g, o, 0, c->nF, c->d_veff, veff_t<T>(c), psi, w, c->stream); },
-        reps);
+    const double ms = time_hloc(v, reps);
     info.ms_hloc[v] = ms;
-    if (ms >= 0.0 && ms < best) {
+    if (ms < 0.0) continue;
+    if (ms < best) {
+      if (best < 1e300) {
+        best2 = best;
+        second = hv_best;
+      }
       best = ms;
       hv_best = v;
+    } else if (ms < best2) {
+      best2 = ms;
+      second = v;
     }
+  }
+  if (second >= 0 && second != hv_best) {
+    double t_best = 0.0, t_second = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      t_best += time_hloc(hv_best, 5);
+      t_second += time_hloc(second, 5);
+    }
+    if (t_second < t_best) hv_best = second;
   }
   g.hloc_variant = hv_best;
   // Gram chunk counts (also leaves a finite matrix in d_gtmp for the rotations)
