@@ -129,6 +129,7 @@ dcdft::KBTables dcdft_ctx::kb() const {
   k.NR = NR;
   k.KS = KS;
   k.reg_atom = d_reg_atom;
+  k.reg_nt = d_reg_nt;
   k.ar_ptr = d_ar_ptr;
   k.ar_reg = d_ar_reg;
   k.ar_slot = d_ar_slot;
@@ -623,6 +624,8 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
                            "need %zu bytes of LDS (at most 65536)", ks, kRegion, need));
     }
     std::vector<int> reg_atom((size_t)nF * c->NR * ks, -1);
+    std::vector<int> reg_nt((size_t)nF * c->NR);
+    for (size_t q = 0; q < reg_nt.size(); ++q) reg_nt[q] = ((int)reg_atoms[q].size() + 15) / 16;
     // slot of (fragment, region, atom)
     std::vector<std::vector<std::pair<int, int>>> ar((size_t)nF * c->A_max);
     for (int f = 0; f < nF; ++f)
@@ -644,6 +647,7 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
       ar_ptr[q + 1] = (long long)ar_reg.size();
     }
     HIPTRY(c, upload(c, &c->d_reg_atom, reg_atom));
+    HIPTRY(c, upload(c, &c->d_reg_nt, reg_nt));
     HIPTRY(c, upload(c, &c->d_ar_ptr, ar_ptr));
     HIPTRY(c, upload(c, &c->d_ar_reg, ar_reg));
     HIPTRY(c, upload(c, &c->d_ar_slot, ar_slot));

@@ -98,6 +98,7 @@ struct KBTables {
   int NR;                            // regions per fragment
   int KS;                            // slots per region (multiple of 16)
   const int *reg_atom;               // [F][NR][KS] local atom index or -1
+  const int *reg_nt;                 // [F][NR] slot tiles in use (16 slots each)
   const long long *ar_ptr;           // [F * A_max + 1] into (region, slot) lists
   const int *ar_reg;                 // region of each entry
   const int *ar_slot;                // slot of each entry
@@ -159,7 +160,7 @@ struct dcdft_ctx {
   double *d_pr_sq = nullptr, *d_pr_par = nullptr, *d_E = nullptr;
   double *d_C = nullptr;             // [F][A_max][m_pad] projections
   int NR = 0, KS = 0;
-  int *d_reg_atom = nullptr, *d_ar_reg = nullptr, *d_ar_slot = nullptr;
+  int *d_reg_atom = nullptr, *d_reg_nt = nullptr, *d_ar_reg = nullptr, *d_ar_slot = nullptr;
   long long *d_ar_ptr = nullptr;
   double *d_cpart = nullptr;         // region projection partials [F][NR][KS][m_pad]
 

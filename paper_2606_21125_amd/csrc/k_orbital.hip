@@ -4,6 +4,7 @@
 // generator and the band-energy functional with its gradient.  Orbital arrays
 // are FP64 or FP32 (template T); reductions accumulate in FP64.
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 
@@ -524,6 +525,8 @@ __global__ void __launch_bounds__(256) k_kb_project(Geo g, OrbSet o, KBTables kb
       }
     }
   };
+  // slot tiles that hold atoms in this region (the rest are skipped)
+  const int nt = kb.reg_nt[(long long)f * kb.NR + reg];
   auto beta_chunk = [&](int ch, T *dst) {
     const int q = threadIdx.x % CH, sg = threadIdx.x / CH;
     const int l = pbase + ch * CH + q;
@@ -551,17 +554,27 @@ __global__ void __launch_bounds__(256) k_kb_project(Geo g, OrbSet o, KBTables kb
     const T *cur = bl + (ch & 1) * KSM * BS;
     T bn[JW][NS][4];
     load_x(ch + 1 < NCH ? ch + 1 : ch, bn);
+    // products of the slot tiles in use (nt is uniform: a compile-time count each)
+    auto products = [&](auto kte) {
+      constexpr int KTE = decltype(kte)::value;
 #pragma unroll
-    for (int u = 0; u < NS; ++u)
+      for (int u = 0; u < NS; ++u)
 #pragma unroll
-      for (int st = 0; st < KT; ++st) {
-        T av[4];
-        lds_read4(cur + (st * 16 + r) * BS + u * 16 + 4 * kk, av);
+        for (int st = 0; st < KTE; ++st) {
+          T av[4];
+          lds_read4(cur + (st * 16 + r) * BS + u * 16 + 4 * kk, av);
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+          for (int t = 0; t < 4; ++t)
 #pragma unroll
-          for (int q = 0; q < JW; ++q) acc[st][q] = MM::mma(av[t], bx[q][u][t], acc[st][q]);
-      }
+            for (int q = 0; q < JW; ++q) acc[st][q] = MM::mma(av[t], bx[q][u][t], acc[st][q]);
+        }
+    };
+    if (nt <= 1)
+      products(std::integral_constant<int, 1>());
+    else if (nt == 2)
+      products(std::integral_constant<int, (KT < 2 ? KT : 2)>());
+    else
+      products(std::integral_constant<int, KT>());
     if (ch + 1 < NCH) beta_chunk(ch + 1, bl + ((ch + 1) & 1) * KSM * BS);
     __syncthreads();
 #pragma unroll
@@ -633,6 +646,7 @@ k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
   const int rmax = o.row_pad ? MP - 1 : mf - 1;
   const int row0 = reg * kRegion / nx;
   const int *ra = kb.reg_atom + ((long long)f * kb.NR + reg) * kb.KS;
+  const int nt = kb.reg_nt[(long long)f * kb.NR + reg];   // slot tiles in use
   const double *Cf = C + (long long)f * kb.A_max * o.m_pad;
   const double *Ef = kb.E + (long long)f * kb.A_max;
   for (int e = threadIdx.x; e < KSM * MP; e += blockDim.x) {
@@ -669,7 +683,7 @@ k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
     const int p = reg * kRegion + (wave + 4 * k) * 16 + c;
     const int pc = p < g.n ? p : g.n - 1;
     const int lx = pc % nx, rr0 = pc / nx - row0;
-    // beta of slots 4 st + kk at the lane's point
+    // beta of slots 4 st + kk at the lane's point (slot tiles in use only)
     T bv[KT * 4];
 #pragma unroll
     for (int st = 0; st < KT * 4; ++st) {
@@ -679,13 +693,23 @@ k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
     typename MM::acc_t acc[TM];
 #pragma unroll
     for (int j = 0; j < TM; ++j) acc[j] = MM::zero();
+    // products of the slot tiles in use (nt is uniform: a compile-time count each)
+    auto products = [&](auto kte) {
+      constexpr int KTE = decltype(kte)::value;
 #pragma unroll
-    for (int st = 0; st < KT * 4; ++st) {
+      for (int st = 0; st < KTE * 4; ++st) {
 #pragma unroll
-      for (int jt = 0; jt < TM; ++jt)
-        acc[jt] = MM::mma(ec[(4 * st + kk) * LD + jt * 16 + c], bv[st], acc[jt]);
-      if ((st & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-    }
+        for (int jt = 0; jt < TM; ++jt)
+          acc[jt] = MM::mma(ec[(4 * st + kk) * LD + jt * 16 + c], bv[st], acc[jt]);
+        if ((st & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+    };
+    if (nt <= 1)
+      products(std::integral_constant<int, 1>());
+    else if (nt == 2)
+      products(std::integral_constant<int, (KT < 2 ? KT : 2)>());
+    else
+      products(std::integral_constant<int, KT>());
 #pragma unroll
     for (int jt = 0; jt < TM; ++jt)
 #pragma unroll

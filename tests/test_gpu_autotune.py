@@ -116,8 +116,10 @@ def test_autotune_choice_cache_and_results(tmp_path):
         print("autotune:", t, flush=True)
         assert not t["from_cache"]
         assert t["hloc_variant"] in HLOC_VARIANTS and t["rot_tiles"] in (2, 4, 8)
-        times = [v for v in t["ms_hloc"].values() if v >= 0]
-        assert len(times) == len(HLOC_VARIANTS) and t["ms_hloc"][t["hloc_variant"]] == min(times)
+        times = sorted(v for v in t["ms_hloc"].values() if v >= 0)
+        # the choice is one of the two fastest of the first timing pass (they are
+        # timed again before the choice)
+        assert len(times) == len(HLOC_VARIANTS) and t["ms_hloc"][t["hloc_variant"]] <= times[1]
         t2 = d.dcdft_autotune(cache)
         assert t2["from_cache"]
         for k in ("hloc_variant", "rot_tiles", "gram_chunks"):
