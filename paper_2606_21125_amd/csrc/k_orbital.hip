@@ -532,12 +532,21 @@ __global__ void __launch_bounds__(256) k_kb_project(Geo g, OrbSet o, KBTables kb
     const int l = pbase + ch * CH + q;
     const int lc = l < g.n ? l : g.n - 1;
     const int lx = lc % nx, rr = lc / nx - row0;
+    auto eval = [&](auto kte) {   // the slot tiles in use only
+      constexpr int KTE = decltype(kte)::value;
 #pragma unroll
-    for (int j = 0; j < KSM / SG; ++j) {
-      const int sl = sg + SG * j;
-      const T v = beta_at<T>(sx, syz, par, kb.KS, nx, RR, sl, lx, rr);
-      dst[sl * BS + q] = l < g.n ? v : (T)0;
-    }
+      for (int j = 0; j < 16 * KTE / SG; ++j) {
+        const int sl = sg + SG * j;
+        const T v = beta_at<T>(sx, syz, par, kb.KS, nx, RR, sl, lx, rr);
+        dst[sl * BS + q] = l < g.n ? v : (T)0;
+      }
+    };
+    if (nt <= 1)
+      eval(std::integral_constant<int, 1>());
+    else if (nt == 2)
+      eval(std::integral_constant<int, (KT < 2 ? KT : 2)>());
+    else
+      eval(std::integral_constant<int, KT>());
   };
   T bx[JW][NS][4];
   load_x(0, bx);
@@ -683,19 +692,19 @@ k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
     const int p = reg * kRegion + (wave + 4 * k) * 16 + c;
     const int pc = p < g.n ? p : g.n - 1;
     const int lx = pc % nx, rr0 = pc / nx - row0;
-    // beta of slots 4 st + kk at the lane's point (slot tiles in use only)
-    T bv[KT * 4];
-#pragma unroll
-    for (int st = 0; st < KT * 4; ++st) {
-      const T v = beta_at<T>(sx, syz, par, kb.KS, nx, RR, 4 * st + kk, lx, rr0);
-      bv[st] = p < g.n ? v : (T)0;
-    }
     typename MM::acc_t acc[TM];
 #pragma unroll
     for (int j = 0; j < TM; ++j) acc[j] = MM::zero();
-    // products of the slot tiles in use (nt is uniform: a compile-time count each)
+    // beta of slots 4 st + kk at the lane's point and the products, over the
+    // slot tiles in use (nt is uniform: a compile-time count each)
     auto products = [&](auto kte) {
       constexpr int KTE = decltype(kte)::value;
+      T bv[KTE * 4];
+#pragma unroll
+      for (int st = 0; st < KTE * 4; ++st) {
+        const T v = beta_at<T>(sx, syz, par, kb.KS, nx, RR, 4 * st + kk, lx, rr0);
+        bv[st] = p < g.n ? v : (T)0;
+      }
 #pragma unroll
       for (int st = 0; st < KTE * 4; ++st) {
 #pragma unroll
