@@ -118,7 +118,8 @@ typedef struct {
  * counter ((alpha << 40) | (i << 24) | l) + 1; value = top 53 bits * 2^-53 - 1/2)
  * and Cholesky-orthonormalise them; the input density starts uniform, N_e / volume.
  * Errors: ARG (null or out-of-range field; also when more projectors meet one
- * 256-point region of a fragment box than the projector kernels hold: 96, or
+ * projector region of a fragment box (a block of whole x rows of at most 256
+ * points, or 256 consecutive points) than the projector kernels hold: 96, or
  * fewer where their slot tables would exceed 64 KB of LDS), SHAPE (n_grid %
  * num_fragment != 0 or ncore + 2 b > N), OOM, HIP, NOT_SPD.  On success *out owns
  * all device memory. */

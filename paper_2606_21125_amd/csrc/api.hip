@@ -130,6 +130,9 @@ dcdft::KBTables dcdft_ctx::kb() const {
   k.KS = KS;
   k.reg_atom = d_reg_atom;
   k.reg_nt = d_reg_nt;
+  k.RY = RY;
+  k.RZ = RZ;
+  k.RP = RP;
   k.ar_ptr = d_ar_ptr;
   k.ar_reg = d_ar_reg;
   k.ar_slot = d_ar_slot;
@@ -588,22 +591,40 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
   c->A = Acount;
   c->A_max = 1;
   for (int f = 0; f < nF; ++f) c->A_max = std::max(c->A_max, Acount[f]);
-  // regions: kRegion consecutive local points; each lists the fragment atoms
-  // whose support meets it (sorted, padded to KS slots)
-  c->NR = (g.n + kRegion - 1) / kRegion;
+  // regions: blocks of whole x rows (RY rows by RZ planes, RP = nx RY RZ points,
+  // a multiple of 64 and at most kRegion) where the box allows, else kRegion
+  // consecutive local points; each lists the fragment atoms whose support meets
+  // it (sorted, padded to KS slots)
+  c->RY = 0;
+  c->RZ = 0;
+  c->RP = kRegion;
+  for (int ry : {4, 2, 1})
+    for (int rz : {2, 1}) {
+      const int rp = g.nl[0] * ry * rz;
+      if (rp <= kRegion && rp % 64 == 0 && g.nl[1] % ry == 0 && g.nl[2] % rz == 0 &&
+          (c->RY == 0 || rp > c->RP)) {
+        c->RY = ry;
+        c->RZ = rz;
+        c->RP = rp;
+      }
+    }
+  auto region_of = [&](int l) {
+    if (c->RY == 0) return l / kRegion;
+    const int ly = (l / g.nl[0]) % g.nl[1], lz = l / (g.nl[0] * g.nl[1]);
+    return ly / c->RY + (g.nl[1] / c->RY) * (lz / c->RZ);
+  };
+  c->NR = c->RY ? (g.nl[1] / c->RY) * (g.nl[2] / c->RZ) : (g.n + kRegion - 1) / kRegion;
   {
     std::vector<std::vector<int>> reg_atoms((size_t)nF * c->NR);
     for (int P = 0; P < c->n_pairs; ++P) {
       const int f = pair_frag[P];
-      int last = -1;
       std::vector<char> seen(c->NR, 0);
       for (long long e = pair_ptr[P]; e < pair_ptr[P + 1]; ++e) {
-        const int r = atom_l[e] / kRegion;
+        const int r = region_of(atom_l[e]);
         if (!seen[r]) {
           seen[r] = 1;
           reg_atoms[(size_t)f * c->NR + r].push_back(pair_atom[P]);
         }
-        (void)last;
       }
     }
     int ks = 16;
@@ -612,7 +633,7 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
     if (ks > 16 * kMaxSlotTiles)
       return set_err(c, DCDFT_ERR_ARG,
                      fmt("%d projectors meet one %d-point region; at most %d are supported", ks,
-                         kRegion, 16 * kMaxSlotTiles));
+                         c->RP, 16 * kMaxSlotTiles));
     c->KS = ks;
     {
       const size_t elem = c->precision == DCDFT_PREC_MIXED ? sizeof(float) : sizeof(double);
@@ -621,7 +642,7 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
       if (need > 65536)
         return set_err(c, DCDFT_ERR_ARG,
                        fmt("%d projectors meet one %d-point region: the projector kernels would "
-                           "need %zu bytes of LDS (at most 65536)", ks, kRegion, need));
+                           "need %zu bytes of LDS (at most 65536)", ks, c->RP, need));
     }
     std::vector<int> reg_atom((size_t)nF * c->NR * ks, -1);
     std::vector<int> reg_nt((size_t)nF * c->NR);

@@ -83,10 +83,13 @@ struct OrbSet {           // flattened orbital layout [M_tot][n]
   long long nb(int f0, int f1) const { return h_moff[f1] - h_moff[f0]; }
 };
 
-// Projector regions: each fragment's points are cut into regions of kRegion
-// consecutive points; a region lists the KS (padded) fragment atoms whose
-// support meets it.  The beta values are not stored: the kernels evaluate
-// beta_a(l) = sc_a exp(-r2 / (2 sigma_a^2)) on r2 <= rcut_a^2, with
+// Projector regions: each fragment's points are cut into regions of at most
+// kRegion points, each listing the KS (padded) fragment atoms whose support
+// meets it.  Block regions (RY > 0) are whole x rows times RY rows times RZ
+// planes (RP = nx RY RZ points, a multiple of 64), compact enough that a
+// region rarely meets more than 16 atoms; otherwise (RY = 0) a region is
+// kRegion consecutive points.  The beta values are not stored: the kernels
+// evaluate beta_a(l) = sc_a exp(-r2 / (2 sigma_a^2)) on r2 <= rcut_a^2, with
 // r2 = (dz^2 + dy^2) + dx^2 taken from per-pair tables of squared offsets.
 constexpr int kRegion = 256;
 constexpr int kMaxSlotTiles = 6;    // KS_max <= 96 slots per region
@@ -97,6 +100,8 @@ struct KBTables {
   int A_max;
   int NR;                            // regions per fragment
   int KS;                            // slots per region (multiple of 16)
+  int RY, RZ;                        // block regions: rows and planes (RY = 0: linear)
+  int RP;                            // points per region
   const int *reg_atom;               // [F][NR][KS] local atom index or -1
   const int *reg_nt;                 // [F][NR] slot tiles in use (16 slots each)
   const long long *ar_ptr;           // [F * A_max + 1] into (region, slot) lists
@@ -159,7 +164,7 @@ struct dcdft_ctx {
   int *d_A = nullptr, *d_pair_frag = nullptr, *d_pair_atom = nullptr, *d_pair_first = nullptr;
   double *d_pr_sq = nullptr, *d_pr_par = nullptr, *d_E = nullptr;
   double *d_C = nullptr;             // [F][A_max][m_pad] projections
-  int NR = 0, KS = 0;
+  int NR = 0, KS = 0, RY = 0, RZ = 0, RP = 256;
   int *d_reg_atom = nullptr, *d_reg_nt = nullptr, *d_ar_reg = nullptr, *d_ar_slot = nullptr;
   long long *d_ar_ptr = nullptr;
   double *d_cpart = nullptr;         // region projection partials [F][NR][KS][m_pad]

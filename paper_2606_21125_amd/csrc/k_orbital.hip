@@ -400,14 +400,52 @@ __device__ inline void load4_aligned<double>(const double *p, double *d) {
   d[0] = a.x; d[1] = a.y; d[2] = b.x; d[3] = b.y;
 }
 
+// Rows (runs of nx points) of a projector region.
+__device__ inline int region_nrows(const Geo &g, const KBTables &kb) {
+  return kb.RY ? kb.RY * kb.RZ : region_rows(g.nl[0]);
+}
+// (ly, lz) of row rr of region reg (rows past the box of the last linear
+// region map to a valid row; their points are masked)
+__device__ inline void region_row(const Geo &g, const KBTables &kb, int reg, int rr, int &ly,
+                                  int &lz) {
+  const int ny = g.nl[1];
+  if (kb.RY) {
+    const int nyr = ny / kb.RY;
+    ly = (reg % nyr) * kb.RY + rr % kb.RY;
+    lz = (reg / nyr) * kb.RZ + rr / kb.RY;
+  } else {
+    const int row = reg * kRegion / g.nl[0] + rr;
+    ly = row % ny;
+    lz = min(row / ny, g.nl[2] - 1);
+  }
+}
+// Local point of region-local index q, with its x and region row (q < RP;
+// linear regions: the result may pass the box, x and row are then clamped)
+__device__ inline int region_point(const Geo &g, const KBTables &kb, int reg, int q, int &lx,
+                                   int &rr) {
+  const int nx = g.nl[0];
+  if (kb.RY) {
+    lx = q % nx;
+    rr = q / nx;
+    int ly, lz;
+    region_row(g, kb, reg, rr, ly, lz);
+    return lx + nx * (ly + g.nl[1] * lz);
+  }
+  const int l = reg * kRegion + q;
+  const int lc = l < g.n ? l : g.n - 1;
+  lx = lc % nx;
+  rr = lc / nx - reg * kRegion / nx;
+  return l;
+}
+
 // Slot tables of one projector region in LDS: sx[KS][nx] (squared x offsets of
-// the slot's atom), syz[KS][RR] (dz^2 + dy^2 of the region's rows, row0 + rr),
-// sc, c2, r2c [KS] (normalisation, 1 / (2 sigma^2), rcut^2).  An empty slot
-// gets rcut^2 = -1, so every point lies outside its support.
+// the slot's atom), syz[KS][RR] (dz^2 + dy^2 of the region's rows), sc, c2, r2c
+// [KS] (normalisation, 1 / (2 sigma^2), rcut^2).  An empty slot gets
+// rcut^2 = -1, so every point lies outside its support.
 __device__ inline void stage_region(const Geo &g, const KBTables &kb, int f, int reg, double *sx,
                                     double *syz, double *par) {
   const int nx = g.nl[0], ny = g.nl[1], nls = g.nl[0] + g.nl[1] + g.nl[2];
-  const int RR = region_rows(nx), row0 = reg * kRegion / nx;
+  const int RR = region_nrows(g, kb);
   const int *ra = kb.reg_atom + ((long long)f * kb.NR + reg) * kb.KS;
   const int pf = kb.pair_first[f];
   for (int e = threadIdx.x; e < kb.KS * nx; e += blockDim.x) {
@@ -416,9 +454,8 @@ __device__ inline void stage_region(const Geo &g, const KBTables &kb, int f, int
   }
   for (int e = threadIdx.x; e < kb.KS * RR; e += blockDim.x) {
     const int a = ra[e / RR];
-    // rows past the box (last region) only meet masked points
-    const int row = row0 + e % RR;
-    const int ly = row % ny, lz = min(row / ny, g.nl[2] - 1);
+    int ly, lz;
+    region_row(g, kb, reg, e % RR, ly, lz);
     double v = 0.0;
     if (a >= 0) {
       const double *q = kb.pr_sq + (long long)(pf + a) * nls;
@@ -441,7 +478,7 @@ __device__ inline void stage_region(const Geo &g, const KBTables &kb, int f, int
   }
 }
 
-// beta of slot s at the point (lx, row0 + rr): sc exp(-r2 c2) on r2 <= rcut^2,
+// beta of slot s at the point (lx, region row rr): sc exp(-r2 c2) on r2 <= rcut^2,
 // r2 = (dz^2 + dy^2) + dx^2 in FP64 (the support test is exact); FP32 arrays
 // take the exponential in FP32.
 template <typename T>
@@ -480,13 +517,13 @@ __global__ void __launch_bounds__(256) k_kb_project(Geo g, OrbSet o, KBTables kb
   constexpr int MP = 16 * TM;
   constexpr int KSM = 16 * KT;
   constexpr int CH = kb_chunk<T>();
-  constexpr int NCH = kRegion / CH;
   constexpr int NS = CH / 16;                  // 16-point steps per chunk
   constexpr int BS = CH + 16 / (int)sizeof(T); // beta row stride (16-byte rows, skewed)
   constexpr int SG = 256 / CH;                 // slot groups of the evaluation
   constexpr int JW = (TM + 3) / 4;             // orbital tiles per wave
   extern __shared__ __attribute__((aligned(16))) double kb_lds[];
-  const int nx = g.nl[0], RR = region_rows(nx);
+  const int nx = g.nl[0], RR = region_nrows(g, kb);
+  const int NCH = kb.RP / CH;
   double *sx = kb_lds, *syz = sx + kb.KS * nx, *par = syz + kb.KS * RR;
   T *bl = reinterpret_cast<T *>(par + 3 * kb.KS);   // [2][KSM][BS]
   const int f = f0 + blockIdx.x / kb.NR;
@@ -495,7 +532,6 @@ __global__ void __launch_bounds__(256) k_kb_project(Geo g, OrbSet o, KBTables kb
   const int r = lane & 15, kk = lane >> 4;
   const int mf = o.m[f];
   const int rmax = o.row_pad ? MP - 1 : mf - 1;
-  const int pbase = reg * kRegion, row0 = pbase / nx;
   const long long base = o.moff[f] * (long long)g.n;
   auto load_x = [&](int ch, T (*bx)[NS][4]) {
 #pragma unroll
@@ -506,7 +542,10 @@ __global__ void __launch_bounds__(256) k_kb_project(Geo g, OrbSet o, KBTables kb
       const T *row = x + base + (long long)(orb < rmax ? orb : rmax) * g.n;
 #pragma unroll
       for (int u = 0; u < NS; ++u) {
-        const int pu = pbase + ch * CH + u * 16 + 4 * kk;
+        // four consecutive region points lie in one x run (nx % 4 == 0 for
+        // block regions), so they are consecutive local points
+        int lx0, rr0;
+        const int pu = region_point(g, kb, reg, ch * CH + u * 16 + 4 * kk, lx0, rr0);
         if (VEC) {
           // n % 4 == 0 and pu % 4 == 0: the run lies wholly inside or outside
           const int pc = pu < g.n ? pu : g.n - 4;
@@ -529,9 +568,8 @@ __global__ void __launch_bounds__(256) k_kb_project(Geo g, OrbSet o, KBTables kb
   const int nt = kb.reg_nt[(long long)f * kb.NR + reg];
   auto beta_chunk = [&](int ch, T *dst) {
     const int q = threadIdx.x % CH, sg = threadIdx.x / CH;
-    const int l = pbase + ch * CH + q;
-    const int lc = l < g.n ? l : g.n - 1;
-    const int lx = lc % nx, rr = lc / nx - row0;
+    int lx, rr;
+    const int l = region_point(g, kb, reg, ch * CH + q, lx, rr);
     auto eval = [&](auto kte) {   // the slot tiles in use only
       constexpr int KTE = decltype(kte)::value;
 #pragma unroll
@@ -643,9 +681,9 @@ k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
   constexpr int MP = 16 * TM;
   constexpr int LD = lds_stride(MP);
   constexpr int KSM = 16 * KT;
-  constexpr int NU = kRegion / 16 / 4;  // tiles per wave
   extern __shared__ __attribute__((aligned(16))) double kb_lds[];
-  const int nx = g.nl[0], RR = region_rows(nx);
+  const int nx = g.nl[0], RR = region_nrows(g, kb);
+  const int NU = kb.RP / 16 / 4;  // tiles per wave
   double *sx = kb_lds, *syz = sx + kb.KS * nx, *par = syz + kb.KS * RR;
   T *ec = reinterpret_cast<T *>(par + 3 * kb.KS);   // [KSM][LD]
   const int f = f0 + blockIdx.x / kb.NR;
@@ -653,7 +691,6 @@ k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mf = o.m[f];
   const int rmax = o.row_pad ? MP - 1 : mf - 1;
-  const int row0 = reg * kRegion / nx;
   const int *ra = kb.reg_atom + ((long long)f * kb.NR + reg) * kb.KS;
   const int nt = kb.reg_nt[(long long)f * kb.NR + reg];   // slot tiles in use
   const double *Cf = C + (long long)f * kb.A_max * o.m_pad;
@@ -677,7 +714,8 @@ k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
     return y + base + (long long)(orb < rmax ? orb : rmax) * g.n + pc;
   };
   auto load_y = [&](int k, T (*yv)[4]) {
-    const int p = reg * kRegion + (wave + 4 * k) * 16 + c;
+    int lx, rr;
+    const int p = region_point(g, kb, reg, (wave + 4 * k) * 16 + c, lx, rr);
     const int pc = p < g.n ? p : g.n - 1;
 #pragma unroll
     for (int jt = 0; jt < TM; ++jt)
@@ -689,9 +727,8 @@ k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
   for (int k = 0; k < NU; ++k) {
     T yn[TM][4];
     load_y(k + 1 < NU ? k + 1 : k, yn);
-    const int p = reg * kRegion + (wave + 4 * k) * 16 + c;
-    const int pc = p < g.n ? p : g.n - 1;
-    const int lx = pc % nx, rr0 = pc / nx - row0;
+    int lx, rr0;
+    const int p = region_point(g, kb, reg, (wave + 4 * k) * 16 + c, lx, rr0);
     typename MM::acc_t acc[TM];
 #pragma unroll
     for (int j = 0; j < TM; ++j) acc[j] = MM::zero();
