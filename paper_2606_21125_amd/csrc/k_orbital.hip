@@ -658,7 +658,20 @@ __global__ void __launch_bounds__(256) k_kb_reduce(Geo g, OrbSet o, KBTables kb,
   const long long fa = (long long)f0 * kb.A_max + idx / o.m_pad;
   const int f = (int)(fa / kb.A_max);
   double s = 0.0;
-  for (long long e = kb.ar_ptr[fa]; e < kb.ar_ptr[fa + 1]; ++e) {
+  // four entries in flight at a time, added in entry order
+  long long e = kb.ar_ptr[fa];
+  const long long e1 = kb.ar_ptr[fa + 1];
+  for (; e + 4 <= e1; e += 4) {
+    double v[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const long long q = ((long long)f * kb.NR + kb.ar_reg[e + t]) * kb.KS + kb.ar_slot[e + t];
+      v[t] = (double)part[q * o.m_pad + i];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) s += v[t];
+  }
+  for (; e < e1; ++e) {
     const long long q = ((long long)f * kb.NR + kb.ar_reg[e]) * kb.KS + kb.ar_slot[e];
     s += (double)part[q * o.m_pad + i];
   }

@@ -654,7 +654,16 @@ __global__ void __launch_bounds__(256) k_gram_reduce2(Geo g, OrbSet o, int f0, i
       sj = i;
     }
     const double *pf = part + (long long)fl * chunks * mp * mp + si * mp + sj;
-    for (int q = 0; q < chunks; ++q) s += pf[(long long)q * mp * mp];
+    // eight partials in flight at a time, added in chunk order
+    int q = 0;
+    for (; q + 8 <= chunks; q += 8) {
+      double v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) v[t] = pf[(long long)(q + t) * mp * mp];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) s += v[t];
+    }
+    for (; q < chunks; ++q) s += pf[(long long)q * mp * mp];
   }
   const double v = g.dv * s;
   G[(long long)f * mp * mp + e] = v;
