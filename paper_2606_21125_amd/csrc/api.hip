@@ -313,7 +313,8 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
     // (d)-(e) P = -G + beta P_prev, X = <Psi, P>
     {
       Timed t(c, DCDFT_KERNEL_GRAM_FUSED, 4.0 * sz * n * nb, 2.0 * n * m2);
-      launch_gram_direction<T>(g, o, f0, f1, ch, psi, q, p, c->d_beta, gpart_at(c, f0), s);
+      launch_gram_direction<T>(g, o, f0, f1, ch, psi, q, p, c->d_beta, gpart_at(c, f0), s,
+                               sw == 0);
     }
     launch_gram_reduce(g, o, f0, f1, ch, 0, gpart_at(c, f0), c->d_x, nullptr, nullptr, s);
     // (e)-(f) P <- P - X^T Psi, nu_i = <p_i, p_i> (and 1/sqrt(nu_i)), <p_i, w_i>

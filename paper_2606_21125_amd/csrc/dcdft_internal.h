@@ -265,11 +265,12 @@ void launch_band_energy(const Geo &g, int nb, const T *psi, const T *hpsi, const
 template <typename T>
 void launch_gram(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, const T *x,
                  const T *y, double *part, hipStream_t s);
-// P = beta P - G (in place over P), Gram partials of Psi^T P
+// P = beta P - G (in place over P), Gram partials of Psi^T P; beta_zero: beta is
+// zero for every band (P_prev is not read)
 template <typename T>
 void launch_gram_direction(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
                            const T *psi, const T *gres, T *p, const double *beta, double *part,
-                           hipStream_t s);
+                           hipStream_t s, bool beta_zero = false);
 // Psi <- cs Psi + sn P, W <- cs W + sn Q (in place), symmetric Gram partials of Psi;
 // with part_m also the partials of the full product <Psi, W> (same layout), and
 // then store_w = false leaves W unwritten (only its product is needed)

@@ -492,8 +492,12 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) acc64[k][rr] = 0.0;
   const T *Yl = SYM ? Xs : Ys;
+  // GM_DIR reads P_prev from a1 unless a3 is given (a3 = G when beta is zero
+  // for every band: the read then hits the lines just loaded for G)
   auto src = [&](int a) -> const T * {
-    return a == 0 ? x : (a == 1 ? (MODE == GM_DIR ? a2 : a1) : (a == 2 ? (MODE == GM_DIR ? a1 : a3) : a4));
+    return a == 0 ? x
+                  : (a == 1 ? (MODE == GM_DIR ? a2 : a1)
+                            : (a == 2 ? (MODE == GM_DIR ? (a3 ? a3 : a1) : a3) : a4));
   };
   // Raw operand values of one step, loaded a step ahead of their use.  Rows up
   // to MP exist in the arrays (m_pad spare rows at the end), points outside
@@ -1179,9 +1183,10 @@ void launch_gram(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, cons
 template <typename T>
 void launch_gram_direction(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
                            const T *psi, const T *gres, T *p, const double *beta, double *part,
-                           hipStream_t s) {
-  gram3_tm<T, GM_DIR, false>(g, o, f0, f1, chunks, const_cast<T *>(psi), p, gres, nullptr,
-                             nullptr, beta, nullptr, part, s);
+                           hipStream_t s, bool beta_zero) {
+  gram3_tm<T, GM_DIR, false>(g, o, f0, f1, chunks, const_cast<T *>(psi), p, gres,
+                             beta_zero ? const_cast<T *>(gres) : nullptr, nullptr, beta, nullptr,
+                             part, s);
 }
 
 template <typename T>
@@ -1274,7 +1279,8 @@ void launch_rot_ritz(const Geo &g, const OrbSet &o, int f0, int f1, const double
   template void launch_gram<T>(const Geo &, const OrbSet &, int, int, int, const T *, const T *, \
                                double *, hipStream_t);                                        \
   template void launch_gram_direction<T>(const Geo &, const OrbSet &, int, int, int, const T *,  \
-                                         const T *, T *, const double *, double *, hipStream_t); \
+                                         const T *, T *, const double *, double *, hipStream_t,  \
+                                         bool);                                                \
   template void launch_gram_update<T>(const Geo &, const OrbSet &, int, int, int, T *, const T *, \
                                       T *, const T *, const double *, const double *, double *,  \
                                       hipStream_t, double *, bool);                           \
