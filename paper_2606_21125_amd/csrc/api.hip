@@ -92,8 +92,7 @@ void axis_ball(double center, double radius, double h, int n, double length, std
 }
 
 struct Support {
-  std::vector<long long> g;
-  std::vector<double> v;
+  std::vector<long long> g;   // global grid points of the projector support
 };
 
 }  // namespace
@@ -120,8 +119,6 @@ dcdft::KBTables dcdft_ctx::kb() const {
   k.A_max = A_max;
   k.n_pairs = n_pairs;
   k.A = d_A;
-  k.pair_frag = d_pair_frag;
-  k.pair_atom = d_pair_atom;
   k.pair_first = d_pair_first;
   k.pr_sq = d_pr_sq;
   k.pr_par = d_pr_par;
@@ -678,8 +675,6 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
   for (int f = 0; f < nF; ++f)
     for (size_t a = 0; a < Ef[f].size(); ++a) Eflat[(size_t)f * c->A_max + a] = Ef[f][a];
 
-  HIPTRY(c, upload(c, &c->d_pair_frag, pair_frag));
-  HIPTRY(c, upload(c, &c->d_pair_atom, pair_atom));
   HIPTRY(c, upload(c, &c->d_pair_first, c->pair_first));
   HIPTRY(c, upload(c, &c->d_pr_sq, pr_sq));
   HIPTRY(c, upload(c, &c->d_pr_par, pr_par));

@@ -109,8 +109,6 @@ struct KBTables {
   const int *ar_slot;                // slot of each entry
   int n_pairs;                       // total (fragment, atom) pairs
   const int *A;                      // [F] atoms per fragment
-  const int *pair_frag;              // [n_pairs]
-  const int *pair_atom;              // [n_pairs] local atom index
   const int *pair_first;             // [F + 1] pair of local atom a of f: pair_first[f] + a
   const double *pr_sq;               // [n_pairs][nl0 + nl1 + nl2] squared axis offsets (inf: outside)
   const double *pr_par;              // [n_pairs][3] sc, 1 / (2 sigma^2), rcut^2
@@ -161,7 +159,7 @@ struct dcdft_ctx {
   int *d_band_frag = nullptr;
   // KB
   int n_pairs = 0;
-  int *d_A = nullptr, *d_pair_frag = nullptr, *d_pair_atom = nullptr, *d_pair_first = nullptr;
+  int *d_A = nullptr, *d_pair_first = nullptr;
   double *d_pr_sq = nullptr, *d_pr_par = nullptr, *d_E = nullptr;
   double *d_C = nullptr;             // [F][A_max][m_pad] projections
   int NR = 0, KS = 0, RY = 0, RZ = 0, RP = 256;
@@ -311,8 +309,6 @@ template <typename T>
 void launch_rot_ritz(const Geo &g, const OrbSet &o, int f0, int f1, const double *U, T *psi,
                      double *dpart, double *wcore, hipStream_t s);
 
-void launch_copy_band(const OrbSet &o, int f0, int f1, const double *src, double *dst,
-                      hipStream_t s);
 // cp[B] += sum_a E_a C[f][a][i]^2, then the 2x2 CG step: theta = atan2(-2 inv bp,
 // inv^2 cp - a) / 2 -> cs = cos(theta), sn = inv sin(theta)
 void launch_kb_quad_theta(const OrbSet &o, int f0, int f1, const KBTables &kb, const double *C,

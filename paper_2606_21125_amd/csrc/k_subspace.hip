@@ -1088,14 +1088,6 @@ __global__ void __launch_bounds__(256) k_kb_quad_theta(long long b0, long long n
   }
 }
 
-__global__ void k_copy(long long b0, long long nb, const double *__restrict__ src,
-                       double *__restrict__ dst) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
-  dst[b0 + i] = src[b0 + i];
-}
-
-
 template <typename T, int TM, int MODE, bool SYM>
 void gram3_t(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int kchunk, T *x, T *a1,
              const T *a2, T *a3, const T *a4, const double *c1, const double *c2, double *part,
@@ -1339,15 +1331,6 @@ void launch_syev(const OrbSet &o, int f0, int f1, const double *Hs, double *U, d
   if (f1 <= f0) return;
   hipLaunchKernelGGL(k_syev, dim3(f1 - f0), dim3(1024), 0, s, o, f0, Hs, U, eps, flags);
 }
-
-void launch_copy_band(const OrbSet &o, int f0, int f1, const double *src, double *dst,
-                      hipStream_t s) {
-  const long long nb = o.nb(f0, f1);
-  if (nb <= 0) return;
-  hipLaunchKernelGGL(k_copy, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, o.b0(f0), nb,
-                     src, dst);
-}
-
 
 void launch_kb_quad_theta(const OrbSet &o, int f0, int f1, const KBTables &kb, const double *C,
                           double *cp, const double *a, const double *bp, const double *inv,
