@@ -18,6 +18,13 @@ total density):
      measure dV sum |rho_k^in - rho_(k-1)^in| / N_e (Sec. 3.3).
   8. linear mixing rho^in <- rho^in + a (rho^out - rho^in), applied to the
      total density and to every fragment density.
+
+Fixed-density DC (Sec. 2.6, third usage; Sec. 3.2): rho_tot^in is a density
+read in and stays frozen.  Every iteration re-solves the fragment eigenproblems
+in the potential of that density (steps 1-7 unchanged) and assembles rho^out,
+but step 8 is skipped: neither rho_tot^in nor any rho_alpha^in changes, so the
+paper's residual is zero and rho^out - rho^in measures how far the fragment
+solution is from reproducing the frozen density.
 """
 from __future__ import annotations
 
@@ -136,6 +143,17 @@ class OracleSCF:
         self.mu = None
         self.iteration = 0
         self.workers = workers
+        self.fixed_density = False
+
+    def set_density(self, rho_tot, rho_frag=None):
+        """Replace rho_tot^in; every rho_alpha^in becomes rho_frag[alpha] or, when
+        rho_frag is None, rho_tot^in on the fragment box (periodic images)."""
+        self.rho_in = np.array(rho_tot, dtype=np.float64).reshape(self.n_grid[::-1])
+        flat = self.rho_in.ravel()
+        if rho_frag is None:
+            self.rho_frag_in = [flat[f.global_index].copy() for f in self.frags]
+        else:
+            self.rho_frag_in = [np.array(r, dtype=np.float64).ravel() for r in rho_frag]
 
     def veff(self, alpha: int, v_h: np.ndarray) -> np.ndarray:
         f = self.frags[alpha]
@@ -189,7 +207,7 @@ class OracleSCF:
         e_tot = total_energy(e_band, self.rho_in, v_h, dv, cfg.smearing, ent)
         r_out_in = dv * float(np.sum(np.abs(rho_out - self.rho_in))) / self.ne
         charge = dv * float(np.sum(rho_out))
-        a_mix = cfg.mixing
+        a_mix = 0.0 if self.fixed_density else cfg.mixing
         rho_new = self.rho_in + a_mix * (rho_out - self.rho_in)
         r_paper = dv * float(np.sum(np.abs(rho_new - self.rho_in))) / self.ne
         self.rho_in = rho_new

@@ -127,3 +127,110 @@ def test_dc_step_conserves_charge_and_mixes_consistently():
             np.testing.assert_allclose(rf[f.core_mask], o.rho_in.ravel()[f.global_index[f.core_mask]],
                                        rtol=1e-13, atol=1e-15)
         prev = o.rho_in.copy()
+
+
+# --- fixed-density DC (Sec. 2.6, third usage; Sec. 3.2) ----------------------------------
+
+def _dense_poisson(shape, h, rho):
+    """V_H of rho with the FD Laplacian as a dense matrix (pseudo-inverse, zero mean)."""
+    lap = -2.0 * dense_kinetic(shape, h, og.FD_COEFFS)
+    v = np.linalg.pinv(lap, rcond=1e-12, hermitian=True) @ (-4 * math.pi * (rho - rho.mean()))
+    return v - v.mean()
+
+
+def _fixed_steps(o, n_max=200, tol=1e-12):
+    """Fixed-density iterations until no eigenvalue and no value of rho^out moves by
+    more than tol (the orbitals converge only as the square root of the
+    eigenvalues); checks on the way that nothing of the frozen density changes."""
+    rho0 = o.rho_in.copy()
+    frag0 = [r.copy() for r in o.rho_frag_in]
+    prev = None
+    for _ in range(n_max):
+        info = o.step()
+        assert info["residual_paper"] == 0.0
+        assert np.array_equal(o.rho_in, rho0)
+        assert all(np.array_equal(a, b) for a, b in zip(o.rho_frag_in, frag0))
+        cur = np.concatenate(o.eps + [o.rho_out.ravel()])
+        if prev is not None and np.abs(cur - prev).max() < tol:
+            break
+        prev = cur
+    else:
+        raise AssertionError("fixed-density iterations did not settle")
+    return info
+
+
+def test_fixed_density_at_conventional_density_reproduces_it():
+    """One fragment (b = 0) frozen at the self-consistent density of the dense
+    conventional SCF: the eigenvalues, mu and the output density are those of the
+    dense solution, and rho^out reproduces the frozen density (the density error
+    specific to DC is absent, Sec. 2.6)."""
+    # two more states than the conventional test: a wider gap at the subspace edge
+    # lets the orbitals (not only the eigenvalues) settle within the step budget
+    cfg = tiny_config(n_grid=(10, 10, 10), cell=(6.0, 6.0, 6.0), n_atoms=2, nstate=8,
+                      smearing=0.05, mixing=0.3, sweeps=4)
+    ref = dense_scf(cfg)
+    assert ref["res"] < 1e-11
+    o = oracle.OracleSCF(cfg)
+    o.fixed_density = True
+    o.set_density(ref["rho"])
+    info = _fixed_steps(o)
+    np.testing.assert_allclose(o.eps[0], ref["eps"], rtol=0, atol=1e-9)
+    assert abs(o.mu - ref["mu"]) < 1e-9
+    assert info["residual_out_in"] < 1e-10
+    np.testing.assert_allclose(o.v_h.ravel(), ref["vh"], rtol=0, atol=1e-10)
+
+
+def test_fixed_density_dc_fragments_solve_the_frozen_potential():
+    """Two buffered fragments frozen at an analytic density: every fragment's
+    eigenvalues are the lowest of its own dense Hamiltonian, built here from the
+    frozen density (kinetic on the periodic fragment box, V_loc + V_H + V_xc of the
+    fragment's share of the density, global projectors restricted to the box without
+    renormalisation, Eq. (5)); mu solves the weighted charge equation (Eq. (4))."""
+    cfg = tiny_config(n_grid=(16, 8, 8), cell=(12.0, 6.0, 6.0), n_atoms=4, nstate=8,
+                      num_fragment=(2, 1, 1), buffer=(2, 0, 0), smearing=0.05, valence=2.0)
+    sysm = cfg.system
+    nx, ny, nz = cfg.n_grid
+    h = sysm.cell / np.array(cfg.n_grid)
+    dv = float(np.prod(h))
+    z, y, x = np.meshgrid(np.arange(nz) * h[2], np.arange(ny) * h[1], np.arange(nx) * h[0],
+                          indexing="ij")
+    shape_g = (nz, ny, nx)
+    rho = 1.0 + 0.4 * np.sin(2 * math.pi * x / sysm.cell[0]) * np.cos(2 * math.pi * y / sysm.cell[1]) \
+        + 0.2 * np.cos(2 * math.pi * z / sysm.cell[2])
+    rho *= sysm.n_electrons / (dv * rho.sum())
+    o = oracle.OracleSCF(cfg)
+    o.fixed_density = True
+    o.set_density(rho)
+    _fixed_steps(o, n_max=400)
+
+    vh = _dense_poisson(shape_g, h, rho.ravel())
+    vloc = om.local_potential(sysm, cfg.n_grid).ravel()
+    beta = []
+    for p in om.kb_projectors(sysm, cfg.n_grid):
+        b = np.zeros(nx * ny * nz)
+        b[p.index] = p.value
+        beta.append((p.energy, b))
+    b_buf, ncore = 2, nx // 2
+    lx = np.arange(ncore + 2 * b_buf)
+    eps_all, w_all = [], []
+    for alpha in range(2):
+        gx = (alpha * ncore - b_buf + lx) % nx
+        gidx = (gx[None, None, :] + nx * (np.arange(ny)[None, :, None]
+                                          + ny * np.arange(nz)[:, None, None])).ravel()
+        rf = rho.ravel()[gidx]
+        _, vxc = om.lda_pz81(rf)
+        hm = dense_kinetic((nz, ny, lx.size), h, og.FD_COEFFS) + np.diag(vloc[gidx] + vh[gidx] + vxc)
+        for e, b in beta:
+            bf = b[gidx]
+            hm += e * dv * np.outer(bf, bf)
+        ev = np.linalg.eigvalsh(hm)
+        m = int(cfg.nstate_frag[alpha])
+        assert ev[m] - ev[m - 1] > 1e-3      # a gap at the subspace edge
+        np.testing.assert_allclose(o.eps[alpha], ev[:m], rtol=0, atol=1e-9)
+        eps_all.append(o.eps[alpha])
+        w_all.append(o.w[alpha])
+    eps_all, w_all = np.concatenate(eps_all), np.concatenate(w_all)
+    count = lambda mu: float(np.sum(2 * w_all / (1 + np.exp((eps_all - mu) / cfg.smearing)))) \
+        - sysm.n_electrons
+    mu = scipy.optimize.brentq(count, eps_all.min() - 5, eps_all.max() + 5, xtol=1e-15, rtol=1e-15)
+    assert abs(o.mu - mu) < 1e-10
