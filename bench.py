@@ -121,7 +121,14 @@ def main() -> int:
     ap.add_argument("--copy-probe-mb", type=float, default=0.0,
                     help="run one plain device-to-device copy of this many MB first (a "
                          "reference kernel for scaling HBM counters)")
+    ap.add_argument("--fixed-density", action="store_true",
+                    help="fixed-density DC: freeze rho_tot at a superposition of atomic "
+                         "Gaussians and time the iterations without Poisson, V_eff or "
+                         "mixing updates (no comparison runs, no CPU baseline)")
     args = ap.parse_args()
+    if args.fixed_density:
+        args.no_compare = True
+        args.no_cpu_baseline = True
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         return 2
@@ -150,6 +157,10 @@ def main() -> int:
     print(f"[bench] setup {cfg.name}: {cfg.system.n_atoms} atoms, grid {cfg.n_grid}, "
           f"{cfg.n_fragments} fragments of {cfg.fragment_shape}", file=sys.stderr, flush=True)
     d = DCDFT.from_config(cfg, batched=args.batched, precision=prec)
+    if args.fixed_density:
+        from workloads import superposed_density
+        d.dcdft_set_density(superposed_density(cfg.system, cfg.n_grid))
+        d.dcdft_fix_density(True)
     launch0 = d.dcdft_get_launch()
     tune = None
     if not args.no_autotune:
@@ -261,7 +272,8 @@ def main() -> int:
                                 f"{int(cfg.nstate_frag[0])} orbitals each, "
                                 f"{cfg.cg_sweeps} CG sweeps per SCF iteration"),
                    "n_fragments": cfg.n_fragments, "batched": bool(args.batched),
-                   "precision": args.precision},
+                   "precision": args.precision,
+                   "mode": "fixed-density" if args.fixed_density else "scf"},
         "roofline": roofline, "cpu_baseline": cpu, "comparisons": comparisons, **extra,
     }
     print(json.dumps(out), flush=True)

@@ -170,6 +170,17 @@ dcdft_status dcdft_set_orbitals(dcdft_ctx *c, int32_t frag, const double *host, 
  * rho_alpha^in ([F][n] doubles); with NULL each fragment gathers rho_tot^in. */
 dcdft_status dcdft_set_density(dcdft_ctx *c, const double *rho_tot_in, const double *rho_frag_in);
 
+/* Fixed-density DC (Sec. 2.6, third usage; Sec. 3.2): with fixed = 1 every later
+ * dcdft_scf_step keeps rho_tot^in and each rho_alpha^in as they are (a density read
+ * in, typically with dcdft_set_density from a conventional calculation): V_H and
+ * V_eff are formed once, here, from the current rho^in, and the step runs the
+ * fragment eigensolvers, mu, rho^out, energies and residuals without the Poisson
+ * solve, the V_eff update or the mixing (residual_paper is 0; residual_out_in
+ * measures how far rho^out is from the frozen density).  dcdft_set_density while
+ * fixed re-forms the potentials of the new density.  fixed = 0 restores the SCF
+ * step.  Errors: ARG (fixed not 0 or 1), HIP. */
+dcdft_status dcdft_fix_density(dcdft_ctx *c, int32_t fixed);
+
 /* H^alpha psi for m vectors of fragment frag with its V_eff of the last step
  * (after setup: V_loc + V_xc of the uniform density, V_H = 0), Eq. (5):
  * kinetic (nine-point FD, periodic on the fragment box) + V_eff + V_NL.

@@ -731,10 +731,14 @@ void enqueue_step(dcdft_ctx *c) {
   hipStream_t s = c->stream;
   OrbSet o = c->orbset(0, c->nF);
   launch_fill_int(c->d_flags, 1, 0, s);
-  // 1. Hartree potential of rho_tot^in
-  launch_poisson(g, c->d_rho_in, c->d_vh, c->d_fft_a, c->d_fft_b, c->d_qf, c->d_qi, c->d_lam, s);
-  // 2. fragment effective potentials
-  launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, c->d_veff32, s);
+  // With a frozen density V_H and V_eff were formed when it was fixed or set and
+  // do not change; otherwise:
+  if (!c->fixed_density) {
+    // 1. Hartree potential of rho_tot^in
+    launch_poisson(g, c->d_rho_in, c->d_vh, c->d_fft_a, c->d_fft_b, c->d_qf, c->d_qi, c->d_lam, s);
+    // 2. fragment effective potentials
+    launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, c->d_veff32, s);
+  }
   // 3. fragment eigensolvers
   if (c->batched) {
     auto run = [&](int a, int b) {
@@ -781,10 +785,11 @@ void enqueue_step(dcdft_ctx *c) {
   else
     launch_density<double>(g, o, 0, c->nF, (const double *)c->d_psi, c->d_occ, c->d_rhof_out,
                            c->d_rho_out, s);
-  // 6-8. energy terms, residuals, mixing
-  launch_global_terms(g, c->d_rho_in, c->d_rho_out, c->d_vh, c->mixing, c->d_part, c->n_part,
-                      c->d_scal, s, c->ne, c->smearing);
-  launch_frag_mix(g, c->nF, c->d_rhof_in, c->d_rhof_out, c->mixing, s);
+  // 6-8. energy terms, residuals, mixing (a mixing fraction of 0 leaves a frozen
+  // rho_tot^in bitwise unchanged and makes the paper's residual 0)
+  launch_global_terms(g, c->d_rho_in, c->d_rho_out, c->d_vh, c->fixed_density ? 0.0 : c->mixing,
+                      c->d_part, c->n_part, c->d_scal, s, c->ne, c->smearing);
+  if (!c->fixed_density) launch_frag_mix(g, c->nF, c->d_rhof_in, c->d_rhof_out, c->mixing, s);
   launch_nan_check(c->d_eps, c->M_tot, c->d_flags, s);
   launch_nan_check(c->d_rho_out, g.Ng, c->d_flags, s);
 }
@@ -1292,6 +1297,24 @@ dcdft_status dcdft_set_density(dcdft_ctx *c, const double *rho_tot_in, const dou
   launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, c->d_veff32, c->stream);
   HIPTRY(c, hipGetLastError());
   HIPTRY(c, hipStreamSynchronize(c->stream));
+  return DCDFT_OK;
+}
+
+dcdft_status dcdft_fix_density(dcdft_ctx *c, int32_t fixed) {
+  if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  if (fixed != 0 && fixed != 1) return set_err(c, DCDFT_ERR_ARG, "fixed must be 0 or 1");
+  drop_graph(c);  // the step's launch sequence changes; re-captured on the next step
+  c->fixed_density = fixed != 0;
+  if (c->fixed_density) {
+    // potentials of the density as it stands now (a step leaves rho^in mixed
+    // and V_H, V_eff still those of the density before the mixing)
+    const Geo &g = c->geo;
+    launch_poisson(g, c->d_rho_in, c->d_vh, c->d_fft_a, c->d_fft_b, c->d_qf, c->d_qi, c->d_lam,
+                   c->stream);
+    launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, c->d_veff32, c->stream);
+    HIPTRY(c, hipGetLastError());
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+  }
   return DCDFT_OK;
 }
 

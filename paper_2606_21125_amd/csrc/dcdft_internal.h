@@ -220,6 +220,7 @@ struct dcdft_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   bool use_graph = true;
+  bool fixed_density = false;  // rho^in frozen: no Poisson, V_eff or mixing update in the step
   bool graph_timed = false;
   std::vector<PendingTimer> graph_timers;
 

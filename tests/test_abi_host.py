@@ -125,6 +125,7 @@ def test_null_safe_calls(lib):
     buf = ctypes.create_string_buffer(8)
     assert lib.dcdft_last_error(None, buf, 0) == -1
     assert lib.dcdft_kernel_timing(None, 1) == -1
+    assert lib.dcdft_fix_density(None, 1) == -1
     assert lib.dcdft_autotune(None, None, None) == -1
     assert lib.dcdft_get_launch(None, None, None, None, None, None) == -1
     assert lib.dcdft_set_launch(None, 1, 4, 1, 2) == -1

@@ -193,6 +193,32 @@ def fragment_valence_counts(system: System, n_grid, num_fragment, buffer) -> np.
     return counts
 
 
+def superposed_density(system: System, n_grid, width: float = 1.2,
+                       background: float = 0.25) -> np.ndarray:
+    """Input density of the fixed-density mode, a stand-in for a density read from
+    a file: a fraction 1 - background of every atom's valence charge in a Gaussian
+    of the given width (bohr) centred on the atom (periodic images, cut at 5
+    widths), the rest spread uniformly, then scaled so that dV * sum = N_e on the
+    grid.  Returns (Nz, Ny, Nx), x fastest."""
+    n = np.array(n_grid, dtype=np.int64)
+    h = system.cell / n
+    val = np.array([s.valence for s in system.species])[system.species_index]
+    rho = np.zeros((n[2], n[1], n[0]))
+    for a in range(system.n_atoms):
+        idx, fac = [], []
+        for d in range(3):
+            half = min(int(math.ceil(5.0 * width / h[d])), int((n[d] - 1) // 2))
+            c = int(math.floor(system.positions[a, d] / h[d]))
+            k = np.arange(c - half, c + half + 1)
+            r = k * h[d] - system.positions[a, d]
+            idx.append(np.mod(k, n[d]))
+            fac.append(np.exp(-r * r / (2.0 * width * width)))
+        g = fac[2][:, None, None] * fac[1][None, :, None] * fac[0][None, None, :]
+        rho[np.ix_(idx[2], idx[1], idx[0])] += val[a] * g / g.sum()
+    rho = (1.0 - background) * rho + background * val.sum() / float(n.prod())
+    return rho * (system.n_electrons / (float(np.prod(h)) * rho.sum()))
+
+
 CONFIG_NAMES = {
     1: "si64_fp64",
     2: "asi512",
