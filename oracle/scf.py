@@ -7,7 +7,9 @@ total density):
      same nine-point-per-axis Laplacian: L V_H = -4 pi (rho - mean rho),
      V_H with zero mean (jellium gauge).
   2. V_eff^alpha = V_loc + V_H (gathered from the global grid) + V_xc[rho_alpha^in]
-     (Eq. (5): exchange-correlation from the fragment density; V^alpha = 0).
+     + V^alpha (Eq. (5): exchange-correlation from the fragment density; the
+     density-template potential V^alpha = (rho_alpha^in - rho_tot^in) / xi when a
+     xi > 0 is set, zero by default as in the paper).
   3. fragment eigensolver (``cg_eigensolver``), core weights.
   4. global mu (``fermi_level``).
   5. rho_alpha^out (Eq. (4)); rho_tot^out = sum_alpha core-projected rho_alpha
@@ -144,6 +146,7 @@ class OracleSCF:
         self.iteration = 0
         self.workers = workers
         self.fixed_density = False
+        self.template_xi = 0.0      # xi of V^alpha (Eq. (5)); 0: no template potential
 
     def set_density(self, rho_tot, rho_frag=None):
         """Replace rho_tot^in; every rho_alpha^in becomes rho_frag[alpha] or, when
@@ -158,7 +161,11 @@ class OracleSCF:
     def veff(self, alpha: int, v_h: np.ndarray) -> np.ndarray:
         f = self.frags[alpha]
         _, vxc = lda_pz81(self.rho_frag_in[alpha])
-        return (self.vloc.ravel()[f.global_index] + v_h.ravel()[f.global_index] + vxc)
+        v = self.vloc.ravel()[f.global_index] + v_h.ravel()[f.global_index] + vxc
+        if self.template_xi > 0.0:
+            # density-template potential (Eq. (5)) of the input densities
+            v = v + (self.rho_frag_in[alpha] - self.rho_in.ravel()[f.global_index]) / self.template_xi
+        return v
 
     def solve_fragments(self, v_h: np.ndarray, alphas=None):
         alphas = range(len(self.frags)) if alphas is None else alphas

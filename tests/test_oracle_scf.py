@@ -234,3 +234,88 @@ def test_fixed_density_dc_fragments_solve_the_frozen_potential():
         - sysm.n_electrons
     mu = scipy.optimize.brentq(count, eps_all.min() - 5, eps_all.max() + 5, xtol=1e-15, rtol=1e-15)
     assert abs(o.mu - mu) < 1e-10
+
+
+# --- density-template potential V^alpha (Eq. (5)) ----------------------------------------
+
+def test_template_potential_enters_the_fragment_hamiltonian():
+    """Frozen total and fragment densities that differ (each fragment's density is
+    the total times its own modulation): with xi > 0 every fragment's eigenvalues are
+    those of its dense Hamiltonian with V^alpha = (rho_alpha - rho_tot) / xi added on
+    the diagonal; with rho_alpha equal to rho_tot the template changes nothing."""
+    cfg = tiny_config(n_grid=(16, 8, 8), cell=(12.0, 6.0, 6.0), n_atoms=4, nstate=9,
+                      num_fragment=(2, 1, 1), buffer=(2, 0, 0), smearing=0.05, valence=2.0)
+    sysm = cfg.system
+    nx, ny, nz = cfg.n_grid
+    h = sysm.cell / np.array(cfg.n_grid)
+    dv = float(np.prod(h))
+    z, y, x = np.meshgrid(np.arange(nz) * h[2], np.arange(ny) * h[1], np.arange(nx) * h[0],
+                          indexing="ij")
+    rho = 1.0 + 0.3 * np.cos(2 * math.pi * x / sysm.cell[0]) + 0.1 * np.sin(2 * math.pi * z / sysm.cell[2])
+    rho *= sysm.n_electrons / (dv * rho.sum())
+    b_buf, ncore = 2, nx // 2
+    lx = np.arange(ncore + 2 * b_buf)
+    gidx = []
+    for alpha in range(2):
+        gx = (alpha * ncore - b_buf + lx) % nx
+        gidx.append((gx[None, None, :] + nx * (np.arange(ny)[None, :, None]
+                                               + ny * np.arange(nz)[:, None, None])).ravel())
+    lxf = np.broadcast_to(lx[None, None, :], (nz, ny, lx.size)).ravel()
+    rho_frag = [rho.ravel()[gidx[a]] * (1.0 + 0.25 * np.sin(2 * math.pi * lxf / lx.size + 1.3 * a))
+                for a in range(2)]
+    xi = 0.05
+
+    o = oracle.OracleSCF(cfg)
+    o.fixed_density = True
+    o.template_xi = xi
+    o.set_density(rho, rho_frag)
+    _fixed_steps(o, n_max=400)
+
+    vh = _dense_poisson((nz, ny, nx), h, rho.ravel())
+    vloc = om.local_potential(sysm, cfg.n_grid).ravel()
+    projs = om.kb_projectors(sysm, cfg.n_grid)
+    for alpha in range(2):
+        g = gidx[alpha]
+        _, vxc = om.lda_pz81(rho_frag[alpha])
+        vtemp = (rho_frag[alpha] - rho.ravel()[g]) / xi
+        assert np.abs(vtemp).max() > 0.05      # the template term is not negligible
+        hm = dense_kinetic((nz, ny, lx.size), h, og.FD_COEFFS) \
+            + np.diag(vloc[g] + vh[g] + vxc + vtemp)
+        for p in projs:
+            bfull = np.zeros(nx * ny * nz)
+            bfull[p.index] = p.value
+            hm += p.energy * dv * np.outer(bfull[g], bfull[g])
+        ev = np.linalg.eigvalsh(hm)
+        m = int(cfg.nstate_frag[alpha])
+        assert ev[m] - ev[m - 1] > 1e-3
+        np.testing.assert_allclose(o.eps[alpha], ev[:m], rtol=0, atol=1e-9)
+
+    # rho_alpha = rho_tot on every fragment point: V^alpha vanishes identically
+    a = oracle.OracleSCF(cfg)
+    b = oracle.OracleSCF(cfg)
+    b.template_xi = xi
+    for o2 in (a, b):
+        o2.fixed_density = True
+        o2.set_density(rho)
+    for _ in range(2):
+        ia, ib = a.step(), b.step()
+        assert ia == ib
+
+
+def test_template_potential_in_the_scf_acts_on_buffers_only():
+    """From the uniform start every fragment density equals the total one, so the
+    first step is unchanged by the template; mixing keeps them equal on core points
+    only, so from the second step on V^alpha is nonzero exactly on buffer points."""
+    cfg = tiny_config(n_grid=(12, 12, 12), cell=(7.2, 7.2, 7.2), n_atoms=4, nstate=10,
+                      num_fragment=(2, 2, 1), buffer=(2, 2, 0), smearing=0.05)
+    a = oracle.OracleSCF(cfg)
+    b = oracle.OracleSCF(cfg)
+    b.template_xi = 2.0
+    assert a.step() == b.step()
+    v_h = oracle.scf.poisson_fd(b.rho_in, b.h)
+    for alpha, f in enumerate(b.frags):
+        dvt = b.veff(alpha, v_h) - a.veff(alpha, v_h)
+        assert np.array_equal(dvt[f.core_mask], np.zeros(int(f.core_mask.sum())))
+        assert np.abs(dvt[~f.core_mask]).max() > 0.0
+    ia, ib = a.step(), b.step()
+    assert ia["e_band"] != ib["e_band"]
