@@ -125,6 +125,8 @@ def main() -> int:
                     help="fixed-density DC: freeze rho_tot at a superposition of atomic "
                          "Gaussians and time the iterations without Poisson, V_eff or "
                          "mixing updates (no comparison runs, no CPU baseline)")
+    ap.add_argument("--template-xi", type=float, default=0.0,
+                    help="xi of the density-template potential V^alpha (0: off, the default)")
     args = ap.parse_args()
     if args.fixed_density:
         args.no_compare = True
@@ -157,6 +159,8 @@ def main() -> int:
     print(f"[bench] setup {cfg.name}: {cfg.system.n_atoms} atoms, grid {cfg.n_grid}, "
           f"{cfg.n_fragments} fragments of {cfg.fragment_shape}", file=sys.stderr, flush=True)
     d = DCDFT.from_config(cfg, batched=args.batched, precision=prec)
+    if args.template_xi > 0.0:
+        d.dcdft_set_template(args.template_xi)
     if args.fixed_density:
         from workloads import superposed_density
         d.dcdft_set_density(superposed_density(cfg.system, cfg.n_grid))
@@ -273,7 +277,8 @@ def main() -> int:
                                 f"{cfg.cg_sweeps} CG sweeps per SCF iteration"),
                    "n_fragments": cfg.n_fragments, "batched": bool(args.batched),
                    "precision": args.precision,
-                   "mode": "fixed-density" if args.fixed_density else "scf"},
+                   "mode": "fixed-density" if args.fixed_density else "scf",
+                   "template_xi": args.template_xi},
         "roofline": roofline, "cpu_baseline": cpu, "comparisons": comparisons, **extra,
     }
     print(json.dumps(out), flush=True)

@@ -181,6 +181,15 @@ dcdft_status dcdft_set_density(dcdft_ctx *c, const double *rho_tot_in, const dou
  * step.  Errors: ARG (fixed not 0 or 1), HIP. */
 dcdft_status dcdft_fix_density(dcdft_ctx *c, int32_t fixed);
 
+/* Density-template potential of Eq. (5): V^alpha(l) = (rho_alpha^in(l) - rho_tot^in(g(l)))
+ * / xi, g(l) the global point of fragment point l, added to every fragment's V_eff.
+ * xi > 0 turns it on; xi = 0 turns it off (the default, as in the paper).  It enters
+ * the next formation of V_eff: the next dcdft_scf_step, or at once in fixed-density
+ * mode.  The energy expression is unchanged (linear mixing keeps the two input
+ * densities equal on core points, so V^alpha acts on buffer points only).
+ * Errors: ARG (xi negative or not finite). */
+dcdft_status dcdft_set_template(dcdft_ctx *c, double xi);
+
 /* H^alpha psi for m vectors of fragment frag with its V_eff of the last step
  * (after setup: V_loc + V_xc of the uniform density, V_H = 0), Eq. (5):
  * kinetic (nine-point FD, periodic on the fragment box) + V_eff + V_NL.

@@ -29,7 +29,7 @@ EXPORTED = [
     "dcdft_setup", "dcdft_scf_step", "dcdft_density", "dcdft_density_device",
     "dcdft_eigenvalues", "dcdft_fragment_info", "dcdft_get_field", "dcdft_get_fragment_field",
     "dcdft_get_orbitals", "dcdft_set_orbitals", "dcdft_set_density", "dcdft_fix_density",
-    "dcdft_apply_h",
+    "dcdft_set_template", "dcdft_apply_h",
     "dcdft_band_energy", "dcdft_kernel_timing", "dcdft_kernel_time", "dcdft_autotune",
     "dcdft_get_launch", "dcdft_set_launch",
     "dcdft_destroy",
@@ -121,6 +121,7 @@ def load_library(path: Optional[str] = None):
         "dcdft_set_orbitals": ([vp, ctypes.c_int32, pd, ctypes.c_size_t], ctypes.c_int),
         "dcdft_set_density": ([vp, pd, pd], ctypes.c_int),
         "dcdft_fix_density": ([vp, ctypes.c_int32], ctypes.c_int),
+        "dcdft_set_template": ([vp, ctypes.c_double], ctypes.c_int),
         "dcdft_apply_h": ([vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32],
                           ctypes.c_int),
         "dcdft_band_energy": ([vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32, vp,
@@ -322,6 +323,9 @@ class DCDFT:
 
     def dcdft_fix_density(self, fixed: bool = True) -> None:
         _check(self._lib.dcdft_fix_density(self.ctx, int(bool(fixed))), self.ctx)
+
+    def dcdft_set_template(self, xi: float) -> None:
+        _check(self._lib.dcdft_set_template(self.ctx, float(xi)), self.ctx)
 
     def dcdft_apply_h(self, frag: int, psi, hpsi, prec: int = PREC_FP64) -> None:
         """psi, hpsi: contiguous device tensors of shape (m, n)."""

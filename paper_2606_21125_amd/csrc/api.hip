@@ -737,7 +737,8 @@ void enqueue_step(dcdft_ctx *c) {
     // 1. Hartree potential of rho_tot^in
     launch_poisson(g, c->d_rho_in, c->d_vh, c->d_fft_a, c->d_fft_b, c->d_qf, c->d_qi, c->d_lam, s);
     // 2. fragment effective potentials
-    launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, c->d_veff32, s);
+    launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_rho_in,
+                c->template_xi, c->d_veff, c->d_veff32, s);
   }
   // 3. fragment eigensolvers
   if (c->batched) {
@@ -1053,7 +1054,8 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   for (double **b : bands) launch_fill(*b, c->M_tot, 0.0, c->stream);
   launch_fill(c->d_scal, SC_COUNT, 0.0, c->stream);
   launch_fill_int(c->d_flags, 1, 0, c->stream);
-  launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, c->d_veff32, c->stream);
+  launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_rho_in,
+              c->template_xi, c->d_veff, c->d_veff32, c->stream);
   if (mixed) {
     launch_init_orbitals<float>(g, c->orbset(0, c->nF), c->seed, (float *)c->d_psi, c->stream);
     orthonormalize_all<float>(c);
@@ -1294,7 +1296,8 @@ dcdft_status dcdft_set_density(dcdft_ctx *c, const double *rho_tot_in, const dou
   // V_eff follows the new density (V_H recomputed from it)
   launch_poisson(g, c->d_rho_in, c->d_vh, c->d_fft_a, c->d_fft_b, c->d_qf, c->d_qi, c->d_lam,
                  c->stream);
-  launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, c->d_veff32, c->stream);
+  launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_rho_in,
+              c->template_xi, c->d_veff, c->d_veff32, c->stream);
   HIPTRY(c, hipGetLastError());
   HIPTRY(c, hipStreamSynchronize(c->stream));
   return DCDFT_OK;
@@ -1311,7 +1314,25 @@ dcdft_status dcdft_fix_density(dcdft_ctx *c, int32_t fixed) {
     const Geo &g = c->geo;
     launch_poisson(g, c->d_rho_in, c->d_vh, c->d_fft_a, c->d_fft_b, c->d_qf, c->d_qi, c->d_lam,
                    c->stream);
-    launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_veff, c->d_veff32, c->stream);
+    launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_rho_in,
+                c->template_xi, c->d_veff, c->d_veff32, c->stream);
+    HIPTRY(c, hipGetLastError());
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+  }
+  return DCDFT_OK;
+}
+
+dcdft_status dcdft_set_template(dcdft_ctx *c, double xi) {
+  if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  if (!(xi >= 0.0) || !std::isfinite(xi))
+    return set_err(c, DCDFT_ERR_ARG, fmt("xi = %g: must be finite and >= 0", xi));
+  drop_graph(c);  // xi is a kernel argument of the captured V_eff launch
+  c->template_xi = xi;
+  if (c->fixed_density) {
+    // the frozen step does not form V_eff: form it here with the new template
+    const Geo &g = c->geo;
+    launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_rho_in, c->template_xi,
+                c->d_veff, c->d_veff32, c->stream);
     HIPTRY(c, hipGetLastError());
     HIPTRY(c, hipStreamSynchronize(c->stream));
   }

@@ -220,6 +220,7 @@ struct dcdft_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   bool use_graph = true;
+  double template_xi = 0.0;    // xi of the density-template potential; 0: off
   bool fixed_density = false;  // rho^in frozen: no Poisson, V_eff or mixing update in the step
   bool graph_timed = false;
   std::vector<PendingTimer> graph_timers;
@@ -343,7 +344,8 @@ void launch_density(const Geo &g, const OrbSet &o, int f0, int f1, const T *psi,
 // V_eff^alpha = V_loc + V_H (gathered) + V_xc(rho_alpha^in)
 // (and, if veff32 is not null, its FP32 rounding)
 void launch_veff(const Geo &g, int f0, int f1, const double *vloc, const double *vh,
-                 const double *rhof_in, double *veff, float *veff32, hipStream_t s);
+                 const double *rhof_in, const double *rho_tot_in, double xi, double *veff,
+                 float *veff32, hipStream_t s);
 // Energy terms, residuals and mixing on the global grid; fragment mixing
 void launch_global_terms(const Geo &g, double *rho_in, const double *rho_out, const double *vh,
                          double mixing, double *part, int n_part, double *scal, hipStream_t s,

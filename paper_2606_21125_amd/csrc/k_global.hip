@@ -162,9 +162,12 @@ __global__ void __launch_bounds__(256) k_density(Geo g, const long long *__restr
   if (is_core_point(g, l)) rho_out[global_of_local(g, f, l)] = acc;
 }
 
+// V_eff of Eq. (5); with xi > 0 (rho_tot_in not NULL) the density-template
+// potential (rho_alpha^in - rho_tot^in) / xi is added.
 __global__ void __launch_bounds__(256) k_veff(Geo g, int f0, int f1, const double *__restrict__ vloc,
                                               const double *__restrict__ vh,
                                               const double *__restrict__ rhof_in,
+                                              const double *__restrict__ rho_tot_in, double xi,
                                               double *__restrict__ veff,
                                               float *__restrict__ veff32) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -172,9 +175,11 @@ __global__ void __launch_bounds__(256) k_veff(Geo g, int f0, int f1, const doubl
   const int f = f0 + (int)(idx / g.n);
   const int l = (int)(idx % g.n);
   const long long gi = global_of_local(g, f, l);
+  const double rf = rhof_in[(long long)f * g.n + l];
   double exc, vxc;
-  pz81(rhof_in[(long long)f * g.n + l], exc, vxc);
-  const double v = vloc[gi] + vh[gi] + vxc;
+  pz81(rf, exc, vxc);
+  double v = vloc[gi] + vh[gi] + vxc;
+  if (rho_tot_in) v = v + (rf - rho_tot_in[gi]) / xi;
   veff[(long long)f * g.n + l] = v;
   if (veff32) veff32[(long long)f * g.n + l] = (float)v;
 }
@@ -377,11 +382,13 @@ void launch_convert(const float *a, double *b, long long n, hipStream_t s) {
 }
 
 void launch_veff(const Geo &g, int f0, int f1, const double *vloc, const double *vh,
-                 const double *rhof_in, double *veff, float *veff32, hipStream_t s) {
+                 const double *rhof_in, const double *rho_tot_in, double xi, double *veff,
+                 float *veff32, hipStream_t s) {
   const long long total = (long long)(f1 - f0) * g.n;
   if (total <= 0) return;
+  if (!(xi > 0.0)) rho_tot_in = nullptr;
   hipLaunchKernelGGL(k_veff, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, f0, f1,
-                     vloc, vh, rhof_in, veff, veff32);
+                     vloc, vh, rhof_in, rho_tot_in, xi, veff, veff32);
 }
 
 void launch_global_terms(const Geo &g, double *rho_in, const double *rho_out, const double *vh,
