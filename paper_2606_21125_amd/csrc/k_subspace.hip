@@ -909,13 +909,15 @@ __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *_
                                               int *flags) {
   __shared__ double A[kMaxOrb * (kMaxOrb + 1)];
   __shared__ double V[kMaxOrb * (kMaxOrb + 1)];
-  __shared__ double cs[kMaxOrb / 2 + 1], sn[kMaxOrb / 2 + 1];
-  __shared__ int pp[kMaxOrb / 2 + 1], qq[kMaxOrb / 2 + 1];
+  // rotations of two consecutive rounds: round r is applied while round r + 1's
+  // angles are formed
+  __shared__ double cs[2][kMaxOrb / 2 + 1], sn[2][kMaxOrb / 2 + 1];
+  __shared__ int pp[2][kMaxOrb / 2 + 1], qq[2][kMaxOrb / 2 + 1];
   __shared__ double red[32];
   __shared__ int rank_of[kMaxOrb];
   const int f = f0 + blockIdx.x;
   const int mf = o.m[f], mp = o.m_pad;
-  const int ld = mf + 1;   // odd row stride: column walks hit distinct banks
+  const int ld = mf | 1;   // odd row stride: column walks hit distinct banks
   const double *Hf = H + (long long)f * mp * mp;
   // 32 x 32 thread grid (no runtime division in the index arithmetic)
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
@@ -926,6 +928,32 @@ __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *_
     }
   const int mm = (mf % 2) ? mf + 1 : mf;   // an odd size gets one idle index
   const int npair = mm / 2;
+  // rotation angles of round r from the current A into buffer b (first wave)
+  auto angles = [&](int r, int b) {
+    for (int k = threadIdx.x; k < npair; k += 64) {
+      int p, q;
+      rr_pair(mm, r, k, p, q);
+      double c = 1.0, s = 0.0;
+      if (q < mf) {
+        const double apq = A[p * ld + q];
+        if (apq != 0.0) {
+          // t = sign(tau) / (|tau| + sqrt(1 + tau^2)), c = 1 / sqrt(1 + t^2), s = t c
+          // (|tau| > 1e100: t = 1 / (2 tau), where 1 + tau^2 would overflow)
+          const double tau = (A[q * ld + q] - A[p * ld + p]) * rcp_f64(2.0 * apq);
+          const double x = fma(tau, tau, 1.0);
+          const double t = fabs(tau) > 1e100
+                               ? 0.5 * rcp_f64(tau)
+                               : (tau >= 0.0 ? 1.0 : -1.0) * rcp_f64(fabs(tau) + x * rsqrt_f64(x));
+          c = rsqrt_f64(fma(t, t, 1.0));
+          s = t * c;
+        }
+      }
+      pp[b][k] = p;
+      qq[b][k] = q;
+      cs[b][k] = c;
+      sn[b][k] = s;
+    }
+  };
   bool converged = (mf <= 1);
   double prev_off = 1e300;
   for (int sweep = 0; sweep < 60 && !converged; ++sweep) {
@@ -960,42 +988,18 @@ __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *_
       break;
     }
     prev_off = offm;
+    if (threadIdx.x < 64) angles(0, 0);
     for (int r = 0; r < mm - 1; ++r) {
-      // the round's rotations (needs the previous round's A: barrier below)
-      __syncthreads();
-      for (int k = threadIdx.x; k < npair; k += blockDim.x) {
-        int p, q;
-        rr_pair(mm, r, k, p, q);
-        double c = 1.0, s = 0.0;
-        if (q < mf) {
-          const double apq = A[p * ld + q];
-          if (apq != 0.0) {
-            // t = sign(tau) / (|tau| + sqrt(1 + tau^2)), c = 1 / sqrt(1 + t^2), s = t c
-            // (|tau| > 1e100: t = 1 / (2 tau), where 1 + tau^2 would overflow)
-            const double tau = (A[q * ld + q] - A[p * ld + p]) * rcp_f64(2.0 * apq);
-            const double x = fma(tau, tau, 1.0);
-            const double t = fabs(tau) > 1e100
-                                 ? 0.5 * rcp_f64(tau)
-                                 : (tau >= 0.0 ? 1.0 : -1.0) * rcp_f64(fabs(tau) + x * rsqrt_f64(x));
-            c = rsqrt_f64(fma(t, t, 1.0));
-            s = t * c;
-          }
-        }
-        pp[k] = p;
-        qq[k] = q;
-        cs[k] = c;
-        sn[k] = s;
-      }
+      const int b = r & 1;
       __syncthreads();
       // A <- J^T A J as 2x2 blocks (rows of pair k1, columns of pair k2: the
-      // blocks are disjoint, so one pass with no intermediate barrier), and
-      // V <- V J.  The idle index of an odd size (q = mf) is neither read nor
-      // written.
+      // blocks are disjoint, so one pass with no intermediate barrier).  The idle
+      // index of an odd size (q = mf) is neither read nor written.
       for (int k1 = ty; k1 < npair; k1 += 32)
       for (int k2 = tx; k2 < npair; k2 += 32) {
-        const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
+        const int p1 = pp[b][k1], q1 = qq[b][k1], p2 = pp[b][k2], q2 = qq[b][k2];
         const bool h1 = q1 < mf, h2 = q2 < mf;
-        const double c1 = cs[k1], s1 = sn[k1], c2 = cs[k2], s2 = sn[k2];
+        const double c1 = cs[b][k1], s1 = sn[b][k1], c2 = cs[b][k2], s2 = sn[b][k2];
         const double app = A[p1 * ld + p2];
         const double apq = h2 ? A[p1 * ld + q2] : 0.0;
         const double aqp = h1 ? A[q1 * ld + p2] : 0.0;
@@ -1008,14 +1012,21 @@ __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *_
         if (h1) A[q1 * ld + p2] = c2 * rqp - s2 * rqq;
         if (h1 && h2) A[q1 * ld + q2] = s2 * rqp + c2 * rqq;
       }
-      for (int k = ty; k < npair; k += 32)
-      for (int i = tx; i < mf; i += 32) {
-        const int p = pp[k], q = qq[k];
-        if (q >= mf) continue;
-        const double c = cs[k], s = sn[k];
-        const double vp = V[i * ld + p], vq = V[i * ld + q];
-        V[i * ld + p] = c * vp - s * vq;
-        V[i * ld + q] = s * vp + c * vq;
+      __syncthreads();
+      // the first wave forms the next round's angles from the updated A while
+      // the other waves apply this round's rotations to V (V <- V J)
+      if (threadIdx.x < 64) {
+        if (r + 1 < mm - 1) angles(r + 1, b ^ 1);
+      } else {
+        for (int k = ty - 2; k < npair; k += 30)
+        for (int i = tx; i < mf; i += 32) {
+          const int p = pp[b][k], q = qq[b][k];
+          if (q >= mf) continue;
+          const double c = cs[b][k], s = sn[b][k];
+          const double vp = V[i * ld + p], vq = V[i * ld + q];
+          V[i * ld + p] = c * vp - s * vq;
+          V[i * ld + q] = s * vp + c * vq;
+        }
       }
     }
   }
