@@ -1,0 +1,72 @@
+"""Twenty SCF iterations of the 64-atom Si workload (8 fragments of 24^3, 64
+orbitals) on the GPU against the FP64 oracle, two ways:
+
+* free running: both sides iterate from the same start and are compared after
+  every step (differences of rounding order may grow with the SCF's own
+  sensitivity, so the per-step errors are printed);
+* same input state: a second GPU context is loaded with the oracle's orbitals and
+  densities before each of its steps, so every step is compared from an identical
+  state.
+
+Tolerances as for the SCF step: eigenvalues and mu 1e-10 Ha, density
+dV sum |d rho| / N_e <= 1e-9; in addition the occupied-space projectors of every
+fragment agree: || Psi Psi^T - Psi' Psi'^T ||_F (dV-orthonormal orbitals) <= 1e-8,
+which compares subspaces and is blind to the basis chosen inside degenerate
+eigenvalues."""
+import math
+
+import numpy as np
+import pytest
+from threadpoolctl import threadpool_limits
+
+import oracle
+from tests.gpu_common import l1_over_ne, require_gpu
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _subspace_distance(a, b, dv):
+    """|| A A^T - B B^T ||_F for dV-orthonormal rows, as sqrt(2 sum sin^2 theta) over the
+    principal angles, with sum sin^2 theta = dV || B - (dV B A^T) A ||^2 (the part of B
+    outside span A; no cancellation against m)."""
+    r = b - (dv * (b @ a.T)) @ a
+    return math.sqrt(2.0 * dv * float(np.sum(r * r)))
+
+
+def _errors(o, d, ri, gi, cfg):
+    deps = max(np.abs(d.dcdft_eigenvalues(f)[0] - o.eps[f]).max() for f in range(cfg.n_fragments))
+    drho = l1_over_ne(d.dcdft_density(), o.rho_out, o.dv, o.ne)
+    dsub = max(_subspace_distance(d.dcdft_get_orbitals(f), o.psi[f], o.dv)
+               for f in range(cfg.n_fragments))
+    return dict(dmu=abs(ri["mu"] - gi["mu"]), deps=deps, drho=drho, dsub=dsub,
+                de=abs(ri["e_total"] - gi["e_total"]))
+
+
+def test_config1_twenty_iterations():
+    require_gpu()
+    from paper_2606_21125_amd import DCDFT
+    cfg = workloads.config(1)
+    o = oracle.OracleSCF(cfg, workers=8)
+    with DCDFT.from_config(cfg) as free, DCDFT.from_config(cfg) as same:
+        for k in range(20):
+            pre_psi = [p.copy() for p in o.psi]
+            pre_rho = o.rho_in.copy()
+            pre_frag = np.concatenate(o.rho_frag_in)
+            with threadpool_limits(1):   # one BLAS thread in each fragment worker
+                ri = o.step()
+            gf = free.dcdft_scf_step()
+            for f in range(cfg.n_fragments):
+                same.dcdft_set_orbitals(f, pre_psi[f])
+            same.dcdft_set_density(pre_rho, pre_frag)
+            gs = same.dcdft_scf_step()
+            ef = _errors(o, free, ri, gf, cfg)
+            es = _errors(o, same, ri, gs, cfg)
+            print(f"step {k}: R_paper {ri['residual_paper']:.3e}  free "
+                  + " ".join(f"{n} {v:.1e}" for n, v in ef.items())
+                  + "  same-state " + " ".join(f"{n} {v:.1e}" for n, v in es.items()), flush=True)
+            for e in (ef, es):
+                assert e["dmu"] < 1e-10 and e["deps"] < 1e-10, k
+                assert e["drho"] < 1e-9, k
+                assert e["dsub"] < 1e-8, k
+                assert e["de"] < 1e-8 * max(1.0, abs(ri["e_total"])), k
