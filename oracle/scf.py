@@ -108,6 +108,19 @@ def total_energy(e_band: float, rho_in: np.ndarray, v_h: np.ndarray, dv: float,
             + dv * float(np.sum(rho_in * exc)) - sigma * entropy)
 
 
+_WORKER_LIMITS = None
+
+
+def _worker_init(blas_threads: int):
+    """Pool worker set-up: BLAS thread count of the worker process."""
+    global _WORKER_LIMITS
+    try:
+        from threadpoolctl import threadpool_limits
+        _WORKER_LIMITS = threadpool_limits(limits=blas_threads)
+    except ImportError:
+        pass
+
+
 def _solve_fragment(args):
     psi, veff, proj, h, dv, sweeps, shape = args
     m = psi.shape[0]
@@ -118,7 +131,7 @@ def _solve_fragment(args):
 class OracleSCF:
     """State and iteration of the DC-DFT SCF on the CPU, FP64."""
 
-    def __init__(self, cfg, workers: int = 1):
+    def __init__(self, cfg, workers: int = 1, blas_threads: int = 1):
         self.cfg = cfg
         sysm = cfg.system
         self.n_grid = tuple(int(v) for v in cfg.n_grid)
@@ -144,7 +157,12 @@ class OracleSCF:
         self.w = None
         self.mu = None
         self.iteration = 0
+        # fragment eigensolves on a pool of fresh interpreter processes ("spawn":
+        # nothing of the caller's process, such as an initialised GPU runtime, is
+        # inherited), created on first use and kept until close()
         self.workers = workers
+        self.blas_threads = blas_threads
+        self._pool = None
         self.fixed_density = False
         self.template_xi = 0.0      # xi of V^alpha (Eq. (5)); 0: no template potential
 
@@ -157,6 +175,19 @@ class OracleSCF:
             self.rho_frag_in = [flat[f.global_index].copy() for f in self.frags]
         else:
             self.rho_frag_in = [np.array(r, dtype=np.float64).ravel() for r in rho_frag]
+
+    def close(self):
+        """End the worker pool (if one was started)."""
+        if self._pool is not None:
+            self._pool.close()
+            self._pool.join()
+            self._pool = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def veff(self, alpha: int, v_h: np.ndarray) -> np.ndarray:
         f = self.frags[alpha]
@@ -175,9 +206,11 @@ class OracleSCF:
             jobs.append((self.psi[a], self.veff(a, v_h).reshape(f.shape), self.fproj[a], self.h,
                          self.dv, self.cfg.cg_sweeps, f.shape))
         if self.workers > 1 and len(jobs) > 1:
-            import multiprocessing as mp
-            with mp.get_context("fork").Pool(self.workers) as pool:
-                res = pool.map(_solve_fragment, jobs)
+            if self._pool is None:
+                import multiprocessing as mp
+                self._pool = mp.get_context("spawn").Pool(self.workers, _worker_init,
+                                                           (self.blas_threads,))
+            res = self._pool.map(_solve_fragment, jobs)
         else:
             res = [_solve_fragment(j) for j in jobs]
         return dict(zip(alphas, res))
