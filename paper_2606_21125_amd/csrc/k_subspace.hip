@@ -911,8 +911,9 @@ __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *_
   __shared__ double V[kMaxOrb * (kMaxOrb + 1)];
   // rotations of two consecutive rounds: round r is applied while round r + 1's
   // angles are formed
-  __shared__ double cs[2][kMaxOrb / 2 + 1], sn[2][kMaxOrb / 2 + 1];
-  __shared__ int pp[2][kMaxOrb / 2 + 1], qq[2][kMaxOrb / 2 + 1];
+  // (p, q) and (c, s) of each pair packed: one LDS read each
+  __shared__ int2 pq_of[2][kMaxOrb / 2 + 1];
+  __shared__ double2 cs_of[2][kMaxOrb / 2 + 1];
   __shared__ double red[32];
   __shared__ int rank_of[kMaxOrb];
   const int f = f0 + blockIdx.x;
@@ -948,10 +949,8 @@ __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *_
           s = t * c;
         }
       }
-      pp[b][k] = p;
-      qq[b][k] = q;
-      cs[b][k] = c;
-      sn[b][k] = s;
+      pq_of[b][k] = make_int2(p, q);
+      cs_of[b][k] = make_double2(c, s);
     }
   };
   bool converged = (mf <= 1);
@@ -997,9 +996,11 @@ __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *_
       // index of an odd size (q = mf) is neither read nor written.
       for (int k1 = ty; k1 < npair; k1 += 32)
       for (int k2 = tx; k2 < npair; k2 += 32) {
-        const int p1 = pp[b][k1], q1 = qq[b][k1], p2 = pp[b][k2], q2 = qq[b][k2];
+        const int2 pq1 = pq_of[b][k1], pq2 = pq_of[b][k2];
+        const double2 cs1 = cs_of[b][k1], cs2 = cs_of[b][k2];
+        const int p1 = pq1.x, q1 = pq1.y, p2 = pq2.x, q2 = pq2.y;
         const bool h1 = q1 < mf, h2 = q2 < mf;
-        const double c1 = cs[b][k1], s1 = sn[b][k1], c2 = cs[b][k2], s2 = sn[b][k2];
+        const double c1 = cs1.x, s1 = cs1.y, c2 = cs2.x, s2 = cs2.y;
         const double app = A[p1 * ld + p2];
         const double apq = h2 ? A[p1 * ld + q2] : 0.0;
         const double aqp = h1 ? A[q1 * ld + p2] : 0.0;
@@ -1020,9 +1021,11 @@ __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *_
       } else {
         for (int k = ty - 2; k < npair; k += 30)
         for (int i = tx; i < mf; i += 32) {
-          const int p = pp[b][k], q = qq[b][k];
+          const int2 pq = pq_of[b][k];
+          const int p = pq.x, q = pq.y;
           if (q >= mf) continue;
-          const double c = cs[b][k], s = sn[b][k];
+          const double2 cq = cs_of[b][k];
+          const double c = cq.x, s = cq.y;
           const double vp = V[i * ld + p], vq = V[i * ld + q];
           V[i * ld + p] = c * vp - s * vq;
           V[i * ld + q] = s * vp + c * vq;
