@@ -3,7 +3,8 @@
 TEST INFRASTRUCTURE ONLY.  Only the test-suite, the package smoke check and the
 CPU-baseline leg of the benchmark may import this package.  The HIP library
 never calls it, and it shares no code, table or constant generator with the
-HIP library: both follow the paper (Sec. 2.2, Eqs. (1)-(5)) and the readings
+HIP library: both follow the paper (Sec. 2.2, Eqs. (1)-(5); the DC-LCFO
+post-processing of Sec. 2.3, Eqs. (6)-(9)) and the readings
 listed in the design notes, independently.
 
 Layout conventions: global arrays are numpy arrays of shape (Nz, Ny, Nx)
@@ -23,3 +24,4 @@ from .solver import (apply_h, apply_h_local, kb_project, cholesky_orthonormalize
                      fermi_level, fragment_density)
 from .scf import (poisson_fd, poisson_fd_cg, OracleSCF, total_energy)  # noqa: F401
 from .grad import band_energy, band_energy_grad  # noqa: F401
+from .lcfo import lcfo_basis, lcfo_hamiltonian  # noqa: F401

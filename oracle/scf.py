@@ -163,6 +163,7 @@ class OracleSCF:
         self.workers = workers
         self.blas_threads = blas_threads
         self._pool = None
+        self.veff_last = {}         # V_eff of each fragment in the last eigensolve
         self.fixed_density = False
         self.template_xi = 0.0      # xi of V^alpha (Eq. (5)); 0: no template potential
 
@@ -203,7 +204,9 @@ class OracleSCF:
         jobs = []
         for a in alphas:
             f = self.frags[a]
-            jobs.append((self.psi[a], self.veff(a, v_h).reshape(f.shape), self.fproj[a], self.h,
+            veff = self.veff(a, v_h)
+            self.veff_last[a] = veff
+            jobs.append((self.psi[a], veff.reshape(f.shape), self.fproj[a], self.h,
                          self.dv, self.cfg.cg_sweeps, f.shape))
         if self.workers > 1 and len(jobs) > 1:
             if self._pool is None:
