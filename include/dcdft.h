@@ -190,6 +190,42 @@ dcdft_status dcdft_fix_density(dcdft_ctx *c, int32_t fixed);
  * Errors: ARG (xi negative or not finite). */
 dcdft_status dcdft_set_template(dcdft_ctx *c, double xi);
 
+/* DC-LCFO post-processing (Sec. 2.3, Eqs. (6)-(9)), on the orbitals and V_eff of
+ * the last step (normally a converged SCF).  Per fragment: the orbitals with
+ * eps < eps_cut (Ha; the paper quotes eps_cut - mu = 0.1 eV) projected on the
+ * core (Eq. (3)'s projection), their overlap S (Eq. (6)), its eigenpairs, and the
+ * basis lambda_l = sum_j phibar_j v_jl / sqrt(sigma_l) over the eigenvalues sigma_l
+ * > lambda_cut (the paper quotes 1e-7), ascending in sigma, orthonormal over the
+ * whole system (Eq. (7)).  Then the global matrix of Eq. (9): same-fragment
+ * blocks <lambda^a_i|H^a lambda^a_j>; blocks of fragments a != b whose core meets
+ * the other's box, 1/2 [<H^a lambda^a_i|lambda^b_j> + <lambda^a_i|H^b lambda^b_j>];
+ * zero elsewhere.  H^a is the fragment Hamiltonian of Eq. (5) on the fragment box.
+ * All of it is FP64 (orbitals of the mixed mode are widened).  The diagonalisation
+ * of the global matrix is not part of this library.  The first call allocates
+ * device memory (two FP64 arrays of the orbital size and the pair tables), kept
+ * until dcdft_destroy; the call overwrites work arrays, never the SCF state.
+ * Errors: ARG (no step taken yet, non-finite eps_cut, lambda_cut not > 0), EIG,
+ * OOM, HIP. */
+typedef struct {
+  int32_t n_basis;              /* basis functions over all fragments               */
+  int32_t n_pairs;              /* ordered fragment pairs with a neighbour block    */
+  float ms;                     /* device time of the build (ms)                    */
+} dcdft_lcfo_info;
+dcdft_status dcdft_lcfo_build(dcdft_ctx *c, double eps_cut, double lambda_cut,
+                              dcdft_lcfo_info *info);
+
+/* Basis of fragment frag from the last dcdft_lcfo_build, host [nb][n] (fragment box
+ * points, zero outside the core); *nb (may be NULL) receives the count; host NULL
+ * queries the count only.  Errors: ARG (no build, index, buffer smaller than nb n). */
+dcdft_status dcdft_lcfo_basis(const dcdft_ctx *c, int32_t frag, double *host, size_t count,
+                              int32_t *nb);
+
+/* The global matrix of the last dcdft_lcfo_build, host row-major [N][N], N the total
+ * basis count (fragments in order, each fragment's basis in its order); host NULL
+ * queries N only.  Errors: ARG (no build, buffer smaller than N^2). */
+dcdft_status dcdft_lcfo_hamiltonian(const dcdft_ctx *c, double *host, size_t count,
+                                    int32_t *n_basis);
+
 /* H^alpha psi for m vectors of fragment frag with its V_eff of the last step
  * (after setup: V_loc + V_xc of the uniform density, V_H = 0), Eq. (5):
  * kinetic (nine-point FD, periodic on the fragment box) + V_eff + V_NL.

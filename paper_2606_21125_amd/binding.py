@@ -29,7 +29,8 @@ EXPORTED = [
     "dcdft_setup", "dcdft_scf_step", "dcdft_density", "dcdft_density_device",
     "dcdft_eigenvalues", "dcdft_fragment_info", "dcdft_get_field", "dcdft_get_fragment_field",
     "dcdft_get_orbitals", "dcdft_set_orbitals", "dcdft_set_density", "dcdft_fix_density",
-    "dcdft_set_template", "dcdft_apply_h",
+    "dcdft_set_template", "dcdft_lcfo_build", "dcdft_lcfo_basis", "dcdft_lcfo_hamiltonian",
+    "dcdft_apply_h",
     "dcdft_band_energy", "dcdft_kernel_timing", "dcdft_kernel_time", "dcdft_autotune",
     "dcdft_get_launch", "dcdft_set_launch",
     "dcdft_destroy",
@@ -86,6 +87,13 @@ class DcdftTuneInfo(ctypes.Structure):
                                                                  self.ms_gram) if v >= 0}}
 
 
+class DcdftLcfoInfo(ctypes.Structure):
+    _fields_ = [("n_basis", ctypes.c_int32), ("n_pairs", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class DcdftError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
@@ -122,6 +130,10 @@ def load_library(path: Optional[str] = None):
         "dcdft_set_density": ([vp, pd, pd], ctypes.c_int),
         "dcdft_fix_density": ([vp, ctypes.c_int32], ctypes.c_int),
         "dcdft_set_template": ([vp, ctypes.c_double], ctypes.c_int),
+        "dcdft_lcfo_build": ([vp, ctypes.c_double, ctypes.c_double,
+                              ctypes.POINTER(DcdftLcfoInfo)], ctypes.c_int),
+        "dcdft_lcfo_basis": ([vp, ctypes.c_int32, pd, ctypes.c_size_t, pi], ctypes.c_int),
+        "dcdft_lcfo_hamiltonian": ([vp, pd, ctypes.c_size_t, pi], ctypes.c_int),
         "dcdft_apply_h": ([vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32],
                           ctypes.c_int),
         "dcdft_band_energy": ([vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32, vp,
@@ -326,6 +338,26 @@ class DCDFT:
 
     def dcdft_set_template(self, xi: float) -> None:
         _check(self._lib.dcdft_set_template(self.ctx, float(xi)), self.ctx)
+
+    def dcdft_lcfo_build(self, eps_cut: float, lambda_cut: float = 1e-7) -> dict:
+        info = DcdftLcfoInfo()
+        _check(self._lib.dcdft_lcfo_build(self.ctx, float(eps_cut), float(lambda_cut),
+                                          ctypes.byref(info)), self.ctx)
+        return info.as_dict()
+
+    def dcdft_lcfo_basis(self, frag: int) -> np.ndarray:
+        nb = ctypes.c_int32(0)
+        _check(self._lib.dcdft_lcfo_basis(self.ctx, frag, None, 0, ctypes.byref(nb)), self.ctx)
+        out = np.empty((nb.value, self.n))
+        _check(self._lib.dcdft_lcfo_basis(self.ctx, frag, _dptr(out), out.size, None), self.ctx)
+        return out
+
+    def dcdft_lcfo_hamiltonian(self) -> np.ndarray:
+        nb = ctypes.c_int32(0)
+        _check(self._lib.dcdft_lcfo_hamiltonian(self.ctx, None, 0, ctypes.byref(nb)), self.ctx)
+        out = np.empty((nb.value, nb.value))
+        _check(self._lib.dcdft_lcfo_hamiltonian(self.ctx, _dptr(out), out.size, None), self.ctx)
+        return out
 
     def dcdft_apply_h(self, frag: int, psi, hpsi, prec: int = PREC_FP64) -> None:
         """psi, hpsi: contiguous device tensors of shape (m, n)."""

@@ -1339,6 +1339,196 @@ dcdft_status dcdft_set_template(dcdft_ctx *c, double xi) {
   return DCDFT_OK;
 }
 
+
+// Neighbour pairs of the DC-LCFO matrix: (a, b != a) whose core b meets the box of
+// a, with the overlapping coordinates per axis as (local in a's box, local in b's
+// box).  The boxes never cover a global coordinate twice (n_core + 2 b <= N).
+static void lcfo_pair_tables(const dcdft_ctx *c, std::vector<int> &pairs,
+                             std::vector<int2> &axes) {
+  const Geo &g = c->geo;
+  pairs.clear();
+  axes.clear();
+  for (int a = 0; a < c->nF; ++a) {
+    const int ac[3] = {a % g.F[0], (a / g.F[0]) % g.F[1], a / (g.F[0] * g.F[1])};
+    for (int b = 0; b < c->nF; ++b) {
+      if (b == a) continue;
+      const int bc[3] = {b % g.F[0], (b / g.F[0]) % g.F[1], b / (g.F[0] * g.F[1])};
+      std::vector<int2> ax[3];
+      for (int d = 0; d < 3; ++d)
+        for (int la = 0; la < g.nl[d]; ++la) {
+          const int gd = ((ac[d] * g.nc[d] - g.b[d] + la) % g.N[d] + g.N[d]) % g.N[d];
+          const int c0 = bc[d] * g.nc[d];
+          if (gd >= c0 && gd < c0 + g.nc[d]) ax[d].push_back(make_int2(la, gd - c0 + g.b[d]));
+        }
+      if (ax[0].empty() || ax[1].empty() || ax[2].empty()) continue;
+      pairs.push_back(a);
+      pairs.push_back(b);
+      for (int d = 0; d < 3; ++d) pairs.push_back((int)ax[d].size());
+      for (int d = 0; d < 3; ++d) {
+        pairs.push_back((int)axes.size());
+        axes.insert(axes.end(), ax[d].begin(), ax[d].end());
+      }
+    }
+  }
+}
+
+dcdft_status dcdft_lcfo_build(dcdft_ctx *c, double eps_cut, double lambda_cut,
+                              dcdft_lcfo_info *info) {
+  if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  if (!std::isfinite(eps_cut) || !std::isfinite(lambda_cut) || !(lambda_cut > 0.0))
+    return set_err(c, DCDFT_ERR_ARG, "eps_cut must be finite and lambda_cut finite and > 0");
+  if (c->iter < 1) return set_err(c, DCDFT_ERR_ARG, "no eigenpairs yet: run dcdft_scf_step first");
+  const Geo &g = c->geo;
+  hipStream_t s = c->stream;
+  c->lcfo_ready = false;
+  const long long rows = c->M_tot + c->m_pad;
+  if (!c->d_lcfo_lam) {
+    HIPTRY(c, dalloc(c, &c->d_lcfo_lam, (size_t)(rows * g.n)));
+    HIPTRY(c, dalloc(c, &c->d_lcfo_hlam, (size_t)(rows * g.n)));
+    // spare rows past the last band stay zero (kernels may read padded rows)
+    HIPTRY(c, hipMemset(c->d_lcfo_lam, 0, (size_t)(rows * g.n) * sizeof(double)));
+    HIPTRY(c, hipMemset(c->d_lcfo_hlam, 0, (size_t)(rows * g.n) * sizeof(double)));
+    HIPTRY(c, dalloc(c, &c->d_lcfo_sig, (size_t)c->M_tot));
+    HIPTRY(c, dalloc(c, &c->d_lcfo_w, (size_t)c->M_tot));
+    HIPTRY(c, dalloc(c, &c->d_lcfo_k, (size_t)c->nF));
+    HIPTRY(c, dalloc(c, &c->d_lcfo_nb, (size_t)c->nF));
+  }
+  if (c->lcfo_pairs < 0) {
+    std::vector<int> pairs;
+    std::vector<int2> axes;
+    lcfo_pair_tables(c, pairs, axes);
+    const int P = (int)(pairs.size() / 8);
+    HIPTRY(c, dalloc(c, &c->d_lcfo_pairs, pairs.size()));
+    HIPTRY(c, dalloc(c, &c->d_lcfo_axes, axes.size()));
+    HIPTRY(c, dalloc(c, &c->d_lcfo_x, (size_t)P * c->m_pad * c->m_pad));
+    if (!pairs.empty())
+      HIPTRY(c, hipMemcpy(c->d_lcfo_pairs, pairs.data(), pairs.size() * sizeof(int),
+                          hipMemcpyHostToDevice));
+    if (!axes.empty())
+      HIPTRY(c, hipMemcpy(c->d_lcfo_axes, axes.data(), axes.size() * sizeof(int2),
+                          hipMemcpyHostToDevice));
+    c->lcfo_pairs = P;
+  }
+  // 1. selection: eigenvalues are ascending per fragment, so the orbitals below
+  //    eps_cut are the first k of each fragment
+  std::vector<double> eps(c->M_tot);
+  HIPTRY(c, hipMemcpyAsync(eps.data(), c->d_eps, eps.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+  HIPTRY(c, hipStreamSynchronize(s));
+  std::vector<int> ksel(c->nF, 0);
+  for (int f = 0; f < c->nF; ++f)
+    for (int i = 0; i < c->m[f]; ++i) ksel[f] += eps[c->moff[f] + i] < eps_cut ? 1 : 0;
+  HIPTRY(c, hipMemcpyAsync(c->d_lcfo_k, ksel.data(), ksel.size() * sizeof(int),
+                           hipMemcpyHostToDevice, s));
+  HIPTRY(c, hipEventRecord(c->ev0, s));
+  OrbSet o = c->orbset(0, c->nF);
+  launch_fill_int(c->d_flags, 1, 0, s);
+  // 2. core projection (FP64 copies of the selected orbitals)
+  if (c->precision == DCDFT_PREC_MIXED)
+    launch_lcfo_gather<float>(g, o, c->d_band_frag, c->d_lcfo_k, (const float *)c->d_psi,
+                              c->d_lcfo_lam, s);
+  else
+    launch_lcfo_gather<double>(g, o, c->d_band_frag, c->d_lcfo_k, (const double *)c->d_psi,
+                               c->d_lcfo_lam, s);
+  // 3. overlap S = <phibar_i|phibar_j> (Eq. (6)) and its eigenpairs
+  launch_gram<double>(g, o, 0, c->nF, c->gram_chunks, c->d_lcfo_lam, c->d_lcfo_lam, c->d_gpart, s);
+  launch_gram_reduce(g, o, 0, c->nF, c->gram_chunks, 1, c->d_gpart, c->d_s, nullptr, nullptr, s);
+  launch_syev(o, 0, c->nF, c->d_s, c->d_u, c->d_lcfo_sig, c->d_flags, s);
+  // 4. basis lambda = phibar V Sigma^-1/2 over the eigenvalues above lambda_cut (Eq. (7))
+  launch_lcfo_coeffs(o, c->d_u, c->d_lcfo_sig, lambda_cut, c->d_x, c->d_lcfo_nb, s);
+  launch_rot_ritz<double>(g, o, 0, c->nF, c->d_x, c->d_lcfo_lam, c->d_dpart, c->d_lcfo_w, s);
+  // 5. H^alpha lambda with each fragment's V_eff of the last step
+  apply_h_range<double>(c, 0, c->nF, c->d_lcfo_lam, c->d_lcfo_hlam);
+  // 6. same-fragment blocks <lambda_i|H^alpha lambda_j> and the neighbour products
+  launch_gram<double>(g, o, 0, c->nF, c->gram_chunks, c->d_lcfo_lam, c->d_lcfo_hlam, c->d_gpart, s);
+  launch_gram_reduce(g, o, 0, c->nF, c->gram_chunks, 0, c->d_gpart, c->d_bmat, nullptr, nullptr,
+                     s);
+  launch_lcfo_cross(g, o, c->lcfo_pairs, c->d_lcfo_pairs, c->d_lcfo_axes, c->d_lcfo_nb, c->d_lcfo_hlam,
+                    c->d_lcfo_lam, c->d_lcfo_x, s);
+  HIPTRY(c, hipGetLastError());
+  HIPTRY(c, hipEventRecord(c->ev1, s));
+  const long long mp2 = (long long)c->m_pad * c->m_pad;
+  std::vector<double> same((size_t)(c->nF * mp2)), cross((size_t)(c->lcfo_pairs * mp2));
+  std::vector<int> pairs((size_t)c->lcfo_pairs * 8);
+  int flags = 0;
+  c->lcfo_nb.assign(c->nF, 0);
+  HIPTRY(c, hipMemcpyAsync(c->lcfo_nb.data(), c->d_lcfo_nb, c->nF * sizeof(int),
+                           hipMemcpyDeviceToHost, s));
+  HIPTRY(c, hipMemcpyAsync(same.data(), c->d_bmat, same.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+  if (!cross.empty())
+    HIPTRY(c, hipMemcpyAsync(cross.data(), c->d_lcfo_x, cross.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+  if (!pairs.empty())
+    HIPTRY(c, hipMemcpyAsync(pairs.data(), c->d_lcfo_pairs, pairs.size() * sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+  HIPTRY(c, hipMemcpyAsync(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPTRY(c, hipStreamSynchronize(s));
+  if (flags & FLAG_EIG)
+    return set_err(c, DCDFT_ERR_EIG, "Jacobi eigensolver of an overlap matrix did not converge");
+  // 7. the global matrix of Eq. (9): same-fragment blocks as they are, neighbour
+  //    blocks 1/2 [<H^a lambda^a|lambda^b> + <lambda^a|H^b lambda^b>]
+  std::vector<long long> off(c->nF + 1, 0);
+  for (int f = 0; f < c->nF; ++f) off[f + 1] = off[f] + c->lcfo_nb[f];
+  const long long N = off[c->nF];
+  c->lcfo_H.assign((size_t)(N * N), 0.0);
+  for (int f = 0; f < c->nF; ++f)
+    for (int i = 0; i < c->lcfo_nb[f]; ++i)
+      for (int j = 0; j < c->lcfo_nb[f]; ++j)
+        c->lcfo_H[(off[f] + i) * N + off[f] + j] = same[f * mp2 + i * c->m_pad + j];
+  for (int p = 0; p < c->lcfo_pairs; ++p) {
+    const int a = pairs[8 * p], b = pairs[8 * p + 1];
+    const double *X = cross.data() + p * mp2;
+    for (int i = 0; i < c->lcfo_nb[a]; ++i)
+      for (int j = 0; j < c->lcfo_nb[b]; ++j) {
+        const double v = 0.5 * X[i * c->m_pad + j];
+        c->lcfo_H[(off[a] + i) * N + off[b] + j] += v;
+        c->lcfo_H[(off[b] + j) * N + off[a] + i] += v;
+      }
+  }
+  c->lcfo_ready = true;
+  if (info) {
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    info->n_basis = (int32_t)N;
+    info->n_pairs = c->lcfo_pairs;
+    info->ms = ms;
+  }
+  return DCDFT_OK;
+}
+
+dcdft_status dcdft_lcfo_basis(const dcdft_ctx *c, int32_t frag, double *host, size_t count,
+                              int32_t *nb) {
+  dcdft_ctx *cc = const_cast<dcdft_ctx *>(c);
+  if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  if (!c->lcfo_ready) return set_err(cc, DCDFT_ERR_ARG, "no DC-LCFO basis: call dcdft_lcfo_build");
+  if (frag < 0 || frag >= c->nF) return set_err(cc, DCDFT_ERR_ARG, "fragment index out of range");
+  const int k = c->lcfo_nb[frag];
+  if (nb) *nb = k;
+  if (!host) return DCDFT_OK;
+  const size_t need = (size_t)k * c->geo.n;
+  if (count < need)
+    return set_err(cc, DCDFT_ERR_ARG, fmt("buffer holds %zu values, %zu needed", count, need));
+  HIPTRY(cc, hipMemcpy(host, c->d_lcfo_lam + c->moff[frag] * (long long)c->geo.n, need * sizeof(double),
+                       hipMemcpyDeviceToHost));
+  return DCDFT_OK;
+}
+
+dcdft_status dcdft_lcfo_hamiltonian(const dcdft_ctx *c, double *host, size_t count,
+                                    int32_t *n_basis) {
+  dcdft_ctx *cc = const_cast<dcdft_ctx *>(c);
+  if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  if (!c->lcfo_ready) return set_err(cc, DCDFT_ERR_ARG, "no DC-LCFO basis: call dcdft_lcfo_build");
+  long long N = 0;
+  for (int k : c->lcfo_nb) N += k;
+  if (n_basis) *n_basis = (int32_t)N;
+  if (!host) return DCDFT_OK;
+  if (count < (size_t)(N * N))
+    return set_err(cc, DCDFT_ERR_ARG, fmt("buffer holds %zu values, %lld needed", count, N * N));
+  std::copy(c->lcfo_H.begin(), c->lcfo_H.end(), host);
+  return DCDFT_OK;
+}
+
 }  // extern "C"
 
 namespace {

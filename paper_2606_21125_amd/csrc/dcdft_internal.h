@@ -221,6 +221,17 @@ struct dcdft_ctx {
   hipGraphExec_t graph_exec = nullptr;
   bool use_graph = true;
   double template_xi = 0.0;    // xi of the density-template potential; 0: off
+  // DC-LCFO post-processing (built on request; FP64 arrays in the orbital layout)
+  double *d_lcfo_lam = nullptr, *d_lcfo_hlam = nullptr;  // basis, H^alpha basis [M_tot + m_pad][n]
+  double *d_lcfo_sig = nullptr, *d_lcfo_w = nullptr;  // overlap eigenvalues, core weights [M_tot]
+  int *d_lcfo_k = nullptr, *d_lcfo_nb = nullptr;      // selected orbitals, basis size [F]
+  int *d_lcfo_pairs = nullptr;                        // [P][8] neighbour pairs
+  int2 *d_lcfo_axes = nullptr;                        // per-axis overlap coordinates
+  double *d_lcfo_x = nullptr;                         // [P][m_pad][m_pad] cross products
+  int lcfo_pairs = -1;                                // -1: tables not built
+  std::vector<int> lcfo_nb;                           // basis functions per fragment
+  std::vector<double> lcfo_H;                         // global matrix, row-major
+  bool lcfo_ready = false;
   bool fixed_density = false;  // rho^in frozen: no Poisson, V_eff or mixing update in the step
   bool graph_timed = false;
   std::vector<PendingTimer> graph_timers;
@@ -334,6 +345,18 @@ void launch_ritz_combine(const OrbSet &o, int f0, int f1, const double *Linv, co
                          double *C, hipStream_t s);
 void launch_syev(const OrbSet &o, int f0, int f1, const double *Hs, double *U, double *eps,
                  int *flags, hipStream_t s);
+// DC-LCFO: core projection of the first k_sel[f] orbitals of every fragment into
+// FP64 arrays; basis coefficients from the overlap eigenpairs (nb[f] functions);
+// products between a fragment's H lambda and its neighbours' lambda on the
+// overlap of core b with box a
+template <typename T>
+void launch_lcfo_gather(const Geo &g, const OrbSet &o, const int *band_frag, const int *k_sel,
+                        const T *psi, double *phi, hipStream_t s);
+void launch_lcfo_coeffs(const OrbSet &o, const double *U, const double *sigma, double lambda_cut,
+                        double *Cm, int *nb, hipStream_t s);
+void launch_lcfo_cross(const Geo &g, const OrbSet &o, int n_pairs, const int *pairs,
+                       const int2 *axes, const int *nb, const double *hlam, const double *lam,
+                       double *X, hipStream_t s);
 // global chemical potential, occupations, band energy, entropy (one workgroup)
 void launch_fermi(const OrbSet &o, const double *eps, const double *w, double ne, double sigma,
                   double *occ, double *scal, int *flags, hipStream_t s);

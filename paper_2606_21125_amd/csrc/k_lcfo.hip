@@ -1,0 +1,151 @@
+// DC-LCFO post-processing kernels (Sec. 2.3, Eqs. (6)-(9)): core projection of the
+// selected fragment orbitals, the basis coefficients from the overlap eigenpairs,
+// and the inner products between neighbouring fragments.  The overlap and
+// same-fragment products, the overlap eigensolve, the rotation into the basis and
+// the Hamiltonian application reuse the SCF kernels on FP64 arrays in the
+// orbital layout [M_tot][n].
+#include "dcdft_internal.h"
+#include "device_common.h"
+
+namespace dcdft {
+namespace {
+
+// phibar[B][l] = psi[B][l] on core points of band B's fragment when B is among the
+// fragment's first k_sel orbitals (eigenvalues ascending: those below eps_cut),
+// 0 otherwise.
+template <typename T>
+__global__ void __launch_bounds__(256) k_lcfo_gather(Geo g, const int *__restrict__ band_frag,
+                                                     const long long *__restrict__ moff,
+                                                     const int *__restrict__ k_sel,
+                                                     long long total, const T *__restrict__ psi,
+                                                     double *__restrict__ phi) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const long long B = idx / g.n;
+  const int l = (int)(idx - B * g.n);
+  const int f = band_frag[B];
+  const int i = (int)(B - moff[f]);
+  const int lx = l % g.nl[0], ly = (l / g.nl[0]) % g.nl[1], lz = l / (g.nl[0] * g.nl[1]);
+  const bool core = lx >= g.b[0] && lx < g.b[0] + g.nc[0] && ly >= g.b[1] &&
+                    ly < g.b[1] + g.nc[1] && lz >= g.b[2] && lz < g.b[2] + g.nc[2];
+  phi[idx] = (i < k_sel[f] && core) ? (double)psi[idx] : 0.0;
+}
+
+// Basis coefficients of fragment f from the overlap eigenpairs (U columns,
+// sigma ascending): the eigenvalues above lambda_cut are a suffix of the sorted
+// list; column t of Cm is U[:, m - nb + t] / sqrt(sigma), t < nb, zero otherwise.
+__global__ void __launch_bounds__(256) k_lcfo_coeffs(OrbSet o, const double *__restrict__ U,
+                                                     const double *__restrict__ sigma,
+                                                     double lambda_cut, double *__restrict__ Cm,
+                                                     int *__restrict__ nb_out) {
+  const int f = blockIdx.x;
+  const int mf = o.m[f], mp = o.m_pad;
+  const double *sg = sigma + o.moff[f];
+  int nb = 0;
+  for (int l = 0; l < mf; ++l) nb += sg[l] > lambda_cut ? 1 : 0;
+  const double *Uf = U + (long long)f * mp * mp;
+  double *Cf = Cm + (long long)f * mp * mp;
+  for (int e = threadIdx.x; e < mp * mp; e += blockDim.x) {
+    const int j = e / mp, t = e % mp;
+    double v = 0.0;
+    if (t < nb && j < mf) {
+      const int l = mf - nb + t;
+      v = Uf[j * mp + l] / sqrt(sg[l]);
+    }
+    Cf[e] = v;
+  }
+  if (threadIdx.x == 0) nb_out[f] = nb;
+}
+
+// X[p][i][j] = dV sum over the points of core b inside the box of a of
+// (H^a lambda^a_i)(l_a) lambda^b_j(l_b), pair p = (a, b).  pairs[p] = {a, b,
+// cx, cy, cz, ox, oy, oz}: per axis c* overlapping coordinates listed from o*
+// in axes as (local coordinate in a's box, local coordinate in b's box).
+// 16 x 16 threads, each holding a 5 x 5 block of the (at most 80 x 80) result;
+// the points pass through LDS 32 at a time.
+__global__ void __launch_bounds__(256) k_lcfo_cross(Geo g, OrbSet o, const int *__restrict__ pairs,
+                                                    const int2 *__restrict__ axes,
+                                                    const int *__restrict__ nbasis,
+                                                    const double *__restrict__ hlam,
+                                                    const double *__restrict__ lam,
+                                                    double *__restrict__ X) {
+  constexpr int R = kMaxOrb / 16;
+  __shared__ double HA[kMaxOrb][33];
+  __shared__ double LB[kMaxOrb][33];
+  const int *pr = pairs + 8LL * blockIdx.x;
+  const int a = pr[0], b = pr[1], cx = pr[2], cy = pr[3], cz = pr[4];
+  const int ox = pr[5], oy = pr[6], oz = pr[7];
+  const int na = nbasis[a], nbb = nbasis[b];
+  const long long ra = o.moff[a] * (long long)g.n, rb = o.moff[b] * (long long)g.n;
+  const int npts = cx * cy * cz;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[R][R];
+  for (int i = 0; i < R; ++i)
+    for (int j = 0; j < R; ++j) acc[i][j] = 0.0;
+  for (int q0 = 0; q0 < npts; q0 += 32) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kMaxOrb * 32; e += blockDim.x) {
+      const int r = e >> 5, pt = e & 31, q = q0 + pt;
+      double va = 0.0, vb = 0.0;
+      if (q < npts) {
+        const int ix = q % cx, iy = (q / cx) % cy, iz = q / (cx * cy);
+        const int2 px = axes[ox + ix], py = axes[oy + iy], pz = axes[oz + iz];
+        const int la = px.x + g.nl[0] * (py.x + g.nl[1] * pz.x);
+        const int lb = px.y + g.nl[0] * (py.y + g.nl[1] * pz.y);
+        if (r < na) va = hlam[ra + (long long)r * g.n + la];
+        if (r < nbb) vb = lam[rb + (long long)r * g.n + lb];
+      }
+      HA[r][pt] = va;
+      LB[r][pt] = vb;
+    }
+    __syncthreads();
+    for (int pt = 0; pt < 32; ++pt) {
+      double x[R], y[R];
+      for (int i = 0; i < R; ++i) {
+        x[i] = HA[ty + 16 * i][pt];
+        y[i] = LB[tx + 16 * i][pt];
+      }
+      for (int i = 0; i < R; ++i)
+        for (int j = 0; j < R; ++j) acc[i][j] = fma(x[i], y[j], acc[i][j]);
+    }
+  }
+  const int mp = o.m_pad;
+  double *Xp = X + (long long)blockIdx.x * mp * mp;
+  for (int i = 0; i < R; ++i)
+    for (int j = 0; j < R; ++j) {
+      const int l = ty + 16 * i, l2 = tx + 16 * j;
+      if (l < mp && l2 < mp) Xp[l * mp + l2] = g.dv * acc[i][j];
+    }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_lcfo_gather(const Geo &g, const OrbSet &o, const int *band_frag, const int *k_sel,
+                        const T *psi, double *phi, hipStream_t s) {
+  const long long total = o.M_tot * (long long)g.n;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_lcfo_gather<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g,
+                     band_frag, o.moff, k_sel, total, psi, phi);
+}
+template void launch_lcfo_gather<double>(const Geo &, const OrbSet &, const int *, const int *,
+                                         const double *, double *, hipStream_t);
+template void launch_lcfo_gather<float>(const Geo &, const OrbSet &, const int *, const int *,
+                                        const float *, double *, hipStream_t);
+
+void launch_lcfo_coeffs(const OrbSet &o, const double *U, const double *sigma, double lambda_cut,
+                        double *Cm, int *nb, hipStream_t s) {
+  if (o.nfrag <= 0) return;
+  hipLaunchKernelGGL(k_lcfo_coeffs, dim3(o.nfrag), dim3(256), 0, s, o, U, sigma, lambda_cut, Cm,
+                     nb);
+}
+
+void launch_lcfo_cross(const Geo &g, const OrbSet &o, int n_pairs, const int *pairs,
+                       const int2 *axes, const int *nb, const double *hlam, const double *lam,
+                       double *X, hipStream_t s) {
+  if (n_pairs <= 0) return;
+  hipLaunchKernelGGL(k_lcfo_cross, dim3(n_pairs), dim3(256), 0, s, g, o, pairs, axes, nb, hlam,
+                     lam, X);
+}
+
+}  // namespace dcdft
