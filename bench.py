@@ -63,6 +63,53 @@ def cpu_baseline(cfg, max_workers: int = 16, min_seconds: float = 10.0) -> dict:
                        f"thread each), {elapsed:.1f} s wall")}
 
 
+def crossover(args, prec) -> dict:
+    """Per-step time of the conventional calculation (one fragment, no buffer,
+    ceil(1.2 N_e / 2) orbitals) and of DC-DFT (cores of one Si cube, buffers of 4
+    points, ceil(1.2 N_loc / 2) orbitals) on Si supercells, same kernels, same
+    precision.  The conventional side stops where one fragment would need more than
+    80 orbitals (the kernels' tile limit)."""
+    import torch
+    import workloads
+    from paper_2606_21125_amd import DCDFT
+    from paper_2606_21125_amd.binding import DcdftError
+
+    def timed(cfg):
+        try:
+            d = DCDFT.from_config(cfg, precision=prec)
+        except DcdftError as e:
+            return {"config": cfg.name, "error": str(e).split(":")[0],
+                    "orbitals": int(cfg.nstate_frag.max())}
+        if not args.no_autotune:
+            d.dcdft_autotune(args.tune_cache)
+        for _ in range(args.warmup):
+            d.dcdft_scf_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            d.dcdft_scf_step()
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+        d.close()
+        return {"config": cfg.name, "ms_per_step": round(ms, 3),
+                "orbitals": int(cfg.nstate_frag.sum()), "fragments": cfg.n_fragments}
+
+    rows = []
+    for cells in ((1, 1, 1), (2, 1, 1), (2, 2, 1), (2, 2, 2), (4, 4, 4)):
+        n_atoms = 8 * cells[0] * cells[1] * cells[2]
+        print(f"[bench] crossover: {n_atoms} atoms", file=sys.stderr, flush=True)
+        row = {"atoms": n_atoms, "grid": [16 * c for c in cells]}
+        row["conventional"] = timed(workloads.si_cells_config(cells))
+        if cells[0] >= 2:     # a buffered box must fit the cell (n_core + 2 b <= N)
+            nf = tuple(cells)
+            b = tuple(4 if c >= 2 else 0 for c in cells)
+            row["dc"] = timed(workloads.si_cells_config(cells, nf, b))
+        rows.append(row)
+    return {"metric": "SCF step time, conventional vs DC, Si cells", "unit": "ms/step",
+            "dtype": "f32/f64" if prec != 0 else "f64", "steps": args.steps,
+            "warmup": args.warmup, "data": "synthetic", "rows": rows}
+
+
 HLOC_KERNEL = {"plane": "k_hloc<{t}>", "halo_pd2": "k_hloc_halo<{t}, {nx}, 2, false>",
                "halo_pd3": "k_hloc_halo<{t}, {nx}, 3, false>",
                "halo_pd4": "k_hloc_halo<{t}, {nx}, 4, false>",
@@ -130,6 +177,10 @@ def main() -> int:
                     help="fixed-density DC: freeze rho_tot at a superposition of atomic "
                          "Gaussians and time the iterations without Poisson, V_eff or "
                          "mixing updates (no comparison runs, no CPU baseline)")
+    ap.add_argument("--crossover", action="store_true",
+                    help="instead of the benchmark line: time conventional (one fragment, "
+                         "no buffer) and DC steps on Si cells of 8 to 512 atoms and print "
+                         "that table as one JSON line")
     ap.add_argument("--lcfo", action="store_true",
                     help="after the timed steps, build the DC-LCFO basis and global matrix "
                          "(eps_cut = mu + 0.1 eV, lambda_cut = 1e-7) and report its time")
@@ -163,6 +214,9 @@ def main() -> int:
         print(f"[bench] copy probe: {n * 8} bytes read, {n * 8} bytes written",
               file=sys.stderr, flush=True)
         del src, dst
+    if args.crossover:
+        print(json.dumps(crossover(args, prec)), flush=True)
+        return 0
     cfg = workload_config(args.config)
     print(f"[bench] setup {cfg.name}: {cfg.system.n_atoms} atoms, grid {cfg.n_grid}, "
           f"{cfg.n_fragments} fragments of {cfg.fragment_shape}", file=sys.stderr, flush=True)

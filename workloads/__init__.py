@@ -9,5 +9,5 @@ computation they are compared on.
 """
 from .systems import (  # noqa: F401
     Species, System, RunConfig, diamond_si, water_box, config, CONFIG_NAMES,
-    fragment_valence_counts, superposed_density,
+    fragment_valence_counts, superposed_density, si_cells_config,
 )

@@ -267,6 +267,30 @@ def config(k: int, nstate: Optional[int] = None) -> RunConfig:
     raise ValueError(f"unknown config {k}")
 
 
+def si_cells_config(cells: Sequence[int], num_fragment: Sequence[int] = (1, 1, 1),
+                    buffer: Sequence[int] = (0, 0, 0), points_per_cell: int = 16,
+                    seed: int = 7, nstate: Optional[int] = None) -> RunConfig:
+    """Diamond Si supercell of ``cells`` cubes (a = 10.26 bohr, jitter 0.05 bohr) on
+    points_per_cell grid points per cube edge (h = 0.641 bohr, the grid density of
+    the other Si workloads).  With one fragment and no buffer this is the
+    conventional calculation of the same cell, with ceil(1.2 N_e / 2) orbitals;
+    with fragments, every fragment gets ceil(1.2 N_loc / 2) orbitals from the
+    valence inside its box (unless nstate is given)."""
+    sysm = diamond_si(cells, 10.26, 0.05, seed=seed)
+    n_grid = tuple(int(points_per_cell * c) for c in cells)
+    nf = int(np.prod(num_fragment))
+    if nstate is not None:
+        m = np.full(nf, nstate, dtype=np.int32)
+    elif nf == 1 and not any(buffer):
+        m = np.array([int(math.ceil(1.2 * sysm.n_electrons / 2.0))], dtype=np.int32)
+    else:
+        counts = fragment_valence_counts(sysm, n_grid, num_fragment, buffer)
+        m = np.ceil(1.2 * counts / 2.0).astype(np.int32)
+    name = f"si{sysm.n_atoms}_{'x'.join(map(str, num_fragment))}"
+    return RunConfig(name, sysm, n_grid, tuple(num_fragment), tuple(buffer), m,
+                     scf_iterations=20, seed=seed)
+
+
 def small_system(n_grid=(12, 12, 12), cell=(7.2, 7.2, 7.2), n_atoms=2, seed=11,
                  depth=-3.0, sigma=1.0, kb_e=1.0, kb_sigma=1.0, kb_rcut=2.4,
                  valence=2.0) -> System:
