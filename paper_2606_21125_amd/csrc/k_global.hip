@@ -71,13 +71,35 @@ __device__ inline long long global_of_local(const Geo &g, int f, int l) {
   return gx + (long long)g.N[0] * (gy + (long long)g.N[1] * gz);
 }
 
+// Two block sums with one exchange: each value is summed exactly as block_sum
+// sums it (wave sums, then the waves in order).  red holds 32 doubles.
+__device__ inline void block_sum2(double &a, double &b, double *red) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    red[wave] = a;
+    red[16 + wave] = b;
+  }
+  __syncthreads();
+  double ta = 0.0, tb = 0.0;
+  for (int w = 0; w < nw; ++w) {
+    ta += red[w];
+    tb += red[16 + w];
+  }
+  a = ta;
+  b = tb;
+}
+
 // N(mu) = sum 2 f((eps - mu) / sigma) w by bisection over the bracket
 // [min eps - 50 sigma, max eps + 50 sigma], one workgroup.
 __global__ void __launch_bounds__(1024) k_fermi(long long nb, const double *__restrict__ eps,
                                                 const double *__restrict__ w, double ne,
                                                 double sigma, double *__restrict__ occ,
                                                 double *__restrict__ scal, int *flags) {
-  __shared__ double red[16];
+  __shared__ double red[32];
   double cap = 0.0, lo = 1e300, hi = 1e300;
   for (long long i = threadIdx.x; i < nb; i += blockDim.x) {
     cap += 2.0 * w[i];
@@ -102,8 +124,8 @@ __global__ void __launch_bounds__(1024) k_fermi(long long nb, const double *__re
       cnt += 2.0 * fo * w[i];
       der += 2.0 * fo * (1.0 - fo) * w[i];
     }
-    cnt = block_sum(cnt, red);
-    der = block_sum(der, red) / sigma;
+    block_sum2(cnt, der, red);
+    der = der / sigma;
     if (fabs(cnt - ne) <= 1e-14 * ne) break;
     if (cnt < ne) lo = mu;
     else hi = mu;
@@ -131,8 +153,7 @@ __global__ void __launch_bounds__(1024) k_fermi(long long nb, const double *__re
     if (fo < 1.0) t += (1.0 - fo) * log(1.0 - fo);
     ent += -2.0 * w[i] * t;
   }
-  eb = block_sum(eb, red);
-  ent = block_sum(ent, red);
+  block_sum2(eb, ent, red);
   if (threadIdx.x == 0) {
     scal[SC_MU] = mu;
     scal[SC_EBAND] = eb;
@@ -153,9 +174,21 @@ __global__ void __launch_bounds__(256) k_density(Geo g, const long long *__restr
   if (idx >= (long long)(f1 - f0) * g.n) return;
   const int f = f0 + (int)(idx / g.n);
   const int l = (int)(idx % g.n);
+  const long long b1 = moff[f + 1];
+  const T *p = psi + l;
   double acc = 0.0;
-  for (long long B = moff[f]; B < moff[f + 1]; ++B) {
-    const double v = (double)psi[B * g.n + l];
+  long long B = moff[f];
+  // eight loads in flight, then the terms added in band order (the same sums as
+  // one band at a time)
+  for (; B + 8 <= b1; B += 8) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = (double)p[(B + k) * g.n];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += 2.0 * occ[B + k] * v[k] * v[k];
+  }
+  for (; B < b1; ++B) {
+    const double v = (double)p[B * g.n];
     acc += 2.0 * occ[B] * v * v;
   }
   rhof_out[(long long)f * g.n + l] = acc;
