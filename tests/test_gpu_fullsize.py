@@ -111,3 +111,50 @@ def test_fullsize_mixed_energy_against_fp64(k):
             print(f"config {k} after {lead} steps: E64 {e64:.10f} E32 {e32:.10f} "
                   f"dE/atom {de:.2e}", flush=True)
             assert de <= 1e-5
+
+
+def test_fullsize_lcfo_properties():
+    """DC-LCFO on the 512-atom cell after two mixed steps (the oracle cannot hold
+    this size whole): properties that hold at any size.  Every fragment's basis is
+    orthonormal and vanishes outside the core (Eq. (7)); the assembled matrix has
+    symmetric neighbour blocks, nonzero blocks only between fragments whose core
+    meets the other's box, and as many rows as basis functions."""
+    require_gpu()
+    from paper_2606_21125_amd import DCDFT, PREC_MIXED
+    cfg = workloads.config(2)
+    frags = build_fragments(cfg.n_grid, cfg.num_fragment, cfg.num_rgrid_buffer)
+    h = cfg.system.cell / np.array(cfg.n_grid)
+    dv = float(np.prod(h))
+    with DCDFT.from_config(cfg, precision=PREC_MIXED) as d:
+        for _ in range(2):
+            info = d.dcdft_scf_step()
+        li = d.dcdft_lcfo_build(info["mu"] + 0.1 / 27.211386, 1e-7)
+        print("lcfo", li, flush=True)
+        hm = d.dcdft_lcfo_hamiltonian()
+        assert hm.shape == (li["n_basis"], li["n_basis"])
+        nb = []
+        for a in range(cfg.n_fragments):
+            lam = d.dcdft_lcfo_basis(a)
+            nb.append(lam.shape[0])
+            if a in (0, 21, 63):
+                np.testing.assert_allclose(dv * lam @ lam.T, np.eye(lam.shape[0]), rtol=0,
+                                           atol=1e-11)
+                assert np.abs(lam[:, ~frags[a].core_mask]).max() == 0.0
+        assert sum(nb) == li["n_basis"]
+        off = np.concatenate([[0], np.cumsum(nb)])
+        ncore = np.array(cfg.n_grid) // np.array(cfg.num_fragment)
+        b = np.array(cfg.num_rgrid_buffer)
+        for a in (0, 21):
+            ca = np.array([a % 4, (a // 4) % 4, a // 16])
+            for c in range(cfg.n_fragments):
+                if c == a:
+                    continue
+                cc = np.array([c % 4, (c // 4) % 4, c // 16])
+                # periodic distance between core origins, in cores; neighbours are
+                # the 26 fragments one core away (a 4-point buffer is less than a core)
+                dist = np.abs(((cc - ca) + 2) % 4 - 2)
+                blk = hm[off[a]:off[a + 1], off[c]:off[c + 1]]
+                assert np.array_equal(blk, hm[off[c]:off[c + 1], off[a]:off[a + 1]].T)
+                if dist.max() > 1:
+                    assert np.abs(blk).max() == 0.0
+        assert np.all(b < ncore)
