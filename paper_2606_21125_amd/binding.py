@@ -333,6 +333,30 @@ class DCDFT:
         _check(self._lib.dcdft_set_density(self.ctx, _dptr(a), None if b is None else _dptr(b)),
                self.ctx)
 
+    def save_state(self, path: str) -> None:
+        """Checkpoint of the SCF state: rho_tot^in, every rho_alpha^in and every
+        fragment's orbitals (FP64), written with numpy.savez (no pickled objects).
+        The CG history is rebuilt in every step, so these arrays are the whole
+        state a later step reads."""
+        arrays = {"n_grid": np.array(self.n_grid), "nstate": np.array(self.nstate),
+                  "rho_in": self.dcdft_get_field(FIELD_RHO_IN),
+                  "rho_frag_in": np.stack([self.dcdft_get_fragment_field(f, FFIELD_RHO_IN)
+                                           for f in range(len(self.nstate))])}
+        for f in range(len(self.nstate)):
+            arrays[f"psi_{f}"] = self.dcdft_get_orbitals(f)
+        np.savez(path, **arrays)
+
+    def load_state(self, path: str) -> None:
+        """Restore a checkpoint written by save_state for the same grid and
+        fragment orbital counts."""
+        with np.load(path, allow_pickle=False) as z:
+            if (tuple(z["n_grid"]) != tuple(self.n_grid)
+                    or tuple(z["nstate"]) != tuple(self.nstate)):
+                raise ValueError("checkpoint does not match this context's grid or orbitals")
+            for f in range(len(self.nstate)):
+                self.dcdft_set_orbitals(f, z[f"psi_{f}"])
+            self.dcdft_set_density(z["rho_in"], z["rho_frag_in"])
+
     def dcdft_fix_density(self, fixed: bool = True) -> None:
         _check(self._lib.dcdft_fix_density(self.ctx, int(bool(fixed))), self.ctx)
 
