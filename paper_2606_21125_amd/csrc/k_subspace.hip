@@ -729,13 +729,14 @@ __device__ inline void lds_gemm_f64(const double *P, const double *Q, int ld, in
 //   Hs = sym(L^-1 M L^-T) = sym(<Psi, W>)  -> Hs (and its diagonal into adiag),
 //   B  = Hs L^-1                          -> Bm,
 // so that G = W - Hs Psi = L^-1 W' - B Psi' needs no second pass.
+// NT: 16-row tiles of the padded size (register blocks per thread are NT x NT)
+template <int NT>
 __global__ void __launch_bounds__(256) k_cholinv(OrbSet o, int f0, const double *__restrict__ S,
                                                  double *__restrict__ Linv, int *flags,
                                                  const double *__restrict__ M,
                                                  double *__restrict__ Hs,
                                                  double *__restrict__ adiag,
                                                  double *__restrict__ Bm) {
-  constexpr int NT = kMaxTiles;
   __shared__ double colb[2][kMaxOrb], xrowb[2][kMaxOrb];
   __shared__ double B0[kMaxOrb * (kMaxOrb + 1)];
   __shared__ double B1[kMaxOrb * (kMaxOrb + 1)];
@@ -1330,8 +1331,18 @@ void launch_gram_reduce_pair(const Geo &g, const OrbSet &o, int f0, int f1, int 
 void launch_cholinv(const OrbSet &o, int f0, int f1, const double *S, double *Linv, int *flags,
                     hipStream_t s, const double *M, double *Hs, double *adiag, double *Bm) {
   if (f1 <= f0) return;
-  hipLaunchKernelGGL(k_cholinv, dim3(f1 - f0), dim3(256), 0, s, o, f0, S, Linv, flags, M, Hs,
-                     adiag, Bm);
+  switch (o.tiles) {
+#define DCDFT_CHOLINV(NT)                                                                       \
+  hipLaunchKernelGGL(k_cholinv<NT>, dim3(f1 - f0), dim3(256), 0, s, o, f0, S, Linv, flags, M, Hs, \
+                     adiag, Bm);                                                                \
+  break
+    case 1: DCDFT_CHOLINV(1);
+    case 2: DCDFT_CHOLINV(2);
+    case 3: DCDFT_CHOLINV(3);
+    case 4: DCDFT_CHOLINV(4);
+    default: DCDFT_CHOLINV(5);
+#undef DCDFT_CHOLINV
+  }
 }
 
 void launch_ritz_combine(const OrbSet &o, int f0, int f1, const double *Linv, const double *U,
