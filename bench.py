@@ -265,7 +265,7 @@ def main() -> int:
                 "ms_device": round(li["ms"], 3), "ms_wall": round(wall, 3),
                 "eps_cut": eps_cut, "lambda_cut": 1e-7,
                 "note": "device time from the core projection to the neighbour products; "
-                        "wall time adds the host assembly of the dense global matrix"}
+                        "wall time adds the copies of the blocks to the host"}
     d.close()
     elapsed = t1 - t0
     ms_per_step = 1000.0 * elapsed / args.steps

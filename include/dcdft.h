@@ -226,6 +226,14 @@ dcdft_status dcdft_lcfo_basis(const dcdft_ctx *c, int32_t frag, double *host, si
 dcdft_status dcdft_lcfo_hamiltonian(const dcdft_ctx *c, double *host, size_t count,
                                     int32_t *n_basis);
 
+/* One block of that matrix, rows of fragment a's basis and columns of b's, host
+ * row-major [rows][cols]: the same-fragment block for a == b, the symmetrised
+ * neighbour block otherwise (zero for fragments that are not neighbours); the same
+ * values as the dense matrix without forming it.  host NULL queries the shape.
+ * Errors: ARG (no build, index, buffer smaller than rows cols). */
+dcdft_status dcdft_lcfo_block(const dcdft_ctx *c, int32_t a, int32_t b, double *host,
+                              size_t count, int32_t *rows, int32_t *cols);
+
 /* H^alpha psi for m vectors of fragment frag with its V_eff of the last step
  * (after setup: V_loc + V_xc of the uniform density, V_H = 0), Eq. (5):
  * kinetic (nine-point FD, periodic on the fragment box) + V_eff + V_NL.

@@ -30,6 +30,7 @@ EXPORTED = [
     "dcdft_eigenvalues", "dcdft_fragment_info", "dcdft_get_field", "dcdft_get_fragment_field",
     "dcdft_get_orbitals", "dcdft_set_orbitals", "dcdft_set_density", "dcdft_fix_density",
     "dcdft_set_template", "dcdft_lcfo_build", "dcdft_lcfo_basis", "dcdft_lcfo_hamiltonian",
+    "dcdft_lcfo_block",
     "dcdft_apply_h",
     "dcdft_band_energy", "dcdft_kernel_timing", "dcdft_kernel_time", "dcdft_autotune",
     "dcdft_get_launch", "dcdft_set_launch",
@@ -134,6 +135,8 @@ def load_library(path: Optional[str] = None):
                               ctypes.POINTER(DcdftLcfoInfo)], ctypes.c_int),
         "dcdft_lcfo_basis": ([vp, ctypes.c_int32, pd, ctypes.c_size_t, pi], ctypes.c_int),
         "dcdft_lcfo_hamiltonian": ([vp, pd, ctypes.c_size_t, pi], ctypes.c_int),
+        "dcdft_lcfo_block": ([vp, ctypes.c_int32, ctypes.c_int32, pd, ctypes.c_size_t, pi, pi],
+                             ctypes.c_int),
         "dcdft_apply_h": ([vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32],
                           ctypes.c_int),
         "dcdft_band_energy": ([vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32, vp,
@@ -381,6 +384,15 @@ class DCDFT:
         _check(self._lib.dcdft_lcfo_hamiltonian(self.ctx, None, 0, ctypes.byref(nb)), self.ctx)
         out = np.empty((nb.value, nb.value))
         _check(self._lib.dcdft_lcfo_hamiltonian(self.ctx, _dptr(out), out.size, None), self.ctx)
+        return out
+
+    def dcdft_lcfo_block(self, a: int, b: int) -> np.ndarray:
+        rows, cols = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(self._lib.dcdft_lcfo_block(self.ctx, a, b, None, 0, ctypes.byref(rows),
+                                          ctypes.byref(cols)), self.ctx)
+        out = np.empty((rows.value, cols.value))
+        _check(self._lib.dcdft_lcfo_block(self.ctx, a, b, _dptr(out), out.size, None, None),
+               self.ctx)
         return out
 
     def dcdft_apply_h(self, frag: int, psi, hpsi, prec: int = PREC_FP64) -> None:

@@ -1466,26 +1466,14 @@ dcdft_status dcdft_lcfo_build(dcdft_ctx *c, double eps_cut, double lambda_cut,
   HIPTRY(c, hipStreamSynchronize(s));
   if (flags & FLAG_EIG)
     return set_err(c, DCDFT_ERR_EIG, "Jacobi eigensolver of an overlap matrix did not converge");
-  // 7. the global matrix of Eq. (9): same-fragment blocks as they are, neighbour
-  //    blocks 1/2 [<H^a lambda^a|lambda^b> + <lambda^a|H^b lambda^b>]
-  std::vector<long long> off(c->nF + 1, 0);
-  for (int f = 0; f < c->nF; ++f) off[f + 1] = off[f] + c->lcfo_nb[f];
-  const long long N = off[c->nF];
-  c->lcfo_H.assign((size_t)(N * N), 0.0);
-  for (int f = 0; f < c->nF; ++f)
-    for (int i = 0; i < c->lcfo_nb[f]; ++i)
-      for (int j = 0; j < c->lcfo_nb[f]; ++j)
-        c->lcfo_H[(off[f] + i) * N + off[f] + j] = same[f * mp2 + i * c->m_pad + j];
-  for (int p = 0; p < c->lcfo_pairs; ++p) {
-    const int a = pairs[8 * p], b = pairs[8 * p + 1];
-    const double *X = cross.data() + p * mp2;
-    for (int i = 0; i < c->lcfo_nb[a]; ++i)
-      for (int j = 0; j < c->lcfo_nb[b]; ++j) {
-        const double v = 0.5 * X[i * c->m_pad + j];
-        c->lcfo_H[(off[a] + i) * N + off[b] + j] += v;
-        c->lcfo_H[(off[b] + j) * N + off[a] + i] += v;
-      }
-  }
+  // 7. keep the blocks of the global matrix of Eq. (9) (assembled on request)
+  c->lcfo_same.swap(same);
+  c->lcfo_cross.swap(cross);
+  c->lcfo_pair_of.assign((size_t)c->nF * c->nF, -1);
+  for (int p = 0; p < c->lcfo_pairs; ++p)
+    c->lcfo_pair_of[(size_t)pairs[8 * p] * c->nF + pairs[8 * p + 1]] = p;
+  long long N = 0;
+  for (int f = 0; f < c->nF; ++f) N += c->lcfo_nb[f];
   c->lcfo_ready = true;
   if (info) {
     float ms = 0.0f;
@@ -1514,18 +1502,65 @@ dcdft_status dcdft_lcfo_basis(const dcdft_ctx *c, int32_t frag, double *host, si
   return DCDFT_OK;
 }
 
+// Element (i, j) of the block of fragments a != b: 1/2 [<H^a lambda^a_i|lambda^b_j> +
+// <lambda^a_i|H^b lambda^b_j>] from the two ordered-pair products.
+static double lcfo_cross_elem(const dcdft_ctx *c, int a, int b, int i, int j) {
+  const long long mp2 = (long long)c->m_pad * c->m_pad;
+  const int pab = c->lcfo_pair_of[(size_t)a * c->nF + b];
+  const int pba = c->lcfo_pair_of[(size_t)b * c->nF + a];
+  const double xab = pab < 0 ? 0.0 : c->lcfo_cross[pab * mp2 + (long long)i * c->m_pad + j];
+  const double xba = pba < 0 ? 0.0 : c->lcfo_cross[pba * mp2 + (long long)j * c->m_pad + i];
+  return 0.5 * xab + 0.5 * xba;
+}
+
 dcdft_status dcdft_lcfo_hamiltonian(const dcdft_ctx *c, double *host, size_t count,
                                     int32_t *n_basis) {
   dcdft_ctx *cc = const_cast<dcdft_ctx *>(c);
   if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
   if (!c->lcfo_ready) return set_err(cc, DCDFT_ERR_ARG, "no DC-LCFO basis: call dcdft_lcfo_build");
-  long long N = 0;
-  for (int k : c->lcfo_nb) N += k;
+  std::vector<long long> off(c->nF + 1, 0);
+  for (int f = 0; f < c->nF; ++f) off[f + 1] = off[f] + c->lcfo_nb[f];
+  const long long N = off[c->nF];
   if (n_basis) *n_basis = (int32_t)N;
   if (!host) return DCDFT_OK;
   if (count < (size_t)(N * N))
     return set_err(cc, DCDFT_ERR_ARG, fmt("buffer holds %zu values, %lld needed", count, N * N));
-  std::copy(c->lcfo_H.begin(), c->lcfo_H.end(), host);
+  std::fill(host, host + N * N, 0.0);
+  const long long mp2 = (long long)c->m_pad * c->m_pad;
+  for (int a = 0; a < c->nF; ++a)
+    for (int i = 0; i < c->lcfo_nb[a]; ++i)
+      for (int j = 0; j < c->lcfo_nb[a]; ++j)
+        host[(off[a] + i) * N + off[a] + j] = c->lcfo_same[a * mp2 + (long long)i * c->m_pad + j];
+  for (int a = 0; a < c->nF; ++a)
+    for (int b = 0; b < c->nF; ++b) {
+      if (b == a || (c->lcfo_pair_of[(size_t)a * c->nF + b] < 0 &&
+                     c->lcfo_pair_of[(size_t)b * c->nF + a] < 0))
+        continue;
+      for (int i = 0; i < c->lcfo_nb[a]; ++i)
+        for (int j = 0; j < c->lcfo_nb[b]; ++j)
+          host[(off[a] + i) * N + off[b] + j] = lcfo_cross_elem(c, a, b, i, j);
+    }
+  return DCDFT_OK;
+}
+
+dcdft_status dcdft_lcfo_block(const dcdft_ctx *c, int32_t a, int32_t b, double *host,
+                              size_t count, int32_t *rows, int32_t *cols) {
+  dcdft_ctx *cc = const_cast<dcdft_ctx *>(c);
+  if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  if (!c->lcfo_ready) return set_err(cc, DCDFT_ERR_ARG, "no DC-LCFO basis: call dcdft_lcfo_build");
+  if (a < 0 || a >= c->nF || b < 0 || b >= c->nF)
+    return set_err(cc, DCDFT_ERR_ARG, "fragment index out of range");
+  const int na = c->lcfo_nb[a], nb = c->lcfo_nb[b];
+  if (rows) *rows = na;
+  if (cols) *cols = nb;
+  if (!host) return DCDFT_OK;
+  if (count < (size_t)na * nb)
+    return set_err(cc, DCDFT_ERR_ARG, fmt("buffer holds %zu values, %d needed", count, na * nb));
+  const long long mp2 = (long long)c->m_pad * c->m_pad;
+  for (int i = 0; i < na; ++i)
+    for (int j = 0; j < nb; ++j)
+      host[(size_t)i * nb + j] = a == b ? c->lcfo_same[a * mp2 + (long long)i * c->m_pad + j]
+                                        : lcfo_cross_elem(c, a, b, i, j);
   return DCDFT_OK;
 }
 

@@ -230,7 +230,9 @@ struct dcdft_ctx {
   double *d_lcfo_x = nullptr;                         // [P][m_pad][m_pad] cross products
   int lcfo_pairs = -1;                                // -1: tables not built
   std::vector<int> lcfo_nb;                           // basis functions per fragment
-  std::vector<double> lcfo_H;                         // global matrix, row-major
+  std::vector<double> lcfo_same;                      // [F][m_pad][m_pad] same-fragment blocks
+  std::vector<double> lcfo_cross;                     // [P][m_pad][m_pad] neighbour products
+  std::vector<int> lcfo_pair_of;                      // [F][F] pair index of (a, b), -1: none
   bool lcfo_ready = false;
   bool fixed_density = false;  // rho^in frozen: no Poisson, V_eff or mixing update in the step
   bool graph_timed = false;

@@ -130,6 +130,7 @@ def test_null_safe_calls(lib):
     assert lib.dcdft_lcfo_build(None, 0.0, 1e-7, None) == -1
     assert lib.dcdft_lcfo_hamiltonian(None, None, 0, None) == -1
     assert lib.dcdft_lcfo_basis(None, 0, None, 0, None) == -1
+    assert lib.dcdft_lcfo_block(None, 0, 0, None, 0, None, None) == -1
     assert lib.dcdft_autotune(None, None, None) == -1
     assert lib.dcdft_get_launch(None, None, None, None, None, None) == -1
     assert lib.dcdft_set_launch(None, 1, 4, 1, 2) == -1

@@ -110,6 +110,14 @@ def test_lcfo_matches_oracle(which):
         print(which, info, "eps_cut", ecut, "lambda_cut", lcut)
         assert info["n_basis"] == sum(b.shape[0] for b in basis)
         _compare(o, d, cfg, basis, h_ref, 1e-9, 1e-8)
+        # every block accessed alone equals its slice of the dense matrix
+        h = d.dcdft_lcfo_hamiltonian()
+        nb = [b.shape[0] for b in basis]
+        off = np.concatenate([[0], np.cumsum(nb)])
+        for a in range(cfg.n_fragments):
+            for b in range(cfg.n_fragments):
+                assert np.array_equal(d.dcdft_lcfo_block(a, b),
+                                      h[off[a]:off[a + 1], off[b]:off[b + 1]]), (a, b)
         # a second build with a lower cut-off selects fewer functions
         d.dcdft_lcfo_build(ecut - 0.05, lcut)
         assert d.dcdft_lcfo_hamiltonian().shape[0] < h_ref.shape[0]
