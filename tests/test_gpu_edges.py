@@ -1,0 +1,56 @@
+"""Edge sizes of the fragment eigenproblem against the FP64 oracle: the largest
+orbital count the kernels hold (80 = five 16-wide tiles), a single orbital (1 x 1
+Gram, Cholesky and eigenproblem; capacity exactly N_e, so mu sits at the top of the
+bracket, where mu itself is not unique and is not compared), and orbital counts on and next to tile boundaries in one batch.
+Tolerances as for the SCF step."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_common import l1_over_ne, require_gpu
+from tests.helpers import tiny_config
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(cfg, **kw):
+    from paper_2606_21125_amd import DCDFT
+    return DCDFT.from_config(cfg, **kw)
+
+
+def _follow(cfg, steps, check_mu=True):
+    o = oracle.OracleSCF(cfg)
+    with _gpu(cfg) as d:
+        for k in range(steps):
+            ri, gi = o.step(), d.dcdft_scf_step()
+            print(cfg.name, k, ri["mu"], gi["mu"])
+            if check_mu:
+                assert abs(ri["mu"] - gi["mu"]) < 1e-10
+            for f in range(cfg.n_fragments):
+                np.testing.assert_allclose(d.dcdft_eigenvalues(f)[0], o.eps[f], rtol=0,
+                                           atol=1e-10)
+            assert l1_over_ne(d.dcdft_density(), o.rho_out, o.dv, o.ne) < 1e-9
+            assert abs(ri["e_total"] - gi["e_total"]) < 1e-8 * max(1.0, abs(ri["e_total"]))
+
+
+def test_largest_orbital_count():
+    require_gpu()
+    _follow(workloads.config(1, nstate=80), 2)
+
+
+def test_single_orbital_exact_capacity():
+    require_gpu()
+    cfg = tiny_config(n_grid=(12, 12, 12), cell=(7.2, 7.2, 7.2), n_atoms=1, nstate=1,
+                      valence=2.0, smearing=0.05)
+    # every mu far enough above the one eigenvalue gives N_e to rounding, so mu is
+    # not unique here; the occupation (1 to rounding), density and energy are
+    _follow(cfg, 3, check_mu=False)
+
+
+def test_tile_boundary_counts_in_one_batch():
+    require_gpu()
+    cfg = tiny_config(n_grid=(12, 12, 10), cell=(7.2, 7.2, 6.0), n_atoms=5, nstate=16,
+                      num_fragment=(2, 2, 1), buffer=(2, 3, 0), smearing=0.05, valence=2.0)
+    cfg.nstate_frag = np.array([16, 32, 15, 33], dtype=np.int32)
+    _follow(cfg, 3)
