@@ -204,8 +204,9 @@ dcdft_status dcdft_set_template(dcdft_ctx *c, double xi);
  * of the global matrix is not part of this library.  The first call allocates
  * device memory (two FP64 arrays of the orbital size and the pair tables), kept
  * until dcdft_destroy; the call overwrites work arrays, never the SCF state.
- * Errors: ARG (no step taken yet, non-finite eps_cut, lambda_cut not > 0), EIG,
- * OOM, HIP. */
+ * Errors: ARG (no step taken yet, non-finite eps_cut, lambda_cut not > 0, or a
+ * projector region too dense for the FP64 projector kernels' 64 KB of LDS, which
+ * a mixed-precision setup does not check), EIG, OOM, HIP. */
 typedef struct {
   int32_t n_basis;              /* basis functions over all fragments               */
   int32_t n_pairs;              /* ordered fragment pairs with a neighbour block    */

@@ -1380,6 +1380,17 @@ dcdft_status dcdft_lcfo_build(dcdft_ctx *c, double eps_cut, double lambda_cut,
   if (c->iter < 1) return set_err(c, DCDFT_ERR_ARG, "no eigenpairs yet: run dcdft_scf_step first");
   const Geo &g = c->geo;
   hipStream_t s = c->stream;
+  {
+    // the basis is FP64 whatever the step's precision: the FP64 projector kernels
+    // must fit their LDS (setup checked the step's own precision only)
+    const size_t need = std::max(kb_lds_bytes(g, c->KS, c->tiles, sizeof(double), true),
+                                 kb_lds_bytes(g, c->KS, c->tiles, sizeof(double), false));
+    if (need > 65536)
+      return set_err(c, DCDFT_ERR_ARG,
+                     fmt("%d projectors meet one projector region: the FP64 projector kernels "
+                         "of the DC-LCFO build would need %zu bytes of LDS (at most 65536)",
+                         c->KS, need));
+  }
   c->lcfo_ready = false;
   const long long rows = c->M_tot + c->m_pad;
   if (!c->d_lcfo_lam) {
