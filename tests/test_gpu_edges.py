@@ -54,3 +54,35 @@ def test_tile_boundary_counts_in_one_batch():
                       num_fragment=(2, 2, 1), buffer=(2, 3, 0), smearing=0.05, valence=2.0)
     cfg.nstate_frag = np.array([16, 32, 15, 33], dtype=np.int32)
     _follow(cfg, 3)
+
+
+def test_no_atoms_reaches_the_closed_form_spectrum():
+    """No atoms (an empty projector table and V_loc = 0), two electrons in the k = 0
+    state: the density stays uniform, so V_H = 0 and V_xc is the constant of the
+    uniform density, and the CG eigensolver must reach the closed-form spectrum of
+    the nine-point Laplacian, eps(k) = sum_d (-c0 - 2 sum_j c_j cos(2 pi j k_d / n_d))
+    / (2 h^2), shifted by that constant."""
+    require_gpu()
+    import math
+    from oracle.grid import FD_COEFFS
+    from oracle.model import lda_pz81
+    from paper_2606_21125_amd import DCDFT
+    from workloads.systems import SI
+    n, L = 10, 5.0
+    h = L / n
+    c = FD_COEFFS
+    lam1 = np.array([(-c[0] - 2 * sum(c[j] * math.cos(2 * math.pi * j * k / n)
+                                      for j in range(1, 5))) / (2 * h * h) for k in range(n)])
+    spec = np.sort((lam1[:, None, None] + lam1[None, :, None] + lam1[None, None, :]).ravel())
+    ne = 2.0
+    _, vxc = lda_pz81(np.array([ne / L ** 3]))
+    with DCDFT((n, n, n), (L, L, L), (1, 1, 1), (0, 0, 0), np.zeros((0, 3)),
+               np.zeros(0, dtype=np.int32), [SI], np.array([7], dtype=np.int32), ne,
+               smearing=0.05, cg_sweeps=6) as d:
+        d.dcdft_fix_density(True)
+        for _ in range(40):
+            info = d.dcdft_scf_step()
+        eps, w = d.dcdft_eigenvalues(0)
+        np.testing.assert_allclose(eps, spec[:7] + vxc[0], rtol=0, atol=1e-10)
+        np.testing.assert_allclose(w, np.ones(7), rtol=0, atol=1e-12)
+        assert abs(info["charge"] - ne) < 1e-12
