@@ -86,3 +86,36 @@ def test_no_atoms_reaches_the_closed_form_spectrum():
         np.testing.assert_allclose(eps, spec[:7] + vxc[0], rtol=0, atol=1e-10)
         np.testing.assert_allclose(w, np.ones(7), rtol=0, atol=1e-12)
         assert abs(info["charge"] - ne) < 1e-12
+
+
+def test_shift_by_one_core_permutes_the_fragments():
+    """Moving every atom and the frozen density by one core length along x maps
+    fragment (ax, ay, az) onto ((ax + 1) mod 2, ay, az): after the fragment
+    eigensolvers have converged in that fixed potential, each fragment's lowest
+    eigenvalues equal those of its image (a check of the box geometry, periodic
+    wrap, projector tables and gathers that needs no oracle)."""
+    require_gpu()
+    from paper_2606_21125_amd import DCDFT
+    cfg = workloads.config(1)
+    sysm = cfg.system
+    nx = cfg.n_grid[0]
+    ncore = nx // cfg.num_fragment[0]
+    h = sysm.cell[0] / nx
+    rho = workloads.superposed_density(sysm, cfg.n_grid)
+    pos_s = sysm.positions.copy()
+    pos_s[:, 0] = np.mod(pos_s[:, 0] + ncore * h, sysm.cell[0])
+    rho_s = np.roll(rho, ncore, axis=2)
+    eps = []
+    for pos, rh in ((sysm.positions, rho), (pos_s, rho_s)):
+        with DCDFT(cfg.n_grid, sysm.cell, cfg.num_fragment, cfg.num_rgrid_buffer, pos,
+                   sysm.species_index, sysm.species, cfg.nstate_frag, sysm.n_electrons,
+                   smearing=cfg.smearing, cg_sweeps=8) as d:
+            d.dcdft_set_density(rh)
+            d.dcdft_fix_density(True)
+            for _ in range(30):
+                d.dcdft_scf_step()
+            eps.append([d.dcdft_eigenvalues(f)[0] for f in range(cfg.n_fragments)])
+    for f in range(cfg.n_fragments):
+        ax, ay, az = f % 2, (f // 2) % 2, f // 4
+        fs = (ax + 1) % 2 + 2 * (ay + 2 * az)
+        np.testing.assert_allclose(eps[1][fs][:48], eps[0][f][:48], rtol=0, atol=1e-8)
