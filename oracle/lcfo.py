@@ -18,6 +18,12 @@ box with its own V_eff:
   different fragments: 1/2 [<H^a lambda_i^a|lambda_j^b> + <lambda_i^a|H^b lambda_j^b>]
 with every inner product taken on the global grid (each function placed at its
 fragment box's global points, zero elsewhere).
+
+Pins (tests/test_oracle_lcfo.py): one unbuffered fragment gives the Ritz
+spectrum of the selected orbitals; buffers wider than the stencil and two
+projector radii give Lambda^T H Lambda with an independently built dense global
+Hamiltonian; narrow buffers give a symmetric matrix; the basis is orthonormal and
+its size matches the singular values of the projected orbitals.
 """
 from __future__ import annotations
 
