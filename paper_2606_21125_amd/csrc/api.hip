@@ -295,7 +295,13 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
   // tile do not fit the FP64 register budget well) except in the last sweep,
   // where both take Hs from <Psi', W'> and fold L^-1 into the Ritz rotation.
   constexpr bool fuse = sizeof(T) == 4;
-  apply_h_range<T>(c, f0, f1, psi, w);
+  if (c->pre_projected) {
+    // the projections of Psi were issued while the potentials were formed
+    hloc<T>(c, f0, f1, psi, w);
+    kb_apply<T>(c, f0, f1, w);
+  } else {
+    apply_h_range<T>(c, f0, f1, psi, w);
+  }
   for (int sw = 0; sw < c->sweeps; ++sw) {
     const bool last = sw + 1 == c->sweeps;
     if (sw == 0 || !fuse) {
@@ -731,22 +737,32 @@ void enqueue_step(dcdft_ctx *c) {
   hipStream_t s = c->stream;
   OrbSet o = c->orbset(0, c->nF);
   launch_fill_int(c->d_flags, 1, 0, s);
-  // With a frozen density V_H and V_eff were formed when it was fixed or set and
-  // do not change; otherwise:
-  if (!c->fixed_density) {
+  const int G = c->batched ? std::min(c->streams, c->nF) : 1;
+  // In the step graph with concurrent fragment groups and a spare stream, the
+  // potentials (steps 1-2) are formed on that stream while every group issues the
+  // projections of its orbitals, which do not read V_eff.
+  const bool overlap = G > 1 && G < dcdft_ctx::kMaxStreams && !c->timing && !c->fixed_density;
+  auto potentials = [&](hipStream_t ps) {
     // 1. Hartree potential of rho_tot^in
-    launch_poisson(g, c->d_rho_in, c->d_vh, c->d_fft_a, c->d_fft_b, c->d_qf, c->d_qi, c->d_lam, s);
+    launch_poisson(g, c->d_rho_in, c->d_vh, c->d_fft_a, c->d_fft_b, c->d_qf, c->d_qi, c->d_lam,
+                   ps);
     // 2. fragment effective potentials
     launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_rho_in,
-                c->template_xi, c->d_veff, c->d_veff32, s);
-  }
+                c->template_xi, c->d_veff, c->d_veff32, ps);
+  };
+  // With a frozen density V_H and V_eff were formed when it was fixed or set and
+  // do not change
+  if (!overlap && !c->fixed_density) potentials(s);
   // 3. fragment eigensolvers
   if (c->batched) {
     auto run = [&](int a, int b) {
       if (c->precision == DCDFT_PREC_MIXED) eigensolver_range<float>(c, a, b);
       else eigensolver_range<double>(c, a, b);
     };
-    const int G = std::min(c->streams, c->nF);
+    auto project = [&](int a, int b) {
+      if (c->precision == DCDFT_PREC_MIXED) kb_project<float>(c, a, b, (const float *)c->d_psi);
+      else kb_project<double>(c, a, b, (const double *)c->d_psi);
+    };
     if (G > 1 && !c->timing) {
       // G fragment groups of about M_tot / G orbitals each, concurrently
       int bound[dcdft_ctx::kMaxStreams + 1];
@@ -759,9 +775,20 @@ void enqueue_step(dcdft_ctx *c) {
       bound[G] = c->nF;
       hipEventRecord(c->ev_fork, s);
       for (int q = 1; q < G; ++q) hipStreamWaitEvent(c->xstreams[q], c->ev_fork, 0);
+      if (overlap) {
+        hipStreamWaitEvent(c->xstreams[G], c->ev_fork, 0);
+        potentials(c->xstreams[G]);
+        hipEventRecord(c->ev_pot, c->xstreams[G]);
+      }
       for (int q = 0; q < G; ++q) {
         c->xs = q ? c->xstreams[q] : s;
+        if (overlap) {
+          project(bound[q], bound[q + 1]);
+          hipStreamWaitEvent(c->xs, c->ev_pot, 0);
+          c->pre_projected = true;
+        }
         run(bound[q], bound[q + 1]);
+        c->pre_projected = false;
       }
       for (int q = 1; q < G; ++q) {
         hipEventRecord(c->ev_join[q], c->xstreams[q]);
@@ -867,6 +894,7 @@ void dcdft_destroy(dcdft_ctx *c) {
     if (c->ev_join[q]) hipEventDestroy(c->ev_join[q]);
   }
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_pot) hipEventDestroy(c->ev_pot);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1029,7 +1057,8 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
     return fail(DCDFT_ERR_HIP);
   }
   {
-    bool ok = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;
+    bool ok = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_pot, hipEventDisableTiming) == hipSuccess;
     for (int q = 1; q < dcdft_ctx::kMaxStreams && ok; ++q)
       ok = hipStreamCreateWithFlags(&c->xstreams[q], hipStreamNonBlocking) == hipSuccess &&
            hipEventCreateWithFlags(&c->ev_join[q], hipEventDisableTiming) == hipSuccess;

@@ -140,6 +140,8 @@ struct dcdft_ctx {
   int streams = 2;
   hipStream_t xstreams[kMaxStreams] = {};  // [0] unused (the context's stream)
   hipEvent_t ev_fork = nullptr, ev_join[kMaxStreams] = {};
+  hipEvent_t ev_pot = nullptr;   // V_eff formed (the potentials' stream of the step graph)
+  bool pre_projected = false;    // the step's first projections were issued before V_eff
   hipStream_t xs = nullptr;
   int iter = 0;
   int gram_chunks = 1;
