@@ -339,17 +339,22 @@ def main() -> int:
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(cfg)
+    kind = ("water-like cell" if cfg.name.startswith("water") else
+            "a-Si-like cell" if cfg.name.startswith("asi") else "diamond Si cell")
+    ms = [int(v) for v in cfg.nstate_frag]
+    orbitals = (f"{ms[0]} orbitals each" if min(ms) == max(ms)
+                else f"{min(ms)}-{max(ms)} orbitals per fragment")
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "SCF iter/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32/f64" if prec != PREC_FP64 else "f64",
         "data": "synthetic",
-        "config": {"workload": (f"{cfg.name}: {cfg.system.n_atoms}-atom a-Si-like cell, grid "
+        "config": {"workload": (f"{cfg.name}: {cfg.system.n_atoms}-atom {kind}, grid "
                                 f"{'x'.join(map(str, cfg.n_grid))}, "
                                 f"{'x'.join(map(str, cfg.num_fragment))} fragments of "
                                 f"{'x'.join(map(str, cfg.fragment_shape))} points, "
-                                f"{int(cfg.nstate_frag[0])} orbitals each, "
+                                f"{orbitals}, "
                                 f"{cfg.cg_sweeps} CG sweeps per SCF iteration"),
                    "n_fragments": cfg.n_fragments, "batched": bool(args.batched),
                    "precision": args.precision,

@@ -504,7 +504,10 @@ constexpr int kb_chunk() { return sizeof(T) == 4 ? 64 : 32; }
 // block (slots x points) with its orbital columns.  The beta block is evaluated
 // chunk by chunk into LDS by all threads (one point and KS / (256 / CH) slots
 // each), the next chunk while the products of the current one run; wave w
-// takes the orbital tiles w, w + 4 over every point.  The K index walks the
+// takes orbital tile w over every point, and with five tiles the fifth goes to
+// wave (workgroup index mod 4), so that no SIMD always takes the heavier wave.
+// Tiles at or beyond the fragment's orbital count are skipped (their partials
+// stay zero).  The K index walks the
 // points of a 16-point step as 4 (lane/16) + t, so every lane reads runs of 4
 // contiguous values of both operands (16-byte loads when VEC: n % 4 == 0); the
 // orbital values of the next chunk are loaded before the products of the
@@ -520,7 +523,8 @@ __global__ void __launch_bounds__(256) k_kb_project(Geo g, OrbSet o, KBTables kb
   constexpr int NS = CH / 16;                  // 16-point steps per chunk
   constexpr int BS = CH + 16 / (int)sizeof(T); // beta row stride (16-byte rows, skewed)
   constexpr int SG = 256 / CH;                 // slot groups of the evaluation
-  constexpr int JW = (TM + 3) / 4;             // orbital tiles per wave
+  constexpr int JW = (TM + 3) / 4;             // orbital tile items per wave
+  static_assert(JW <= 2, "at most eight orbital tiles");
   extern __shared__ __attribute__((aligned(16))) double kb_lds[];
   const int nx = g.nl[0], RR = region_nrows(g, kb);
   const int NCH = kb.RP / CH;
@@ -533,12 +537,30 @@ __global__ void __launch_bounds__(256) k_kb_project(Geo g, OrbSet o, KBTables kb
   const int mf = o.m[f];
   const int rmax = o.row_pad ? MP - 1 : mf - 1;
   const long long base = o.moff[f] * (long long)g.n;
+  // orbital tile of item q of this wave (TM when the item has none) and whether
+  // it holds orbitals of the fragment (uniform over the wave)
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  int jts[JW];
+  bool live[JW];
+#pragma unroll
+  for (int q = 0; q < JW; ++q) {
+    jts[q] = q == 0 ? wv : (wv == (int)(blockIdx.x & 3) ? 4 * q : TM);
+    if (jts[q] > TM) jts[q] = TM;
+    live[q] = jts[q] < TM && jts[q] * 16 < mf;
+  }
   auto load_x = [&](int ch, T (*bx)[NS][4]) {
 #pragma unroll
     for (int q = 0; q < JW; ++q) {
-      const int jt = wave + 4 * q;
+      const int jt = jts[q];
       const int orb = jt * 16 + r;
-      const bool ok = jt < TM && orb < mf;
+      const bool ok = live[q] && orb < mf;
+      if (!live[q]) {
+#pragma unroll
+        for (int u = 0; u < NS; ++u)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) bx[q][u][t] = (T)0;
+        continue;
+      }
       const T *row = x + base + (long long)(orb < rmax ? orb : rmax) * g.n;
 #pragma unroll
       for (int u = 0; u < NS; ++u) {
@@ -611,9 +633,10 @@ __global__ void __launch_bounds__(256) k_kb_project(Geo g, OrbSet o, KBTables kb
           T av[4];
           lds_read4(cur + (st * 16 + r) * BS + u * 16 + 4 * kk, av);
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
+          for (int q = 0; q < JW; ++q)
+            if (live[q])
 #pragma unroll
-            for (int q = 0; q < JW; ++q) acc[st][q] = MM::mma(av[t], bx[q][u][t], acc[st][q]);
+              for (int t = 0; t < 4; ++t) acc[st][q] = MM::mma(av[t], bx[q][u][t], acc[st][q]);
         }
     };
     if (nt <= 1)
@@ -635,7 +658,7 @@ __global__ void __launch_bounds__(256) k_kb_project(Geo g, OrbSet o, KBTables kb
   T *out = reinterpret_cast<T *>(part) + ((long long)f * kb.NR + reg) * kb.KS * o.m_pad;
 #pragma unroll
   for (int q = 0; q < JW; ++q) {
-    const int jt = wave + 4 * q;
+    const int jt = jts[q];
     if (jt >= TM) continue;
 #pragma unroll
     for (int st = 0; st < KT; ++st)
