@@ -513,7 +513,8 @@ constexpr int kb_chunk() { return sizeof(T) == 4 ? 64 : 32; }
 // orbital values of the next chunk are loaded before the products of the
 // current one (unconditional loads, rows and points clamped, values masked).
 template <typename T, int TM, int KT, bool VEC>
-__global__ void __launch_bounds__(256) k_kb_project(Geo g, OrbSet o, KBTables kb, int f0,
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && KT == 3 ? 3 : 1, 8))) k_kb_project(Geo g, OrbSet o, KBTables kb, int f0,
                                                     const T *__restrict__ x,
                                                     double *__restrict__ part) {
   typedef Mfma<T> MM;
