@@ -111,6 +111,15 @@ typedef struct {
   double residual_out_in;       /* dV sum |rho^out - rho^in| / N_e                  */
   double charge;                /* dV sum rho_tot^out                               */
   float ms_step;                /* device time of the step (ms)                     */
+  /* Device time of the step's phases (ms; they add up to ms_step less the host
+   * launch gap, -1 where the runtime could not time them):
+   *   ms_poisson       from the start to V_eff formed (Hartree solve, V_eff; the
+   *                    first projections of the orbitals overlap this phase),
+   *   ms_fragments     from there to the last fragment eigensolve finished,
+   *   ms_fermi_density chemical potential, densities, energy terms, mixing. */
+  float ms_poisson;
+  float ms_fragments;
+  float ms_fermi_density;
 } dcdft_scf_info;
 
 /* Validate p, build the fragment and projector tables, upload them, draw the
@@ -130,9 +139,12 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out);
  * V_eff of every fragment, cg_sweeps CG sweeps + Rayleigh-Ritz per fragment,
  * core weights, global mu, rho^out assembly (Eqs. (2)-(4)), energy, residuals,
  * linear mixing of rho_tot and of every fragment density.  info may be NULL.
- * Errors: CAPACITY (sum 2 w < N_e), NOT_SPD, EIG, NAN, HIP.  After an error the
- * orbitals and densities are unspecified; destroy the context or reset them
- * with dcdft_set_orbitals / dcdft_set_density. */
+ * Errors: CAPACITY (sum 2 w < N_e), NOT_SPD, EIG, NAN, HIP.  The step is atomic:
+ * after CAPACITY, NOT_SPD, EIG or NAN the context holds the state of the last
+ * completed step, bit for bit (orbitals, input and output densities, potentials,
+ * eigenvalues, weights, occupations, mixer history), and the iteration count is
+ * unchanged; info (if given) then carries the failed step's scalars.  After HIP
+ * the state is unspecified. */
 dcdft_status dcdft_scf_step(dcdft_ctx *c, dcdft_scf_info *info);
 
 /* Host copy of rho_tot^out of the last step (Eq. (2)), n = Nx Ny Nz doubles. */
@@ -167,7 +179,9 @@ dcdft_status dcdft_get_orbitals(const dcdft_ctx *c, int32_t frag, double *host, 
 dcdft_status dcdft_set_orbitals(dcdft_ctx *c, int32_t frag, const double *host, size_t count);
 
 /* Replace rho_tot^in (N doubles) and, if rho_frag_in is not NULL, every fragment's
- * rho_alpha^in ([F][n] doubles); with NULL each fragment gathers rho_tot^in. */
+ * rho_alpha^in ([F][n] doubles); with NULL each fragment gathers rho_tot^in.  V_H
+ * and V_eff are formed from the new density.  Errors: ARG (NULL), NAN (a value of
+ * either array not finite; nothing is changed), HIP. */
 dcdft_status dcdft_set_density(dcdft_ctx *c, const double *rho_tot_in, const double *rho_frag_in);
 
 /* Fixed-density DC (Sec. 2.6, third usage; Sec. 3.2): with fixed = 1 every later
@@ -238,7 +252,13 @@ dcdft_status dcdft_lcfo_block(const dcdft_ctx *c, int32_t a, int32_t b, double *
 /* H^alpha psi for m vectors of fragment frag with its V_eff of the last step
  * (after setup: V_loc + V_xc of the uniform density, V_H = 0), Eq. (5):
  * kinetic (nine-point FD, periodic on the fragment box) + V_eff + V_NL.
- * psi, hpsi: device [m][n] of double (prec 0) or float (prec 1); may not alias. */
+ * psi, hpsi: device [m][n] of double (prec 0) or float (prec 1); may not alias.
+ * The work runs on the context's stream, in chunks of at most m_pad vectors,
+ * with scratch the context allocated at setup (nothing is allocated per call).
+ * psi must be complete when the call is made (the call does not wait for work
+ * on other streams); hpsi is complete when the call returns (the call
+ * synchronises the context's stream).  Errors: ARG (NULL, fragment index, m < 0,
+ * prec, aliasing), HIP. */
 dcdft_status dcdft_apply_h(dcdft_ctx *c, int32_t frag, const void *psi, void *hpsi,
                            int32_t m, int32_t prec);
 
@@ -250,8 +270,11 @@ dcdft_status dcdft_apply_h(dcdft_ctx *c, int32_t frag, const void *psi, void *hp
  * psi, grad_psi: device [m][n], double (prec 0) or float (prec 1); f: device
  * double [m]; veff: device double [n] used as V_eff of the fragment, or NULL for
  * the fragment's V_eff of the last step; grad_v: device double [n]; energy:
- * device double [1].  Any of energy, grad_psi, grad_v may be NULL.  The call
- * allocates device scratch for H psi. */
+ * device double [1].  Any of energy, grad_psi, grad_v may be NULL.  H psi is
+ * formed chunk by chunk (at most m_pad vectors) in scratch the context allocated
+ * at setup; nothing is allocated per call.  Inputs must be complete when the call
+ * is made; outputs are complete when it returns (the context's stream is
+ * synchronised).  Errors: ARG (NULL psi or f, fragment index, m < 1, prec), HIP. */
 dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, const double *f,
                                int32_t m, int32_t prec, const double *veff, double *energy,
                                void *grad_psi, double *grad_v);

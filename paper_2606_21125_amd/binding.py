@@ -67,7 +67,9 @@ class DcdftScfInfo(ctypes.Structure):
     _fields_ = [("iter", ctypes.c_int32), ("mu", ctypes.c_double), ("e_total", ctypes.c_double),
                 ("e_band", ctypes.c_double), ("entropy", ctypes.c_double),
                 ("residual_paper", ctypes.c_double), ("residual_out_in", ctypes.c_double),
-                ("charge", ctypes.c_double), ("ms_step", ctypes.c_float)]
+                ("charge", ctypes.c_double), ("ms_step", ctypes.c_float),
+                ("ms_poisson", ctypes.c_float), ("ms_fragments", ctypes.c_float),
+                ("ms_fermi_density", ctypes.c_float)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -170,6 +172,14 @@ def dcdft_last_error(ctx) -> str:
 def _check(status: int, ctx=None):
     if status != DCDFT_OK:
         raise DcdftError(status, dcdft_last_error(ctx))
+
+
+def _device_inputs_ready(t) -> None:
+    """The library works on its own stream and does not wait for work queued on
+    torch's streams: finish what torch's current stream has queued (which
+    produced the tensors handed over) before the call."""
+    import torch
+    torch.cuda.current_stream(t.device).synchronize()
 
 
 def _dptr(a: np.ndarray):
@@ -338,10 +348,15 @@ class DCDFT:
 
     def save_state(self, path: str) -> None:
         """Checkpoint of the SCF state: rho_tot^in, every rho_alpha^in and every
-        fragment's orbitals (FP64), written with numpy.savez (no pickled objects).
-        The CG history is rebuilt in every step, so these arrays are the whole
-        state a later step reads."""
+        fragment's orbitals (FP64), written with numpy.savez (no pickled objects),
+        with the geometry and precision they belong to.  The CG history is rebuilt
+        in every step, so these arrays are the whole state a later step reads."""
+        p = self.params
         arrays = {"n_grid": np.array(self.n_grid), "nstate": np.array(self.nstate),
+                  "frag_shape": np.array(self.frag_shape),
+                  "num_fragment": np.array(list(p.num_fragment)),
+                  "num_rgrid_buffer": np.array(list(p.num_rgrid_buffer)),
+                  "precision": np.array(p.precision),
                   "rho_in": self.dcdft_get_field(FIELD_RHO_IN),
                   "rho_frag_in": np.stack([self.dcdft_get_fragment_field(f, FFIELD_RHO_IN)
                                            for f in range(len(self.nstate))])}
@@ -350,13 +365,31 @@ class DCDFT:
         np.savez(path, **arrays)
 
     def load_state(self, path: str) -> None:
-        """Restore a checkpoint written by save_state for the same grid and
-        fragment orbital counts."""
+        """Restore a checkpoint written by save_state for the same grid, fragment
+        decomposition, buffer, orbital counts and precision; every array's shape
+        is checked before anything is handed to the library."""
+        p = self.params
         with np.load(path, allow_pickle=False) as z:
-            if (tuple(z["n_grid"]) != tuple(self.n_grid)
-                    or tuple(z["nstate"]) != tuple(self.nstate)):
-                raise ValueError("checkpoint does not match this context's grid or orbitals")
-            for f in range(len(self.nstate)):
+            want = {"n_grid": tuple(self.n_grid), "nstate": tuple(int(v) for v in self.nstate),
+                    "frag_shape": tuple(self.frag_shape),
+                    "num_fragment": tuple(p.num_fragment),
+                    "num_rgrid_buffer": tuple(p.num_rgrid_buffer)}
+            for key, val in want.items():
+                if key not in z or tuple(int(v) for v in np.atleast_1d(z[key])) != val:
+                    raise ValueError(f"checkpoint {key} does not match this context ({val})")
+            if "precision" not in z or int(z["precision"]) != int(p.precision):
+                raise ValueError("checkpoint precision does not match this context")
+            nf = len(self.nstate)
+            if z["rho_in"].size != int(np.prod(self.n_grid)):
+                raise ValueError("checkpoint rho_in has the wrong size")
+            if z["rho_frag_in"].shape != (nf, self.n):
+                raise ValueError(f"checkpoint rho_frag_in is {z['rho_frag_in'].shape}, "
+                                 f"expected {(nf, self.n)}")
+            for f in range(nf):
+                if z[f"psi_{f}"].shape != (int(self.nstate[f]), self.n):
+                    raise ValueError(f"checkpoint psi_{f} is {z[f'psi_{f}'].shape}, expected "
+                                     f"{(int(self.nstate[f]), self.n)}")
+            for f in range(nf):
                 self.dcdft_set_orbitals(f, z[f"psi_{f}"])
             self.dcdft_set_density(z["rho_in"], z["rho_frag_in"])
 
@@ -398,6 +431,7 @@ class DCDFT:
     def dcdft_apply_h(self, frag: int, psi, hpsi, prec: int = PREC_FP64) -> None:
         """psi, hpsi: contiguous device tensors of shape (m, n)."""
         m = psi.shape[0]
+        _device_inputs_ready(psi)
         _check(self._lib.dcdft_apply_h(self.ctx, frag, ctypes.c_void_p(psi.data_ptr()),
                                        ctypes.c_void_p(hpsi.data_ptr()), m, prec), self.ctx)
 
@@ -438,6 +472,7 @@ class DCDFT:
         double or None; outputs are device tensors (energy (1,), grad_psi like psi,
         grad_v (n,) double)."""
         ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+        _device_inputs_ready(psi)
         _check(self._lib.dcdft_band_energy(self.ctx, frag, ctypes.c_void_p(psi.data_ptr()),
                                            ctypes.c_void_p(f.data_ptr()), psi.shape[0], prec,
                                            ptr(veff), ptr(energy), ptr(grad_psi), ptr(grad_v)),

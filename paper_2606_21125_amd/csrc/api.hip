@@ -284,7 +284,11 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
   OrbSet o = c->orbset(f0, f1);
   KBTables kb = c->kb();
   hipStream_t s = xstream(c);
-  T *psi = (T *)c->d_psi, *w = (T *)c->d_w, *p = (T *)c->d_p, *q = (T *)c->d_q;
+  // psi0: the orbitals of the last completed step, only read; the first band
+  // update writes the new orbitals into psi, the other buffer, and every later
+  // kernel works on psi (a failed step leaves psi0 as it was)
+  const T *psi0 = (const T *)c->d_psi;
+  T *psi = (T *)c->d_psi_next, *w = (T *)c->d_w, *p = (T *)c->d_p, *q = (T *)c->d_q;
   const double n = g.n, sz = sizeof(T);
   const double nb = orbitals_in(c, f0, f1);
   const double m2 = sum_m2(c, f0, f1);
@@ -297,33 +301,34 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
   constexpr bool fuse = sizeof(T) == 4;
   if (c->pre_projected) {
     // the projections of Psi were issued while the potentials were formed
-    hloc<T>(c, f0, f1, psi, w);
+    hloc<T>(c, f0, f1, psi0, w);
     kb_apply<T>(c, f0, f1, w);
   } else {
-    apply_h_range<T>(c, f0, f1, psi, w);
+    apply_h_range<T>(c, f0, f1, psi0, w);
   }
   for (int sw = 0; sw < c->sweeps; ++sw) {
     const bool last = sw + 1 == c->sweeps;
+    const T *pin = sw == 0 ? psi0 : psi;   // orbitals entering this sweep
     if (sw == 0 || !fuse) {
       // (a) Hs = sym(<Psi, W>), a_i = <psi_i, w_i>; (b) G = W - Hs Psi (in q),
       // gamma_i = <g_i, g_i>
-      gram<T>(c, f0, f1, psi, w, c->d_hs_full, c->d_hs, c->d_a);
+      gram<T>(c, f0, f1, pin, w, c->d_hs_full, c->d_hs, c->d_a);
       Timed t(c, DCDFT_KERNEL_ROTATE, 3.0 * sz * n * nb, 2.0 * n * m2);
       // (c) with the Fletcher-Reeves beta
-      launch_rot_residual<T>(g, o, f0, f1, c->d_hs, psi, w, q, c->d_dpart, c->d_gamma, s, sw == 0,
+      launch_rot_residual<T>(g, o, f0, f1, c->d_hs, pin, w, q, c->d_dpart, c->d_gamma, s, sw == 0,
                              c->d_gamma_prev, c->d_beta);
     }
     // (d)-(e) P = -G + beta P_prev, X = <Psi, P>
     {
       Timed t(c, DCDFT_KERNEL_GRAM_FUSED, 4.0 * sz * n * nb, 2.0 * n * m2);
-      launch_gram_direction<T>(g, o, f0, f1, ch, psi, q, p, c->d_beta, gpart_at(c, f0), s,
+      launch_gram_direction<T>(g, o, f0, f1, ch, pin, q, p, c->d_beta, gpart_at(c, f0), s,
                                sw == 0);
     }
     launch_gram_reduce(g, o, f0, f1, ch, 0, gpart_at(c, f0), c->d_x, nullptr, nullptr, s);
     // (e)-(f) P <- P - X^T Psi, nu_i = <p_i, p_i> (and 1/sqrt(nu_i)), <p_i, w_i>
     {
       Timed t(c, DCDFT_KERNEL_ROTATE, 4.0 * sz * n * nb, 2.0 * n * m2);
-      launch_rot_project_out<T>(g, o, f0, f1, c->d_x, psi, p, w, c->d_dpart, c->d_nu, c->d_bb,
+      launch_rot_project_out<T>(g, o, f0, f1, c->d_x, pin, p, w, c->d_dpart, c->d_nu, c->d_bb,
                                 s, c->d_inv);
     }
     // (g) Q = H P and <p_i, q_i>
@@ -341,8 +346,8 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
       Timed t(c, DCDFT_KERNEL_GRAM_FUSED, (last ? 5.0 : 6.0) * sz * n * nb,
               (with_m ? 3.0 : 1.0) * n * m2);
       // after the last sweep W is not used (the next step rebuilds it)
-      launch_gram_update<T>(g, o, f0, f1, ch, psi, p, w, q, c->d_cos, c->d_sin, gpart_at(c, f0), s,
-                            with_m ? gpart2_at(c, f0) : nullptr, !last);
+      launch_gram_update<T>(g, o, f0, f1, ch, pin, psi, p, w, q, c->d_cos, c->d_sin,
+                            gpart_at(c, f0), s, with_m ? gpart2_at(c, f0) : nullptr, !last);
     }
     if (!with_m) {
       launch_gram_reduce(g, o, f0, f1, ch, 1, gpart_at(c, f0), c->d_s, nullptr, nullptr, s);
@@ -388,15 +393,18 @@ void orthonormalize_all(dcdft_ctx *c) {
   launch_rot_cholesky<T>(c->geo, o, 0, c->nF, c->d_lin, psi, (T *)nullptr, c->stream);
 }
 
+// Status of a step from its device flags.  A non-finite value makes every later
+// test meaningless (the capacity of NaN weights is not >= N_e, Jacobi on NaN does
+// not converge), so it is reported first.
 dcdft_status check_flags(dcdft_ctx *c, int flags) {
+  if (flags & FLAG_NAN) return set_err(c, DCDFT_ERR_NAN, "non-finite value in the SCF state");
+  if (flags & FLAG_NOT_SPD)
+    return set_err(c, DCDFT_ERR_NOT_SPD, "overlap matrix not positive definite in Cholesky");
+  if (flags & FLAG_EIG) return set_err(c, DCDFT_ERR_EIG, "Jacobi eigensolver did not converge");
   if (flags & FLAG_CAPACITY)
     return set_err(c, DCDFT_ERR_CAPACITY,
                    fmt("fragment states hold %.6f electrons < N_e = %.6f",
                        c->d_info_host[SC_CAPACITY], c->ne));
-  if (flags & FLAG_NOT_SPD)
-    return set_err(c, DCDFT_ERR_NOT_SPD, "overlap matrix not positive definite in Cholesky");
-  if (flags & FLAG_EIG) return set_err(c, DCDFT_ERR_EIG, "Jacobi eigensolver did not converge");
-  if (flags & FLAG_NAN) return set_err(c, DCDFT_ERR_NAN, "non-finite value in the SCF state");
   return DCDFT_OK;
 }
 
@@ -731,17 +739,40 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
 
 namespace {
 
-// Every kernel of one SCF iteration, in order, on the context's stream.
-void enqueue_step(dcdft_ctx *c) {
+// Fragment groups of the batched step: G groups of about M_tot / G orbitals each
+// (group q holds fragments [bound[q], bound[q + 1])); G = 1 when not batched or
+// when kernel timing runs the step on one stream.
+int step_groups(const dcdft_ctx *c, int *bound) {
+  const int G = (c->batched && !c->timing) ? std::min(c->streams, c->nF) : 1;
+  bound[0] = 0;
+  for (int q = 1; q < G; ++q) {
+    int h = bound[q - 1] + 1;
+    while (h < c->nF - (G - q) && (long long)G * c->moff[h] < (long long)q * c->M_tot) ++h;
+    bound[q] = h;
+  }
+  bound[G] = c->nF;
+  return G;
+}
+
+// One SCF iteration is issued as three phases, each beginning and ending on the
+// context's stream (forks onto the group streams are joined inside the phase), so
+// that events between them time the phases.  The step reads the current state
+// and writes the next one: new orbitals into d_psi_next (swapped in on success),
+// everything else in place after a copy of it has been set aside (copied back on
+// failure).
+//   phase 0: set the state aside, Hartree potential and V_eff (steps 1-2); with
+//            concurrent groups and a spare stream the potentials are formed there
+//            while every group projects its orbitals (which does not need V_eff)
+//   phase 1: the fragment eigensolvers (step 3)
+//   phase 2: chemical potential, densities, energy terms, residuals, mixing (4-8)
+void enqueue_phase(dcdft_ctx *c, int phase) {
   const Geo &g = c->geo;
   hipStream_t s = c->stream;
   OrbSet o = c->orbset(0, c->nF);
-  launch_fill_int(c->d_flags, 1, 0, s);
-  const int G = c->batched ? std::min(c->streams, c->nF) : 1;
-  // In the step graph with concurrent fragment groups and a spare stream, the
-  // potentials (steps 1-2) are formed on that stream while every group issues the
-  // projections of its orbitals, which do not read V_eff.
-  const bool overlap = G > 1 && G < dcdft_ctx::kMaxStreams && !c->timing && !c->fixed_density;
+  int bound[dcdft_ctx::kMaxStreams + 1];
+  const int G = step_groups(c, bound);
+  const bool overlap = G > 1 && G < dcdft_ctx::kMaxStreams && !c->fixed_density;
+  const bool mixed = c->precision == DCDFT_PREC_MIXED;
   auto potentials = [&](hipStream_t ps) {
     // 1. Hartree potential of rho_tot^in
     launch_poisson(g, c->d_rho_in, c->d_vh, c->d_fft_a, c->d_fft_b, c->d_qf, c->d_qi, c->d_lam,
@@ -750,69 +781,67 @@ void enqueue_step(dcdft_ctx *c) {
     launch_veff(g, 0, c->nF, c->d_vloc, c->d_vh, c->d_rhof_in, c->d_rho_in,
                 c->template_xi, c->d_veff, c->d_veff32, ps);
   };
-  // With a frozen density V_H and V_eff were formed when it was fixed or set and
-  // do not change
-  if (!overlap && !c->fixed_density) potentials(s);
-  // 3. fragment eigensolvers
-  if (c->batched) {
+  auto fork = [&](int nstreams) {
+    hipEventRecord(c->ev_fork, s);
+    for (int q = 1; q < nstreams; ++q) hipStreamWaitEvent(c->xstreams[q], c->ev_fork, 0);
+  };
+  auto join = [&](int nstreams) {
+    for (int q = 1; q < nstreams; ++q) {
+      hipEventRecord(c->ev_join[q], c->xstreams[q]);
+      hipStreamWaitEvent(s, c->ev_join[q], 0);
+    }
+  };
+  if (phase == 0) {
+    for (const auto &b : c->backups)
+      hipMemcpyAsync(b.save, b.live, b.bytes, hipMemcpyDeviceToDevice, s);
+    launch_fill_int(c->d_flags, 1, 0, s);
+    // with a frozen density V_H and V_eff were formed when it was fixed or set
+    if (!overlap) {
+      if (!c->fixed_density) potentials(s);
+      return;
+    }
+    fork(G + 1);
+    potentials(c->xstreams[G]);
+    for (int q = 0; q < G; ++q) {
+      c->xs = q ? c->xstreams[q] : s;
+      if (mixed) kb_project<float>(c, bound[q], bound[q + 1], (const float *)c->d_psi);
+      else kb_project<double>(c, bound[q], bound[q + 1], (const double *)c->d_psi);
+    }
+    c->xs = nullptr;
+    join(G + 1);
+    return;
+  }
+  if (phase == 1) {
     auto run = [&](int a, int b) {
-      if (c->precision == DCDFT_PREC_MIXED) eigensolver_range<float>(c, a, b);
+      if (mixed) eigensolver_range<float>(c, a, b);
       else eigensolver_range<double>(c, a, b);
     };
-    auto project = [&](int a, int b) {
-      if (c->precision == DCDFT_PREC_MIXED) kb_project<float>(c, a, b, (const float *)c->d_psi);
-      else kb_project<double>(c, a, b, (const double *)c->d_psi);
-    };
-    if (G > 1 && !c->timing) {
-      // G fragment groups of about M_tot / G orbitals each, concurrently
-      int bound[dcdft_ctx::kMaxStreams + 1];
-      bound[0] = 0;
-      for (int q = 1; q < G; ++q) {
-        int h = bound[q - 1] + 1;
-        while (h < c->nF - (G - q) && (long long)G * c->moff[h] < (long long)q * c->M_tot) ++h;
-        bound[q] = h;
-      }
-      bound[G] = c->nF;
-      hipEventRecord(c->ev_fork, s);
-      for (int q = 1; q < G; ++q) hipStreamWaitEvent(c->xstreams[q], c->ev_fork, 0);
-      if (overlap) {
-        hipStreamWaitEvent(c->xstreams[G], c->ev_fork, 0);
-        potentials(c->xstreams[G]);
-        hipEventRecord(c->ev_pot, c->xstreams[G]);
-      }
+    c->pre_projected = overlap;
+    if (!c->batched) {
+      for (int f = 0; f < c->nF; ++f) run(f, f + 1);
+    } else if (G == 1) {
+      run(0, c->nF);
+    } else {
+      fork(G);
       for (int q = 0; q < G; ++q) {
         c->xs = q ? c->xstreams[q] : s;
-        if (overlap) {
-          project(bound[q], bound[q + 1]);
-          hipStreamWaitEvent(c->xs, c->ev_pot, 0);
-          c->pre_projected = true;
-        }
         run(bound[q], bound[q + 1]);
-        c->pre_projected = false;
-      }
-      for (int q = 1; q < G; ++q) {
-        hipEventRecord(c->ev_join[q], c->xstreams[q]);
-        hipStreamWaitEvent(s, c->ev_join[q], 0);
       }
       c->xs = nullptr;
-    } else {
-      run(0, c->nF);
+      join(G);
     }
-  } else {
-    for (int f = 0; f < c->nF; ++f) {
-      if (c->precision == DCDFT_PREC_MIXED) eigensolver_range<float>(c, f, f + 1);
-      else eigensolver_range<double>(c, f, f + 1);
-    }
+    c->pre_projected = false;
+    return;
   }
   // 4. global chemical potential
   launch_fermi(o, c->d_eps, c->d_wcore, c->ne, c->smearing, c->d_occ, c->d_scal, c->d_flags, s);
-  // 5. densities
-  if (c->precision == DCDFT_PREC_MIXED)
-    launch_density<float>(g, o, 0, c->nF, (const float *)c->d_psi, c->d_occ, c->d_rhof_out,
+  // 5. densities of the new orbitals
+  if (mixed)
+    launch_density<float>(g, o, 0, c->nF, (const float *)c->d_psi_next, c->d_occ, c->d_rhof_out,
                           c->d_rho_out, s);
   else
-    launch_density<double>(g, o, 0, c->nF, (const double *)c->d_psi, c->d_occ, c->d_rhof_out,
-                           c->d_rho_out, s);
+    launch_density<double>(g, o, 0, c->nF, (const double *)c->d_psi_next, c->d_occ,
+                           c->d_rhof_out, c->d_rho_out, s);
   // 6-8. energy terms, residuals, mixing (a mixing fraction of 0 leaves a frozen
   // rho_tot^in bitwise unchanged and makes the paper's residual 0)
   launch_global_terms(g, c->d_rho_in, c->d_rho_out, c->d_vh, c->fixed_density ? 0.0 : c->mixing,
@@ -823,28 +852,34 @@ void enqueue_step(dcdft_ctx *c) {
 }
 
 void drop_graph(dcdft_ctx *c) {
-  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
-  if (c->graph) hipGraphDestroy(c->graph);
-  c->graph_exec = nullptr;
-  c->graph = nullptr;
-  for (auto &t : c->graph_timers) {
-    c->event_pool.push_back(t.a);
-    c->event_pool.push_back(t.b);
-  }
-  c->graph_timers.clear();
+  for (int k = 0; k < 2; ++k)
+    for (int ph = 0; ph < 3; ++ph) {
+      if (c->graph_exec[k][ph]) hipGraphExecDestroy(c->graph_exec[k][ph]);
+      if (c->graph[k][ph]) hipGraphDestroy(c->graph[k][ph]);
+      c->graph_exec[k][ph] = nullptr;
+      c->graph[k][ph] = nullptr;
+    }
 }
 
-// Accumulate the event pairs recorded inside the graph (they persist across replays).
-void read_graph_timers(dcdft_ctx *c) {
-  for (auto &t : c->graph_timers) {
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
-      c->k_launches[t.kind] += 1;
-      c->k_ms[t.kind] += ms;
-      c->k_bytes[t.kind] += t.bytes;
-      c->k_flops[t.kind] += t.flops;
+// Capture the three phases of the step into graph slot k (the slot of the
+// orbital buffer that holds the current state).
+dcdft_status capture_step(dcdft_ctx *c, int k) {
+  hipStream_t s = c->stream;
+  for (int ph = 0; ph < 3; ++ph) {
+    HIPTRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    enqueue_phase(c, ph);
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &gr);
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec[k][ph], gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      if (gr) hipGraphDestroy(gr);
+      c->graph_exec[k][ph] = nullptr;
+      drop_graph(c);
+      return set_err(c, DCDFT_ERR_HIP, fmt("graph capture: %s", hipGetErrorString(e)));
     }
+    c->graph[k][ph] = gr;
   }
+  return DCDFT_OK;
 }
 
 }  // namespace
@@ -879,22 +914,23 @@ dcdft_status dcdft_last_error(const dcdft_ctx *c, char *buf, size_t n) {
 void dcdft_destroy(dcdft_ctx *c) {
   if (!c) return;
   if (c->stream) hipStreamSynchronize(c->stream);
+  drop_graph(c);
   for (void *q : c->allocs) hipFree(q);
   if (c->d_info_host) hipHostFree(c->d_info_host);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
+  for (hipEvent_t e : c->ev_ph)
+    if (e) hipEventDestroy(e);
   for (auto &t : c->pending) {
     hipEventDestroy(t.a);
     hipEventDestroy(t.b);
   }
   for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
-  drop_graph(c);
   for (int q = 1; q < dcdft_ctx::kMaxStreams; ++q) {
     if (c->xstreams[q]) hipStreamDestroy(c->xstreams[q]);
     if (c->ev_join[q]) hipEventDestroy(c->ev_join[q]);
   }
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
-  if (c->ev_pot) hipEventDestroy(c->ev_pot);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1003,7 +1039,7 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
     // m_pad zeroed rows of n points after the last band: kernels may read rows
     // up to the padded count of any fragment without a per-lane clamp
     const long long pad = (long long)c->m_pad * g.n;
-    void **orb[] = {&c->d_psi, &c->d_w, &c->d_p, &c->d_q};
+    void **orb[] = {&c->d_psi, &c->d_psi_next, &c->d_w, &c->d_p, &c->d_q};
     for (void **a : orb) {
       char *q = nullptr;
       hipError_t e_ = dalloc(c, &q, (size_t)(norb + pad) * c->elem);
@@ -1051,14 +1087,43 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   ALLOC(c->d_scal, SC_COUNT);
   ALLOC(c->d_part, (long long)c->n_part * 6);
   ALLOC(c->d_flags, 1);
+  // scratch of dcdft_apply_h / dcdft_band_energy: layout tables of one fragment's
+  // vectors and H psi of one chunk of m_pad vectors (sized for FP64)
+  ALLOC(c->ext.m, c->nF);
+  ALLOC(c->ext.moff, c->nF + 1);
+  ALLOC(c->ext.band, c->m_pad);
+  ALLOC(c->ext.eb, c->m_pad);
+  {
+    char *hp = nullptr;
+    ALLOC(hp, (size_t)c->m_pad * g.n * sizeof(double));
+    c->ext.hp = hp;
+  }
+  c->ext.chunk = c->m_pad;
+  c->ext_h_m.assign(c->nF, 0);
+  c->ext_h_moff.assign(c->nF + 1, 0);
+  {
+    // what a step overwrites in place, set aside at its start
+    const size_t fn = (size_t)c->nF * g.n;
+    const std::pair<void *, size_t> live[] = {
+        {c->d_rho_in, g.Ng * sizeof(double)},   {c->d_rhof_in, fn * sizeof(double)},
+        {c->d_rho_out, g.Ng * sizeof(double)},  {c->d_rhof_out, fn * sizeof(double)},
+        {c->d_vh, g.Ng * sizeof(double)},       {c->d_veff, fn * sizeof(double)},
+        {c->d_veff32, fn * sizeof(float)},      {c->d_eps, c->M_tot * sizeof(double)},
+        {c->d_wcore, c->M_tot * sizeof(double)}, {c->d_occ, c->M_tot * sizeof(double)},
+        {c->d_scal, SC_COUNT * sizeof(double)}};
+    for (const auto &l : live) {
+      char *save = nullptr;
+      ALLOC(save, l.second);
+      c->backups.push_back({l.first, save, l.second});
+    }
+  }
 #undef ALLOC
   if (hipHostMalloc((void **)&c->d_info_host, SC_COUNT * sizeof(double), 0) != hipSuccess) {
     c->last_error = "pinned host allocation failed";
     return fail(DCDFT_ERR_HIP);
   }
   {
-    bool ok = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess &&
-              hipEventCreateWithFlags(&c->ev_pot, hipEventDisableTiming) == hipSuccess;
+    bool ok = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;
     for (int q = 1; q < dcdft_ctx::kMaxStreams && ok; ++q)
       ok = hipStreamCreateWithFlags(&c->xstreams[q], hipStreamNonBlocking) == hipSuccess &&
            hipEventCreateWithFlags(&c->ev_join[q], hipEventDisableTiming) == hipSuccess;
@@ -1071,6 +1136,12 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
     c->last_error = "event creation failed";
     return fail(DCDFT_ERR_HIP);
   }
+  for (hipEvent_t &e : c->ev_ph)
+    if (hipEventCreate(&e) != hipSuccess) {
+      c->last_error = "event creation failed";
+      return fail(DCDFT_ERR_HIP);
+    }
+  c->psi_first = c->d_psi;
   // initial state
   const double rho0 = c->ne / (p->cell[0] * p->cell[1] * p->cell[2]);
   launch_fill(c->d_rho_in, g.Ng, rho0, c->stream);
@@ -1110,31 +1181,21 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
 dcdft_status dcdft_scf_step(dcdft_ctx *c, dcdft_scf_info *info) {
   if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
   hipStream_t s = c->stream;
-  // Timed steps run eagerly: event records are not captured into the graph.
+  // Timed steps run eagerly: their per-launch event records are host decisions.
   const bool graph = c->batched && c->use_graph && !c->timing;
-  if (graph && !c->graph_exec) {
+  const int slot = c->d_psi == c->psi_first ? 0 : 1;
+  if (graph && !c->graph_exec[slot][0]) {
     drain_timers(c);
-    HIPTRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    enqueue_step(c);
-    hipGraph_t gr = nullptr;
-    hipError_t e = hipStreamEndCapture(s, &gr);
-    c->graph_timers.swap(c->pending);
-    c->pending.clear();
-    c->graph_timed = c->timing;
-    if (e != hipSuccess) return set_err(c, DCDFT_ERR_HIP, fmt("graph capture: %s", hipGetErrorString(e)));
-    c->graph = gr;
-    e = hipGraphInstantiate(&c->graph_exec, gr, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      drop_graph(c);
-      return set_err(c, DCDFT_ERR_HIP, fmt("graph instantiation: %s", hipGetErrorString(e)));
-    }
+    dcdft_status st = capture_step(c, slot);
+    if (st != DCDFT_OK) return st;
   }
   HIPTRY(c, hipEventRecord(c->ev0, s));
-  if (graph) {
-    HIPTRY(c, hipGraphLaunch(c->graph_exec, s));
-  } else {
-    enqueue_step(c);
+  for (int ph = 0; ph < 3; ++ph) {
+    HIPTRY(c, hipEventRecord(c->ev_ph[ph], s));
+    if (graph) HIPTRY(c, hipGraphLaunch(c->graph_exec[slot][ph], s));
+    else enqueue_phase(c, ph);
   }
+  HIPTRY(c, hipEventRecord(c->ev_ph[3], s));
   HIPTRY(c, hipGetLastError());
   HIPTRY(c, hipEventRecord(c->ev1, s));
   HIPTRY(c, hipMemcpyAsync(c->d_info_host, c->d_scal, SC_COUNT * sizeof(double),
@@ -1142,14 +1203,12 @@ dcdft_status dcdft_scf_step(dcdft_ctx *c, dcdft_scf_info *info) {
   int flags = 0;
   HIPTRY(c, hipMemcpyAsync(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPTRY(c, hipStreamSynchronize(s));
-  if (graph) read_graph_timers(c);
-  else drain_timers(c);
-  c->iter++;
+  drain_timers(c);
   const double *sc = c->d_info_host;
   if (info) {
     float ms = 0.0f;
     hipEventElapsedTime(&ms, c->ev0, c->ev1);
-    info->iter = c->iter;
+    info->iter = c->iter + (flags ? 0 : 1);
     info->mu = sc[SC_MU];
     info->e_band = sc[SC_EBAND];
     info->entropy = sc[SC_ENTROPY];
@@ -1158,8 +1217,24 @@ dcdft_status dcdft_scf_step(dcdft_ctx *c, dcdft_scf_info *info) {
     info->residual_out_in = sc[SC_RES_OUT_IN];
     info->charge = sc[SC_CHARGE];
     info->ms_step = ms;
+    float ph[3] = {-1.0f, -1.0f, -1.0f};
+    for (int k = 0; k < 3; ++k)
+      if (hipEventElapsedTime(&ph[k], c->ev_ph[k], c->ev_ph[k + 1]) != hipSuccess) ph[k] = -1.0f;
+    info->ms_poisson = ph[0];
+    info->ms_fragments = ph[1];
+    info->ms_fermi_density = ph[2];
   }
-  return check_flags(c, flags);
+  if (flags) {
+    // failed step: the state of the last completed step comes back (the orbitals
+    // were never overwritten; everything else from the copies set aside)
+    for (const auto &b : c->backups)
+      HIPTRY(c, hipMemcpyAsync(b.live, b.save, b.bytes, hipMemcpyDeviceToDevice, s));
+    HIPTRY(c, hipStreamSynchronize(s));
+    return check_flags(c, flags);
+  }
+  std::swap(c->d_psi, c->d_psi_next);
+  c->iter++;
+  return DCDFT_OK;
 }
 
 dcdft_status dcdft_density(const dcdft_ctx *c, double *rho, size_t n) {
@@ -1298,6 +1373,10 @@ dcdft_status dcdft_set_density(dcdft_ctx *c, const double *rho_tot_in, const dou
   const Geo &g = c->geo;
   for (long long i = 0; i < g.Ng; ++i)
     if (!std::isfinite(rho_tot_in[i])) return set_err(c, DCDFT_ERR_NAN, "non-finite density");
+  if (rho_frag_in)
+    for (long long i = 0; i < (long long)c->nF * g.n; ++i)
+      if (!std::isfinite(rho_frag_in[i]))
+        return set_err(c, DCDFT_ERR_NAN, "non-finite fragment density");
   HIPTRY(c, hipMemcpyAsync(c->d_rho_in, rho_tot_in, g.Ng * sizeof(double), hipMemcpyHostToDevice,
                            c->stream));
   if (rho_frag_in) {
@@ -1608,61 +1687,28 @@ dcdft_status dcdft_lcfo_block(const dcdft_ctx *c, int32_t a, int32_t b, double *
 
 namespace {
 
-// Run fn over an external block of m vectors of fragment frag, in chunks of at
-// most m_pad vectors, with a temporary single-fragment layout on the device.
-struct ExtLayout {
-  int *m = nullptr;
-  long long *moff = nullptr;
-  int *band_frag = nullptr;
-  std::vector<long long> h_moff;
-  std::vector<int> h_m;
-};
-
-dcdft_status make_ext(dcdft_ctx *c, int frag, int mm, ExtLayout &L) {
-  L.h_m.assign(c->nF, 0);
-  L.h_m[frag] = mm;
-  L.h_moff.assign(c->nF + 1, 0);
-  for (int f = 0; f < c->nF; ++f) L.h_moff[f + 1] = L.h_moff[f] + L.h_m[f];
-  std::vector<int> bf(std::max(mm, 1), frag);
-  HIPTRY(c, hipMalloc(&L.m, c->nF * sizeof(int)));
-  HIPTRY(c, hipMalloc(&L.moff, (c->nF + 1) * sizeof(long long)));
-  HIPTRY(c, hipMalloc(&L.band_frag, bf.size() * sizeof(int)));
-  HIPTRY(c, hipMemcpy(L.m, L.h_m.data(), c->nF * sizeof(int), hipMemcpyHostToDevice));
-  HIPTRY(c, hipMemcpy(L.moff, L.h_moff.data(), (c->nF + 1) * sizeof(long long),
-                      hipMemcpyHostToDevice));
-  HIPTRY(c, hipMemcpy(L.band_frag, bf.data(), bf.size() * sizeof(int), hipMemcpyHostToDevice));
-  return DCDFT_OK;
-}
-
-void free_ext(ExtLayout &L) {
-  if (L.m) hipFree(L.m);
-  if (L.moff) hipFree(L.moff);
-  if (L.band_frag) hipFree(L.band_frag);
-}
-
 // H psi for an external block of m vectors of fragment frag, in chunks of at most
-// m_pad vectors; veff_ext (device, n doubles) replaces the fragment's V_eff if given.
+// X.chunk vectors, each with the layout of that fragment alone (tables written on
+// the device into X); veff_ext (device, n doubles) replaces the fragment's V_eff
+// if given.  Everything is issued on the context's stream; nothing is allocated.
 template <typename T>
-dcdft_status apply_h_ext(dcdft_ctx *c, int frag, const T *psi, T *hpsi, int m,
-                         const double *veff_ext = nullptr) {
+void apply_h_ext(dcdft_ctx *c, const dcdft_ctx::ExtScratch &X, int frag, const T *psi, T *hpsi,
+                 int m, const double *veff_ext = nullptr) {
   const Geo &g = c->geo;
-  for (int i0 = 0; i0 < m; i0 += c->m_pad) {
-    const int mm = std::min(c->m_pad, m - i0);
-    ExtLayout L;
-    dcdft_status st = make_ext(c, frag, mm, L);
-    if (st != DCDFT_OK) {
-      free_ext(L);
-      return st;
-    }
+  KBTables kb = c->kb();
+  for (int i0 = 0; i0 < m; i0 += X.chunk) {
+    const int mm = std::min(X.chunk, m - i0);
+    launch_single_layout(c->nF, frag, mm, X.m, X.moff, X.band, c->stream);
+    c->ext_h_m[frag] = mm;
+    for (int f = frag + 1; f <= c->nF; ++f) c->ext_h_moff[f] = mm;
     OrbSet o = c->orbset(frag, frag + 1);
-    o.m = L.m;
-    o.moff = L.moff;
-    o.band_frag = L.band_frag;
-    o.h_moff = L.h_moff.data();
-    o.h_m = L.h_m.data();
+    o.m = X.m;
+    o.moff = X.moff;
+    o.band_frag = X.band;
+    o.h_moff = c->ext_h_moff.data();
+    o.h_m = c->ext_h_m.data();
     o.M_tot = mm;
     o.row_pad = 0;
-    KBTables kb = c->kb();
     const T *x = psi + (long long)i0 * g.n;
     T *y = hpsi + (long long)i0 * g.n;
     if (veff_ext) {
@@ -1673,33 +1719,43 @@ dcdft_status apply_h_ext(dcdft_ctx *c, int frag, const T *psi, T *hpsi, int m,
     }
     launch_kb_project<T>(g, o, kb, frag, frag + 1, x, c->d_C, c->d_cpart, c->stream);
     launch_kb_apply<T>(g, o, kb, frag, frag + 1, c->d_C, y, c->stream);
-    hipError_t e = hipStreamSynchronize(c->stream);
-    free_ext(L);
-    if (e != hipSuccess) return set_err(c, DCDFT_ERR_HIP, hipGetErrorString(e));
   }
+  c->ext_h_m[frag] = 0;
+  for (int f = frag + 1; f <= c->nF; ++f) c->ext_h_moff[f] = 0;
+}
+
+// Band energy and gradients of m vectors of fragment frag: H psi chunk by chunk
+// into X.hp, the per-band terms and grad_psi of each chunk, the energy summed
+// over the chunks in order, then grad_v over all bands.
+template <typename T>
+void band_energy_ext(dcdft_ctx *c, const dcdft_ctx::ExtScratch &X, int frag, const T *psi,
+                     const double *f, int m, const double *veff, double *energy, T *grad_psi,
+                     double *grad_v) {
+  const Geo &g = c->geo;
+  T *hp = static_cast<T *>(X.hp);
+  for (int i0 = 0; i0 < m; i0 += X.chunk) {
+    const int mm = std::min(X.chunk, m - i0);
+    apply_h_ext<T>(c, X, frag, psi + (long long)i0 * g.n, hp, mm, veff);
+    launch_band_energy_terms<T>(g, mm, psi + (long long)i0 * g.n, hp, f + i0, X.eb, energy,
+                                i0 > 0, grad_psi ? grad_psi + (long long)i0 * g.n : nullptr,
+                                c->stream);
+  }
+  if (grad_v) launch_grad_v<T>(g, m, psi, f, grad_v, c->stream);
+}
+
+dcdft_status check_ext_args(dcdft_ctx *c, int frag, int m, int prec) {
+  if (frag < 0 || frag >= c->nF)
+    return set_err(c, DCDFT_ERR_ARG, fmt("fragment %d out of range", frag));
+  if (m < 0) return set_err(c, DCDFT_ERR_ARG, "m < 0");
+  if (prec != DCDFT_PREC_FP64 && prec != DCDFT_PREC_MIXED)
+    return set_err(c, DCDFT_ERR_ARG, "prec must be 0 (double) or 1 (float)");
   return DCDFT_OK;
 }
 
-template <typename T>
-dcdft_status band_energy_t(dcdft_ctx *c, int frag, const T *psi, const double *f, int m,
-                           const double *veff, double *energy, T *grad_psi, double *grad_v) {
-  const Geo &g = c->geo;
-  T *hp = nullptr;
-  double *eb = nullptr;
-  HIPTRY(c, hipMalloc(&hp, (size_t)m * g.n * sizeof(T)));
-  if (hipMalloc(&eb, (size_t)m * sizeof(double)) != hipSuccess) {
-    hipFree(hp);
-    return set_err(c, DCDFT_ERR_OOM, "scratch allocation failed");
-  }
-  dcdft_status st = apply_h_ext<T>(c, frag, psi, hp, m, veff);
-  if (st == DCDFT_OK) {
-    launch_band_energy<T>(g, m, psi, hp, f, eb, energy, grad_psi, grad_v, c->stream);
-    hipError_t e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) st = set_err(c, DCDFT_ERR_HIP, hipGetErrorString(e));
-  }
-  hipFree(hp);
-  hipFree(eb);
-  return st;
+dcdft_status finish_ext(dcdft_ctx *c) {
+  HIPTRY(c, hipGetLastError());
+  HIPTRY(c, hipStreamSynchronize(c->stream));
+  return DCDFT_OK;
 }
 
 }  // namespace
@@ -1709,30 +1765,31 @@ extern "C" {
 dcdft_status dcdft_apply_h(dcdft_ctx *c, int32_t frag, const void *psi, void *hpsi, int32_t m,
                            int32_t prec) {
   if (!c || !psi || !hpsi) return set_err(c, DCDFT_ERR_ARG, "NULL argument");
-  if (frag < 0 || frag >= c->nF) return set_err(c, DCDFT_ERR_ARG, fmt("fragment %d out of range", frag));
-  if (m < 0) return set_err(c, DCDFT_ERR_ARG, "m < 0");
-  if (prec != DCDFT_PREC_FP64 && prec != DCDFT_PREC_MIXED)
-    return set_err(c, DCDFT_ERR_ARG, "prec must be 0 (double) or 1 (float)");
+  dcdft_status st = check_ext_args(c, frag, m, prec);
+  if (st != DCDFT_OK) return st;
   if (psi == hpsi) return set_err(c, DCDFT_ERR_ARG, "psi and hpsi may not alias");
   if (m == 0) return DCDFT_OK;
   if (prec == DCDFT_PREC_MIXED)
-    return apply_h_ext<float>(c, frag, (const float *)psi, (float *)hpsi, m);
-  return apply_h_ext<double>(c, frag, (const double *)psi, (double *)hpsi, m);
+    apply_h_ext<float>(c, c->ext, frag, (const float *)psi, (float *)hpsi, m);
+  else
+    apply_h_ext<double>(c, c->ext, frag, (const double *)psi, (double *)hpsi, m);
+  return finish_ext(c);
 }
 
 dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, const double *f,
                                int32_t m, int32_t prec, const double *veff, double *energy,
                                void *grad_psi, double *grad_v) {
   if (!c || !psi || !f) return set_err(c, DCDFT_ERR_ARG, "NULL argument");
-  if (frag < 0 || frag >= c->nF) return set_err(c, DCDFT_ERR_ARG, fmt("fragment %d out of range", frag));
+  dcdft_status st = check_ext_args(c, frag, m, prec);
+  if (st != DCDFT_OK) return st;
   if (m < 1) return set_err(c, DCDFT_ERR_ARG, "m < 1");
-  if (prec != DCDFT_PREC_FP64 && prec != DCDFT_PREC_MIXED)
-    return set_err(c, DCDFT_ERR_ARG, "prec must be 0 (double) or 1 (float)");
   if (prec == DCDFT_PREC_MIXED)
-    return band_energy_t<float>(c, frag, (const float *)psi, f, m, veff, energy,
-                                (float *)grad_psi, grad_v);
-  return band_energy_t<double>(c, frag, (const double *)psi, f, m, veff, energy,
-                               (double *)grad_psi, grad_v);
+    band_energy_ext<float>(c, c->ext, frag, (const float *)psi, f, m, veff, energy,
+                           (float *)grad_psi, grad_v);
+  else
+    band_energy_ext<double>(c, c->ext, frag, (const double *)psi, f, m, veff, energy,
+                            (double *)grad_psi, grad_v);
+  return finish_ext(c);
 }
 
 }  // extern "C"

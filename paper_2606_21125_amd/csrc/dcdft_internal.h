@@ -140,7 +140,6 @@ struct dcdft_ctx {
   int streams = 2;
   hipStream_t xstreams[kMaxStreams] = {};  // [0] unused (the context's stream)
   hipEvent_t ev_fork = nullptr, ev_join[kMaxStreams] = {};
-  hipEvent_t ev_pot = nullptr;   // V_eff formed (the potentials' stream of the step graph)
   bool pre_projected = false;    // the step's first projections were issued before V_eff
   hipStream_t xs = nullptr;
   int iter = 0;
@@ -169,8 +168,12 @@ struct dcdft_ctx {
   long long *d_ar_ptr = nullptr;
   double *d_cpart = nullptr;         // region projection partials [F][NR][KS][m_pad]
 
-  // orbital arrays [M_tot][n], element type double (FP64) or float (mixed)
-  void *d_psi = nullptr, *d_w = nullptr, *d_p = nullptr, *d_q = nullptr;
+  // orbital arrays [M_tot][n], element type double (FP64) or float (mixed).
+  // The orbitals live in two buffers: d_psi holds the state of the last
+  // completed step; a step reads it and writes its new orbitals into
+  // d_psi_next, and the two swap only when the step succeeds.
+  void *d_psi = nullptr, *d_psi_next = nullptr, *d_w = nullptr, *d_p = nullptr, *d_q = nullptr;
+  void *psi_first = nullptr;    // the buffer d_psi pointed to after setup (graph slot 0)
   size_t elem = sizeof(double);
 
   // fields
@@ -218,9 +221,35 @@ struct dcdft_ctx {
   double k_ms[DCDFT_KERNEL_COUNT] = {}, k_bytes[DCDFT_KERNEL_COUNT] = {},
          k_flops[DCDFT_KERNEL_COUNT] = {};
 
-  // graph of one batched SCF step (captured on first use, replayed after)
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
+  // graphs of the three phases of one batched SCF step (captured on first use,
+  // replayed after), one set per orbital buffer holding the current state
+  hipGraph_t graph[2][3] = {};
+  hipGraphExec_t graph_exec[2][3] = {};
+  // State that a step overwrites in place, copied aside at the start of every step
+  // and copied back when the step fails (densities, potentials, eigenpairs,
+  // occupations, scalars, mixer history)
+  struct Backup {
+    void *live;
+    void *save;
+    size_t bytes;
+  };
+  std::vector<Backup> backups;
+  // Scratch of the calls on caller-provided vectors (apply_h, band_energy):
+  // single-fragment layout tables, H psi of one chunk of vectors, per-band terms
+  struct ExtScratch {
+    int *m = nullptr;             // [F]
+    long long *moff = nullptr;    // [F + 1]
+    int *band = nullptr;          // [chunk]
+    void *hp = nullptr;           // [chunk][n] of double or float
+    double *eb = nullptr;         // [chunk]
+    int chunk = 0;                // vectors per chunk (<= m_pad)
+  };
+  ExtScratch ext;
+  std::vector<int> ext_h_m;           // host copies of the layout tables (launch ranges)
+  std::vector<long long> ext_h_moff;
+  // phase boundaries of a step: start, V_eff formed, fragment eigensolvers
+  // joined, end (recorded between the phases' graph launches)
+  hipEvent_t ev_ph[4] = {nullptr, nullptr, nullptr, nullptr};
   bool use_graph = true;
   double template_xi = 0.0;    // xi of the density-template potential; 0: off
   // DC-LCFO post-processing (built on request; FP64 arrays in the orbital layout)
@@ -237,8 +266,6 @@ struct dcdft_ctx {
   std::vector<int> lcfo_pair_of;                      // [F][F] pair index of (a, b), -1: none
   bool lcfo_ready = false;
   bool fixed_density = false;  // rho^in frozen: no Poisson, V_eff or mixing update in the step
-  bool graph_timed = false;
-  std::vector<PendingTimer> graph_timers;
 
   dcdft::OrbSet orbset(int f0, int f1) const;
   dcdft::KBTables kb() const;
@@ -271,10 +298,21 @@ void launch_kb_apply(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, 
                      const double *C, T *y, hipStream_t s);
 template <typename T>
 void launch_init_orbitals(const Geo &g, const OrbSet &o, uint64_t seed, T *psi, hipStream_t s);
-// band energy: eb[B] = f_B <psi_B|H psi_B>, energy = sum eb, grads
+// band energy of nb bands: eb[B] = f_B <psi_B|H psi_B>, energy = sum eb (or
+// energy += sum eb with accumulate; energy may be null), grad_psi = 2 f dV H psi
+// (may be null)
 template <typename T>
-void launch_band_energy(const Geo &g, int nb, const T *psi, const T *hpsi, const double *f,
-                        double *eb, double *energy, T *grad_psi, double *grad_v, hipStream_t s);
+void launch_band_energy_terms(const Geo &g, int nb, const T *psi, const T *hpsi, const double *f,
+                              double *eb, double *energy, int accumulate, T *grad_psi,
+                              hipStream_t s);
+// grad_v(l) = dV sum_B f_B psi_B(l)^2 over nb bands
+template <typename T>
+void launch_grad_v(const Geo &g, int nb, const T *psi, const double *f, double *grad_v,
+                   hipStream_t s);
+// device layout tables of mm vectors of fragment frag alone (m [nf], moff [nf + 1],
+// band_frag [mm])
+void launch_single_layout(int nf, int frag, int mm, int *m, long long *moff, int *band_frag,
+                          hipStream_t s);
 
 // Gram partials of X^T Y (row form G_ij = sum_l X_i(l) Y_j(l)); X == Y is symmetric
 template <typename T>
@@ -286,13 +324,14 @@ template <typename T>
 void launch_gram_direction(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
                            const T *psi, const T *gres, T *p, const double *beta, double *part,
                            hipStream_t s, bool beta_zero = false);
-// Psi <- cs Psi + sn P, W <- cs W + sn Q (in place), symmetric Gram partials of Psi;
-// with part_m also the partials of the full product <Psi, W> (same layout), and
-// then store_w = false leaves W unwritten (only its product is needed)
+// Psi_out <- cs Psi + sn P (psi_out may be psi), W <- cs W + sn Q (in place),
+// symmetric Gram partials of Psi_out; with part_m also the partials of the full
+// product <Psi_out, W> (same layout), and then store_w = false leaves W unwritten
+// (only its product is needed)
 template <typename T>
-void launch_gram_update(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, T *psi,
-                        const T *p, T *w, const T *q, const double *cs, const double *sn,
-                        double *part, hipStream_t s, double *part_m = nullptr,
+void launch_gram_update(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
+                        const T *psi, T *psi_out, const T *p, T *w, const T *q, const double *cs,
+                        const double *sn, double *part, hipStream_t s, double *part_m = nullptr,
                         bool store_w = true);
 // G = dV sum of chunk partials (sym: X == Y, lower tiles mirrored); Gs = sym(G) if
 // not null; diag -> per-band (may be null)

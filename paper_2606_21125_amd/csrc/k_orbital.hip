@@ -854,13 +854,31 @@ __global__ void __launch_bounds__(256) k_band_energy_terms(Geo g, const T *__res
   if (threadIdx.x == 0) eb[B] = f[B] * g.dv * acc;
 }
 
+// energy = sum eb (accumulate: energy += sum eb, for a later chunk of bands)
 __global__ void __launch_bounds__(64) k_band_energy_sum(int nb, const double *__restrict__ eb,
-                                                        double *__restrict__ energy) {
+                                                        double *__restrict__ energy,
+                                                        int accumulate) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
+    double s = accumulate ? energy[0] : 0.0;
     for (int i = 0; i < nb; ++i) s += eb[i];
     energy[0] = s;
   }
+}
+
+// Orbital layout of mm vectors of fragment frag alone (every other fragment
+// empty): m[f], moff[f] for f < nf and moff[nf], band_frag[B] for B < mm.
+__global__ void __launch_bounds__(256) k_single_layout(int nf, int frag, int mm,
+                                                       int *__restrict__ m,
+                                                       long long *__restrict__ moff,
+                                                       int *__restrict__ band_frag) {
+  for (int f = blockIdx.x * blockDim.x + threadIdx.x; f <= nf; f += gridDim.x * blockDim.x) {
+    if (f < nf) m[f] = f == frag ? mm : 0;
+    moff[f] = f > frag ? mm : 0;
+    if (f < mm) band_frag[f] = frag;
+  }
+  for (int B = nf + 1 + blockIdx.x * blockDim.x + threadIdx.x; B < mm;
+       B += gridDim.x * blockDim.x)
+    band_frag[B] = frag;
 }
 
 // grad_v(l) = dV sum_i f_i psi_i(l)^2
@@ -1071,15 +1089,29 @@ void launch_init_orbitals(const Geo &g, const OrbSet &o, uint64_t seed, T *psi, 
 }
 
 template <typename T>
-void launch_band_energy(const Geo &g, int nb, const T *psi, const T *hpsi, const double *f,
-                        double *eb, double *energy, T *grad_psi, double *grad_v, hipStream_t s) {
+void launch_band_energy_terms(const Geo &g, int nb, const T *psi, const T *hpsi, const double *f,
+                              double *eb, double *energy, int accumulate, T *grad_psi,
+                              hipStream_t s) {
   if (nb <= 0) return;
   hipLaunchKernelGGL(k_band_energy_terms<T>, dim3(nb), dim3(256), 0, s, g, psi, hpsi, f, eb,
                      grad_psi);
-  if (energy) hipLaunchKernelGGL(k_band_energy_sum, dim3(1), dim3(64), 0, s, nb, eb, energy);
-  if (grad_v)
-    hipLaunchKernelGGL(k_grad_v<T>, dim3((g.n + 255) / 256), dim3(256), 0, s, g, nb, psi, f,
-                       grad_v);
+  if (energy)
+    hipLaunchKernelGGL(k_band_energy_sum, dim3(1), dim3(64), 0, s, nb, eb, energy, accumulate);
+}
+
+template <typename T>
+void launch_grad_v(const Geo &g, int nb, const T *psi, const double *f, double *grad_v,
+                   hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_grad_v<T>, dim3((g.n + 255) / 256), dim3(256), 0, s, g, nb, psi, f,
+                     grad_v);
+}
+
+void launch_single_layout(int nf, int frag, int mm, int *m, long long *moff, int *band_frag,
+                          hipStream_t s) {
+  const int n = std::max(nf + 1, mm);
+  hipLaunchKernelGGL(k_single_layout, dim3((n + 255) / 256), dim3(256), 0, s, nf, frag, mm, m,
+                     moff, band_frag);
 }
 
 #define DCDFT_INSTANTIATE(T)                                                                   \
@@ -1092,8 +1124,11 @@ void launch_band_energy(const Geo &g, int nb, const T *psi, const T *hpsi, const
                                    const double *, T *, hipStream_t);                        \
   template void launch_init_orbitals<T>(const Geo &, const OrbSet &, uint64_t, T *,           \
                                         hipStream_t);                                        \
-  template void launch_band_energy<T>(const Geo &, int, const T *, const T *, const double *, \
-                                      double *, double *, T *, double *, hipStream_t);
+  template void launch_band_energy_terms<T>(const Geo &, int, const T *, const T *,            \
+                                            const double *, double *, double *, int, T *,     \
+                                            hipStream_t);                                     \
+  template void launch_grad_v<T>(const Geo &, int, const T *, const double *, double *,       \
+                                 hipStream_t);
 DCDFT_INSTANTIATE(double)
 DCDFT_INSTANTIATE(float)
 #undef DCDFT_INSTANTIATE

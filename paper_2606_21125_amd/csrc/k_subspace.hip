@@ -380,8 +380,8 @@ __global__ void __launch_bounds__(256) k_band_reduce(Geo g, OrbSet o, long long 
 // tiles.  The second operand can be built during the load:
 //   GM_PLAIN:  Y given (SYM when X == Y: upper tiles only, one operand).
 //   GM_DIR:    Y = P = beta P_prev - G, written over P_prev.
-//   GM_UPDATE: X = Psi' = c Psi + s P and W' = c W + s Q, both written in place;
-//              symmetric product of Psi'.
+//   GM_UPDATE: X = Psi' = c Psi + s P, written to xo (which may be X itself), and
+//              W' = c W + s Q, written in place; symmetric product of Psi'.
 //   GM_UPDATE_M: as GM_UPDATE, and also the full product <Psi', W'> (into part2).
 // Partials are written in FP64 (one per workgroup).
 enum { GM_PLAIN = 0, GM_DIR = 1, GM_UPDATE = 2, GM_UPDATE_M = 3 };
@@ -419,8 +419,8 @@ struct Vec4Load<float> {
 template <typename T, int TM, int MODE, bool SYM, bool VEC>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(MODE == GM_UPDATE_M ? 3 : (sizeof(T) == 4 || TM < 5 ? 4 : 2), 8)))
-k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a2, T *a3,
-        const T *a4, const double *__restrict__ c1, const double *__restrict__ c2,
+k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, const T *x, T *xo, T *a1,
+        const T *a2, T *a3, const T *a4, const double *__restrict__ c1, const double *__restrict__ c2,
         double *__restrict__ part, double *__restrict__ part2, int store_w) {
   typedef Mfma<T> MM;
   constexpr int MP = 16 * TM;
@@ -565,7 +565,7 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, T *x, T *a1, const T *a
       }
       if (MODE != GM_PLAIN && rin) {
         const long long ro = base + (long long)row * g.n;
-        T *d0 = MODE == GM_DIR ? a1 : x;
+        T *d0 = MODE == GM_DIR ? a1 : xo;
         const T *v0 = MODE == GM_DIR ? yv : xv;
         if (VEC && p + 3 < p_end) {
           Vec4Load<T>::store(d0 + ro + p, v0);
@@ -1104,31 +1104,31 @@ __global__ void __launch_bounds__(256) k_kb_quad_theta(long long b0, long long n
 }
 
 template <typename T, int TM, int MODE, bool SYM>
-void gram3_t(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int kchunk, T *x, T *a1,
-             const T *a2, T *a3, const T *a4, const double *c1, const double *c2, double *part,
+void gram3_t(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, int kchunk, const T *x,
+             T *xo, T *a1, const T *a2, T *a3, const T *a4, const double *c1, const double *c2, double *part,
              double *part2, int store_w, hipStream_t s) {
   const dim3 grid((f1 - f0) * chunks), block(256);
   if ((g.n % 4) == 0)
     hipLaunchKernelGGL((k_gram3<T, TM, MODE, SYM, true>), grid, block, 0, s, g, o, f0, chunks,
-                       kchunk, x, a1, a2, a3, a4, c1, c2, part, part2, store_w);
+                       kchunk, x, xo, a1, a2, a3, a4, c1, c2, part, part2, store_w);
   else
     hipLaunchKernelGGL((k_gram3<T, TM, MODE, SYM, false>), grid, block, 0, s, g, o, f0, chunks,
-                       kchunk, x, a1, a2, a3, a4, c1, c2, part, part2, store_w);
+                       kchunk, x, xo, a1, a2, a3, a4, c1, c2, part, part2, store_w);
 }
 
 template <typename T, int MODE, bool SYM>
-void gram3_tm(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, T *x, T *a1,
+void gram3_tm(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, const T *x, T *xo, T *a1,
               const T *a2, T *a3, const T *a4, const double *c1, const double *c2, double *part,
               hipStream_t s, double *part2 = nullptr, int store_w = 1) {
   if (f1 <= f0) return;
   int kc = (g.n + chunks - 1) / chunks;
   kc = ((kc + kGramKT - 1) / kGramKT) * kGramKT;
   switch (o.tiles) {
-    case 1: gram3_t<T, 1, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, store_w, s); break;
-    case 2: gram3_t<T, 2, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, store_w, s); break;
-    case 3: gram3_t<T, 3, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, store_w, s); break;
-    case 4: gram3_t<T, 4, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, store_w, s); break;
-    default: gram3_t<T, 5, MODE, SYM>(g, o, f0, f1, chunks, kc, x, a1, a2, a3, a4, c1, c2, part, part2, store_w, s); break;
+    case 1: gram3_t<T, 1, MODE, SYM>(g, o, f0, f1, chunks, kc, x, xo, a1, a2, a3, a4, c1, c2, part, part2, store_w, s); break;
+    case 2: gram3_t<T, 2, MODE, SYM>(g, o, f0, f1, chunks, kc, x, xo, a1, a2, a3, a4, c1, c2, part, part2, store_w, s); break;
+    case 3: gram3_t<T, 3, MODE, SYM>(g, o, f0, f1, chunks, kc, x, xo, a1, a2, a3, a4, c1, c2, part, part2, store_w, s); break;
+    case 4: gram3_t<T, 4, MODE, SYM>(g, o, f0, f1, chunks, kc, x, xo, a1, a2, a3, a4, c1, c2, part, part2, store_w, s); break;
+    default: gram3_t<T, 5, MODE, SYM>(g, o, f0, f1, chunks, kc, x, xo, a1, a2, a3, a4, c1, c2, part, part2, store_w, s); break;
   }
 }
 
@@ -1180,32 +1180,33 @@ void launch_gram(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, cons
                  const T *y, double *part, hipStream_t s) {
   T *xx = const_cast<T *>(x), *yy = const_cast<T *>(y);
   if (x == y)
-    gram3_tm<T, GM_PLAIN, true>(g, o, f0, f1, chunks, xx, xx, nullptr, nullptr, nullptr, nullptr,
-                                nullptr, part, s);
+    gram3_tm<T, GM_PLAIN, true>(g, o, f0, f1, chunks, xx, xx, xx, nullptr, nullptr, nullptr,
+                                nullptr, nullptr, part, s);
   else
-    gram3_tm<T, GM_PLAIN, false>(g, o, f0, f1, chunks, xx, yy, nullptr, nullptr, nullptr, nullptr,
-                                 nullptr, part, s);
+    gram3_tm<T, GM_PLAIN, false>(g, o, f0, f1, chunks, xx, xx, yy, nullptr, nullptr, nullptr,
+                                 nullptr, nullptr, part, s);
 }
 
 template <typename T>
 void launch_gram_direction(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
                            const T *psi, const T *gres, T *p, const double *beta, double *part,
                            hipStream_t s, bool beta_zero) {
-  gram3_tm<T, GM_DIR, false>(g, o, f0, f1, chunks, const_cast<T *>(psi), p, gres,
+  gram3_tm<T, GM_DIR, false>(g, o, f0, f1, chunks, psi, const_cast<T *>(psi), p, gres,
                              beta_zero ? const_cast<T *>(gres) : nullptr, nullptr, beta, nullptr,
                              part, s);
 }
 
 template <typename T>
-void launch_gram_update(const Geo &g, const OrbSet &o, int f0, int f1, int chunks, T *psi,
-                        const T *p, T *w, const T *q, const double *cs, const double *sn,
-                        double *part, hipStream_t s, double *part_m, bool store_w) {
+void launch_gram_update(const Geo &g, const OrbSet &o, int f0, int f1, int chunks,
+                        const T *psi, T *psi_out, const T *p, T *w, const T *q, const double *cs,
+                        const double *sn, double *part, hipStream_t s, double *part_m,
+                        bool store_w) {
   if (part_m)
-    gram3_tm<T, GM_UPDATE_M, true>(g, o, f0, f1, chunks, psi, const_cast<T *>(p), nullptr, w, q,
-                                   cs, sn, part, s, part_m, store_w ? 1 : 0);
+    gram3_tm<T, GM_UPDATE_M, true>(g, o, f0, f1, chunks, psi, psi_out, const_cast<T *>(p),
+                                   nullptr, w, q, cs, sn, part, s, part_m, store_w ? 1 : 0);
   else
-    gram3_tm<T, GM_UPDATE, true>(g, o, f0, f1, chunks, psi, const_cast<T *>(p), nullptr, w, q,
-                                 cs, sn, part, s);
+    gram3_tm<T, GM_UPDATE, true>(g, o, f0, f1, chunks, psi, psi_out, const_cast<T *>(p), nullptr,
+                                 w, q, cs, sn, part, s);
 }
 
 template <typename T>
@@ -1288,9 +1289,9 @@ void launch_rot_ritz(const Geo &g, const OrbSet &o, int f0, int f1, const double
   template void launch_gram_direction<T>(const Geo &, const OrbSet &, int, int, int, const T *,  \
                                          const T *, T *, const double *, double *, hipStream_t,  \
                                          bool);                                                \
-  template void launch_gram_update<T>(const Geo &, const OrbSet &, int, int, int, T *, const T *, \
-                                      T *, const T *, const double *, const double *, double *,  \
-                                      hipStream_t, double *, bool);                           \
+  template void launch_gram_update<T>(const Geo &, const OrbSet &, int, int, int, const T *, T *, \
+                                      const T *, T *, const T *, const double *, const double *, \
+                                      double *, hipStream_t, double *, bool);                 \
   template void launch_rot_residual<T>(const Geo &, const OrbSet &, int, int, const double *,    \
                                        const T *, const T *, T *, double *, double *,            \
                                        hipStream_t, int, double *, double *);                 \
