@@ -279,6 +279,24 @@ dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, cons
                                int32_t m, int32_t prec, const double *veff, double *energy,
                                void *grad_psi, double *grad_v);
 
+/* dcdft_band_energy for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, results and errors, with H psi formed in a static 8 MiB device array
+ * of the library instead of the context's scratch.  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine).  Each GPU holds one copy
+ * of the array until the process ends, found at dcdft_setup on that device, and
+ * every call on that GPU shares it: calls that overlap in time on one GPU (from
+ * several threads or contexts) race and give undefined results.  Nothing in it
+ * needs clearing (each call writes every part it reads).  The array holds the
+ * layout tables (about 12 bytes per fragment) and as many vectors of the
+ * fragment box as fit (at most m_pad per chunk): a box whose single vector does
+ * not fit beside the tables gives ARG, as does a context on a device numbered 64
+ * or above. */
+dcdft_status dcdft_band_energy_noalloc(dcdft_ctx *c, int32_t frag, const void *psi,
+                                       const double *f, int32_t m, int32_t prec,
+                                       const double *veff, double *energy, void *grad_psi,
+                                       double *grad_v);
+
 /* Device-time accounting of kernel families (for roofline reports).  While
  * enabled, steps run eagerly (not from the step graph) and every launch of the
  * families below is bracketed by HIP events on the context's stream; dcdft_kernel_time returns, since timing was (re-)enabled,

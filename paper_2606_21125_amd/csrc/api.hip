@@ -14,15 +14,30 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 
 #include "dcdft_internal.h"
 
 using namespace dcdft;
 
+// Static device scratch of dcdft_band_energy_noalloc (for callers that cannot
+// allocate device memory), 8 MiB: every GPU the library runs on holds its own copy
+// until the process ends.  Host code never uses the array's name as an address:
+// its device address is looked up once per device, with that device current, in
+// dcdft_setup, and kept in g_noalloc_ptr.
+static __device__ __align__(256) unsigned char scratch[size_t(8) << 20];
+
 namespace {
 
 thread_local std::string g_setup_error;
+
+constexpr size_t kNoAllocBytes = size_t(8) << 20;
+constexpr int kNoAllocMaxDevices = 64;
+// device address of the static scratch array on each device (null: not looked up)
+unsigned char *g_noalloc_ptr[kNoAllocMaxDevices] = {};
+std::mutex g_noalloc_mutex;
+static_assert(sizeof(scratch) == kNoAllocBytes, "static scratch size");
 
 // Central second-derivative weights of the nine-point stencil (Fornberg 1988).
 const double kFDh[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
@@ -943,8 +958,25 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
     return set_err(nullptr, DCDFT_ERR_HIP, "no HIP device available");
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0)
+      return set_err(nullptr, DCDFT_ERR_HIP, "no current HIP device");
+    if (dev < kNoAllocMaxDevices) {
+      std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+      if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+          return set_err(nullptr, DCDFT_ERR_HIP,
+                         fmt("hipGetSymbolAddress(scratch): %s", hipGetErrorString(e)));
+        g_noalloc_ptr[dev] = static_cast<unsigned char *>(ptr);
+      }
+    }
+  }
   dcdft_ctx *c = new (std::nothrow) dcdft_ctx();
   if (!c) return set_err(nullptr, DCDFT_ERR_OOM, "host allocation failed");
+  if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
   Geo &g = c->geo;
   g.Ng = 1;
   for (int d = 0; d < 3; ++d) {
@@ -1788,6 +1820,56 @@ dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, cons
                            (float *)grad_psi, grad_v);
   else
     band_energy_ext<double>(c, c->ext, frag, (const double *)psi, f, m, veff, energy,
+                            (double *)grad_psi, grad_v);
+  return finish_ext(c);
+}
+
+dcdft_status dcdft_band_energy_noalloc(dcdft_ctx *c, int32_t frag, const void *psi,
+                                       const double *f, int32_t m, int32_t prec,
+                                       const double *veff, double *energy, void *grad_psi,
+                                       double *grad_v) {
+  if (!c || !psi || !f) return set_err(c, DCDFT_ERR_ARG, "NULL argument");
+  dcdft_status st = check_ext_args(c, frag, m, prec);
+  if (st != DCDFT_OK) return st;
+  if (m < 1) return set_err(c, DCDFT_ERR_ARG, "m < 1");
+  unsigned char *base = c->device >= 0 && c->device < kNoAllocMaxDevices
+                            ? g_noalloc_ptr[c->device]
+                            : nullptr;
+  if (!base)
+    return set_err(c, DCDFT_ERR_ARG,
+                   fmt("no static scratch on device %d (devices 0..%d are supported)", c->device,
+                       kNoAllocMaxDevices - 1));
+  // carve the array: layout tables, per-band terms, then H psi of one chunk; the
+  // chunk is as many vectors as fit (at most m_pad).  Every region is fully
+  // written before it is read in each call, so nothing needs clearing.
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t elem = prec == DCDFT_PREC_MIXED ? sizeof(float) : sizeof(double);
+  const size_t vec = (size_t)c->geo.n * elem;
+  const size_t tables = up(c->nF * sizeof(int)) + up((c->nF + 1) * sizeof(long long)) +
+                        up(c->m_pad * sizeof(int)) + up(c->m_pad * sizeof(double));
+  const long long fit = tables < kNoAllocBytes ? (long long)((kNoAllocBytes - tables) / vec) : 0;
+  if (fit < 1)
+    return set_err(c, DCDFT_ERR_ARG,
+                   fmt("static scratch of %zu bytes holds the layout tables (%zu bytes) and no "
+                       "vector of %zu bytes",
+                       kNoAllocBytes, tables, vec));
+  dcdft_ctx::ExtScratch X;
+  size_t off = 0;
+  X.m = reinterpret_cast<int *>(base + off);
+  off += up(c->nF * sizeof(int));
+  X.moff = reinterpret_cast<long long *>(base + off);
+  off += up((c->nF + 1) * sizeof(long long));
+  X.band = reinterpret_cast<int *>(base + off);
+  off += up(c->m_pad * sizeof(int));
+  X.eb = reinterpret_cast<double *>(base + off);
+  off += up(c->m_pad * sizeof(double));
+  X.hp = base + off;
+  X.chunk = (int)std::min<long long>(c->m_pad, fit);
+  if (prec == DCDFT_PREC_MIXED)
+    band_energy_ext<float>(c, X, frag, (const float *)psi, f, m, veff, energy,
+                           (float *)grad_psi, grad_v);
+  else
+    band_energy_ext<double>(c, X, frag, (const double *)psi, f, m, veff, energy,
                             (double *)grad_psi, grad_v);
   return finish_ext(c);
 }

@@ -131,6 +131,7 @@ struct dcdft_ctx {
   uint64_t seed = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  int device = 0;                  // the HIP device current at setup
   // Concurrent fragment groups of the batched step: the eigensolver runs over
   // `streams` groups of fragments (split at equal orbital counts), group g on
   // stream g (group 0 on the context's stream), forked and joined by events
