@@ -109,16 +109,29 @@ def total_energy(e_band: float, rho_in: np.ndarray, v_h: np.ndarray, dv: float,
 
 
 _WORKER_LIMITS = None
+_WORKER_PROJECTORS = None
 
 
-def _worker_init(blas_threads: int):
-    """Pool worker set-up: BLAS thread count of the worker process."""
-    global _WORKER_LIMITS
+def _worker_init(blas_threads: int, system=None, n_grid=None):
+    """Pool worker set-up: BLAS thread count of the worker process and, when the
+    system is given, its own copy of the global projectors (for _setup_fragment)."""
+    global _WORKER_LIMITS, _WORKER_PROJECTORS
     try:
         from threadpoolctl import threadpool_limits
         _WORKER_LIMITS = threadpool_limits(limits=blas_threads)
     except ImportError:
         pass
+    if system is not None:
+        _WORKER_PROJECTORS = kb_projectors(system, n_grid)
+
+
+def _setup_fragment(args):
+    """Projectors restricted to one fragment and its orthonormalised initial
+    orbitals (the per-fragment part of OracleSCF's set-up, run in a worker)."""
+    frag, n_global, seed, m, dv = args
+    proj = fragment_projectors(_WORKER_PROJECTORS, frag, n_global)
+    raw = initial_orbitals(seed, frag.alpha, m, frag.shape).reshape(m, -1)
+    return proj, cholesky_orthonormalize(raw, dv)[0]
 
 
 def _solve_fragment(args):
@@ -131,7 +144,10 @@ def _solve_fragment(args):
 class OracleSCF:
     """State and iteration of the DC-DFT SCF on the CPU, FP64."""
 
-    def __init__(self, cfg, workers: int = 1, blas_threads: int = 1):
+    def __init__(self, cfg, workers: int = 1, blas_threads: int = 1, fragments=None):
+        """fragments: None for the whole system, or a subset of fragment indices;
+        only those fragments then get projectors and orbitals (for timing a sample
+        of the fragment eigensolves with solve_fragments; step() needs them all)."""
         self.cfg = cfg
         sysm = cfg.system
         self.n_grid = tuple(int(v) for v in cfg.n_grid)
@@ -141,13 +157,31 @@ class OracleSCF:
         self.ne = sysm.n_electrons
         self.frags = build_fragments(self.n_grid, cfg.num_fragment, cfg.num_rgrid_buffer)
         self.vloc = local_potential(sysm, self.n_grid)
-        self.projectors = kb_projectors(sysm, self.n_grid)
-        self.fproj = [fragment_projectors(self.projectors, f, self.n_global) for f in self.frags]
+        keep = set(range(len(self.frags)) if fragments is None else (int(a) for a in fragments))
+        self.subset = None if fragments is None else sorted(keep)
         self.m = [int(v) for v in cfg.nstate_frag]
-        self.psi = []
-        for f in self.frags:
-            raw = initial_orbitals(cfg.seed, f.alpha, self.m[f.alpha], f.shape).reshape(self.m[f.alpha], -1)
-            self.psi.append(cholesky_orthonormalize(raw, self.dv)[0])
+        # fragment eigensolves on a pool of fresh interpreter processes ("spawn":
+        # nothing of the caller's process, such as an initialised GPU runtime, is
+        # inherited), kept until close(); with a pool the per-fragment set-up
+        # (restricted projectors, initial orbitals) runs there too
+        self.workers = workers
+        self.blas_threads = blas_threads
+        self._pool = None
+        self.fproj = [None] * len(self.frags)
+        self.psi = [None] * len(self.frags)
+        todo = [f for f in self.frags if f.alpha in keep]
+        if workers > 1 and len(todo) > 1:
+            self._start_pool()
+            jobs = [(f, self.n_global, cfg.seed, self.m[f.alpha], self.dv) for f in todo]
+            for f, (proj, psi) in zip(todo, self._pool.map(_setup_fragment, jobs)):
+                self.fproj[f.alpha], self.psi[f.alpha] = proj, psi
+        else:
+            projectors = kb_projectors(sysm, self.n_grid)
+            for f in todo:
+                self.fproj[f.alpha] = fragment_projectors(projectors, f, self.n_global)
+                raw = initial_orbitals(cfg.seed, f.alpha, self.m[f.alpha], f.shape).reshape(
+                    self.m[f.alpha], -1)
+                self.psi[f.alpha] = cholesky_orthonormalize(raw, self.dv)[0]
         omega = float(np.prod(sysm.cell))
         self.rho_in = np.full(self.n_grid[::-1], self.ne / omega)
         self.rho_frag_in = [np.full(f.n, self.ne / omega) for f in self.frags]
@@ -157,12 +191,6 @@ class OracleSCF:
         self.w = None
         self.mu = None
         self.iteration = 0
-        # fragment eigensolves on a pool of fresh interpreter processes ("spawn":
-        # nothing of the caller's process, such as an initialised GPU runtime, is
-        # inherited), created on first use and kept until close()
-        self.workers = workers
-        self.blas_threads = blas_threads
-        self._pool = None
         self.veff_last = {}         # V_eff of each fragment in the last eigensolve
         self.fixed_density = False
         self.template_xi = 0.0      # xi of V^alpha (Eq. (5)); 0: no template potential
@@ -176,6 +204,12 @@ class OracleSCF:
             self.rho_frag_in = [flat[f.global_index].copy() for f in self.frags]
         else:
             self.rho_frag_in = [np.array(r, dtype=np.float64).ravel() for r in rho_frag]
+
+    def _start_pool(self):
+        if self._pool is None:
+            import multiprocessing as mp
+            self._pool = mp.get_context("spawn").Pool(
+                self.workers, _worker_init, (self.blas_threads, self.cfg.system, self.n_grid))
 
     def close(self):
         """End the worker pool (if one was started)."""
@@ -209,16 +243,15 @@ class OracleSCF:
             jobs.append((self.psi[a], veff.reshape(f.shape), self.fproj[a], self.h,
                          self.dv, self.cfg.cg_sweeps, f.shape))
         if self.workers > 1 and len(jobs) > 1:
-            if self._pool is None:
-                import multiprocessing as mp
-                self._pool = mp.get_context("spawn").Pool(self.workers, _worker_init,
-                                                           (self.blas_threads,))
+            self._start_pool()
             res = self._pool.map(_solve_fragment, jobs)
         else:
             res = [_solve_fragment(j) for j in jobs]
         return dict(zip(alphas, res))
 
     def step(self) -> dict:
+        if self.subset is not None:
+            raise RuntimeError("this oracle holds a subset of the fragments; step() needs all")
         cfg = self.cfg
         dv = self.dv
         v_h = poisson_fd(self.rho_in, self.h)

@@ -728,6 +728,9 @@ k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mf = o.m[f];
   const int rmax = o.row_pad ? MP - 1 : mf - 1;
+  // 16-orbital tiles this fragment uses (wave-uniform): the rest are not loaded
+  // (their addresses repeat the first tile's) nor multiplied
+  const int tf = __builtin_amdgcn_readfirstlane((mf + 15) >> 4);
   const int *ra = kb.reg_atom + ((long long)f * kb.NR + reg) * kb.KS;
   const int nt = kb.reg_nt[(long long)f * kb.NR + reg];   // slot tiles in use
   const double *Cf = C + (long long)f * kb.A_max * o.m_pad;
@@ -757,7 +760,7 @@ k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
 #pragma unroll
     for (int jt = 0; jt < TM; ++jt)
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) yv[jt][rr] = *yaddr(jt, rr, pc);
+      for (int rr = 0; rr < 4; ++rr) yv[jt][rr] = *yaddr(jt < tf ? jt : 0, rr, pc);
   };
   T yv[TM][4];
   load_y(0, yv);
@@ -783,7 +786,7 @@ k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
       for (int st = 0; st < KTE * 4; ++st) {
 #pragma unroll
         for (int jt = 0; jt < TM; ++jt)
-          acc[jt] = MM::mma(ec[(4 * st + kk) * LD + jt * 16 + c], bv[st], acc[jt]);
+          if (jt < tf) acc[jt] = MM::mma(ec[(4 * st + kk) * LD + jt * 16 + c], bv[st], acc[jt]);
         if ((st & 3) == 3) __builtin_amdgcn_sched_barrier(0);
       }
     };

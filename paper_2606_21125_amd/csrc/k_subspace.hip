@@ -91,6 +91,9 @@ k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int 
   const int wg = blockIdx.x % wpf;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mf = o.m[f], mp = o.m_pad;
+  // 16-orbital tiles this fragment uses (wave-uniform); the rest are neither
+  // loaded from memory nor multiplied
+  const int tf = __builtin_amdgcn_readfirstlane((mf + 15) >> 4);
   const double *Mf = M + (long long)f * mp * mp;
   // R^T with output orbital j as the row: RtT[j][kpos(i)] = R[i][j]
   for (int e = threadIdx.x; e < MP * MP; e += blockDim.x) {
@@ -123,7 +126,10 @@ k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int 
     const T *xs = (arr ? x2 : x) + base;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      const T v = (xs + (long long)(4 * s) * g.n)[lo];
+      // rows past the fragment's tiles repeat the first step's address (a cache
+      // hit, no memory traffic); their values are masked
+      const int sr = s < 4 * tf ? s : 0;
+      const T v = (xs + (long long)(4 * sr) * g.n)[lo];
       bx[s] = (4 * s + kk < mf && pin) ? v : (T)0;
     }
   };
@@ -144,14 +150,14 @@ k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int 
       for (int jt = 0; jt < TM; ++jt)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr)
-          zv[jt][rr] = (z + base + (long long)(jt * 16 + MM::row_u(rr)) * g.n)[lo_out];
+          zv[jt][rr] = (z + base + (long long)((jt < tf ? jt : 0) * 16 + MM::row_u(rr)) * g.n)[lo_out];
     }
     if (FL & RF_DOT_W) {
 #pragma unroll
       for (int jt = 0; jt < TM; ++jt)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr)
-          wv[jt][rr] = (wdot + base + (long long)(jt * 16 + MM::row_u(rr)) * g.n)[lo_out];
+          wv[jt][rr] = (wdot + base + (long long)((jt < tf ? jt : 0) * 16 + MM::row_u(rr)) * g.n)[lo_out];
     }
     T bn[NS];
     load_rows(it + 1 < NITEM ? it + 1 : it, bn);  // unconditional (see above)
@@ -160,11 +166,13 @@ k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int 
     for (int jt = 0; jt < TM; ++jt) acc[jt] = MM::zero();
 #pragma unroll
     for (int jt = 0; jt < TM; ++jt) {
+      if (jt >= tf) continue;
       T a[NS];
       lds_read_vec<T, NS>(RtT + (jt * 16 + jl) * S2 + kk * NS, a);
 #pragma unroll
       for (int s = 0; s < NS; ++s)
-        if (!(FL & RF_TRI) || s < 4 * jt + 4) acc[jt] = MM::mma(a[s], bx[s], acc[jt]);
+        if ((!(FL & RF_TRI) || s < 4 * jt + 4) && s < 4 * tf)
+          acc[jt] = MM::mma(a[s], bx[s], acc[jt]);
       // keep later operand reads from being hoisted (register pressure)
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -225,6 +233,7 @@ k_rot_cholres(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ Linv,
   const int wg = blockIdx.x % wpf;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mf = o.m[f], mp = o.m_pad;
+  const int tf = __builtin_amdgcn_readfirstlane((mf + 15) >> 4);   // tiles in use
   const double *Lf = Linv + (long long)f * mp * mp, *Bf = Bm + (long long)f * mp * mp;
   for (int e = threadIdx.x; e < MP * MP; e += blockDim.x) {
     const int j = e / MP, i = e % MP;
@@ -243,7 +252,8 @@ k_rot_cholres(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ Linv,
     const int lo = kk * g.n + (pin ? pc : g.n - 1);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      const T v = (xs + base + (long long)(4 * s) * g.n)[lo];
+      const int sr = s < 4 * tf ? s : 0;   // past the fragment's tiles: a cache hit
+      const T v = (xs + base + (long long)(4 * sr) * g.n)[lo];
       bx[s] = (4 * s + kk < mf && pin) ? v : (T)0;
     }
   };
@@ -267,6 +277,7 @@ k_rot_cholres(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ Linv,
       ap[jt] = MM::zero();
       aw[jt] = MM::zero();
       ab[jt] = MM::zero();
+      if (jt >= tf) continue;
       T a[NS];
       lds_read_vec<T, NS>(R1 + (jt * 16 + jl) * S2 + kk * NS, a);
       // L^-1 is lower triangular: inputs past the output tile contribute nothing
@@ -279,7 +290,8 @@ k_rot_cholres(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ Linv,
       __builtin_amdgcn_sched_barrier(0);
       lds_read_vec<T, NS>(R2 + (jt * 16 + jl) * S2 + kk * NS, a);
 #pragma unroll
-      for (int s = 0; s < NS; ++s) ab[jt] = MM::mma(a[s], bx[s], ab[jt]);
+      for (int s = 0; s < NS; ++s)
+        if (s < 4 * tf) ab[jt] = MM::mma(a[s], bx[s], ab[jt]);
       __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
@@ -440,6 +452,9 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, const T *x, T *xo, T *a
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int mf = o.m[f];
   const int mp = o.m_pad;
+  // 16-orbital tiles this fragment uses (wave-uniform): rows past them are not
+  // read from memory and their output tiles are not multiplied (they stay zero)
+  const int tf = __builtin_amdgcn_readfirstlane((mf + 15) >> 4);
   const long long base = o.moff[f] * (long long)g.n;
   const int p_begin = c * kchunk;
   const int p_end = min(p_begin + kchunk, g.n);
@@ -508,7 +523,10 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, const T *x, T *xo, T *a
   auto load_item = [&](int k, int p0) {
     {
       const int it = threadIdx.x + 256 * k;
-      const int row = it / (kGramKT / 4) < MP ? it / (kGramKT / 4) : MP - 1;
+      const int row0 = it / (kGramKT / 4) < MP ? it / (kGramKT / 4) : MP - 1;
+      // rows past the fragment's tiles repeat a row of the first tile (a cache
+      // hit); their values are masked at commit
+      const int row = row0 < 16 * tf ? row0 : (row0 & 15);
       const int p = p0 + (it % (kGramKT / 4)) * 4;
       const int lo = row * g.n;  // lane offset (fits: m_pad n < 2^31)
 #pragma unroll
@@ -596,7 +614,7 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, const T *x, T *xo, T *a
     constexpr int KQ = kGramKT / 4;
 #pragma unroll
     for (int k = 0; k < PER_WAVE; ++k) {
-      if (tI[k] < 0) continue;
+      if (tI[k] < 0 || tI[k] >= tf || tJ[k] >= tf) continue;
       T av[KQ], bv[KQ];
       lds_read_vec<T, KQ>(Xs + (tI[k] * 16 + r) * LD + kk * KQ, av);
       lds_read_vec<T, KQ>((UPM && tW[k] ? Ys : Yl) + (tJ[k] * 16 + r) * LD + kk * KQ, bv);

@@ -1,5 +1,6 @@
 """Band-energy functional E = sum_i f_i <psi_i|H|psi_i> and its gradient through
-torch.autograd (BandEnergy -> dcdft_band_energy), on the 64-atom system.
+torch.autograd (BandEnergy -> dcdft_band_energy), on the 64-atom system (8
+fragments of 24^3) and on two fragments of the 512-atom cell (64 fragments of 24^3).
 
 Checks: forward and both gradients against the oracle's analytic formulas;
 central differences of the GPU forward along 32 random unit directions with
@@ -17,25 +18,29 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 
-def _setup():
+FRAGS = {4: (0, 5), 2: (0, 37)}
+
+
+def _setup(k=4):
     from paper_2606_21125_amd import DCDFT
-    cfg = workloads.config(4)
-    o = oracle.OracleSCF(cfg)
+    cfg = workloads.config(k)
+    o = oracle.OracleSCF(cfg, fragments=FRAGS[k] if k == 2 else None)
     d = DCDFT.from_config(cfg)
     return cfg, o, d
 
 
+@pytest.mark.parametrize("k", [4, 2])
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
-def test_band_energy_gradients_against_oracle(dtype):
+def test_band_energy_gradients_against_oracle(dtype, k):
     require_gpu()
     import torch
     from paper_2606_21125_amd.autograd import band_energy
-    cfg, o, d = _setup()
+    cfg, o, d = _setup(k)
     tdt = getattr(torch, dtype)
     rng = np.random.default_rng(21)
     v_h = np.zeros_like(o.rho_in)
     with d:
-        for frag in (0, 5):
+        for frag in FRAGS[k]:
             shape = o.frags[frag].shape
             m = 12
             psi = rng.normal(size=(m,) + shape) * 0.05
