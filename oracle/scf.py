@@ -18,8 +18,9 @@ total density):
      for a fixed geometry, is omitted).
   7. residuals: dV sum |rho_out - rho_in| / N_e and the paper's convergence
      measure dV sum |rho_k^in - rho_(k-1)^in| / N_e (Sec. 3.3).
-  8. linear mixing rho^in <- rho^in + a (rho^out - rho^in), applied to the
-     total density and to every fragment density.
+  8. mixing: linear, rho^in <- rho^in + a (rho^out - rho^in), applied to the
+     total density and to every fragment density; or, after set_mixer("pulay",
+     ...), Pulay mixing with a Kerker preconditioner (``oracle.mixing``).
 
 Fixed-density DC (Sec. 2.6, third usage; Sec. 3.2): rho_tot^in is a density
 read in and stays frozen.  Every iteration re-solves the fragment eigenproblems
@@ -38,6 +39,7 @@ import numpy as np
 from .grid import FD_COEFFS, HALF_WIDTH, build_fragments, laplacian_periodic
 from .model import (fragment_projectors, grid_spacing, kb_projectors, lda_pz81,
                     local_potential)
+from .mixing import PulayKerkerMixer
 from .rng import initial_orbitals
 from .solver import (apply_h, cg_eigensolver, cholesky_orthonormalize, core_weights,
                      fermi_level, fermi_occupation, fragment_density)
@@ -194,6 +196,18 @@ class OracleSCF:
         self.veff_last = {}         # V_eff of each fragment in the last eigensolve
         self.fixed_density = False
         self.template_xi = 0.0      # xi of V^alpha (Eq. (5)); 0: no template potential
+        self.mixer = None           # None: linear mixing with cfg.mixing
+
+    def set_mixer(self, kind: str, alpha: float = 0.3, q0: float = 0.8, history: int = 8):
+        """kind "linear" (cfg.mixing, the default) or "pulay" (Pulay mixing with
+        step alpha, Kerker wave number q0 (bohr^-1; 0: no preconditioner) and up to
+        `history` pairs); a new Pulay mixer starts with an empty history."""
+        if kind == "linear":
+            self.mixer = None
+        elif kind == "pulay":
+            self.mixer = PulayKerkerMixer(self.n_grid, self.h, alpha, q0, history)
+        else:
+            raise ValueError(f"unknown mixer {kind}")
 
     def set_density(self, rho_tot, rho_frag=None):
         """Replace rho_tot^in; every rho_alpha^in becomes rho_frag[alpha] or, when
@@ -283,11 +297,24 @@ class OracleSCF:
         e_tot = total_energy(e_band, self.rho_in, v_h, dv, cfg.smearing, ent)
         r_out_in = dv * float(np.sum(np.abs(rho_out - self.rho_in))) / self.ne
         charge = dv * float(np.sum(rho_out))
-        a_mix = 0.0 if self.fixed_density else cfg.mixing
-        rho_new = self.rho_in + a_mix * (rho_out - self.rho_in)
+        if self.fixed_density:
+            rho_new, frag_new = self.rho_in, self.rho_frag_in
+        elif self.mixer is None:
+            a_mix = cfg.mixing
+            rho_new = self.rho_in + a_mix * (rho_out - self.rho_in)
+            frag_new = [ri + a_mix * (ro - ri)
+                        for ri, ro in zip(self.rho_frag_in, self.rho_frag_out)]
+        else:
+            # fragment densities as the gathered total density plus a deviation
+            fin, fout = self.rho_in.ravel(), rho_out.ravel()
+            d_in = [self.rho_frag_in[a] - fin[f.global_index] for a, f in enumerate(self.frags)]
+            d_out = [self.rho_frag_out[a] - fout[f.global_index] for a, f in enumerate(self.frags)]
+            rho_new, d_new = self.mixer.mix(self.rho_in, rho_out, d_in, d_out)
+            fnew = rho_new.ravel()
+            frag_new = [fnew[f.global_index] + d_new[a] for a, f in enumerate(self.frags)]
         r_paper = dv * float(np.sum(np.abs(rho_new - self.rho_in))) / self.ne
         self.rho_in = rho_new
-        self.rho_frag_in = [ri + a_mix * (ro - ri) for ri, ro in zip(self.rho_frag_in, self.rho_frag_out)]
+        self.rho_frag_in = frag_new
         self.iteration += 1
         self.v_h = v_h
         return dict(iter=self.iteration, mu=mu, e_total=e_tot, e_band=e_band,
