@@ -204,6 +204,28 @@ dcdft_status dcdft_fix_density(dcdft_ctx *c, int32_t fixed);
  * Errors: ARG (xi negative or not finite). */
 dcdft_status dcdft_set_template(dcdft_ctx *c, double xi);
 
+/* Density mixing of the SCF step.  The paper iterates rho_tot "by the same
+ * procedure as conventional DFT" (Sec. 2.2) and names no scheme.
+ *   DCDFT_MIX_LINEAR: rho <- rho + alpha (rho^out - rho) for rho_tot and every
+ *     fragment density (setup's `mixing` is this alpha); q0 and history ignored.
+ *   DCDFT_MIX_PULAY: Pulay (DIIS) mixing with a Kerker preconditioner.  From the
+ *     last `history` pairs (rho_in^(j), R^(j) = rho_out^(j) - rho_in^(j)) the weights
+ *     c (sum 1) minimise |sum c_j R^(j)|^2 (plain sum over grid points, Gaussian
+ *     elimination with partial pivoting on the bordered system, oldest entry
+ *     first; a pivot at most 1e-12 max|A| cuts the history to the newest entry),
+ *     and rho_new = sum c_j rho_in^(j) + alpha K[sum c_j R^(j)], K(q) = q^2 /
+ *     (q^2 + q0^2) on the Fourier modes of the periodic grid with q^2 the symbol
+ *     of minus the nine-point Laplacian of the Poisson solve (K = 1 when q0 = 0).
+ *     Every fragment density is the gathered rho_tot plus a deviation (zero on
+ *     its core, Eq. (3)), mixed with the same weights and alpha without K.
+ *     A new Pulay mixer starts with an empty history.
+ * alpha in (0, 1], q0 >= 0 (bohr^-1), history 1..16.  The first Pulay call
+ * allocates (history + 1) x (N + F n) doubles twice, kept until dcdft_destroy.
+ * Errors: ARG, OOM, HIP. */
+enum { DCDFT_MIX_LINEAR = 0, DCDFT_MIX_PULAY = 1 };
+dcdft_status dcdft_set_mixer(dcdft_ctx *c, int32_t kind, double alpha, double q0,
+                             int32_t history);
+
 /* DC-LCFO post-processing (Sec. 2.3, Eqs. (6)-(9)), on the orbitals and V_eff of
  * the last step (normally a converged SCF).  Per fragment: the orbitals with
  * eps < eps_cut (Ha; the paper quotes eps_cut - mu = 0.1 eV) projected on the

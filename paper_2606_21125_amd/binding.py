@@ -29,7 +29,7 @@ EXPORTED = [
     "dcdft_setup", "dcdft_scf_step", "dcdft_density", "dcdft_density_device",
     "dcdft_eigenvalues", "dcdft_fragment_info", "dcdft_get_field", "dcdft_get_fragment_field",
     "dcdft_get_orbitals", "dcdft_set_orbitals", "dcdft_set_density", "dcdft_fix_density",
-    "dcdft_set_template", "dcdft_lcfo_build", "dcdft_lcfo_basis", "dcdft_lcfo_hamiltonian",
+    "dcdft_set_template", "dcdft_set_mixer", "dcdft_lcfo_build", "dcdft_lcfo_basis", "dcdft_lcfo_hamiltonian",
     "dcdft_lcfo_block",
     "dcdft_apply_h",
     "dcdft_band_energy", "dcdft_band_energy_noalloc", "dcdft_kernel_timing", "dcdft_kernel_time", "dcdft_autotune",
@@ -38,6 +38,7 @@ EXPORTED = [
     "dcdft_status_string", "dcdft_last_error",
 ]
 KERNEL_HLOC, KERNEL_GRAM, KERNEL_ROTATE, KERNEL_GRAM_FUSED, KERNEL_KB = 0, 1, 2, 3, 4
+MIX_LINEAR, MIX_PULAY = 0, 1
 HLOC_VARIANTS = ("plane", "halo_pd2", "halo_pd3", "halo_pd4", "halo_pd2_ends", "vec",
                  "vec_wide", "vec_z2", "vec_z3", "vec8", "vec8_wide")
 
@@ -133,6 +134,8 @@ def load_library(path: Optional[str] = None):
         "dcdft_set_density": ([vp, pd, pd], ctypes.c_int),
         "dcdft_fix_density": ([vp, ctypes.c_int32], ctypes.c_int),
         "dcdft_set_template": ([vp, ctypes.c_double], ctypes.c_int),
+        "dcdft_set_mixer": ([vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_int32], ctypes.c_int),
         "dcdft_lcfo_build": ([vp, ctypes.c_double, ctypes.c_double,
                               ctypes.POINTER(DcdftLcfoInfo)], ctypes.c_int),
         "dcdft_lcfo_basis": ([vp, ctypes.c_int32, pd, ctypes.c_size_t, pi], ctypes.c_int),
@@ -400,6 +403,13 @@ class DCDFT:
 
     def dcdft_set_template(self, xi: float) -> None:
         _check(self._lib.dcdft_set_template(self.ctx, float(xi)), self.ctx)
+
+    def dcdft_set_mixer(self, kind, alpha: float = 0.3, q0: float = 0.8,
+                        history: int = 8) -> None:
+        """kind: MIX_LINEAR / MIX_PULAY (or "linear" / "pulay")."""
+        k = {"linear": MIX_LINEAR, "pulay": MIX_PULAY}.get(kind, kind)
+        _check(self._lib.dcdft_set_mixer(self.ctx, int(k), float(alpha), float(q0),
+                                         int(history)), self.ctx)
 
     def dcdft_lcfo_build(self, eps_cut: float, lambda_cut: float = 1e-7) -> dict:
         info = DcdftLcfoInfo()

@@ -859,9 +859,15 @@ void enqueue_phase(dcdft_ctx *c, int phase) {
                            c->d_rhof_out, c->d_rho_out, s);
   // 6-8. energy terms, residuals, mixing (a mixing fraction of 0 leaves a frozen
   // rho_tot^in bitwise unchanged and makes the paper's residual 0)
-  launch_global_terms(g, c->d_rho_in, c->d_rho_out, c->d_vh, c->fixed_density ? 0.0 : c->mixing,
-                      c->d_part, c->n_part, c->d_scal, s, c->ne, c->smearing);
-  if (!c->fixed_density) launch_frag_mix(g, c->nF, c->d_rhof_in, c->d_rhof_out, c->mixing, s);
+  const bool pulay = c->mix_kind == DCDFT_MIX_PULAY && !c->fixed_density;
+  launch_global_terms(g, c->d_rho_in, c->d_rho_out, c->d_vh,
+                      (c->fixed_density || pulay) ? 0.0 : c->mixing, c->d_part, c->n_part,
+                      c->d_scal, s, c->ne, c->smearing);
+  if (pulay)
+    launch_pulay_mix(g, c->nF, c->mix, c->d_rho_out, c->d_rhof_out, c->d_rho_in, c->d_rhof_in,
+                     c->ne, c->d_qf, c->d_qi, c->d_lam, c->d_fft_a, c->d_fft_b, c->d_scal, s);
+  else if (!c->fixed_density)
+    launch_frag_mix(g, c->nF, c->d_rhof_in, c->d_rhof_out, c->mixing, s);
   launch_nan_check(c->d_eps, c->M_tot, c->d_flags, s);
   launch_nan_check(c->d_rho_out, g.Ng, c->d_flags, s);
 }
@@ -1479,6 +1485,71 @@ dcdft_status dcdft_set_template(dcdft_ctx *c, double xi) {
   return DCDFT_OK;
 }
 
+
+dcdft_status dcdft_set_mixer(dcdft_ctx *c, int32_t kind, double alpha, double q0,
+                             int32_t history) {
+  if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  if (kind != DCDFT_MIX_LINEAR && kind != DCDFT_MIX_PULAY)
+    return set_err(c, DCDFT_ERR_ARG, fmt("unknown mixer kind %d", kind));
+  if (!(alpha > 0.0 && alpha <= 1.0))
+    return set_err(c, DCDFT_ERR_ARG, fmt("alpha = %g outside (0, 1]", alpha));
+  if (kind == DCDFT_MIX_PULAY && (!(q0 >= 0.0) || !std::isfinite(q0) || history < 1 ||
+                                  history > kMixMaxSlots - 1))
+    return set_err(c, DCDFT_ERR_ARG,
+                   fmt("Pulay mixer: q0 = %g must be finite and >= 0, history = %d in 1..%d",
+                       q0, history, kMixMaxSlots - 1));
+  HIPTRY(c, hipStreamSynchronize(c->stream));
+  drop_graph(c);   // the mixing launches and their arguments change
+  if (kind == DCDFT_MIX_LINEAR) {
+    c->mix_kind = kind;
+    c->mixing = alpha;
+    return DCDFT_OK;
+  }
+  MixState &m = c->mix;
+  const Geo &g = c->geo;
+  const size_t fn = (size_t)c->nF * g.n;
+  if (history + 1 > m.S) {
+    // (re)allocate the ring for history + 1 slots; earlier buffers stay owned by
+    // the context until dcdft_destroy
+    const bool first = m.st == nullptr;
+    m.S = history + 1;
+    m.nblk = 1024;
+    HIPTRY(c, dalloc(c, &m.hrho, (size_t)m.S * g.Ng));
+    HIPTRY(c, dalloc(c, &m.hres, (size_t)m.S * g.Ng));
+    HIPTRY(c, dalloc(c, &m.hdin, (size_t)m.S * fn));
+    HIPTRY(c, dalloc(c, &m.hdres, (size_t)m.S * fn));
+    HIPTRY(c, dalloc(c, &m.rbar, (size_t)g.Ng));
+    HIPTRY(c, dalloc(c, &m.kres, (size_t)g.Ng));
+    HIPTRY(c, dalloc(c, &m.part, (size_t)m.nblk * kMixMaxSlots));
+    if (first) {
+      HIPTRY(c, dalloc(c, &m.st, 2));
+      HIPTRY(c, dalloc(c, &m.A, (size_t)kMixMaxSlots * kMixMaxSlots));
+      HIPTRY(c, dalloc(c, &m.c, (size_t)kMixMaxSlots));
+      // the history bookkeeping is state of the step: set aside and restored with it
+      for (const std::pair<void *, size_t> l :
+           {std::pair<void *, size_t>{m.st, 2 * sizeof(int)},
+            std::pair<void *, size_t>{m.A, kMixMaxSlots * kMixMaxSlots * sizeof(double)},
+            std::pair<void *, size_t>{m.c, kMixMaxSlots * sizeof(double)}}) {
+        char *save = nullptr;
+        HIPTRY(c, dalloc(c, &save, l.second));
+        c->backups.push_back({l.first, save, l.second});
+      }
+    }
+    // slots hold finite values before their first use (their dot products are
+    // formed but not used until the slot enters the history)
+    HIPTRY(c, hipMemsetAsync(m.hres, 0, (size_t)m.S * g.Ng * sizeof(double), c->stream));
+  }
+  m.H = history;
+  m.alpha = alpha;
+  m.q0 = q0;
+  const int st0[2] = {0, -1};
+  HIPTRY(c, hipMemcpyAsync(m.st, st0, sizeof(st0), hipMemcpyHostToDevice, c->stream));
+  HIPTRY(c, hipMemsetAsync(m.A, 0, kMixMaxSlots * kMixMaxSlots * sizeof(double), c->stream));
+  HIPTRY(c, hipMemsetAsync(m.c, 0, kMixMaxSlots * sizeof(double), c->stream));
+  HIPTRY(c, hipStreamSynchronize(c->stream));
+  c->mix_kind = kind;
+  return DCDFT_OK;
+}
 
 // Neighbour pairs of the DC-LCFO matrix: (a, b != a) whose core b meets the box of
 // a, with the overlapping coordinates per axis as (local in a's box, local in b's

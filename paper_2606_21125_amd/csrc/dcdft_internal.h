@@ -117,6 +117,21 @@ struct KBTables {
 
 void fail_hip(hipError_t e, const char *what);
 
+// Pulay mixing with a Kerker preconditioner: history of at most H entries in
+// S = H + 1 ring slots (the step writes the free one), device-side bookkeeping
+// st = {entries in use, newest slot}, residual Gram A [S][S] by slot, weights c [S].
+constexpr int kMixMaxSlots = 17;    // H <= 16
+struct MixState {
+  int S = 0, H = 0, nblk = 0;
+  double alpha = 0.3, q0 = 0.0;
+  int *st = nullptr;                 // [2]
+  double *A = nullptr, *c = nullptr; // [S * S], [S]
+  double *part = nullptr;            // [nblk * kMixMaxSlots] block partials
+  double *hrho = nullptr, *hres = nullptr;   // [S][N_g]: rho_in^(j), R^(j)
+  double *hdin = nullptr, *hdres = nullptr;  // [S][F n]: fragment deviations
+  double *rbar = nullptr, *kres = nullptr;   // [N_g]: sum c rho_in, K sum c R
+};
+
 }  // namespace dcdft
 
 struct dcdft_ctx {
@@ -253,6 +268,8 @@ struct dcdft_ctx {
   hipEvent_t ev_ph[4] = {nullptr, nullptr, nullptr, nullptr};
   bool use_graph = true;
   double template_xi = 0.0;    // xi of the density-template potential; 0: off
+  int mix_kind = DCDFT_MIX_LINEAR;
+  dcdft::MixState mix;
   // DC-LCFO post-processing (built on request; FP64 arrays in the orbital layout)
   double *d_lcfo_lam = nullptr, *d_lcfo_hlam = nullptr;  // basis, H^alpha basis [M_tot + m_pad][n]
   double *d_lcfo_sig = nullptr, *d_lcfo_w = nullptr;  // overlap eigenvalues, core weights [M_tot]
@@ -419,6 +436,12 @@ void launch_global_terms(const Geo &g, double *rho_in, const double *rho_out, co
                          double ne, double sigma);
 void launch_frag_mix(const Geo &g, int nfrag, double *rhof_in, const double *rhof_out,
                      double mixing, hipStream_t s);
+// Pulay-Kerker mixing of rho_in (with the paper's residual into scal) and of every
+// fragment density (gathered total density plus the mixed deviation)
+void launch_pulay_mix(const Geo &g, int nfrag, const MixState &m, const double *rho_out,
+                      const double *rhof_out, double *rho_in, double *rhof_in, double ne,
+                      double *const qf[3], double *const qi[3], double *const lam[3],
+                      double *wa, double *wb, double *scal, hipStream_t s);
 // Poisson: V_H from rho (exact FD solution, zero mean)
 void launch_poisson(const Geo &g, const double *rho, double *vh, double *wa, double *wb,
                     double *const qf[3], double *const qi[3], double *const lam[3],

@@ -367,6 +367,228 @@ __global__ void k_nan_check(const double *p, long long n, int *flags) {
   if (bad) atomicOr(flags, FLAG_NAN);
 }
 
+// ---- Pulay mixing with a Kerker preconditioner ----------------------------------
+// History slots: S = H + 1 ring slots of rho_in, R = rho_out - rho_in (global) and
+// of the fragment deviations delta_in, delta_R (fragment boxes); at most H are in
+// use, so the slot a step writes never holds an entry of the history it mixes.
+// st[0] = entries in use, st[1] = newest slot (-1: none yet).
+// A[i * S + j] = sum_g R_i(g) R_j(g) by slot; c[slot] = Pulay weight.
+
+// Record the step in the free slot s = st[1] + 1 (mod S) and form the partial
+// dot products of its residual with every slot's: part[block][j], j < S.
+__global__ void __launch_bounds__(256) k_mix_record(Geo g, int S, const int *__restrict__ st,
+                                                    const double *__restrict__ rho_in,
+                                                    const double *__restrict__ rho_out,
+                                                    double *__restrict__ hrho,
+                                                    double *__restrict__ hres,
+                                                    double *__restrict__ part) {
+  __shared__ double red[16];
+  const int s = (st[1] + 1) % S;
+  double acc[kMixMaxSlots];
+#pragma unroll
+  for (int j = 0; j < kMixMaxSlots; ++j) acc[j] = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.Ng;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double ri = rho_in[i];
+    const double r = rho_out[i] - ri;
+    hrho[(long long)s * g.Ng + i] = ri;
+    hres[(long long)s * g.Ng + i] = r;
+#pragma unroll
+    for (int j = 0; j < kMixMaxSlots; ++j)
+      if (j < S) acc[j] += r * (j == s ? r : hres[(long long)j * g.Ng + i]);
+  }
+  for (int j = 0; j < S; ++j) {
+    const double t = block_sum(acc[j], red);
+    if (threadIdx.x == 0) part[blockIdx.x * kMixMaxSlots + j] = t;
+  }
+}
+
+// Fragment deviations of the step into slot s: delta_in = rho_alpha^in - rho_in(g(l)),
+// delta_R = (rho_alpha^out - rho_out(g(l))) - delta_in.
+__global__ void __launch_bounds__(256) k_mix_record_frag(Geo g, int nfrag, int S,
+                                                         const int *__restrict__ st,
+                                                         const double *__restrict__ rho_in,
+                                                         const double *__restrict__ rho_out,
+                                                         const double *__restrict__ rhof_in,
+                                                         const double *__restrict__ rhof_out,
+                                                         double *__restrict__ hdin,
+                                                         double *__restrict__ hdres) {
+  const int s = (st[1] + 1) % S;
+  const long long total = (long long)nfrag * g.n;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int f = (int)(i / g.n), l = (int)(i % g.n);
+    const long long gi = global_of_local(g, f, l);
+    const double din = rhof_in[i] - rho_in[gi];
+    hdin[(long long)s * total + i] = din;
+    hdres[(long long)s * total + i] = (rhof_out[i] - rho_out[gi]) - din;
+  }
+}
+
+// One thread: the new row of A from the partials, the history advanced by one,
+// and the Pulay weights from the bordered system [[A, 1], [1^T, 0]] [c; l] = [0; 1]
+// over the entries in use, oldest first, by Gaussian elimination with partial
+// pivoting; a pivot at most 1e-12 max|A| cuts the history to the newest entry.
+__global__ void __launch_bounds__(64) k_mix_solve(int S, int H, int nblk, int *__restrict__ st,
+                                                  const double *__restrict__ part,
+                                                  double *__restrict__ A,
+                                                  double *__restrict__ c) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int s = (st[1] + 1) % S;
+  for (int j = 0; j < S; ++j) {
+    double t = 0.0;
+    for (int b = 0; b < nblk; ++b) t += part[b * kMixMaxSlots + j];
+    A[s * S + j] = t;
+    A[j * S + s] = t;
+  }
+  int k = st[0] + 1 > H ? H : st[0] + 1;
+  st[0] = k;
+  st[1] = s;
+  int slot[kMixMaxSlots];
+  for (int q = 0; q < k; ++q) slot[q] = ((s - (k - 1) + q) % S + S) % S;
+  double m[kMixMaxSlots + 1][kMixMaxSlots + 2];
+  double amax = 0.0;
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      m[i][j] = A[slot[i] * S + slot[j]];
+      amax = fmax(amax, fabs(m[i][j]));
+    }
+  for (int i = 0; i < k; ++i) {
+    m[i][k] = 1.0;
+    m[k][i] = 1.0;
+    m[i][k + 1] = 0.0;
+  }
+  m[k][k] = 0.0;
+  m[k][k + 1] = 1.0;
+  const double tiny = 1e-12 * amax;
+  bool ok = true;
+  for (int col = 0; col <= k && ok; ++col) {
+    int piv = col;
+    for (int r = col + 1; r <= k; ++r)
+      if (fabs(m[r][col]) > fabs(m[piv][col])) piv = r;
+    if (!(fabs(m[piv][col]) > tiny)) {
+      ok = false;
+      break;
+    }
+    if (piv != col)
+      for (int j = 0; j <= k + 1; ++j) {
+        const double t = m[col][j];
+        m[col][j] = m[piv][j];
+        m[piv][j] = t;
+      }
+    for (int r = col + 1; r <= k; ++r) {
+      const double fr = m[r][col] / m[col][col];
+      for (int j = col; j <= k + 1; ++j) m[r][j] -= fr * m[col][j];
+    }
+  }
+  for (int j = 0; j < S; ++j) c[j] = 0.0;
+  if (!ok) {
+    st[0] = 1;
+    c[s] = 1.0;
+    return;
+  }
+  double x[kMixMaxSlots + 1];
+  for (int r = k; r >= 0; --r) {
+    double t = 0.0;
+    for (int j = r + 1; j <= k; ++j) t += m[r][j] * x[j];
+    x[r] = (m[r][k + 1] - t) / m[r][r];
+  }
+  for (int q = 0; q < k; ++q) c[slot[q]] = x[q];
+}
+
+// rho_bar = sum_j c_j rho_j into rbar, R_bar = sum_j c_j R_j into res (slots in use,
+// oldest first)
+__global__ void __launch_bounds__(256) k_mix_combine(Geo g, int S, const int *__restrict__ st,
+                                                     const double *__restrict__ c,
+                                                     const double *__restrict__ hrho,
+                                                     const double *__restrict__ hres,
+                                                     double *__restrict__ rbar,
+                                                     double *__restrict__ res) {
+  const int k = st[0], s = st[1];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.Ng;
+       i += (long long)gridDim.x * blockDim.x) {
+    double a = 0.0, b = 0.0;
+    for (int q = 0; q < k; ++q) {
+      const int j = ((s - (k - 1) + q) % S + S) % S;
+      a += c[j] * hrho[(long long)j * g.Ng + i];
+      b += c[j] * hres[(long long)j * g.Ng + i];
+    }
+    rbar[i] = a;
+    res[i] = b;
+  }
+}
+
+// Kerker filter in the real Fourier basis: v <- q^2 / (q^2 + q0^2) v, q^2 = -(lx + ly
+// + lz), zero for the constant mode
+__global__ void __launch_bounds__(256) k_kerker_scale(Geo g, const double *__restrict__ lx,
+                                                      const double *__restrict__ ly,
+                                                      const double *__restrict__ lz, double q02,
+                                                      double *__restrict__ v) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < g.Ng;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int kx = (int)(e % g.N[0]);
+    const int ky = (int)((e / g.N[0]) % g.N[1]);
+    const int kz = (int)(e / ((long long)g.N[0] * g.N[1]));
+    const double q2 = -(lx[kx] + ly[ky] + lz[kz]);
+    v[e] = (kx == 0 && ky == 0 && kz == 0) ? 0.0 : q2 / (q2 + q02) * v[e];
+  }
+}
+
+// rho_in <- rho_bar + a K[R_bar], with partial sums of |rho_new - rho_in^(newest)|
+// (the input density of this step) per block in part[block]
+__global__ void __launch_bounds__(256) k_mix_update(Geo g, int S, const int *__restrict__ st,
+                                                    const double *__restrict__ hrho,
+                                                    const double *__restrict__ rbar,
+                                                    const double *__restrict__ kres, double a,
+                                                    double *__restrict__ rho_in,
+                                                    double *__restrict__ part) {
+  __shared__ double red[16];
+  const int s = st[1];
+  double d = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.Ng;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double v = rbar[i] + a * kres[i];
+    d += fabs(v - hrho[(long long)s * g.Ng + i]);
+    rho_in[i] = v;
+  }
+  const double t = block_sum(d, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// rho_alpha^in = rho_new(g(l)) + sum_j c_j delta_in^(j) + a sum_j c_j delta_R^(j)
+__global__ void __launch_bounds__(256) k_mix_update_frag(Geo g, int nfrag, int S,
+                                                         const int *__restrict__ st,
+                                                         const double *__restrict__ c,
+                                                         const double *__restrict__ hdin,
+                                                         const double *__restrict__ hdres,
+                                                         const double *__restrict__ rho_new,
+                                                         double a, double *__restrict__ rhof_in) {
+  const int k = st[0], s = st[1];
+  const long long total = (long long)nfrag * g.n;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    double di = 0.0, dr = 0.0;
+    for (int q = 0; q < k; ++q) {
+      const int j = ((s - (k - 1) + q) % S + S) % S;
+      di += c[j] * hdin[(long long)j * total + i];
+      dr += c[j] * hdres[(long long)j * total + i];
+    }
+    const int f = (int)(i / g.n), l = (int)(i % g.n);
+    rhof_in[i] = rho_new[global_of_local(g, f, l)] + (di + a * dr);
+  }
+}
+
+// scal[SC_RES_PAPER] = dV sum of the block partials / N_e
+__global__ void __launch_bounds__(256) k_mix_residual(Geo g, int nblk, double ne,
+                                                      const double *__restrict__ part,
+                                                      double *__restrict__ scal) {
+  __shared__ double red[16];
+  double t = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) t += part[b];
+  t = block_sum(t, red);
+  if (threadIdx.x == 0) scal[SC_RES_PAPER] = g.dv * t / ne;
+}
+
 inline int grid_for(long long n, int block) {
   long long b = (n + block - 1) / block;
   if (b > 8192) b = 8192;
@@ -484,6 +706,40 @@ void launch_fill_int(int *p, long long n, int v, hipStream_t s) {
 void launch_nan_check(const double *p, long long n, int *flags, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_nan_check, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, flags);
+}
+
+void launch_pulay_mix(const Geo &g, int nfrag, const MixState &m, const double *rho_out,
+                      const double *rhof_out, double *rho_in, double *rhof_in, double ne,
+                      double *const qf[3], double *const qi[3], double *const lam[3],
+                      double *wa, double *wb, double *scal, hipStream_t s) {
+  const int nblk = m.nblk;
+  const long long fn = (long long)nfrag * g.n;
+  hipLaunchKernelGGL(k_mix_record, dim3(nblk), dim3(256), 0, s, g, m.S, m.st, rho_in, rho_out,
+                     m.hrho, m.hres, m.part);
+  hipLaunchKernelGGL(k_mix_record_frag, dim3(grid_for(fn, 256)), dim3(256), 0, s, g, nfrag,
+                     m.S, m.st, rho_in, rho_out, rhof_in, rhof_out, m.hdin, m.hdres);
+  hipLaunchKernelGGL(k_mix_solve, dim3(1), dim3(64), 0, s, m.S, m.H, nblk, m.st, m.part, m.A,
+                     m.c);
+  hipLaunchKernelGGL(k_mix_combine, dim3(grid_for(g.Ng, 256)), dim3(256), 0, s, g, m.S, m.st,
+                     m.c, m.hrho, m.hres, m.rbar, m.kres);
+  if (m.q0 > 0.0) {
+    // K R_bar through the real Fourier basis of the Poisson solve
+    const long long Ng = g.Ng;
+    const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+    axis_transform(Ng, Nx, 1LL, m.kres, qf[0], wa, s);
+    axis_transform(Ng, Ny, (long long)Nx, wa, qf[1], wb, s);
+    axis_transform(Ng, Nz, (long long)Nx * Ny, wb, qf[2], wa, s);
+    hipLaunchKernelGGL(k_kerker_scale, dim3(grid_for(Ng, 256)), dim3(256), 0, s, g, lam[0],
+                       lam[1], lam[2], m.q0 * m.q0, wa);
+    axis_transform(Ng, Nz, (long long)Nx * Ny, wa, qi[2], wb, s);
+    axis_transform(Ng, Ny, (long long)Nx, wb, qi[1], wa, s);
+    axis_transform(Ng, Nx, 1LL, wa, qi[0], m.kres, s);
+  }
+  hipLaunchKernelGGL(k_mix_update, dim3(nblk), dim3(256), 0, s, g, m.S, m.st, m.hrho, m.rbar,
+                     m.kres, m.alpha, rho_in, m.part);
+  hipLaunchKernelGGL(k_mix_update_frag, dim3(grid_for(fn, 256)), dim3(256), 0, s, g, nfrag,
+                     m.S, m.st, m.c, m.hdin, m.hdres, rho_in, m.alpha, rhof_in);
+  hipLaunchKernelGGL(k_mix_residual, dim3(1), dim3(256), 0, s, g, nblk, ne, m.part, scal);
 }
 
 }  // namespace dcdft
