@@ -148,6 +148,72 @@ def crossover(args, prec) -> dict:
             "warmup": args.warmup, "data": "synthetic", "rows": rows}
 
 
+def converge(args) -> dict:
+    """Whole SCF runs to the paper's convergence measure (Sec. 3.3: dV sum |rho_k^in -
+    rho_(k-1)^in| / N_e) below args.converge, from the initial state, for the
+    workload and for the 64-atom cell (per-atom time, linearity), in mixed and FP64
+    precision, with Pulay-Kerker mixing and the density-template potential as
+    given.  Reports the first iteration that meets the tolerance, the time to it,
+    the time per iteration and per atom, and the spread of both residuals over the
+    last 50 of up to args.max_iter iterations."""
+    import torch
+    import workloads
+    from paper_2606_21125_amd import DCDFT, PREC_FP64, PREC_MIXED
+    from paper_2606_21125_amd.binding import DcdftError
+
+    rows = []
+    for role, k in (("workload", args.config), ("si64", 1)):
+        for prec in (PREC_MIXED, PREC_FP64):
+            cfg = workloads.config(k)
+            name = "mixed" if prec == PREC_MIXED else "fp64"
+            print(f"[bench] converge {cfg.name} {name}", file=sys.stderr, flush=True)
+            d = DCDFT.from_config(cfg, precision=prec)
+            if not args.no_autotune:
+                d.dcdft_autotune(args.tune_cache)
+            d.dcdft_set_mixer(args.mixer, args.mix_alpha, args.kerker_q0, args.mix_history)
+            if args.template_xi > 0.0:
+                d.dcdft_set_template(args.template_xi)
+            rp, ro, first, t_first, err = [], [], None, None, None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            try:
+                for it in range(args.max_iter):
+                    info = d.dcdft_scf_step()
+                    rp.append(info["residual_paper"])
+                    ro.append(info["residual_out_in"])
+                    if first is None and it > 0 and rp[-1] < args.converge:
+                        first = it + 1
+                        t_first = time.perf_counter() - t0
+            except DcdftError as e:
+                err = str(e).split(":")[0]
+            wall = time.perf_counter() - t0
+            d.close()
+            n = len(rp)
+            tail = slice(max(0, n - 50), n)
+            rows.append({"role": role, "workload": cfg.name, "atoms": cfg.system.n_atoms,
+                         "precision": name,
+                         "iterations_run": n, "error": err,
+                         "first_iteration_below_tol": first,
+                         "seconds_to_tol": None if t_first is None else round(t_first, 3),
+                         "ms_per_iteration": round(1000.0 * wall / max(1, n), 3),
+                         "us_per_atom_iteration": round(1e6 * wall / max(1, n)
+                                                        / cfg.system.n_atoms, 4),
+                         "residual_paper_last50": [min(rp[tail]), max(rp[tail])] if n else None,
+                         "residual_out_in_last50": [min(ro[tail]), max(ro[tail])] if n else None})
+            print(f"[bench] {json.dumps(rows[-1])}", file=sys.stderr, flush=True)
+    lin = {}
+    for name in ("mixed", "fp64"):
+        big = next(r for r in rows if r["precision"] == name and r["role"] == "workload")
+        small = next(r for r in rows if r["precision"] == name and r["role"] == "si64")
+        lin[name] = round(big["us_per_atom_iteration"] / small["us_per_atom_iteration"], 3)
+    return {"metric": "SCF iterations and time to the paper's density residual",
+            "tolerance": args.converge, "max_iter": args.max_iter,
+            "mixer": {"kind": args.mixer, "alpha": args.mix_alpha, "kerker_q0": args.kerker_q0,
+                      "history": args.mix_history}, "template_xi": args.template_xi,
+            "data": "synthetic", "rows": rows,
+            "per_atom_time_ratio_to_si64": lin}
+
+
 HLOC_KERNEL = {"plane": "k_hloc<{t}>", "halo_pd2": "k_hloc_halo<{t}, {nx}, 2, false>",
                "halo_pd3": "k_hloc_halo<{t}, {nx}, 3, false>",
                "halo_pd4": "k_hloc_halo<{t}, {nx}, 4, false>",
@@ -224,8 +290,29 @@ def main() -> int:
                     help="after the timed steps, build the DC-LCFO basis and global matrix "
                          "(eps_cut = mu + 0.1 eV, lambda_cut = 1e-7) and report its time")
     ap.add_argument("--template-xi", type=float, default=0.0,
-                    help="xi of the density-template potential V^alpha (0: off, the default)")
+                    help="xi of the density-template potential V^alpha (0: off, the default; "
+                         "--converge uses 1.0 unless given)")
+    ap.add_argument("--converge", type=float, default=0.0,
+                    help="instead of the benchmark line: run whole SCFs (the workload, default "
+                         "5, and the 64-atom cell) until the paper's residual is below this "
+                         "tolerance and print that table as one JSON line")
+    ap.add_argument("--max-iter", type=int, default=300)
+    ap.add_argument("--mixer", choices=("linear", "pulay"), default=None,
+                    help="density mixing (default: linear for the benchmark, pulay for "
+                         "--converge)")
+    ap.add_argument("--mix-alpha", type=float, default=0.3)
+    ap.add_argument("--kerker-q0", type=float, default=0.8)
+    ap.add_argument("--mix-history", type=int, default=8)
     args = ap.parse_args()
+    if args.converge > 0.0:
+        if args.mixer is None:
+            args.mixer = "pulay"
+        if "--template-xi" not in sys.argv:
+            args.template_xi = 1.0
+        if "--config" not in sys.argv:
+            args.config = 5
+    elif args.mixer is None:
+        args.mixer = "linear"
     if args.fixed_density:
         args.no_compare = True
         args.no_cpu_baseline = True
@@ -256,12 +343,17 @@ def main() -> int:
     if args.crossover:
         print(json.dumps(crossover(args, prec)), flush=True)
         return 0
+    if args.converge > 0.0:
+        print(json.dumps(converge(args)), flush=True)
+        return 0
     cfg = workload_config(args.config)
     print(f"[bench] setup {cfg.name}: {cfg.system.n_atoms} atoms, grid {cfg.n_grid}, "
           f"{cfg.n_fragments} fragments of {cfg.fragment_shape}", file=sys.stderr, flush=True)
     d = DCDFT.from_config(cfg, batched=args.batched, precision=prec)
     if args.template_xi > 0.0:
         d.dcdft_set_template(args.template_xi)
+    if args.mixer == "pulay":
+        d.dcdft_set_mixer("pulay", args.mix_alpha, args.kerker_q0, args.mix_history)
     if args.fixed_density:
         from workloads import superposed_density
         d.dcdft_set_density(superposed_density(cfg.system, cfg.n_grid))
@@ -412,7 +504,7 @@ def main() -> int:
                    "n_fragments": cfg.n_fragments, "batched": bool(args.batched),
                    "precision": args.precision,
                    "mode": "fixed-density" if args.fixed_density else "scf",
-                   "template_xi": args.template_xi},
+                   "template_xi": args.template_xi, "mixer": args.mixer},
         "roofline": roofline, "cpu_baseline": cpu, "comparisons": comparisons, **extra,
         **({"lcfo": lcfo} if lcfo else {}),
     }
