@@ -122,8 +122,9 @@ dcdft::OrbSet dcdft_ctx::orbset(int f0, int f1) const {
   o.M_tot = M_tot;
   o.m = d_m;
   o.moff = d_moff;
+  o.perm = d_perm;
   o.band_frag = d_band_frag;
-  o.h_moff = moff.data();
+  o.h_moff = pmoff.data();
   o.h_m = m.data();
   o.row_pad = 1;
   return o;
@@ -142,6 +143,7 @@ dcdft::KBTables dcdft_ctx::kb() const {
   k.KS = KS;
   k.reg_atom = d_reg_atom;
   k.reg_nt = d_reg_nt;
+  k.RX = RX;
   k.RY = RY;
   k.RZ = RZ;
   k.RP = RP;
@@ -205,12 +207,13 @@ void drain_timers(dcdft_ctx *c) {
 }
 
 double orbitals_in(const dcdft_ctx *c, int f0, int f1) {
-  return (double)(c->moff[f1] - c->moff[f0]);
+  return (double)(c->pmoff[f1] - c->pmoff[f0]);
 }
 
-double sum_m2(const dcdft_ctx *c, int f0, int f1) {
+// sum of m^2 over the fragments at launch positions [p0, p1)
+double sum_m2(const dcdft_ctx *c, int p0, int p1) {
   double s = 0.0;
-  for (int f = f0; f < f1; ++f) s += (double)c->m[f] * c->m[f];
+  for (int q = p0; q < p1; ++q) s += (double)c->m[c->perm[q]] * c->m[c->perm[q]];
   return s;
 }
 
@@ -238,6 +241,19 @@ double *gpart2_at(const dcdft_ctx *c, int f0) {
   return c->d_gpart2 + (long long)f0 * c->gram_chunks * c->m_pad * c->m_pad;
 }
 
+// fn(a, b, o) for every tile class meeting the launch positions [p0, p1): o is the
+// layout with the class's tile count, for the kernels compiled per tile count
+template <typename F>
+void by_class(const dcdft_ctx *c, int p0, int p1, F fn) {
+  for (const auto &k : c->classes) {
+    const int a = std::max(p0, k.p0), b = std::min(p1, k.p1);
+    if (a >= b) continue;
+    OrbSet o = c->orbset(a, b);
+    o.tiles = k.tiles;
+    fn(a, b, o);
+  }
+}
+
 template <typename T>
 void hloc(dcdft_ctx *c, int f0, int f1, const T *x, T *y, double *dot = nullptr) {
   const double n = c->geo.n, sz = sizeof(T);
@@ -245,20 +261,23 @@ void hloc(dcdft_ctx *c, int f0, int f1, const T *x, T *y, double *dot = nullptr)
           55.0 * n * orbitals_in(c, f0, f1));
   // dot partials at [kHlocZsMax x bands) from the group's first band
   launch_hloc<T>(c->geo, c->orbset(f0, f1), f0, f1, c->d_veff, veff_t<T>(c), x, y, xstream(c),
-                 dot, 0, c->d_hdot + (long long)kHlocZsMax * c->moff[f0]);
+                 dot, 0, c->d_hdot + (long long)kHlocZsMax * c->pmoff[f0]);
 }
 
 template <typename T>
 void kb_project(dcdft_ctx *c, int f0, int f1, const T *x) {
-  Timed t(c, DCDFT_KERNEL_KB, (double)sizeof(T) * c->geo.n * orbitals_in(c, f0, f1), 0.0);
-  launch_kb_project<T>(c->geo, c->orbset(f0, f1), c->kb(), f0, f1, x, c->d_C, c->d_cpart,
-                       xstream(c));
+  by_class(c, f0, f1, [&](int a, int b, const OrbSet &o) {
+    Timed t(c, DCDFT_KERNEL_KB, (double)sizeof(T) * c->geo.n * orbitals_in(c, a, b), 0.0);
+    launch_kb_project<T>(c->geo, o, c->kb(), a, b, x, c->d_C, c->d_cpart, xstream(c));
+  });
 }
 
 template <typename T>
 void kb_apply(dcdft_ctx *c, int f0, int f1, T *y) {
-  Timed t(c, DCDFT_KERNEL_KB, 2.0 * sizeof(T) * c->geo.n * orbitals_in(c, f0, f1), 0.0);
-  launch_kb_apply<T>(c->geo, c->orbset(f0, f1), c->kb(), f0, f1, c->d_C, y, xstream(c));
+  by_class(c, f0, f1, [&](int a, int b, const OrbSet &o) {
+    Timed t(c, DCDFT_KERNEL_KB, 2.0 * sizeof(T) * c->geo.n * orbitals_in(c, a, b), 0.0);
+    launch_kb_apply<T>(c->geo, o, c->kb(), a, b, c->d_C, y, xstream(c));
+  });
 }
 
 // H X for the orbitals of fragments [f0, f1) in the context layout.
@@ -273,12 +292,12 @@ template <typename T>
 void gram(dcdft_ctx *c, int f0, int f1, const T *x, const T *y, double *G, double *Gs,
           double *diag) {
   OrbSet o = c->orbset(f0, f1);
-  {
+  by_class(c, f0, f1, [&](int a, int b, const OrbSet &oc) {
     const double n = c->geo.n, sz = sizeof(T);
-    Timed t(c, DCDFT_KERNEL_GRAM, sz * n * orbitals_in(c, f0, f1) * (x == y ? 1.0 : 2.0),
-            2.0 * n * sum_m2(c, f0, f1));
-    launch_gram<T>(c->geo, o, f0, f1, c->gram_chunks, x, y, gpart_at(c, f0), xstream(c));
-  }
+    Timed t(c, DCDFT_KERNEL_GRAM, sz * n * orbitals_in(c, a, b) * (x == y ? 1.0 : 2.0),
+            2.0 * n * sum_m2(c, a, b));
+    launch_gram<T>(c->geo, oc, a, b, c->gram_chunks, x, y, gpart_at(c, a), xstream(c));
+  });
   launch_gram_reduce(c->geo, o, f0, f1, c->gram_chunks, x == y, gpart_at(c, f0),
                      G ? G : c->d_gtmp, Gs, diag, xstream(c));
 }
@@ -305,8 +324,6 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
   const T *psi0 = (const T *)c->d_psi;
   T *psi = (T *)c->d_psi_next, *w = (T *)c->d_w, *p = (T *)c->d_p, *q = (T *)c->d_q;
   const double n = g.n, sz = sizeof(T);
-  const double nb = orbitals_in(c, f0, f1);
-  const double m2 = sum_m2(c, f0, f1);
   const int ch = c->gram_chunks;
   // FP32 arrays: the re-orthonormalisation of one sweep also forms the next
   // sweep's Hs and residual (fused rotation, fewer passes).  FP64 arrays keep
@@ -321,31 +338,37 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
   } else {
     apply_h_range<T>(c, f0, f1, psi0, w);
   }
+  // kernels compiled per tile count run once per tile class, timed as one family
+  // launch each: bytes = bf * s n (orbitals of the class), flops = ff * n sum m^2
+  auto per_class = [&](int kind, double bf, double ff, auto fn) {
+    by_class(c, f0, f1, [&](int a, int b, const OrbSet &oc) {
+      Timed t(c, kind, bf * sz * n * orbitals_in(c, a, b), ff * n * sum_m2(c, a, b));
+      fn(a, b, oc);
+    });
+  };
   for (int sw = 0; sw < c->sweeps; ++sw) {
     const bool last = sw + 1 == c->sweeps;
     const T *pin = sw == 0 ? psi0 : psi;   // orbitals entering this sweep
     if (sw == 0 || !fuse) {
       // (a) Hs = sym(<Psi, W>), a_i = <psi_i, w_i>; (b) G = W - Hs Psi (in q),
-      // gamma_i = <g_i, g_i>
+      // gamma_i = <g_i, g_i>, (c) with the Fletcher-Reeves beta
       gram<T>(c, f0, f1, pin, w, c->d_hs_full, c->d_hs, c->d_a);
-      Timed t(c, DCDFT_KERNEL_ROTATE, 3.0 * sz * n * nb, 2.0 * n * m2);
-      // (c) with the Fletcher-Reeves beta
-      launch_rot_residual<T>(g, o, f0, f1, c->d_hs, pin, w, q, c->d_dpart, c->d_gamma, s, sw == 0,
-                             c->d_gamma_prev, c->d_beta);
+      per_class(DCDFT_KERNEL_ROTATE, 3.0, 2.0, [&](int a, int b, const OrbSet &oc) {
+        launch_rot_residual<T>(g, oc, a, b, c->d_hs, pin, w, q, c->d_dpart, c->d_gamma, s,
+                               sw == 0, c->d_gamma_prev, c->d_beta);
+      });
     }
     // (d)-(e) P = -G + beta P_prev, X = <Psi, P>
-    {
-      Timed t(c, DCDFT_KERNEL_GRAM_FUSED, 4.0 * sz * n * nb, 2.0 * n * m2);
-      launch_gram_direction<T>(g, o, f0, f1, ch, pin, q, p, c->d_beta, gpart_at(c, f0), s,
+    per_class(DCDFT_KERNEL_GRAM_FUSED, 4.0, 2.0, [&](int a, int b, const OrbSet &oc) {
+      launch_gram_direction<T>(g, oc, a, b, ch, pin, q, p, c->d_beta, gpart_at(c, a), s,
                                sw == 0);
-    }
+    });
     launch_gram_reduce(g, o, f0, f1, ch, 0, gpart_at(c, f0), c->d_x, nullptr, nullptr, s);
     // (e)-(f) P <- P - X^T Psi, nu_i = <p_i, p_i> (and 1/sqrt(nu_i)), <p_i, w_i>
-    {
-      Timed t(c, DCDFT_KERNEL_ROTATE, 4.0 * sz * n * nb, 2.0 * n * m2);
-      launch_rot_project_out<T>(g, o, f0, f1, c->d_x, pin, p, w, c->d_dpart, c->d_nu, c->d_bb,
+    per_class(DCDFT_KERNEL_ROTATE, 4.0, 2.0, [&](int a, int b, const OrbSet &oc) {
+      launch_rot_project_out<T>(g, oc, a, b, c->d_x, pin, p, w, c->d_dpart, c->d_nu, c->d_bb,
                                 s, c->d_inv);
-    }
+    });
     // (g) Q = H P and <p_i, q_i>
     hloc<T>(c, f0, f1, p, q, c->d_cc);
     kb_project<T>(c, f0, f1, p);
@@ -355,35 +378,41 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
     launch_kb_quad_theta(o, f0, f1, kb, c->d_C, c->d_cc, c->d_a, c->d_bb, c->d_inv, c->d_cos,
                          c->d_sin, s);
     // (j) band rotations and (l) S = sym(<Psi, Psi>); with_m: also M = <Psi', W'>
-    // of the rotated (not yet re-orthonormalised) arrays
+    // of the rotated (not yet re-orthonormalised) arrays; after the last sweep W is
+    // not used (the next step rebuilds it)
     const bool with_m = fuse || last;
-    {
-      Timed t(c, DCDFT_KERNEL_GRAM_FUSED, (last ? 5.0 : 6.0) * sz * n * nb,
-              (with_m ? 3.0 : 1.0) * n * m2);
-      // after the last sweep W is not used (the next step rebuilds it)
-      launch_gram_update<T>(g, o, f0, f1, ch, pin, psi, p, w, q, c->d_cos, c->d_sin,
-                            gpart_at(c, f0), s, with_m ? gpart2_at(c, f0) : nullptr, !last);
-    }
+    per_class(DCDFT_KERNEL_GRAM_FUSED, last ? 5.0 : 6.0, with_m ? 3.0 : 1.0,
+              [&](int a, int b, const OrbSet &oc) {
+                launch_gram_update<T>(g, oc, a, b, ch, pin, psi, p, w, q, c->d_cos, c->d_sin,
+                                      gpart_at(c, a), s, with_m ? gpart2_at(c, a) : nullptr,
+                                      !last);
+              });
     if (!with_m) {
       launch_gram_reduce(g, o, f0, f1, ch, 1, gpart_at(c, f0), c->d_s, nullptr, nullptr, s);
       // (l) S = L L^T, Psi <- L^-1 Psi, W <- L^-1 W
-      launch_cholinv(o, f0, f1, c->d_s, c->d_lin, c->d_flags, s);
-      Timed t(c, DCDFT_KERNEL_ROTATE, 4.0 * sz * n * nb, 2.0 * n * m2);
-      launch_rot_cholesky<T>(g, o, f0, f1, c->d_lin, psi, w, s);
+      by_class(c, f0, f1, [&](int a, int b, const OrbSet &oc) {
+        launch_cholinv(oc, a, b, c->d_s, c->d_lin, c->d_flags, s);
+      });
+      per_class(DCDFT_KERNEL_ROTATE, 4.0, 2.0, [&](int a, int b, const OrbSet &oc) {
+        launch_rot_cholesky<T>(g, oc, a, b, c->d_lin, psi, w, s);
+      });
       continue;
     }
     launch_gram_reduce_pair(g, o, f0, f1, ch, gpart_at(c, f0), c->d_s, gpart2_at(c, f0),
                             c->d_hs_full, s);
     // (l) S = L L^T; with Psi = L^-1 Psi', W = L^-1 W' the next sweep's
     // Hs = sym(<Psi, W>) = sym(L^-1 M L^-T) and a_i = Hs_ii, B = Hs L^-1
-    launch_cholinv(o, f0, f1, c->d_s, c->d_lin, c->d_flags, s, c->d_hs_full, c->d_hs, c->d_a,
-                   c->d_bmat);
+    by_class(c, f0, f1, [&](int a, int b, const OrbSet &oc) {
+      launch_cholinv(oc, a, b, c->d_s, c->d_lin, c->d_flags, s, c->d_hs_full, c->d_hs, c->d_a,
+                     c->d_bmat);
+    });
     if (!last) {
       // Psi <- L^-1 Psi', W <- L^-1 W' and the next sweep's (b) and (c):
       // G = W - B Psi', gamma and the Fletcher-Reeves beta
-      Timed t(c, DCDFT_KERNEL_ROTATE, 5.0 * sz * n * nb, 6.0 * n * m2);
-      launch_rot_cholres<T>(g, o, f0, f1, c->d_lin, c->d_bmat, psi, w, q, c->d_dpart,
-                            c->d_gamma, s, c->d_gamma_prev, c->d_beta);
+      per_class(DCDFT_KERNEL_ROTATE, 5.0, 6.0, [&](int a, int b, const OrbSet &oc) {
+        launch_rot_cholres<T>(g, oc, a, b, c->d_lin, c->d_bmat, psi, w, q, c->d_dpart,
+                              c->d_gamma, s, c->d_gamma_prev, c->d_beta);
+      });
     }
     // after the last sweep only Psi is used (W is rebuilt by the next step), and
     // its re-orthonormalisation L^-1 is folded into the Ritz rotation below
@@ -393,10 +422,9 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
   // then core weights w_i = dV sum_core psi_i^2
   launch_syev(o, f0, f1, c->d_hs, c->d_u, c->d_eps, c->d_flags, s);
   launch_ritz_combine(o, f0, f1, c->d_lin, c->d_u, c->d_bmat, s);
-  {
-    Timed t(c, DCDFT_KERNEL_ROTATE, 2.0 * sz * n * nb, 2.0 * n * m2);
-    launch_rot_ritz<T>(g, o, f0, f1, c->d_bmat, psi, c->d_dpart, c->d_wcore, s);
-  }
+  per_class(DCDFT_KERNEL_ROTATE, 2.0, 2.0, [&](int a, int b, const OrbSet &oc) {
+    launch_rot_ritz<T>(g, oc, a, b, c->d_bmat, psi, c->d_dpart, c->d_wcore, s);
+  });
 }
 
 template <typename T>
@@ -618,29 +646,48 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
   c->A = Acount;
   c->A_max = 1;
   for (int f = 0; f < nF; ++f) c->A_max = std::max(c->A_max, Acount[f]);
-  // regions: blocks of whole x rows (RY rows by RZ planes, RP = nx RY RZ points,
-  // a multiple of 64 and at most kRegion) where the box allows, else kRegion
-  // consecutive local points; each lists the fragment atoms whose support meets
-  // it (sorted, padded to KS slots)
+  // regions: blocks of RX x-points by RY rows by RZ planes (RP = RX RY RZ points,
+  // a multiple of 64 and at most kBlockRegionMax) where the box allows, else
+  // kRegion consecutive local points; each lists the fragment atoms whose support
+  // meets it (sorted, padded to KS slots).  Blocks are whole x rows (RX = nx: the
+  // orbital loads stay in runs of whole rows; 8-point runs, which meet 35% fewer
+  // atoms on the water boxes, were measured slower), and among the shapes with
+  // the most points the one whose reach (the block grown by the largest support
+  // radius on every side) has the smallest volume, so it meets the fewest atoms.
+  c->RX = 0;
   c->RY = 0;
   c->RZ = 0;
   c->RP = kRegion;
-  for (int ry : {4, 2, 1})
-    for (int rz : {2, 1}) {
-      const int rp = g.nl[0] * ry * rz;
-      if (rp <= kRegion && rp % 64 == 0 && g.nl[1] % ry == 0 && g.nl[2] % rz == 0 &&
-          (c->RY == 0 || rp > c->RP)) {
-        c->RY = ry;
-        c->RZ = rz;
-        c->RP = rp;
-      }
-    }
+  {
+    double rmax = 0.0;
+    for (int sp = 0; sp < p->n_species; ++sp) rmax = std::max(rmax, p->species[sp].kb_rcut);
+    double best = 0.0;
+    for (int rx = g.nl[0]; rx <= g.nl[0]; rx += 4)
+      for (int ry = 1; ry <= g.nl[1]; ++ry)
+        for (int rz = 1; rz <= g.nl[2]; ++rz) {
+          const int rp = rx * ry * rz;
+          if (g.nl[0] % rx || g.nl[1] % ry || g.nl[2] % rz || rp % 64 || rp > kBlockRegionMax ||
+              rx % 4)
+            continue;
+          const double reach = (rx * g.h[0] + 2 * rmax) * (ry * g.h[1] + 2 * rmax) *
+                               (rz * g.h[2] + 2 * rmax);
+          if (c->RY == 0 || rp > c->RP || (rp == c->RP && reach < best)) {
+            c->RX = rx;
+            c->RY = ry;
+            c->RZ = rz;
+            c->RP = rp;
+            best = reach;
+          }
+        }
+  }
   auto region_of = [&](int l) {
     if (c->RY == 0) return l / kRegion;
-    const int ly = (l / g.nl[0]) % g.nl[1], lz = l / (g.nl[0] * g.nl[1]);
-    return ly / c->RY + (g.nl[1] / c->RY) * (lz / c->RZ);
+    const int lx = l % g.nl[0], ly = (l / g.nl[0]) % g.nl[1], lz = l / (g.nl[0] * g.nl[1]);
+    return lx / c->RX +
+           (g.nl[0] / c->RX) * (ly / c->RY + (g.nl[1] / c->RY) * (lz / c->RZ));
   };
-  c->NR = c->RY ? (g.nl[1] / c->RY) * (g.nl[2] / c->RZ) : (g.n + kRegion - 1) / kRegion;
+  c->NR = c->RY ? (g.nl[0] / c->RX) * (g.nl[1] / c->RY) * (g.nl[2] / c->RZ)
+                : (g.n + kRegion - 1) / kRegion;
   {
     std::vector<std::vector<int>> reg_atoms((size_t)nF * c->NR);
     for (int P = 0; P < c->n_pairs; ++P) {
@@ -664,8 +711,9 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
     c->KS = ks;
     {
       const size_t elem = c->precision == DCDFT_PREC_MIXED ? sizeof(float) : sizeof(double);
-      const size_t need = std::max(kb_lds_bytes(g, ks, c->tiles, elem, true),
-                                   kb_lds_bytes(g, ks, c->tiles, elem, false));
+      const int rr = c->RY ? c->RY * c->RZ : region_rows(g.nl[0]);
+      const size_t need = std::max(kb_lds_bytes(g, ks, rr, c->tiles, elem, true),
+                                   kb_lds_bytes(g, ks, rr, c->tiles, elem, false));
       if (need > 65536)
         return set_err(c, DCDFT_ERR_ARG,
                        fmt("%d projectors meet one %d-point region: the projector kernels would "
@@ -762,7 +810,7 @@ int step_groups(const dcdft_ctx *c, int *bound) {
   bound[0] = 0;
   for (int q = 1; q < G; ++q) {
     int h = bound[q - 1] + 1;
-    while (h < c->nF - (G - q) && (long long)G * c->moff[h] < (long long)q * c->M_tot) ++h;
+    while (h < c->nF - (G - q) && (long long)G * c->pmoff[h] < (long long)q * c->M_tot) ++h;
     bound[q] = h;
   }
   bound[G] = c->nF;
@@ -1005,14 +1053,35 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   }
   c->nF = g.F[0] * g.F[1] * g.F[2];
   c->m.resize(c->nF);
-  c->moff.assign(c->nF + 1, 0);
   int mmax = 1;
   for (int f = 0; f < c->nF; ++f) {
     c->m[f] = p->nstate_frag ? p->nstate_frag[f] : p->nstate_frag_uniform;
-    c->moff[f + 1] = c->moff[f] + c->m[f];
     mmax = std::max(mmax, c->m[f]);
   }
-  c->M_tot = c->moff[c->nF];
+  // launch order: fragments sorted by their count of 16-orbital tiles (stable, so
+  // the identity when all counts agree); bands laid out in that order; runs of
+  // equal counts are the tile classes, launched with kernels compiled for them
+  c->perm.resize(c->nF);
+  for (int f = 0; f < c->nF; ++f) c->perm[f] = f;
+  std::stable_sort(c->perm.begin(), c->perm.end(), [&](int a, int b) {
+    return (c->m[a] + 15) / 16 < (c->m[b] + 15) / 16;
+  });
+  c->inv_perm.assign(c->nF, 0);
+  c->moff.assign(c->nF + 1, 0);
+  c->pmoff.assign(c->nF + 1, 0);
+  for (int q = 0; q < c->nF; ++q) {
+    const int f = c->perm[q];
+    c->inv_perm[f] = q;
+    c->moff[f] = c->pmoff[q];
+    c->pmoff[q + 1] = c->pmoff[q] + c->m[f];
+  }
+  c->moff[c->nF] = c->pmoff[c->nF];
+  for (int q = 0; q < c->nF; ++q) {
+    const int t = (c->m[c->perm[q]] + 15) / 16;
+    if (c->classes.empty() || c->classes.back().tiles != t) c->classes.push_back({q, q + 1, t});
+    else c->classes.back().p1 = q + 1;
+  }
+  c->M_tot = c->pmoff[c->nF];
   c->tiles = (mmax + 15) / 16;
   c->m_pad = 16 * c->tiles;
   c->ne = p->n_electrons;
@@ -1052,7 +1121,7 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   const long long mp2 = (long long)c->m_pad * c->m_pad;
   std::vector<int> band_frag(c->M_tot);
   for (int f = 0; f < c->nF; ++f)
-    for (long long B = c->moff[f]; B < c->moff[f + 1]; ++B) band_frag[B] = f;
+    for (long long B = c->moff[f]; B < c->moff[f] + c->m[f]; ++B) band_frag[B] = f;
   c->n_part = 1024;
 #define ALLOC(ptr, n)                                                     \
   do {                                                                    \
@@ -1065,6 +1134,7 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   {
     hipError_t e = upload(c, &c->d_m, c->m);
     if (e == hipSuccess) e = upload(c, &c->d_moff, c->moff);
+    if (e == hipSuccess) e = upload(c, &c->d_perm, c->perm);
     if (e == hipSuccess) e = upload(c, &c->d_band_frag, band_frag);
     if (e != hipSuccess) {
       c->last_error = "table upload failed";
@@ -1594,8 +1664,9 @@ dcdft_status dcdft_lcfo_build(dcdft_ctx *c, double eps_cut, double lambda_cut,
   {
     // the basis is FP64 whatever the step's precision: the FP64 projector kernels
     // must fit their LDS (setup checked the step's own precision only)
-    const size_t need = std::max(kb_lds_bytes(g, c->KS, c->tiles, sizeof(double), true),
-                                 kb_lds_bytes(g, c->KS, c->tiles, sizeof(double), false));
+    const int rr = c->RY ? c->RY * c->RZ : region_rows(g.nl[0]);
+    const size_t need = std::max(kb_lds_bytes(g, c->KS, rr, c->tiles, sizeof(double), true),
+                                 kb_lds_bytes(g, c->KS, rr, c->tiles, sizeof(double), false));
     if (need > 65536)
       return set_err(c, DCDFT_ERR_ARG,
                      fmt("%d projectors meet one projector region: the FP64 projector kernels "
@@ -1799,12 +1870,13 @@ void apply_h_ext(dcdft_ctx *c, const dcdft_ctx::ExtScratch &X, int frag, const T
                  int m, const double *veff_ext = nullptr) {
   const Geo &g = c->geo;
   KBTables kb = c->kb();
+  const int q = c->inv_perm[frag];   // launch position of the fragment
   for (int i0 = 0; i0 < m; i0 += X.chunk) {
     const int mm = std::min(X.chunk, m - i0);
     launch_single_layout(c->nF, frag, mm, X.m, X.moff, X.band, c->stream);
     c->ext_h_m[frag] = mm;
-    for (int f = frag + 1; f <= c->nF; ++f) c->ext_h_moff[f] = mm;
-    OrbSet o = c->orbset(frag, frag + 1);
+    for (int p = q + 1; p <= c->nF; ++p) c->ext_h_moff[p] = mm;
+    OrbSet o = c->orbset(q, q + 1);
     o.m = X.m;
     o.moff = X.moff;
     o.band_frag = X.band;
@@ -1816,15 +1888,15 @@ void apply_h_ext(dcdft_ctx *c, const dcdft_ctx::ExtScratch &X, int frag, const T
     T *y = hpsi + (long long)i0 * g.n;
     if (veff_ext) {
       const T *vt = sizeof(T) == sizeof(double) ? reinterpret_cast<const T *>(veff_ext) : nullptr;
-      launch_hloc<T>(g, o, frag, frag + 1, veff_ext, vt, x, y, c->stream, nullptr, frag);
+      launch_hloc<T>(g, o, q, q + 1, veff_ext, vt, x, y, c->stream, nullptr, frag);
     } else {
-      launch_hloc<T>(g, o, frag, frag + 1, c->d_veff, veff_t<T>(c), x, y, c->stream);
+      launch_hloc<T>(g, o, q, q + 1, c->d_veff, veff_t<T>(c), x, y, c->stream);
     }
-    launch_kb_project<T>(g, o, kb, frag, frag + 1, x, c->d_C, c->d_cpart, c->stream);
-    launch_kb_apply<T>(g, o, kb, frag, frag + 1, c->d_C, y, c->stream);
+    launch_kb_project<T>(g, o, kb, q, q + 1, x, c->d_C, c->d_cpart, c->stream);
+    launch_kb_apply<T>(g, o, kb, q, q + 1, c->d_C, y, c->stream);
   }
   c->ext_h_m[frag] = 0;
-  for (int f = frag + 1; f <= c->nF; ++f) c->ext_h_moff[f] = 0;
+  for (int p = q + 1; p <= c->nF; ++p) c->ext_h_moff[p] = 0;
 }
 
 // Band energy and gradients of m vectors of fragment frag: H psi chunk by chunk

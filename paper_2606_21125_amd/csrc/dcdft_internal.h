@@ -62,36 +62,44 @@ enum {
 };
 bool hloc_halo_ok(const Geo &g);
 // LDS bytes a projector kernel needs (slot tables plus the (E C)^T block of apply
-// or the partial sums of project) for KS slots and tiles 16-orbital tiles
-size_t kb_lds_bytes(const Geo &g, int KS, int tiles, size_t elem, bool apply);
+// or the partial sums of project) for KS slots, rr region rows and tiles 16-orbital
+// tiles
+size_t kb_lds_bytes(const Geo &g, int KS, int rr, int tiles, size_t elem, bool apply);
 
+// Fragments are launched in an order sorted by their count of 16-orbital tiles
+// (launch order; the identity when every fragment has the same count): kernels
+// tiled by fragment take a range [f0, f1) of launch positions and the fragment at
+// position p is perm[p].  Bands are laid out in launch order, so a launch range
+// covers a contiguous range of bands.
 struct OrbSet {           // flattened orbital layout [M_tot][n]
   int nfrag;
-  int m_pad;              // multiple of 16, >= max m
-  int tiles;              // m_pad / 16
+  int m_pad;              // multiple of 16, >= max m (stride of the small matrices)
+  int tiles;              // 16-orbital tiles the launched kernels are compiled for
   long long M_tot;
-  const int *m;           // [F]
-  const long long *moff;  // [F + 1] band offset of each fragment
+  const int *m;           // [F] orbitals of each fragment
+  const long long *moff;  // [F] first band of each fragment
   const int *band_frag;   // [M_tot]
-  const long long *h_moff;  // host copy of moff (launch ranges)
+  const int *perm;        // [F] fragment at each launch position
+  const long long *h_moff;  // host [F + 1]: first band of each launch position (ranges)
   const int *h_m;           // host copy of m
   // 1: the arrays hold m_pad spare rows after the last band, so a kernel may
   // read any padded row of a fragment (context arrays); 0: rows past a
   // fragment's m must not be read (caller-provided arrays)
   int row_pad;
-  long long b0(int f) const { return h_moff[f]; }
-  long long nb(int f0, int f1) const { return h_moff[f1] - h_moff[f0]; }
+  long long b0(int p) const { return h_moff[p]; }
+  long long nb(int p0, int p1) const { return h_moff[p1] - h_moff[p0]; }
 };
 
 // Projector regions: each fragment's points are cut into regions of at most
 // kRegion points, each listing the KS (padded) fragment atoms whose support
-// meets it.  Block regions (RY > 0) are whole x rows times RY rows times RZ
-// planes (RP = nx RY RZ points, a multiple of 64), compact enough that a
-// region rarely meets more than 16 atoms; otherwise (RY = 0) a region is
+// meets it.  Block regions (RY > 0) are RX x-points (a multiple of 4 dividing
+// nx) times RY rows times RZ planes (RP = RX RY RZ points, a multiple of 64),
+// shaped to meet as few atoms as possible; otherwise (RY = 0) a region is
 // kRegion consecutive points.  The beta values are not stored: the kernels
 // evaluate beta_a(l) = sc_a exp(-r2 / (2 sigma_a^2)) on r2 <= rcut_a^2, with
 // r2 = (dz^2 + dy^2) + dx^2 taken from per-pair tables of squared offsets.
 constexpr int kRegion = 256;
+constexpr int kBlockRegionMax = 512;   // points of a block region, at most
 constexpr int kMaxSlotTiles = 6;    // KS_max <= 96 slots per region
 // local rows (runs of nl[0] points) a region can touch
 __host__ __device__ constexpr int region_rows(int nx) { return (kRegion - 1) / nx + 2; }
@@ -100,7 +108,7 @@ struct KBTables {
   int A_max;
   int NR;                            // regions per fragment
   int KS;                            // slots per region (multiple of 16)
-  int RY, RZ;                        // block regions: rows and planes (RY = 0: linear)
+  int RX, RY, RZ;                    // block regions: x points, rows, planes (RY = 0: linear)
   int RP;                            // points per region
   const int *reg_atom;               // [F][NR][KS] local atom index or -1
   const int *reg_nt;                 // [F][NR] slot tiles in use (16 slots each)
@@ -138,7 +146,14 @@ struct dcdft_ctx {
   dcdft::Geo geo;
   int nF = 0;
   std::vector<int> m;
-  std::vector<long long> moff;
+  std::vector<long long> moff;       // [F + 1] first band of each fragment (moff[F] = M_tot)
+  std::vector<int> perm, inv_perm;   // launch order: fragment at each position, and back
+  std::vector<long long> pmoff;      // [F + 1] first band of each launch position
+  // runs of launch positions whose fragments use the same number of 16-orbital tiles
+  struct TileClass {
+    int p0, p1, tiles;
+  };
+  std::vector<TileClass> classes;
   int m_pad = 0, tiles = 0;
   long long M_tot = 0;
   double ne = 0, smearing = 0, mixing = 0;
@@ -171,7 +186,7 @@ struct dcdft_ctx {
   std::vector<void *> allocs;
 
   // tables
-  int *d_m = nullptr;
+  int *d_m = nullptr, *d_perm = nullptr;
   long long *d_moff = nullptr;
   int *d_band_frag = nullptr;
   // KB
@@ -179,7 +194,7 @@ struct dcdft_ctx {
   int *d_A = nullptr, *d_pair_first = nullptr;
   double *d_pr_sq = nullptr, *d_pr_par = nullptr, *d_E = nullptr;
   double *d_C = nullptr;             // [F][A_max][m_pad] projections
-  int NR = 0, KS = 0, RY = 0, RZ = 0, RP = 256;
+  int NR = 0, KS = 0, RX = 0, RY = 0, RZ = 0, RP = 256;
   int *d_reg_atom = nullptr, *d_reg_nt = nullptr, *d_ar_reg = nullptr, *d_ar_slot = nullptr;
   long long *d_ar_ptr = nullptr;
   double *d_cpart = nullptr;         // region projection partials [F][NR][KS][m_pad]
@@ -262,7 +277,7 @@ struct dcdft_ctx {
   };
   ExtScratch ext;
   std::vector<int> ext_h_m;           // host copies of the layout tables (launch ranges)
-  std::vector<long long> ext_h_moff;
+  std::vector<long long> ext_h_moff;  // [F + 1] in launch order
   // phase boundaries of a step: start, V_eff formed, fragment eigensolvers
   // joined, end (recorded between the phases' graph launches)
   hipEvent_t ev_ph[4] = {nullptr, nullptr, nullptr, nullptr};

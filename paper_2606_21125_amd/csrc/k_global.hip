@@ -166,6 +166,7 @@ __global__ void __launch_bounds__(1024) k_fermi(long long nb, const double *__re
 // rho_alpha^out(l) = sum_i 2 f_i psi_i(l)^2; core points also written to rho_tot^out.
 template <typename T>
 __global__ void __launch_bounds__(256) k_density(Geo g, const long long *__restrict__ moff,
+                                                 const int *__restrict__ mcount,
                                                  int f0, int f1, const T *__restrict__ psi,
                                                  const double *__restrict__ occ,
                                                  double *__restrict__ rhof_out,
@@ -174,7 +175,7 @@ __global__ void __launch_bounds__(256) k_density(Geo g, const long long *__restr
   if (idx >= (long long)(f1 - f0) * g.n) return;
   const int f = f0 + (int)(idx / g.n);
   const int l = (int)(idx % g.n);
-  const long long b1 = moff[f + 1];
+  const long long b1 = moff[f] + mcount[f];
   const T *p = psi + l;
   double acc = 0.0;
   long long B = moff[f];
@@ -609,7 +610,7 @@ void launch_density(const Geo &g, const OrbSet &o, int f0, int f1, const T *psi,
   const long long total = (long long)(f1 - f0) * g.n;
   if (total <= 0) return;
   hipLaunchKernelGGL(k_density<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g,
-                     o.moff, f0, f1, psi, occ, rhof_out, rho_out);
+                     o.moff, o.m, f0, f1, psi, occ, rhof_out, rho_out);
 }
 template void launch_density<double>(const Geo &, const OrbSet &, int, int, const double *,
                                      const double *, double *, double *, hipStream_t);

@@ -410,9 +410,10 @@ __device__ inline void region_row(const Geo &g, const KBTables &kb, int reg, int
                                   int &lz) {
   const int ny = g.nl[1];
   if (kb.RY) {
+    const int b = reg / (g.nl[0] / kb.RX);   // (row block, plane block) of the region
     const int nyr = ny / kb.RY;
-    ly = (reg % nyr) * kb.RY + rr % kb.RY;
-    lz = (reg / nyr) * kb.RZ + rr / kb.RY;
+    ly = (b % nyr) * kb.RY + rr % kb.RY;
+    lz = (b / nyr) * kb.RZ + rr / kb.RY;
   } else {
     const int row = reg * kRegion / g.nl[0] + rr;
     ly = row % ny;
@@ -425,8 +426,8 @@ __device__ inline int region_point(const Geo &g, const KBTables &kb, int reg, in
                                    int &rr) {
   const int nx = g.nl[0];
   if (kb.RY) {
-    lx = q % nx;
-    rr = q / nx;
+    lx = (reg % (nx / kb.RX)) * kb.RX + q % kb.RX;
+    rr = q / kb.RX;
     int ly, lz;
     region_row(g, kb, reg, rr, ly, lz);
     return lx + nx * (ly + g.nl[1] * lz);
@@ -531,7 +532,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && KT == 3 ? 3 : 1, 8))) k_kb_
   const int NCH = kb.RP / CH;
   double *sx = kb_lds, *syz = sx + kb.KS * nx, *par = syz + kb.KS * RR;
   T *bl = reinterpret_cast<T *>(par + 3 * kb.KS);   // [2][KSM][BS]
-  const int f = f0 + blockIdx.x / kb.NR;
+  const int f = o.perm[f0 + blockIdx.x / kb.NR];
   const int reg = blockIdx.x % kb.NR;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, kk = lane >> 4;
@@ -679,8 +680,9 @@ __global__ void __launch_bounds__(256) k_kb_reduce(Geo g, OrbSet o, KBTables kb,
   const long long total = (long long)nf * kb.A_max * o.m_pad;
   if (idx >= total) return;
   const int i = (int)(idx % o.m_pad);
-  const long long fa = (long long)f0 * kb.A_max + idx / o.m_pad;
-  const int f = (int)(fa / kb.A_max);
+  const long long la = idx / o.m_pad;   // (launch-local fragment, atom)
+  const int f = o.perm[f0 + (int)(la / kb.A_max)];
+  const long long fa = (long long)f * kb.A_max + la % kb.A_max;
   double s = 0.0;
   // four entries in flight at a time, added in entry order
   long long e = kb.ar_ptr[fa];
@@ -723,7 +725,7 @@ k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
   const int NU = kb.RP / 16 / 4;  // tiles per wave
   double *sx = kb_lds, *syz = sx + kb.KS * nx, *par = syz + kb.KS * RR;
   T *ec = reinterpret_cast<T *>(par + 3 * kb.KS);   // [KSM][LD]
-  const int f = f0 + blockIdx.x / kb.NR;
+  const int f = o.perm[f0 + blockIdx.x / kb.NR];
   const int reg = blockIdx.x % kb.NR;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mf = o.m[f];
@@ -910,7 +912,8 @@ void kb_t(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1, con
           double *C, double *part, T *y, hipStream_t s) {
   const dim3 grid((f1 - f0) * kb.NR), block(256);
   if (x) {
-    const size_t lds = kb_lds_bytes(g, kb.KS, TM, sizeof(T), false);
+    const size_t lds = kb_lds_bytes(g, kb.KS, kb.RY ? kb.RY * kb.RZ : region_rows(g.nl[0]), TM,
+                                    sizeof(T), false);
     // 16-byte runs need n % 4 == 0 and an aligned array
     if (g.n % 4 == 0 && (uintptr_t)x % 16 == 0)
       hipLaunchKernelGGL((k_kb_project<T, TM, KT, true>), grid, block, lds, s, g, o, kb, f0, x,
@@ -922,7 +925,8 @@ void kb_t(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1, con
     hipLaunchKernelGGL(k_kb_reduce<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g,
                        o, kb, f0, f1 - f0, reinterpret_cast<const T *>(part), C);
   } else {
-    const size_t lds = kb_lds_bytes(g, kb.KS, TM, sizeof(T), true);
+    const size_t lds = kb_lds_bytes(g, kb.KS, kb.RY ? kb.RY * kb.RZ : region_rows(g.nl[0]), TM,
+                                    sizeof(T), true);
     if (o.row_pad)
       hipLaunchKernelGGL((k_kb_apply<T, TM, KT, true>), grid, block, lds, s, g, o, kb, f0, C, y);
     else
@@ -1013,8 +1017,8 @@ void launch_vec(const Geo &g, long long nb, int opw, int zs, const OrbSet &o, in
 
 // LDS bytes of the projector kernels: the slot tables, and the (E C)^T block
 // (apply) or the partial sums (project) of the widest orbital count
-size_t kb_lds_bytes(const Geo &g, int KS, int tiles, size_t elem, bool apply) {
-  const size_t tab = (size_t)KS * (g.nl[0] + region_rows(g.nl[0]) + 3) * sizeof(double);
+size_t kb_lds_bytes(const Geo &g, int KS, int rr, int tiles, size_t elem, bool apply) {
+  const size_t tab = (size_t)KS * (g.nl[0] + rr + 3) * sizeof(double);
   const int MP = 16 * tiles;
   if (apply) return tab + (size_t)KS * lds_stride(MP) * elem;
   const int ch = elem == 4 ? 64 : 32;   // project: two beta chunks

@@ -87,7 +87,7 @@ k_rot_fused(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ M, int 
                 "the second array is rotated without z or reductions");
   __shared__ __attribute__((aligned(16))) T RtT[MP * S2];
   __shared__ double red[4][2][MP];
-  const int f = f0 + blockIdx.x / wpf;
+  const int f = o.perm[f0 + blockIdx.x / wpf];
   const int wg = blockIdx.x % wpf;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mf = o.m[f], mp = o.m_pad;
@@ -229,7 +229,7 @@ k_rot_cholres(Geo g, OrbSet o, int f0, int wpf, const double *__restrict__ Linv,
   __shared__ __attribute__((aligned(16))) T R1[MP * S2];
   __shared__ __attribute__((aligned(16))) T R2[MP * S2];
   __shared__ double red[4][MP];
-  const int f = f0 + blockIdx.x / wpf;
+  const int f = o.perm[f0 + blockIdx.x / wpf];
   const int wg = blockIdx.x % wpf;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int mf = o.m[f], mp = o.m_pad;
@@ -447,7 +447,7 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, const T *x, T *xo, T *a
   constexpr int LD = gram_ld<T>();
   __shared__ __attribute__((aligned(16))) T Xs[MP * LD];
   __shared__ __attribute__((aligned(16))) T Ys[SYM && !UPM ? 4 : MP * LD];
-  const int f = f0 + blockIdx.x / chunks;
+  const int f = o.perm[f0 + blockIdx.x / chunks];
   const int c = blockIdx.x % chunks;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int mf = o.m[f];
@@ -628,7 +628,7 @@ k_gram3(Geo g, OrbSet o, int f0, int chunks, int kchunk, const T *x, T *xo, T *a
       __builtin_amdgcn_sched_barrier(0);
     }
   }
-  const long long po = ((long long)(f - f0) * chunks + c) * mp * mp;
+  const long long po = (long long)blockIdx.x * mp * mp;   // (launch-local fragment, chunk)
 #pragma unroll
   for (int k = 0; k < PER_WAVE; ++k) {
     if (tI[k] < 0) continue;
@@ -665,7 +665,7 @@ __global__ void __launch_bounds__(256) k_gram_reduce2(Geo g, OrbSet o, int f0, i
   }
   const int fl = (int)(idx / (mp * mp));
   const int e = (int)(idx % (mp * mp));
-  const int f = f0 + fl;
+  const int f = o.perm[f0 + fl];
   int i = e / mp, j = e % mp;
   const int mf = o.m[f];
   double s = 0.0;
@@ -699,7 +699,7 @@ __global__ void __launch_bounds__(256) k_symmetrize(OrbSet o, int f0, int nf,
   const long long total = (long long)nf * mp * mp;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  const int f = f0 + (int)(idx / (mp * mp));
+  const int f = o.perm[f0 + (int)(idx / (mp * mp))];
   const int e = (int)(idx % (mp * mp));
   const int i = e / mp, j = e % mp;
   const double *Gf = G + (long long)f * mp * mp;
@@ -760,7 +760,7 @@ __global__ void __launch_bounds__(256) k_cholinv(OrbSet o, int f0, const double 
   __shared__ double B1[kMaxOrb * (kMaxOrb + 1)];
   __shared__ double B2[kMaxOrb * (kMaxOrb + 1)];
   __shared__ int bad;
-  const int f = f0 + blockIdx.x;
+  const int f = o.perm[f0 + blockIdx.x];
   const int mf = o.m[f], mp = o.m_pad;
   const double *Sf = S + (long long)f * mp * mp;
   double *Lf = Linv + (long long)f * mp * mp;
@@ -884,7 +884,7 @@ __global__ void __launch_bounds__(256) k_ritz_combine(OrbSet o, int f0,
                                                       double *__restrict__ C) {
   __shared__ double P[kMaxOrb * (kMaxOrb + 1)];
   __shared__ double Q[kMaxOrb * (kMaxOrb + 1)];
-  const int f = f0 + blockIdx.x;
+  const int f = o.perm[f0 + blockIdx.x];
   const int mf = o.m[f], mp = o.m_pad;
   const int nt = (mf + 15) / 16, mt = 16 * nt, ld = mt + 1;
   const double *Lf = Linv + (long long)f * mp * mp, *Uf = U + (long long)f * mp * mp;
@@ -935,7 +935,7 @@ __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *_
   __shared__ double2 cs_of[2][kMaxOrb / 2 + 1];
   __shared__ double red[32];
   __shared__ int rank_of[kMaxOrb];
-  const int f = f0 + blockIdx.x;
+  const int f = o.perm[f0 + blockIdx.x];
   const int mf = o.m[f], mp = o.m_pad;
   const int ld = mf | 1;   // odd row stride: column walks hit distinct banks
   const double *Hf = H + (long long)f * mp * mp;
