@@ -234,11 +234,21 @@ hipStream_t xstream(const dcdft_ctx *c) { return c->xs ? c->xs : c->stream; }
 
 // Gram partials of fragments [f0, ...) at their absolute place
 // [F][chunks][m_pad][m_pad], so concurrent fragment groups do not share rows
+// (every launch position owns gram_chunks_max partial matrices, so launches with
+// different chunk counts never overlap)
 double *gpart_at(const dcdft_ctx *c, int f0) {
-  return c->d_gpart + (long long)f0 * c->gram_chunks * c->m_pad * c->m_pad;
+  return c->d_gpart + (long long)f0 * c->gram_chunks_max * c->m_pad * c->m_pad;
 }
 double *gpart2_at(const dcdft_ctx *c, int f0) {
-  return c->d_gpart2 + (long long)f0 * c->gram_chunks * c->m_pad * c->m_pad;
+  return c->d_gpart2 + (long long)f0 * c->gram_chunks_max * c->m_pad * c->m_pad;
+}
+
+// Gram chunks for a launch over launch positions [a, b): the tuned count, raised
+// (up to the maximum) so that a small tile class still spreads over about 1024
+// workgroups
+int chunks_for(const dcdft_ctx *c, int a, int b) {
+  const int want = (1024 + (b - a) - 1) / std::max(1, b - a);
+  return std::max(c->gram_chunks, std::min(c->gram_chunks_max, want));
 }
 
 // fn(a, b, o) for every tile class meeting the launch positions [p0, p1): o is the
@@ -291,15 +301,17 @@ void apply_h_range(dcdft_ctx *c, int f0, int f1, const T *x, T *y) {
 template <typename T>
 void gram(dcdft_ctx *c, int f0, int f1, const T *x, const T *y, double *G, double *Gs,
           double *diag) {
-  OrbSet o = c->orbset(f0, f1);
   by_class(c, f0, f1, [&](int a, int b, const OrbSet &oc) {
     const double n = c->geo.n, sz = sizeof(T);
-    Timed t(c, DCDFT_KERNEL_GRAM, sz * n * orbitals_in(c, a, b) * (x == y ? 1.0 : 2.0),
-            2.0 * n * sum_m2(c, a, b));
-    launch_gram<T>(c->geo, oc, a, b, c->gram_chunks, x, y, gpart_at(c, a), xstream(c));
+    const int ch = chunks_for(c, a, b);
+    {
+      Timed t(c, DCDFT_KERNEL_GRAM, sz * n * orbitals_in(c, a, b) * (x == y ? 1.0 : 2.0),
+              2.0 * n * sum_m2(c, a, b));
+      launch_gram<T>(c->geo, oc, a, b, ch, x, y, gpart_at(c, a), xstream(c));
+    }
+    launch_gram_reduce(c->geo, oc, a, b, ch, x == y, gpart_at(c, a), G ? G : c->d_gtmp, Gs,
+                       diag, xstream(c));
   });
-  launch_gram_reduce(c->geo, o, f0, f1, c->gram_chunks, x == y, gpart_at(c, f0),
-                     G ? G : c->d_gtmp, Gs, diag, xstream(c));
 }
 
 // Steps (a)-(l) of the fragment CG eigensolver and the Rayleigh-Ritz rotation,
@@ -324,7 +336,6 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
   const T *psi0 = (const T *)c->d_psi;
   T *psi = (T *)c->d_psi_next, *w = (T *)c->d_w, *p = (T *)c->d_p, *q = (T *)c->d_q;
   const double n = g.n, sz = sizeof(T);
-  const int ch = c->gram_chunks;
   // FP32 arrays: the re-orthonormalisation of one sweep also forms the next
   // sweep's Hs and residual (fused rotation, fewer passes).  FP64 arrays keep
   // the separate passes (the fused rotation's three matrix-core products per
@@ -360,10 +371,13 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
     }
     // (d)-(e) P = -G + beta P_prev, X = <Psi, P>
     per_class(DCDFT_KERNEL_GRAM_FUSED, 4.0, 2.0, [&](int a, int b, const OrbSet &oc) {
-      launch_gram_direction<T>(g, oc, a, b, ch, pin, q, p, c->d_beta, gpart_at(c, a), s,
-                               sw == 0);
+      launch_gram_direction<T>(g, oc, a, b, chunks_for(c, a, b), pin, q, p, c->d_beta,
+                               gpart_at(c, a), s, sw == 0);
     });
-    launch_gram_reduce(g, o, f0, f1, ch, 0, gpart_at(c, f0), c->d_x, nullptr, nullptr, s);
+    by_class(c, f0, f1, [&](int a, int b, const OrbSet &oc) {
+      launch_gram_reduce(g, oc, a, b, chunks_for(c, a, b), 0, gpart_at(c, a), c->d_x, nullptr,
+                         nullptr, s);
+    });
     // (e)-(f) P <- P - X^T Psi, nu_i = <p_i, p_i> (and 1/sqrt(nu_i)), <p_i, w_i>
     per_class(DCDFT_KERNEL_ROTATE, 4.0, 2.0, [&](int a, int b, const OrbSet &oc) {
       launch_rot_project_out<T>(g, oc, a, b, c->d_x, pin, p, w, c->d_dpart, c->d_nu, c->d_bb,
@@ -383,14 +397,15 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
     const bool with_m = fuse || last;
     per_class(DCDFT_KERNEL_GRAM_FUSED, last ? 5.0 : 6.0, with_m ? 3.0 : 1.0,
               [&](int a, int b, const OrbSet &oc) {
-                launch_gram_update<T>(g, oc, a, b, ch, pin, psi, p, w, q, c->d_cos, c->d_sin,
-                                      gpart_at(c, a), s, with_m ? gpart2_at(c, a) : nullptr,
-                                      !last);
+                launch_gram_update<T>(g, oc, a, b, chunks_for(c, a, b), pin, psi, p, w, q,
+                                      c->d_cos, c->d_sin, gpart_at(c, a), s,
+                                      with_m ? gpart2_at(c, a) : nullptr, !last);
               });
     if (!with_m) {
-      launch_gram_reduce(g, o, f0, f1, ch, 1, gpart_at(c, f0), c->d_s, nullptr, nullptr, s);
       // (l) S = L L^T, Psi <- L^-1 Psi, W <- L^-1 W
       by_class(c, f0, f1, [&](int a, int b, const OrbSet &oc) {
+        launch_gram_reduce(g, oc, a, b, chunks_for(c, a, b), 1, gpart_at(c, a), c->d_s,
+                           nullptr, nullptr, s);
         launch_cholinv(oc, a, b, c->d_s, c->d_lin, c->d_flags, s);
       });
       per_class(DCDFT_KERNEL_ROTATE, 4.0, 2.0, [&](int a, int b, const OrbSet &oc) {
@@ -398,11 +413,11 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
       });
       continue;
     }
-    launch_gram_reduce_pair(g, o, f0, f1, ch, gpart_at(c, f0), c->d_s, gpart2_at(c, f0),
-                            c->d_hs_full, s);
     // (l) S = L L^T; with Psi = L^-1 Psi', W = L^-1 W' the next sweep's
     // Hs = sym(<Psi, W>) = sym(L^-1 M L^-T) and a_i = Hs_ii, B = Hs L^-1
     by_class(c, f0, f1, [&](int a, int b, const OrbSet &oc) {
+      launch_gram_reduce_pair(g, oc, a, b, chunks_for(c, a, b), gpart_at(c, a), c->d_s,
+                              gpart2_at(c, a), c->d_hs_full, s);
       launch_cholinv(oc, a, b, c->d_s, c->d_lin, c->d_flags, s, c->d_hs_full, c->d_hs, c->d_a,
                      c->d_bmat);
     });
