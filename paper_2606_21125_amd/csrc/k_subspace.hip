@@ -755,10 +755,11 @@ __global__ void __launch_bounds__(256) k_cholinv(OrbSet o, int f0, const double 
                                                  double *__restrict__ Hs,
                                                  double *__restrict__ adiag,
                                                  double *__restrict__ Bm) {
-  __shared__ double colb[2][kMaxOrb], xrowb[2][kMaxOrb];
-  __shared__ double B0[kMaxOrb * (kMaxOrb + 1)];
-  __shared__ double B1[kMaxOrb * (kMaxOrb + 1)];
-  __shared__ double B2[kMaxOrb * (kMaxOrb + 1)];
+  constexpr int MTS = 16 * NT;   // staging sized for the tile count
+  __shared__ double colb[2][MTS], xrowb[2][MTS];
+  __shared__ double B0[MTS * (MTS + 1)];
+  __shared__ double B1[MTS * (MTS + 1)];
+  __shared__ double B2[MTS * (MTS + 1)];
   __shared__ int bad;
   const int f = o.perm[f0 + blockIdx.x];
   const int mf = o.m[f], mp = o.m_pad;
@@ -877,13 +878,15 @@ __global__ void __launch_bounds__(256) k_cholinv(OrbSet o, int f0, const double 
 // C = L^-T U for the closing rotation of the re-orthonormalisation and the
 // Rayleigh-Ritz step together: with Psi = L^-1 Psi' the Ritz vectors are
 // U^T Psi = (L^-T U)^T Psi', so one rotation of Psi' by C replaces two.  One
-// workgroup per fragment, FP64 matrix cores.
+// workgroup per fragment, FP64 matrix cores; LDS sized for NT 16-orbital tiles.
+template <int NT>
 __global__ void __launch_bounds__(256) k_ritz_combine(OrbSet o, int f0,
                                                       const double *__restrict__ Linv,
                                                       const double *__restrict__ U,
                                                       double *__restrict__ C) {
-  __shared__ double P[kMaxOrb * (kMaxOrb + 1)];
-  __shared__ double Q[kMaxOrb * (kMaxOrb + 1)];
+  constexpr int MT = 16 * NT;
+  __shared__ double P[MT * (MT + 1)];
+  __shared__ double Q[MT * (MT + 1)];
   const int f = o.perm[f0 + blockIdx.x];
   const int mf = o.m[f], mp = o.m_pad;
   const int nt = (mf + 15) / 16, mt = 16 * nt, ld = mt + 1;
@@ -923,18 +926,22 @@ __device__ inline void rr_pair(int mm, int r, int k, int &p, int &q) {
 }
 
 // Parallel cyclic Jacobi: each round rotates mm/2 disjoint (p, q) planes at once.
+// A and V in LDS sized for NT 16-orbital tiles (launched per tile class, so that
+// the workgroups of small fragments fit several to a compute unit).
+template <int NT>
 __global__ void __launch_bounds__(1024) k_syev(OrbSet o, int f0, const double *__restrict__ H,
                                               double *__restrict__ U, double *__restrict__ eps,
                                               int *flags) {
-  __shared__ double A[kMaxOrb * (kMaxOrb + 1)];
-  __shared__ double V[kMaxOrb * (kMaxOrb + 1)];
+  constexpr int MT = 16 * NT;
+  __shared__ double A[MT * (MT + 1)];
+  __shared__ double V[MT * (MT + 1)];
   // rotations of two consecutive rounds: round r is applied while round r + 1's
   // angles are formed
   // (p, q) and (c, s) of each pair packed: one LDS read each
-  __shared__ int2 pq_of[2][kMaxOrb / 2 + 1];
-  __shared__ double2 cs_of[2][kMaxOrb / 2 + 1];
+  __shared__ int2 pq_of[2][MT / 2 + 1];
+  __shared__ double2 cs_of[2][MT / 2 + 1];
   __shared__ double red[32];
-  __shared__ int rank_of[kMaxOrb];
+  __shared__ int rank_of[MT];
   const int f = o.perm[f0 + blockIdx.x];
   const int mf = o.m[f], mp = o.m_pad;
   const int ld = mf | 1;   // odd row stride: column walks hit distinct banks
@@ -1367,13 +1374,33 @@ void launch_cholinv(const OrbSet &o, int f0, int f1, const double *S, double *Li
 void launch_ritz_combine(const OrbSet &o, int f0, int f1, const double *Linv, const double *U,
                          double *C, hipStream_t s) {
   if (f1 <= f0) return;
-  hipLaunchKernelGGL(k_ritz_combine, dim3(f1 - f0), dim3(256), 0, s, o, f0, Linv, U, C);
+  switch (o.tiles) {
+#define DCDFT_RITZ(NT)                                                                          \
+  hipLaunchKernelGGL(k_ritz_combine<NT>, dim3(f1 - f0), dim3(256), 0, s, o, f0, Linv, U, C);   \
+  break
+    case 1: DCDFT_RITZ(1);
+    case 2: DCDFT_RITZ(2);
+    case 3: DCDFT_RITZ(3);
+    case 4: DCDFT_RITZ(4);
+    default: DCDFT_RITZ(5);
+#undef DCDFT_RITZ
+  }
 }
 
 void launch_syev(const OrbSet &o, int f0, int f1, const double *Hs, double *U, double *eps,
                  int *flags, hipStream_t s) {
   if (f1 <= f0) return;
-  hipLaunchKernelGGL(k_syev, dim3(f1 - f0), dim3(1024), 0, s, o, f0, Hs, U, eps, flags);
+  switch (o.tiles) {
+#define DCDFT_SYEV(NT)                                                                          \
+  hipLaunchKernelGGL(k_syev<NT>, dim3(f1 - f0), dim3(1024), 0, s, o, f0, Hs, U, eps, flags);   \
+  break
+    case 1: DCDFT_SYEV(1);
+    case 2: DCDFT_SYEV(2);
+    case 3: DCDFT_SYEV(3);
+    case 4: DCDFT_SYEV(4);
+    default: DCDFT_SYEV(5);
+#undef DCDFT_SYEV
+  }
 }
 
 void launch_kb_quad_theta(const OrbSet &o, int f0, int f1, const KBTables &kb, const double *C,
