@@ -729,8 +729,8 @@ dcdft_status build_and_upload(dcdft_ctx *c, const dcdft_params *p) {
     {
       const size_t elem = c->precision == DCDFT_PREC_MIXED ? sizeof(float) : sizeof(double);
       const int rr = c->RY ? c->RY * c->RZ : region_rows(g.nl[0]);
-      const size_t need = std::max(kb_lds_bytes(g, ks, rr, c->tiles, elem, true),
-                                   kb_lds_bytes(g, ks, rr, c->tiles, elem, false));
+      const size_t need = std::max(kb_lds_bytes(g, ks, rr, c->RP, c->tiles, elem, true),
+                                   kb_lds_bytes(g, ks, rr, c->RP, c->tiles, elem, false));
       if (need > 65536)
         return set_err(c, DCDFT_ERR_ARG,
                        fmt("%d projectors meet one %d-point region: the projector kernels would "
@@ -1682,8 +1682,9 @@ dcdft_status dcdft_lcfo_build(dcdft_ctx *c, double eps_cut, double lambda_cut,
     // the basis is FP64 whatever the step's precision: the FP64 projector kernels
     // must fit their LDS (setup checked the step's own precision only)
     const int rr = c->RY ? c->RY * c->RZ : region_rows(g.nl[0]);
-    const size_t need = std::max(kb_lds_bytes(g, c->KS, rr, c->tiles, sizeof(double), true),
-                                 kb_lds_bytes(g, c->KS, rr, c->tiles, sizeof(double), false));
+    const size_t need =
+        std::max(kb_lds_bytes(g, c->KS, rr, c->RP, c->tiles, sizeof(double), true),
+                 kb_lds_bytes(g, c->KS, rr, c->RP, c->tiles, sizeof(double), false));
     if (need > 65536)
       return set_err(c, DCDFT_ERR_ARG,
                      fmt("%d projectors meet one projector region: the FP64 projector kernels "

@@ -64,7 +64,7 @@ bool hloc_halo_ok(const Geo &g);
 // LDS bytes a projector kernel needs (slot tables plus the (E C)^T block of apply
 // or the partial sums of project) for KS slots, rr region rows and tiles 16-orbital
 // tiles
-size_t kb_lds_bytes(const Geo &g, int KS, int rr, int tiles, size_t elem, bool apply);
+size_t kb_lds_bytes(const Geo &g, int KS, int rr, int rp, int tiles, size_t elem, bool apply);
 
 // Fragments are launched in an order sorted by their count of 16-orbital tiles
 // (launch order; the identity when every fragment has the same count): kernels
@@ -97,7 +97,8 @@ struct OrbSet {           // flattened orbital layout [M_tot][n]
 // shaped to meet as few atoms as possible; otherwise (RY = 0) a region is
 // kRegion consecutive points.  The beta values are not stored: the kernels
 // evaluate beta_a(l) = sc_a exp(-r2 / (2 sigma_a^2)) on r2 <= rcut_a^2, with
-// r2 = (dz^2 + dy^2) + dx^2 taken from per-pair tables of squared offsets.
+// r2 = (dz^2 + dy^2) + dx^2 taken from per-pair tables of squared offsets, as
+// the product of per-row and per-x exponential factors staged per region.
 constexpr int kRegion = 256;
 constexpr int kBlockRegionMax = 512;   // points of a block region, at most
 constexpr int kMaxSlotTiles = 6;    // KS_max <= 96 slots per region

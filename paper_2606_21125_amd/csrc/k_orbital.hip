@@ -371,7 +371,6 @@ __global__ void __launch_bounds__(256) k_dot_segments(Geo g, long long b0, long 
   dot[b0 + i] = g.dv * sum;
 }
 
-// Four consecutive values from global memory at a 16-byte aligned address.
 // Four consecutive values from 16-byte aligned LDS.
 template <typename T>
 __device__ inline void lds_read4(const T *p, T *d) {
@@ -439,99 +438,132 @@ __device__ inline int region_point(const Geo &g, const KBTables &kb, int reg, in
   return l;
 }
 
-// Slot tables of one projector region in LDS: sx[KS][nx] (squared x offsets of
-// the slot's atom), syz[KS][RR] (dz^2 + dy^2 of the region's rows), sc, c2, r2c
-// [KS] (normalisation, 1 / (2 sigma^2), rcut^2).  An empty slot gets
-// rcut^2 = -1, so every point lies outside its support.
-__device__ inline void stage_region(const Geo &g, const KBTables &kb, int f, int reg, double *sx,
-                                    double *syz, double *par) {
+// Tables of one projector region in LDS, built once per workgroup (byte
+// offsets from kb_tab): the region's points pts[q] = (local point l, x | row
+// << 16); per slot s the separable factors of the Gaussian, ex[s][x] =
+// exp(-c2 dx^2) and eyz[s][row] = sc exp(-c2 (dz^2 + dy^2)); and the support
+// of the slot as bit masks over x, msk[s][row][x / 32], bit set where
+// r2 = (dz^2 + dy^2) + dx^2 <= rcut^2 in FP64 (the test of the definition).
+// An empty slot has no support bits.  The FP64 squared offsets are staged in
+// tmp (the kernel's own area, free until the tables are built).
+struct KbTab {
+  int nxs, rrs;                     // row strides of ex and of eyz / msk (bank spread)
+  int msk, eyz, ex, pts, area;
+};
+__host__ __device__ inline int kb_align16(int b) { return (b + 15) & ~15; }
+__host__ __device__ inline KbTab kb_tab(int KS, int nx, int RR, int RP, int elem) {
+  KbTab t;
+  t.nxs = nx + 16 / elem;           // 16-byte rows when 16 bytes hold whole x runs
+  t.rrs = RR | 1;
+  t.msk = 0;
+  t.eyz = kb_align16(KS * t.rrs * ((nx + 31) >> 5) * 4);
+  t.ex = kb_align16(t.eyz + KS * t.rrs * elem);
+  t.pts = kb_align16(t.ex + KS * t.nxs * elem);
+  t.area = kb_align16(t.pts + RP * 8);
+  return t;
+}
+
+template <typename T>
+__device__ inline void stage_region(const Geo &g, const KBTables &kb, const KbTab &tb, int f,
+                                    int reg, unsigned *msk, T *eyz, T *ex, int2 *pts,
+                                    double *tmp) {
   const int nx = g.nl[0], ny = g.nl[1], nls = g.nl[0] + g.nl[1] + g.nl[2];
-  const int RR = region_nrows(g, kb);
-  const int *ra = kb.reg_atom + ((long long)f * kb.NR + reg) * kb.KS;
+  const int RR = region_nrows(g, kb), NWD = (nx + 31) >> 5, KS = kb.KS;
+  const int *ra = kb.reg_atom + ((long long)f * kb.NR + reg) * KS;
   const int pf = kb.pair_first[f];
-  for (int e = threadIdx.x; e < kb.KS * nx; e += blockDim.x) {
-    const int a = ra[e / nx];
-    sx[e] = a >= 0 ? kb.pr_sq[(long long)(pf + a) * nls + e % nx] : 0.0;
+  double *tsx = tmp, *tsyz = tmp + KS * nx;
+  for (int q = threadIdx.x; q < kb.RP; q += blockDim.x) {
+    int lx, rr;
+    const int l = region_point(g, kb, reg, q, lx, rr);
+    pts[q] = make_int2(l, lx | (rr << 16));
   }
-  for (int e = threadIdx.x; e < kb.KS * RR; e += blockDim.x) {
+  for (int e = threadIdx.x; e < KS * nx; e += blockDim.x) {
+    const int a = ra[e / nx];
+    double v = 0.0, c2 = 0.0;
+    if (a >= 0) {
+      v = kb.pr_sq[(long long)(pf + a) * nls + e % nx];
+      c2 = kb.pr_par[(long long)(pf + a) * 3 + 1];
+    }
+    tsx[e] = v;
+    ex[(e / nx) * tb.nxs + e % nx] = (T)exp(-v * c2);
+  }
+  for (int e = threadIdx.x; e < KS * RR; e += blockDim.x) {
     const int a = ra[e / RR];
     int ly, lz;
     region_row(g, kb, reg, e % RR, ly, lz);
-    double v = 0.0;
+    double v = 0.0, w = 0.0;
     if (a >= 0) {
       const double *q = kb.pr_sq + (long long)(pf + a) * nls;
+      const double *par = kb.pr_par + (long long)(pf + a) * 3;
       v = q[nx + ny + lz] + q[nx + ly];
+      w = par[0] * exp(-v * par[1]);
     }
-    syz[e] = v;
+    tsyz[e] = v;
+    eyz[(e / RR) * tb.rrs + e % RR] = (T)w;
   }
-  for (int e = threadIdx.x; e < kb.KS; e += blockDim.x) {
-    const int a = ra[e];
-    double v0 = 0.0, v1 = 0.0, v2 = -1.0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < KS * RR * NWD; e += blockDim.x) {
+    const int sl = e / (RR * NWD), row = (e / NWD) % RR, w = e % NWD;
+    const int a = ra[sl];
+    unsigned m = 0u;
     if (a >= 0) {
-      const double *q = kb.pr_par + (long long)(pf + a) * 3;
-      v0 = q[0];
-      v1 = q[1];
-      v2 = q[2];
+      const double rc2 = kb.pr_par[(long long)(pf + a) * 3 + 2], yz = tsyz[sl * RR + row];
+      const double *sx = tsx + sl * nx + 32 * w;
+      const int nb = min(32, nx - 32 * w);
+      for (int b = 0; b < nb; ++b)
+        if (!(yz + sx[b] > rc2)) m |= 1u << b;
     }
-    par[e] = v0;
-    par[kb.KS + e] = v1;
-    par[2 * kb.KS + e] = v2;
+    msk[(sl * tb.rrs + row) * NWD + w] = m;
   }
 }
 
-// beta of slot s at the point (lx, region row rr): sc exp(-r2 c2) on r2 <= rcut^2,
-// r2 = (dz^2 + dy^2) + dx^2 in FP64 (the support test is exact); FP32 arrays
-// take the exponential in FP32.
+// beta of slot s at the point (lx, region row rr): eyz ex on the support, else 0
 template <typename T>
-__device__ inline T beta_at(const double *sx, const double *syz, const double *par, int KS, int nx,
-                            int RR, int s, int lx, int rr) {
-  const double r2 = syz[s * RR + rr] + sx[s * nx + lx];
-  const double sc = par[s], c2 = par[KS + s], rc2 = par[2 * KS + s];
-  T v;
-  if (sizeof(T) == 8)
-    v = (T)(sc * exp(-r2 * c2));
-  else
-    v = (T)((float)sc * expf((float)(-r2 * c2)));
-  return r2 > rc2 ? (T)0 : v;
+__device__ inline T beta_at(const KbTab &tb, const unsigned *msk, const T *eyz, const T *ex,
+                            int NWD, int s, int lx, int rr) {
+  const int sr = s * tb.rrs + rr;
+  const unsigned m = msk[sr * NWD + (lx >> 5)];
+  const T v = eyz[sr] * ex[s * tb.nxs + lx];
+  return ((m >> (lx & 31)) & 1u) ? v : (T)0;
 }
 
-// Points per projector chunk: the region's beta block is evaluated CH points at
-// a time into LDS (double-buffered) and shared by the four waves.
+// Points per load step of the projection.
 template <typename T>
 constexpr int kb_chunk() { return sizeof(T) == 4 ? 64 : 32; }
 
 // Region partials of the projections: part[(f, region)][slot][i] =
 // sum_{l in region} beta_slot(l) X_i(l), as MFMA products of the region's beta
-// block (slots x points) with its orbital columns.  The beta block is evaluated
-// chunk by chunk into LDS by all threads (one point and KS / (256 / CH) slots
-// each), the next chunk while the products of the current one run; wave w
-// takes orbital tile w over every point, and with five tiles the fifth goes to
-// wave (workgroup index mod 4), so that no SIMD always takes the heavier wave.
-// Tiles at or beyond the fragment's orbital count are skipped (their partials
-// stay zero).  The K index walks the
-// points of a 16-point step as 4 (lane/16) + t, so every lane reads runs of 4
-// contiguous values of both operands (16-byte loads when VEC: n % 4 == 0); the
-// orbital values of the next chunk are loaded before the products of the
-// current one (unconditional loads, rows and points clamped, values masked).
+// block (slots x points) with its orbital columns.  Wave w takes orbital tile w
+// over every point, and with five tiles the fifth goes to wave (workgroup index
+// mod 4), so that no SIMD always takes the heavier wave; tiles at or beyond the
+// fragment's orbital count are skipped (their partials stay zero).  The K index
+// walks the points of a 16-point step as 4 (lane/16) + t, so every lane reads
+// runs of 4 contiguous orbital values (16-byte loads when VEC: n % 4 == 0 and
+// nx % 4 == 0).  Each wave forms its own beta operand in registers from the
+// region tables: with VEC a lane's 4 points lie in one x run, so one 16-byte
+// read of ex, one eyz value and one mask word give all four.  The main loop
+// has no barrier; the orbital values of the next step are loaded before the
+// products of the current one (unconditional loads, rows and points clamped,
+// values masked).
 template <typename T, int TM, int KT, bool VEC>
 __global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && KT == 3 ? 3 : 1, 8))) k_kb_project(Geo g, OrbSet o, KBTables kb, int f0,
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (TM < 5 ? 4 : 3) : 1, 8))) k_kb_project(Geo g, OrbSet o, KBTables kb, int f0,
                                                     const T *__restrict__ x,
                                                     double *__restrict__ part) {
   typedef Mfma<T> MM;
   constexpr int MP = 16 * TM;
-  constexpr int KSM = 16 * KT;
   constexpr int CH = kb_chunk<T>();
-  constexpr int NS = CH / 16;                  // 16-point steps per chunk
-  constexpr int BS = CH + 16 / (int)sizeof(T); // beta row stride (16-byte rows, skewed)
-  constexpr int SG = 256 / CH;                 // slot groups of the evaluation
+  constexpr int NS = CH / 16;                  // 16-point steps per load step
   constexpr int JW = (TM + 3) / 4;             // orbital tile items per wave
   static_assert(JW <= 2, "at most eight orbital tiles");
   extern __shared__ __attribute__((aligned(16))) double kb_lds[];
-  const int nx = g.nl[0], RR = region_nrows(g, kb);
+  const int nx = g.nl[0], RR = region_nrows(g, kb), NWD = (nx + 31) >> 5;
   const int NCH = kb.RP / CH;
-  double *sx = kb_lds, *syz = sx + kb.KS * nx, *par = syz + kb.KS * RR;
-  T *bl = reinterpret_cast<T *>(par + 3 * kb.KS);   // [2][KSM][BS]
+  const KbTab tb = kb_tab(kb.KS, nx, RR, kb.RP, (int)sizeof(T));
+  char *lds = reinterpret_cast<char *>(kb_lds);
+  unsigned *msk = reinterpret_cast<unsigned *>(lds + tb.msk);
+  T *eyz = reinterpret_cast<T *>(lds + tb.eyz), *ex = reinterpret_cast<T *>(lds + tb.ex);
+  int2 *pts = reinterpret_cast<int2 *>(lds + tb.pts);
   const int f = o.perm[f0 + blockIdx.x / kb.NR];
   const int reg = blockIdx.x % kb.NR;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -550,7 +582,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && KT == 3 ? 3 : 1, 8))) k_kb_
     if (jts[q] > TM) jts[q] = TM;
     live[q] = jts[q] < TM && jts[q] * 16 < mf;
   }
-  auto load_x = [&](int ch, T (*bx)[NS][4]) {
+  // (the first step's loads are issued before the point table exists)
+  auto load_x = [&](int ch, T (*bx)[NS][4], bool direct) {
 #pragma unroll
     for (int q = 0; q < JW; ++q) {
       const int jt = jts[q];
@@ -566,12 +599,17 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && KT == 3 ? 3 : 1, 8))) k_kb_
       const T *row = x + base + (long long)(orb < rmax ? orb : rmax) * g.n;
 #pragma unroll
       for (int u = 0; u < NS; ++u) {
-        // four consecutive region points lie in one x run (nx % 4 == 0 for
-        // block regions), so they are consecutive local points
-        int lx0, rr0;
-        const int pu = region_point(g, kb, reg, ch * CH + u * 16 + 4 * kk, lx0, rr0);
+        const int qu = ch * CH + u * 16 + 4 * kk;
+        int pu;
+        if (direct) {
+          int lx0, rr0;
+          pu = region_point(g, kb, reg, qu, lx0, rr0);
+        } else {
+          pu = pts[qu].x;
+        }
         if (VEC) {
-          // n % 4 == 0 and pu % 4 == 0: the run lies wholly inside or outside
+          // four consecutive region points are consecutive local points of one
+          // x run, wholly inside or outside the box
           const int pc = pu < g.n ? pu : g.n - 4;
           T v[4];
           load4_aligned(row + pc, v);
@@ -580,7 +618,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && KT == 3 ? 3 : 1, 8))) k_kb_
         } else {
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
-            const int pt = pu + t;
+            const int pt = direct ? pu + t : pts[qu + t].x;
             const T v = row[pt < g.n ? pt : g.n - 1];
             bx[q][u][t] = (ok && pt < g.n) ? v : (T)0;
           }
@@ -588,33 +626,34 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && KT == 3 ? 3 : 1, 8))) k_kb_
       }
     }
   };
+  // beta of slot tile st (slot st * 16 + r) at the lane's four points of region
+  // index q0 .. q0 + 3
+  auto beta4 = [&](int st, int q0, T *av) {
+    const int sl = st * 16 + r;
+    if (VEC) {
+      const int2 pq = pts[q0];
+      const int lx = (pq.y & 0xFFFF) & ~3, rr = pq.y >> 16;
+      const int sr = sl * tb.rrs + rr;
+      const unsigned m = msk[sr * NWD + (lx >> 5)] >> (lx & 31);
+      const T e = eyz[sr];
+      T xv[4];
+      lds_read4(ex + sl * tb.nxs + lx, xv);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) av[t] = (pq.x < g.n && ((m >> t) & 1u)) ? e * xv[t] : (T)0;
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int2 pq = pts[q0 + t];
+        const T v = beta_at<T>(tb, msk, eyz, ex, NWD, sl, pq.y & 0xFFFF, pq.y >> 16);
+        av[t] = pq.x < g.n ? v : (T)0;
+      }
+    }
+  };
   // slot tiles that hold atoms in this region (the rest are skipped)
   const int nt = kb.reg_nt[(long long)f * kb.NR + reg];
-  auto beta_chunk = [&](int ch, T *dst) {
-    const int q = threadIdx.x % CH, sg = threadIdx.x / CH;
-    int lx, rr;
-    const int l = region_point(g, kb, reg, ch * CH + q, lx, rr);
-    auto eval = [&](auto kte) {   // the slot tiles in use only
-      constexpr int KTE = decltype(kte)::value;
-#pragma unroll
-      for (int j = 0; j < 16 * KTE / SG; ++j) {
-        const int sl = sg + SG * j;
-        const T v = beta_at<T>(sx, syz, par, kb.KS, nx, RR, sl, lx, rr);
-        dst[sl * BS + q] = l < g.n ? v : (T)0;
-      }
-    };
-    if (nt <= 1)
-      eval(std::integral_constant<int, 1>());
-    else if (nt == 2)
-      eval(std::integral_constant<int, (KT < 2 ? KT : 2)>());
-    else
-      eval(std::integral_constant<int, KT>());
-  };
   T bx[JW][NS][4];
-  load_x(0, bx);
-  stage_region(g, kb, f, reg, sx, syz, par);
-  __syncthreads();
-  beta_chunk(0, bl);
+  load_x(0, bx, true);
+  stage_region<T>(g, kb, tb, f, reg, msk, eyz, ex, pts, reinterpret_cast<double *>(lds + tb.area));
   __syncthreads();
   typename MM::acc_t acc[KT][JW];
 #pragma unroll
@@ -622,9 +661,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && KT == 3 ? 3 : 1, 8))) k_kb_
 #pragma unroll
     for (int q = 0; q < JW; ++q) acc[st][q] = MM::zero();
   for (int ch = 0; ch < NCH; ++ch) {
-    const T *cur = bl + (ch & 1) * KSM * BS;
     T bn[JW][NS][4];
-    load_x(ch + 1 < NCH ? ch + 1 : ch, bn);
+    load_x(ch + 1 < NCH ? ch + 1 : ch, bn, false);
     // products of the slot tiles in use (nt is uniform: a compile-time count each)
     auto products = [&](auto kte) {
       constexpr int KTE = decltype(kte)::value;
@@ -633,7 +671,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && KT == 3 ? 3 : 1, 8))) k_kb_
 #pragma unroll
         for (int st = 0; st < KTE; ++st) {
           T av[4];
-          lds_read4(cur + (st * 16 + r) * BS + u * 16 + 4 * kk, av);
+          beta4(st, ch * CH + u * 16 + 4 * kk, av);
 #pragma unroll
           for (int q = 0; q < JW; ++q)
             if (live[q])
@@ -647,8 +685,6 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && KT == 3 ? 3 : 1, 8))) k_kb_
       products(std::integral_constant<int, (KT < 2 ? KT : 2)>());
     else
       products(std::integral_constant<int, KT>());
-    if (ch + 1 < NCH) beta_chunk(ch + 1, bl + ((ch + 1) & 1) * KSM * BS);
-    __syncthreads();
 #pragma unroll
     for (int q = 0; q < JW; ++q)
 #pragma unroll
@@ -721,10 +757,14 @@ k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
   constexpr int LD = lds_stride(MP);
   constexpr int KSM = 16 * KT;
   extern __shared__ __attribute__((aligned(16))) double kb_lds[];
-  const int nx = g.nl[0], RR = region_nrows(g, kb);
+  const int nx = g.nl[0], RR = region_nrows(g, kb), NWD = (nx + 31) >> 5;
   const int NU = kb.RP / 16 / 4;  // tiles per wave
-  double *sx = kb_lds, *syz = sx + kb.KS * nx, *par = syz + kb.KS * RR;
-  T *ec = reinterpret_cast<T *>(par + 3 * kb.KS);   // [KSM][LD]
+  const KbTab tb = kb_tab(kb.KS, nx, RR, kb.RP, (int)sizeof(T));
+  char *lds = reinterpret_cast<char *>(kb_lds);
+  unsigned *msk = reinterpret_cast<unsigned *>(lds + tb.msk);
+  T *eyz = reinterpret_cast<T *>(lds + tb.eyz), *ex = reinterpret_cast<T *>(lds + tb.ex);
+  int2 *pts = reinterpret_cast<int2 *>(lds + tb.pts);
+  T *ec = reinterpret_cast<T *>(lds + tb.area);   // [KSM][LD]
   const int f = o.perm[f0 + blockIdx.x / kb.NR];
   const int reg = blockIdx.x % kb.NR;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -737,12 +777,14 @@ k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
   const int nt = kb.reg_nt[(long long)f * kb.NR + reg];   // slot tiles in use
   const double *Cf = C + (long long)f * kb.A_max * o.m_pad;
   const double *Ef = kb.E + (long long)f * kb.A_max;
+  // the tables first: their FP64 staging shares the area of (E C)^T
+  stage_region<T>(g, kb, tb, f, reg, msk, eyz, ex, pts, reinterpret_cast<double *>(lds + tb.area));
+  __syncthreads();
   for (int e = threadIdx.x; e < KSM * MP; e += blockDim.x) {
     const int slot = e / MP, i = e % MP;
     const int a = (slot < kb.KS) ? ra[slot] : -1;
     ec[slot * LD + i] = (a >= 0 && i < mf) ? (T)(Ef[a] * Cf[(long long)a * o.m_pad + i]) : (T)0;
   }
-  stage_region(g, kb, f, reg, sx, syz, par);
   __syncthreads();
   const long long base = o.moff[f] * (long long)g.n;
   const int c = lane & 15, kk = lane >> 4;
@@ -756,8 +798,7 @@ k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
     return y + base + (long long)(orb < rmax ? orb : rmax) * g.n + pc;
   };
   auto load_y = [&](int k, T (*yv)[4]) {
-    int lx, rr;
-    const int p = region_point(g, kb, reg, (wave + 4 * k) * 16 + c, lx, rr);
+    const int p = pts[(wave + 4 * k) * 16 + c].x;
     const int pc = p < g.n ? p : g.n - 1;
 #pragma unroll
     for (int jt = 0; jt < TM; ++jt)
@@ -769,8 +810,8 @@ k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
   for (int k = 0; k < NU; ++k) {
     T yn[TM][4];
     load_y(k + 1 < NU ? k + 1 : k, yn);
-    int lx, rr0;
-    const int p = region_point(g, kb, reg, (wave + 4 * k) * 16 + c, lx, rr0);
+    const int2 pq = pts[(wave + 4 * k) * 16 + c];
+    const int p = pq.x, lx = pq.y & 0xFFFF, rr0 = pq.y >> 16;
     typename MM::acc_t acc[TM];
 #pragma unroll
     for (int j = 0; j < TM; ++j) acc[j] = MM::zero();
@@ -781,7 +822,7 @@ k_kb_apply(Geo g, OrbSet o, KBTables kb, int f0, const double *__restrict__ C,
       T bv[KTE * 4];
 #pragma unroll
       for (int st = 0; st < KTE * 4; ++st) {
-        const T v = beta_at<T>(sx, syz, par, kb.KS, nx, RR, 4 * st + kk, lx, rr0);
+        const T v = beta_at<T>(tb, msk, eyz, ex, NWD, 4 * st + kk, lx, rr0);
         bv[st] = p < g.n ? v : (T)0;
       }
 #pragma unroll
@@ -912,10 +953,10 @@ void kb_t(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1, con
           double *C, double *part, T *y, hipStream_t s) {
   const dim3 grid((f1 - f0) * kb.NR), block(256);
   if (x) {
-    const size_t lds = kb_lds_bytes(g, kb.KS, kb.RY ? kb.RY * kb.RZ : region_rows(g.nl[0]), TM,
+    const size_t lds = kb_lds_bytes(g, kb.KS, kb.RY ? kb.RY * kb.RZ : region_rows(g.nl[0]), kb.RP, TM,
                                     sizeof(T), false);
-    // 16-byte runs need n % 4 == 0 and an aligned array
-    if (g.n % 4 == 0 && (uintptr_t)x % 16 == 0)
+    // 16-byte runs of one x run need n % 4 == 0, nx % 4 == 0 and an aligned array
+    if (g.n % 4 == 0 && g.nl[0] % 4 == 0 && (uintptr_t)x % 16 == 0)
       hipLaunchKernelGGL((k_kb_project<T, TM, KT, true>), grid, block, lds, s, g, o, kb, f0, x,
                          part);
     else
@@ -925,7 +966,7 @@ void kb_t(const Geo &g, const OrbSet &o, const KBTables &kb, int f0, int f1, con
     hipLaunchKernelGGL(k_kb_reduce<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g,
                        o, kb, f0, f1 - f0, reinterpret_cast<const T *>(part), C);
   } else {
-    const size_t lds = kb_lds_bytes(g, kb.KS, kb.RY ? kb.RY * kb.RZ : region_rows(g.nl[0]), TM,
+    const size_t lds = kb_lds_bytes(g, kb.KS, kb.RY ? kb.RY * kb.RZ : region_rows(g.nl[0]), kb.RP, TM,
                                     sizeof(T), true);
     if (o.row_pad)
       hipLaunchKernelGGL((k_kb_apply<T, TM, KT, true>), grid, block, lds, s, g, o, kb, f0, C, y);
@@ -1015,14 +1056,15 @@ void launch_vec(const Geo &g, long long nb, int opw, int zs, const OrbSet &o, in
 
 }  // namespace
 
-// LDS bytes of the projector kernels: the slot tables, and the (E C)^T block
-// (apply) or the partial sums (project) of the widest orbital count
-size_t kb_lds_bytes(const Geo &g, int KS, int rr, int tiles, size_t elem, bool apply) {
-  const size_t tab = (size_t)KS * (g.nl[0] + rr + 3) * sizeof(double);
+// LDS bytes of the projector kernels: the region tables, then an area that
+// holds the FP64 staging of the tables (and afterwards, in the application,
+// the (E C)^T block of the widest orbital count)
+size_t kb_lds_bytes(const Geo &g, int KS, int rr, int rp, int tiles, size_t elem, bool apply) {
+  const KbTab t = kb_tab(KS, g.nl[0], rr, rp, (int)elem);
+  const size_t tmp = (size_t)KS * (g.nl[0] + rr) * sizeof(double);
   const int MP = 16 * tiles;
-  if (apply) return tab + (size_t)KS * lds_stride(MP) * elem;
-  const int ch = elem == 4 ? 64 : 32;   // project: two beta chunks
-  return tab + 2 * (size_t)KS * (ch + 16 / elem) * elem;
+  const size_t own = apply ? (size_t)KS * lds_stride(MP) * elem : 0;
+  return (size_t)t.area + std::max(own, tmp);
 }
 
 bool hloc_halo_ok(const Geo &g) {
