@@ -236,24 +236,44 @@ def hloc_kernel_name(variant: str, prec_mixed: bool, box) -> str:
     return HLOC_KERNEL[variant].format(t=t, nx=nx if nx in (24, 32) else 0)
 
 
-def recorded_traffic(variant: str, kernel: str, workload: str):
-    """HBM bytes per launch from the committed counter summaries, if they were
-    taken on the current stencil source for this launch shape (variant and
-    kernel) and workload."""
-    import glob
+def _orbital_source_sha() -> str:
     import hashlib
     src = os.path.join(ROOT, "paper_2606_21125_amd", "csrc", "k_orbital.hip")
     with open(src, "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def _traffic_records(tag: str):
+    """(fields, file) of every '<tag>: a | b | ...' line of the committed counter
+    summaries."""
+    import glob
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_counters.md"))):
         with open(path) as fh:
             for line in fh:
-                if not line.startswith("traffic:"):
-                    continue
-                parts = [p.strip() for p in line[len("traffic:"):].split("|")]
-                if len(parts) == 5 and parts[0] == variant and parts[1] == kernel and \
-                        parts[2] == workload and parts[4] == sha:
-                    return float(parts[3]), os.path.relpath(path, ROOT)
+                if line.startswith(tag + ":"):
+                    yield ([p.strip() for p in line[len(tag) + 1:].split("|")],
+                           os.path.relpath(path, ROOT))
+
+
+def recorded_traffic(variant: str, kernel: str, workload: str):
+    """HBM bytes per stencil launch from the committed counter summaries, if they
+    were taken on the current kernel source for this launch shape (variant and
+    kernel) and workload."""
+    sha = _orbital_source_sha()
+    for parts, path in _traffic_records("traffic"):
+        if len(parts) == 5 and parts[0] == variant and parts[1] == kernel and \
+                parts[2] == workload and parts[4] == sha:
+            return float(parts[3]), path
+    return None, None
+
+
+def recorded_projector_traffic(workload: str):
+    """HBM bytes of the projector kernels (projection, reduction, application)
+    per H psi application, under the same conditions."""
+    sha = _orbital_source_sha()
+    for parts, path in _traffic_records("traffic_kb"):
+        if len(parts) == 3 and parts[0] == workload and parts[2] == sha:
+            return float(parts[1]), path
     return None, None
 
 
@@ -416,6 +436,7 @@ def main() -> int:
     variant = tune["hloc_variant"] if tune else HLOC_VARIANTS[launch0["hloc_variant"]]
     kname = hloc_kernel_name(variant, prec != PREC_FP64, cfg.fragment_shape)
     traffic, traffic_src = recorded_traffic(variant, kname, cfg.name)
+    kb_traffic, kb_src = recorded_projector_traffic(cfg.name)
     n_app = max(1, h["launches"])            # H psi applications (one stencil launch each)
     stencil = {"bound": "hbm", "achieved": round(h_gbs, 1), "peak": HBM_PEAK_GBS,
                "unit": "GB/s", "frac": round(h_gbs / HBM_PEAK_GBS, 4),
@@ -429,7 +450,10 @@ def main() -> int:
     hpsi_gbs = (h["bytes"] / n_app) / (hpsi_ms * 1e-3) / 1e9 if hpsi_ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(hpsi_gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(hpsi_gbs / HBM_PEAK_GBS, 4),
-                "traffic": None, "kernel": f"H psi = {kname} + k_kb_project + k_kb_reduce + "
+                "traffic": (None if traffic is None or kb_traffic is None
+                            else round(traffic + kb_traffic)),
+                "traffic_source": None if kb_src is None or traffic_src is None else kb_src,
+                "kernel": f"H psi = {kname} + k_kb_project + k_kb_reduce + "
                                             f"k_kb_apply",
                 "avg_launch_ms": round(hpsi_ms, 4),
                 "bytes_per_launch": h["bytes"] / n_app,
