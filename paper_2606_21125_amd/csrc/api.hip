@@ -435,8 +435,10 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
   // Rayleigh-Ritz on Hs = sym(<Psi, W>) from the last sweep's re-orthonormalisation;
   // Psi' is not yet re-orthonormalised, so it is rotated by C = L^-T U at once;
   // then core weights w_i = dV sum_core psi_i^2
+  // one Jacobi launch over every class: the workgroups of one fragment each are
+  // latency-bound, so the classes run side by side rather than one after another
+  launch_syev(o, f0, f1, c->d_hs, c->d_u, c->d_eps, c->d_flags, s);
   by_class(c, f0, f1, [&](int a, int b, const OrbSet &oc) {
-    launch_syev(oc, a, b, c->d_hs, c->d_u, c->d_eps, c->d_flags, s);
     launch_ritz_combine(oc, a, b, c->d_lin, c->d_u, c->d_bmat, s);
   });
   per_class(DCDFT_KERNEL_ROTATE, 2.0, 2.0, [&](int a, int b, const OrbSet &oc) {

@@ -139,14 +139,14 @@ def test_autotune_choice_cache_and_results(tmp_path):
 @pytest.mark.parametrize("which", ["config1", "ragged"])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_concurrent_fragment_groups_bitwise(which, prec):
-    """The batched step with its eigensolver split over two or four streams
-    computes the same per-fragment sums as with one stream: bitwise-equal
-    results."""
+    """The batched step with its eigensolver split over two, three (the
+    default) or four streams computes the same per-fragment sums as with one
+    stream: bitwise-equal results."""
     require_gpu()
     from paper_2606_21125_amd import DCDFT
     cfg = workloads.config(1) if which == "config1" else _ragged_tiny()
     out = []
-    for streams in (1, 2, 4):
+    for streams in (1, 2, 3, 4):
         with DCDFT.from_config(cfg, precision=prec) as d:
             l0 = d.dcdft_get_launch()
             d.dcdft_set_launch(l0["hloc_variant"], l0["rot_tiles"], l0["gram_chunks"], streams)
