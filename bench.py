@@ -369,15 +369,20 @@ def main() -> int:
     cfg = workload_config(args.config)
     print(f"[bench] setup {cfg.name}: {cfg.system.n_atoms} atoms, grid {cfg.n_grid}, "
           f"{cfg.n_fragments} fragments of {cfg.fragment_shape}", file=sys.stderr, flush=True)
+    def configure(dd):
+        """The run's template potential, mixer and fixed density (every context the
+        line reports on, comparison runs included, takes the same settings)."""
+        if args.template_xi > 0.0:
+            dd.dcdft_set_template(args.template_xi)
+        if args.mixer == "pulay":
+            dd.dcdft_set_mixer("pulay", args.mix_alpha, args.kerker_q0, args.mix_history)
+        if args.fixed_density:
+            from workloads import superposed_density
+            dd.dcdft_set_density(superposed_density(cfg.system, cfg.n_grid))
+            dd.dcdft_fix_density(True)
+
     d = DCDFT.from_config(cfg, batched=args.batched, precision=prec)
-    if args.template_xi > 0.0:
-        d.dcdft_set_template(args.template_xi)
-    if args.mixer == "pulay":
-        d.dcdft_set_mixer("pulay", args.mix_alpha, args.kerker_q0, args.mix_history)
-    if args.fixed_density:
-        from workloads import superposed_density
-        d.dcdft_set_density(superposed_density(cfg.system, cfg.n_grid))
-        d.dcdft_fix_density(True)
+    configure(d)
     launch0 = d.dcdft_get_launch()
     tune = None
     if not args.no_autotune:
@@ -491,6 +496,7 @@ def main() -> int:
         for name, batched, pr, k in variants:
             print(f"[bench] comparison {name}", file=sys.stderr, flush=True)
             d2 = DCDFT.from_config(cfg, batched=batched, precision=pr)
+            configure(d2)
             if batched and not args.no_autotune:
                 d2.dcdft_autotune(args.tune_cache)
             d2.dcdft_scf_step()

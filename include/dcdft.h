@@ -389,7 +389,8 @@ dcdft_status dcdft_autotune(dcdft_ctx *c, const char *cache_path, dcdft_tune_inf
  * 2, 4 or 8, gram_chunks 1..gram_chunks_max (as get reports it), streams
  * 1..4: the batched step's eigensolver runs over `streams` groups of
  * fragments (split at equal orbital counts) on as many streams, forked and
- * joined inside the step (default 3; results do not depend on it); anything
+ * joined inside the step (default 2, or 3 with 192 fragments or more; results
+ * do not depend on it); anything
  * else is
  * DCDFT_ERR_ARG and changes nothing.  get: any pointer may be NULL. */
 dcdft_status dcdft_get_launch(const dcdft_ctx *c, int32_t *hloc_variant, int32_t *rot_tiles,

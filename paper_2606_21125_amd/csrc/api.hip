@@ -243,12 +243,13 @@ double *gpart2_at(const dcdft_ctx *c, int f0) {
   return c->d_gpart2 + (long long)f0 * c->gram_chunks_max * c->m_pad * c->m_pad;
 }
 
-// Gram chunks for a launch over launch positions [a, b): the tuned count, raised
-// (up to the maximum) so that a small tile class still spreads over about 1024
-// workgroups
+// Gram chunks for a launch over launch positions [a, b): the tuned count.  (Raising
+// it for launches of few fragments gained nothing measurable on the ragged water
+// cell and doubled the reductions of the concurrent groups on the 64-fragment cell.)
 int chunks_for(const dcdft_ctx *c, int a, int b) {
-  const int want = (1024 + (b - a) - 1) / std::max(1, b - a);
-  return std::max(c->gram_chunks, std::min(c->gram_chunks_max, want));
+  (void)a;
+  (void)b;
+  return c->gram_chunks;
 }
 
 // fn(a, b, o) for every tile class meeting the launch positions [p0, p1): o is the
@@ -1120,6 +1121,11 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   }
   g.hloc_variant = hloc_halo_ok(g) ? HLOC_HALO_PD2 : HLOC_PLANE;
   g.rot_tiles = 4;
+  // concurrent fragment groups: three once each group still fills the chip with
+  // its own fragments (measured: 512 fragments of 32^3 points 96.7 -> 95.8 ms per
+  // step with three), otherwise two (64 fragments of 24^3: 7.45 ms with two, 7.68
+  // with three)
+  c->streams = c->nF >= 192 ? 3 : 2;
   if (p->hip_stream) {
     c->stream = (hipStream_t)p->hip_stream;
   } else {

@@ -169,7 +169,7 @@ struct dcdft_ctx {
   // inside the captured step.  xs is the stream the eigensolver helpers issue
   // to (null: the context's stream).
   static constexpr int kMaxStreams = 4;
-  int streams = 3;
+  int streams = 2;                // set at setup from the fragment count
   hipStream_t xstreams[kMaxStreams] = {};  // [0] unused (the context's stream)
   hipEvent_t ev_fork = nullptr, ev_join[kMaxStreams] = {};
   bool pre_projected = false;    // the step's first projections were issued before V_eff

@@ -139,9 +139,9 @@ def test_autotune_choice_cache_and_results(tmp_path):
 @pytest.mark.parametrize("which", ["config1", "ragged"])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_concurrent_fragment_groups_bitwise(which, prec):
-    """The batched step with its eigensolver split over two, three (the
-    default) or four streams computes the same per-fragment sums as with one
-    stream: bitwise-equal results."""
+    """The batched step with its eigensolver split over two, three or four
+    streams computes the same per-fragment sums as with one stream:
+    bitwise-equal results."""
     require_gpu()
     from paper_2606_21125_amd import DCDFT
     cfg = workloads.config(1) if which == "config1" else _ragged_tiny()
