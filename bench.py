@@ -337,7 +337,7 @@ def main() -> int:
         args.no_compare = True
         args.no_cpu_baseline = True
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the SCF step runs on one GPU per process (no multi-GPU path); --gpus must be 1"}))
         return 2
 
     import torch
