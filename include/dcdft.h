@@ -301,6 +301,29 @@ dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, cons
                                int32_t m, int32_t prec, const double *veff, double *energy,
                                void *grad_psi, double *grad_v);
 
+/* The band-energy functional of every fragment in one call, with its gradients
+ * (Eq. (5) for each H^alpha, V_eff^alpha of the last step):
+ *   E = sum_alpha sum_i f_i <psi_i^alpha|H^alpha|psi_i^alpha>  (inner products with dV),
+ *   grad_psi[B][l] = 2 f_B dV (H^alpha psi_B)(l),
+ *   grad_v[G] = dV sum over the fragment boxes containing global point G of
+ *               sum_i f_i psi_i^alpha(l)^2, l the local point of G in the box,
+ * grad_v being the derivative with respect to the local potential on the global
+ * grid, which enters every H^alpha through V_eff^alpha.  psi, grad_psi: device
+ * [M_tot][n] of double (prec 0) or float (prec 1): the vectors of every fragment
+ * in fragment order (fragment alpha's nstate_frag[alpha] vectors after those of
+ * the fragments before it; M_tot their sum); f: device double [M_tot]; energy:
+ * device double [1]; grad_v: device double [Nx Ny Nz], x fastest.  Any of energy,
+ * grad_psi, grad_v may be NULL.  H psi is formed in grad_psi when given (and
+ * scaled there to the gradient), else in the context's search-direction array,
+ * which holds it when prec's element is no wider than the context's.  Nothing is
+ * allocated; the call shares scratch with dcdft_scf_step, so both go on the
+ * context's stream (never concurrently).  Inputs must be complete when the call
+ * is made; outputs are complete when it returns.  Errors: ARG (NULL psi or f,
+ * prec, grad_psi aliasing psi, an FP64 call on a mixed-precision context without
+ * grad_psi, projector LDS of that precision), HIP. */
+dcdft_status dcdft_band_energy_all(dcdft_ctx *c, const void *psi, const double *f, int32_t prec,
+                                   double *energy, void *grad_psi, double *grad_v);
+
 /* dcdft_band_energy for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * arguments, results and errors, with H psi formed in a static 8 MiB device array

@@ -1161,11 +1161,22 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
     if (e == hipSuccess) e = upload(c, &c->d_moff, c->moff);
     if (e == hipSuccess) e = upload(c, &c->d_perm, c->perm);
     if (e == hipSuccess) e = upload(c, &c->d_band_frag, band_frag);
+    c->nmoff.assign(c->nF + 1, 0);
+    for (int f = 0; f < c->nF; ++f) c->nmoff[f + 1] = c->nmoff[f] + c->m[f];
+    std::vector<int> nband(c->M_tot), ident(c->nF);
+    for (int f = 0; f < c->nF; ++f) {
+      ident[f] = f;
+      for (long long B = c->nmoff[f]; B < c->nmoff[f + 1]; ++B) nband[B] = f;
+    }
+    if (e == hipSuccess) e = upload(c, &c->d_nmoff, c->nmoff);
+    if (e == hipSuccess) e = upload(c, &c->d_nband, nband);
+    if (e == hipSuccess) e = upload(c, &c->d_ident, ident);
     if (e != hipSuccess) {
       c->last_error = "table upload failed";
       return fail(DCDFT_ERR_HIP);
     }
   }
+  ALLOC(c->d_eb_all, std::max(1LL, c->M_tot));
   const bool mixed = c->precision == DCDFT_PREC_MIXED;
   c->elem = mixed ? sizeof(float) : sizeof(double);
   {
@@ -1944,6 +1955,30 @@ void band_energy_ext(dcdft_ctx *c, const dcdft_ctx::ExtScratch &X, int frag, con
   if (grad_v) launch_grad_v<T>(g, m, psi, f, grad_v, c->stream);
 }
 
+// Band energy and gradients of caller arrays holding every fragment's vectors
+// in fragment order: one launch of each kernel over all fragments (stencil,
+// projection, application, per-band terms, global dE/dV_loc).  H psi goes into hg
+// (grad_psi, scaled in place to the gradient, or scratch).
+template <typename T>
+void band_energy_all(dcdft_ctx *c, const T *psi, const double *f, double *energy, T *hg,
+                     bool scale, double *grad_v) {
+  const Geo &g = c->geo;
+  KBTables kb = c->kb();
+  hipStream_t s = c->stream;
+  OrbSet o = c->orbset(0, c->nF);
+  o.moff = c->d_nmoff;
+  o.band_frag = c->d_nband;
+  o.perm = c->d_ident;
+  o.h_moff = c->nmoff.data();
+  o.row_pad = 0;
+  launch_hloc<T>(g, o, 0, c->nF, c->d_veff, veff_t<T>(c), psi, hg, s);
+  launch_kb_project<T>(g, o, kb, 0, c->nF, psi, c->d_C, c->d_cpart, s);
+  launch_kb_apply<T>(g, o, kb, 0, c->nF, c->d_C, hg, s);
+  launch_band_terms_inplace<T>(g, (int)c->M_tot, psi, hg, f, c->d_eb_all, energy, scale ? 1 : 0,
+                               s);
+  if (grad_v) launch_grad_v_all<T>(g, c->d_nmoff, c->d_m, psi, f, grad_v, s);
+}
+
 dcdft_status check_ext_args(dcdft_ctx *c, int frag, int m, int prec) {
   if (frag < 0 || frag >= c->nF)
     return set_err(c, DCDFT_ERR_ARG, fmt("fragment %d out of range", frag));
@@ -1990,6 +2025,41 @@ dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, cons
   else
     band_energy_ext<double>(c, c->ext, frag, (const double *)psi, f, m, veff, energy,
                             (double *)grad_psi, grad_v);
+  return finish_ext(c);
+}
+
+dcdft_status dcdft_band_energy_all(dcdft_ctx *c, const void *psi, const double *f,
+                                   int32_t prec, double *energy, void *grad_psi,
+                                   double *grad_v) {
+  if (!c || !psi || !f) return set_err(c, DCDFT_ERR_ARG, "NULL argument");
+  if (prec != DCDFT_PREC_FP64 && prec != DCDFT_PREC_MIXED)
+    return set_err(c, DCDFT_ERR_ARG, "prec must be 0 (double) or 1 (float)");
+  if (grad_psi && grad_psi == psi) return set_err(c, DCDFT_ERR_ARG, "grad_psi may not alias psi");
+  const size_t elem = prec == DCDFT_PREC_MIXED ? sizeof(float) : sizeof(double);
+  if (!grad_psi && elem > c->elem)
+    return set_err(c, DCDFT_ERR_ARG,
+                   "an FP64 call on a mixed-precision context needs grad_psi (it holds H psi)");
+  if (elem != c->elem) {
+    // the projector kernels of the other precision must fit their LDS (setup
+    // checked the context's own precision only)
+    const int rr = c->RY ? c->RY * c->RZ : region_rows(c->geo.nl[0]);
+    const size_t need =
+        std::max(kb_lds_bytes(c->geo, c->KS, rr, c->RP, c->tiles, elem, true),
+                 kb_lds_bytes(c->geo, c->KS, rr, c->RP, c->tiles, elem, false));
+    if (need > 65536)
+      return set_err(c, DCDFT_ERR_ARG,
+                     fmt("the projector kernels in this precision would need %zu bytes of LDS "
+                         "(at most 65536)", need));
+  }
+  if (c->M_tot < 1) return set_err(c, DCDFT_ERR_ARG, "no orbitals");
+  if (prec == DCDFT_PREC_MIXED)
+    band_energy_all<float>(c, (const float *)psi, f, energy,
+                           grad_psi ? (float *)grad_psi : (float *)c->d_q, grad_psi != nullptr,
+                           grad_v);
+  else
+    band_energy_all<double>(c, (const double *)psi, f, energy,
+                            grad_psi ? (double *)grad_psi : (double *)c->d_q,
+                            grad_psi != nullptr, grad_v);
   return finish_ext(c);
 }
 

@@ -190,6 +190,12 @@ struct dcdft_ctx {
   int *d_m = nullptr, *d_perm = nullptr;
   long long *d_moff = nullptr;
   int *d_band_frag = nullptr;
+  // the same tables in fragment order (bands of fragment f after those of the
+  // fragments before it), for calls on caller arrays of every fragment
+  std::vector<long long> nmoff;      // [F + 1]
+  long long *d_nmoff = nullptr;
+  int *d_nband = nullptr, *d_ident = nullptr;
+  double *d_eb_all = nullptr;        // [M_tot] per-band energy terms
   // KB
   int n_pairs = 0;
   int *d_A = nullptr, *d_pair_first = nullptr;
@@ -340,6 +346,15 @@ void launch_band_energy_terms(const Geo &g, int nb, const T *psi, const T *hpsi,
                               double *eb, double *energy, int accumulate, T *grad_psi,
                               hipStream_t s);
 // grad_v(l) = dV sum_B f_B psi_B(l)^2 over nb bands
+// Per-band terms of the band energy with H psi given in hg (replaced in place by
+// 2 f dV H psi when scale is set); energy = sum of the band terms in band order.
+template <typename T>
+void launch_band_terms_inplace(const Geo &g, int nb, const T *psi, T *hg, const double *f,
+                               double *eb, double *energy, int scale, hipStream_t s);
+// dE/dV_loc on the global grid [Ng] for bands in fragment order (moff, m).
+template <typename T>
+void launch_grad_v_all(const Geo &g, const long long *moff, const int *m, const T *psi,
+                       const double *f, double *grad_v, hipStream_t s);
 template <typename T>
 void launch_grad_v(const Geo &g, int nb, const T *psi, const double *f, double *grad_v,
                    hipStream_t s);

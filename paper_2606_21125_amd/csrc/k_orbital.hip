@@ -900,6 +900,82 @@ __global__ void __launch_bounds__(256) k_band_energy_terms(Geo g, const T *__res
   if (threadIdx.x == 0) eb[B] = f[B] * g.dv * acc;
 }
 
+// The same per band with H psi given in hg and, when scale is set, replaced in
+// place by the gradient 2 f_B dV H psi_B (each value read, then written, by the
+// same thread).
+template <typename T>
+__global__ void __launch_bounds__(256) k_band_terms_inplace(Geo g, const T *__restrict__ psi,
+                                                            T *hg, const double *__restrict__ f,
+                                                            double *__restrict__ eb, int scale) {
+  __shared__ double red[16];
+  const long long B = blockIdx.x;
+  const T *pb = psi + B * (long long)g.n;
+  T *hb = hg + B * (long long)g.n;
+  double acc = 0.0;
+  const double s = 2.0 * f[B] * g.dv;
+  for (int l = threadIdx.x; l < g.n; l += blockDim.x) {
+    const double h = (double)hb[l];
+    acc += (double)pb[l] * h;
+    if (scale) hb[l] = (T)(s * h);
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) eb[B] = f[B] * g.dv * acc;
+}
+
+// dE/dV_loc on the global grid for the orbitals of every fragment: at global
+// point G, dV sum over the fragment boxes that contain G (fragments in z, y, x
+// order of their indices along each axis) of sum_i f_i psi_i(l)^2, l the local
+// point of G in that box.  moff, m: band offsets and counts in fragment order.
+template <typename T>
+__global__ void __launch_bounds__(256) k_grad_v_all(Geo g, const long long *__restrict__ moff,
+                                                    const int *__restrict__ m,
+                                                    const T *__restrict__ psi,
+                                                    const double *__restrict__ f,
+                                                    double *__restrict__ gv) {
+  const long long G = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (G >= g.Ng) return;
+  const int gc[3] = {(int)(G % g.N[0]), (int)((G / g.N[0]) % g.N[1]),
+                     (int)(G / ((long long)g.N[0] * g.N[1]))};
+  // per axis: the fragment indices whose box covers the coordinate, and the local
+  // coordinate in each (a box holds a point once: n_core + 2 b <= N)
+  int fa[3][7], la[3][7], na[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    na[d] = 0;
+    const int kmax = min(3, (g.b[d] + g.nc[d] - 1) / g.nc[d]);
+    const int a0 = gc[d] / g.nc[d];
+    for (int da = -kmax; da <= kmax; ++da) {
+      int a = (a0 + da) % g.F[d];
+      if (a < 0) a += g.F[d];
+      bool dup = false;
+      for (int k = 0; k < na[d]; ++k) dup |= fa[d][k] == a;
+      if (dup) continue;
+      int l = (gc[d] - (a * g.nc[d] - g.b[d])) % g.N[d];
+      if (l < 0) l += g.N[d];
+      if (l < g.nl[d]) {
+        fa[d][na[d]] = a;
+        la[d][na[d]] = l;
+        ++na[d];
+      }
+    }
+  }
+  double acc = 0.0;
+  for (int kz = 0; kz < na[2]; ++kz)
+    for (int ky = 0; ky < na[1]; ++ky)
+      for (int kx = 0; kx < na[0]; ++kx) {
+        const int fr = fa[0][kx] + g.F[0] * (fa[1][ky] + g.F[1] * fa[2][kz]);
+        const int l = la[0][kx] + g.nl[0] * (la[1][ky] + g.nl[1] * la[2][kz]);
+        const long long b0 = moff[fr], b1 = b0 + m[fr];
+        double s = 0.0;
+        for (long long B = b0; B < b1; ++B) {
+          const double v = (double)psi[B * g.n + l];
+          s += f[B] * v * v;
+        }
+        acc += s;
+      }
+  gv[G] = g.dv * acc;
+}
+
 // energy = sum eb (accumulate: energy += sum eb, for a later chunk of bands)
 __global__ void __launch_bounds__(64) k_band_energy_sum(int nb, const double *__restrict__ eb,
                                                         double *__restrict__ energy,
@@ -1149,6 +1225,23 @@ void launch_band_energy_terms(const Geo &g, int nb, const T *psi, const T *hpsi,
 }
 
 template <typename T>
+void launch_band_terms_inplace(const Geo &g, int nb, const T *psi, T *hg, const double *f,
+                               double *eb, double *energy, int scale, hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_band_terms_inplace<T>, dim3(nb), dim3(256), 0, s, g, psi, hg, f, eb,
+                     scale);
+  if (energy)
+    hipLaunchKernelGGL(k_band_energy_sum, dim3(1), dim3(64), 0, s, nb, eb, energy, 0);
+}
+
+template <typename T>
+void launch_grad_v_all(const Geo &g, const long long *moff, const int *m, const T *psi,
+                       const double *f, double *grad_v, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_v_all<T>, dim3((unsigned)((g.Ng + 255) / 256)), dim3(256), 0, s, g,
+                     moff, m, psi, f, grad_v);
+}
+
+template <typename T>
 void launch_grad_v(const Geo &g, int nb, const T *psi, const double *f, double *grad_v,
                    hipStream_t s) {
   if (nb <= 0) return;
@@ -1177,7 +1270,11 @@ void launch_single_layout(int nf, int frag, int mm, int *m, long long *moff, int
                                             const double *, double *, double *, int, T *,     \
                                             hipStream_t);                                     \
   template void launch_grad_v<T>(const Geo &, int, const T *, const double *, double *,       \
-                                 hipStream_t);
+                                 hipStream_t);                                                \
+  template void launch_band_terms_inplace<T>(const Geo &, int, const T *, T *, const double *, \
+                                             double *, double *, int, hipStream_t);           \
+  template void launch_grad_v_all<T>(const Geo &, const long long *, const int *, const T *,   \
+                                     const double *, double *, hipStream_t);
 DCDFT_INSTANTIATE(double)
 DCDFT_INSTANTIATE(float)
 #undef DCDFT_INSTANTIATE

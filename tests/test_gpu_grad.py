@@ -104,3 +104,132 @@ def test_potential_gradient_is_the_core_density():
             f_ = o.frags[frag]
             core_rho = rho[f_.global_index[f_.core_mask]]
             assert np.abs(gv[f_.core_mask] - core_rho).max() <= 1e-12 * core_rho.max()
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_band_energy_of_every_fragment_in_one_call(dtype):
+    """dcdft_band_energy_all on the 64-atom system (8 fragments, V_eff of setup):
+    E, dE/dpsi and the global dE/dV_loc against the oracle's per-fragment analytic
+    formulas (dE/dV_loc summed over the boxes that contain each grid point),
+    against the per-fragment calls, the energy-only call (H psi in the context's
+    scratch) equal to the full one, and an SCF step after the call equal, bitwise,
+    to one without it (the call only uses scratch the step rewrites)."""
+    require_gpu()
+    import torch
+    from paper_2606_21125_amd import DCDFT, PREC_FP64, PREC_MIXED
+    cfg, o, d = _setup(4)
+    tdt = getattr(torch, dtype)
+    prec = PREC_FP64 if dtype == "float64" else PREC_MIXED
+    rng = np.random.default_rng(33)
+    v_h = np.zeros_like(o.rho_in)
+    ms = [int(v) for v in cfg.nstate_frag]
+    psis = [rng.normal(size=(m,) + o.frags[a].shape) * 0.05 for a, m in enumerate(ms)]
+    fs = [rng.uniform(0.2, 2.0, size=m) for m in ms]
+    e_ref, gp_ref = 0.0, []
+    gv_ref = np.zeros(o.rho_in.size)
+    for a in range(cfg.n_fragments):
+        shape = o.frags[a].shape
+        veff = o.veff(a, v_h).reshape(shape)
+        e_ref += oracle.band_energy(psis[a], veff, o.fproj[a], o.h, o.dv, fs[a])
+        gp, gv = oracle.band_energy_grad(psis[a], veff, o.fproj[a], o.h, o.dv, fs[a])
+        gp_ref.append(gp.reshape(ms[a], -1))
+        np.add.at(gv_ref, o.frags[a].global_index, gv.ravel())
+    gp_ref = np.concatenate(gp_ref)
+    psi = torch.tensor(np.concatenate([p.reshape(p.shape[0], -1) for p in psis]), device="cuda",
+                       dtype=tdt)
+    f = torch.tensor(np.concatenate(fs), device="cuda", dtype=torch.float64)
+    tol = 1e-12 if dtype == "float64" else 1e-5
+    with d:
+        energy = torch.empty(1, device="cuda", dtype=torch.float64)
+        gpsi = torch.empty_like(psi)
+        gv = torch.empty(o.rho_in.size, device="cuda", dtype=torch.float64)
+        d.dcdft_band_energy_all(psi, f, energy=energy, grad_psi=gpsi, grad_v=gv, prec=prec)
+        e = energy.item()
+        print(f"{dtype}: E {e:.12f} oracle {e_ref:.12f}", flush=True)
+        assert abs(e - e_ref) <= tol * abs(e_ref) * (1 if dtype == "float64" else 10)
+        gp = gpsi.double().cpu().numpy()
+        assert np.abs(gp - gp_ref).max() <= tol * np.abs(gp_ref).max()
+        assert np.abs(gv.cpu().numpy() - gv_ref).max() <= tol * np.abs(gv_ref).max()
+        # the per-fragment calls give the same values
+        off = np.concatenate([[0], np.cumsum(ms)])
+        e_sum = 0.0
+        for a in range(cfg.n_fragments):
+            ea = torch.empty(1, device="cuda", dtype=torch.float64)
+            ga = torch.empty(ms[a], o.frags[a].n, device="cuda", dtype=tdt)
+            d.dcdft_band_energy(a, psi[off[a]:off[a + 1]].contiguous(), f[off[a]:off[a + 1]],
+                                energy=ea, grad_psi=ga, prec=prec)
+            e_sum += ea.item()
+            np.testing.assert_allclose(ga.double().cpu().numpy(), gp[off[a]:off[a + 1]],
+                                       rtol=0, atol=1e-14 * np.abs(gp).max()
+                                       if dtype == "float64" else 1e-6 * np.abs(gp).max())
+        assert abs(e_sum - e) <= 1e-13 * abs(e) * (1 if dtype == "float64" else 1e6)
+        # energy alone: H psi in the context's scratch
+        e2 = torch.empty(1, device="cuda", dtype=torch.float64)
+        d.dcdft_band_energy_all(psi, f, energy=e2, prec=prec)
+        assert e2.item() == e
+        # the step after the call equals a step without it
+        s1 = d.dcdft_scf_step()
+    with DCDFT.from_config(cfg) as d2:
+        s2 = d2.dcdft_scf_step()
+    assert s1["e_total"] == s2["e_total"] and s1["mu"] == s2["mu"]
+
+
+def test_band_energy_of_every_fragment_argument_errors():
+    require_gpu()
+    import torch
+    from paper_2606_21125_amd import DCDFT, PREC_FP64, PREC_MIXED
+    from paper_2606_21125_amd.binding import DcdftError
+    cfg = workloads.config(4)
+    mt = int(np.sum(cfg.nstate_frag))
+    n = int(np.prod(cfg.fragment_shape))
+    with DCDFT.from_config(cfg, precision=PREC_MIXED) as d:
+        psi = torch.zeros(mt, n, device="cuda", dtype=torch.float64)
+        f = torch.ones(mt, device="cuda", dtype=torch.float64)
+        e = torch.empty(1, device="cuda", dtype=torch.float64)
+        # FP64 vectors on a mixed-precision context need grad_psi to hold H psi
+        with pytest.raises(DcdftError):
+            d.dcdft_band_energy_all(psi, f, energy=e, prec=PREC_FP64)
+        with pytest.raises(DcdftError):
+            d.dcdft_band_energy_all(psi, f, energy=e, grad_psi=psi, prec=PREC_FP64)
+        with pytest.raises(DcdftError):
+            d.dcdft_band_energy_all(psi, f, energy=e, grad_psi=torch.empty_like(psi), prec=7)
+        g = torch.empty_like(psi)
+        d.dcdft_band_energy_all(psi, f, energy=e, grad_psi=g, prec=PREC_FP64)
+        assert e.item() == 0.0 and float(g.abs().max()) == 0.0
+
+
+def test_band_energy_all_through_autograd():
+    """BandEnergyAll: the backward equals dcdft_band_energy_all's dE/dpsi, the
+    Euler identity sum psi . dE/dpsi = 2E holds, and central differences along
+    random directions (step 1e-2: E is quadratic in psi) match the gradient, on an FP64 and a
+    mixed-precision context with FP64 vectors."""
+    require_gpu()
+    import torch
+    from paper_2606_21125_amd import DCDFT, PREC_FP64, PREC_MIXED
+    from paper_2606_21125_amd.autograd import band_energy_all
+    cfg = workloads.config(4)
+    mt = int(np.sum(cfg.nstate_frag))
+    n = int(np.prod(cfg.fragment_shape))
+    rng = np.random.default_rng(5)
+    for cprec in (PREC_FP64, PREC_MIXED):
+        with DCDFT.from_config(cfg, precision=cprec) as d:
+            d.dcdft_scf_step()
+            psi = torch.tensor(rng.normal(size=(mt, n)) * 0.05, device="cuda",
+                               requires_grad=True)
+            f = torch.tensor(rng.uniform(0.2, 2.0, size=mt), device="cuda")
+            e = band_energy_all(d, psi, f)
+            e.backward()
+            g = torch.empty_like(psi)
+            d.dcdft_band_energy_all(psi.detach(), f, grad_psi=g, prec=PREC_FP64)
+            assert torch.equal(psi.grad, g)
+            assert abs(float((psi.detach() * psi.grad).sum()) - 2 * e.item()) <= 1e-11 * abs(e.item())
+            with torch.no_grad():
+                for _ in range(4):
+                    dp = torch.tensor(rng.normal(size=(mt, n)), device="cuda")
+                    dp /= dp.norm()
+                    # E is quadratic in psi: central differences are exact for any
+                    # step, and a large one keeps E's rounding (E ~ 1e5) out of them
+                    t = 1e-2
+                    fd = (band_energy_all(d, psi + t * dp, f) - band_energy_all(d, psi - t * dp, f)) / (2 * t)
+                    an = float((psi.grad * dp).sum())
+                    assert abs(fd.item() - an) <= 1e-6 * max(1.0, abs(an)), (fd.item(), an)
