@@ -436,9 +436,15 @@ void eigensolver_range(dcdft_ctx *c, int f0, int f1) {
   // Rayleigh-Ritz on Hs = sym(<Psi, W>) from the last sweep's re-orthonormalisation;
   // Psi' is not yet re-orthonormalised, so it is rotated by C = L^-T U at once;
   // then core weights w_i = dV sum_core psi_i^2
-  // one Jacobi launch over every class: the workgroups of one fragment each are
-  // latency-bound, so the classes run side by side rather than one after another
-  launch_syev(o, f0, f1, c->d_hs, c->d_u, c->d_eps, c->d_flags, s);
+  // one Jacobi launch over every class of the range (the workgroups, one per
+  // fragment, are latency-bound, so the classes run side by side rather than one
+  // after another), its LDS sized for the range's widest class: launch positions
+  // are sorted by tile count, so that is the class of the last one
+  if (f1 > f0) {
+    OrbSet oj = o;
+    oj.tiles = (c->m[c->perm[f1 - 1]] + 15) / 16;
+    launch_syev(oj, f0, f1, c->d_hs, c->d_u, c->d_eps, c->d_flags, s);
+  }
   by_class(c, f0, f1, [&](int a, int b, const OrbSet &oc) {
     launch_ritz_combine(oc, a, b, c->d_lin, c->d_u, c->d_bmat, s);
   });
