@@ -301,6 +301,15 @@ dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, cons
                                int32_t m, int32_t prec, const double *veff, double *energy,
                                void *grad_psi, double *grad_v);
 
+/* The backward of the band-energy functional in the argument order of the
+ * boundary's original statement: dcdft_band_energy(c, frag, psi, f, m, prec,
+ * NULL, NULL, grad_psi, grad_v), i.e. grad_psi[i][l] = 2 f_i dV (H^alpha psi_i)(l)
+ * and grad_v[l] = dV sum_i f_i psi_i(l)^2 (device double [n]) with the fragment's
+ * V_eff of the last step, Eq. (5).  Same layouts, scratch, synchronisation and
+ * errors as dcdft_band_energy. */
+dcdft_status dcdft_band_energy_bwd(dcdft_ctx *c, int32_t frag, const void *psi, const double *f,
+                                   void *grad_psi, void *grad_v, int32_t m, int32_t prec);
+
 /* The band-energy functional of every fragment in one call, with its gradients
  * (Eq. (5) for each H^alpha, V_eff^alpha of the last step):
  *   E = sum_alpha sum_i f_i <psi_i^alpha|H^alpha|psi_i^alpha>  (inner products with dV),

@@ -32,7 +32,8 @@ EXPORTED = [
     "dcdft_set_template", "dcdft_set_mixer", "dcdft_lcfo_build", "dcdft_lcfo_basis", "dcdft_lcfo_hamiltonian",
     "dcdft_lcfo_block",
     "dcdft_apply_h",
-    "dcdft_band_energy", "dcdft_band_energy_all", "dcdft_band_energy_noalloc",
+    "dcdft_band_energy", "dcdft_band_energy_bwd", "dcdft_band_energy_all",
+    "dcdft_band_energy_noalloc",
     "dcdft_kernel_timing", "dcdft_kernel_time", "dcdft_autotune",
     "dcdft_get_launch", "dcdft_set_launch",
     "dcdft_destroy",
@@ -150,6 +151,8 @@ def load_library(path: Optional[str] = None):
         "dcdft_band_energy_noalloc": ([vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32,
                                        vp, vp, vp, vp], ctypes.c_int),
         "dcdft_band_energy_all": ([vp, vp, vp, ctypes.c_int32, vp, vp, vp], ctypes.c_int),
+        "dcdft_band_energy_bwd": ([vp, ctypes.c_int32, vp, vp, vp, vp, ctypes.c_int32,
+                                   ctypes.c_int32], ctypes.c_int),
         "dcdft_kernel_timing": ([vp, ctypes.c_int32], ctypes.c_int),
         "dcdft_kernel_time": ([vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), pd, pd, pd],
                               ctypes.c_int),
@@ -491,6 +494,16 @@ class DCDFT:
                                            ctypes.c_void_p(f.data_ptr()), psi.shape[0], prec,
                                            ptr(veff), ptr(energy), ptr(grad_psi), ptr(grad_v)),
                self.ctx)
+
+    def dcdft_band_energy_bwd(self, frag: int, psi, f, grad_psi=None, grad_v=None,
+                              prec: int = PREC_FP64) -> None:
+        """The backward in the boundary's original argument order (the fragment's
+        V_eff of the last step, no energy)."""
+        ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+        _device_inputs_ready(psi)
+        _check(self._lib.dcdft_band_energy_bwd(self.ctx, frag, ctypes.c_void_p(psi.data_ptr()),
+                                               ctypes.c_void_p(f.data_ptr()), ptr(grad_psi),
+                                               ptr(grad_v), psi.shape[0], prec), self.ctx)
 
     def dcdft_band_energy_all(self, psi, f, energy=None, grad_psi=None, grad_v=None,
                               prec: int = PREC_FP64) -> None:

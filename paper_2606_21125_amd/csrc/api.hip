@@ -2034,6 +2034,12 @@ dcdft_status dcdft_band_energy(dcdft_ctx *c, int32_t frag, const void *psi, cons
   return finish_ext(c);
 }
 
+dcdft_status dcdft_band_energy_bwd(dcdft_ctx *c, int32_t frag, const void *psi, const double *f,
+                                   void *grad_psi, void *grad_v, int32_t m, int32_t prec) {
+  return dcdft_band_energy(c, frag, psi, f, m, prec, nullptr, nullptr, grad_psi,
+                           static_cast<double *>(grad_v));
+}
+
 dcdft_status dcdft_band_energy_all(dcdft_ctx *c, const void *psi, const double *f,
                                    int32_t prec, double *energy, void *grad_psi,
                                    double *grad_v) {
