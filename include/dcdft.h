@@ -433,8 +433,9 @@ dcdft_status dcdft_set_launch(dcdft_ctx *c, int32_t hloc_variant, int32_t rot_ti
 /* Release everything owned by c.  NULL-safe. */
 void dcdft_destroy(dcdft_ctx *c);
 
-/* Static string for a status code. */
-const char *dcdft_status_string(dcdft_status s);
+/* Static string for a status code (any int32 value: codes outside the
+ * dcdft_status values give "unknown status"). */
+const char *dcdft_status_string(int32_t s);
 
 /* Copy the last error message of c (or of the last failed setup if c is NULL)
  * into buf (NUL-terminated, truncated to n bytes). */

@@ -490,11 +490,13 @@ dcdft_status validate(const dcdft_params *p) {
       return set_err(nullptr, DCDFT_ERR_SHAPE,
                      fmt("n_grid[%d] = %d not divisible by num_fragment[%d] = %d", d,
                          p->n_grid[d], d, p->num_fragment[d]));
-    const int nc = p->n_grid[d] / p->num_fragment[d];
-    if (nc + 2 * p->num_rgrid_buffer[d] > p->n_grid[d])
+    // sizes in 64 bits: the inputs may be anywhere in the int32 range
+    const long long box = (long long)(p->n_grid[d] / p->num_fragment[d]) +
+                          2LL * p->num_rgrid_buffer[d];
+    if (box > p->n_grid[d])
       return set_err(nullptr, DCDFT_ERR_SHAPE,
-                     fmt("fragment box %d exceeds the grid %d on axis %d",
-                         nc + 2 * p->num_rgrid_buffer[d], p->n_grid[d], d));
+                     fmt("fragment box %lld exceeds the grid %d on axis %d", box,
+                         p->n_grid[d], d));
   }
   if (p->n_atoms < 0) return set_err(nullptr, DCDFT_ERR_ARG, "n_atoms < 0");
   if (p->n_atoms > 0 && (!p->atom_pos || !p->atom_species))
@@ -521,19 +523,32 @@ dcdft_status validate(const dcdft_params *p) {
   if (p->precision != DCDFT_PREC_FP64 && p->precision != DCDFT_PREC_MIXED)
     return set_err(nullptr, DCDFT_ERR_ARG, "precision must be DCDFT_PREC_FP64 or DCDFT_PREC_MIXED");
   if (p->batched != 0 && p->batched != 1) return set_err(nullptr, DCDFT_ERR_ARG, "batched not 0/1");
-  const int nF = p->num_fragment[0] * p->num_fragment[1] * p->num_fragment[2];
-  for (int f = 0; f < nF; ++f) {
-    const int m = p->nstate_frag ? p->nstate_frag[f] : p->nstate_frag_uniform;
-    if (m < 1 || m > kMaxOrb)
-      return set_err(nullptr, DCDFT_ERR_ARG,
-                     fmt("nstate_frag of fragment %d is %d; supported range 1..%d", f, m, kMaxOrb));
+  // fragment count and box size multiplied axis by axis, each partial product
+  // checked before the next factor (every factor is below 2^31)
+  long long nF = 1, n = 1;
+  for (int d = 0; d < 3; ++d) {
+    nF *= p->num_fragment[d];
+    if (nF > (1LL << 24))
+      return set_err(nullptr, DCDFT_ERR_ARG, "more than 2^24 fragments");
+    n *= (long long)(p->n_grid[d] / p->num_fragment[d]) + 2LL * p->num_rgrid_buffer[d];
+    if (n >= (1LL << 24)) return set_err(nullptr, DCDFT_ERR_ARG, "fragment box >= 2^24 points");
   }
-  long long n = 1;
-  for (int d = 0; d < 3; ++d)
-    n *= p->n_grid[d] / p->num_fragment[d] + 2 * p->num_rgrid_buffer[d];
-  if (n >= (1LL << 24)) return set_err(nullptr, DCDFT_ERR_ARG, "fragment box >= 2^24 points");
-  const int plane = (p->n_grid[0] / p->num_fragment[0] + 2 * p->num_rgrid_buffer[0]) *
-                    (p->n_grid[1] / p->num_fragment[1] + 2 * p->num_rgrid_buffer[1]);
+  if (p->nstate_frag) {
+    for (long long f = 0; f < nF; ++f) {
+      const int m = p->nstate_frag[f];
+      if (m < 1 || m > kMaxOrb)
+        return set_err(nullptr, DCDFT_ERR_ARG,
+                       fmt("nstate_frag of fragment %lld is %d; supported range 1..%d", f, m,
+                           kMaxOrb));
+    }
+  } else if (p->nstate_frag_uniform < 1 || p->nstate_frag_uniform > kMaxOrb) {
+    return set_err(nullptr, DCDFT_ERR_ARG,
+                   fmt("nstate_frag_uniform is %d; supported range 1..%d",
+                       p->nstate_frag_uniform, kMaxOrb));
+  }
+  const long long plane =
+      ((long long)(p->n_grid[0] / p->num_fragment[0]) + 2LL * p->num_rgrid_buffer[0]) *
+      ((long long)(p->n_grid[1] / p->num_fragment[1]) + 2LL * p->num_rgrid_buffer[1]);
   if (plane > 1024)
     return set_err(nullptr, DCDFT_ERR_ARG, "fragment x-y plane larger than 1024 points");
   return DCDFT_OK;
@@ -981,7 +996,8 @@ dcdft_status capture_step(dcdft_ctx *c, int k) {
 
 extern "C" {
 
-const char *dcdft_status_string(dcdft_status s) {
+const char *dcdft_status_string(int32_t s) {
+  // an int: codes outside the enumeration's range are valid input here
   switch (s) {
     case DCDFT_OK: return "ok";
     case DCDFT_ERR_ARG: return "invalid argument";
