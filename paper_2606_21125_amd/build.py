@@ -19,6 +19,9 @@ LIB = os.path.join(HERE, "libdcdft.so")
 ARCH = os.environ.get("DCDFT_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+ROCM_LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(HIPCC))), "lib")
+# roctx ranges of the runtime (marker traces of rocprofv3)
+LIBS = [f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx"]
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument", "-Wno-unused-result"]
@@ -74,7 +77,7 @@ def build_host_sanitized() -> str:
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed on api.hip:\n{res.stderr[-6000:]}")
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", api_obj, *objs, *SAN_FLAGS,
-           "-o", SAN_LIB]
+           *LIBS, "-o", SAN_LIB]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr[-6000:]}")
@@ -87,7 +90,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, *LIBS, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr[-6000:]}")

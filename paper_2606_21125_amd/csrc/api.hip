@@ -17,6 +17,8 @@
 #include <mutex>
 #include <new>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "dcdft_internal.h"
 
 using namespace dcdft;
@@ -167,6 +169,16 @@ hipEvent_t pool_event(dcdft_ctx *c) {
 }
 
 // Bracket one launch of a timed kernel family with events.
+// roctx range for the length of a host call (profiler timelines: with
+// rocprofv3 --marker-trace the SCF steps, their phases and the autotuner show
+// as named ranges and marks beside the kernels)
+struct RoctxRange {
+  explicit RoctxRange(const char *name) { roctxRangePushA(name); }
+  ~RoctxRange() { roctxRangePop(); }
+  RoctxRange(const RoctxRange &) = delete;
+  RoctxRange &operator=(const RoctxRange &) = delete;
+};
+
 struct Timed {
   dcdft_ctx *c;
   dcdft_ctx::PendingTimer t;
@@ -1346,6 +1358,7 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
 
 dcdft_status dcdft_scf_step(dcdft_ctx *c, dcdft_scf_info *info) {
   if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  RoctxRange range("dcdft_scf_step");   // until the step's results are on the host
   hipStream_t s = c->stream;
   // Timed steps run eagerly: their per-launch event records are host decisions.
   const bool graph = c->batched && c->use_graph && !c->timing;
@@ -1356,7 +1369,11 @@ dcdft_status dcdft_scf_step(dcdft_ctx *c, dcdft_scf_info *info) {
     if (st != DCDFT_OK) return st;
   }
   HIPTRY(c, hipEventRecord(c->ev0, s));
+  static const char *const kPhaseName[3] = {"dcdft phase: potentials",
+                                            "dcdft phase: fragment eigensolvers",
+                                            "dcdft phase: Fermi level, densities, mixing"};
   for (int ph = 0; ph < 3; ++ph) {
+    roctxMarkA(kPhaseName[ph]);
     HIPTRY(c, hipEventRecord(c->ev_ph[ph], s));
     if (graph) HIPTRY(c, hipGraphLaunch(c->graph_exec[slot][ph], s));
     else enqueue_phase(c, ph);
@@ -2316,6 +2333,7 @@ extern "C" {
 
 dcdft_status dcdft_autotune(dcdft_ctx *c, const char *cache_path, dcdft_tune_info *out) {
   if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  RoctxRange range("dcdft_autotune");
   dcdft_tune_info info;
   std::memset(&info, 0, sizeof(info));
   for (double &v : info.ms_hloc) v = -1.0;
