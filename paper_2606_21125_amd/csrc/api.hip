@@ -861,9 +861,17 @@ namespace {
 int step_groups(const dcdft_ctx *c, int *bound) {
   const int G = (c->batched && !c->timing) ? std::min(c->streams, c->nF) : 1;
   bound[0] = 0;
+  // groups of equal padded matrix-core work, sum of m (16 tiles): a fragment's
+  // Gram and rotation products scale with its orbitals times its padded count
+  // (water: 94.8 against 95.7 ms per step when split at equal orbital counts)
+  std::vector<long long> cw(c->nF + 1, 0);
+  for (int q = 0; q < c->nF; ++q) {
+    const int mq = c->m[c->perm[q]];
+    cw[q + 1] = cw[q] + (long long)mq * (16 * ((mq + 15) / 16));
+  }
   for (int q = 1; q < G; ++q) {
     int h = bound[q - 1] + 1;
-    while (h < c->nF - (G - q) && (long long)G * c->pmoff[h] < (long long)q * c->M_tot) ++h;
+    while (h < c->nF - (G - q) && (long long)G * cw[h] < (long long)q * cw[c->nF]) ++h;
     bound[q] = h;
   }
   bound[G] = c->nF;

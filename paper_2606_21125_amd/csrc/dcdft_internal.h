@@ -164,7 +164,7 @@ struct dcdft_ctx {
   bool own_stream = false;
   int device = 0;                  // the HIP device current at setup
   // Concurrent fragment groups of the batched step: the eigensolver runs over
-  // `streams` groups of fragments (split at equal orbital counts), group g on
+  // `streams` groups of fragments (split at equal padded matrix-core work), group g on
   // stream g (group 0 on the context's stream), forked and joined by events
   // inside the captured step.  xs is the stream the eigensolver helpers issue
   // to (null: the context's stream).
