@@ -255,13 +255,15 @@ double *gpart2_at(const dcdft_ctx *c, int f0) {
   return c->d_gpart2 + (long long)f0 * c->gram_chunks_max * c->m_pad * c->m_pad;
 }
 
-// Gram chunks for a launch over launch positions [a, b): the tuned count.  (Raising
-// it for launches of few fragments gained nothing measurable on the ragged water
-// cell and doubled the reductions of the concurrent groups on the 64-fragment cell.)
+// Gram chunks for a launch over launch positions [a, b): the tuned count in the
+// batched step.  (Raising it for launches of few fragments gained nothing
+// measurable on the ragged water cell and doubled the reductions of the
+// concurrent groups on the 64-fragment cell.)  The plain step launches one
+// fragment at a time with the GPU to itself: the largest count.
 int chunks_for(const dcdft_ctx *c, int a, int b) {
   (void)a;
   (void)b;
-  return c->gram_chunks;
+  return c->batched ? c->gram_chunks : c->gram_chunks_max;
 }
 
 // fn(a, b, o) for every tile class meeting the launch positions [p0, p1): o is the
