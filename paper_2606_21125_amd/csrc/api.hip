@@ -1182,6 +1182,9 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   auto fail = [&](dcdft_status s) {
     g_setup_error = c->last_error;
     dcdft_destroy(c);
+    // a failed allocation stays in the runtime's last-error slot, where a later
+    // context's error check would find it: clear it
+    (void)hipGetLastError();
     return s;
   };
   st = build_and_upload(c, p);
