@@ -168,7 +168,12 @@ hipEvent_t pool_event(dcdft_ctx *c) {
   return e;
 }
 
-// Bracket one launch of a timed kernel family with events.
+// The runtime's last-error slot is per thread and sticky until read: errors that
+// other code in the process left there (a failed allocation of a tensor, of an
+// earlier context) would otherwise be reported by the launch checks of the next
+// call that issues work.  Such calls clear it first.
+inline void clear_stale_error() { (void)hipGetLastError(); }
+
 // roctx range for the length of a host call (profiler timelines: with
 // rocprofv3 --marker-trace the SCF steps, their phases and the autotuner show
 // as named ranges and marks beside the kernels)
@@ -179,6 +184,7 @@ struct RoctxRange {
   RoctxRange &operator=(const RoctxRange &) = delete;
 };
 
+// Bracket one launch of a timed kernel family with events.
 struct Timed {
   dcdft_ctx *c;
   dcdft_ctx::PendingTimer t;
@@ -1371,6 +1377,7 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
 
 dcdft_status dcdft_scf_step(dcdft_ctx *c, dcdft_scf_info *info) {
   if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  clear_stale_error();
   RoctxRange range("dcdft_scf_step");   // until the step's results are on the host
   hipStream_t s = c->stream;
   // Timed steps run eagerly: their per-launch event records are host decisions.
@@ -1566,6 +1573,7 @@ dcdft_status dcdft_set_orbitals(dcdft_ctx *c, int32_t frag, const double *host, 
 
 dcdft_status dcdft_set_density(dcdft_ctx *c, const double *rho_tot_in, const double *rho_frag_in) {
   if (!c || !rho_tot_in) return set_err(c, DCDFT_ERR_ARG, "NULL argument");
+  clear_stale_error();
   const Geo &g = c->geo;
   for (long long i = 0; i < g.Ng; ++i)
     if (!std::isfinite(rho_tot_in[i])) return set_err(c, DCDFT_ERR_NAN, "non-finite density");
@@ -1609,6 +1617,7 @@ dcdft_status dcdft_set_density(dcdft_ctx *c, const double *rho_tot_in, const dou
 
 dcdft_status dcdft_fix_density(dcdft_ctx *c, int32_t fixed) {
   if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  clear_stale_error();
   if (fixed != 0 && fixed != 1) return set_err(c, DCDFT_ERR_ARG, "fixed must be 0 or 1");
   drop_graph(c);  // the step's launch sequence changes; re-captured on the next step
   c->fixed_density = fixed != 0;
@@ -1628,6 +1637,7 @@ dcdft_status dcdft_fix_density(dcdft_ctx *c, int32_t fixed) {
 
 dcdft_status dcdft_set_template(dcdft_ctx *c, double xi) {
   if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  clear_stale_error();
   if (!(xi >= 0.0) || !std::isfinite(xi))
     return set_err(c, DCDFT_ERR_ARG, fmt("xi = %g: must be finite and >= 0", xi));
   drop_graph(c);  // xi is a kernel argument of the captured V_eff launch
@@ -1744,6 +1754,7 @@ static void lcfo_pair_tables(const dcdft_ctx *c, std::vector<int> &pairs,
 dcdft_status dcdft_lcfo_build(dcdft_ctx *c, double eps_cut, double lambda_cut,
                               dcdft_lcfo_info *info) {
   if (!c) return set_err(nullptr, DCDFT_ERR_ARG, "ctx is NULL");
+  clear_stale_error();
   if (!std::isfinite(eps_cut) || !std::isfinite(lambda_cut) || !(lambda_cut > 0.0))
     return set_err(c, DCDFT_ERR_ARG, "eps_cut must be finite and lambda_cut finite and > 0");
   if (c->iter < 1) return set_err(c, DCDFT_ERR_ARG, "no eigenpairs yet: run dcdft_scf_step first");
@@ -2032,6 +2043,7 @@ void band_energy_all(dcdft_ctx *c, const T *psi, const double *f, double *energy
 }
 
 dcdft_status check_ext_args(dcdft_ctx *c, int frag, int m, int prec) {
+  clear_stale_error();
   if (frag < 0 || frag >= c->nF)
     return set_err(c, DCDFT_ERR_ARG, fmt("fragment %d out of range", frag));
   if (m < 0) return set_err(c, DCDFT_ERR_ARG, "m < 0");
@@ -2090,6 +2102,7 @@ dcdft_status dcdft_band_energy_all(dcdft_ctx *c, const void *psi, const double *
                                    int32_t prec, double *energy, void *grad_psi,
                                    double *grad_v) {
   if (!c || !psi || !f) return set_err(c, DCDFT_ERR_ARG, "NULL argument");
+  clear_stale_error();
   if (prec != DCDFT_PREC_FP64 && prec != DCDFT_PREC_MIXED)
     return set_err(c, DCDFT_ERR_ARG, "prec must be 0 (double) or 1 (float)");
   if (grad_psi && grad_psi == psi) return set_err(c, DCDFT_ERR_ARG, "grad_psi may not alias psi");

@@ -3,11 +3,19 @@ orbitals each needs five FP64 orbital arrays of 86 GB, more than one GPU holds.
 Setup must return the status (not crash), free what it allocated, and leave the
 runtime usable: a small context set up afterwards runs a step and matches one set
 up before (the failed allocation must not surface as an error of the next
-context)."""
+context).
+
+Also here: an error that other code of the process left in the runtime's
+per-thread last-error slot (an impossible hipMalloc through the same HIP
+runtime, a documented error return) is not reported by the library's next step,
+H psi or density call; their results equal those of a clean run."""
+import ctypes
+
 import numpy as np
 import pytest
 
 from tests.gpu_common import require_gpu
+from tests.helpers import tiny_config
 from workloads.systems import RunConfig, Species, System
 import workloads
 
@@ -35,3 +43,48 @@ def test_setup_out_of_device_memory_then_a_normal_context():
     with DCDFT.from_config(small) as d1:
         e1 = d1.dcdft_scf_step()["e_total"]
     assert e1 == e0
+
+
+def _plant_runtime_error():
+    """Leave hipErrorOutOfMemory in this thread's last-error slot.  The library
+    and torch load the same runtime (soname libamdhip64.so.7), so this is the
+    slot the library's launch checks read."""
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    ptr = ctypes.c_void_p()
+    rc = hip.hipMalloc(ctypes.byref(ptr), ctypes.c_size_t(1 << 60))
+    assert rc != 0 and not ptr.value
+    assert hip.hipPeekAtLastError() == rc     # pending, as the next call will find it
+
+
+def test_stale_runtime_error_is_not_reported_by_the_next_call():
+    require_gpu()
+    import torch
+    from paper_2606_21125_amd import DCDFT
+    cfg = tiny_config(n_grid=(12, 12, 10), cell=(7.2, 7.2, 6.0), n_atoms=4, nstate=10,
+                      num_fragment=(2, 1, 1), buffer=(2, 0, 0))
+    out = []
+    for planted in (False, True):
+        with DCDFT.from_config(cfg) as d:
+            info = d.dcdft_fragment_info(0)
+            n = int(np.prod(info["shape"]))
+            x = torch.tensor(np.random.default_rng(5).normal(size=(7, n)), device="cuda")
+            y = torch.empty_like(x)
+            torch.cuda.synchronize()
+            steps = []
+            for _ in range(2):
+                if planted:
+                    _plant_runtime_error()
+                steps.append(d.dcdft_scf_step()["e_total"])
+            if planted:
+                _plant_runtime_error()
+            d.dcdft_apply_h(0, x, y)
+            torch.cuda.synchronize()
+            if planted:
+                _plant_runtime_error()
+            rho = d.dcdft_density()
+            out.append((steps, y.cpu().numpy(), rho))
+    print("steps:", out[0][0], out[1][0], flush=True)
+    assert out[0][0] == out[1][0]
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][2], out[1][2])
