@@ -20,8 +20,9 @@ ARCH = os.environ.get("DCDFT_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ROCM_LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(HIPCC))), "lib")
-# roctx ranges of the runtime (marker traces of rocprofv3)
-LIBS = [f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx"]
+# roctx ranges of the runtime (marker traces of rocprofv3); rocBLAS and rocSOLVER
+# for the dense algebra of the large-orbital path
+LIBS = [f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx", "-lrocsolver", "-lrocblas"]
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument", "-Wno-unused-result"]

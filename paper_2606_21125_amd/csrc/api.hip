@@ -482,6 +482,148 @@ void orthonormalize_all(dcdft_ctx *c) {
   launch_rot_cholesky<T>(c->geo, o, 0, c->nF, c->d_lin, psi, (T *)nullptr, c->stream);
 }
 
+// H X on caller-laid-out vectors of one fragment, chunk by chunk (defined with
+// the calls on caller arrays below)
+template <typename T>
+void apply_h_ext(dcdft_ctx *c, const dcdft_ctx::ExtScratch &X, int frag, const T *psi, T *hpsi,
+                 int m, const double *veff_ext = nullptr);
+
+// the first failed library call of the large-orbital path, reported by the step
+void large_note(dcdft_ctx *c, int st, const char *what) {
+  if (st == 0 || c->large_status) return;
+  c->large_status = st;
+  c->large_error = fmt("%s failed: %s", what, large_status_string(st));
+}
+
+template <typename T>
+void large_gram_t(dcdft_ctx *c, const T *x, const T *y, double *out) {
+  const Geo &g = c->geo;
+  const int m = c->m[0];
+  Timed t(c, DCDFT_KERNEL_GRAM, sizeof(T) * (double)g.n * m * (x == y ? 1.0 : 2.0),
+          2.0 * g.n * (double)m * m);
+  large_note(c, large_gram(c->blas, g.n, m, c->m_pad, x, y, g.dv, out, c->d_lpart, c->stream),
+             "Gram product");
+}
+
+// out_i = alpha sum_j R'_ij x_j + beta out_i, R' = R (trans_r) or R^T
+template <typename T>
+void large_rotate_t(dcdft_ctx *c, const T *x, const double *r, bool trans_r, double alpha,
+                    double beta, T *out) {
+  const Geo &g = c->geo;
+  const int m = c->m[0];
+  Timed t(c, DCDFT_KERNEL_ROTATE, sizeof(T) * (double)g.n * m * (beta != 0.0 ? 3.0 : 2.0),
+          2.0 * g.n * (double)m * m);
+  large_note(c, large_rotate(c->blas, g.n, m, c->m_pad, x, r, trans_r, alpha, beta, out,
+                             (T *)c->d_lrot, c->stream),
+             "rotation");
+}
+
+// lin <- L^-1 of sym(s) = L L^T (FLAG_NOT_SPD when it is not positive definite)
+void large_chol_t(dcdft_ctx *c, const double *s, double *lin) {
+  const int m = c->m[0];
+  launch_large_sym(m, c->m_pad, s, lin, nullptr, c->stream);
+  large_note(c, large_chol_inverse(c->blas, m, c->m_pad, lin, c->d_linfo, c->d_flags, c->stream),
+             "Cholesky factor and inverse");
+}
+
+// Steps (a)-(l) of the band-by-band CG and the Rayleigh-Ritz rotation for one
+// fragment with more orbitals than the tiled kernels take, step by step as
+// defined (no fusion): Gram products and rotations are BLAS products over the
+// fragment's points, per-band terms the row kernels of k_large.hip, H X the
+// stencil and projector kernels chunk by chunk.  The orbitals of the last
+// completed step (d_psi) are only read; the arrays d_psi_next, d_w, d_p and d_q
+// are the working set, and the new orbitals end in d_psi_next.
+template <typename T>
+void eigensolver_large(dcdft_ctx *c) {
+  const Geo &g = c->geo;
+  const int m = c->m[0], ld = c->m_pad;
+  hipStream_t s = c->stream;
+  const size_t bytes = (size_t)m * g.n * sizeof(T);
+  std::vector<T *> spare = {(T *)c->d_q, (T *)c->d_psi_next};
+  auto take = [&]() {
+    T *b = spare.back();
+    spare.pop_back();
+    return b;
+  };
+  auto give = [&](T *b) { spare.push_back(b); };
+  T *W = (T *)c->d_w, *P = (T *)c->d_p;
+  const T *psi = (const T *)c->d_psi;   // orbitals entering the sweep
+  T *psi_w = nullptr;                    // the same once they live in the working set
+  apply_h_ext<T>(c, c->ext, 0, psi, W, m);
+  for (int sw = 0; sw < c->sweeps; ++sw) {
+    // (a) Hs = sym(<Psi, W>), a_i = <psi_i, w_i>
+    large_gram_t<T>(c, psi, W, c->d_hs_full);
+    launch_large_sym(m, ld, c->d_hs_full, c->d_hs, c->d_a, s);
+    // (b) G = W - Hs Psi, (c) gamma_i = <g_i, g_i>
+    T *G = take();
+    hipMemcpyAsync(G, W, bytes, hipMemcpyDeviceToDevice, s);
+    large_rotate_t<T>(c, psi, c->d_hs, true, -1.0, 1.0, G);
+    launch_large_row_dots<T>(g, m, G, G, nullptr, c->d_gamma, nullptr, false, s);
+    // (d) P = -G + beta P_prev (Fletcher-Reeves), written over G
+    launch_large_direction<T>(g, m, G, P, G, c->d_gamma, c->d_gamma_prev, sw == 0, s);
+    give(P);
+    P = G;
+    // (e) X = <Psi, P>, P <- P - X^T Psi
+    large_gram_t<T>(c, psi, P, c->d_x);
+    large_rotate_t<T>(c, psi, c->d_x, false, -1.0, 1.0, P);
+    // (f) nu_i = <p_i, p_i> and <p_i, w_i>
+    launch_large_row_dots<T>(g, m, P, P, W, c->d_nu, c->d_bb, false, s);
+    // (g) Q = H P and <p_i, q_i>
+    T *Q = take();
+    apply_h_ext<T>(c, c->ext, 0, P, Q, m);
+    launch_large_row_dots<T>(g, m, P, Q, nullptr, c->d_cc, nullptr, false, s);
+    // (h)-(i) the exact minimiser of each band's 2x2 Rayleigh quotient
+    launch_large_theta(m, ld, c->d_hs_full, c->d_nu, c->d_bb, c->d_cc, c->d_cos, c->d_sin,
+                       c->d_inv, s);
+    // (j) psi <- cos psi + sin p / |p|, w <- cos w + sin q / |p|
+    T *out = psi_w ? psi_w : take();
+    launch_large_band_update<T>(g, m, psi, out, W, P, Q, c->d_cos, c->d_sin, c->d_inv, s);
+    psi = psi_w = out;
+    give(Q);
+    // (k) P stays as P_prev; gamma_prev <- gamma
+    hipMemcpyAsync(c->d_gamma_prev, c->d_gamma, (size_t)m * sizeof(double),
+                   hipMemcpyDeviceToDevice, s);
+    // (l) S = sym(<Psi, Psi>) = L L^T; Psi <- L^-1 Psi, W <- L^-1 W
+    large_gram_t<T>(c, psi, psi, c->d_s);
+    large_chol_t(c, c->d_s, c->d_lin);
+    T *np = take();
+    large_rotate_t<T>(c, psi_w, c->d_lin, true, 1.0, 0.0, np);
+    give(psi_w);
+    psi = psi_w = np;
+    T *nw = take();
+    large_rotate_t<T>(c, W, c->d_lin, true, 1.0, 0.0, nw);
+    give(W);
+    W = nw;
+  }
+  // Rayleigh-Ritz: sym(<Psi, W>) = U diag(eps) U^T, Psi <- U^T Psi, into d_psi_next
+  large_gram_t<T>(c, psi, W, c->d_hs_full);
+  launch_large_sym(m, ld, c->d_hs_full, c->d_u, nullptr, s);
+  large_note(c, large_eigh(c->blas, m, ld, c->d_u, c->d_eps, c->d_le, c->d_linfo + 2, c->d_flags,
+                           s),
+             "symmetric eigensolve");
+  T *dst = (T *)c->d_psi_next;
+  if (psi_w == dst) {
+    T *tmp = take();
+    large_rotate_t<T>(c, psi, c->d_u, false, 1.0, 0.0, tmp);
+    hipMemcpyAsync(dst, tmp, bytes, hipMemcpyDeviceToDevice, s);
+  } else {
+    large_rotate_t<T>(c, psi, c->d_u, false, 1.0, 0.0, dst);
+  }
+  // core weights w_i = dV sum_core psi_i^2
+  launch_large_row_dots<T>(g, m, dst, dst, nullptr, c->d_wcore, nullptr, true, s);
+}
+
+// Initial orthonormalisation on the large-orbital path: Psi <- L^-1 Psi
+template <typename T>
+void orthonormalize_large(dcdft_ctx *c) {
+  T *psi = (T *)c->d_psi, *tmp = (T *)c->d_w;
+  large_gram_t<T>(c, psi, psi, c->d_s);
+  large_chol_t(c, c->d_s, c->d_lin);
+  large_rotate_t<T>(c, psi, c->d_lin, true, 1.0, 0.0, tmp);
+  hipMemcpyAsync(psi, tmp, (size_t)c->m[0] * c->geo.n * sizeof(T), hipMemcpyDeviceToDevice,
+                 c->stream);
+}
+
 // Status of a step from its device flags.  A non-finite value makes every later
 // test meaningless (the capacity of NaN weights is not >= N_e, Jacobi on NaN does
 // not converge), so it is reported first.
@@ -553,18 +695,20 @@ dcdft_status validate(const dcdft_params *p) {
     n *= (long long)(p->n_grid[d] / p->num_fragment[d]) + 2LL * p->num_rgrid_buffer[d];
     if (n >= (1LL << 24)) return set_err(nullptr, DCDFT_ERR_ARG, "fragment box >= 2^24 points");
   }
+  // one fragment (the conventional calculation) may take the large-orbital path
+  const int mlim = nF == 1 ? kMaxOrbLarge : kMaxOrb;
   if (p->nstate_frag) {
     for (long long f = 0; f < nF; ++f) {
       const int m = p->nstate_frag[f];
-      if (m < 1 || m > kMaxOrb)
+      if (m < 1 || m > mlim)
         return set_err(nullptr, DCDFT_ERR_ARG,
                        fmt("nstate_frag of fragment %lld is %d; supported range 1..%d", f, m,
-                           kMaxOrb));
+                           mlim));
     }
-  } else if (p->nstate_frag_uniform < 1 || p->nstate_frag_uniform > kMaxOrb) {
+  } else if (p->nstate_frag_uniform < 1 || p->nstate_frag_uniform > mlim) {
     return set_err(nullptr, DCDFT_ERR_ARG,
                    fmt("nstate_frag_uniform is %d; supported range 1..%d",
-                       p->nstate_frag_uniform, kMaxOrb));
+                       p->nstate_frag_uniform, mlim));
   }
   const long long plane =
       ((long long)(p->n_grid[0] / p->num_fragment[0]) + 2LL * p->num_rgrid_buffer[0]) *
@@ -944,6 +1088,11 @@ void enqueue_phase(dcdft_ctx *c, int phase) {
     return;
   }
   if (phase == 1) {
+    if (c->large) {
+      if (mixed) eigensolver_large<float>(c);
+      else eigensolver_large<double>(c);
+      return;
+    }
     auto run = [&](int a, int b) {
       if (mixed) eigensolver_range<float>(c, a, b);
       else eigensolver_range<double>(c, a, b);
@@ -1070,6 +1219,7 @@ void dcdft_destroy(dcdft_ctx *c) {
     if (c->ev_join[q]) hipEventDestroy(c->ev_join[q]);
   }
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  large_destroy(c->blas);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1152,8 +1302,11 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
     else c->classes.back().p1 = q + 1;
   }
   c->M_tot = c->pmoff[c->nF];
-  c->tiles = (mmax + 15) / 16;
-  c->m_pad = 16 * c->tiles;
+  // large-orbital path: the stencil and projector kernels take the orbitals in
+  // chunks of kMaxOrb, the subspace algebra runs on rocBLAS / rocSOLVER
+  c->large = c->nF == 1 && mmax > kMaxOrb;
+  c->tiles = std::min((mmax + 15) / 16, kMaxTiles);
+  c->m_pad = 16 * ((mmax + 15) / 16);
   c->ne = p->n_electrons;
   c->smearing = p->smearing;
   c->mixing = p->mixing;
@@ -1168,6 +1321,7 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
     const int maxch = std::max(1, g.n / 128);
     c->gram_chunks = std::max(1, std::min(ch, maxch));
     c->gram_chunks_max = std::max(1, std::min(4 * c->gram_chunks, maxch));
+    if (c->large) c->gram_chunks = c->gram_chunks_max = 1;   // the tiled Gram is not used
   }
   g.hloc_variant = hloc_halo_ok(g) ? HLOC_HALO_PD2 : HLOC_PLANE;
   g.rot_tiles = 4;
@@ -1290,12 +1444,26 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
   ALLOC(c->ext.moff, c->nF + 1);
   ALLOC(c->ext.band, c->m_pad);
   ALLOC(c->ext.eb, c->m_pad);
+  c->ext.chunk = 16 * c->tiles;
   {
     char *hp = nullptr;
-    ALLOC(hp, (size_t)c->m_pad * g.n * sizeof(double));
+    ALLOC(hp, (size_t)c->ext.chunk * g.n * sizeof(double));
     c->ext.hp = hp;
   }
-  c->ext.chunk = c->m_pad;
+  if (c->large) {
+    if (mixed) ALLOC(c->d_lpart, (long long)(large_gram_parts(g.n) + 1) * mp2);
+    char *rt = nullptr;
+    ALLOC(rt, (size_t)mp2 * c->elem);
+    c->d_lrot = rt;
+    ALLOC(c->d_linfo, 4);
+    ALLOC(c->d_le, c->m_pad);
+    std::string err;
+    c->blas = large_create(c->stream, &err);
+    if (!c->blas) {
+      c->last_error = err;
+      return fail(DCDFT_ERR_HIP);
+    }
+  }
   c->ext_h_m.assign(c->nF, 0);
   c->ext_h_moff.assign(c->nF + 1, 0);
   {
@@ -1355,10 +1523,16 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
               c->template_xi, c->d_veff, c->d_veff32, c->stream);
   if (mixed) {
     launch_init_orbitals<float>(g, c->orbset(0, c->nF), c->seed, (float *)c->d_psi, c->stream);
-    orthonormalize_all<float>(c);
+    if (c->large) orthonormalize_large<float>(c);
+    else orthonormalize_all<float>(c);
   } else {
     launch_init_orbitals<double>(g, c->orbset(0, c->nF), c->seed, (double *)c->d_psi, c->stream);
-    orthonormalize_all<double>(c);
+    if (c->large) orthonormalize_large<double>(c);
+    else orthonormalize_all<double>(c);
+  }
+  if (c->large_status) {
+    c->last_error = fmt("setup: %s", c->large_error.c_str());
+    return fail(DCDFT_ERR_HIP);
   }
   int flags = 0;
   if (hipMemcpyAsync(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->stream) !=
@@ -1381,7 +1555,10 @@ dcdft_status dcdft_scf_step(dcdft_ctx *c, dcdft_scf_info *info) {
   RoctxRange range("dcdft_scf_step");   // until the step's results are on the host
   hipStream_t s = c->stream;
   // Timed steps run eagerly: their per-launch event records are host decisions.
-  const bool graph = c->batched && c->use_graph && !c->timing;
+  // the large-orbital path runs its library calls eagerly (their workspace is
+  // allocated on first use, which a captured graph cannot hold)
+  const bool graph = c->batched && c->use_graph && !c->timing && !c->large;
+  c->large_status = 0;
   const int slot = c->d_psi == c->psi_first ? 0 : 1;
   if (graph && !c->graph_exec[slot][0]) {
     drain_timers(c);
@@ -1411,7 +1588,7 @@ dcdft_status dcdft_scf_step(dcdft_ctx *c, dcdft_scf_info *info) {
   if (info) {
     float ms = 0.0f;
     hipEventElapsedTime(&ms, c->ev0, c->ev1);
-    info->iter = c->iter + (flags ? 0 : 1);
+    info->iter = c->iter + ((flags || c->large_status) ? 0 : 1);
     info->mu = sc[SC_MU];
     info->e_band = sc[SC_EBAND];
     info->entropy = sc[SC_ENTROPY];
@@ -1427,12 +1604,13 @@ dcdft_status dcdft_scf_step(dcdft_ctx *c, dcdft_scf_info *info) {
     info->ms_fragments = ph[1];
     info->ms_fermi_density = ph[2];
   }
-  if (flags) {
+  if (flags || c->large_status) {
     // failed step: the state of the last completed step comes back (the orbitals
     // were never overwritten; everything else from the copies set aside)
     for (const auto &b : c->backups)
       HIPTRY(c, hipMemcpyAsync(b.live, b.save, b.bytes, hipMemcpyDeviceToDevice, s));
     HIPTRY(c, hipStreamSynchronize(s));
+    if (c->large_status) return set_err(c, DCDFT_ERR_HIP, c->large_error);
     return check_flags(c, flags);
   }
   std::swap(c->d_psi, c->d_psi_next);
@@ -1758,6 +1936,10 @@ dcdft_status dcdft_lcfo_build(dcdft_ctx *c, double eps_cut, double lambda_cut,
   if (!std::isfinite(eps_cut) || !std::isfinite(lambda_cut) || !(lambda_cut > 0.0))
     return set_err(c, DCDFT_ERR_ARG, "eps_cut must be finite and lambda_cut finite and > 0");
   if (c->iter < 1) return set_err(c, DCDFT_ERR_ARG, "no eigenpairs yet: run dcdft_scf_step first");
+  if (c->large)
+    return set_err(c, DCDFT_ERR_ARG,
+                   fmt("DC-LCFO takes fragments of at most %d orbitals (this one has %d)",
+                       kMaxOrb, c->m[0]));
   const Geo &g = c->geo;
   hipStream_t s = c->stream;
   {
@@ -1967,7 +2149,7 @@ namespace {
 // if given.  Everything is issued on the context's stream; nothing is allocated.
 template <typename T>
 void apply_h_ext(dcdft_ctx *c, const dcdft_ctx::ExtScratch &X, int frag, const T *psi, T *hpsi,
-                 int m, const double *veff_ext = nullptr) {
+                 int m, const double *veff_ext) {
   const Geo &g = c->geo;
   KBTables kb = c->kb();
   const int q = c->inv_perm[frag];   // launch position of the fragment
@@ -2123,6 +2305,25 @@ dcdft_status dcdft_band_energy_all(dcdft_ctx *c, const void *psi, const double *
                          "(at most 65536)", need));
   }
   if (c->M_tot < 1) return set_err(c, DCDFT_ERR_ARG, "no orbitals");
+  if (c->large) {
+    // one fragment: the per-fragment call, chunk by chunk (its H psi scratch),
+    // and dE/dV_loc on the global grid
+    const int m = c->m[0];
+    if (prec == DCDFT_PREC_MIXED) {
+      band_energy_ext<float>(c, c->ext, 0, (const float *)psi, f, m, nullptr, energy,
+                             (float *)grad_psi, nullptr);
+      if (grad_v)
+        launch_grad_v_all<float>(c->geo, c->d_nmoff, c->d_m, (const float *)psi, f, grad_v,
+                                 c->stream);
+    } else {
+      band_energy_ext<double>(c, c->ext, 0, (const double *)psi, f, m, nullptr, energy,
+                              (double *)grad_psi, nullptr);
+      if (grad_v)
+        launch_grad_v_all<double>(c->geo, c->d_nmoff, c->d_m, (const double *)psi, f, grad_v,
+                                  c->stream);
+    }
+    return finish_ext(c);
+  }
   if (prec == DCDFT_PREC_MIXED)
     band_energy_all<float>(c, (const float *)psi, f, energy,
                            grad_psi ? (float *)grad_psi : (float *)c->d_q, grad_psi != nullptr,
@@ -2150,7 +2351,7 @@ dcdft_status dcdft_band_energy_noalloc(dcdft_ctx *c, int32_t frag, const void *p
                    fmt("no static scratch on device %d (devices 0..%d are supported)", c->device,
                        kNoAllocMaxDevices - 1));
   // carve the array: layout tables, per-band terms, then H psi of one chunk; the
-  // chunk is as many vectors as fit (at most m_pad).  Every region is fully
+  // chunk is as many vectors as fit (at most the context's chunk).  Every region is fully
   // written before it is read in each call, so nothing needs clearing.
   auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t elem = prec == DCDFT_PREC_MIXED ? sizeof(float) : sizeof(double);
@@ -2174,7 +2375,7 @@ dcdft_status dcdft_band_energy_noalloc(dcdft_ctx *c, int32_t frag, const void *p
   X.eb = reinterpret_cast<double *>(base + off);
   off += up(c->m_pad * sizeof(double));
   X.hp = base + off;
-  X.chunk = (int)std::min<long long>(c->m_pad, fit);
+  X.chunk = (int)std::min<long long>(c->ext.chunk, fit);
   if (prec == DCDFT_PREC_MIXED)
     band_energy_ext<float>(c, X, frag, (const float *)psi, f, m, veff, energy,
                            (float *)grad_psi, grad_v);
@@ -2304,6 +2505,8 @@ void autotune_t(dcdft_ctx *c, dcdft_tune_info &info) {
     if (t_second < t_best) hv_best = second;
   }
   g.hloc_variant = hv_best;
+  // the large-orbital path has no tiled Gram or rotation kernels to tune
+  if (c->large) return;
   // Gram chunk counts (also leaves a finite matrix in d_gtmp for the rotations)
   const int base = c->gram_chunks;
   int cand[4] = {std::max(1, base / 2), base, 2 * base, 4 * base};

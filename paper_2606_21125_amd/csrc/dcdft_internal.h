@@ -15,6 +15,10 @@ namespace dcdft {
 constexpr int kWave = 64;
 constexpr int kMaxTiles = 5;        // m_pad <= 80 orbitals per fragment (16-wide MFMA tiles)
 constexpr int kMaxOrb = 16 * kMaxTiles;
+// one fragment (the conventional calculation of a cell) may hold more: its
+// subspace algebra then runs on rocBLAS / rocSOLVER (the large-orbital path)
+constexpr int kMaxOrbLarge = 4096;
+constexpr int kLargeGramParts = 64;  // FP32 Gram products: chunks of points summed in FP64
 
 // Device-side status flags (bit mask, read back once per step).
 enum : int { FLAG_NOT_SPD = 1, FLAG_EIG = 2, FLAG_CAPACITY = 4, FLAG_NAN = 8 };
@@ -71,6 +75,8 @@ size_t kb_lds_bytes(const Geo &g, int KS, int rr, int rp, int tiles, size_t elem
 // tiled by fragment take a range [f0, f1) of launch positions and the fragment at
 // position p is perm[p].  Bands are laid out in launch order, so a launch range
 // covers a contiguous range of bands.
+struct LargeBlas;         // rocBLAS state of the large-orbital path (k_large.hip)
+
 struct OrbSet {           // flattened orbital layout [M_tot][n]
   int nfrag;
   int m_pad;              // multiple of 16, >= max m (stride of the small matrices)
@@ -306,6 +312,17 @@ struct dcdft_ctx {
   std::vector<int> lcfo_pair_of;                      // [F][F] pair index of (a, b), -1: none
   bool lcfo_ready = false;
   bool fixed_density = false;  // rho^in frozen: no Poisson, V_eff or mixing update in the step
+  // large-orbital path: one fragment with more than kMaxOrb orbitals; tiles is
+  // then kMaxTiles (the chunk of the stencil and projector launches) and m_pad
+  // the padded orbital count
+  bool large = false;
+  dcdft::LargeBlas *blas = nullptr;
+  float *d_lpart = nullptr;          // FP32 Gram chunk products [(parts + 1)][m_pad][m_pad]
+  void *d_lrot = nullptr;            // rotation matrix in the orbital type [m_pad][m_pad]
+  int *d_linfo = nullptr;            // rocSOLVER info words [4]
+  double *d_le = nullptr;            // eigensolver work [m_pad]
+  int large_status = 0;              // first failed library call of the step (0: none)
+  std::string large_error;
 
   dcdft::OrbSet orbset(int f0, int f1) const;
   dcdft::KBTables kb() const;
@@ -478,6 +495,51 @@ void launch_poisson(const Geo &g, const double *rho, double *vh, double *wa, dou
                     double *const qf[3], double *const qi[3], double *const lam[3],
                     hipStream_t s);
 void launch_fill(double *p, long long n, double v, hipStream_t s);
+
+// ---- large-orbital path (one fragment, m > kMaxOrb): k_large.hip -------------------------
+// Orbital arrays: m rows of n points; small matrices FP64 column-major with
+// leading dimension ld >= m.  The int results are rocBLAS statuses (0: success).
+LargeBlas *large_create(hipStream_t s, std::string *err);
+void large_destroy(LargeBlas *b);
+const char *large_status_string(int st);
+int large_gram_parts(int n);
+// out = dv X Y^T (out[i + j ld] = dv <x_i, y_j>); FP32 arrays: products over
+// large_gram_parts(n) chunks of points into part ((parts + 1) ld^2 floats),
+// summed in FP64
+int large_gram(LargeBlas *b, int n, int m, int ld, const double *x, const double *y, double dv,
+               double *out, float *part, hipStream_t s);
+int large_gram(LargeBlas *b, int n, int m, int ld, const float *x, const float *y, double dv,
+               double *out, float *part, hipStream_t s);
+// out_i = alpha sum_j R'_ij x_j + beta out_i with R' = R^T (trans_r false) or R
+// (trans_r true); FP32 arrays use rt (ld^2 floats) for the rounded R
+int large_rotate(LargeBlas *b, int n, int m, int ld, const double *x, const double *r,
+                 bool trans_r, double alpha, double beta, double *out, double *rt, hipStream_t s);
+int large_rotate(LargeBlas *b, int n, int m, int ld, const float *x, const double *r,
+                 bool trans_r, double alpha, double beta, float *out, float *rt, hipStream_t s);
+// s (S on entry) <- L^-1 with S = L L^T, strict upper part zeroed; info[0..1]
+// device ints; FLAG_NOT_SPD raised when S is not positive definite (s is then
+// the identity)
+int large_chol_inverse(LargeBlas *b, int m, int ld, double *s, int *info, int *flags,
+                       hipStream_t st);
+// a (symmetric on entry) <- eigenvectors (columns, ascending eigenvalues in eps,
+// each with its largest entry positive); e_work: m doubles; FLAG_EIG on failure,
+// FLAG_NAN (and the identity solved instead) for a non-finite or overflowing a
+int large_eigh(LargeBlas *b, int m, int ld, double *a, double *eps, double *e_work, int *info,
+               int *flags, hipStream_t st);
+template <typename T>
+void launch_large_row_dots(const Geo &g, int m, const T *x, const T *y, const T *z, double *oy,
+                           double *oz, bool core, hipStream_t s);
+template <typename T>
+void launch_large_direction(const Geo &g, int m, const T *gbuf, const T *pprev, T *pout,
+                            const double *gamma, const double *gamma_prev, bool first,
+                            hipStream_t s);
+void launch_large_theta(int m, int ld, const double *hs_full, const double *nu, const double *bb,
+                        const double *cc, double *cs, double *sn, double *inv, hipStream_t s);
+template <typename T>
+void launch_large_band_update(const Geo &g, int m, const T *psi_in, T *psi_out, T *w, const T *p,
+                              const T *q, const double *cs, const double *sn, const double *inv,
+                              hipStream_t s);
+void launch_large_sym(int m, int ld, const double *a, double *s_out, double *diag, hipStream_t s);
 void launch_fill_int(int *p, long long n, int v, hipStream_t s);
 void launch_nan_check(const double *p, long long n, int *flags, hipStream_t s);
 void launch_convert(const double *a, float *b, long long n, hipStream_t s);

@@ -96,7 +96,10 @@ def _setup_status(lib, p):
     (dict(smearing=0.0), -1, "smearing"),
     (dict(mixing=1.5), -1, "mixing"),
     (dict(cg_sweeps=0), -1, "cg_sweeps"),
-    (dict(nstate_frag_uniform=81), -1, "nstate_frag"),
+    (dict(nstate_frag_uniform=81), -1, "range 1..80"),
+    # one fragment (the conventional calculation) takes the large-orbital path
+    (dict(num_fragment=[1, 1, 1], num_rgrid_buffer=[0, 0, 0], nstate_frag_uniform=4097), -1,
+     "range 1..4096"),
     (dict(n_electrons=-1.0), -1, "n_electrons"),
     (dict(precision=7), -1, "PREC"),
     (dict(n_species=0), -1, "species"),
@@ -136,10 +139,15 @@ def test_null_safe_calls(lib):
     assert lib.dcdft_set_launch(None, 1, 4, 1, 2) == -1
 
 
-def test_valid_setup_without_gpu_reports_hip_error(lib):
+@pytest.mark.parametrize("over", [
+    dict(),
+    # 200 orbitals in one fragment pass validation (large-orbital path)
+    dict(num_fragment=[1, 1, 1], num_rgrid_buffer=[0, 0, 0], nstate_frag_uniform=200),
+])
+def test_valid_setup_without_gpu_reports_hip_error(lib, over):
     import torch
     if torch.cuda.is_available():
         pytest.skip("a GPU is visible; the GPU tests cover a successful setup")
-    p, keep = _params()
+    p, keep = _params(**over)
     st, msg = _setup_status(lib, p)
     assert st == -7 and "device" in msg.lower()

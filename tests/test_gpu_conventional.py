@@ -3,7 +3,12 @@ with no buffer (the core is the whole cell, so Eqs. (2)-(4) reduce to the ordina
 density and the fragment Hamiltonian to the global one), ceil(1.2 N_e / 2) orbitals.
 The oracle in this configuration is pinned to an independent dense-diagonalisation
 SCF (tests/test_oracle_scf.py); here the GPU follows it step by step.  Tolerances
-as for the SCF step (FP64), and 1e-5 Ha per atom for the mixed path's energy."""
+as for the SCF step (FP64), and 1e-5 Ha per atom for the mixed path's energy.
+
+The 64-atom cell (154 orbitals, a ragged last tile of 10) is past the 80 orbitals
+of the tiled subspace kernels and runs on the large-orbital path (BLAS products,
+FP64 factorisations in the solver library, the same per-band steps); its
+status handling (a failed Cholesky, a non-finite state) is checked here too."""
 import numpy as np
 import pytest
 
@@ -19,7 +24,7 @@ def _gpu(cfg, **kw):
     return DCDFT.from_config(cfg, **kw)
 
 
-@pytest.mark.parametrize("cells,steps", [((1, 1, 1), 8), ((2, 2, 1), 3)])
+@pytest.mark.parametrize("cells,steps", [((1, 1, 1), 8), ((2, 2, 1), 3), ((2, 2, 2), 3)])
 def test_conventional_steps_match_oracle(cells, steps):
     require_gpu()
     cfg = workloads.si_cells_config(cells)
@@ -38,9 +43,10 @@ def test_conventional_steps_match_oracle(cells, steps):
             assert abs(ri["e_total"] - gi["e_total"]) < 1e-8 * max(1.0, abs(ri["e_total"]))
 
 
-def test_conventional_mixed_precision():
+@pytest.mark.parametrize("cells", [(2, 2, 1), (2, 2, 2)])
+def test_conventional_mixed_precision(cells):
     require_gpu()
-    cfg = workloads.si_cells_config((2, 2, 1))
+    cfg = workloads.si_cells_config(cells)
     o = oracle.OracleSCF(cfg)
     with _gpu(cfg, precision=1) as d:
         for k in range(3):
@@ -50,11 +56,86 @@ def test_conventional_mixed_precision():
             assert de <= 1e-5
 
 
-def test_orbital_limit_is_reported():
-    """More than 80 orbitals in a fragment is outside the kernels' register and LDS
-    tiles: setup reports it as an argument error rather than running."""
+def _state(d):
+    from paper_2606_21125_amd.binding import FIELD_RHO_IN, FIELD_RHO_OUT, FIELD_VH
+    eps, w = d.dcdft_eigenvalues(0)
+    return {"psi": d.dcdft_get_orbitals(0), "eps": eps, "w": w,
+            "rho_in": d.dcdft_get_field(FIELD_RHO_IN), "rho_out": d.dcdft_get_field(FIELD_RHO_OUT),
+            "vh": d.dcdft_get_field(FIELD_VH)}
+
+
+def test_large_orbital_path_calls():
+    """On the 154-orbital fragment: H psi of every orbital against the oracle
+    (relative 1e-12), the all-fragment band energy equal to the per-fragment call
+    (dE/dV_loc on the global grid, the same points as the box here),
+    the DC-LCFO build refused (its kernels hold at most 80 orbitals), and a step
+    after autotuning (stencil variants only) equal to one without."""
+    require_gpu()
+    import torch
+    from oracle import solver as osol
+    from paper_2606_21125_amd.binding import DcdftError, FFIELD_VEFF
+    cfg = workloads.si_cells_config((2, 2, 2))
+    o = oracle.OracleSCF(cfg)
+    with _gpu(cfg) as d, _gpu(cfg) as ref:
+        d.dcdft_autotune(None)
+        a, b = d.dcdft_scf_step(), ref.dcdft_scf_step()
+        assert a["e_total"] == b["e_total"] and a["mu"] == b["mu"]
+        psi = d.dcdft_get_orbitals(0)
+        m = psi.shape[0]
+        assert m == 154
+        shape = o.frags[0].shape
+        veff = d.dcdft_get_fragment_field(0, FFIELD_VEFF).reshape(shape)
+        ref_h = osol.apply_h(psi.reshape((m,) + shape), veff, o.fproj[0], o.h,
+                             o.dv).reshape(m, -1)
+        xt = torch.tensor(psi, device="cuda")
+        yt = torch.empty_like(xt)
+        d.dcdft_apply_h(0, xt, yt)
+        assert np.abs(yt.cpu().numpy() - ref_h).max() <= 1e-12 * np.abs(ref_h).max()
+        f = np.linspace(0.0, 2.0, m)
+        ft = torch.tensor(f, device="cuda")
+        e1, g1, v1 = (torch.zeros(1, device="cuda", dtype=torch.float64), torch.empty_like(xt),
+                      torch.empty(xt.shape[1], device="cuda", dtype=torch.float64))
+        e2, g2, v2 = torch.zeros_like(e1), torch.empty_like(xt), torch.empty_like(v1)
+        d.dcdft_band_energy(0, xt, ft, energy=e1, grad_psi=g1, grad_v=v1)
+        d.dcdft_band_energy_all(xt, ft, energy=e2, grad_psi=g2, grad_v=v2)
+        torch.cuda.synchronize()
+        assert torch.equal(e1, e2) and torch.equal(g1, g2)
+        # grad_v: the fragment box and the global grid are the same points here
+        np.testing.assert_allclose(v2.cpu().numpy(), v1.cpu().numpy(), rtol=1e-14, atol=0)
+        with pytest.raises(DcdftError) as err:
+            d.dcdft_lcfo_build(0.0)
+        assert "at most 80" in str(err.value)
+
+
+@pytest.mark.parametrize("kind", ["not_spd", "nan"])
+def test_large_orbital_failed_step_keeps_the_state(kind):
+    """A zero orbital makes the overlap singular (its Cholesky fails); orbitals
+    scaled by 1e200 overflow.  Either step returns its status, leaves the state of
+    the last completed step bit for bit, and after the orbitals are put back the
+    next step equals that of a context that never failed."""
     require_gpu()
     from paper_2606_21125_amd.binding import DcdftError
-    cfg = workloads.si_cells_config((2, 2, 2))       # 154 orbitals in one fragment
-    with pytest.raises(DcdftError):
-        _gpu(cfg)
+    cfg = workloads.si_cells_config((2, 2, 2))
+    with _gpu(cfg) as d, _gpu(cfg) as ref:
+        d.dcdft_scf_step()
+        ref.dcdft_scf_step()
+        good = d.dcdft_get_orbitals(0)
+        bad = good.copy()
+        if kind == "not_spd":
+            bad[100] = 0.0
+        else:
+            bad *= 1e200
+        d.dcdft_set_orbitals(0, bad)
+        before = _state(d)
+        with pytest.raises(DcdftError) as err:
+            d.dcdft_scf_step()
+        print(kind, err.value, flush=True)
+        assert err.value.status == (-4 if kind == "not_spd" else -6)
+        after = _state(d)
+        for k in before:
+            assert np.array_equal(before[k], after[k], equal_nan=True), k
+        d.dcdft_set_orbitals(0, good)
+        gi, ri = d.dcdft_scf_step(), ref.dcdft_scf_step()
+        assert gi["iter"] == ri["iter"] == 2
+        for k in ("mu", "e_total", "residual_paper", "charge"):
+            assert gi[k] == ri[k], k
