@@ -105,8 +105,10 @@ def crossover(args, prec) -> dict:
     """Per-step time of the conventional calculation (one fragment, no buffer,
     ceil(1.2 N_e / 2) orbitals) and of DC-DFT (cores of one Si cube, buffers of 4
     points, ceil(1.2 N_loc / 2) orbitals) on Si supercells, same kernels, same
-    precision.  The conventional side stops where one fragment would need more than
-    80 orbitals (the kernels' tile limit)."""
+    precision.  Past 80 orbitals the conventional side runs the large-orbital
+    path (BLAS products, FP64 factorisations in the solver library); its Gram
+    products are reported as achieved TFLOP/s against the dense matrix-core peak
+    of the orbital precision, from one more step with per-launch timing."""
     import torch
     import workloads
     from paper_2606_21125_amd import DCDFT
@@ -128,12 +130,25 @@ def crossover(args, prec) -> dict:
             d.dcdft_scf_step()
         torch.cuda.synchronize()
         ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+        out = {"config": cfg.name, "ms_per_step": round(ms, 3),
+               "orbitals": int(cfg.nstate_frag.sum()), "fragments": cfg.n_fragments}
+        if cfg.n_fragments == 1 and int(cfg.nstate_frag[0]) > 80:
+            from paper_2606_21125_amd.binding import KERNEL_GRAM
+            d.dcdft_kernel_timing(True)
+            d.dcdft_scf_step()
+            kt = d.dcdft_kernel_time(KERNEL_GRAM)
+            d.dcdft_kernel_timing(False)
+            if kt["ms"] > 0:
+                tf = kt["flops"] / (kt["ms"] * 1e-3) / 1e12
+                peak = 157.3 if prec != 0 else 78.6
+                out["gram"] = {"launches": kt["launches"], "ms": round(kt["ms"], 3),
+                               "tflops": round(tf, 2), "peak_tflops": peak,
+                               "frac": round(tf / peak, 3)}
         d.close()
-        return {"config": cfg.name, "ms_per_step": round(ms, 3),
-                "orbitals": int(cfg.nstate_frag.sum()), "fragments": cfg.n_fragments}
+        return out
 
     rows = []
-    for cells in ((1, 1, 1), (2, 1, 1), (2, 2, 1), (2, 2, 2), (4, 4, 4)):
+    for cells in ((1, 1, 1), (2, 1, 1), (2, 2, 1), (2, 2, 2), (3, 3, 3), (4, 4, 4)):
         n_atoms = 8 * cells[0] * cells[1] * cells[2]
         print(f"[bench] crossover: {n_atoms} atoms", file=sys.stderr, flush=True)
         row = {"atoms": n_atoms, "grid": [16 * c for c in cells]}

@@ -710,11 +710,6 @@ dcdft_status validate(const dcdft_params *p) {
                    fmt("nstate_frag_uniform is %d; supported range 1..%d",
                        p->nstate_frag_uniform, mlim));
   }
-  const long long plane =
-      ((long long)(p->n_grid[0] / p->num_fragment[0]) + 2LL * p->num_rgrid_buffer[0]) *
-      ((long long)(p->n_grid[1] / p->num_fragment[1]) + 2LL * p->num_rgrid_buffer[1]);
-  if (plane > 1024)
-    return set_err(nullptr, DCDFT_ERR_ARG, "fragment x-y plane larger than 1024 points");
   return DCDFT_OK;
 }
 

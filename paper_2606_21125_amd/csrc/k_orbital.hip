@@ -1143,10 +1143,98 @@ size_t kb_lds_bytes(const Geo &g, int KS, int rr, int rp, int tiles, size_t elem
   return (size_t)t.area + std::max(own, tmp);
 }
 
+// Planes of more than 1024 points (one workgroup cannot hold a thread per
+// point): one workgroup per (kTileX x kTileY tile of the plane, orbital).  The
+// tile with a four-point periodic halo of the current plane is staged in LDS
+// (double-buffered, one barrier per plane); each thread's own column marches
+// along z with the nine-plane register window.  The terms are added in the
+// order of k_hloc, so both give the same values.
+constexpr int kTileX = 32, kTileY = 8;
+
+template <typename T>
+__global__ void __launch_bounds__(kTileX * kTileY)
+    k_hloc_tile(Geo g, const int *__restrict__ band_frag, long long b0, int vbase,
+                const double *__restrict__ veff, const T *__restrict__ x, T *__restrict__ y) {
+  constexpr int LX = kTileX + 8, LY = kTileY + 8;
+  __shared__ T lds[2][LY][LX];
+  const int nx = g.nl[0], ny = g.nl[1], nz = g.nl[2];
+  const int ntx = (nx + kTileX - 1) / kTileX;
+  const int tx0 = (blockIdx.x % ntx) * kTileX, ty0 = (blockIdx.x / ntx) * kTileY;
+  const long long B = b0 + blockIdx.y;
+  const int f = band_frag[B];
+  const long long plane = (long long)nx * ny;
+  const int t = threadIdx.x, lx = t % kTileX, ly = t / kTileX;
+  const int ix = tx0 + lx, iy = ty0 + ly;
+  const bool own = ix < nx && iy < ny;
+  const long long pt = own ? ix + (long long)iy * nx : 0;   // idle lanes read point 0
+  const T *xb = x + B * (long long)g.n;
+  T *yb = y + B * (long long)g.n;
+  const double *vb = veff + (long long)(f - vbase) * g.n;
+  const T c0 = (T)g.kc[0];
+  T ax[4], ay[4], az[4];
+#pragma unroll
+  for (int k = 1; k <= 4; ++k) {
+    ax[k - 1] = (T)g.kc[k];
+    ay[k - 1] = (T)g.kc[4 + k];
+    az[k - 1] = (T)g.kc[8 + k];
+  }
+  T win[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const int zz = ((k - 4) % nz + nz) % nz;
+    win[k] = xb[zz * plane + pt];
+  }
+  double v0 = vb[pt], v1 = (nz > 1) ? vb[plane + pt] : 0.0;
+  for (int z = 0; z < nz; ++z) {
+    T(*pl)[LX] = lds[z & 1];
+    const T *xp = xb + z * plane;
+    for (int e = t; e < LX * LY; e += kTileX * kTileY) {
+      const int ex = e % LX, ey = e / LX;
+      const int gx = ((tx0 - 4 + ex) % nx + nx) % nx;
+      const int gy = ((ty0 - 4 + ey) % ny + ny) % ny;
+      pl[ey][ex] = xp[gx + (long long)gy * nx];
+    }
+    __syncthreads();
+    if (own) {
+      const int cx = lx + 4, cy = ly + 4;
+      T acc = c0 * win[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        acc += ax[k] * (pl[cy][cx + k + 1] + pl[cy][cx - k - 1]);
+        acc += ay[k] * (pl[cy + k + 1][cx] + pl[cy - k - 1][cx]);
+        acc += az[k] * (win[5 + k] + win[3 - k]);
+      }
+      acc += (T)v0 * win[4];
+      yb[z * plane + pt] = acc;
+    }
+    v0 = v1;
+    if (z + 2 < nz) v1 = vb[(z + 2) * plane + pt];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) win[k] = win[k + 1];
+    win[8] = xb[(long long)((z + 5) % nz) * plane + pt];
+  }
+}
+
+// dot[B] = dV <x_B, y_B> for nb bands from b0 (the stencil's fused dot, for the
+// tiled stencil); one workgroup per band
+template <typename T>
+__global__ void __launch_bounds__(256) k_band_dot(Geo g, long long b0, const T *__restrict__ x,
+                                                  const T *__restrict__ y,
+                                                  double *__restrict__ dot) {
+  __shared__ double red[4];
+  const long long B = b0 + blockIdx.x;
+  const T *xb = x + B * (long long)g.n, *yb = y + B * (long long)g.n;
+  double acc = 0.0;
+  for (int l = threadIdx.x; l < g.n; l += blockDim.x) acc += (double)xb[l] * (double)yb[l];
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) dot[B] = g.dv * acc;
+}
+
 bool hloc_halo_ok(const Geo &g) {
   // halo copies need nx, ny >= 4; the held end planes need nz >= 8; the padded
   // double plane must fit the 64 KB LDS a workgroup may address
-  return g.nl[0] >= 4 && g.nl[1] >= 4 && g.nl[2] >= 8 &&
+  // (and a thread per point of the plane)
+  return g.nl[0] >= 4 && g.nl[1] >= 4 && g.nl[2] >= 8 && g.nl[0] * g.nl[1] <= 1024 &&
          2 * (size_t)(g.nl[1] + 8) * (g.nl[0] + 32) * sizeof(double) <= 65536;
 }
 
@@ -1157,6 +1245,20 @@ void launch_hloc(const Geo &g, const OrbSet &o, int f0, int f1, const double *ve
   const long long nb = o.nb(f0, f1);
   if (nb <= 0) return;
   const int plane = g.nl[0] * g.nl[1];
+  if (plane > 1024) {
+    // tiled plane (every variant); the dot in a pass of its own
+    const unsigned tiles = (unsigned)(((g.nl[0] + kTileX - 1) / kTileX) *
+                                      ((g.nl[1] + kTileY - 1) / kTileY));
+    for (long long j0 = 0; j0 < nb; j0 += 65535) {
+      const unsigned nj = (unsigned)std::min<long long>(65535, nb - j0);
+      hipLaunchKernelGGL(k_hloc_tile<T>, dim3(tiles, nj), dim3(kTileX * kTileY), 0, s, g,
+                         o.band_frag, o.b0(f0) + j0, vbase, veff, x, y);
+    }
+    if (dot)
+      hipLaunchKernelGGL(k_band_dot<T>, dim3((unsigned)nb), dim3(256), 0, s, g, o.b0(f0), x, y,
+                         dot);
+    return;
+  }
   int hv = g.hloc_variant;
   if (hv == HLOC_VEC || hv == HLOC_VEC_WIDE || hv == HLOC_VEC_Z2 || hv == HLOC_VEC_Z3 ||
       hv == HLOC_VEC8 || hv == HLOC_VEC8_WIDE) {
