@@ -5,10 +5,12 @@ The oracle in this configuration is pinned to an independent dense-diagonalisati
 SCF (tests/test_oracle_scf.py); here the GPU follows it step by step.  Tolerances
 as for the SCF step (FP64), and 1e-5 Ha per atom for the mixed path's energy.
 
-The 64-atom cell (154 orbitals, a ragged last tile of 10) is past the 80 orbitals
-of the tiled subspace kernels and runs on the large-orbital path (BLAS products,
-FP64 factorisations in the solver library, the same per-band steps); its
-status handling (a failed Cholesky, a non-finite state) is checked here too."""
+The 64-atom cell (154 orbitals, a ragged last tile of 10) and the 216-atom cell
+(519 orbitals on a 48 x 48 plane, one step) are past the 80 orbitals of the tiled
+subspace kernels and run on the large-orbital path (BLAS products, FP64
+factorisations in the solver library, the same per-band steps; the 48^3 box also
+takes the plane-tiled stencil); its status handling (a failed Cholesky, a
+non-finite state) is checked here too."""
 import numpy as np
 import pytest
 
@@ -24,7 +26,9 @@ def _gpu(cfg, **kw):
     return DCDFT.from_config(cfg, **kw)
 
 
-@pytest.mark.parametrize("cells,steps", [((1, 1, 1), 8), ((2, 2, 1), 3), ((2, 2, 2), 3)])
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("cells,steps", [((1, 1, 1), 8), ((2, 2, 1), 3), ((2, 2, 2), 3),
+                                         ((3, 3, 3), 1)])
 def test_conventional_steps_match_oracle(cells, steps):
     require_gpu()
     cfg = workloads.si_cells_config(cells)
