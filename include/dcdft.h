@@ -86,6 +86,10 @@ typedef struct {
   const int32_t *atom_species;  /* host [n_atoms], index into species               */
   int32_t n_species;
   const dcdft_species *species; /* host [n_species]                                 */
+  /* orbitals per fragment: 1..80; with one fragment (the conventional
+   * calculation of the cell) 1..4096, more than 80 taking the large-orbital path
+   * (BLAS products and FP64 factorisations of the solver library, no captured
+   * graph; DC-LCFO is not available there) */
   const int32_t *nstate_frag;   /* host [F] orbitals per fragment, or NULL          */
   int32_t nstate_frag_uniform;  /* Table 1 nstate_frag, used when the array is NULL */
   double n_electrons;           /* N_e fixed by the global chemical potential       */
@@ -240,9 +244,10 @@ dcdft_status dcdft_set_mixer(dcdft_ctx *c, int32_t kind, double alpha, double q0
  * of the global matrix is not part of this library.  The first call allocates
  * device memory (two FP64 arrays of the orbital size and the pair tables), kept
  * until dcdft_destroy; the call overwrites work arrays, never the SCF state.
- * Errors: ARG (no step taken yet, non-finite eps_cut, lambda_cut not > 0, or a
- * projector region too dense for the FP64 projector kernels' 64 KB of LDS, which
- * a mixed-precision setup does not check), EIG, OOM, HIP. */
+ * Errors: ARG (no step taken yet, non-finite eps_cut, lambda_cut not > 0, a
+ * fragment of more than 80 orbitals, or a projector region too dense for the FP64
+ * projector kernels' 64 KB of LDS, which a mixed-precision setup does not
+ * check), EIG, OOM, HIP. */
 typedef struct {
   int32_t n_basis;              /* basis functions over all fragments               */
   int32_t n_pairs;              /* ordered fragment pairs with a neighbour block    */
