@@ -1146,17 +1146,21 @@ size_t kb_lds_bytes(const Geo &g, int KS, int rr, int rp, int tiles, size_t elem
 // Planes of more than 1024 points (one workgroup cannot hold a thread per
 // point): one workgroup per (kTileX x kTileY tile of the plane, orbital).  The
 // tile with a four-point periodic halo of the current plane is staged in LDS
-// (double-buffered, one barrier per plane); each thread's own column marches
-// along z with the nine-plane register window.  The terms are added in the
-// order of k_hloc, so both give the same values.
-constexpr int kTileX = 32, kTileY = 8;
+// (double-buffered, one barrier per plane); its entries are loaded kTilePD
+// planes ahead into registers (each thread holds kTilePer entries of each plane
+// in flight, at offsets computed once).  Each thread's own column marches along
+// z with the nine-plane register window.  The terms are added in the order of
+// k_hloc, so both give the same values.
+constexpr int kTileX = 32, kTileY = 16, kTileNT = kTileX * kTileY, kTilePD = 4;
+constexpr int kTileLX = kTileX + 8, kTileLY = kTileY + 8;
+constexpr int kTilePer = (kTileLX * kTileLY + kTileNT - 1) / kTileNT;
 
 template <typename T>
-__global__ void __launch_bounds__(kTileX * kTileY)
+__global__ void __launch_bounds__(kTileNT)
     k_hloc_tile(Geo g, const int *__restrict__ band_frag, long long b0, int vbase,
                 const double *__restrict__ veff, const T *__restrict__ x, T *__restrict__ y) {
-  constexpr int LX = kTileX + 8, LY = kTileY + 8;
-  __shared__ T lds[2][LY][LX];
+  constexpr int LX = kTileLX, LY = kTileLY;
+  __shared__ T lds[2][LY * LX];
   const int nx = g.nl[0], ny = g.nl[1], nz = g.nl[2];
   const int ntx = (nx + kTileX - 1) / kTileX;
   const int tx0 = (blockIdx.x % ntx) * kTileX, ty0 = (blockIdx.x / ntx) * kTileY;
@@ -1178,6 +1182,27 @@ __global__ void __launch_bounds__(kTileX * kTileY)
     ay[k - 1] = (T)g.kc[4 + k];
     az[k - 1] = (T)g.kc[8 + k];
   }
+  // this thread's tile entries: plane offset (periodic wrap) and LDS slot;
+  // entries past the tile repeat the last slot (loaded and stored like it)
+  int off[kTilePer], slot[kTilePer];
+#pragma unroll
+  for (int j = 0; j < kTilePer; ++j) {
+    const int e = min(t + j * kTileNT, LX * LY - 1);
+    const int ex = e % LX, ey = e / LX;
+    const int gx = ((tx0 - 4 + ex) % nx + nx) % nx;
+    const int gy = ((ty0 - 4 + ey) % ny + ny) % ny;
+    off[j] = gx + gy * nx;
+    slot[j] = e;
+  }
+  // planes z .. z + kTilePD - 1 in flight (plane indices clamped into the box:
+  // loads past the last plane are issued but never stored)
+  T pre[kTilePD][kTilePer];
+#pragma unroll
+  for (int k = 0; k < kTilePD; ++k) {
+    const long long zz = min(k, nz - 1);
+#pragma unroll
+    for (int j = 0; j < kTilePer; ++j) pre[k][j] = xb[zz * plane + off[j]];
+  }
   T win[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
@@ -1185,33 +1210,37 @@ __global__ void __launch_bounds__(kTileX * kTileY)
     win[k] = xb[zz * plane + pt];
   }
   double v0 = vb[pt], v1 = (nz > 1) ? vb[plane + pt] : 0.0;
-  for (int z = 0; z < nz; ++z) {
-    T(*pl)[LX] = lds[z & 1];
-    const T *xp = xb + z * plane;
-    for (int e = t; e < LX * LY; e += kTileX * kTileY) {
-      const int ex = e % LX, ey = e / LX;
-      const int gx = ((tx0 - 4 + ex) % nx + nx) % nx;
-      const int gy = ((ty0 - 4 + ey) % ny + ny) % ny;
-      pl[ey][ex] = xp[gx + (long long)gy * nx];
-    }
-    __syncthreads();
-    if (own) {
-      const int cx = lx + 4, cy = ly + 4;
-      T acc = c0 * win[4];
+  for (int z0 = 0; z0 < nz; z0 += kTilePD) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        acc += ax[k] * (pl[cy][cx + k + 1] + pl[cy][cx - k - 1]);
-        acc += ay[k] * (pl[cy + k + 1][cx] + pl[cy - k - 1][cx]);
-        acc += az[k] * (win[5 + k] + win[3 - k]);
+    for (int k = 0; k < kTilePD; ++k) {
+      const int z = z0 + k;
+      if (z < nz) {   // uniform over the workgroup
+        T *pl = lds[z & 1];
+#pragma unroll
+        for (int j = 0; j < kTilePer; ++j) pl[slot[j]] = pre[k][j];
+        __syncthreads();
+        const long long zn = min(z + kTilePD, nz - 1);
+#pragma unroll
+        for (int j = 0; j < kTilePer; ++j) pre[k][j] = xb[zn * plane + off[j]];
+        if (own) {
+          const int c = (ly + 4) * LX + lx + 4;
+          T acc = c0 * win[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            acc += ax[q] * (pl[c + q + 1] + pl[c - q - 1]);
+            acc += ay[q] * (pl[c + (q + 1) * LX] + pl[c - (q + 1) * LX]);
+            acc += az[q] * (win[5 + q] + win[3 - q]);
+          }
+          acc += (T)v0 * win[4];
+          yb[z * plane + pt] = acc;
+        }
+        v0 = v1;
+        if (z + 2 < nz) v1 = vb[(z + 2) * plane + pt];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) win[q] = win[q + 1];
+        win[8] = xb[(long long)((z + 5) % nz) * plane + pt];
       }
-      acc += (T)v0 * win[4];
-      yb[z * plane + pt] = acc;
     }
-    v0 = v1;
-    if (z + 2 < nz) v1 = vb[(z + 2) * plane + pt];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) win[k] = win[k + 1];
-    win[8] = xb[(long long)((z + 5) % nz) * plane + pt];
   }
 }
 
@@ -1251,7 +1280,7 @@ void launch_hloc(const Geo &g, const OrbSet &o, int f0, int f1, const double *ve
                                       ((g.nl[1] + kTileY - 1) / kTileY));
     for (long long j0 = 0; j0 < nb; j0 += 65535) {
       const unsigned nj = (unsigned)std::min<long long>(65535, nb - j0);
-      hipLaunchKernelGGL(k_hloc_tile<T>, dim3(tiles, nj), dim3(kTileX * kTileY), 0, s, g,
+      hipLaunchKernelGGL(k_hloc_tile<T>, dim3(tiles, nj), dim3(kTileNT), 0, s, g,
                          o.band_frag, o.b0(f0) + j0, vbase, veff, x, y);
     }
     if (dot)

@@ -143,3 +143,36 @@ def test_large_orbital_failed_step_keeps_the_state(kind):
         assert gi["iter"] == ri["iter"] == 2
         for k in ("mu", "e_total", "residual_paper", "charge"):
             assert gi[k] == ri[k], k
+
+
+def test_large_orbital_pulay_and_fixed_density():
+    """The step modes on the large-orbital path, FP64, against the oracle: three
+    steps with Pulay-Kerker mixing, then two with the density frozen at the one
+    those steps reached (the step bounds as above)."""
+    require_gpu()
+    cfg = workloads.si_cells_config((2, 2, 2))
+    o = oracle.OracleSCF(cfg)
+    o.set_mixer("pulay", alpha=0.3, q0=0.8, history=8)
+    with _gpu(cfg) as d:
+        d.dcdft_set_mixer("pulay", alpha=0.3, q0=0.8, history=8)
+        for k in range(3):
+            ri, gi = o.step(), d.dcdft_scf_step()
+            print("pulay", k, ri["residual_paper"], gi["residual_paper"], flush=True)
+            assert abs(ri["mu"] - gi["mu"]) < 1e-10
+            np.testing.assert_allclose(d.dcdft_eigenvalues(0)[0], o.eps[0], rtol=0, atol=1e-10)
+            assert l1_over_ne(d.dcdft_density(), o.rho_out, o.dv, o.ne) < 1e-9
+            assert abs(ri["residual_paper"] - gi["residual_paper"]) <= 1e-9 * max(
+                1e-3, ri["residual_paper"])
+        rho = np.ascontiguousarray(o.rho_out)
+    o2 = oracle.OracleSCF(cfg)
+    o2.fixed_density = True
+    o2.set_density(rho)
+    with _gpu(cfg) as d:
+        d.dcdft_set_density(rho.ravel())
+        d.dcdft_fix_density(True)
+        for k in range(2):
+            ri, gi = o2.step(), d.dcdft_scf_step()
+            print("fixed", k, ri["mu"], gi["mu"], flush=True)
+            assert abs(ri["mu"] - gi["mu"]) < 1e-10
+            np.testing.assert_allclose(d.dcdft_eigenvalues(0)[0], o2.eps[0], rtol=0, atol=1e-10)
+            assert l1_over_ne(d.dcdft_density(), o2.rho_out, o2.dv, o2.ne) < 1e-9
