@@ -522,8 +522,9 @@ int large_rotate(LargeBlas *b, int n, int m, int ld, const float *x, const doubl
 int large_chol_inverse(LargeBlas *b, int m, int ld, double *s, int *info, int *flags,
                        hipStream_t st);
 // a (symmetric on entry) <- eigenvectors (columns, ascending eigenvalues in eps,
-// each with its largest entry positive); e_work: m doubles; FLAG_EIG on failure,
-// FLAG_NAN (and the identity solved instead) for a non-finite or overflowing a
+// each with its largest entry positive); e_work: m doubles; info: two device
+// ints; FLAG_EIG on failure, FLAG_NAN (and the identity solved instead) for a
+// non-finite or overflowing a
 int large_eigh(LargeBlas *b, int m, int ld, double *a, double *eps, double *e_work, int *info,
                int *flags, hipStream_t st);
 template <typename T>

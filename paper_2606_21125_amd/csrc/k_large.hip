@@ -142,28 +142,24 @@ __global__ void k_large_tril(int m, int ld, double *__restrict__ l, const int *_
 }
 
 // The eigensolver is iterative: a matrix with a non-finite or overflowing entry
-// (|a| > 1e150) raises flag and is replaced by the identity before it.  One
-// workgroup.
-__global__ void __launch_bounds__(1024)
-    k_large_finite_guard(int m, int ld, double *__restrict__ a, int *__restrict__ flags,
-                         int flag) {
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  const long long mm = (long long)m * m;
-  int mine = 0;
-  for (long long e = threadIdx.x; e < mm; e += blockDim.x) {
-    const double v = a[(e / m) * ld + e % m];
-    if (!(fabs(v) <= 1e150)) mine = 1;
-  }
-  if (mine) atomicOr(&bad, 1);
-  __syncthreads();
-  if (!bad) return;
-  if (threadIdx.x == 0) atomicOr(flags, flag);
-  for (long long e = threadIdx.x; e < mm; e += blockDim.x) {
-    const long long i = e % m, j = e / m;
-    a[j * ld + i] = i == j ? 1.0 : 0.0;
-  }
+// (|a| > 1e150) raises flag and is replaced by the identity before it.  Scan:
+// any workgroup that finds such an entry sets *bad (cleared by the caller);
+// fill: with *bad set, the identity and the flag.
+__global__ void __launch_bounds__(256)
+    k_large_finite_scan(int m, int ld, const double *__restrict__ a, int *__restrict__ bad) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)m * m) return;
+  if (!(fabs(a[(e / m) * ld + e % m]) <= 1e150)) atomicOr(bad, 1);
+}
+__global__ void __launch_bounds__(256)
+    k_large_finite_fill(int m, int ld, double *__restrict__ a, const int *__restrict__ bad,
+                        int *__restrict__ flags, int flag) {
+  if (!*bad) return;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0) atomicOr(flags, flag);
+  if (e >= (long long)m * m) return;
+  const long long i = e % m, j = e / m;
+  a[j * ld + i] = i == j ? 1.0 : 0.0;
 }
 
 // Each eigenvector (column) flipped so that its largest-magnitude entry, the
@@ -205,6 +201,8 @@ __global__ void __launch_bounds__(256)
   if (flip)
     for (int i = threadIdx.x; i < m; i += blockDim.x) col[i] = -col[i];
 }
+
+__global__ void k_large_fill_int(int *p, int v) { *p = v; }
 
 __global__ void k_large_to_float(long long n, const double *__restrict__ a, float *__restrict__ b) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -326,7 +324,11 @@ int large_chol_inverse(LargeBlas *b, int m, int ld, double *s, int *info, int *f
 
 int large_eigh(LargeBlas *b, int m, int ld, double *a, double *eps, double *e_work, int *info,
                int *flags, hipStream_t st) {
-  hipLaunchKernelGGL(k_large_finite_guard, dim3(1), dim3(1024), 0, st, m, ld, a, flags,
+  // info[1] holds the scan's finding (info[0] is the eigensolver's)
+  const unsigned nb = blocks_for((long long)m * m, 256);
+  hipLaunchKernelGGL(k_large_fill_int, dim3(1), dim3(1), 0, st, info + 1, 0);
+  hipLaunchKernelGGL(k_large_finite_scan, dim3(nb), dim3(256), 0, st, m, ld, a, info + 1);
+  hipLaunchKernelGGL(k_large_finite_fill, dim3(nb), dim3(256), 0, st, m, ld, a, info + 1, flags,
                      (int)FLAG_NAN);
   rocblas_status e = rocsolver_dsyevd(b->h, rocblas_evect_original, rocblas_fill_lower, m, a, ld,
                                       eps, e_work, info);
