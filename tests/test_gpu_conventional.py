@@ -176,3 +176,60 @@ def test_large_orbital_pulay_and_fixed_density():
             assert abs(ri["mu"] - gi["mu"]) < 1e-10
             np.testing.assert_allclose(d.dcdft_eigenvalues(0)[0], o2.eps[0], rtol=0, atol=1e-10)
             assert l1_over_ne(d.dcdft_density(), o2.rho_out, o2.dv, o2.ne) < 1e-9
+
+
+@pytest.mark.parametrize("m", [80, 81, 96, 97])
+def test_orbital_counts_around_the_switch(m):
+    """One fragment with 80 (tiled kernels), 81 (the first count on the large-orbital
+    path, one orbital past a 16-tile), 96 (whole tiles) and 97 orbitals: three FP64
+    steps against the oracle, the mixed path's energy within 1e-5 Ha per atom."""
+    require_gpu()
+    from tests.helpers import tiny_config
+    cfg = tiny_config(n_grid=(16, 16, 16), cell=(10.0, 10.0, 10.0), n_atoms=12, nstate=m,
+                      valence=2.0)
+    o = oracle.OracleSCF(cfg)
+    with _gpu(cfg) as d, _gpu(cfg, precision=1) as dm:
+        for k in range(3):
+            ri, gi, mi = o.step(), d.dcdft_scf_step(), dm.dcdft_scf_step()
+            de = abs(ri["e_total"] - mi["e_total"]) / cfg.system.n_atoms
+            print(m, k, ri["mu"], gi["mu"], f"mixed dE/atom {de:.1e}", flush=True)
+            assert abs(ri["mu"] - gi["mu"]) < 1e-10
+            np.testing.assert_allclose(d.dcdft_eigenvalues(0)[0], o.eps[0], rtol=0, atol=1e-10)
+            assert l1_over_ne(d.dcdft_density(), o.rho_out, o.dv, o.ne) < 1e-9
+            assert de <= 1e-5
+
+
+def test_large_orbital_noalloc_and_checkpoint(tmp_path):
+    """On the 154-orbital fragment: the entry point that allocates nothing equals
+    the band-energy call (its chunk is the context's 80 vectors or fewer, so the
+    energy agrees to rounding, the gradients bit for bit), and a
+    context restored from a checkpoint continues the iteration (FP64 bounds)."""
+    require_gpu()
+    import torch
+    cfg = workloads.si_cells_config((2, 2, 2))
+    path = str(tmp_path / "state.npz")
+    with _gpu(cfg) as a:
+        a.dcdft_scf_step()
+        psi = torch.tensor(a.dcdft_get_orbitals(0), device="cuda")
+        f = torch.linspace(0.0, 2.0, psi.shape[0], device="cuda", dtype=torch.float64)
+        outs = []
+        for call in (a.dcdft_band_energy, a.dcdft_band_energy_noalloc):
+            e = torch.zeros(1, device="cuda", dtype=torch.float64)
+            g, v = torch.empty_like(psi), torch.empty(psi.shape[1], device="cuda",
+                                                      dtype=torch.float64)
+            call(0, psi, f, energy=e, grad_psi=g, grad_v=v)
+            torch.cuda.synchronize()
+            outs.append((e, g, v))
+        # the static scratch holds fewer vectors per chunk: the energy's chunk sums
+        # are grouped differently (rounding), the gradients are the same values
+        (e1, g1, v1), (e2, g2, v2) = outs
+        assert abs(e1.item() - e2.item()) <= 1e-13 * abs(e1.item())
+        assert torch.equal(g1, g2) and torch.equal(v1, v2)
+        a.save_state(path)
+        with _gpu(cfg) as b:
+            b.load_state(path)
+            for k in range(2):
+                ia, ib = a.dcdft_scf_step(), b.dcdft_scf_step()
+                assert abs(ia["mu"] - ib["mu"]) < 1e-10, k
+                np.testing.assert_allclose(b.dcdft_eigenvalues(0)[0], a.dcdft_eigenvalues(0)[0],
+                                           rtol=0, atol=1e-10)
