@@ -1,10 +1,11 @@
 """Fragment boxes whose x-y plane has more than 1024 points (one thread per point
-no longer fits a workgroup): the stencil runs plane-tiled (32 x 8 point tiles
+no longer fits a workgroup): the stencil runs plane-tiled (32 x 16 point tiles
 with a periodic halo), and the fused <x, Hx> of the CG sweep takes a pass of its
 own.  Checked against the oracle on planes that are ragged against the tiles
 (40 x 36 points):
   * H psi of a one-fragment cell, FP64 (relative 1e-12) and FP32 (2e-6);
-  * DC SCF steps of two fragments with 40 x 36 x 12 boxes (FP64 step bounds);
+  * DC SCF steps of two fragments with 40 x 36 x 12 boxes and 12 and 21 orbitals
+    (two tile classes; FP64 step bounds, and the mixed path's energy);
   * one wide fragment with 90 orbitals (the large-orbital path on a tiled plane)."""
 import numpy as np
 import pytest
@@ -59,6 +60,7 @@ def test_wide_plane_scf_steps_match_oracle(cfg_kind):
     require_gpu()
     if cfg_kind == "dc":
         cfg = _wide(12, num_fragment=(1, 1, 2), buffer=(0, 0, 2), n_grid=(40, 36, 16))
+        cfg.nstate_frag = np.array([12, 21], dtype=np.int32)   # two tile classes
     else:
         cfg = _wide(90)
     o = oracle.OracleSCF(cfg)
@@ -73,3 +75,18 @@ def test_wide_plane_scf_steps_match_oracle(cfg_kind):
                 np.testing.assert_allclose(w, o.w[f], rtol=0, atol=1e-9)
             assert l1_over_ne(d.dcdft_density(), o.rho_out, o.dv, o.ne) < 1e-9
             assert abs(ri["e_total"] - gi["e_total"]) < 1e-8 * max(1.0, abs(ri["e_total"]))
+
+
+def test_wide_plane_mixed_precision_energy():
+    """The FP32 path on the wide DC boxes (tiled stencil and its dot pass in FP32):
+    total energy within 1e-5 Ha per atom of the oracle over three steps."""
+    require_gpu()
+    cfg = _wide(12, num_fragment=(1, 1, 2), buffer=(0, 0, 2), n_grid=(40, 36, 16))
+    cfg.nstate_frag = np.array([12, 21], dtype=np.int32)
+    o = oracle.OracleSCF(cfg)
+    with _gpu(cfg, precision=1) as d:
+        for k in range(3):
+            ri, gi = o.step(), d.dcdft_scf_step()
+            de = abs(ri["e_total"] - gi["e_total"]) / cfg.system.n_atoms
+            print(f"wide mixed step {k}: dE/atom {de:.2e}", flush=True)
+            assert de <= 1e-5
