@@ -1446,7 +1446,11 @@ dcdft_status dcdft_setup(const dcdft_params *p, dcdft_ctx **out) {
     c->ext.hp = hp;
   }
   if (c->large) {
-    if (mixed) ALLOC(c->d_lpart, (long long)(large_gram_parts(g.n) + 1) * mp2);
+    {
+      char *part = nullptr;
+      ALLOC(part, (size_t)(large_gram_parts(g.n) + 1) * mp2 * c->elem);
+      c->d_lpart = part;
+    }
     char *rt = nullptr;
     ALLOC(rt, (size_t)mp2 * c->elem);
     c->d_lrot = rt;

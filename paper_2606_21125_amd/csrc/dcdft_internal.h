@@ -18,7 +18,7 @@ constexpr int kMaxOrb = 16 * kMaxTiles;
 // one fragment (the conventional calculation of a cell) may hold more: its
 // subspace algebra then runs on rocBLAS / rocSOLVER (the large-orbital path)
 constexpr int kMaxOrbLarge = 4096;
-constexpr int kLargeGramParts = 64;  // FP32 Gram products: chunks of points summed in FP64
+constexpr int kLargeGramParts = 64;  // Gram products: chunks of points summed in FP64
 
 // Device-side status flags (bit mask, read back once per step).
 enum : int { FLAG_NOT_SPD = 1, FLAG_EIG = 2, FLAG_CAPACITY = 4, FLAG_NAN = 8 };
@@ -317,7 +317,7 @@ struct dcdft_ctx {
   // the padded orbital count
   bool large = false;
   dcdft::LargeBlas *blas = nullptr;
-  float *d_lpart = nullptr;          // FP32 Gram chunk products [(parts + 1)][m_pad][m_pad]
+  void *d_lpart = nullptr;           // Gram chunk products [(parts + 1)][m_pad][m_pad], orbital type
   void *d_lrot = nullptr;            // rotation matrix in the orbital type [m_pad][m_pad]
   int *d_linfo = nullptr;            // rocSOLVER info words [4]
   double *d_le = nullptr;            // eigensolver work [m_pad]
@@ -503,13 +503,13 @@ LargeBlas *large_create(hipStream_t s, std::string *err);
 void large_destroy(LargeBlas *b);
 const char *large_status_string(int st);
 int large_gram_parts(int n);
-// out = dv X Y^T (out[i + j ld] = dv <x_i, y_j>); FP32 arrays: products over
-// large_gram_parts(n) chunks of points into part ((parts + 1) ld^2 floats),
-// summed in FP64
+// out = dv X Y^T (out[i + j ld] = dv <x_i, y_j>): products over
+// large_gram_parts(n) chunks of points into part ((parts + 1) ld^2 values of the
+// orbital type), summed in FP64 in chunk order
 int large_gram(LargeBlas *b, int n, int m, int ld, const double *x, const double *y, double dv,
-               double *out, float *part, hipStream_t s);
+               double *out, void *part, hipStream_t s);
 int large_gram(LargeBlas *b, int n, int m, int ld, const float *x, const float *y, double dv,
-               double *out, float *part, hipStream_t s);
+               double *out, void *part, hipStream_t s);
 // out_i = alpha sum_j R'_ij x_j + beta out_i with R' = R^T (trans_r false) or R
 // (trans_r true); FP32 arrays use rt (ld^2 floats) for the rounded R
 int large_rotate(LargeBlas *b, int n, int m, int ld, const double *x, const double *r,

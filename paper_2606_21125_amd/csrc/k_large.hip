@@ -114,7 +114,8 @@ __global__ void k_large_sym(int m, int ld, const double *__restrict__ a, double 
 
 // out = scale * sum_k part_k on the leading m x m block (parts in order, FP64),
 // zero in the padding
-__global__ void k_large_reduce_parts(int m, int ld, int nparts, const float *__restrict__ part,
+template <typename P>
+__global__ void k_large_reduce_parts(int m, int ld, int nparts, const P *__restrict__ part,
                                      double scale, double *__restrict__ out) {
   const long long mm = (long long)ld * ld;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -265,33 +266,58 @@ const char *large_status_string(int st) {
 
 int large_gram_parts(int n) { return std::min(kLargeGramParts, std::max(1, n)); }
 
-int large_gram(LargeBlas *b, int n, int m, int ld, const double *x, const double *y, double dv,
-               double *out, float *, hipStream_t) {
-  return gemm(b, rocblas_operation_transpose, rocblas_operation_none, m, m, n, dv, x, n, y, n,
-              0.0, out, ld);
+namespace {
+
+rocblas_status gemm_batched(LargeBlas *b, int M, int N, int K, const double *x, int lx,
+                            long long sx, const double *y, int ly, long long sy, double *c,
+                            int ldc, long long sc, int batch) {
+  const double one = 1.0, zero = 0.0;
+  return rocblas_dgemm_strided_batched(b->h, rocblas_operation_transpose, rocblas_operation_none,
+                                       M, N, K, &one, x, lx, sx, y, ly, sy, &zero, c, ldc, sc,
+                                       batch);
+}
+rocblas_status gemm_batched(LargeBlas *b, int M, int N, int K, const float *x, int lx,
+                            long long sx, const float *y, int ly, long long sy, float *c,
+                            int ldc, long long sc, int batch) {
+  const float one = 1.0f, zero = 0.0f;
+  return rocblas_sgemm_strided_batched(b->h, rocblas_operation_transpose, rocblas_operation_none,
+                                       M, N, K, &one, x, lx, sx, y, ly, sy, &zero, c, ldc, sc,
+                                       batch);
 }
 
-int large_gram(LargeBlas *b, int n, int m, int ld, const float *x, const float *y, double dv,
-               double *out, float *part, hipStream_t s) {
-  // FP32 products over chunks of the points, summed in FP64 in chunk order
+// The products over chunks of the points (one batched GEMM, the remainder in a
+// second call), summed in FP64 in chunk order: a Gram product has an m x m
+// result and n-long sums, and without split-K kernels (atomics are off) an
+// unchunked GEMM would run on a handful of workgroups
+template <typename T>
+int gram_chunked(LargeBlas *b, int n, int m, int ld, const T *x, const T *y, double dv,
+                 double *out, T *part, hipStream_t s) {
   const int parts = large_gram_parts(n);
   const int kc = (n + parts - 1) / parts;
   const int full = n / kc, tail = n - full * kc;
   const long long mm = (long long)ld * ld;
-  const float one = 1.0f, zero = 0.0f;
-  rocblas_status st = rocblas_sgemm_strided_batched(
-      b->h, rocblas_operation_transpose, rocblas_operation_none, m, m, kc, &one, x, n, kc, y, n,
-      kc, &zero, part, ld, mm, full);
+  rocblas_status st = gemm_batched(b, m, m, kc, x, n, kc, y, n, kc, part, ld, mm, full);
   if (st != rocblas_status_success) return (int)st;
   if (tail > 0) {
-    st = rocblas_sgemm(b->h, rocblas_operation_transpose, rocblas_operation_none, m, m, tail,
-                       &one, x + (long long)full * kc, n, y + (long long)full * kc, n, &zero,
-                       part + full * mm, ld);
+    st = gemm_batched(b, m, m, tail, x + (long long)full * kc, n, 0, y + (long long)full * kc, n,
+                      0, part + full * mm, ld, 0, 1);
     if (st != rocblas_status_success) return (int)st;
   }
-  hipLaunchKernelGGL(k_large_reduce_parts, dim3(blocks_for(mm, 256)), dim3(256), 0, s, m, ld,
+  hipLaunchKernelGGL(k_large_reduce_parts<T>, dim3(blocks_for(mm, 256)), dim3(256), 0, s, m, ld,
                      full + (tail > 0 ? 1 : 0), part, dv, out);
   return 0;
+}
+
+}  // namespace
+
+int large_gram(LargeBlas *b, int n, int m, int ld, const double *x, const double *y, double dv,
+               double *out, void *part, hipStream_t s) {
+  return gram_chunked<double>(b, n, m, ld, x, y, dv, out, static_cast<double *>(part), s);
+}
+
+int large_gram(LargeBlas *b, int n, int m, int ld, const float *x, const float *y, double dv,
+               double *out, void *part, hipStream_t s) {
+  return gram_chunked<float>(b, n, m, ld, x, y, dv, out, static_cast<float *>(part), s);
 }
 
 int large_rotate(LargeBlas *b, int n, int m, int ld, const double *x, const double *r,
