@@ -233,3 +233,39 @@ def test_large_orbital_noalloc_and_checkpoint(tmp_path):
                 assert abs(ia["mu"] - ib["mu"]) < 1e-10, k
                 np.testing.assert_allclose(b.dcdft_eigenvalues(0)[0], a.dcdft_eigenvalues(0)[0],
                                            rtol=0, atol=1e-10)
+
+
+def test_largest_orbital_count_properties():
+    """The largest orbital count one fragment takes (4096, on a 20^3 box of 8000
+    points), one FP64 step, checked by properties that hold at any size, with the
+    oracle's H (the step's V_eff) on sampled orbitals: each eigenvalue equals the
+    Rayleigh quotient of its Ritz vector, Ritz vectors are H-orthogonal and
+    orthonormal, the eigenvalues ascend, and the density holds N_e electrons."""
+    require_gpu()
+    from oracle import solver as osol
+    from paper_2606_21125_amd.binding import FFIELD_VEFF
+    from tests.helpers import tiny_config
+    cfg = tiny_config(n_grid=(20, 20, 20), cell=(12.0, 12.0, 12.0), n_atoms=8, nstate=4096,
+                      valence=2.0)
+    o = oracle.OracleSCF(cfg)       # tables and projectors only; no oracle step
+    with _gpu(cfg) as d:
+        info = d.dcdft_scf_step()
+        print("4096 orbitals: step", info["ms_step"], "ms, charge", info["charge"], flush=True)
+        assert abs(info["charge"] - cfg.system.n_electrons) < 1e-9 * cfg.system.n_electrons
+        eps, w = d.dcdft_eigenvalues(0)
+        assert eps.shape == (4096,) and np.all(np.diff(eps) >= 0)
+        np.testing.assert_allclose(w, np.ones_like(w), rtol=0, atol=1e-10)
+        psi = d.dcdft_get_orbitals(0)
+        shape = o.frags[0].shape
+        veff = d.dcdft_get_fragment_field(0, FFIELD_VEFF).reshape(shape)
+        sample = [0, 1, 17, 2047, 4094, 4095]
+        x = psi[sample]
+        hx = osol.apply_h(x.reshape((len(sample),) + shape), veff, o.fproj[0], o.h,
+                          o.dv).reshape(len(sample), -1)
+        h = o.dv * (x @ hx.T)               # <psi_i, H psi_j> on the sample
+        s = o.dv * (x @ x.T)
+        scale = np.abs(eps).max()
+        np.testing.assert_allclose(np.diag(h), eps[sample], rtol=0, atol=1e-9 * scale)
+        off = h - np.diag(np.diag(h))
+        assert np.abs(off).max() <= 1e-9 * scale
+        np.testing.assert_allclose(s, np.eye(len(sample)), rtol=0, atol=1e-10)
