@@ -24,6 +24,17 @@ __device__ inline double rsqrt_f64(double x) {
   return r * fma(-h * r, r, 1.5);
 }
 
+// Workgroups are dealt to the eight XCDs in turn (linear id mod 8), and each XCD
+// has its own L2.  xcd_ordered(b, n) is the work item workgroup b of n takes so
+// that every XCD works through one contiguous range of items (a bijection on
+// [0, n)): neighbouring items, which read the same inputs (the orbitals of one
+// fragment read its V_eff), are then cached in one L2 instead of eight.
+__device__ inline unsigned xcd_ordered(unsigned b, unsigned n) {
+  constexpr unsigned kXcd = 8;
+  const unsigned q = n / kXcd, r = n % kXcd, x = b % kXcd;
+  return x * q + (x < r ? x : r) + b / kXcd;
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(1024) k_hloc(Geo g, const int *__restrict__ ba
   T *lds = reinterpret_cast<T *>(lds_raw);
   __shared__ double red[16];
   double dacc = 0.0;
-  const long long B = b0 + blockIdx.x;
+  const long long B = b0 + xcd_ordered(blockIdx.x, gridDim.x);
   const int f = band_frag[B];
   const int nx = g.nl[0], ny = g.nl[1], nz = g.nl[2];
   const int plane = nx * ny;
@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(1024) k_hloc_halo(Geo g, const int *__restrict
   extern __shared__ char lds_raw[];
   T *lds = reinterpret_cast<T *>(lds_raw);
   __shared__ double red[16];
-  const long long B = b0 + blockIdx.x;
+  const long long B = b0 + xcd_ordered(blockIdx.x, gridDim.x);
   const int f = band_frag[B];
   const int nx = NX > 0 ? NX : g.nl[0];
   const int ny = g.nl[1], nz = g.nl[2];
@@ -236,11 +236,12 @@ __global__ void __launch_bounds__(1024) k_hloc_vec(Geo g, const int *__restrict_
   const int bx = nx / RX, tpo = bx * ny;
   const int SX = nx + 32, lplane = (ny + 8) * SX;  // rows continue the bank sequence
   const int ol = threadIdx.x / tpo, tt = threadIdx.x % tpo;
-  // z segments of one orbital group are consecutive workgroups
-  const int seg = blockIdx.x % zs;
+  // z segments of one orbital group are consecutive work items
+  const unsigned wi = xcd_ordered(blockIdx.x, gridDim.x);
+  const int seg = wi % zs;
   const int zlen = (nz + zs - 1) / zs;
   const int zb = seg * zlen, ze = zb + zlen < nz ? zb + zlen : nz;
-  long long B = b0 + (long long)(blockIdx.x / zs) * opw + ol;
+  long long B = b0 + (long long)(wi / zs) * opw + ol;
   const bool valid = B < b0 + nbands;
   if (!valid) B = b0 + nbands - 1;
   const int f = band_frag[B];
@@ -1163,8 +1164,11 @@ __global__ void __launch_bounds__(kTileNT)
   __shared__ T lds[2][LY * LX];
   const int nx = g.nl[0], ny = g.nl[1], nz = g.nl[2];
   const int ntx = (nx + kTileX - 1) / kTileX;
-  const int tx0 = (blockIdx.x % ntx) * kTileX, ty0 = (blockIdx.x / ntx) * kTileY;
-  const long long B = b0 + blockIdx.y;
+  // the tiles of one orbital are consecutive work items
+  const unsigned wi = xcd_ordered(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+  const int tile = wi % gridDim.x;
+  const int tx0 = (tile % ntx) * kTileX, ty0 = (tile / ntx) * kTileY;
+  const long long B = b0 + wi / gridDim.x;
   const int f = band_frag[B];
   const long long plane = (long long)nx * ny;
   const int t = threadIdx.x, lx = t % kTileX, ly = t / kTileX;
