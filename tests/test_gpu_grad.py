@@ -7,7 +7,8 @@ central differences of the GPU forward along 32 random unit directions with
 step 1e-6 (E is quadratic in psi and linear in V, so central differences are
 exact up to rounding); Euler identity sum psi . dE/dpsi = 2E; FP32 gradients
 within 1e-5 relative of the FP64 oracle; dE/dV divided by dV on core points
-equals rho_tot^out of the same step when f carries 2 x the occupations."""
+equals rho_tot^out of the same step when f carries 2 x the occupations; the
+gradient projected off span(Psi) is the CG step's residual."""
 import numpy as np
 import pytest
 
@@ -256,3 +257,37 @@ def test_band_energy_bwd_entry_point():
             d.dcdft_band_energy(3, psi, f, grad_psi=g1, grad_v=v1, prec=prec)
             d.dcdft_band_energy_bwd(3, psi, f, grad_psi=g2, grad_v=v2, prec=prec)
             assert torch.equal(g1, g2) and torch.equal(v1, v2)
+
+
+def test_projected_gradient_is_the_cg_residual():
+    """With f = 1 the band-energy gradient from the library's backward, projected
+    off span(Psi) and divided by 2 dV, is the residual g = W - Hs Psi of the CG
+    step (b), formed the oracle's way (H psi by the oracle's operator, Hs =
+    sym(<Psi, W>)) from the same orbitals and V_eff: relative 1e-11."""
+    require_gpu()
+    import torch
+    from oracle import solver as osol
+    from paper_2606_21125_amd.binding import FFIELD_VEFF
+    cfg, o, d = _setup(4)
+    with d:
+        for _ in range(2):
+            d.dcdft_scf_step()
+        for frag in (0, 5):
+            psi = d.dcdft_get_orbitals(frag)             # orthonormal Ritz vectors
+            m = psi.shape[0]
+            shape = o.frags[frag].shape
+            veff = d.dcdft_get_fragment_field(frag, FFIELD_VEFF).reshape(shape)
+            pt = torch.tensor(psi, device="cuda")
+            ft = torch.ones(m, device="cuda", dtype=torch.float64)
+            grad = torch.empty_like(pt)
+            d.dcdft_band_energy(frag, pt, ft, grad_psi=grad)
+            torch.cuda.synchronize()
+            gh = grad.cpu().numpy() / (2.0 * o.dv)       # H psi from the gradient
+            g_lib = gh - (o.dv * (gh @ psi.T)) @ psi      # off span(Psi)
+            w = osol.apply_h(psi.reshape((m,) + shape), veff, o.fproj[frag], o.h,
+                             o.dv).reshape(m, -1)
+            hs = o.dv * (psi @ w.T)
+            g_ref = w - 0.5 * (hs + hs.T) @ psi
+            err = np.abs(g_lib - g_ref).max() / np.abs(w).max()
+            print(f"fragment {frag}: projected gradient vs CG residual {err:.2e}", flush=True)
+            assert err <= 1e-11
