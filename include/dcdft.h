@@ -332,9 +332,12 @@ dcdft_status dcdft_band_energy_bwd(dcdft_ctx *c, int32_t frag, const void *psi, 
  * which holds it when prec's element is no wider than the context's.  Nothing is
  * allocated; the call shares scratch with dcdft_scf_step, so both go on the
  * context's stream (never concurrently).  Inputs must be complete when the call
- * is made; outputs are complete when it returns.  Errors: ARG (NULL psi or f,
- * prec, grad_psi aliasing psi, an FP64 call on a mixed-precision context without
- * grad_psi, projector LDS of that precision), HIP. */
+ * is made; outputs are complete when it returns.  On the large-orbital path (one
+ * fragment of more than 80 orbitals) the call is dcdft_band_energy of fragment 0
+ * (chunk by chunk, H psi in its scratch) with grad_v formed on the global grid.
+ * Errors: ARG (NULL psi or f, prec, grad_psi aliasing psi, an FP64 call on a
+ * mixed-precision context without grad_psi, projector LDS of that precision),
+ * HIP. */
 dcdft_status dcdft_band_energy_all(dcdft_ctx *c, const void *psi, const double *f, int32_t prec,
                                    double *energy, void *grad_psi, double *grad_v);
 
@@ -404,7 +407,10 @@ dcdft_status dcdft_kernel_time(dcdft_ctx *c, int32_t kernel, int64_t *launches, 
  * new choice is appended (an unwritable file gives DCDFT_ERR_ARG after the
  * choice has been applied).  out (may be NULL) receives the choice and the
  * measured milliseconds per launch (-1: candidate not applicable or not
- * timed). */
+ * timed).  A context on the large-orbital path (one fragment of more than 80
+ * orbitals) tunes the stencil variant only: its products are library GEMMs.
+ * Fragment boxes with more than 1024 points per plane use the plane-tiled
+ * stencil whatever the variant. */
 enum { DCDFT_HLOC_PLANE = 0, DCDFT_HLOC_HALO_PD2 = 1, DCDFT_HLOC_HALO_PD3 = 2,
        DCDFT_HLOC_HALO_PD4 = 3, DCDFT_HLOC_HALO_PD2_ENDS = 4, DCDFT_HLOC_VEC = 5,
        DCDFT_HLOC_VEC_WIDE = 6, DCDFT_HLOC_VEC_Z2 = 7, DCDFT_HLOC_VEC_Z3 = 8,
