@@ -92,10 +92,20 @@ def _compare(o, d, cfg, basis_ref, h_ref, tol_h, tol_span):
                                        rtol=0, atol=tol_h)
 
 
-@pytest.mark.parametrize("which", ["ragged", "config1"])
+def _wide_dc():
+    """Two fragments with 40 x 36 x 12 boxes (planes past 1024 points: the tiled
+    stencil applies H^alpha to the basis) and 12 and 21 orbitals."""
+    from tests.test_gpu_wide_plane import _wide
+    cfg = _wide(12, num_fragment=(1, 1, 2), buffer=(0, 0, 2), n_grid=(40, 36, 16))
+    cfg.nstate_frag = np.array([12, 21], dtype=np.int32)
+    return cfg
+
+
+@pytest.mark.parametrize("which", ["ragged", "config1", "wide"])
 def test_lcfo_matches_oracle(which):
     require_gpu()
-    cfg = workloads.config(1) if which == "config1" else _ragged_tiny()
+    cfg = {"config1": lambda: workloads.config(1), "ragged": _ragged_tiny,
+           "wide": _wide_dc}[which]()
     o = oracle.OracleSCF(cfg)
     with _gpu(cfg) as d:
         for _ in range(3):
