@@ -6,7 +6,7 @@ SCF (tests/test_oracle_scf.py); here the GPU follows it step by step.  Tolerance
 as for the SCF step (FP64), and 1e-5 Ha per atom for the mixed path's energy.
 
 The 64-atom cell (154 orbitals, a ragged last tile of 10) and the 216-atom cell
-(519 orbitals on a 48 x 48 plane, one step) are past the 80 orbitals of the tiled
+(519 orbitals on a 48 x 48 plane, one step in FP64 and mixed) are past the 80 orbitals of the tiled
 subspace kernels and run on the large-orbital path (BLAS products, FP64
 factorisations in the solver library, the same per-band steps; the 48^3 box also
 takes the plane-tiled stencil); its status handling (a failed Cholesky, a
@@ -34,9 +34,15 @@ def test_conventional_steps_match_oracle(cells, steps):
     cfg = workloads.si_cells_config(cells)
     assert cfg.n_fragments == 1 and cfg.fragment_shape == tuple(cfg.n_grid)
     o = oracle.OracleSCF(cfg)
+    # the largest cell also checks the mixed path against the same oracle step
+    dm = _gpu(cfg, precision=1) if cells == (3, 3, 3) else None
     with _gpu(cfg) as d:
         for k in range(steps):
             ri, gi = o.step(), d.dcdft_scf_step()
+            if dm is not None:
+                de = abs(ri["e_total"] - dm.dcdft_scf_step()["e_total"]) / cfg.system.n_atoms
+                print(f"mixed step {k}: dE/atom {de:.2e}", flush=True)
+                assert de <= 1e-5
             print(cfg.name, k, ri["mu"], gi["mu"], ri["residual_paper"])
             assert abs(ri["mu"] - gi["mu"]) < 1e-10
             eps, w = d.dcdft_eigenvalues(0)
@@ -45,6 +51,8 @@ def test_conventional_steps_match_oracle(cells, steps):
             np.testing.assert_allclose(w, np.ones_like(w), rtol=0, atol=1e-12)
             assert l1_over_ne(d.dcdft_density(), o.rho_out, o.dv, o.ne) < 1e-9
             assert abs(ri["e_total"] - gi["e_total"]) < 1e-8 * max(1.0, abs(ri["e_total"]))
+    if dm is not None:
+        dm.close()
 
 
 @pytest.mark.parametrize("cells", [(2, 2, 1), (2, 2, 2)])
