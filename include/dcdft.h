@@ -431,7 +431,8 @@ dcdft_status dcdft_autotune(dcdft_ctx *c, const char *cache_path, dcdft_tune_inf
  * halo variants need a fragment box of at least 4 x 4 x 8 points), rot_tiles
  * 2, 4 or 8, gram_chunks 1..gram_chunks_max (as get reports it), streams
  * 1..4: the batched step's eigensolver runs over `streams` groups of
- * fragments (split at equal sums of m_alpha times its 16-padded count) on as
+ * fragments (split at equal sums of m_alpha times the square of its 16-padded
+ * count) on as
  * many streams, forked and joined inside the step (default 2, or 3 with 192
  * fragments or more; results do not depend on it); anything else is
  * DCDFT_ERR_ARG and changes nothing.  get: any pointer may be NULL. */

@@ -1008,13 +1008,16 @@ namespace {
 int step_groups(const dcdft_ctx *c, int *bound) {
   const int G = (c->batched && !c->timing) ? std::min(c->streams, c->nF) : 1;
   bound[0] = 0;
-  // groups of equal padded matrix-core work, sum of m (16 tiles): a fragment's
-  // Gram and rotation products scale with its orbitals times its padded count
-  // (water: 94.8 against 95.7 ms per step when split at equal orbital counts)
+  // groups of equal sums of m m_pad^2 (m_pad: the 16-padded count): a
+  // fragment's Gram and rotation products scale with m m_pad, and the wider
+  // classes run their kernels at lower rates and the longest Jacobi, so the
+  // group holding them must hold fewer (water: 93.6 ms per step, against 94.7
+  // at equal sums of m m_pad, where that group ran alone for the last ~15 ms
+  // of the eigensolvers, and 95.7 at equal orbital counts)
   std::vector<long long> cw(c->nF + 1, 0);
   for (int q = 0; q < c->nF; ++q) {
-    const int mq = c->m[c->perm[q]];
-    cw[q + 1] = cw[q] + (long long)mq * (16 * ((mq + 15) / 16));
+    const long long mq = c->m[c->perm[q]], mp = 16 * ((mq + 15) / 16);
+    cw[q + 1] = cw[q] + mq * mp * mp;
   }
   for (int q = 1; q < G; ++q) {
     int h = bound[q - 1] + 1;
